@@ -1,0 +1,186 @@
+"""CPU oracle for the Schulze method's hot path.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this package; the product path never does.  It
+shares no code with the GPU library (``paper_2505_12976_amd``).
+
+The arithmetic lives in ``oracle.c`` (plain C, 64-bit integers, OpenMP over
+independent output rows); this module builds it with gcc, loads it with
+ctypes and converts numpy arrays.  Each function restates a definition from
+the paper's voting preliminaries (Section 2.1):
+
+* :func:`pairwise`  -- d[x][y], total weight of voters preferring x to y.
+* :func:`weights`   -- weighted tournament graph: winning votes (mode 0) or
+  majority margin (mode 1, the paper's mu).
+* :func:`closure`   -- p(a,b), width of a widest path (Floyd-Warshall over
+  (max, min), the original sequential algorithm named in Section 5.2).
+* :func:`rank`      -- beats relation, winners, ranking by (beaten_by, id).
+* :func:`widest_from` / :func:`widest_to` -- single-source/target widest
+  paths by dense Dijkstra (the path problems of the NL-membership proof,
+  Section 3).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+WINNING_VOTES = 0
+MARGIN = 1
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def build() -> str:
+    """Compile oracle.c into liboracle.so (always recompiles)."""
+    tmp = _LIB + ".tmp"
+    subprocess.check_call(["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall",
+                           _SRC, "-o", tmp])
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    lib.oracle_pairwise.argtypes = [vp, ctypes.c_int, i64, i32, i32, vp, vp]
+    lib.oracle_pairwise_rows.argtypes = [vp, ctypes.c_int, i64, i32, i32, vp, vp, i64, vp]
+    lib.oracle_pairwise_cols.argtypes = [vp, ctypes.c_int, i64, i32, i32, vp, vp, i64, vp]
+    lib.oracle_weights.argtypes = [vp, i32, ctypes.c_int, vp]
+    lib.oracle_closure.argtypes = [vp, i32, vp]
+    lib.oracle_rank.argtypes = [vp, i32, vp, vp, vp]
+    lib.oracle_widest_from.argtypes = [vp, i32, i32, vp]
+    lib.oracle_widest_to.argtypes = [vp, i32, i32, vp]
+    for name in ("oracle_pairwise", "oracle_pairwise_rows", "oracle_pairwise_cols", "oracle_weights",
+                 "oracle_closure", "oracle_rank", "oracle_widest_from", "oracle_widest_to"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, what: str) -> int:
+    if rc < 0:
+        raise OracleError(f"{what} failed with code {rc}")
+    return rc
+
+
+def _ballots(ballots: np.ndarray):
+    b = np.ascontiguousarray(ballots)
+    if b.ndim != 2:
+        raise ValueError("ballots must be an (n, L) array")
+    if b.dtype == np.uint16:
+        return b, 0
+    if b.dtype == np.int32:
+        return b, 1
+    raise ValueError("ballots must be uint16 or int32")
+
+
+def _weights_arg(weight, n):
+    if weight is None:
+        return None, None
+    w = np.ascontiguousarray(weight, dtype=np.uint32)
+    if w.shape != (n,):
+        raise ValueError("voter weights must have shape (n,)")
+    return w, w.ctypes.data
+
+
+def pairwise(ballots: np.ndarray, m: int, weight=None) -> np.ndarray:
+    """d[x][y] = total weight of voters ranking x strictly above y (int64, m x m)."""
+    b, d32 = _ballots(ballots)
+    n, L = b.shape
+    w, wp = _weights_arg(weight, n)
+    d = np.empty((m, m), dtype=np.int64)
+    _check(_load().oracle_pairwise(b.ctypes.data, d32, n, L, m, wp, d.ctypes.data), "oracle_pairwise")
+    return d
+
+
+def pairwise_rows(ballots: np.ndarray, m: int, rows, weight=None) -> np.ndarray:
+    """Rows of d for the listed candidates: out[r] = d[rows[r], :]."""
+    b, d32 = _ballots(ballots)
+    n, L = b.shape
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    w, wp = _weights_arg(weight, n)
+    out = np.empty((len(rows), m), dtype=np.int64)
+    _check(_load().oracle_pairwise_rows(b.ctypes.data, d32, n, L, m, wp, rows.ctypes.data, len(rows),
+                                        out.ctypes.data), "oracle_pairwise_rows")
+    return out
+
+
+def pairwise_cols(ballots: np.ndarray, m: int, cols, weight=None) -> np.ndarray:
+    """Columns of d for the listed candidates: out[c] = d[:, cols[c]]."""
+    b, d32 = _ballots(ballots)
+    n, L = b.shape
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    w, wp = _weights_arg(weight, n)
+    out = np.empty((len(cols), m), dtype=np.int64)
+    _check(_load().oracle_pairwise_cols(b.ctypes.data, d32, n, L, m, wp, cols.ctypes.data, len(cols),
+                                        out.ctypes.data), "oracle_pairwise_cols")
+    return out
+
+
+def weights(d: np.ndarray, mode: int = WINNING_VOTES) -> np.ndarray:
+    d = np.ascontiguousarray(d, dtype=np.int64)
+    m = d.shape[0]
+    w = np.empty_like(d)
+    _check(_load().oracle_weights(d.ctypes.data, m, mode, w.ctypes.data), "oracle_weights")
+    return w
+
+
+def closure(w: np.ndarray) -> np.ndarray:
+    """Widest-path widths p (int64, zero diagonal) of the weight matrix w."""
+    w = np.ascontiguousarray(w, dtype=np.int64)
+    m = w.shape[0]
+    p = np.empty_like(w)
+    _check(_load().oracle_closure(w.ctypes.data, m, p.ctypes.data), "oracle_closure")
+    return p
+
+
+def rank(p: np.ndarray):
+    """(beaten_by int32[m], is_winner bool[m], order int32[m])."""
+    p = np.ascontiguousarray(p, dtype=np.int64)
+    m = p.shape[0]
+    beaten = np.empty(m, dtype=np.int32)
+    win = np.empty(m, dtype=np.uint8)
+    order = np.empty(m, dtype=np.int32)
+    _check(_load().oracle_rank(p.ctypes.data, m, beaten.ctypes.data, win.ctypes.data,
+                               order.ctypes.data), "oracle_rank")
+    return beaten, win.astype(bool), order
+
+
+def widest_from(w: np.ndarray, s: int) -> np.ndarray:
+    """out[v] = p(s, v); out[s] = 0."""
+    w = np.ascontiguousarray(w, dtype=np.int64)
+    out = np.empty(w.shape[0], dtype=np.int64)
+    _check(_load().oracle_widest_from(w.ctypes.data, w.shape[0], s, out.ctypes.data), "oracle_widest_from")
+    return out
+
+
+def widest_to(w: np.ndarray, t: int) -> np.ndarray:
+    """out[v] = p(v, t); out[t] = 0."""
+    w = np.ascontiguousarray(w, dtype=np.int64)
+    out = np.empty(w.shape[0], dtype=np.int64)
+    _check(_load().oracle_widest_to(w.ctypes.data, w.shape[0], t, out.ctypes.data), "oracle_widest_to")
+    return out
+
+
+def schulze(ballots: np.ndarray, m: int, mode: int = WINNING_VOTES, weight=None) -> dict:
+    """The whole path on the CPU: d, w, p, beaten_by, winners, order."""
+    d = pairwise(ballots, m, weight)
+    w = weights(d, mode)
+    p = closure(w)
+    beaten, win, order = rank(p)
+    return {"d": d, "w": w, "p": p, "beaten_by": beaten, "is_winner": win, "order": order}

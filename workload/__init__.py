@@ -1,0 +1,188 @@
+"""Seeded synthetic preference profiles for the Schulze method.
+
+The ballots stand in for the paper's Spotify chart profiles (Section 5.1,
+Table 1), which are not available: full or truncated rankings drawn from a
+Mallows model, and top-k rankings drawn from Plackett-Luce with Zipf weights.
+The generator is plain C (``gen.c``); this module builds it, loads it with
+ctypes and names the workloads.  It holds no part of the method's
+arithmetic, so the CPU oracle and the GPU library can both take its output
+as input bytes.
+
+Ballot layout: ``(n, L)`` array of candidate ids, best first, padded with
+0xFFFF (uint16) or -1 (int32); unlisted candidates are unranked and tied
+below every ranked one.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gen.c")
+_LIB = os.path.join(_HERE, "libgen.so")
+_lib = None
+
+GEN_FLAGS = ["-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall", "-Wno-unknown-pragmas"]
+
+
+def build() -> str:
+    """Compile gen.c into libgen.so next to it (always recompiles)."""
+    tmp = _LIB + ".tmp"
+    subprocess.check_call(["gcc", *GEN_FLAGS, _SRC, "-o", tmp, "-lm"])
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.gen_permutation.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32, i32p]
+    lib.gen_mallows.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32,
+                                ctypes.c_double, i32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                ctypes.c_int32, ctypes.c_int, ctypes.c_void_p]
+    lib.gen_pl_zipf.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32,
+                                ctypes.c_double, i32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int,
+                                ctypes.c_void_p]
+    lib.gen_uniform_int.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64,
+                                    ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    lib.gen_uniform_real.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_double,
+                                     ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
+    lib.gen_uniform_ballots.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.c_void_p]
+    for f in (lib.gen_permutation, lib.gen_mallows, lib.gen_pl_zipf, lib.gen_uniform_int,
+              lib.gen_uniform_real, lib.gen_uniform_ballots):
+        f.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != 0:
+        raise RuntimeError(f"{what} failed with code {rc}")
+
+
+def _i32p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def permutation(seed: int, stream: int, m: int) -> np.ndarray:
+    out = np.empty(m, dtype=np.int32)
+    _check(_load().gen_permutation(seed, stream, m, _i32p(out)), "gen_permutation")
+    return out
+
+
+def _ballot_dtype(m: int, dtype):
+    if dtype is None:
+        dtype = np.uint16 if m <= 65535 else np.int32
+    dtype = np.dtype(dtype)
+    if dtype not in (np.dtype(np.uint16), np.dtype(np.int32)):
+        raise ValueError("ballot dtype must be uint16 or int32")
+    return dtype
+
+
+def mallows(seed: int, n: int, m: int, phi: float, *, election: int = 0, L: int | None = None,
+            trunc_mod: int = 0, trunc_lt: int = 0, trunc_k: int = 0, ref_order=None,
+            dtype=None) -> np.ndarray:
+    """Mallows(phi) rankings around a seeded reference order.
+
+    Voter v is cut to its top ``trunc_k`` when ``v % trunc_mod < trunc_lt``.
+    """
+    dtype = _ballot_dtype(m, dtype)
+    L = m if L is None else L
+    if ref_order is None:
+        ref_order = permutation(seed, election, m)
+    ref_order = np.ascontiguousarray(ref_order, dtype=np.int32)
+    out = np.empty((n, L), dtype=dtype)
+    rc = _load().gen_mallows(seed, election, n, m, phi, _i32p(ref_order), L, trunc_mod, trunc_lt,
+                             trunc_k, int(dtype == np.int32), out.ctypes.data)
+    _check(rc, "gen_mallows")
+    return out
+
+
+def pl_zipf(seed: int, n: int, m: int, s: float, k: int, *, election: int = 0, L: int | None = None,
+            pop_order=None, dtype=None) -> np.ndarray:
+    """Top-k Plackett-Luce rankings with Zipf(s) weights over a seeded popularity order."""
+    dtype = _ballot_dtype(m, dtype)
+    L = k if L is None else L
+    if pop_order is None:
+        pop_order = permutation(seed, election, m)
+    pop_order = np.ascontiguousarray(pop_order, dtype=np.int32)
+    out = np.empty((n, max(L, 1)), dtype=dtype)
+    rc = _load().gen_pl_zipf(seed, election, n, m, s, _i32p(pop_order), k, max(L, 1),
+                             int(dtype == np.int32), out.ctypes.data)
+    _check(rc, "gen_pl_zipf")
+    return out
+
+
+def uniform_ballots(seed: int, n: int, m: int, L: int | None = None, *, min_len: int = 0,
+                    election: int = 0, dtype=None) -> np.ndarray:
+    """Random-length lists of distinct random ids (heavy ties, edge cases)."""
+    dtype = _ballot_dtype(m, dtype)
+    L = m if L is None else L
+    out = np.empty((n, L), dtype=dtype)
+    rc = _load().gen_uniform_ballots(seed, election, n, m, L, min_len, int(dtype == np.int32),
+                                     out.ctypes.data)
+    _check(rc, "gen_uniform_ballots")
+    return out
+
+
+def uniform_int(seed: int, stream: int, count: int, lo: int, hi: int) -> np.ndarray:
+    out = np.empty(count, dtype=np.int64)
+    rc = _load().gen_uniform_int(seed, stream, count, lo, hi,
+                                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    _check(rc, "gen_uniform_int")
+    return out
+
+
+def uniform_real(seed: int, stream: int, count: int, lo: float, hi: float) -> np.ndarray:
+    out = np.empty(count, dtype=np.float64)
+    rc = _load().gen_uniform_real(seed, stream, count, lo, hi,
+                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    _check(rc, "gen_uniform_real")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Named workloads.  Each stands in for a preference data set of the paper's
+# shape (dense tournament graphs built from truncated rankings, Section 5.1).
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Workload:
+    name: str
+    m: int
+    n: int
+    ballots: np.ndarray
+    d_dtype: str                     # "u16" or "i32": counter width of d and p
+    recipe: str
+    extra: dict = field(default_factory=dict)
+
+
+def plain_small(seed: int = 1001) -> Workload:
+    """m=64, n=1000 full Mallows(0.8) rankings; int32 counts."""
+    b = mallows(seed, 1000, 64, 0.8)
+    return Workload("mallows_m64_n1000", 64, 1000, b, "i32",
+                    "Mallows phi=0.8, full rankings, m=64, n=1000, seed %d" % seed)
+
+
+def plain_mid(seed: int = 1002, n: int = 60000, m: int = 4096) -> Workload:
+    """m=4096, n=60000 Mallows(0.97); voters with v % 10 < 3 cut to top-100; uint16 counts."""
+    b = mallows(seed, n, m, 0.97, trunc_mod=10, trunc_lt=3, trunc_k=100)
+    return Workload("mallows_m%d_n%d_top100x30pct" % (m, n), m, n, b, "u16",
+                    "Mallows phi=0.97, m=%d, n=%d, v%%10<3 truncated to top-100, seed %d" % (m, n, seed))
+
+
+def plain_large(seed: int = 1003, n: int = 1_000_000, m: int = 16384) -> Workload:
+    """m=16384, n=1e6 top-20 Plackett-Luce with Zipf(1.1) weights; int32 counts."""
+    b = pl_zipf(seed, n, m, 1.1, 20)
+    return Workload("plzipf_m%d_n%d_top20" % (m, n), m, n, b, "i32",
+                    "Plackett-Luce Zipf s=1.1, top-20, m=%d, n=%d, seed %d" % (m, n, seed))
