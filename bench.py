@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Benchmark of the Schulze hot path on one MI355X.
+
+A step is one pass of the whole path over one election whose ballots are
+already resident in HBM: pairwise counts -> widest-path closure -> winners
+-> ranking.  The default workload is m=4096 candidates, n=60000 voters drawn
+from Mallows(0.97) with 30% of the ballots cut to their top-100, uint16
+counters.
+
+Printed (one JSON line): throughput as m^3 max-min updates per second of the
+whole step (Gop/s), per-kernel times from HIP events recorded on the launch
+stream inside the timed region, the roofline of the dominant kernel and of
+the closure, and the CPU oracle timed on a bounded sample of the same
+workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks: 256 CUs x 64 lanes x 2.4 GHz 32-bit VALU lane-ops,
+# 8 TB/s HBM3E.
+VALU_LANE_OPS = 256 * 64 * 2.4e9
+HBM_BYTES = 8.0e12
+
+WORKLOADS = ("mid", "small", "large")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=WORKLOADS, default="mid")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-voters", type=int, default=3000)
+    return ap.parse_args()
+
+
+def make_workload(name):
+    import workload
+    return {"mid": workload.plain_mid, "small": workload.plain_small, "large": workload.plain_large}[name]()
+
+
+def cpu_baseline(wl, sample_voters):
+    """Oracle on a bounded sample: the count over the first `sample_voters`
+    ballots (scaled to all n), then weights, closure and ranking at full m."""
+    import oracle
+    ns = min(sample_voters, wl.n)
+    sample = wl.ballots[:ns]
+    t0 = time.perf_counter()
+    d = oracle.pairwise(sample, wl.m)
+    t_count = (time.perf_counter() - t0) * (wl.n / ns)
+    t0 = time.perf_counter()
+    w = oracle.weights(d, oracle.WINNING_VOTES)
+    p = oracle.closure(w)
+    oracle.rank(p)
+    t_rest = time.perf_counter() - t0
+    t_step = t_count + t_rest
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    return {
+        "value": wl.m ** 3 / t_step / 1e9,
+        "unit": "Gop/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"count over the first {ns} of {wl.n} ballots scaled by n/{ns} "
+                   f"({t_count:.1f} s scaled); weights+closure+ranking at full m={wl.m} ({t_rest:.1f} s)"),
+        "seconds_per_step": t_step,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2505_12976_amd as sz
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU available"}), flush=True)
+        sys.exit(1)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    t0 = time.time()
+    wl = make_workload(args.workload)
+    print(f"[bench] workload {wl.name} generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    m, n = wl.m, wl.n
+    ballots = torch.from_numpy(wl.ballots).to(dev)
+    ctx = sz.Context(0)
+    dcode = wl.d_dtype
+    tdtype = torch.uint16 if dcode == "u16" else torch.int32
+    d = torch.empty((m, m), dtype=tdtype, device=dev)
+    p = torch.empty((m, m), dtype=tdtype, device=dev)
+
+    def step():
+        ctx.pairwise(ballots, m, dtype=dcode, out=d)
+        ctx.closure(d, "winning_votes", out=p)
+        ctx.winners(p)
+        ctx.ranking(p)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    if ctx.device_error() != 0:
+        raise RuntimeError("device error during warmup")
+    print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+
+    ctx.reset_timing()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    ctx.set_timing(False)
+    ms_per_step = (t_end - t_start) * 1e3 / args.steps
+    print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
+
+    names = ["ballot_scan", "ballot_scatter", "count_dense", "count_sparse", "count_finish", "weights",
+             "fw_diag", "fw_panel", "fw_rest", "fw_store", "beaten_by", "rank_sort", "winners", "fill"]
+    kern = {}
+    for nm in names:
+        launches, total = ctx.kernel_time(nm)
+        if launches:
+            kern[nm] = {"launches_per_step": launches / args.steps, "ms_per_step": total / args.steps,
+                        "avg_launch_ms": total / launches}
+    closure_ms = sum(kern.get(k, {}).get("ms_per_step", 0.0) for k in
+                     ("weights", "fw_diag", "fw_panel", "fw_rest", "fw_store"))
+    count_ms = sum(kern.get(k, {}).get("ms_per_step", 0.0) for k in
+                   ("ballot_scan", "ballot_scatter", "count_dense", "count_sparse", "count_finish"))
+    dominant = max(kern, key=lambda k: kern[k]["ms_per_step"])
+
+    # algorithmic work of the two main kernels
+    n_full = int(np.count_nonzero((wl.ballots != (0xFFFF if wl.ballots.dtype == np.uint16 else -1)).sum(axis=1)
+                                  >= m - 1)) if wl.ballots.shape[1] >= m - 1 else 0
+    roof = None
+    if dominant == "count_dense":
+        # one comparison per (full ranking, unordered pair): one VALU lane-op each
+        work = n_full * m * (m - 1) / 2
+        avg = kern["count_dense"]["avg_launch_ms"] / 1e3
+        roof = {"bound": "alu", "kernel": "count_dense", "achieved": work / avg / 1e12,
+                "peak": VALU_LANE_OPS / 1e12, "unit": "Tops/s", "traffic": None}
+    elif dominant in ("fw_rest", "fw_panel", "fw_diag"):
+        ops_per_update = 1 if dcode == "u16" else 2
+        work = m ** 3 * ops_per_update
+        roof = {"bound": "alu", "kernel": "closure", "achieved": work / (closure_ms / 1e3) / 1e12,
+                "peak": VALU_LANE_OPS / 1e12, "unit": "Tops/s", "traffic": None}
+    else:
+        avg = kern[dominant]["avg_launch_ms"] / 1e3
+        roof = {"bound": "hbm", "kernel": dominant, "achieved": None, "peak": HBM_BYTES / 1e9,
+                "unit": "GB/s", "traffic": None}
+    if roof.get("achieved") is not None:
+        roof["frac"] = roof["achieved"] / roof["peak"]
+    ops_per_update = 1 if dcode == "u16" else 2
+    closure_roof = {"bound": "alu", "achieved": m ** 3 * ops_per_update / (closure_ms / 1e3) / 1e12,
+                    "peak": VALU_LANE_OPS / 1e12, "unit": "Tops/s",
+                    "updates_per_s": m ** 3 / (closure_ms / 1e3)}
+    closure_roof["frac"] = closure_roof["achieved"] / closure_roof["peak"]
+
+    out = {
+        "metric": "closure Gop/s (max-min) + elections/sec; learned-verify vs full-closure speedup",
+        "value": m ** 3 / (ms_per_step / 1e3) / 1e9,
+        "unit": "Gop/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dcode,
+        "data": "synthetic",
+        "config": {"workload": wl.name, "m": m, "n": n, "recipe": wl.recipe, "weight_mode": "winning_votes",
+                   "parallelism": "single GPU"},
+        "elections_per_s": 1e3 / ms_per_step,
+        "closure_ms": closure_ms,
+        "closure_gops": m ** 3 / (closure_ms / 1e3) / 1e9,
+        "count_ms": count_ms,
+        "kernels": kern,
+        "roofline": roof,
+        "roofline_closure": closure_roof,
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_voters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,165 @@
+/*
+ * schulze.h -- C ABI of the MI355X (gfx950) Schulze hot-path library.
+ *
+ * The library computes, for one election given as a preference profile,
+ * the quantities of the Schulze method as the paper defines them in its
+ * voting preliminaries (Section 2.1):
+ *
+ *   schulze_pairwise   d[x][y] = total weight of voters who strictly prefer
+ *                      candidate x to candidate y;
+ *   schulze_closure    p[x][y] = width of a widest x->y path in the weighted
+ *                      tournament graph built from d (width of a path = its
+ *                      smallest edge weight), computed by a blocked
+ *                      Floyd-Warshall over (max, min) -- the classical
+ *                      algorithm the paper compares against (Section 5.2);
+ *   schulze_winners    x is a Schulze winner iff no y beats x, where y beats
+ *                      x iff p[y][x] > p[x][y];
+ *   schulze_ranking    candidates ordered by the number of candidates that
+ *                      beat them, then by id.
+ *
+ * Conventions shared by every entry point:
+ *  - All array arguments are DEVICE pointers into memory the caller owns
+ *    (e.g. torch tensors); the library never frees them.  The context owns
+ *    only its internal workspace.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls enqueue work on that stream and return without waiting; outputs
+ *    are valid once the stream has been synchronised.
+ *  - Matrices are row-major with a leading dimension (ld*) in elements,
+ *    ld >= m.  Candidate ids are 0..m-1 (the paper numbers them 1..m).
+ *  - Errors found on the host (bad arguments, unsupported sizes, failed
+ *    allocation or launch) are returned at once as a negative code and
+ *    nothing is enqueued.  Errors found in the data (an invalid ballot, a
+ *    count that overflows uint16) are written to the context's device error
+ *    word and reported by schulze_get_device_error.  No C++ exception
+ *    crosses this boundary.
+ *  - A context is not thread-safe: use one context per host thread/stream.
+ */
+#ifndef SCHULZE_H
+#define SCHULZE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct schulze_ctx schulze_ctx;
+
+/* Counter width of d and p.  Closure values are a subset of {0} u values(d),
+ * so p fits the same type as d. */
+typedef enum { SCHULZE_U16 = 1, SCHULZE_I32 = 2 } schulze_dtype;
+
+/* Edge weight of the weighted tournament graph.
+ *  WINNING_VOTES: w[x][y] = d[x][y] if d[x][y] > d[y][x], else 0.
+ *  MARGIN:        w[x][y] = d[x][y] - d[y][x] if positive, else 0 -- the
+ *                 majority margin mu restricted to its positive part
+ *                 (Section 2.1).
+ * For profiles of full strict rankings both give the same winners and
+ * ranking (the margin is 2 d[x][y] - n, a strictly increasing function). */
+typedef enum { SCHULZE_WINNING_VOTES = 0, SCHULZE_MARGIN = 1 } schulze_weight_mode;
+
+enum {
+    SCHULZE_OK = 0,
+    SCHULZE_EINVAL = -1,       /* bad argument (null pointer, size, ld, enum) */
+    SCHULZE_ERANGE = -2,       /* counts do not fit the requested dtype */
+    SCHULZE_ENOMEM = -3,       /* workspace allocation failed */
+    SCHULZE_EDEVICE = -4,      /* HIP runtime error (launch, copy, device) */
+    SCHULZE_EBALLOT = -5,      /* ballot lists an id out of range or twice */
+    SCHULZE_EUNSUPPORTED = -6  /* valid request this build does not handle */
+};
+
+/* Create a context bound to HIP device `device`.  On success *ctx is set and
+ * SCHULZE_OK returned; on failure *ctx is NULL. */
+int schulze_create(schulze_ctx **ctx, int device);
+
+/* Release the context and its workspace.  Synchronises the device first.
+ * NULL is accepted. */
+void schulze_destroy(schulze_ctx *ctx);
+
+/* Static string for an error code (never NULL). */
+const char *schulze_strerror(int code);
+
+/* Wait for `stream`, copy the device error word to *err_host (SCHULZE_OK if
+ * no data error occurred since the last call) and reset it. */
+int schulze_get_device_error(schulze_ctx *ctx, void *stream, int32_t *err_host);
+
+/*
+ * Pairwise preference counts d (Section 2.1: profile of weak orders).
+ *
+ * ballots       n x L candidate ids, row-major, best first.  ballot_dtype
+ *               SCHULZE_U16 (uint16 ids, 0xFFFF = padding; needs m <= 65535)
+ *               or SCHULZE_I32 (int32 ids, any negative = padding).  Each row
+ *               lists its ranked candidates and ends at its first padding
+ *               entry; candidates not listed are tied below every listed one.
+ *               A row listing an id >= m or the same id twice sets the
+ *               device error word to SCHULZE_EBALLOT (d is then undefined).
+ * n, L, m       voters (n >= 0), row length (1 <= L <= m), candidates
+ *               (1 <= m <= 65535).
+ * voter_weight  NULL (every voter counts once) or n uint32 multiplicities.
+ * d_dtype       SCHULZE_U16 requires the total weight to be <= 65535: with
+ *               voter_weight == NULL this is checked on the host (n > 65535
+ *               -> SCHULZE_ERANGE); with weights, an overflowing count sets
+ *               the device error word to SCHULZE_ERANGE.  SCHULZE_I32 requires
+ *               counts < 2^31 (device error SCHULZE_ERANGE otherwise).
+ * d, ldd        output m x m matrix, d[x][x] = 0.
+ *
+ * Workspace: up to m*m*4 bytes plus about n*m*2 bytes for full rankings.
+ */
+int schulze_pairwise(schulze_ctx *ctx, void *stream, const void *ballots, int ballot_dtype,
+                     int64_t n, int32_t L, int32_t m, const uint32_t *voter_weight,
+                     int d_dtype, void *d, int64_t ldd);
+
+/*
+ * Widest-path closure (Section 2.1 "widest paths"; the Floyd-Warshall
+ * algorithm of Section 5.2, blocked).
+ *
+ * d, ldd   m x m pairwise counts (as written by schulze_pairwise), dtype.
+ * mode     edge weights built from d (schulze_weight_mode).
+ * p, ldp   output m x m: p[x][y] = width of a widest x->y path, 0 if y is
+ *          unreachable from x; p[x][x] = 0.  p must not overlap d.
+ * Exact integer arithmetic; results are independent of blocking.
+ */
+int schulze_closure(schulze_ctx *ctx, void *stream, const void *d, int64_t ldd, int32_t m,
+                    int dtype, int mode, void *p, int64_t ldp);
+
+/*
+ * Schulze winners (Section 2.1: a candidate no other candidate beats).
+ *
+ * p, ldp     closure from schulze_closure (dtype as given there).
+ * is_winner  m bytes: 1 for winners, 0 otherwise.
+ * n_winners  NULL or one device int32 receiving the number of winners
+ *            (always >= 1 for a closure produced by this library).
+ */
+int schulze_winners(schulze_ctx *ctx, void *stream, const void *p, int64_t ldp, int32_t m,
+                    int dtype, uint8_t *is_winner, int32_t *n_winners);
+
+/*
+ * Ranking (Section 2.1: the order R by p(a,b) >= p(b,a), winners on top).
+ *
+ * beaten_by  NULL or m int32: beaten_by[x] = number of y with p[y][x] > p[x][y].
+ * order      m int32: candidates sorted by (beaten_by ascending, id ascending).
+ *            Whenever a beats b, a comes before b; when R is a weak order its
+ *            classes are the runs of equal beaten_by, and the first run is the
+ *            winner set.
+ */
+int schulze_ranking(schulze_ctx *ctx, void *stream, const void *p, int64_t ldp, int32_t m,
+                    int dtype, int32_t *order, int32_t *beaten_by);
+
+/*
+ * Per-kernel timing (a profiling aid, off by default).  While enabled, every
+ * kernel the library launches is bracketed by HIP events on its own stream;
+ * schulze_kernel_time synchronises and returns the number of launches and
+ * their summed duration (milliseconds) for the named kernel since the last
+ * reset.  Names: "ballot_scan", "ballot_scatter", "count_dense",
+ * "count_sparse", "count_finish", "weights", "fw_diag", "fw_panel",
+ * "fw_rest", "fw_store", "beaten_by", "rank_sort", "winners".
+ */
+int schulze_set_timing(schulze_ctx *ctx, int enable);
+int schulze_kernel_time(schulze_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms);
+int schulze_reset_timing(schulze_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCHULZE_H */

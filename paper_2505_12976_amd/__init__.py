@@ -1,0 +1,224 @@
+"""Python binding of the MI355X Schulze library (``libschulze.so``).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+Tensors are torch tensors on the GPU; the library receives their device
+pointers and torch's current stream.  The entry points carry the C ABI's
+names (``include/schulze.h``):
+
+    pairwise(ballots, m, voter_weight=None, dtype="u16"|"i32") -> d
+    closure(d, mode="winning_votes"|"margin")                  -> p
+    winners(p)                                                  -> (is_winner, n_winners)
+    ranking(p)                                                  -> (order, beaten_by)
+
+A missing or unloadable library raises; nothing falls back to the CPU.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libschulze.so")
+
+OK, EINVAL, ERANGE, ENOMEM, EDEVICE, EBALLOT, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+U16, I32 = 1, 2
+WINNING_VOTES, MARGIN = 0, 1
+
+EXPORTS = (
+    "schulze_create", "schulze_destroy", "schulze_strerror", "schulze_get_device_error",
+    "schulze_pairwise", "schulze_closure", "schulze_winners", "schulze_ranking",
+    "schulze_set_timing", "schulze_kernel_time", "schulze_reset_timing",
+)
+
+_lib = None
+
+
+class SchulzeError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+def build() -> str:
+    from . import _build
+    return _build.build()
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libschulze.so (building it first only if it does not exist)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        build()
+    lib = ctypes.CDLL(path)
+    c_int, c_i32, c_i64, vp = ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    lib.schulze_create.argtypes = [ctypes.POINTER(vp), c_int]
+    lib.schulze_destroy.argtypes = [vp]
+    lib.schulze_destroy.restype = None
+    lib.schulze_strerror.argtypes = [c_int]
+    lib.schulze_strerror.restype = ctypes.c_char_p
+    lib.schulze_get_device_error.argtypes = [vp, vp, ctypes.POINTER(c_i32)]
+    lib.schulze_pairwise.argtypes = [vp, vp, vp, c_int, c_i64, c_i32, c_i32, vp, c_int, vp, c_i64]
+    lib.schulze_closure.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_int, vp, c_i64]
+    lib.schulze_winners.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, vp, vp]
+    lib.schulze_ranking.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, vp, vp]
+    lib.schulze_set_timing.argtypes = [vp, c_int]
+    lib.schulze_kernel_time.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(c_i64), ctypes.POINTER(ctypes.c_double)]
+    lib.schulze_reset_timing.argtypes = [vp]
+    for name in EXPORTS:
+        if name not in ("schulze_destroy", "schulze_strerror"):
+            getattr(lib, name).restype = c_int
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load_library().schulze_strerror(code).decode()
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != OK:
+        raise SchulzeError(rc, where)
+
+
+def _dtype_code(dtype) -> int:
+    import torch
+    if dtype in ("u16", U16, torch.uint16):
+        return U16
+    if dtype in ("i32", I32, torch.int32):
+        return I32
+    raise ValueError(f"unknown counter dtype {dtype!r}")
+
+
+def _torch_dtype(code: int):
+    import torch
+    return torch.uint16 if code == U16 else torch.int32
+
+
+def _mode_code(mode) -> int:
+    if mode in ("winning_votes", WINNING_VOTES):
+        return WINNING_VOTES
+    if mode in ("margin", MARGIN):
+        return MARGIN
+    raise ValueError(f"unknown weight mode {mode!r}")
+
+
+class Context:
+    """One library context bound to a GPU (one per host thread)."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.device = device
+        self._torch_device = torch.device("cuda", device)
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.schulze_create(ctypes.byref(h), device), "schulze_create")
+        self._h = h
+        self._lib = lib
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.schulze_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- helpers
+    def _stream(self):
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream(self._torch_device).cuda_stream)
+
+    def _dev(self, t, what):
+        if t.device != self._torch_device:
+            raise ValueError(f"{what} must live on {self._torch_device}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def device_error(self) -> int:
+        v = ctypes.c_int32(0)
+        _check(self._lib.schulze_get_device_error(self._h, self._stream(), ctypes.byref(v)),
+               "schulze_get_device_error")
+        return v.value
+
+    def raise_device_error(self) -> None:
+        code = self.device_error()
+        if code != OK:
+            raise SchulzeError(code, "device")
+
+    # -------------------------------------------------------------- entry points
+    def pairwise(self, ballots, m: int, voter_weight=None, dtype="i32", out=None):
+        """d[x][y] = weight of voters preferring x to y.  ballots: (n, L)
+        uint16 (0xFFFF pads) or int32 (negative pads) on the GPU."""
+        import torch
+        if ballots.dim() != 2 or not ballots.is_contiguous():
+            raise ValueError("ballots must be a contiguous (n, L) tensor")
+        if ballots.dtype == torch.uint16:
+            bcode = U16
+        elif ballots.dtype == torch.int32:
+            bcode = I32
+        else:
+            raise ValueError("ballots must be uint16 or int32")
+        n, L = ballots.shape
+        dcode = _dtype_code(dtype)
+        d = out if out is not None else torch.empty((m, m), dtype=_torch_dtype(dcode), device=self._torch_device)
+        wp = None
+        if voter_weight is not None:
+            if voter_weight.dtype != torch.uint32 or voter_weight.shape != (n,) or not voter_weight.is_contiguous():
+                raise ValueError("voter_weight must be a contiguous uint32 tensor of shape (n,)")
+            wp = self._dev(voter_weight, "voter_weight")
+        rc = self._lib.schulze_pairwise(self._h, self._stream(), self._dev(ballots, "ballots"), bcode, n, L, m,
+                                        wp, dcode, self._dev(d, "d"), d.stride(0))
+        _check(rc, "schulze_pairwise")
+        return d
+
+    def closure(self, d, mode="winning_votes", out=None):
+        """p[x][y] = width of a widest x->y path (zero diagonal)."""
+        import torch
+        m = d.shape[0]
+        dcode = _dtype_code(d.dtype)
+        p = out if out is not None else torch.empty_like(d)
+        rc = self._lib.schulze_closure(self._h, self._stream(), self._dev(d, "d"), d.stride(0), m, dcode,
+                                       _mode_code(mode), self._dev(p, "p"), p.stride(0))
+        _check(rc, "schulze_closure")
+        return p
+
+    def winners(self, p):
+        """(is_winner uint8[m], n_winners int32[1]) on the GPU."""
+        import torch
+        m = p.shape[0]
+        w = torch.empty(m, dtype=torch.uint8, device=self._torch_device)
+        nw = torch.empty(1, dtype=torch.int32, device=self._torch_device)
+        rc = self._lib.schulze_winners(self._h, self._stream(), self._dev(p, "p"), p.stride(0), m,
+                                       _dtype_code(p.dtype), self._dev(w, "is_winner"), self._dev(nw, "n_winners"))
+        _check(rc, "schulze_winners")
+        return w, nw
+
+    def ranking(self, p):
+        """(order int32[m], beaten_by int32[m]) on the GPU."""
+        import torch
+        m = p.shape[0]
+        order = torch.empty(m, dtype=torch.int32, device=self._torch_device)
+        beaten = torch.empty(m, dtype=torch.int32, device=self._torch_device)
+        rc = self._lib.schulze_ranking(self._h, self._stream(), self._dev(p, "p"), p.stride(0), m,
+                                       _dtype_code(p.dtype), self._dev(order, "order"), self._dev(beaten, "beaten_by"))
+        _check(rc, "schulze_ranking")
+        return order, beaten
+
+    # -------------------------------------------------------------- timing
+    def set_timing(self, enable: bool) -> None:
+        _check(self._lib.schulze_set_timing(self._h, int(bool(enable))), "schulze_set_timing")
+
+    def reset_timing(self) -> None:
+        _check(self._lib.schulze_reset_timing(self._h), "schulze_reset_timing")
+
+    def kernel_time(self, name: str):
+        """(launches, total milliseconds) for a kernel since the last reset."""
+        n = ctypes.c_int64(0)
+        ms = ctypes.c_double(0.0)
+        _check(self._lib.schulze_kernel_time(self._h, name.encode(), ctypes.byref(n), ctypes.byref(ms)),
+               "schulze_kernel_time")
+        return n.value, ms.value

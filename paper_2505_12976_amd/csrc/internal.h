@@ -1,0 +1,95 @@
+// Internal declarations of the Schulze GPU library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/schulze.h"
+
+// Workspace slots owned by a context.  Each slot is a grow-only device
+// buffer; a call that needs more than the slot holds reallocates it.
+enum WsSlot {
+    WS_BALLOT_META = 0,  // per-ballot listed length and class, counters
+    WS_POSITIONS,        // packed rank pairs of full rankings
+    WS_ACC32,            // m x m uint32 accumulator of the count
+    WS_ROWSUM,           // per-candidate uint32 sums
+    WS_CLOSURE,          // padded closure matrix
+    WS_RANK,             // ranking keys
+    WS_NUM_SLOTS
+};
+
+struct PendingTiming {
+    int name;
+    hipEvent_t start, stop;
+};
+
+struct schulze_ctx {
+    int device = 0;
+    int num_cus = 0;
+    int32_t *err = nullptr;  // device error word
+    void *ws[WS_NUM_SLOTS] = {};
+    size_t ws_bytes[WS_NUM_SLOTS] = {};
+    // per-kernel timing
+    bool timing = false;
+    std::vector<PendingTiming> pending;
+    std::vector<hipEvent_t> event_pool;
+    std::vector<int64_t> launches;
+    std::vector<double> total_ms;
+};
+
+// Kernel names used by the timing facility (index = id).
+enum KernelId {
+    K_BALLOT_SCAN = 0,
+    K_BALLOT_SCATTER,
+    K_COUNT_DENSE,
+    K_COUNT_SPARSE,
+    K_COUNT_FINISH,
+    K_WEIGHTS,
+    K_FW_DIAG,
+    K_FW_PANEL,
+    K_FW_REST,
+    K_FW_STORE,
+    K_BEATEN_BY,
+    K_RANK_SORT,
+    K_WINNERS,
+    K_FILL,
+    K_NUM_KERNELS
+};
+extern const char *const kKernelNames[K_NUM_KERNELS];
+
+// Device error word helpers (used inside kernels): the first error wins.
+__device__ inline void set_device_error(int32_t *err, int32_t code) {
+    atomicCAS(err, 0, code);
+}
+
+// Make sure `slot` holds at least `bytes`; returns SCHULZE_OK or ENOMEM.
+int ws_reserve(schulze_ctx *ctx, WsSlot slot, size_t bytes);
+
+// Bracket a launch with events when timing is on.
+void timing_begin(schulze_ctx *ctx, int kernel, hipStream_t s, int *token);
+void timing_end(schulze_ctx *ctx, int token, hipStream_t s);
+
+// Check the last launch; returns SCHULZE_OK or SCHULZE_EDEVICE.
+int launch_status();
+
+// Zero `words` 32-bit words with a fill kernel (graph-capture friendly).
+int fill_u32(schulze_ctx *ctx, hipStream_t s, uint32_t *ptr, size_t words, uint32_t value);
+
+// Bind the context's device to the calling thread.
+int bind_device(schulze_ctx *ctx);
+
+#define SCHULZE_LAUNCH(ctx, kid, stream, ...)                  \
+    do {                                                        \
+        int tok_;                                               \
+        timing_begin((ctx), (kid), (stream), &tok_);            \
+        __VA_ARGS__;                                            \
+        timing_end((ctx), tok_, (stream));                      \
+        int rc_ = launch_status();                              \
+        if (rc_ != SCHULZE_OK) return rc_;                      \
+    } while (0)
+
+static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
