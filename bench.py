@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--workload", choices=WORKLOADS, default="mid")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-voters", type=int, default=3000)
+    ap.add_argument("--closure-schedule", choices=("auto", "phased"), default="auto")
     return ap.parse_args()
 
 
@@ -97,6 +98,7 @@ def main():
     m, n = wl.m, wl.n
     ballots = torch.from_numpy(wl.ballots).to(dev)
     ctx = sz.Context(0)
+    ctx.set_closure_schedule(args.closure_schedule)
     dcode = wl.d_dtype
     tdtype = torch.uint16 if dcode == "u16" else torch.int32
     d = torch.empty((m, m), dtype=tdtype, device=dev)
@@ -127,8 +129,10 @@ def main():
     ms_per_step = (t_end - t_start) * 1e3 / args.steps
     print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
 
-    names = ["ballot_scan", "ballot_scatter", "count_dense", "count_sparse", "count_finish", "weights",
-             "fw_diag", "fw_panel", "fw_rest", "fw_store", "beaten_by", "rank_sort", "winners", "fill"]
+    names = ["ballot_scan", "route", "ballot_scatter", "count_dense", "count_trunc", "count_sparse", "count_finish",
+             "weights",
+             "fw_diag", "fw_panel", "fw_rest", "fw_persist", "fw_store", "beaten_by", "rank_sort", "winners",
+             "fill"]
     kern = {}
     for nm in names:
         launches, total = ctx.kernel_time(nm)
@@ -136,9 +140,10 @@ def main():
             kern[nm] = {"launches_per_step": launches / args.steps, "ms_per_step": total / args.steps,
                         "avg_launch_ms": total / launches}
     closure_ms = sum(kern.get(k, {}).get("ms_per_step", 0.0) for k in
-                     ("weights", "fw_diag", "fw_panel", "fw_rest", "fw_store"))
+                     ("weights", "fw_diag", "fw_panel", "fw_rest", "fw_persist", "fw_store"))
     count_ms = sum(kern.get(k, {}).get("ms_per_step", 0.0) for k in
-                   ("ballot_scan", "ballot_scatter", "count_dense", "count_sparse", "count_finish"))
+                   ("ballot_scan", "route", "ballot_scatter", "count_dense", "count_trunc", "count_sparse",
+                    "count_finish"))
     dominant = max(kern, key=lambda k: kern[k]["ms_per_step"])
 
     # algorithmic work of the two main kernels
@@ -151,7 +156,7 @@ def main():
         avg = kern["count_dense"]["avg_launch_ms"] / 1e3
         roof = {"bound": "alu", "kernel": "count_dense", "achieved": work / avg / 1e12,
                 "peak": VALU_LANE_OPS / 1e12, "unit": "Tops/s", "traffic": None}
-    elif dominant in ("fw_rest", "fw_panel", "fw_diag"):
+    elif dominant in ("fw_rest", "fw_panel", "fw_diag", "fw_persist"):
         ops_per_update = 1 if dcode == "u16" else 2
         work = m ** 3 * ops_per_update
         roof = {"bound": "alu", "kernel": "closure", "achieved": work / (closure_ms / 1e3) / 1e12,
@@ -182,7 +187,8 @@ def main():
         "dtype": dcode,
         "data": "synthetic",
         "config": {"workload": wl.name, "m": m, "n": n, "recipe": wl.recipe, "weight_mode": "winning_votes",
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU",
+                   "closure_schedule": args.closure_schedule},
         "elections_per_s": 1e3 / ms_per_step,
         "closure_ms": closure_ms,
         "closure_gops": m ** 3 / (closure_ms / 1e3) / 1e9,

@@ -146,13 +146,24 @@ int schulze_ranking(schulze_ctx *ctx, void *stream, const void *p, int64_t ldp, 
                     int dtype, int32_t *order, int32_t *beaten_by);
 
 /*
+ * Closure schedule.  AUTO (default): one persistent cooperative launch whose
+ * workgroups exchange the diagonal and panel tiles of each round through
+ * device memory and flags, falling back to PHASED when the device refuses a
+ * cooperative launch.  PHASED: three launches per round (diagonal, panels,
+ * rest).  Both give identical results.
+ */
+enum { SCHULZE_SCHEDULE_AUTO = 0, SCHULZE_SCHEDULE_PHASED = 1 };
+int schulze_set_closure_schedule(schulze_ctx *ctx, int schedule);
+
+/*
  * Per-kernel timing (a profiling aid, off by default).  While enabled, every
  * kernel the library launches is bracketed by HIP events on its own stream;
  * schulze_kernel_time synchronises and returns the number of launches and
  * their summed duration (milliseconds) for the named kernel since the last
- * reset.  Names: "ballot_scan", "ballot_scatter", "count_dense",
- * "count_sparse", "count_finish", "weights", "fw_diag", "fw_panel",
- * "fw_rest", "fw_store", "beaten_by", "rank_sort", "winners".
+ * reset.  Names: "ballot_scan", "route", "ballot_scatter", "count_dense",
+ * "count_trunc", "count_sparse", "count_finish", "weights", "fw_diag", "fw_panel",
+ * "fw_rest", "fw_persist", "fw_store", "beaten_by", "rank_sort",
+ * "winners", "fill".
  */
 int schulze_set_timing(schulze_ctx *ctx, int enable);
 int schulze_kernel_time(schulze_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms);

@@ -27,8 +27,9 @@ WINNING_VOTES, MARGIN = 0, 1
 EXPORTS = (
     "schulze_create", "schulze_destroy", "schulze_strerror", "schulze_get_device_error",
     "schulze_pairwise", "schulze_closure", "schulze_winners", "schulze_ranking",
-    "schulze_set_timing", "schulze_kernel_time", "schulze_reset_timing",
+    "schulze_set_timing", "schulze_kernel_time", "schulze_reset_timing", "schulze_set_closure_schedule",
 )
+SCHEDULE_AUTO, SCHEDULE_PHASED = 0, 1
 
 _lib = None
 
@@ -66,6 +67,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.schulze_set_timing.argtypes = [vp, c_int]
     lib.schulze_kernel_time.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(c_i64), ctypes.POINTER(ctypes.c_double)]
     lib.schulze_reset_timing.argtypes = [vp]
+    lib.schulze_set_closure_schedule.argtypes = [vp, c_int]
     for name in EXPORTS:
         if name not in ("schulze_destroy", "schulze_strerror"):
             getattr(lib, name).restype = c_int
@@ -207,6 +209,11 @@ class Context:
                                        _dtype_code(p.dtype), self._dev(order, "order"), self._dev(beaten, "beaten_by"))
         _check(rc, "schulze_ranking")
         return order, beaten
+
+    def set_closure_schedule(self, schedule: str) -> None:
+        """"auto" (one persistent launch) or "phased" (three launches per round)."""
+        code = {"auto": SCHEDULE_AUTO, "phased": SCHEDULE_PHASED}[schedule]
+        _check(self._lib.schulze_set_closure_schedule(self._h, code), "schulze_set_closure_schedule")
 
     # -------------------------------------------------------------- timing
     def set_timing(self, enable: bool) -> None:

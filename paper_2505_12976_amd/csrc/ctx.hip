@@ -8,7 +8,7 @@
 const char *const kKernelNames[K_NUM_KERNELS] = {
     "ballot_scan", "ballot_scatter", "count_dense", "count_sparse", "count_finish", "weights",
     "fw_diag",     "fw_panel",       "fw_rest",     "fw_store",     "beaten_by",    "rank_sort",
-    "winners",     "fill"};
+    "winners",     "fill",           "fw_persist",  "route",        "count_trunc"};
 
 extern "C" const char *schulze_strerror(int code) {
     switch (code) {
@@ -185,6 +185,12 @@ static int drain_timing(schulze_ctx *ctx) {
     }
     ctx->pending.clear();
     return rc;
+}
+
+extern "C" int schulze_set_closure_schedule(schulze_ctx *ctx, int schedule) {
+    if (!ctx || (schedule != SCHULZE_SCHEDULE_AUTO && schedule != SCHULZE_SCHEDULE_PHASED)) return SCHULZE_EINVAL;
+    ctx->force_phased = schedule == SCHULZE_SCHEDULE_PHASED;
+    return SCHULZE_OK;
 }
 
 extern "C" int schulze_set_timing(schulze_ctx *ctx, int enable) {

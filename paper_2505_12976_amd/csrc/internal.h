@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -14,10 +15,13 @@
 enum WsSlot {
     WS_BALLOT_META = 0,  // per-ballot listed length and class, counters
     WS_POSITIONS,        // packed rank pairs of full rankings
+    WS_TRUNC_POS,        // packed rank pairs of truncated ballots (U space)
     WS_ACC32,            // m x m uint32 accumulator of the count
     WS_ROWSUM,           // per-candidate uint32 sums
     WS_CLOSURE,          // padded closure matrix
     WS_RANK,             // ranking keys
+    WS_RING,             // closure tiles published once per round
+    WS_FLAGS,            // closure publication flags
     WS_NUM_SLOTS
 };
 
@@ -38,6 +42,8 @@ struct schulze_ctx {
     std::vector<hipEvent_t> event_pool;
     std::vector<int64_t> launches;
     std::vector<double> total_ms;
+    // closure schedule: false = one persistent launch when possible
+    bool force_phased = false;
 };
 
 // Kernel names used by the timing facility (index = id).
@@ -56,6 +62,9 @@ enum KernelId {
     K_RANK_SORT,
     K_WINNERS,
     K_FILL,
+    K_FW_PERSIST,
+    K_ROUTE,
+    K_COUNT_TRUNC,
     K_NUM_KERNELS
 };
 extern const char *const kKernelNames[K_NUM_KERNELS];

@@ -1,44 +1,62 @@
 // Pairwise preference counts d[x][y] (Section 2.1: profile of weak orders).
 //
 // d[x][y] is the total weight of voters who list x and list y later or not
-// at all.  Ballots take one of two routes:
+// at all.  Ballots are split by a scan into full rankings (at least m-1
+// listed candidates) and truncated ballots, which take different routes:
 //
-//  * full rankings (at least m-1 listed candidates): the rank of every
-//    candidate is scattered into a position array, two voters per 32-bit
-//    word (low half: voter 2q, high half: voter 2q+1).  For one (x, y) pair
-//    and one voter, the 16-bit difference t = (pos(x) - pos(y)) mod 2^16
-//    equals pos(x) - pos(y) + 2^16 [pos(x) < pos(y)].  Summed over voters,
+//  * Position counting.  The rank of every candidate is scattered into a
+//    position array, two voters per 32-bit word (low half: one voter, high
+//    half: the next).  For one (x, y) pair and one voter, the 16-bit
+//    difference t = (pos(x) - pos(y)) mod 2^16 equals
+//    pos(x) - pos(y) + 2^16 [pos(x) < pos(y)], so summed over voters
 //        sum t = Sx - Sy + 2^16 * #(x before y),
 //    where Sx is the sum of x's positions.  One v_pk_sub_u16 yields t for two
 //    voters and one v_dot2_u32_u16 adds both halves into a 32-bit
-//    accumulator, so each comparison costs one VALU lane-op; the count is
-//    recovered as (acc - Sx + Sy) >> 16, exact while fewer than 2^16 voters
-//    are summed at once.  Full rankings have no ties, so only tiles with
-//    x-block <= y-block are computed and d[y][x] = voters - d[x][y].
-//
-//  * truncated ballots: d[x][y] = R[x] - C[y][x], where R[x] is the weight of
-//    ballots listing x and C[y][x] the weight of ballots listing y before x;
-//    the listed pairs are scattered with atomics.
-//
-// Both routes accumulate into one m x m uint32 matrix that a final pass adds
-// to R and converts to the output dtype.
+//    accumulator: one VALU lane-op per comparison.  The count is
+//    (acc - Sx + Sy) >> 16, exact while fewer than 2^16 voters are summed.
+//    - Full rankings have no ties, so only tiles with x-block <= y-block are
+//      counted and d[y][x] = voters - d[x][y].
+//    - Truncated ballots are counted the same way over the candidates U that
+//      any truncated ballot lists (unlisted candidates share one sentinel
+//      position, so ties count for neither side), over all ordered tiles.
+//      One extra always-sentinel column gives R[x], the number of truncated
+//      ballots listing x, and d[x][y] = R[x] for x in U, y outside U.
+//  * Pair scattering, for truncated ballots when U is large: d[x][y] =
+//    R[x] - C[y][x], where C[y][x] is the weight of ballots listing y before
+//    x; the listed pairs are scattered with atomics.
+// A small decision kernel picks the cheaper truncated route on the device.
+// Everything accumulates into one m x m uint32 matrix that a final pass
+// completes and converts to the output dtype.
 #include "internal.h"
 
 namespace {
 
-constexpr int SCAN_THREADS = 256;
-constexpr int CT = 128;         // count tile (candidates per side)
-constexpr int VC = 32;          // voter pairs per staged chunk
+constexpr int CT = 128;           // count tile (candidates per side)
+constexpr int VC = 32;            // voter pairs per staged chunk
 constexpr int CNT_THREADS = 256;
-constexpr int SEG_PAIRS = 32767; // at most 65534 voters per exact segment
+constexpr int SEG_PAIRS = 32767;  // at most 65534 voters per exact segment
 constexpr int SEGC = SEG_PAIRS / VC;
-constexpr int SCATTER_CH = 8192; // candidates per LDS chunk of the scatter
+constexpr int SCATTER_CH = 8192;  // columns per LDS chunk of the scatters
+constexpr int LONG_CHUNK = 32;    // ballots per workgroup of the long-row scan
+constexpr int SHORT_PER_WAVE = 8; // ballots per wavefront of the short-row scan
+constexpr int NPART = 64;         // partial sums of the pair-scattering cost
+constexpr uint16_t UNSET = 0xFFFF;
 
-// Workspace layout of WS_BALLOT_META (int32 words).
+enum { MODE_SPARSE = 0, MODE_DENSE_U = 1 };
+
+typedef __attribute__((ext_vector_type(2))) unsigned short us2;
+
+// Workspace views (WS_BALLOT_META).
 struct Meta {
-    int32_t *counters;  // [0] = number of full rankings
-    int32_t *len;       // listed length per ballot
-    int32_t *full_src;  // slot -> ballot index for full rankings
+    int32_t *ctr;            // [0] full rankings [1] truncated ballots [2] route
+                             // [3] |U| [4] U-space pitch
+    unsigned long long *k2;  // NPART partial sums of k(k-1)/2 over truncated ballots
+    int32_t *len;            // listed length per ballot
+    int32_t *full_src;       // slot -> ballot of a full ranking
+    int32_t *trunc_src;      // slot -> ballot of a truncated ballot
+    uint8_t *in_u;           // candidate listed by some truncated ballot
+    int32_t *ulist;          // U-space index -> candidate
+    int32_t *umap;           // candidate -> U-space index or -1
 };
 
 __device__ inline int32_t read_id(const void *ballots, int dtype32, int64_t idx) {
@@ -51,130 +69,247 @@ __device__ inline int32_t read_id(const void *ballots, int dtype32, int64_t idx)
 }
 
 // ------------------------------------------------------------------ scan
-// One workgroup per ballot: listed length, id range and duplicate checks
-// (LDS bitmap over candidates), and the full/truncated split.
-__global__ __launch_bounds__(SCAN_THREADS) void k_ballot_scan(const void *__restrict__ ballots, int dtype32,
-                                                              int64_t n, int32_t L, int32_t m, Meta meta,
-                                                              int32_t *err) {
-    extern __shared__ uint32_t seen[];  // ceil(m/32) words
+// Listed length, id range check, full/truncated split (slots reserved once
+// per workgroup), candidates listed by truncated ballots, and the pair count
+// of the truncated ballots.
+__device__ inline void record_ballots(Meta meta, int nf, const int32_t *lf, int nt, const int32_t *lt) {
+    __shared__ int32_t base_f, base_t;
+    if (threadIdx.x == 0) {
+        base_f = nf ? atomicAdd(&meta.ctr[0], nf) : 0;
+        base_t = nt ? atomicAdd(&meta.ctr[1], nt) : 0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nf; i += blockDim.x) meta.full_src[base_f + i] = lf[i];
+    for (int i = threadIdx.x; i < nt; i += blockDim.x) meta.trunc_src[base_t + i] = lt[i];
+}
+
+// Long rows: one workgroup walks LONG_CHUNK ballots.
+__global__ __launch_bounds__(256) void k_scan_long(const void *__restrict__ ballots, int dtype32, int64_t n, int32_t L,
+                                                   int32_t m, Meta meta, int32_t *err) {
     __shared__ int32_t first_pad;
-    const int64_t v = blockIdx.x;
-    if (v >= n) return;
-    const int words = (m + 31) >> 5;
-    for (int i = threadIdx.x; i < words; i += SCAN_THREADS) seen[i] = 0u;
-    if (threadIdx.x == 0) first_pad = L;
-    __syncthreads();
-    const int64_t base = v * (int64_t)L;
-    for (int t = threadIdx.x; t < L; t += SCAN_THREADS)
-        if (read_id(ballots, dtype32, base + t) < 0) atomicMin(&first_pad, t);
-    __syncthreads();
-    const int k = first_pad;
+    __shared__ int32_t lf[LONG_CHUNK], lt[LONG_CHUNK];
+    __shared__ int32_t nf, nt;
+    const int64_t v0 = (int64_t)blockIdx.x * LONG_CHUNK;
+    if (threadIdx.x == 0) nf = nt = 0;
     bool bad = false;
-    for (int t = threadIdx.x; t < k; t += SCAN_THREADS) {
-        int32_t c = read_id(ballots, dtype32, base + t);
-        if (c >= m) {
-            bad = true;
-            continue;
+    unsigned long long k2 = 0;
+    for (int q = 0; q < LONG_CHUNK; ++q) {
+        const int64_t v = v0 + q;
+        if (v >= n) break;
+        __syncthreads();
+        if (threadIdx.x == 0) first_pad = L;
+        __syncthreads();
+        const int64_t base = v * (int64_t)L;
+        for (int t = threadIdx.x; t < L; t += 256)
+            if (read_id(ballots, dtype32, base + t) < 0) {
+                atomicMin(&first_pad, t);
+                break;
+            }
+        __syncthreads();
+        const int k = first_pad;
+        const bool trunc = k < m - 1;
+        for (int t = threadIdx.x; t < k; t += 256) {
+            const int32_t c = read_id(ballots, dtype32, base + t);
+            if (c >= m)
+                bad = true;
+            else if (trunc)
+                meta.in_u[c] = 1;
         }
-        uint32_t bit = 1u << (c & 31);
-        uint32_t old = atomicOr(&seen[c >> 5], bit);
-        if (old & bit) bad = true;
+        if (threadIdx.x == 0) {
+            meta.len[v] = k;
+            if (trunc) {
+                lt[nt++] = (int32_t)v;
+                k2 += (unsigned long long)k * (k - 1) / 2;
+            } else {
+                lf[nf++] = (int32_t)v;
+            }
+        }
     }
     if (bad) set_device_error(err, SCHULZE_EBALLOT);
+    if (threadIdx.x == 0 && k2) atomicAdd(&meta.k2[blockIdx.x % NPART], k2);
+    __syncthreads();
+    record_ballots(meta, nf, lf, nt, lt);
+}
+
+// Short rows (L <= 64): one lane per entry, SHORT_PER_WAVE ballots per wave.
+__global__ __launch_bounds__(256) void k_scan_short(const void *__restrict__ ballots, int dtype32, int64_t n, int32_t L,
+                                                    int32_t m, Meta meta, int32_t *err) {
+    constexpr int PER_WG = 4 * SHORT_PER_WAVE;
+    __shared__ int32_t lf[PER_WG], lt[PER_WG];
+    __shared__ int32_t nf, nt;
+    if (threadIdx.x == 0) nf = nt = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    bool bad = false;
+    unsigned long long k2 = 0;
+    for (int q = 0; q < SHORT_PER_WAVE; ++q) {
+        const int64_t v = (int64_t)blockIdx.x * PER_WG + wave * SHORT_PER_WAVE + q;
+        if (v >= n) break;
+        const int64_t base = v * (int64_t)L;
+        const int32_t c = lane < L ? read_id(ballots, dtype32, base + lane) : -1;
+        const uint64_t pad = __ballot(c < 0);
+        const int k = pad ? (int)__builtin_ctzll(pad) : 64;  // lanes >= L count as padding
+        const bool trunc = k < m - 1;
+        if (lane < k) {
+            if (c >= m)
+                bad = true;
+            else if (trunc)
+                meta.in_u[c] = 1;
+        }
+        if (lane == 0) {
+            meta.len[v] = k;
+            if (trunc) {
+                lt[atomicAdd(&nt, 1)] = (int32_t)v;
+                k2 += (unsigned long long)k * (k - 1) / 2;
+            } else {
+                lf[atomicAdd(&nf, 1)] = (int32_t)v;
+            }
+        }
+    }
+    if (__ballot(bad) && lane == 0) set_device_error(err, SCHULZE_EBALLOT);
+    if (lane == 0 && k2) atomicAdd(&meta.k2[(blockIdx.x * 4 + wave) % NPART], k2);
+    __syncthreads();
+    record_ballots(meta, nf, lf, nt, lt);
+}
+
+// ------------------------------------------------------------------ route decision
+// One workgroup: U-space compaction (prefix sum over candidates) and the
+// choice between the dense route over U and pair scattering for truncated
+// ballots.  Costs: dense ~ (n_T / 2) * pitch^2 lane-ops, scattering
+// ~ sum k(k-1)/2 atomics, an atomic charged as ATOMIC_COST lane-ops (about
+// the measured ratio of the two rates on MI355X).
+constexpr double ATOMIC_COST = 1024.0;
+
+__global__ __launch_bounds__(256) void k_route(int32_t m, Meta meta, int weighted, int64_t cap_words) {
+    __shared__ int32_t part[256];
+    const int32_t per = (m + 255) / 256;
+    const int32_t c0 = min(m, (int32_t)threadIdx.x * per), c1 = min(m, c0 + per);
+    int32_t cnt = 0;
+    for (int32_t c = c0; c < c1; ++c) cnt += meta.in_u[c] ? 1 : 0;
+    part[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {  // inclusive scan
+        const int32_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int32_t idx = part[threadIdx.x] - cnt;
+    for (int32_t c = c0; c < c1; ++c) {
+        if (meta.in_u[c]) {
+            meta.ulist[idx] = c;
+            meta.umap[c] = idx++;
+        } else {
+            meta.umap[c] = -1;
+        }
+    }
     if (threadIdx.x == 0) {
-        meta.len[v] = k;
-        if (k >= m - 1) {
-            int32_t slot = atomicAdd(&meta.counters[0], 1);
-            meta.full_src[slot] = (int32_t)v;
-        }
+        const int32_t nu = part[255];
+        const int32_t pitch = (nu + 1 + CT - 1) / CT * CT;  // room for one sentinel column
+        const int64_t n_t = meta.ctr[1];
+        unsigned long long k2 = 0;
+        for (int i = 0; i < NPART; ++i) k2 += meta.k2[i];
+        const int64_t pairs = (n_t + 1) / 2;
+        const double dense = (double)pairs * (double)pitch * (double)pitch;
+        const bool fits = pairs * (int64_t)pitch <= cap_words;
+        const bool use_dense = !weighted && fits && n_t > 0 && dense <= ATOMIC_COST * (double)k2;
+        meta.ctr[2] = use_dense ? MODE_DENSE_U : MODE_SPARSE;
+        meta.ctr[3] = nu;
+        meta.ctr[4] = pitch;
     }
 }
 
-// Short rows (L <= 64): one wavefront per ballot, one lane per entry.
-__global__ __launch_bounds__(SCAN_THREADS) void k_ballot_scan_short(const void *__restrict__ ballots, int dtype32,
-                                                                    int64_t n, int32_t L, int32_t m, Meta meta,
-                                                                    int32_t *err) {
-    const int lane = threadIdx.x & 63;
-    const int64_t v = (int64_t)blockIdx.x * (SCAN_THREADS / 64) + (threadIdx.x >> 6);
-    if (v >= n) return;
-    const int64_t base = v * (int64_t)L;
-    int32_t c = lane < L ? read_id(ballots, dtype32, base + lane) : -1;
-    uint64_t pad = __ballot(c < 0);
-    const int k = pad ? (int)__builtin_ctzll(pad) : 64;  // pad bit is set for every lane >= L
-    bool listed = lane < k;
-    bool bad = listed && c >= m;
-    // duplicate check: compare with every earlier listed entry
-    for (int j = 0; j < 64; ++j) {
-        int32_t cj = __shfl(c, j);
-        if (j < lane && listed && cj == c) bad = true;
-    }
-    if (__ballot(bad)) {
-        if (lane == 0) set_device_error(err, SCHULZE_EBALLOT);
-    }
-    if (lane == 0) {
-        meta.len[v] = k;
-        if (k >= m - 1) {
-            int32_t slot = atomicAdd(&meta.counters[0], 1);
-            meta.full_src[slot] = (int32_t)v;
-        }
-    }
-}
-
-// ------------------------------------------------------------------ scatter
-// One workgroup per voter pair q: positions of voters full_src[2q] (low
-// half) and full_src[2q+1] (high half, or 0 for the missing partner of an
-// odd count) for every candidate, in chunks of SCATTER_CH candidates staged
-// in LDS, written as rows of `pitch` words (columns >= m are 0).
-__global__ __launch_bounds__(256) void k_ballot_scatter(const void *__restrict__ ballots, int dtype32, int32_t L,
-                                                        int32_t m, int32_t pitch, Meta meta,
-                                                        uint32_t *__restrict__ pos) {
+// ------------------------------------------------------------------ scatters
+// One workgroup per voter pair q: positions of slots 2q (low half) and
+// 2q+1 (high half; 0 for the missing partner of an odd count), staged in
+// LDS in chunks of SCATTER_CH columns and written as rows of `pitch` words.
+// A ballot lists distinct candidates iff its entries leave exactly
+// (columns - listed) positions unset; anything else is a repeated id.
+template <bool FULL>
+__global__ __launch_bounds__(256) void k_scatter(const void *__restrict__ ballots, int dtype32, int32_t L, int32_t m,
+                                                 int32_t full_pitch, Meta meta, uint32_t *__restrict__ pos,
+                                                 int32_t *err) {
     __shared__ uint16_t buf[2 * SCATTER_CH];
-    const int32_t n_full = meta.counters[0];
+    __shared__ int32_t unset_cnt[2];
+    const int32_t count = FULL ? meta.ctr[0] : meta.ctr[1];
+    if (!FULL && meta.ctr[2] != MODE_DENSE_U) return;
     const int64_t q = blockIdx.x;
-    if (2 * q >= n_full) return;
-    const bool has_hi = 2 * q + 1 < n_full;
-    const int32_t src[2] = {meta.full_src[2 * q], has_hi ? meta.full_src[2 * q + 1] : -1};
+    if (2 * q >= count) return;
+    const int32_t pitch = FULL ? full_pitch : meta.ctr[4];
+    const int32_t ncols = FULL ? m : meta.ctr[3];  // real columns: candidates or U
+    const int32_t *srcs = FULL ? meta.full_src : meta.trunc_src;
+    const bool has_hi = 2 * q + 1 < count;
+    const int32_t src[2] = {srcs[2 * q], has_hi ? srcs[2 * q + 1] : -1};
+    if (threadIdx.x < 2) unset_cnt[threadIdx.x] = 0;
     for (int32_t c0 = 0; c0 < pitch; c0 += SCATTER_CH) {
         const int32_t cn = min(SCATTER_CH, pitch - c0);
         __syncthreads();
-        for (int i = threadIdx.x; i < cn; i += 256) {
-            const int32_t c = c0 + i;
-            // a ballot listing m-1 candidates leaves one unlisted: it is last
-            buf[2 * i] = c < m ? (uint16_t)(m - 1) : (uint16_t)0;
-            buf[2 * i + 1] = (c < m && has_hi) ? (uint16_t)(m - 1) : (uint16_t)0;
-        }
+        for (int i = threadIdx.x; i < 2 * cn; i += 256) buf[i] = UNSET;
         __syncthreads();
         for (int h = 0; h < 2; ++h) {
             if (src[h] < 0) continue;
             const int32_t k = meta.len[src[h]];
             const int64_t base = (int64_t)src[h] * L;
             for (int t = threadIdx.x; t < k; t += 256) {
-                const int32_t c = read_id(ballots, dtype32, base + t);
-                if (c >= c0 && c < c0 + cn) buf[2 * (c - c0) + h] = (uint16_t)t;
+                const int32_t id = read_id(ballots, dtype32, base + t);
+                if (id < 0 || id >= m) continue;  // reported by the scan
+                const int32_t col = FULL ? id : meta.umap[id];
+                if (col >= c0 && col < c0 + cn) buf[2 * (col - c0) + h] = (uint16_t)t;
             }
         }
         __syncthreads();
-        const uint32_t *b32 = reinterpret_cast<const uint32_t *>(buf);
-        for (int i = threadIdx.x; i < cn; i += 256) pos[q * (int64_t)pitch + c0 + i] = b32[i];
+        int32_t un0 = 0, un1 = 0;
+        for (int i = threadIdx.x; i < cn; i += 256) {
+            const int32_t col = c0 + i;
+            uint16_t lo = buf[2 * i], hi = buf[2 * i + 1];
+            if (col < ncols) {
+                un0 += lo == UNSET;
+                un1 += hi == UNSET;
+            }
+            if (FULL) {
+                // the candidate a ballot of m-1 entries leaves out is last
+                if (col >= m) lo = hi = 0;
+                if (lo == UNSET) lo = (uint16_t)(m - 1);
+                if (hi == UNSET) hi = has_hi ? (uint16_t)(m - 1) : (uint16_t)0;
+            } else {
+                // unlisted (and the sentinel column): one shared position
+                if (!has_hi) hi = 0;
+            }
+            pos[q * (int64_t)pitch + c0 + i] = (uint32_t)lo | ((uint32_t)hi << 16);
+        }
+        if (un0) atomicAdd(&unset_cnt[0], un0);
+        if (un1) atomicAdd(&unset_cnt[1], un1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int h = 0; h < 2; ++h) {
+            if (src[h] < 0) continue;
+            if (unset_cnt[h] != ncols - meta.len[src[h]]) set_device_error(err, SCHULZE_EBALLOT);
+        }
     }
 }
 
-// ------------------------------------------------------------------ dense count
-// Persistent kernel.  Work units are (tile, chunk of VC voter pairs) with
-// tiles (X, Y), X <= Y, over CT x CT candidate blocks; each workgroup takes a
-// contiguous range of units (so every workgroup does the same amount of
-// work) and flushes its accumulators into acc32 whenever the tile changes,
-// a segment of SEG_PAIRS pairs ends, or its range ends.
+// ------------------------------------------------------------------ position count
+// Persistent kernel.  Work units are (tile, chunk of VC voter pairs); each
+// workgroup takes a contiguous range of units (equal work per workgroup)
+// and flushes its accumulators into acc whenever the tile changes, a
+// segment of SEG_PAIRS pairs ends, or its range ends.
+//   SQUARE = false: full rankings, tiles X <= Y over candidates; the flush
+//                   also writes d[y][x] = voters - d[x][y].
+//   SQUARE = true:  truncated ballots over U space, all tiles (X, Y); U
+//                   indices map back through ulist; the sentinel column
+//                   y = |U| gives R[x].
 struct DenseArgs {
     const uint32_t *pos;
-    int32_t pitch;         // words per position row (multiple of CT)
+    int32_t pitch;  // full rankings: words per position row (multiple of CT)
     int32_t m;
-    const int32_t *counters;
-    uint32_t *acc;         // m x m
+    Meta meta;
+    uint32_t *acc;  // m x m
     int64_t lda;
+    uint32_t *rsum;
 };
 
-__device__ inline void tile_coords(int32_t t, int32_t nb, int32_t &X, int32_t &Y) {
+__device__ inline void tri_coords(int32_t t, int32_t nb, int32_t &X, int32_t &Y) {
     int32_t x = 0, start = 0;
     while (start + (nb - x) <= t) {
         start += nb - x;
@@ -184,18 +319,22 @@ __device__ inline void tile_coords(int32_t t, int32_t nb, int32_t &X, int32_t &Y
     Y = x + (t - start);
 }
 
-__global__ __launch_bounds__(CNT_THREADS, 2) void k_count_dense(DenseArgs a) {
+template <bool SQUARE>
+__global__ __launch_bounds__(CNT_THREADS, 2) void k_count_pos(DenseArgs a) {
     __shared__ __attribute__((aligned(16))) uint32_t xs[VC][CT];
     __shared__ __attribute__((aligned(16))) uint32_t ys[VC][CT];
     __shared__ uint32_t sred[4][2 * CT];
 
+    if (SQUARE && a.meta.ctr[2] != MODE_DENSE_U) return;
     const int tid = threadIdx.x;
     const int tx = tid & 15, ty = tid >> 4;
-    const int32_t n_full = a.counters[0];
-    const int64_t n_pairs = (n_full + 1) / 2;
+    const int32_t nvoters = SQUARE ? a.meta.ctr[1] : a.meta.ctr[0];
+    const int64_t n_pairs = (nvoters + 1) / 2;
     if (n_pairs == 0) return;
-    const int32_t nb = a.pitch / CT;
-    const int64_t ntiles = (int64_t)nb * (nb + 1) / 2;
+    const int32_t pitch = SQUARE ? a.meta.ctr[4] : a.pitch;
+    const int32_t nu = SQUARE ? a.meta.ctr[3] : a.m;
+    const int32_t nb = pitch / CT;
+    const int64_t ntiles = SQUARE ? (int64_t)nb * nb : (int64_t)nb * (nb + 1) / 2;
     const int64_t cpt = (n_pairs + VC - 1) / VC;  // chunks per tile
     const int64_t U = ntiles * cpt;
     const int64_t u0 = U * blockIdx.x / gridDim.x;
@@ -216,17 +355,26 @@ __global__ __launch_bounds__(CNT_THREADS, 2) void k_count_dense(DenseArgs a) {
     int32_t cur_tile = -1, X = 0, Y = 0;
     int64_t seg_p0 = 0, seg_p1 = 0;
 
+    auto coords = [&](int32_t t, int32_t &tX, int32_t &tY) {
+        if (SQUARE) {
+            tX = t / nb;
+            tY = t % nb;
+        } else {
+            tri_coords(t, nb, tX, tY);
+        }
+    };
+
     auto load_unit = [&](int64_t u, uint4 (&dst)[8]) {
         const int32_t t = (int32_t)(u / cpt);
         const int64_t chunk = u % cpt;
         int32_t tX, tY;
-        tile_coords(t, nb, tX, tY);
+        coords(t, tX, tY);
         const int32_t col = col4 < 32 ? tX * CT + col4 * 4 : tY * CT + (col4 - 32) * 4;
         const int64_t p0 = chunk * VC;
         for (int q = 0; q < 8; ++q) {
             const int64_t pr = p0 + prow + 4 * q;
             if (pr < n_pairs)
-                dst[q] = *reinterpret_cast<const uint4 *>(a.pos + pr * a.pitch + col);
+                dst[q] = *reinterpret_cast<const uint4 *>(a.pos + pr * pitch + col);
             else
                 dst[q] = make_uint4(0u, 0u, 0u, 0u);
         }
@@ -245,14 +393,22 @@ __global__ __launch_bounds__(CNT_THREADS, 2) void k_count_dense(DenseArgs a) {
             const int c = CT + tx * 8 + j;
             sy[j] = sred[0][c] + sred[1][c] + sred[2][c] + sred[3][c];
         }
-        const int64_t hi = min((int64_t)n_full, 2 * seg_p1);
+        const int64_t hi = min((int64_t)nvoters, 2 * seg_p1);
         const uint32_t nv = (uint32_t)max((int64_t)0, hi - 2 * seg_p0);
         for (int i = 0; i < 8; ++i) {
             const int32_t x = X * CT + ty * 8 + i;
             for (int j = 0; j < 8; ++j) {
                 const int32_t y = Y * CT + tx * 8 + j;
                 const uint32_t cnt = (acc[i][j] - sx[i] + sy[j]) >> 16;
-                if (x < a.m && y < a.m && x != y) {
+                if (SQUARE) {
+                    if (x < nu) {
+                        const int32_t gx = a.meta.ulist[x];
+                        if (y < nu && x != y)
+                            atomicAdd(&a.acc[(int64_t)gx * a.lda + a.meta.ulist[y]], cnt);
+                        else if (y == nu)
+                            atomicAdd(&a.rsum[gx], cnt);
+                    }
+                } else if (x < nu && y < nu && x != y) {
                     atomicAdd(&a.acc[(int64_t)x * a.lda + y], cnt);
                     if (X != Y) atomicAdd(&a.acc[(int64_t)y * a.lda + x], nv - cnt);
                 }
@@ -268,7 +424,7 @@ __global__ __launch_bounds__(CNT_THREADS, 2) void k_count_dense(DenseArgs a) {
         const int64_t chunk = u % cpt;
         if (t != cur_tile) {
             cur_tile = t;
-            tile_coords(t, nb, X, Y);
+            coords(t, X, Y);
             seg_p0 = chunk * VC;
         } else if (chunk % SEGC == 0) {
             seg_p0 = chunk * VC;
@@ -276,24 +432,19 @@ __global__ __launch_bounds__(CNT_THREADS, 2) void k_count_dense(DenseArgs a) {
         seg_p1 = min(n_pairs, (chunk + 1) * VC);
 
         __syncthreads();  // previous compute done with xs/ys
+        const us2 ones = {1, 1};
         for (int q = 0; q < 8; ++q) {
             const int pr = prow + 4 * q;
             uint32_t *dst = col4 < 32 ? &xs[pr][col4 * 4] : &ys[pr][(col4 - 32) * 4];
             *reinterpret_cast<uint4 *>(dst) = stage[q];
-            s4[0] = __builtin_amdgcn_udot2(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned short, stage[q].x),
-                                           (__attribute__((ext_vector_type(2))) unsigned short){1, 1}, s4[0], false);
-            s4[1] = __builtin_amdgcn_udot2(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned short, stage[q].y),
-                                           (__attribute__((ext_vector_type(2))) unsigned short){1, 1}, s4[1], false);
-            s4[2] = __builtin_amdgcn_udot2(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned short, stage[q].z),
-                                           (__attribute__((ext_vector_type(2))) unsigned short){1, 1}, s4[2], false);
-            s4[3] = __builtin_amdgcn_udot2(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned short, stage[q].w),
-                                           (__attribute__((ext_vector_type(2))) unsigned short){1, 1}, s4[3], false);
+            s4[0] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, stage[q].x), ones, s4[0], false);
+            s4[1] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, stage[q].y), ones, s4[1], false);
+            s4[2] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, stage[q].z), ones, s4[2], false);
+            s4[3] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, stage[q].w), ones, s4[3], false);
         }
         __syncthreads();
         if (u + 1 < u1) load_unit(u + 1, stage);  // overlaps the compute below
 
-        typedef __attribute__((ext_vector_type(2))) unsigned short us2;
-        const us2 ones = {1, 1};
 #pragma unroll 1
         for (int v = 0; v < VC; ++v) {
             const uint4 xa = *reinterpret_cast<const uint4 *>(&xs[v][ty * 8]);
@@ -324,46 +475,48 @@ __global__ __launch_bounds__(CNT_THREADS, 2) void k_count_dense(DenseArgs a) {
     }
 }
 
-// ------------------------------------------------------------------ sparse count
+// ------------------------------------------------------------------ pair scattering
 // One wavefront per truncated ballot: lane t handles listed entry t.  For
 // every earlier entry i < t the pair (c_i before c_t) adds the voter's
 // weight to C[c_i][c_t], i.e. subtracts it from acc[c_t][c_i]; every listed
-// entry adds the weight to R.
-__global__ __launch_bounds__(256) void k_count_sparse(const void *__restrict__ ballots, int dtype32, int64_t n,
-                                                      int32_t L, int32_t m, const uint32_t *__restrict__ weight,
-                                                      Meta meta, uint32_t *__restrict__ acc, int64_t lda,
-                                                      uint32_t *__restrict__ rsum) {
+// entry adds the weight to R.  Equal entries are a repeated id.
+__global__ __launch_bounds__(256) void k_count_pairs(const void *__restrict__ ballots, int dtype32, int32_t L,
+                                                     int32_t m, const uint32_t *__restrict__ weight, Meta meta,
+                                                     uint32_t *__restrict__ acc, int64_t lda,
+                                                     uint32_t *__restrict__ rsum, int32_t *err) {
+    if (meta.ctr[2] != MODE_SPARSE) return;
     const int lane = threadIdx.x & 63;
-    const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (v >= n) return;
+    const int64_t slot = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (slot >= meta.ctr[1]) return;
+    const int32_t v = meta.trunc_src[slot];
     const int32_t k = meta.len[v];
-    if (k >= m - 1) return;  // full ranking: dense route
     const uint32_t w = weight ? weight[v] : 1u;
-    if (w == 0u) return;
-    const int64_t base = v * (int64_t)L;
+    const int64_t base = (int64_t)v * L;
+    bool dup = false;
     for (int t = lane; t < k; t += 64) {
         const int32_t ct = read_id(ballots, dtype32, base + t);
-        if (ct >= m) continue;  // reported by the scan
-        atomicAdd(&rsum[ct], w);
+        if (ct < 0 || ct >= m) continue;  // reported by the scan
+        if (w) atomicAdd(&rsum[ct], w);
         uint32_t *row = acc + (int64_t)ct * lda;
         for (int i = 0; i < t; ++i) {
             const int32_t ci = read_id(ballots, dtype32, base + i);
-            if (ci < m) atomicSub(&row[ci], w);
+            if (ci == ct) dup = true;
+            if (w && ci >= 0 && ci < m) atomicSub(&row[ci], w);
         }
     }
+    if (__ballot(dup) && lane == 0) set_device_error(err, SCHULZE_EBALLOT);
 }
 
-// ------------------------------------------------------------------ weighted dense count
+// ------------------------------------------------------------------ weighted full rankings
 // Full rankings with voter weights: plain compare-and-add per voter (the
-// modular trick needs unit weights to bound the segment's total).
-__global__ __launch_bounds__(256) void k_count_dense_weighted(const void *__restrict__ ballots, int dtype32,
-                                                              int32_t L, int32_t m, const uint32_t *__restrict__ weight,
-                                                              Meta meta, const uint32_t *__restrict__ pos,
-                                                              int32_t pitch, uint32_t *__restrict__ acc, int64_t lda) {
+// modular trick needs unit weights to bound a segment's total).
+__global__ __launch_bounds__(256) void k_count_full_weighted(const uint32_t *__restrict__ weight, Meta meta,
+                                                             const uint32_t *__restrict__ pos, int32_t pitch, int32_t m,
+                                                             uint32_t *__restrict__ acc, int64_t lda) {
     // one thread per (x, y) pair of a 16 x 16 block, looping over voters
     const int32_t x = blockIdx.y * 16 + (threadIdx.x >> 4);
     const int32_t y = blockIdx.x * 16 + (threadIdx.x & 15);
-    const int32_t n_full = meta.counters[0];
+    const int32_t n_full = meta.ctr[0];
     if (x >= m || y >= m || x == y) return;
     uint32_t s = 0u;
     for (int32_t q = 0; 2 * q < n_full; ++q) {
@@ -377,23 +530,56 @@ __global__ __launch_bounds__(256) void k_count_dense_weighted(const void *__rest
 }
 
 // ------------------------------------------------------------------ finish
-// d[x][y] = acc[x][y] + R[x] for x != y, d[x][x] = 0; range-checked store.
+// d[x][y] = acc[x][y] plus the truncated ballots' R term, 0 on the
+// diagonal; range-checked store.
 template <typename T>
 __global__ __launch_bounds__(256) void k_count_finish(const uint32_t *__restrict__ acc, int64_t lda,
-                                                      const uint32_t *__restrict__ rsum, int32_t m, T *__restrict__ d,
-                                                      int64_t ldd, uint32_t limit, int32_t *err) {
+                                                      const uint32_t *__restrict__ rsum, Meta meta, int32_t m,
+                                                      T *__restrict__ d, int64_t ldd, uint32_t limit, int32_t *err) {
     const int32_t col_blocks = (m + 255) / 256;
     const int32_t x = blockIdx.x / col_blocks;
     const int32_t y = (blockIdx.x % col_blocks) * 256 + threadIdx.x;
     if (y >= m) return;
+    const bool dense_u = meta.ctr[2] == MODE_DENSE_U;
     uint32_t v = 0u;
-    if (x != y) v = acc[(int64_t)x * lda + y] + rsum[x];
+    if (x != y) {
+        v = acc[(int64_t)x * lda + y];
+        // pair scattering: acc holds -C^T, add R[x]; dense over U: U x U is
+        // complete, x in U beats every y outside U on the R[x] ballots
+        if (!dense_u || (meta.in_u[x] && !meta.in_u[y])) v += rsum[x];
+    }
     if (v > limit) {
         set_device_error(err, SCHULZE_ERANGE);
         v = limit;
     }
     d[(int64_t)x * ldd + y] = (T)v;
 }
+
+// Byte layout of WS_BALLOT_META for n ballots and m candidates.
+struct MetaLayout {
+    size_t ctr, k2, len, full_src, trunc_src, in_u, ulist, umap, total;
+    MetaLayout(int64_t n, int32_t m) {
+        size_t o = 0;
+        auto take = [&](size_t bytes) {
+            size_t at = o;
+            o += (bytes + 255) / 256 * 256;
+            return at;
+        };
+        ctr = take(64 * sizeof(int32_t));
+        k2 = take(NPART * sizeof(unsigned long long));
+        len = take(sizeof(int32_t) * (size_t)n);
+        full_src = take(sizeof(int32_t) * (size_t)n);
+        trunc_src = take(sizeof(int32_t) * (size_t)n);
+        in_u = take((size_t)m);
+        ulist = take(sizeof(int32_t) * (size_t)m);
+        umap = take(sizeof(int32_t) * (size_t)m);
+        total = o;
+    }
+};
+
+// Truncated positions in U space are reserved up to this many bytes; beyond
+// it the route decision falls back to pair scattering.
+constexpr size_t TRUNC_POS_CAP = (size_t)1 << 30;
 
 }  // namespace
 
@@ -411,67 +597,97 @@ extern "C" int schulze_pairwise(schulze_ctx *ctx, void *stream, const void *ball
     hipStream_t s = (hipStream_t)stream;
     const int dtype32 = ballot_dtype == SCHULZE_I32;
     const int32_t pitch = (int32_t)round_up(m, CT);
-
-    int rc;
-    if ((rc = ws_reserve(ctx, WS_BALLOT_META, sizeof(int32_t) * (size_t)(64 + 2 * n))) != SCHULZE_OK) return rc;
-    if ((rc = ws_reserve(ctx, WS_ACC32, sizeof(uint32_t) * (size_t)m * m)) != SCHULZE_OK) return rc;
-    if ((rc = ws_reserve(ctx, WS_ROWSUM, sizeof(uint32_t) * (size_t)m)) != SCHULZE_OK) return rc;
     const int64_t max_pairs = (n + 1) / 2;
     const bool may_have_full = L >= m - 1 && n > 0;
+    const bool may_have_trunc = n > 0;  // a row may always end early
+    const int64_t upitch_max = round_up((int64_t)m + 1, CT);
+    const size_t tpos_bytes = may_have_trunc && !voter_weight
+                                  ? std::min(TRUNC_POS_CAP, sizeof(uint32_t) * (size_t)max_pairs * (size_t)upitch_max)
+                                  : 0;
+
+    const MetaLayout lay(n, m);
+    int rc;
+    if ((rc = ws_reserve(ctx, WS_BALLOT_META, lay.total)) != SCHULZE_OK) return rc;
+    if ((rc = ws_reserve(ctx, WS_ACC32, sizeof(uint32_t) * (size_t)m * m)) != SCHULZE_OK) return rc;
+    if ((rc = ws_reserve(ctx, WS_ROWSUM, sizeof(uint32_t) * (size_t)m)) != SCHULZE_OK) return rc;
     if (may_have_full &&
         (rc = ws_reserve(ctx, WS_POSITIONS, sizeof(uint32_t) * (size_t)max_pairs * pitch)) != SCHULZE_OK)
         return rc;
+    if (tpos_bytes && (rc = ws_reserve(ctx, WS_TRUNC_POS, tpos_bytes)) != SCHULZE_OK) return rc;
 
-    int32_t *mw = static_cast<int32_t *>(ctx->ws[WS_BALLOT_META]);
-    Meta meta{mw, mw + 64, mw + 64 + n};
+    char *mb = static_cast<char *>(ctx->ws[WS_BALLOT_META]);
+    Meta meta{reinterpret_cast<int32_t *>(mb + lay.ctr),
+              reinterpret_cast<unsigned long long *>(mb + lay.k2),
+              reinterpret_cast<int32_t *>(mb + lay.len),
+              reinterpret_cast<int32_t *>(mb + lay.full_src),
+              reinterpret_cast<int32_t *>(mb + lay.trunc_src),
+              reinterpret_cast<uint8_t *>(mb + lay.in_u),
+              reinterpret_cast<int32_t *>(mb + lay.ulist),
+              reinterpret_cast<int32_t *>(mb + lay.umap)};
     uint32_t *acc = static_cast<uint32_t *>(ctx->ws[WS_ACC32]);
     uint32_t *rsum = static_cast<uint32_t *>(ctx->ws[WS_ROWSUM]);
-    uint32_t *pos = static_cast<uint32_t *>(ctx->ws[WS_POSITIONS]);
     const int64_t lda = m;
 
-    if ((rc = fill_u32(ctx, s, (uint32_t *)meta.counters, 64, 0u)) != SCHULZE_OK) return rc;
+    // counters, partial sums and the U bitmap start at zero
+    if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(mb + lay.ctr), (lay.len - lay.ctr) / 4, 0u)) !=
+        SCHULZE_OK)
+        return rc;
+    if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(mb + lay.in_u), (lay.ulist - lay.in_u) / 4, 0u)) !=
+        SCHULZE_OK)
+        return rc;
     if ((rc = fill_u32(ctx, s, acc, (size_t)m * m, 0u)) != SCHULZE_OK) return rc;
     if ((rc = fill_u32(ctx, s, rsum, (size_t)m, 0u)) != SCHULZE_OK) return rc;
 
     if (n > 0) {
         if (L <= 64) {
+            constexpr int per_wg = 4 * SHORT_PER_WAVE;
             SCHULZE_LAUNCH(ctx, K_BALLOT_SCAN, s,
-                           k_ballot_scan_short<<<dim3((unsigned)ceil_div(n, SCAN_THREADS / 64)), dim3(SCAN_THREADS),
-                                                 0, s>>>(ballots, dtype32, n, L, m, meta, ctx->err));
+                           k_scan_short<<<dim3((unsigned)ceil_div(n, per_wg)), dim3(256), 0, s>>>(
+                               ballots, dtype32, n, L, m, meta, ctx->err));
         } else {
-            const size_t lds = sizeof(uint32_t) * (size_t)((m + 31) / 32);
             SCHULZE_LAUNCH(ctx, K_BALLOT_SCAN, s,
-                           k_ballot_scan<<<dim3((unsigned)n), dim3(SCAN_THREADS), lds, s>>>(ballots, dtype32, n, L,
-                                                                                           m, meta, ctx->err));
+                           k_scan_long<<<dim3((unsigned)ceil_div(n, LONG_CHUNK)), dim3(256), 0, s>>>(
+                               ballots, dtype32, n, L, m, meta, ctx->err));
         }
-        // full rankings (only possible when L >= m - 1)
+        SCHULZE_LAUNCH(ctx, K_ROUTE, s,
+                       k_route<<<dim3(1), dim3(256), 0, s>>>(m, meta, voter_weight != nullptr,
+                                                             (int64_t)(tpos_bytes / sizeof(uint32_t))));
+        const unsigned cgrid = (unsigned)ctx->num_cus * 2;
         if (may_have_full) {
+            uint32_t *pos = static_cast<uint32_t *>(ctx->ws[WS_POSITIONS]);
             SCHULZE_LAUNCH(ctx, K_BALLOT_SCATTER, s,
-                           k_ballot_scatter<<<dim3((unsigned)max_pairs), dim3(256), 0, s>>>(ballots, dtype32, L, m,
-                                                                                           pitch, meta, pos));
+                           k_scatter<true><<<dim3((unsigned)max_pairs), dim3(256), 0, s>>>(
+                               ballots, dtype32, L, m, pitch, meta, pos, ctx->err));
             if (!voter_weight) {
-                DenseArgs da{pos, pitch, m, meta.counters, acc, lda};
-                const unsigned grid = (unsigned)ctx->num_cus * 2;
-                SCHULZE_LAUNCH(ctx, K_COUNT_DENSE, s, k_count_dense<<<dim3(grid), dim3(CNT_THREADS), 0, s>>>(da));
+                DenseArgs da{pos, pitch, m, meta, acc, lda, rsum};
+                SCHULZE_LAUNCH(ctx, K_COUNT_DENSE, s, k_count_pos<false><<<dim3(cgrid), dim3(CNT_THREADS), 0, s>>>(da));
             } else {
                 dim3 grid((unsigned)ceil_div(m, 16), (unsigned)ceil_div(m, 16));
                 SCHULZE_LAUNCH(ctx, K_COUNT_DENSE, s,
-                               k_count_dense_weighted<<<grid, dim3(256), 0, s>>>(ballots, dtype32, L, m, voter_weight,
-                                                                                 meta, pos, pitch, acc, lda));
+                               k_count_full_weighted<<<grid, dim3(256), 0, s>>>(voter_weight, meta, pos, pitch, m, acc,
+                                                                               lda));
             }
         }
+        if (tpos_bytes) {
+            uint32_t *tpos = static_cast<uint32_t *>(ctx->ws[WS_TRUNC_POS]);
+            SCHULZE_LAUNCH(ctx, K_BALLOT_SCATTER, s,
+                           k_scatter<false><<<dim3((unsigned)max_pairs), dim3(256), 0, s>>>(
+                               ballots, dtype32, L, m, 0, meta, tpos, ctx->err));
+            DenseArgs da{tpos, 0, m, meta, acc, lda, rsum};
+            SCHULZE_LAUNCH(ctx, K_COUNT_TRUNC, s, k_count_pos<true><<<dim3(cgrid), dim3(CNT_THREADS), 0, s>>>(da));
+        }
         SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
-                       k_count_sparse<<<dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, s>>>(
-                           ballots, dtype32, n, L, m, voter_weight, meta, acc, lda, rsum));
+                       k_count_pairs<<<dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, s>>>(
+                           ballots, dtype32, L, m, voter_weight, meta, acc, lda, rsum, ctx->err));
     }
     dim3 fgrid((unsigned)(ceil_div(m, 256) * m));
     if (d_dtype == SCHULZE_U16) {
         SCHULZE_LAUNCH(ctx, K_COUNT_FINISH, s,
-                       k_count_finish<uint16_t><<<fgrid, dim3(256), 0, s>>>(acc, lda, rsum, m, (uint16_t *)d, ldd,
+                       k_count_finish<uint16_t><<<fgrid, dim3(256), 0, s>>>(acc, lda, rsum, meta, m, (uint16_t *)d, ldd,
                                                                             65535u, ctx->err));
     } else {
         SCHULZE_LAUNCH(ctx, K_COUNT_FINISH, s,
-                       k_count_finish<int32_t><<<fgrid, dim3(256), 0, s>>>(acc, lda, rsum, m, (int32_t *)d, ldd,
+                       k_count_finish<int32_t><<<fgrid, dim3(256), 0, s>>>(acc, lda, rsum, meta, m, (int32_t *)d, ldd,
                                                                            (uint32_t)INT32_MAX, ctx->err));
     }
     return SCHULZE_OK;

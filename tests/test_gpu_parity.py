@@ -37,8 +37,9 @@ def ctx():
     c.close()
 
 
-def gpu_path(ctx, ballots, m, dtype="i32", mode="winning_votes", weight=None):
+def gpu_path(ctx, ballots, m, dtype="i32", mode="winning_votes", weight=None, schedule="auto"):
     import torch
+    ctx.set_closure_schedule(schedule)
     b = torch.from_numpy(np.ascontiguousarray(ballots)).cuda()
     wt = None if weight is None else torch.from_numpy(np.ascontiguousarray(weight, dtype=np.uint32)).cuda()
     d = ctx.pairwise(b, m, voter_weight=wt, dtype=dtype)
@@ -68,29 +69,34 @@ def assert_same(got, want, tag):
     assert got["n_winners"] == int(want["is_winner"].sum()), tag
 
 
-def check_case(ctx, ballots, m, dtype, mode, weight=None, tag=""):
-    log(f"[case] {tag} m={m} n={ballots.shape[0]} L={ballots.shape[1]} dtype={dtype} mode={mode}")
+def check_case(ctx, ballots, m, dtype, mode, weight=None, tag="", schedules=("auto",)):
     want = oracle.schulze(ballots, m, oracle.MARGIN if mode == "margin" else oracle.WINNING_VOTES, weight)
-    got = gpu_path(ctx, ballots, m, dtype, mode, weight)
-    assert_same(got, want, tag)
+    for sched in schedules:
+        log(f"[case] {tag} m={m} n={ballots.shape[0]} L={ballots.shape[1]} dtype={dtype} mode={mode} "
+            f"closure={sched}")
+        got = gpu_path(ctx, ballots, m, dtype, mode, weight, schedule=sched)
+        assert_same(got, want, f"{tag}/{sched}")
 
 
-SIZES = [1, 2, 3, 7, 31, 64, 65, 127, 128, 129, 200, 257, 700]
+SIZES = [1, 2, 3, 7, 31, 64, 65, 127, 128, 129, 200, 257, 700, 2100]
+
+
+BOTH = ("auto", "phased")
 
 
 @pytest.mark.parametrize("m", SIZES)
 def test_full_mallows(ctx, m):
     b = workload.mallows(100 + m, 301, m, 0.9)
-    check_case(ctx, b, m, "i32", "winning_votes", tag="full-mallows")
-    check_case(ctx, b, m, "u16", "margin", tag="full-mallows")
+    check_case(ctx, b, m, "i32", "winning_votes", tag="full-mallows", schedules=BOTH)
+    check_case(ctx, b, m, "u16", "margin", tag="full-mallows", schedules=BOTH)
 
 
 @pytest.mark.parametrize("m", SIZES)
 def test_truncated_mixture(ctx, m):
     k = max(1, m // 3)
     b = workload.mallows(200 + m, 257, m, 0.95, trunc_mod=5, trunc_lt=2, trunc_k=k)
-    check_case(ctx, b, m, "u16", "winning_votes", tag="mallows-truncated")
-    check_case(ctx, b, m, "i32", "margin", tag="mallows-truncated")
+    check_case(ctx, b, m, "u16", "winning_votes", tag="mallows-truncated", schedules=BOTH)
+    check_case(ctx, b, m, "i32", "margin", tag="mallows-truncated", schedules=BOTH)
 
 
 @pytest.mark.parametrize("m", [5, 64, 130, 300])
@@ -98,6 +104,13 @@ def test_pl_topk_int32_ballots(ctx, m):
     b = workload.pl_zipf(300 + m, 999, m, 1.1, min(20, m), dtype=np.int32)
     check_case(ctx, b, m, "i32", "winning_votes", tag="pl-zipf")
     check_case(ctx, b, m, "i32", "margin", tag="pl-zipf")
+
+
+@pytest.mark.parametrize("m,n,k", [(2500, 3000, 5), (1500, 4001, 3)])
+def test_short_lists_many_candidates(ctx, m, n, k):
+    """Short ballots over many candidates: the pair-scattering route."""
+    b = workload.pl_zipf(600 + m, n, m, 1.0, k)
+    check_case(ctx, b, m, "i32", "winning_votes", tag="short-lists")
 
 
 @pytest.mark.parametrize("m", [4, 65, 150])
