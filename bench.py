@@ -30,6 +30,26 @@ HBM_BYTES = 8.0e12
 WORKLOADS = ("mid", "small", "large")
 
 
+def measured_traffic(kernel, workload_name):
+    """HBM bytes per launch recorded in profiles/traffic.txt, or None when no
+    record exists or the kernel's source changed since it was measured."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, wl, src, sha, fetch, write = line.split()[:6]
+        if k != kernel or wl != workload_name:
+            continue
+        with open(os.path.join(ROOT, src), "rb") as f:
+            if not hashlib.sha256(f.read()).hexdigest().startswith(sha):
+                return None
+        return float(fetch) + float(write)
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -39,6 +59,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-voters", type=int, default=3000)
     ap.add_argument("--closure-schedule", choices=("auto", "phased"), default="auto")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the timed steps, copy a 1 GiB buffer once (a known-size reference "
+                         "for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -155,12 +178,14 @@ def main():
         work = n_full * m * (m - 1) / 2
         avg = kern["count_dense"]["avg_launch_ms"] / 1e3
         roof = {"bound": "alu", "kernel": "count_dense", "achieved": work / avg / 1e12,
-                "peak": VALU_LANE_OPS / 1e12, "unit": "Tops/s", "traffic": None}
+                "peak": VALU_LANE_OPS / 1e12, "unit": "Tops/s",
+                "traffic": measured_traffic("count_dense", wl.name)}
     elif dominant in ("fw_rest", "fw_panel", "fw_diag", "fw_persist"):
         ops_per_update = 1 if dcode == "u16" else 2
         work = m ** 3 * ops_per_update
         roof = {"bound": "alu", "kernel": "closure", "achieved": work / (closure_ms / 1e3) / 1e12,
-                "peak": VALU_LANE_OPS / 1e12, "unit": "Tops/s", "traffic": None}
+                "peak": VALU_LANE_OPS / 1e12, "unit": "Tops/s",
+                "traffic": measured_traffic("fw_persist", wl.name)}
     else:
         avg = kern[dominant]["avg_launch_ms"] / 1e3
         roof = {"bound": "hbm", "kernel": dominant, "achieved": None, "peak": HBM_BYTES / 1e9,
@@ -172,6 +197,7 @@ def main():
                     "peak": VALU_LANE_OPS / 1e12, "unit": "Tops/s",
                     "updates_per_s": m ** 3 / (closure_ms / 1e3)}
     closure_roof["frac"] = closure_roof["achieved"] / closure_roof["peak"]
+    closure_roof["traffic"] = measured_traffic("fw_persist", wl.name)
 
     out = {
         "metric": "closure Gop/s (max-min) + elections/sec; learned-verify vs full-closure speedup",
@@ -197,6 +223,14 @@ def main():
         "roofline": roof,
         "roofline_closure": closure_roof,
     }
+    if args.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.int32, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = src.numel() * src.element_size()
+        del src, dst
     ctx.close()
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
