@@ -146,6 +146,51 @@ int schulze_ranking(schulze_ctx *ctx, void *stream, const void *p, int64_t ldp, 
                     int dtype, int32_t *order, int32_t *beaten_by);
 
 /*
+ * Edge weights of the weighted tournament graph (Section 2.1), the input of
+ * the widest-path computations below.
+ *
+ * d, ldd    m x m pairwise counts; dtype as for schulze_closure.
+ * mode      schulze_weight_mode.
+ * w, ldw    NULL or output m x m: w[i][j] = weight of edge (i, j), 0 = no edge.
+ * wt, ldwt  NULL or output m x m transposed weights: wt[j][i] = w[i][j]
+ *           (the single-target direction reads it row by row).
+ * At least one of w, wt must be given.
+ */
+int schulze_weights(schulze_ctx *ctx, void *stream, const void *d, int64_t ldd, int32_t m,
+                    int dtype, int mode, void *w, int64_t ldw, void *wt, int64_t ldwt);
+
+/*
+ * Single-source widest paths: out[v] = p(source, v), the width of a widest
+ * source->v path (Section 2.1), out[source] = 0.  Given transposed weights
+ * it yields the single-target widths p(v, source).  Exact: (max, min)
+ * relaxation sweeps over the rows whose value grew, to the fixpoint, in one
+ * cooperative launch.  Returns SCHULZE_EDEVICE if the device refuses a
+ * cooperative launch.
+ */
+int schulze_widest_from(schulze_ctx *ctx, void *stream, const void *w, int64_t ldw, int32_t m,
+                        int dtype, int32_t source, void *out);
+
+/*
+ * Exact winner check of one candidate, the deterministic form of the
+ * NL-membership argument (Section 3): cand is a Schulze winner iff
+ * p(cand, x) >= p(x, cand) for every x.
+ *
+ * w, wt      weights and transposed weights (schulze_weights).
+ * score      NULL or m floats used to pick the reported beater.
+ * p_from     m outputs: p(cand, x).     p_to: m outputs: p(x, cand).
+ * verdict    4 device int32: [0] 1 if cand is a winner, [1] number of x
+ *            that beat cand, [2] one beater (highest score; without scores
+ *            the widest margin p(x,cand) - p(cand,x); ties -> lowest id) or
+ *            -1, [3] number of x != cand tied with it (p(cand,x) = p(x,cand)).
+ * tied       NULL or m device int32 receiving the tied candidates (any order).
+ * Every winner is tied with every other winner, so when cand wins the
+ * winner set is cand plus the tied candidates that pass the same check.
+ */
+int schulze_verify(schulze_ctx *ctx, void *stream, const void *w, int64_t ldw, const void *wt,
+                   int64_t ldwt, int32_t m, int dtype, int32_t cand, const float *score,
+                   void *p_from, void *p_to, int32_t *verdict, int32_t *tied);
+
+/*
  * Closure schedule.  AUTO (default): one persistent cooperative launch whose
  * workgroups exchange the diagonal and panel tiles of each round through
  * device memory and flags, falling back to PHASED when the device refuses a
@@ -163,7 +208,7 @@ int schulze_set_closure_schedule(schulze_ctx *ctx, int schedule);
  * reset.  Names: "ballot_scan", "route", "ballot_scatter", "count_dense",
  * "count_trunc", "count_sparse", "count_finish", "weights", "fw_diag", "fw_panel",
  * "fw_rest", "fw_persist", "fw_store", "beaten_by", "rank_sort",
- * "winners", "fill".
+ * "winners", "fill", "widest", "verdict".
  */
 int schulze_set_timing(schulze_ctx *ctx, int enable);
 int schulze_kernel_time(schulze_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms);

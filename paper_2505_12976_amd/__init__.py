@@ -28,6 +28,7 @@ EXPORTS = (
     "schulze_create", "schulze_destroy", "schulze_strerror", "schulze_get_device_error",
     "schulze_pairwise", "schulze_closure", "schulze_winners", "schulze_ranking",
     "schulze_set_timing", "schulze_kernel_time", "schulze_reset_timing", "schulze_set_closure_schedule",
+    "schulze_weights", "schulze_widest_from", "schulze_verify",
 )
 SCHEDULE_AUTO, SCHEDULE_PHASED = 0, 1
 
@@ -68,6 +69,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.schulze_kernel_time.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(c_i64), ctypes.POINTER(ctypes.c_double)]
     lib.schulze_reset_timing.argtypes = [vp]
     lib.schulze_set_closure_schedule.argtypes = [vp, c_int]
+    lib.schulze_weights.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_int, vp, c_i64, vp, c_i64]
+    lib.schulze_widest_from.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_i32, vp]
+    lib.schulze_verify.argtypes = [vp, vp, vp, c_i64, vp, c_i64, c_i32, c_int, c_i32, vp, vp, vp, vp, vp]
     for name in EXPORTS:
         if name not in ("schulze_destroy", "schulze_strerror"):
             getattr(lib, name).restype = c_int
@@ -209,6 +213,50 @@ class Context:
                                        _dtype_code(p.dtype), self._dev(order, "order"), self._dev(beaten, "beaten_by"))
         _check(rc, "schulze_ranking")
         return order, beaten
+
+    def weights(self, d, mode="winning_votes", transposed=True, direct=True):
+        """(w, wt): edge weights and their transpose (either may be skipped)."""
+        import torch
+        m = d.shape[0]
+        w = torch.empty_like(d) if direct else None
+        wt = torch.empty_like(d) if transposed else None
+        rc = self._lib.schulze_weights(self._h, self._stream(), self._dev(d, "d"), d.stride(0), m,
+                                       _dtype_code(d.dtype), _mode_code(mode),
+                                       None if w is None else self._dev(w, "w"), 0 if w is None else w.stride(0),
+                                       None if wt is None else self._dev(wt, "wt"),
+                                       0 if wt is None else wt.stride(0))
+        _check(rc, "schulze_weights")
+        return w, wt
+
+    def widest_from(self, w, source: int, out=None):
+        """out[v] = p(source, v) (with transposed weights: p(v, source))."""
+        import torch
+        m = w.shape[0]
+        out = out if out is not None else torch.empty(m, dtype=w.dtype, device=self._torch_device)
+        rc = self._lib.schulze_widest_from(self._h, self._stream(), self._dev(w, "w"), w.stride(0), m,
+                                           _dtype_code(w.dtype), source, self._dev(out, "out"))
+        _check(rc, "schulze_widest_from")
+        return out
+
+    def verify(self, w, wt, cand: int, score=None, want_tied=False):
+        """(verdict int32[4], p_from, p_to, tied or None); see schulze_verify."""
+        import torch
+        m = w.shape[0]
+        p_from = torch.empty(m, dtype=w.dtype, device=self._torch_device)
+        p_to = torch.empty(m, dtype=w.dtype, device=self._torch_device)
+        verdict = torch.empty(4, dtype=torch.int32, device=self._torch_device)
+        tied = torch.empty(m, dtype=torch.int32, device=self._torch_device) if want_tied else None
+        sp = None
+        if score is not None:
+            if score.dtype != torch.float32 or score.shape != (m,):
+                raise ValueError("score must be a float32 tensor of shape (m,)")
+            sp = self._dev(score, "score")
+        rc = self._lib.schulze_verify(self._h, self._stream(), self._dev(w, "w"), w.stride(0),
+                                      self._dev(wt, "wt"), wt.stride(0), m, _dtype_code(w.dtype), cand, sp,
+                                      self._dev(p_from, "p_from"), self._dev(p_to, "p_to"),
+                                      self._dev(verdict, "verdict"), None if tied is None else self._dev(tied, "tied"))
+        _check(rc, "schulze_verify")
+        return verdict, p_from, p_to, tied
 
     def set_closure_schedule(self, schedule: str) -> None:
         """"auto" (one persistent launch) or "phased" (three launches per round)."""

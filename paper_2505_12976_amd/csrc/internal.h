@@ -22,6 +22,7 @@ enum WsSlot {
     WS_RANK,             // ranking keys
     WS_RING,             // closure tiles published once per round
     WS_FLAGS,            // closure publication flags
+    WS_VERIFY,           // widest-path sweeps: value vectors, frontiers, barrier
     WS_NUM_SLOTS
 };
 
@@ -65,6 +66,8 @@ enum KernelId {
     K_FW_PERSIST,
     K_ROUTE,
     K_COUNT_TRUNC,
+    K_WIDEST,
+    K_VERDICT,
     K_NUM_KERNELS
 };
 extern const char *const kKernelNames[K_NUM_KERNELS];

@@ -1,0 +1,339 @@
+// Edge weights and single-source / single-target widest paths.
+//
+// Winner verification follows the NL-membership argument of Section 3: a
+// candidate c is a Schulze winner iff for every other candidate x the widest
+// c->x path is at least as wide as the widest x->c path.  Both families of
+// widths are computed exactly with (max, min) relaxation sweeps:
+//     x_s[j] <- max(x_s[j], max_i min(x_s[i], w[i][j])),
+// started from x_s[s] = MAX and 0 elsewhere.  The values only grow, each is
+// the width of some path, and after k sweeps every path of <= k edges has
+// been seen, so the fixpoint is the widest-path row p[s][.] (at most m - 1
+// sweeps).  Only rows whose value grew in the previous sweep can raise
+// anything, so each sweep walks just that frontier.  The target direction
+// p[.][t] is the same computation on the transposed weights.
+//
+// One persistent cooperative launch runs all sweeps; workgroups own column
+// ranges and meet at a grid barrier between sweeps.
+#include "internal.h"
+
+namespace {
+
+template <typename E>
+__device__ inline E max_value() {
+    return sizeof(E) == 2 ? (E)0xFFFF : (E)0x7FFFFFFF;
+}
+
+// ------------------------------------------------------------------ weights
+// w[i][j] and wt[j][i] = edge weight of (i, j) from d (winning votes or
+// margin), one 64 x 64 block of (i, j) and its transpose per workgroup.
+template <typename E>
+__global__ __launch_bounds__(256) void k_weights_pair(const E *__restrict__ d, int64_t ldd, int32_t m, int mode,
+                                                      E *__restrict__ w, int64_t ldw, E *__restrict__ wt,
+                                                      int64_t ldwt) {
+    __shared__ E a[64][65];  // a[r][c] = d[I0 + r][J0 + c]
+    __shared__ E b[64][65];  // b[r][c] = d[J0 + r][I0 + c]
+    const int32_t I0 = blockIdx.y * 64, J0 = blockIdx.x * 64;
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int r = e >> 6, c = e & 63;
+        a[r][c] = (I0 + r < m && J0 + c < m) ? d[(int64_t)(I0 + r) * ldd + J0 + c] : (E)0;
+        b[r][c] = (J0 + r < m && I0 + c < m) ? d[(int64_t)(J0 + r) * ldd + I0 + c] : (E)0;
+    }
+    __syncthreads();
+    auto weight = [&](E x, E y, bool diag) -> E {
+        if (diag || x <= y) return (E)0;
+        return mode == SCHULZE_MARGIN ? (E)(x - y) : x;
+    };
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int r = e >> 6, c = e & 63;
+        const int32_t i = I0 + r, j = J0 + c;
+        if (w && i < m && j < m) w[(int64_t)i * ldw + j] = weight(a[r][c], b[c][r], i == j);
+        // wt row (J0 + r), column (I0 + c) holds the weight of edge (I0 + c, J0 + r)
+        const int32_t ti = J0 + r, tj = I0 + c;
+        if (wt && ti < m && tj < m) wt[(int64_t)ti * ldwt + tj] = weight(a[c][r], b[r][c], ti == tj);
+    }
+}
+
+// ------------------------------------------------------------------ grid barrier
+struct GridBar {
+    int32_t count;
+    int32_t gen;
+    int32_t abort;
+};
+
+// All workgroups of a cooperative launch meet here.  Stores before the
+// barrier are written back (release) and caches are refreshed after it
+// (acquire).  A bounded spin turns a stuck barrier into an abort.
+__device__ inline bool grid_sync(GridBar *b, int64_t limit) {
+    __shared__ int32_t ok;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t good = 1;
+        const int32_t g = __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int32_t arrived = __hip_atomic_fetch_add(&b->count, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
+        if (arrived == (int32_t)gridDim.x) {
+            __hip_atomic_store(&b->count, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&b->gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            int64_t spins = 0;
+            while (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                if (__hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || ++spins > limit) {
+                    __hip_atomic_store(&b->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    good = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        ok = good;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const bool res = ok != 0;
+    __syncthreads();
+    return res;
+}
+
+// ------------------------------------------------------------------ sweeps
+template <typename E>
+struct WidestArgs {
+    const E *w;         // rows = sources of edges (w, or wt for the target direction)
+    int64_t ldw;
+    int32_t m;
+    int32_t s;          // source (or target) vertex
+    E *out;             // m widths, out[s] = 0
+    E *x[2];            // ping-pong value vectors
+    int32_t *front[2];  // frontier lists (m entries each)
+    int32_t *fcount;    // [0], [1]: frontier sizes; [2]: sweeps run
+    GridBar *bar;
+    int32_t *err;
+    int64_t spin_limit;
+};
+
+template <typename E>
+__global__ __launch_bounds__(256) void k_widest(WidestArgs<E> a) {
+    __shared__ E part[4][64];
+    const int32_t m = a.m, G = gridDim.x, g = blockIdx.x;
+    const int32_t c0 = (int32_t)((int64_t)m * g / G), c1 = (int32_t)((int64_t)m * (g + 1) / G);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+    // sweep 0: x = MAX at s, 0 elsewhere; frontier = {s}
+    for (int32_t j = c0 + threadIdx.x; j < c1; j += 256) a.x[0][j] = j == a.s ? max_value<E>() : (E)0;
+    if (g == 0 && threadIdx.x == 0) {
+        a.front[0][0] = a.s;
+        a.fcount[0] = 1;
+        a.fcount[1] = 0;
+    }
+    if (!grid_sync(a.bar, a.spin_limit)) goto stuck;
+    {
+        int cur = 0;
+        int32_t sweeps = 0;
+        for (;;) {
+            const int32_t nf = __hip_atomic_load(&a.fcount[cur], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (nf == 0) break;
+            if (++sweeps > m + 1) {  // cannot happen for a correct fixpoint iteration
+                if (threadIdx.x == 0) set_device_error(a.err, SCHULZE_EDEVICE);
+                break;
+            }
+            const E *xc = a.x[cur];
+            E *xn = a.x[cur ^ 1];
+            const int32_t *F = a.front[cur];
+            int32_t *Fn = a.front[cur ^ 1];
+            for (int32_t cb = c0; cb < c1; cb += 64) {
+                const int32_t j = cb + lane;
+                E best = 0;
+                if (j < c1) {
+                    for (int32_t q = wave; q < nf; q += 4) {
+                        const int32_t i = F[q];
+                        const E via = min(xc[i], a.w[(int64_t)i * a.ldw + j]);
+                        best = max(best, via);
+                    }
+                }
+                part[wave][lane] = best;
+                __syncthreads();
+                if (wave == 0 && j < c1) {
+                    const E old = xc[j];
+                    const E nv = max(max(old, part[0][lane]), max(part[1][lane], max(part[2][lane], part[3][lane])));
+                    xn[j] = nv;
+                    if (nv > old) Fn[atomicAdd(&a.fcount[cur ^ 1], 1)] = j;
+                }
+                __syncthreads();
+            }
+            if (!grid_sync(a.bar, a.spin_limit)) goto stuck;
+            // the list just consumed becomes the next target: reset its size
+            if (g == 0 && threadIdx.x == 0) a.fcount[cur] = 0;
+            cur ^= 1;
+            if (!grid_sync(a.bar, a.spin_limit)) goto stuck;
+        }
+        for (int32_t j = c0 + threadIdx.x; j < c1; j += 256) a.out[j] = j == a.s ? (E)0 : a.x[cur][j];
+        if (g == 0 && threadIdx.x == 0) a.fcount[2] = sweeps;
+        return;
+    }
+stuck:
+    if (threadIdx.x == 0) set_device_error(a.err, SCHULZE_EDEVICE);
+}
+
+// ------------------------------------------------------------------ verdict
+// out[0] = 1 if c is a winner; out[1] = number of candidates beating c;
+// out[2] = a beater (highest score, or widest margin p(x,c) - p(c,x) when
+// no scores are given; ties -> lowest id) or -1; out[3] = number of x != c
+// tied with c (p(c,x) = p(x,c)).  tied[] (optional) lists them.
+template <typename E>
+__global__ __launch_bounds__(256) void k_verdict(const E *__restrict__ from, const E *__restrict__ to, int32_t m,
+                                                 int32_t c, const float *__restrict__ score, int32_t *out,
+                                                 int32_t *tied) {
+    __shared__ int32_t nbeat, ntie;
+    __shared__ unsigned long long best;
+    if (threadIdx.x == 0) {
+        nbeat = 0;
+        ntie = 0;
+        best = 0ull;
+    }
+    __syncthreads();
+    for (int32_t x = threadIdx.x; x < m; x += 256) {
+        if (x == c) continue;
+        const E f = from[x], t = to[x];
+        if (t > f) {
+            atomicAdd(&nbeat, 1);
+            // key: larger is better; ids ascending on ties
+            uint32_t hi;
+            if (score) {
+                const float sc = score[x];
+                uint32_t bits = __float_as_uint(sc);
+                hi = (bits & 0x80000000u) ? ~bits : (bits | 0x80000000u);  // order-preserving
+            } else {
+                hi = (uint32_t)(t - f);
+            }
+            const unsigned long long key = ((unsigned long long)hi << 32) | (uint32_t)(0xFFFFFFFFu - (uint32_t)x);
+            atomicMax(&best, key);
+        } else if (t == f) {
+            const int32_t k = atomicAdd(&ntie, 1);
+            if (tied) tied[k] = x;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = nbeat == 0 ? 1 : 0;
+        out[1] = nbeat;
+        out[2] = nbeat ? (int32_t)(0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull)) : -1;
+        out[3] = ntie;
+    }
+}
+
+template <typename E>
+int widest(schulze_ctx *ctx, hipStream_t s, const E *w, int64_t ldw, int32_t m, int32_t src, E *out) {
+    // workspace: two value vectors, two frontiers, counters, barrier
+    const size_t xbytes = round_up(sizeof(E) * (size_t)m, 256);
+    const size_t fbytes = round_up(sizeof(int32_t) * (size_t)m, 256);
+    const size_t need = 2 * xbytes + 2 * fbytes + 256;
+    int rc = ws_reserve(ctx, WS_VERIFY, need);
+    if (rc != SCHULZE_OK) return rc;
+    char *base = static_cast<char *>(ctx->ws[WS_VERIFY]);
+    WidestArgs<E> a;
+    a.w = w;
+    a.ldw = ldw;
+    a.m = m;
+    a.s = src;
+    a.out = out;
+    a.x[0] = reinterpret_cast<E *>(base);
+    a.x[1] = reinterpret_cast<E *>(base + xbytes);
+    a.front[0] = reinterpret_cast<int32_t *>(base + 2 * xbytes);
+    a.front[1] = reinterpret_cast<int32_t *>(base + 2 * xbytes + fbytes);
+    int32_t *tail = reinterpret_cast<int32_t *>(base + 2 * xbytes + 2 * fbytes);
+    a.fcount = tail;
+    a.bar = reinterpret_cast<GridBar *>(tail + 8);
+    a.err = ctx->err;
+    a.spin_limit = (int64_t)1 << 24;
+    if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(tail), 64, 0u)) != SCHULZE_OK) return rc;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_widest<E>, 256, 0) != hipSuccess || per_cu < 1)
+        return SCHULZE_EDEVICE;
+    int64_t G = (int64_t)ctx->num_cus * std::min(per_cu, 2);
+    G = std::min<int64_t>(G, ceil_div(m, 64));
+    if (G < 1) G = 1;
+    void *args[] = {&a};
+    int tok;
+    timing_begin(ctx, K_WIDEST, s, &tok);
+    hipError_t e = hipLaunchCooperativeKernel((const void *)k_widest<E>, dim3((unsigned)G), dim3(256), args, 0, s);
+    timing_end(ctx, tok, s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return SCHULZE_EDEVICE;
+    }
+    return SCHULZE_OK;
+}
+
+int check_square(schulze_ctx *ctx, const void *a, int64_t ld, int32_t m, int dtype) {
+    if (!ctx || !a) return SCHULZE_EINVAL;
+    if (m < 1 || ld < m) return SCHULZE_EINVAL;
+    if (dtype != SCHULZE_U16 && dtype != SCHULZE_I32) return SCHULZE_EINVAL;
+    if (m > 65535) return SCHULZE_EUNSUPPORTED;
+    return bind_device(ctx);
+}
+
+}  // namespace
+
+extern "C" int schulze_weights(schulze_ctx *ctx, void *stream, const void *d, int64_t ldd, int32_t m, int dtype,
+                               int mode, void *w, int64_t ldw, void *wt, int64_t ldwt) {
+    int rc = check_square(ctx, d, ldd, m, dtype);
+    if (rc != SCHULZE_OK) return rc;
+    if (mode != SCHULZE_WINNING_VOTES && mode != SCHULZE_MARGIN) return SCHULZE_EINVAL;
+    if (!w && !wt) return SCHULZE_EINVAL;
+    if ((w && ldw < m) || (wt && ldwt < m)) return SCHULZE_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    dim3 grid((unsigned)ceil_div(m, 64), (unsigned)ceil_div(m, 64));
+    if (dtype == SCHULZE_U16) {
+        SCHULZE_LAUNCH(ctx, K_WEIGHTS, s,
+                       k_weights_pair<uint16_t><<<grid, dim3(256), 0, s>>>(
+                           static_cast<const uint16_t *>(d), ldd, m, mode, static_cast<uint16_t *>(w), ldw,
+                           static_cast<uint16_t *>(wt), ldwt));
+    } else {
+        SCHULZE_LAUNCH(ctx, K_WEIGHTS, s,
+                       k_weights_pair<int32_t><<<grid, dim3(256), 0, s>>>(
+                           static_cast<const int32_t *>(d), ldd, m, mode, static_cast<int32_t *>(w), ldw,
+                           static_cast<int32_t *>(wt), ldwt));
+    }
+    return SCHULZE_OK;
+}
+
+extern "C" int schulze_widest_from(schulze_ctx *ctx, void *stream, const void *w, int64_t ldw, int32_t m, int dtype,
+                                   int32_t source, void *out) {
+    int rc = check_square(ctx, w, ldw, m, dtype);
+    if (rc != SCHULZE_OK) return rc;
+    if (!out || source < 0 || source >= m) return SCHULZE_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == SCHULZE_U16)
+        return widest<uint16_t>(ctx, s, static_cast<const uint16_t *>(w), ldw, m, source, static_cast<uint16_t *>(out));
+    return widest<int32_t>(ctx, s, static_cast<const int32_t *>(w), ldw, m, source, static_cast<int32_t *>(out));
+}
+
+extern "C" int schulze_verify(schulze_ctx *ctx, void *stream, const void *w, int64_t ldw, const void *wt,
+                              int64_t ldwt, int32_t m, int dtype, int32_t cand, const float *score, void *p_from,
+                              void *p_to, int32_t *verdict, int32_t *tied) {
+    int rc = check_square(ctx, w, ldw, m, dtype);
+    if (rc != SCHULZE_OK) return rc;
+    if (!wt || ldwt < m || !p_from || !p_to || !verdict || cand < 0 || cand >= m) return SCHULZE_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == SCHULZE_U16) {
+        using E = uint16_t;
+        if ((rc = widest<E>(ctx, s, static_cast<const E *>(w), ldw, m, cand, static_cast<E *>(p_from))) != SCHULZE_OK)
+            return rc;
+        if ((rc = widest<E>(ctx, s, static_cast<const E *>(wt), ldwt, m, cand, static_cast<E *>(p_to))) != SCHULZE_OK)
+            return rc;
+        SCHULZE_LAUNCH(ctx, K_VERDICT, s,
+                       k_verdict<E><<<dim3(1), dim3(256), 0, s>>>(static_cast<const E *>(p_from),
+                                                                  static_cast<const E *>(p_to), m, cand, score,
+                                                                  verdict, tied));
+    } else {
+        using E = int32_t;
+        if ((rc = widest<E>(ctx, s, static_cast<const E *>(w), ldw, m, cand, static_cast<E *>(p_from))) != SCHULZE_OK)
+            return rc;
+        if ((rc = widest<E>(ctx, s, static_cast<const E *>(wt), ldwt, m, cand, static_cast<E *>(p_to))) != SCHULZE_OK)
+            return rc;
+        SCHULZE_LAUNCH(ctx, K_VERDICT, s,
+                       k_verdict<E><<<dim3(1), dim3(256), 0, s>>>(static_cast<const E *>(p_from),
+                                                                  static_cast<const E *>(p_to), m, cand, score,
+                                                                  verdict, tied));
+    }
+    return SCHULZE_OK;
+}
