@@ -191,6 +191,53 @@ int schulze_verify(schulze_ctx *ctx, void *stream, const void *w, int64_t ldw, c
                    void *p_from, void *p_to, int32_t *verdict, int32_t *tied);
 
 /*
+ * Per-candidate features of the weighted tournament graph (the learned
+ * proposer's input), computed from d in one pass:
+ *   feat[x][0..15] = Copeland score, ties, Borda score (the vertex-id order of
+ *   Section 4), largest outgoing / incoming edge weight, the initialisation
+ *   filter of Section 4 (1 if the largest incoming weight exceeds the largest
+ *   outgoing one: x cannot win), mean outgoing / incoming weight, smallest /
+ *   largest margin, log(m)/10, Copeland / max, Borda / max, largest outgoing
+ *   weight / max, (largest outgoing - largest incoming) / n, 1.
+ * Counts are scaled by 1/n_voters and by 1/(m-1) where they sum over
+ * candidates.  feat: m x 16 floats, row-major, device memory.
+ */
+int schulze_features(schulze_ctx *ctx, void *stream, const void *d, int64_t ldd, int32_t m,
+                     int dtype, int mode, float n_voters, float *feat);
+
+/*
+ * Learned proposer: a 16 -> 128 -> 128 -> 1 ReLU network, BF16 MFMA products
+ * with FP32 accumulation, FP32 master parameters in one array of
+ * schulze_mlp_param_count() floats laid out as
+ *   W1[16][128] | b1[128] | W2[128][128] | b2[128] | W3[128] | b3[1].
+ * Inputs and the hidden activations are rounded to BF16 (nearest even), as
+ * are W1, W2, W3 and the backward activations dz2, dz1.
+ */
+int schulze_mlp_param_count(void);
+
+/* score[r] = network output for feature row r (feat: M x 16 floats). */
+int schulze_mlp_forward(schulze_ctx *ctx, void *stream, const float *params, const float *feat,
+                        int64_t M, float *score);
+
+/* Segmented softmax cross-entropy over E elections, rows off[e] .. off[e+1]-1
+ * (off: E+1 device int64), winner[r] = 1 for the election's Schulze winners:
+ * loss[e] = log sum_rows exp(score) - log sum_winners exp(score);
+ * dscore = gradient of the mean loss.  Elections without a marked winner get
+ * loss 0 and zero gradient. */
+int schulze_mlp_loss(schulze_ctx *ctx, void *stream, const float *score, const int64_t *offsets,
+                     const uint8_t *winner, int32_t E, float *dscore, float *loss);
+
+/* grad = gradient of sum_r dscore[r] * score[r] with respect to params
+ * (deterministic: fixed per-workgroup partials reduced in a fixed order). */
+int schulze_mlp_backward(schulze_ctx *ctx, void *stream, const float *params, const float *feat,
+                         int64_t M, const float *dscore, float *grad);
+
+/* One Adam step (bias-corrected, step >= 1) on the FP32 parameters. */
+int schulze_mlp_adam(schulze_ctx *ctx, void *stream, float *params, const float *grad,
+                     float *adam_m, float *adam_v, float lr, float beta1, float beta2, float eps,
+                     int32_t step);
+
+/*
  * Closure schedule.  AUTO (default): one persistent cooperative launch whose
  * workgroups exchange the diagonal and panel tiles of each round through
  * device memory and flags, falling back to PHASED when the device refuses a
@@ -208,7 +255,8 @@ int schulze_set_closure_schedule(schulze_ctx *ctx, int schedule);
  * reset.  Names: "ballot_scan", "route", "ballot_scatter", "count_dense",
  * "count_trunc", "count_sparse", "count_finish", "weights", "fw_diag", "fw_panel",
  * "fw_rest", "fw_persist", "fw_store", "beaten_by", "rank_sort",
- * "winners", "fill", "widest", "verdict".
+ * "winners", "fill", "widest", "verdict", "features", "mlp_prepare",
+ * "mlp_forward", "mlp_backward", "mlp_loss", "mlp_adam".
  */
 int schulze_set_timing(schulze_ctx *ctx, int enable);
 int schulze_kernel_time(schulze_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms);

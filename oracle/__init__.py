@@ -184,3 +184,42 @@ def schulze(ballots: np.ndarray, m: int, mode: int = WINNING_VOTES, weight=None)
     p = closure(w)
     beaten, win, order = rank(p)
     return {"d": d, "w": w, "p": p, "beaten_by": beaten, "is_winner": win, "order": order}
+
+
+def features(d: np.ndarray, n_voters: float, mode: int = WINNING_VOTES) -> np.ndarray:
+    """m x 16 per-candidate features of the weighted tournament graph (float64
+    arithmetic, float32 result); column meanings as in the GPU library."""
+    d = np.asarray(d, dtype=np.int64)
+    m = d.shape[0]
+    dt = d.T
+    off = ~np.eye(m, dtype=bool)
+    w_out = np.where(off & (d > dt), d if mode == WINNING_VOTES else d - dt, 0)
+    w_in = w_out.T
+    marg = np.where(off, d - dt, 0)
+    cope = ((d > dt) & off).sum(axis=1)
+    ties = ((d == dt) & off).sum(axis=1)
+    borda = np.where(off, d, 0).sum(axis=1)
+    mx_out, mx_in = w_out.max(axis=1), w_in.max(axis=1)
+    big = np.iinfo(np.int64).max
+    mn = np.where(off, marg, big).min(axis=1) if m > 1 else np.zeros(m, dtype=np.int64)
+    mxm = np.where(off, marg, -big).max(axis=1) if m > 1 else np.zeros(m, dtype=np.int64)
+    inv_m1 = 1.0 / (m - 1) if m > 1 else 0.0
+    inv_n = 1.0 / n_voters if n_voters > 0 else 1.0
+    F = np.zeros((m, 16), dtype=np.float64)
+    F[:, 0] = cope * inv_m1
+    F[:, 1] = ties * inv_m1
+    F[:, 2] = borda * inv_m1 * inv_n
+    F[:, 3] = mx_out * inv_n
+    F[:, 4] = mx_in * inv_n
+    F[:, 5] = (mx_in > mx_out).astype(np.float64)
+    F[:, 6] = w_out.sum(axis=1) * inv_m1 * inv_n
+    F[:, 7] = w_in.sum(axis=1) * inv_m1 * inv_n
+    F[:, 8] = mn * inv_n
+    F[:, 9] = mxm * inv_n
+    F[:, 10] = np.log(m) * 0.1
+    F[:, 11] = cope / cope.max() if cope.max() > 0 else 0.0
+    F[:, 12] = borda / borda.max() if borda.max() > 0 else 0.0
+    F[:, 13] = mx_out / mx_out.max() if mx_out.max() > 0 else 0.0
+    F[:, 14] = (mx_out - mx_in) * inv_n
+    F[:, 15] = 1.0
+    return F.astype(np.float32)

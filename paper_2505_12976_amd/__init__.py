@@ -28,7 +28,8 @@ EXPORTS = (
     "schulze_create", "schulze_destroy", "schulze_strerror", "schulze_get_device_error",
     "schulze_pairwise", "schulze_closure", "schulze_winners", "schulze_ranking",
     "schulze_set_timing", "schulze_kernel_time", "schulze_reset_timing", "schulze_set_closure_schedule",
-    "schulze_weights", "schulze_widest_from", "schulze_verify",
+    "schulze_weights", "schulze_widest_from", "schulze_verify", "schulze_features",
+    "schulze_mlp_param_count", "schulze_mlp_forward", "schulze_mlp_loss", "schulze_mlp_backward", "schulze_mlp_adam",
 )
 SCHEDULE_AUTO, SCHEDULE_PHASED = 0, 1
 
@@ -72,11 +73,22 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.schulze_weights.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_int, vp, c_i64, vp, c_i64]
     lib.schulze_widest_from.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_i32, vp]
     lib.schulze_verify.argtypes = [vp, vp, vp, c_i64, vp, c_i64, c_i32, c_int, c_i32, vp, vp, vp, vp, vp]
+    lib.schulze_features.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_int, ctypes.c_float, vp]
+    lib.schulze_mlp_param_count.argtypes = []
+    lib.schulze_mlp_forward.argtypes = [vp, vp, vp, vp, c_i64, vp]
+    lib.schulze_mlp_loss.argtypes = [vp, vp, vp, vp, vp, c_i32, vp, vp]
+    lib.schulze_mlp_backward.argtypes = [vp, vp, vp, vp, c_i64, vp, vp]
+    lib.schulze_mlp_adam.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                     ctypes.c_float, c_i32]
     for name in EXPORTS:
         if name not in ("schulze_destroy", "schulze_strerror"):
             getattr(lib, name).restype = c_int
     _lib = lib
     return lib
+
+
+def mlp_param_count() -> int:
+    return int(load_library().schulze_mlp_param_count())
 
 
 def strerror(code: int) -> str:
@@ -257,6 +269,53 @@ class Context:
                                       self._dev(verdict, "verdict"), None if tied is None else self._dev(tied, "tied"))
         _check(rc, "schulze_verify")
         return verdict, p_from, p_to, tied
+
+    def features(self, d, n_voters: float, mode="winning_votes", out=None):
+        """m x 16 float32 per-candidate features of d."""
+        import torch
+        m = d.shape[0]
+        out = out if out is not None else torch.empty((m, 16), dtype=torch.float32, device=self._torch_device)
+        rc = self._lib.schulze_features(self._h, self._stream(), self._dev(d, "d"), d.stride(0), m,
+                                        _dtype_code(d.dtype), _mode_code(mode), float(n_voters),
+                                        self._dev(out, "feat"))
+        _check(rc, "schulze_features")
+        return out
+
+    def mlp_forward(self, params, feat, out=None):
+        import torch
+        M = feat.shape[0]
+        out = out if out is not None else torch.empty(M, dtype=torch.float32, device=self._torch_device)
+        rc = self._lib.schulze_mlp_forward(self._h, self._stream(), self._dev(params, "params"),
+                                           self._dev(feat, "feat"), M, self._dev(out, "score"))
+        _check(rc, "schulze_mlp_forward")
+        return out
+
+    def mlp_loss(self, score, offsets, winner):
+        """(dscore, loss per election)."""
+        import torch
+        E = offsets.shape[0] - 1
+        ds = torch.empty_like(score)
+        loss = torch.empty(E, dtype=torch.float32, device=self._torch_device)
+        rc = self._lib.schulze_mlp_loss(self._h, self._stream(), self._dev(score, "score"),
+                                        self._dev(offsets, "offsets"), self._dev(winner, "winner"), E,
+                                        self._dev(ds, "dscore"), self._dev(loss, "loss"))
+        _check(rc, "schulze_mlp_loss")
+        return ds, loss
+
+    def mlp_backward(self, params, feat, dscore, out=None):
+        import torch
+        out = out if out is not None else torch.empty_like(params)
+        rc = self._lib.schulze_mlp_backward(self._h, self._stream(), self._dev(params, "params"),
+                                            self._dev(feat, "feat"), feat.shape[0], self._dev(dscore, "dscore"),
+                                            self._dev(out, "grad"))
+        _check(rc, "schulze_mlp_backward")
+        return out
+
+    def mlp_adam(self, params, grad, m1, m2, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
+        rc = self._lib.schulze_mlp_adam(self._h, self._stream(), self._dev(params, "params"), self._dev(grad, "grad"),
+                                        self._dev(m1, "adam_m"), self._dev(m2, "adam_v"), float(lr), float(beta1),
+                                        float(beta2), float(eps), int(step))
+        _check(rc, "schulze_mlp_adam")
 
     def set_closure_schedule(self, schedule: str) -> None:
         """"auto" (one persistent launch) or "phased" (three launches per round)."""

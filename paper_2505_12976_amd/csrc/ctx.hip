@@ -9,7 +9,8 @@ const char *const kKernelNames[K_NUM_KERNELS] = {
     "ballot_scan", "ballot_scatter", "count_dense", "count_sparse", "count_finish", "weights",
     "fw_diag",     "fw_panel",       "fw_rest",     "fw_store",     "beaten_by",    "rank_sort",
     "winners",     "fill",           "fw_persist",  "route",        "count_trunc",
-    "widest",      "verdict"};
+    "widest",      "verdict",        "features",    "mlp_prepare",  "mlp_forward",
+    "mlp_backward", "mlp_loss",      "mlp_adam"};
 
 extern "C" const char *schulze_strerror(int code) {
     switch (code) {

@@ -1,0 +1,178 @@
+// Per-candidate features of the weighted tournament graph, the input of the
+// learned winner proposer.  All are read off the pairwise counts d in one
+// pass (each workgroup owns 64 candidates and walks their rows, taking the
+// transposed blocks through LDS):
+//   0  Copeland score: #{y : d[x][y] > d[y][x]} / (m-1)
+//   1  ties: #{y != x : d[x][y] = d[y][x]} / (m-1)
+//   2  Borda score: sum_y d[x][y] / ((m-1) n)   (the order Section 4 uses for vertex ids)
+//   3  largest outgoing edge weight / n
+//   4  largest incoming edge weight / n
+//   5  initialisation filter of Section 4: 1 if the largest incoming weight
+//      exceeds the largest outgoing one (then x is never a winner)
+//   6  mean outgoing weight / n      7  mean incoming weight / n
+//   8  smallest margin d[x][y]-d[y][x] / n   9  largest margin / n
+//   10 log(m) / 10
+//   11 Copeland / max Copeland       12 Borda / max Borda
+//   13 largest outgoing weight / its maximum over candidates
+//   14 (largest outgoing - largest incoming weight) / n
+//   15 1 (bias input)
+// n is the number of voters (any positive scale works; it keeps features O(1)).
+#include "internal.h"
+
+namespace {
+
+constexpr int NF = 16;
+
+struct RawStats {
+    int32_t *cope, *ties;
+    unsigned long long *borda, *sum_out, *sum_in;
+    int32_t *max_out, *max_in;
+    long long *min_marg, *max_marg;
+};
+
+template <typename E>
+__global__ __launch_bounds__(256) void k_feature_rows(const E *__restrict__ d, int64_t ldd, int32_t m, int mode,
+                                                      RawStats st) {
+    __shared__ E a[64][65];  // a[r][c] = d[X0 + r][Y0 + c]
+    __shared__ E b[64][65];  // b[r][c] = d[Y0 + r][X0 + c]
+    const int32_t X0 = blockIdx.x * 64;
+    const int r = threadIdx.x >> 2, part = threadIdx.x & 3;  // 4 threads per row, 16 columns each
+    const int32_t x = X0 + r;
+    int32_t cope = 0, ties = 0, mx_out = 0, mx_in = 0;
+    unsigned long long borda = 0, s_out = 0, s_in = 0;
+    long long mn = LLONG_MAX, mxm = LLONG_MIN;
+    for (int32_t Y0 = 0; Y0 < m; Y0 += 64) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+            const int rr = e >> 6, cc = e & 63;
+            a[rr][cc] = (X0 + rr < m && Y0 + cc < m) ? d[(int64_t)(X0 + rr) * ldd + Y0 + cc] : (E)0;
+            b[rr][cc] = (Y0 + rr < m && X0 + cc < m) ? d[(int64_t)(Y0 + rr) * ldd + X0 + cc] : (E)0;
+        }
+        __syncthreads();
+        if (x >= m) continue;
+        for (int c = part * 16; c < part * 16 + 16; ++c) {
+            const int32_t y = Y0 + c;
+            if (y >= m || y == x) continue;
+            const int64_t dxy = a[r][c], dyx = b[c][r];
+            cope += dxy > dyx;
+            ties += dxy == dyx;
+            borda += (unsigned long long)dxy;
+            const long long marg = dxy - dyx;
+            mn = min(mn, marg);
+            mxm = max(mxm, marg);
+            const int32_t wout = dxy > dyx ? (int32_t)(mode == SCHULZE_MARGIN ? dxy - dyx : dxy) : 0;
+            const int32_t win = dyx > dxy ? (int32_t)(mode == SCHULZE_MARGIN ? dyx - dxy : dyx) : 0;
+            mx_out = max(mx_out, wout);
+            mx_in = max(mx_in, win);
+            s_out += (unsigned long long)wout;
+            s_in += (unsigned long long)win;
+        }
+    }
+    // combine the 4 threads of a row (adjacent lanes)
+    for (int off = 1; off < 4; off <<= 1) {
+        cope += __shfl_xor(cope, off);
+        ties += __shfl_xor(ties, off);
+        borda += __shfl_xor(borda, off);
+        s_out += __shfl_xor(s_out, off);
+        s_in += __shfl_xor(s_in, off);
+        mx_out = max(mx_out, __shfl_xor(mx_out, off));
+        mx_in = max(mx_in, __shfl_xor(mx_in, off));
+        mn = min(mn, (long long)__shfl_xor(mn, off));
+        mxm = max(mxm, (long long)__shfl_xor(mxm, off));
+    }
+    if (part == 0 && x < m) {
+        st.cope[x] = cope;
+        st.ties[x] = ties;
+        st.borda[x] = borda;
+        st.sum_out[x] = s_out;
+        st.sum_in[x] = s_in;
+        st.max_out[x] = mx_out;
+        st.max_in[x] = mx_in;
+        st.min_marg[x] = m > 1 ? mn : 0;
+        st.max_marg[x] = m > 1 ? mxm : 0;
+    }
+}
+
+// Normalise: one workgroup finds the maxima, every thread writes rows.
+__global__ __launch_bounds__(256) void k_feature_norm(int32_t m, RawStats st, float n_voters,
+                                                      float *__restrict__ feat) {
+    __shared__ int32_t mcope, mout;
+    __shared__ unsigned long long mborda;
+    if (threadIdx.x == 0) {
+        mcope = 0;
+        mout = 0;
+        mborda = 0;
+    }
+    __syncthreads();
+    int32_t c = 0, o = 0;
+    unsigned long long bd = 0;
+    for (int32_t x = threadIdx.x; x < m; x += 256) {
+        c = max(c, st.cope[x]);
+        o = max(o, st.max_out[x]);
+        bd = max(bd, st.borda[x]);
+    }
+    atomicMax(&mcope, c);
+    atomicMax(&mout, o);
+    atomicMax(&mborda, bd);
+    __syncthreads();
+    const float inv_m1 = m > 1 ? 1.0f / (float)(m - 1) : 0.0f;
+    const float inv_n = n_voters > 0.f ? 1.0f / n_voters : 1.0f;
+    for (int32_t x = threadIdx.x; x < m; x += 256) {
+        float *f = feat + (int64_t)x * NF;
+        f[0] = (float)st.cope[x] * inv_m1;
+        f[1] = (float)st.ties[x] * inv_m1;
+        f[2] = (float)st.borda[x] * inv_m1 * inv_n;
+        f[3] = (float)st.max_out[x] * inv_n;
+        f[4] = (float)st.max_in[x] * inv_n;
+        f[5] = st.max_in[x] > st.max_out[x] ? 1.0f : 0.0f;
+        f[6] = (float)st.sum_out[x] * inv_m1 * inv_n;
+        f[7] = (float)st.sum_in[x] * inv_m1 * inv_n;
+        f[8] = (float)st.min_marg[x] * inv_n;
+        f[9] = (float)st.max_marg[x] * inv_n;
+        f[10] = logf((float)m) * 0.1f;
+        f[11] = mcope > 0 ? (float)st.cope[x] / (float)mcope : 0.0f;
+        f[12] = mborda > 0 ? (float)((double)st.borda[x] / (double)mborda) : 0.0f;
+        f[13] = mout > 0 ? (float)st.max_out[x] / (float)mout : 0.0f;
+        f[14] = ((float)st.max_out[x] - (float)st.max_in[x]) * inv_n;
+        f[15] = 1.0f;
+    }
+}
+
+template <typename E>
+int run_features(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32_t m, int mode, float n_voters,
+                 float *feat) {
+    const size_t i4 = round_up(sizeof(int32_t) * (size_t)m, 256), i8 = round_up(8 * (size_t)m, 256);
+    int rc = ws_reserve(ctx, WS_FEATURES, 4 * i4 + 5 * i8);
+    if (rc != SCHULZE_OK) return rc;
+    char *p = static_cast<char *>(ctx->ws[WS_FEATURES]);
+    RawStats st;
+    st.cope = reinterpret_cast<int32_t *>(p);
+    st.ties = reinterpret_cast<int32_t *>(p + i4);
+    st.max_out = reinterpret_cast<int32_t *>(p + 2 * i4);
+    st.max_in = reinterpret_cast<int32_t *>(p + 3 * i4);
+    st.borda = reinterpret_cast<unsigned long long *>(p + 4 * i4);
+    st.sum_out = reinterpret_cast<unsigned long long *>(p + 4 * i4 + i8);
+    st.sum_in = reinterpret_cast<unsigned long long *>(p + 4 * i4 + 2 * i8);
+    st.min_marg = reinterpret_cast<long long *>(p + 4 * i4 + 3 * i8);
+    st.max_marg = reinterpret_cast<long long *>(p + 4 * i4 + 4 * i8);
+    SCHULZE_LAUNCH(ctx, K_FEATURES, s,
+                   k_feature_rows<E><<<dim3((unsigned)ceil_div(m, 64)), dim3(256), 0, s>>>(d, ldd, m, mode, st));
+    SCHULZE_LAUNCH(ctx, K_FEATURES, s, k_feature_norm<<<dim3(1), dim3(256), 0, s>>>(m, st, n_voters, feat));
+    return SCHULZE_OK;
+}
+
+}  // namespace
+
+extern "C" int schulze_features(schulze_ctx *ctx, void *stream, const void *d, int64_t ldd, int32_t m, int dtype,
+                                int mode, float n_voters, float *feat) {
+    if (!ctx || !d || !feat) return SCHULZE_EINVAL;
+    if (m < 1 || ldd < m) return SCHULZE_EINVAL;
+    if (dtype != SCHULZE_U16 && dtype != SCHULZE_I32) return SCHULZE_EINVAL;
+    if (mode != SCHULZE_WINNING_VOTES && mode != SCHULZE_MARGIN) return SCHULZE_EINVAL;
+    if (m > 65535) return SCHULZE_EUNSUPPORTED;
+    if (bind_device(ctx) != SCHULZE_OK) return SCHULZE_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == SCHULZE_U16)
+        return run_features(ctx, s, static_cast<const uint16_t *>(d), ldd, m, mode, n_voters, feat);
+    return run_features(ctx, s, static_cast<const int32_t *>(d), ldd, m, mode, n_voters, feat);
+}

@@ -23,6 +23,9 @@ enum WsSlot {
     WS_RING,             // closure tiles published once per round
     WS_FLAGS,            // closure publication flags
     WS_VERIFY,           // widest-path sweeps: value vectors, frontiers, barrier
+    WS_FEATURES,         // per-candidate raw statistics
+    WS_MLP,              // BF16 copies of the network weights
+    WS_MLP_PARTIAL,      // per-workgroup gradient partials
     WS_NUM_SLOTS
 };
 
@@ -68,6 +71,12 @@ enum KernelId {
     K_COUNT_TRUNC,
     K_WIDEST,
     K_VERDICT,
+    K_FEATURES,
+    K_MLP_PREP,
+    K_MLP_FWD,
+    K_MLP_BWD,
+    K_MLP_LOSS,
+    K_MLP_ADAM,
     K_NUM_KERNELS
 };
 extern const char *const kKernelNames[K_NUM_KERNELS];
