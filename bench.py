@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 VALU_LANE_OPS = 256 * 64 * 2.4e9
 HBM_BYTES = 8.0e12
 
-WORKLOADS = ("mid", "small", "large")
+WORKLOADS = ("mid", "small", "large", "learned")
 
 
 def measured_traffic(kernel, workload_name):
@@ -67,7 +67,79 @@ def parse():
 
 def make_workload(name):
     import workload
-    return {"mid": workload.plain_mid, "small": workload.plain_small, "large": workload.plain_large}[name]()
+    return {"mid": workload.plain_mid, "small": workload.plain_small, "large": workload.plain_large,
+            "learned": workload.plain_learned}[name]()
+
+
+def bench_learned(args):
+    """Exact winners through the learned proposal versus the full closure, on
+    m=32768 candidates, n=200000 top-30 Plackett-Luce Zipf(1.0) ballots."""
+    import numpy as np
+    import torch
+
+    import paper_2505_12976_amd as sz
+    from paper_2505_12976_amd.proposer import load_checkpoint
+
+    dev = torch.device("cuda", 0)
+    wl = make_workload("learned")
+    m, n = wl.m, wl.n
+    ckpt = os.path.join(ROOT, "paper_2505_12976_amd", "data", "proposer.npz")
+    params = torch.from_numpy(load_checkpoint(ckpt)["params"]).to(dev)
+    ctx = sz.Context(0)
+    ballots = torch.from_numpy(wl.ballots).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d = ctx.pairwise(ballots, m, dtype="i32")
+    torch.cuda.synchronize()
+    t_count = time.perf_counter() - t0
+    print(f"[bench] count {t_count * 1e3:.1f} ms", file=sys.stderr, flush=True)
+
+    def full():
+        p = ctx.closure(d)
+        w, nw = ctx.winners(p)
+        torch.cuda.synchronize()
+        return w
+
+    def learned():
+        w, nw, st = ctx.winners_learned(d, float(n), params)
+        torch.cuda.synchronize()
+        return w, st
+
+    learned()  # warm-up
+    t_learned = []
+    for _ in range(max(args.steps, 1)):
+        t0 = time.perf_counter()
+        w_l, st = learned()
+        t_learned.append(time.perf_counter() - t0)
+    print(f"[bench] learned {np.median(t_learned) * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    t_full = []
+    for _ in range(2):
+        t0 = time.perf_counter()
+        w_f = full()
+        t_full.append(time.perf_counter() - t0)
+        print(f"[bench] full closure {t_full[-1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    exact = bool((w_l.cpu().numpy() == w_f.cpu().numpy()).all())
+    tl, tf = float(np.median(t_learned)), float(min(t_full))
+    out = {
+        "metric": "learned-verify vs full-closure speedup",
+        "value": tf / tl,
+        "unit": "x",
+        "n_gpus": 1,
+        "steps": len(t_learned),
+        "higher_is_better": True,
+        "dtype": "i32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "m": m, "n": n, "recipe": wl.recipe},
+        "ms_learned": tl * 1e3,
+        "ms_full_closure_and_winners": tf * 1e3,
+        "ms_count": t_count * 1e3,
+        "closure_gops": m ** 3 / tf / 1e9,
+        "exact": exact,
+        "winners": np.nonzero(w_l.cpu().numpy())[0].tolist(),
+        "learned_stats": st,
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(wl, sample_voters):
@@ -103,6 +175,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
+    if args.workload == "learned":
+        bench_learned(args)
+        return
 
     import numpy as np
     import torch

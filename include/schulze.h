@@ -237,6 +237,38 @@ int schulze_mlp_adam(schulze_ctx *ctx, void *stream, float *params, const float 
                      float *adam_m, float *adam_v, float lr, float beta1, float beta2, float eps,
                      int32_t step);
 
+/* Statistics of one schulze_winners_learned call. */
+typedef struct {
+    int32_t proposal;      /* first candidate the network proposed */
+    int32_t first_hit;     /* 1 if that candidate is a winner */
+    int32_t verify_calls;  /* exact checks run (proposal, climbs, tied candidates) */
+    int32_t climbs;        /* moves to a beater */
+    int32_t fallback;      /* 1 if the full closure decided */
+    int32_t n_winners;
+} schulze_learned_stats;
+
+/*
+ * Exact Schulze winners via a learned proposal.  The network (params, see
+ * schulze_mlp_param_count) scores the features of d; the best candidate the
+ * initialisation filter of Section 4 keeps is checked with schulze_verify.
+ * If it is beaten, the check moves to the highest-scored beater (at most
+ * max_climb times); once a winner is found the candidates tied with it are
+ * checked too (every winner is tied with every other winner).  If no winner
+ * is found or more than max_tied candidates are tied, schulze_closure and
+ * schulze_winners decide.  The result equals schulze_winners on the closure
+ * for any network.  Synchronises the stream (the search runs on the host).
+ *
+ * n_voters   feature scale (number of voters).
+ * is_winner  m device bytes.   n_winners: NULL or one device int32.
+ * stats      NULL or host struct.
+ * Workspace: 2 m^2 elements of dtype (weights and transposed weights) plus
+ * O(m); m^2 more if the fallback runs.
+ */
+int schulze_winners_learned(schulze_ctx *ctx, void *stream, const void *d, int64_t ldd, int32_t m,
+                            int dtype, int mode, float n_voters, const float *params,
+                            int32_t max_climb, int32_t max_tied, uint8_t *is_winner,
+                            int32_t *n_winners, schulze_learned_stats *stats);
+
 /*
  * Closure schedule.  AUTO (default): one persistent cooperative launch whose
  * workgroups exchange the diagonal and panel tiles of each round through
@@ -256,7 +288,7 @@ int schulze_set_closure_schedule(schulze_ctx *ctx, int schedule);
  * "count_trunc", "count_sparse", "count_finish", "weights", "fw_diag", "fw_panel",
  * "fw_rest", "fw_persist", "fw_store", "beaten_by", "rank_sort",
  * "winners", "fill", "widest", "verdict", "features", "mlp_prepare",
- * "mlp_forward", "mlp_backward", "mlp_loss", "mlp_adam".
+ * "mlp_forward", "mlp_backward", "mlp_loss", "mlp_adam", "propose".
  */
 int schulze_set_timing(schulze_ctx *ctx, int enable);
 int schulze_kernel_time(schulze_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms);

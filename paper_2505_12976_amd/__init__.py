@@ -30,7 +30,16 @@ EXPORTS = (
     "schulze_set_timing", "schulze_kernel_time", "schulze_reset_timing", "schulze_set_closure_schedule",
     "schulze_weights", "schulze_widest_from", "schulze_verify", "schulze_features",
     "schulze_mlp_param_count", "schulze_mlp_forward", "schulze_mlp_loss", "schulze_mlp_backward", "schulze_mlp_adam",
+    "schulze_winners_learned",
 )
+
+
+class LearnedStats(ctypes.Structure):
+    _fields_ = [("proposal", ctypes.c_int32), ("first_hit", ctypes.c_int32), ("verify_calls", ctypes.c_int32),
+                ("climbs", ctypes.c_int32), ("fallback", ctypes.c_int32), ("n_winners", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 SCHEDULE_AUTO, SCHEDULE_PHASED = 0, 1
 
 _lib = None
@@ -75,6 +84,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.schulze_verify.argtypes = [vp, vp, vp, c_i64, vp, c_i64, c_i32, c_int, c_i32, vp, vp, vp, vp, vp]
     lib.schulze_features.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_int, ctypes.c_float, vp]
     lib.schulze_mlp_param_count.argtypes = []
+    lib.schulze_winners_learned.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_int, ctypes.c_float, vp, c_i32, c_i32,
+                                            vp, vp, ctypes.POINTER(LearnedStats)]
     lib.schulze_mlp_forward.argtypes = [vp, vp, vp, vp, c_i64, vp]
     lib.schulze_mlp_loss.argtypes = [vp, vp, vp, vp, vp, c_i32, vp, vp]
     lib.schulze_mlp_backward.argtypes = [vp, vp, vp, vp, c_i64, vp, vp]
@@ -316,6 +327,22 @@ class Context:
                                         self._dev(m1, "adam_m"), self._dev(m2, "adam_v"), float(lr), float(beta1),
                                         float(beta2), float(eps), int(step))
         _check(rc, "schulze_mlp_adam")
+
+    def winners_learned(self, d, n_voters: float, params, mode="winning_votes", max_climb=8, max_tied=64):
+        """(is_winner uint8[m], n_winners int32[1], stats dict): exact winners
+        found through the proposer network (synchronises)."""
+        import torch
+        m = d.shape[0]
+        w = torch.empty(m, dtype=torch.uint8, device=self._torch_device)
+        nw = torch.empty(1, dtype=torch.int32, device=self._torch_device)
+        st = LearnedStats()
+        rc = self._lib.schulze_winners_learned(self._h, self._stream(), self._dev(d, "d"), d.stride(0), m,
+                                               _dtype_code(d.dtype), _mode_code(mode), float(n_voters),
+                                               self._dev(params, "params"), int(max_climb), int(max_tied),
+                                               self._dev(w, "is_winner"), self._dev(nw, "n_winners"),
+                                               ctypes.byref(st))
+        _check(rc, "schulze_winners_learned")
+        return w, nw, st.as_dict()
 
     def set_closure_schedule(self, schedule: str) -> None:
         """"auto" (one persistent launch) or "phased" (three launches per round)."""

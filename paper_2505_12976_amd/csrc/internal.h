@@ -26,6 +26,8 @@ enum WsSlot {
     WS_FEATURES,         // per-candidate raw statistics
     WS_MLP,              // BF16 copies of the network weights
     WS_MLP_PARTIAL,      // per-workgroup gradient partials
+    WS_LEARNED,          // learned path: weights, transposed weights, features, scores
+    WS_LEARNED_P,        // learned path: closure for the fallback
     WS_NUM_SLOTS
 };
 
@@ -77,6 +79,7 @@ enum KernelId {
     K_MLP_BWD,
     K_MLP_LOSS,
     K_MLP_ADAM,
+    K_PROPOSE,
     K_NUM_KERNELS
 };
 extern const char *const kKernelNames[K_NUM_KERNELS];

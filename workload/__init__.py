@@ -58,8 +58,11 @@ def _load():
                                      ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
     lib.gen_uniform_ballots.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.c_void_p]
+    lib.gen_mallows_topk.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32,
+                                     ctypes.c_double, i32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int,
+                                     ctypes.c_void_p]
     for f in (lib.gen_permutation, lib.gen_mallows, lib.gen_pl_zipf, lib.gen_uniform_int,
-              lib.gen_uniform_real, lib.gen_uniform_ballots):
+              lib.gen_uniform_real, lib.gen_uniform_ballots, lib.gen_mallows_topk):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -120,6 +123,21 @@ def pl_zipf(seed: int, n: int, m: int, s: float, k: int, *, election: int = 0, L
     rc = _load().gen_pl_zipf(seed, election, n, m, s, _i32p(pop_order), k, max(L, 1),
                              int(dtype == np.int32), out.ctypes.data)
     _check(rc, "gen_pl_zipf")
+    return out
+
+
+def mallows_topk(seed: int, n: int, m: int, phi: float, k: int, *, election: int = 0, L: int | None = None,
+                 ref_order=None, dtype=None) -> np.ndarray:
+    """Top-k of Mallows(phi) rankings (inversion-vector sampling, O(k^2) per voter)."""
+    dtype = _ballot_dtype(m, dtype)
+    L = k if L is None else L
+    if ref_order is None:
+        ref_order = permutation(seed, election, m)
+    ref_order = np.ascontiguousarray(ref_order, dtype=np.int32)
+    out = np.empty((n, max(L, 1)), dtype=dtype)
+    rc = _load().gen_mallows_topk(seed, election, n, m, phi, _i32p(ref_order), k, max(L, 1),
+                                  int(dtype == np.int32), out.ctypes.data)
+    _check(rc, "gen_mallows_topk")
     return out
 
 
@@ -186,3 +204,41 @@ def plain_large(seed: int = 1003, n: int = 1_000_000, m: int = 16384) -> Workloa
     b = pl_zipf(seed, n, m, 1.1, 20)
     return Workload("plzipf_m%d_n%d_top20" % (m, n), m, n, b, "i32",
                     "Plackett-Luce Zipf s=1.1, top-20, m=%d, n=%d, seed %d" % (m, n, seed))
+
+
+def plain_learned(seed: int = 1005, n: int = 200_000, m: int = 32768) -> Workload:
+    """m=32768, n=200000 top-30 Plackett-Luce with Zipf(1.0) weights; int32 counts."""
+    b = pl_zipf(seed, n, m, 1.0, 30)
+    return Workload("plzipf_m%d_n%d_top30" % (m, n), m, n, b, "i32",
+                    "Plackett-Luce Zipf s=1.0, top-30, m=%d, n=%d, seed %d" % (m, n, seed))
+
+
+def training_mixture(seed: int, count: int, m_lo: int = 256, m_hi: int = 2048, full_m_hi: int = 1024):
+    """Elections for training the proposer: m ~ U{m_lo..m_hi}, n = round(rho m)
+    with rho ~ U[3, 12].  Election e is, by e mod 10:
+      0-4  Plackett-Luce top-k with Zipf(s) weights, s ~ U[0.8, 1.2], k ~ U{10..50};
+      5-8  Mallows top-k, phi ~ U[0.9, 1.0], k ~ U{10..50};
+      9    full Mallows rankings, phi ~ U[0.9, 1.0], with m capped at full_m_hi
+           (near phi = 1 these often have no Condorcet winner).
+    Yields dicts with the ballots (uint16) and the drawn parameters."""
+    ms = uniform_int(seed, 1, count, m_lo, m_hi)
+    rhos = uniform_real(seed, 2, count, 3.0, 12.0)
+    ks = uniform_int(seed, 3, count, 10, 50)
+    ss = uniform_real(seed, 4, count, 0.8, 1.2)
+    phis = uniform_real(seed, 5, count, 0.9, 1.0)
+    for e in range(count):
+        m, k = int(ms[e]), int(ks[e])
+        kind_id = e % 10
+        if kind_id == 9:
+            m = min(m, full_m_hi)
+        n = int(round(rhos[e] * m))
+        if kind_id <= 4:
+            b = pl_zipf(seed, n, m, float(ss[e]), k, election=e)
+            kind = "plzipf s=%.3f k=%d" % (ss[e], k)
+        elif kind_id <= 8:
+            b = mallows_topk(seed, n, m, float(phis[e]), k, election=e)
+            kind = "mallows-topk phi=%.3f k=%d" % (phis[e], k)
+        else:
+            b = mallows(seed, n, m, float(phis[e]), election=e)
+            kind = "mallows phi=%.3f" % phis[e]
+        yield {"election": e, "m": m, "n": n, "kind": kind, "ballots": b}

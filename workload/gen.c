@@ -214,6 +214,46 @@ int gen_pl_zipf(uint64_t seed, uint64_t election, int64_t n, int32_t m, double s
     return GEN_OK;
 }
 
+/*
+ * Top-k of a Mallows(phi) ranking around ref_order, by the inversion-vector
+ * form of the model: the t-th ranked item is the (V_t)-th item (0-based) of
+ * the reference order not yet chosen, with V_t independent and
+ * P(V_t = v) proportional to phi^v for v in {0 .. m-t} (the same
+ * distribution as the repeated insertion model, truncated after k places).
+ * Output: n x L ids, L >= k, padded.
+ */
+int gen_mallows_topk(uint64_t seed, uint64_t election, int64_t n, int32_t m, double phi,
+                     const int32_t *ref_order, int32_t k, int32_t L, int dtype32, void *out) {
+    if (n < 0 || m < 1 || k < 0 || k > m || L < k || L < 1 || !ref_order || !out) return GEN_EINVAL;
+    if (!dtype32 && m > 65535) return GEN_EINVAL;
+#pragma omp parallel
+    {
+        int32_t taken[4096];
+        int32_t *tk = k <= 4096 ? taken : (int32_t *)malloc(sizeof(int32_t) * (size_t)k);
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t v = 0; v < n; ++v) {
+            uint64_t st = stream_key(seed, election, (uint64_t)v);
+            int32_t nt = 0;  /* sorted reference positions already chosen */
+            int64_t base = v * (int64_t)L;
+            for (int32_t t = 0; t < k; ++t) {
+                int32_t remaining = m - t;
+                int32_t want = trunc_geom(&st, phi, remaining);  /* 0-based among remaining */
+                /* the want-th unchosen reference position */
+                int32_t pos = want, i = 0;
+                while (i < nt && tk[i] <= pos) { ++pos; ++i; }
+                /* insert pos into the sorted list */
+                int32_t j = nt++;
+                while (j > 0 && tk[j - 1] > pos) { tk[j] = tk[j - 1]; --j; }
+                tk[j] = pos;
+                store_id(out, dtype32, base + t, ref_order[pos]);
+            }
+            for (int32_t t = k; t < L; ++t) store_pad(out, dtype32, base + t);
+        }
+        if (tk != taken) free(tk);
+    }
+    return GEN_OK;
+}
+
 /* Uniform integers in [lo, hi] for per-election parameters (batch workloads). */
 int gen_uniform_int(uint64_t seed, uint64_t stream, int64_t count, int64_t lo, int64_t hi, int64_t *out) {
     if (count < 0 || hi < lo || (count > 0 && !out)) return GEN_EINVAL;
