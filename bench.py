@@ -43,9 +43,12 @@ def measured_traffic(kernel, workload_name):
         k, wl, src, sha, fetch, write = line.split()[:6]
         if k != kernel or wl != workload_name:
             continue
-        with open(os.path.join(ROOT, src), "rb") as f:
-            if not hashlib.sha256(f.read()).hexdigest().startswith(sha):
-                return None
+        h = hashlib.sha256()
+        for part in src.split("+"):  # the kernel's source files, hashed in order
+            with open(os.path.join(ROOT, part), "rb") as f:
+                h.update(f.read())
+        if not h.hexdigest().startswith(sha):
+            return None
         return float(fetch) + float(write)
     return None
 

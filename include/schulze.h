@@ -280,6 +280,117 @@ enum { SCHULZE_SCHEDULE_AUTO = 0, SCHULZE_SCHEDULE_PHASED = 1 };
 int schulze_set_closure_schedule(schulze_ctx *ctx, int schedule);
 
 /*
+ * Batches of independent elections (Section 2.1 applied to each election of
+ * the batch), run by one persistent launch whose workgroups take work items
+ * from a queue: ballot scans, pairwise counts split into runs of candidate
+ * sub-blocks and voter ranges, and per election one workgroup for weights,
+ * closure, winners and ranking.  Results equal schulze_pairwise,
+ * schulze_closure, schulze_winners and schulze_ranking applied election by
+ * election (int32 counts).
+ */
+#define SCHULZE_BATCH_MAX_M 1024
+
+/* One election of a batch.  Offsets are in elements of the arrays they index. */
+typedef struct {
+    int64_t ballot_off; /* first entry of the election's n x L ballots in `ballots` */
+    int64_t n;          /* ballots (voters), 0 <= n < 2^31 */
+    int32_t L;          /* entries per ballot, 1 <= L <= m */
+    int32_t m;          /* candidates, 1 <= m <= SCHULZE_BATCH_MAX_M */
+    int64_t mat_off;    /* first element of the election's m x m blocks (row pitch m) in d and p */
+    int64_t vec_off;    /* first element of its m-entry blocks in is_winner, beaten_by and order */
+} schulze_election;
+
+typedef struct {
+    int32_t max_range_pairs; /* 0 = automatic; else at most this many voter pairs per counting range */
+    int32_t closure_only;    /* 1 = the plan only serves runs without ballots (no rank-pair buffer) */
+    int32_t reserved[6];     /* zero */
+} schulze_batch_options;
+
+typedef struct schulze_batch schulze_batch;
+
+/*
+ * Plan a batch: validate the descriptors (host memory, E entries), choose per
+ * election the counting layout and the closure schedule (see
+ * schulze_batch_set_closure), order the work largest election first, and
+ * allocate the plan's device memory: about n*m*2 bytes of rank pairs per
+ * election, one closure matrix per resident workgroup, counters.
+ *
+ * Ballots follow schulze_pairwise (ids best first, padding ends a ballot), with
+ * two batch rules: an id after a padding entry is an invalid ballot, and an
+ * election with L >= m-1 is taken as complete rankings, so each of its
+ * ballots must list at least m-1 candidates (the unlisted one is last);
+ * elections with L < m-1 may end ballots early.  Voter weights are not
+ * supported.  Counts of elections with n <= 65535 run the closure on uint16,
+ * others on int32.
+ * ballot_dtype  SCHULZE_U16 or SCHULZE_I32; mode  schulze_weight_mode.
+ * opt           NULL for defaults.
+ */
+int schulze_batch_plan(schulze_ctx *ctx, const schulze_election *elections, int32_t E,
+                       int ballot_dtype, int mode, const schulze_batch_options *opt,
+                       schulze_batch **plan);
+
+/* Free a plan (synchronises the device).  NULL is accepted. */
+void schulze_batch_destroy(schulze_batch *plan);
+
+enum { SCHULZE_BATCH_GRAPH = 1 };
+
+/*
+ * Run a planned batch on `stream`.
+ *
+ * ballots    device ballots addressed by the descriptors, or NULL: then d is
+ *            an INPUT (counts of each election, e.g. from an earlier run; each
+ *            count at most the election's n) and only weights, closure,
+ *            winners and ranking run.
+ * d          int32 counts, written when ballots != NULL (d[x][x] = 0).
+ * p          NULL or int32 closures (p[x][x] = 0).
+ * is_winner  1 for Schulze winners, else 0.     n_winners: NULL or E int32.
+ * beaten_by  NULL or int32 (candidates beating x).  order: NULL or int32
+ *            (candidates by beaten_by, then id), as schulze_ranking.
+ * All are device pointers that the descriptors' offsets index; the caller
+ * sizes them.  Invalid ballots set the device error word to SCHULZE_EBALLOT.
+ * flags      SCHULZE_BATCH_GRAPH: capture the reset of the plan's counters and
+ *            the persistent launch in a HIP graph on first use (again when any
+ *            pointer argument changes) and launch the graph; 0: launch directly.
+ * Calls on one plan must not overlap (the plan owns the queue counters).
+ */
+int schulze_batch_run(schulze_ctx *ctx, void *stream, schulze_batch *plan, const void *ballots,
+                      int32_t *d, int32_t *p, uint8_t *is_winner, int32_t *n_winners,
+                      int32_t *beaten_by, int32_t *order, int flags);
+
+/*
+ * Closure schedules of a batch election, chosen per value width (16 or 32
+ * bits) and per bucket of 32 candidate counts (1-32, 33-64, ...):
+ *   REGISTERS  plain Floyd-Warshall recurrence with the matrix, padded to a
+ *              multiple of 32, in the registers of one workgroup (at most
+ *              192 candidates for 16-bit values, 128 for 32-bit);
+ *   TILED32/64/128  three-phase blocked recurrence with tiles of that size
+ *              (TILED32 and TILED128 for 16-bit values only).
+ * AUTO (-1) restores the built-in choice.  Plans read the table when created.
+ */
+enum {
+    SCHULZE_BATCH_CLOSURE_AUTO = -1,
+    SCHULZE_BATCH_CLOSURE_REGISTERS = 0,
+    SCHULZE_BATCH_CLOSURE_TILED32 = 1,
+    SCHULZE_BATCH_CLOSURE_TILED64 = 2,
+    SCHULZE_BATCH_CLOSURE_TILED128 = 3
+};
+int schulze_batch_set_closure(schulze_ctx *ctx, int32_t value_bits, int32_t m_lo, int32_t m_hi,
+                              int32_t variant);
+/* The schedule a plan would use for an election of m candidates. */
+int schulze_batch_get_closure(schulze_ctx *ctx, int32_t value_bits, int32_t m, int32_t *variant);
+
+/*
+ * Autotuner: for each bucket of 32 candidate counts up to m_max, time every
+ * schedule that applies on a closure-only batch of one election per resident
+ * workgroup (pseudo-random tournament counts at the bucket's largest m) and
+ * store the fastest in the context's table.  ms: NULL or host floats
+ * [ceil(m_max/32)][4], the best of two timed runs per schedule in
+ * milliseconds (-1 where a schedule does not apply).  Synchronises `stream`.
+ */
+int schulze_batch_autotune(schulze_ctx *ctx, void *stream, int32_t value_bits, int32_t m_max,
+                           float *ms);
+
+/*
  * Per-kernel timing (a profiling aid, off by default).  While enabled, every
  * kernel the library launches is bracketed by HIP events on its own stream;
  * schulze_kernel_time synchronises and returns the number of launches and
@@ -288,7 +399,8 @@ int schulze_set_closure_schedule(schulze_ctx *ctx, int schedule);
  * "count_trunc", "count_sparse", "count_finish", "weights", "fw_diag", "fw_panel",
  * "fw_rest", "fw_persist", "fw_store", "beaten_by", "rank_sort",
  * "winners", "fill", "widest", "verdict", "features", "mlp_prepare",
- * "mlp_forward", "mlp_backward", "mlp_loss", "mlp_adam", "propose".
+ * "mlp_forward", "mlp_backward", "mlp_loss", "mlp_adam", "propose", "batch"
+ * (a batch run: the persistent launch, or the whole graph when captured).
  */
 int schulze_set_timing(schulze_ctx *ctx, int enable);
 int schulze_kernel_time(schulze_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms);

@@ -31,6 +31,8 @@ EXPORTS = (
     "schulze_weights", "schulze_widest_from", "schulze_verify", "schulze_features",
     "schulze_mlp_param_count", "schulze_mlp_forward", "schulze_mlp_loss", "schulze_mlp_backward", "schulze_mlp_adam",
     "schulze_winners_learned",
+    "schulze_batch_plan", "schulze_batch_destroy", "schulze_batch_run", "schulze_batch_set_closure",
+    "schulze_batch_get_closure", "schulze_batch_autotune",
 )
 
 
@@ -43,6 +45,22 @@ class LearnedStats(ctypes.Structure):
 SCHEDULE_AUTO, SCHEDULE_PHASED = 0, 1
 
 _lib = None
+
+
+BATCH_MAX_M = 1024
+BATCH_GRAPH = 1
+CLOSURE_VARIANTS = {"auto": -1, "registers": 0, "tiled32": 1, "tiled64": 2, "tiled128": 3}
+
+
+class Election(ctypes.Structure):
+    """One election of a batch (offsets in elements)."""
+    _fields_ = [("ballot_off", ctypes.c_int64), ("n", ctypes.c_int64), ("L", ctypes.c_int32),
+                ("m", ctypes.c_int32), ("mat_off", ctypes.c_int64), ("vec_off", ctypes.c_int64)]
+
+
+class BatchOptions(ctypes.Structure):
+    _fields_ = [("max_range_pairs", ctypes.c_int32), ("closure_only", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class SchulzeError(RuntimeError):
@@ -91,8 +109,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.schulze_mlp_backward.argtypes = [vp, vp, vp, vp, c_i64, vp, vp]
     lib.schulze_mlp_adam.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                      ctypes.c_float, c_i32]
+    lib.schulze_batch_plan.argtypes = [vp, ctypes.POINTER(Election), c_i32, c_int, c_int,
+                                       ctypes.POINTER(BatchOptions), ctypes.POINTER(vp)]
+    lib.schulze_batch_destroy.argtypes = [vp]
+    lib.schulze_batch_destroy.restype = None
+    lib.schulze_batch_run.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, c_int]
+    lib.schulze_batch_set_closure.argtypes = [vp, c_i32, c_i32, c_i32, c_i32]
+    lib.schulze_batch_get_closure.argtypes = [vp, c_i32, c_i32, ctypes.POINTER(c_i32)]
+    lib.schulze_batch_autotune.argtypes = [vp, vp, c_i32, c_i32, ctypes.POINTER(ctypes.c_float)]
     for name in EXPORTS:
-        if name not in ("schulze_destroy", "schulze_strerror"):
+        if name not in ("schulze_destroy", "schulze_strerror", "schulze_batch_destroy"):
             getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -344,6 +370,70 @@ class Context:
         _check(rc, "schulze_winners_learned")
         return w, nw, st.as_dict()
 
+    # -------------------------------------------------------------- batches
+    def batch_plan(self, elections, ballot_dtype="u16", mode="winning_votes", max_range_pairs=0,
+                   closure_only=False):
+        """Plan a batch.  elections: sequence of (ballot_off, n, L, m, mat_off,
+        vec_off) tuples (element offsets) or of Election structs."""
+        import torch
+        bcode = U16 if ballot_dtype in ("u16", U16, torch.uint16) else (
+            I32 if ballot_dtype in ("i32", I32, torch.int32) else None)
+        if bcode is None:
+            raise ValueError("ballot dtype must be uint16 or int32")
+        E = len(elections)
+        arr = (Election * max(E, 1))()
+        for i, el in enumerate(elections):
+            arr[i] = el if isinstance(el, Election) else Election(*[int(v) for v in el])
+        opt = BatchOptions(int(max_range_pairs), int(bool(closure_only)))
+        h = ctypes.c_void_p()
+        rc = self._lib.schulze_batch_plan(self._h, arr, E, bcode, _mode_code(mode), ctypes.byref(opt), ctypes.byref(h))
+        _check(rc, "schulze_batch_plan")
+        d_elems = max((arr[i].mat_off + arr[i].m * arr[i].m for i in range(E)), default=0)
+        vec_elems = max((arr[i].vec_off + arr[i].m for i in range(E)), default=0)
+        return BatchPlan(self, h, E, bcode, d_elems, vec_elems)
+
+    def batch_run(self, plan, ballots, d, is_winner, p=None, n_winners=None, beaten_by=None, order=None,
+                  graph=False):
+        """Run a planned batch (ballots None: d is the input counts)."""
+        import torch
+
+        def ptr(t, what, dtype, elems):
+            if t is None:
+                return None
+            if t.dtype != dtype or not t.is_contiguous() or t.numel() < elems:
+                raise ValueError(f"{what} must be a contiguous {dtype} tensor of at least {elems} elements")
+            return self._dev(t, what)
+
+        if ballots is not None and ballots.dtype != _torch_dtype(plan.ballot_dtype):
+            raise ValueError("ballots dtype differs from the plan's")
+        bp = None if ballots is None else self._dev(ballots, "ballots")
+        rc = self._lib.schulze_batch_run(
+            self._h, self._stream(), plan._h, bp, ptr(d, "d", torch.int32, plan.d_elems),
+            ptr(p, "p", torch.int32, plan.d_elems), ptr(is_winner, "is_winner", torch.uint8, plan.vec_elems),
+            ptr(n_winners, "n_winners", torch.int32, plan.E), ptr(beaten_by, "beaten_by", torch.int32, plan.vec_elems),
+            ptr(order, "order", torch.int32, plan.vec_elems), BATCH_GRAPH if graph else 0)
+        _check(rc, "schulze_batch_run")
+
+    def batch_set_closure(self, value_bits: int, m_lo: int, m_hi: int, variant) -> None:
+        v = CLOSURE_VARIANTS[variant] if isinstance(variant, str) else int(variant)
+        _check(self._lib.schulze_batch_set_closure(self._h, value_bits, m_lo, m_hi, v), "schulze_batch_set_closure")
+
+    def batch_get_closure(self, value_bits: int, m: int) -> str:
+        v = ctypes.c_int32(0)
+        _check(self._lib.schulze_batch_get_closure(self._h, value_bits, m, ctypes.byref(v)),
+               "schulze_batch_get_closure")
+        return {c: k for k, c in CLOSURE_VARIANTS.items()}[v.value]
+
+    def batch_autotune(self, value_bits: int, m_max: int):
+        """Time every closure schedule per bucket of 32 candidates up to m_max
+        and keep the fastest; returns the (buckets, 4) millisecond table."""
+        import numpy as np
+        nb = (m_max + 31) // 32
+        ms = (ctypes.c_float * (nb * 4))()
+        _check(self._lib.schulze_batch_autotune(self._h, self._stream(), value_bits, m_max, ms),
+               "schulze_batch_autotune")
+        return np.array(ms[:], dtype=np.float32).reshape(nb, 4)
+
     def set_closure_schedule(self, schedule: str) -> None:
         """"auto" (one persistent launch) or "phased" (three launches per round)."""
         code = {"auto": SCHEDULE_AUTO, "phased": SCHEDULE_PHASED}[schedule]
@@ -363,3 +453,26 @@ class Context:
         _check(self._lib.schulze_kernel_time(self._h, name.encode(), ctypes.byref(n), ctypes.byref(ms)),
                "schulze_kernel_time")
         return n.value, ms.value
+
+
+class BatchPlan:
+    """A planned batch (owns the plan's device memory until destroyed)."""
+
+    def __init__(self, ctx, handle, E, ballot_dtype, d_elems, vec_elems):
+        self._ctx = ctx
+        self._h = handle
+        self.E = E
+        self.ballot_dtype = ballot_dtype
+        self.d_elems = d_elems
+        self.vec_elems = vec_elems
+
+    def destroy(self) -> None:
+        if getattr(self, "_h", None):
+            self._ctx._lib.schulze_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -50,6 +50,12 @@ struct schulze_ctx {
     std::vector<double> total_ms;
     // closure schedule: false = one persistent launch when possible
     bool force_phased = false;
+    // batch closure schedule per value width (16, 32) and bucket of 32 candidates; -1 = built-in
+    int8_t batch_variant[2][SCHULZE_BATCH_MAX_M / 32];
+    schulze_ctx() {
+        for (auto &row : batch_variant)
+            for (auto &v : row) v = -1;
+    }
 };
 
 // Kernel names used by the timing facility (index = id).
@@ -80,6 +86,7 @@ enum KernelId {
     K_MLP_LOSS,
     K_MLP_ADAM,
     K_PROPOSE,
+    K_BATCH,
     K_NUM_KERNELS
 };
 extern const char *const kKernelNames[K_NUM_KERNELS];

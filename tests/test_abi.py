@@ -56,6 +56,17 @@ def test_null_handles_are_rejected_on_the_host():
     ms = ctypes.c_double()
     assert lib.schulze_kernel_time(None, b"count_dense", ctypes.byref(n), ctypes.byref(ms)) == sz.EINVAL
     lib.schulze_destroy(vp(None))  # accepted
+    h = vp()
+    el = sz.Election(0, 1, 1, 1, 0, 0)
+    assert lib.schulze_batch_plan(None, ctypes.byref(el), 1, sz.U16, 0, None, ctypes.byref(h)) == sz.EINVAL
+    assert lib.schulze_batch_plan(None, ctypes.byref(el), 1, sz.U16, 0, None, None) == sz.EINVAL
+    assert not h.value
+    assert lib.schulze_batch_run(None, None, None, None, None, None, None, None, None, None, 0) == sz.EINVAL
+    assert lib.schulze_batch_set_closure(None, 16, 1, 32, 0) == sz.EINVAL
+    v = ctypes.c_int32()
+    assert lib.schulze_batch_get_closure(None, 16, 32, ctypes.byref(v)) == sz.EINVAL
+    assert lib.schulze_batch_autotune(None, None, 16, 64, None) == sz.EINVAL
+    lib.schulze_batch_destroy(vp(None))  # accepted
 
 
 def test_create_without_a_device_fails_cleanly():

@@ -213,6 +213,47 @@ def plain_learned(seed: int = 1005, n: int = 200_000, m: int = 32768) -> Workloa
                     "Plackett-Luce Zipf s=1.0, top-30, m=%d, n=%d, seed %d" % (m, n, seed))
 
 
+def batch_params(seed: int = 1004, count: int = 4096, m_lo: int = 8, m_hi: int = 512, n_lo: int = 50,
+                 n_hi: int = 20000, phi_lo: float = 0.5, phi_hi: float = 1.0):
+    """Per-election sizes of a batch of independent elections:
+    m ~ U{m_lo..m_hi}, n ~ U{n_lo..n_hi}, phi ~ U[phi_lo, phi_hi]."""
+    ms = uniform_int(seed, 11, count, m_lo, m_hi)
+    ns = uniform_int(seed, 12, count, n_lo, n_hi)
+    phis = uniform_real(seed, 13, count, phi_lo, phi_hi)
+    return ms.astype(np.int64), ns.astype(np.int64), phis
+
+
+def batch_election(seed: int, e: int, m: int, n: int, phi: float) -> np.ndarray:
+    """Ballots of election e of a batch: n full Mallows(phi) rankings (uint16)
+    around the election's own seeded reference order."""
+    return mallows(seed, int(n), int(m), float(phi), election=int(e), dtype=np.uint16)
+
+
+def batch_mallows(seed: int = 1004, count: int = 4096, **size_kw):
+    """A batch of `count` elections of full Mallows rankings with the sizes of
+    batch_params, ballots written back to back into one flat uint16 array.
+    Returns (flat ballots, descriptors, (ms, ns, phis)); a descriptor is
+    (ballot_off, n, L, m, mat_off, vec_off) with L = m and the m x m and
+    m-entry output blocks laid out back to back."""
+    ms, ns, phis = batch_params(seed, count, **size_kw)
+    total = int(np.sum(ms * ns))
+    flat = np.empty(max(total, 1), dtype=np.uint16)
+    desc = []
+    bo = mo = vo = 0
+    lib = _load()
+    for e in range(count):
+        m, n = int(ms[e]), int(ns[e])
+        ref = permutation(seed, e, m)
+        rc = lib.gen_mallows(seed, e, n, m, float(phis[e]), _i32p(ref), m, 0, 0, 0, 0,
+                             flat.ctypes.data + 2 * bo)
+        _check(rc, "gen_mallows")
+        desc.append((bo, n, m, m, mo, vo))
+        bo += n * m
+        mo += m * m
+        vo += m
+    return flat, desc, (ms, ns, phis)
+
+
 def training_mixture(seed: int, count: int, m_lo: int = 256, m_hi: int = 2048, full_m_hi: int = 1024):
     """Elections for training the proposer: m ~ U{m_lo..m_hi}, n = round(rho m)
     with rho ~ U[3, 12].  Election e is, by e mod 10:
