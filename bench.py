@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 VALU_LANE_OPS = 256 * 64 * 2.4e9
 HBM_BYTES = 8.0e12
 
-WORKLOADS = ("mid", "small", "large", "learned")
+WORKLOADS = ("mid", "small", "large", "learned", "batch")
 
 
 def measured_traffic(kernel, workload_name):
@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--workload", choices=WORKLOADS, default="mid")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-voters", type=int, default=3000)
+    ap.add_argument("--batch-elections", type=int, default=4096)
     ap.add_argument("--closure-schedule", choices=("auto", "phased"), default="auto")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, copy a 1 GiB buffer once (a known-size reference "
@@ -145,6 +146,145 @@ def bench_learned(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_batch(args):
+    """4096 independent elections (m ~ U{8..512}, n ~ U{50..20000}, full
+    Mallows rankings with phi ~ U[0.5, 1]) in one persistent launch replayed
+    from a captured HIP graph, against one pass of per-election calls
+    (pairwise, closure, winners, ranking for each election in turn)."""
+    import numpy as np
+    import torch
+
+    import paper_2505_12976_amd as sz
+    import workload
+    from paper_2505_12976_amd.batch import Packed, alloc_outputs
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    E = args.batch_elections
+    t0 = time.time()
+    flat, desc, (ms, ns, phis) = workload.batch_mallows(1004, E)
+    print(f"[bench] batch of {E} elections generated in {time.time() - t0:.1f}s "
+          f"({flat.nbytes / 1e9:.1f} GB of ballots)", file=sys.stderr, flush=True)
+    packed = Packed(flat, desc, int(np.sum(ms * ms)), int(np.sum(ms)))
+    ctx = sz.Context(0)
+    ballots = torch.from_numpy(flat).to(dev)
+    del flat
+    t0 = time.time()
+    tune_ms = ctx.batch_autotune(16, int(ms.max()))
+    names = ["registers", "tiled32", "tiled64", "tiled128"]
+    tuned = [ctx.batch_get_closure(16, 32 * (b + 1)) for b in range(tune_ms.shape[0])]
+    print(f"[bench] autotuned closure schedules in {time.time() - t0:.1f}s: {tuned}", file=sys.stderr, flush=True)
+    plan = ctx.batch_plan(desc, "u16", "winning_votes")
+    outs = alloc_outputs(packed, dev)
+
+    def run():
+        ctx.batch_run(plan, ballots, outs["d"], outs["is_winner"], p=outs["p"], n_winners=outs["n_winners"],
+                      beaten_by=outs["beaten_by"], order=outs["order"], graph=True)
+
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    if ctx.device_error() != 0:
+        raise RuntimeError("device error during warmup")
+    ctx.reset_timing()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        run()
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    ctx.set_timing(False)
+    ms_per_step = (t_end - t_start) * 1e3 / args.steps
+    launches, total = ctx.kernel_time("batch")
+    kernel_ms = total / max(launches, 1)
+    print(f"[bench] batch: {ms_per_step:.2f} ms per step (graph {kernel_ms:.2f} ms)", file=sys.stderr, flush=True)
+
+    # per-election launches: the same outputs, election by election
+    d_ref = torch.empty_like(outs["d"])
+    p_ref = torch.empty_like(outs["p"])
+    w_ref = torch.empty_like(outs["is_winner"])
+    o_ref = torch.empty_like(outs["order"])
+    bb_ref = torch.empty_like(outs["beaten_by"])
+
+    def per_election():
+        for e, (bo, n, L, m, mo, vo) in enumerate(desc):
+            b = ballots[bo:bo + n * L].view(n, L)
+            d = ctx.pairwise(b, m, dtype="i32", out=d_ref[mo:mo + m * m].view(m, m))
+            p = ctx.closure(d, "winning_votes", out=p_ref[mo:mo + m * m].view(m, m))
+            w, _ = ctx.winners(p)
+            order, beaten = ctx.ranking(p)
+            w_ref[vo:vo + m].copy_(w)
+            o_ref[vo:vo + m].copy_(order)
+            bb_ref[vo:vo + m].copy_(beaten)
+
+    per_election()  # warm-up (workspace growth)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    per_election()
+    torch.cuda.synchronize()
+    t_per = time.perf_counter() - t0
+    exact = bool(torch.equal(d_ref, outs["d"]) and torch.equal(p_ref, outs["p"]) and
+                 torch.equal(w_ref, outs["is_winner"]) and torch.equal(o_ref, outs["order"]) and
+                 torch.equal(bb_ref, outs["beaten_by"]))
+    print(f"[bench] per-election calls: {t_per * 1e3:.1f} ms, identical outputs: {exact}", file=sys.stderr,
+          flush=True)
+    if ctx.device_error() != 0:
+        raise RuntimeError("device error")
+
+    # algorithmic work: one VALU lane-op per (voter, candidate pair) of the count,
+    # one per packed max-min update of the closure (padded sizes actually run)
+    count_ops = float(np.sum(ns * ms * (ms - 1) / 2))
+    closure_ops = float(np.sum(ms.astype(np.float64) ** 3))
+    work = count_ops + closure_ops
+    roof = {"bound": "alu", "kernel": "batch", "achieved": work / (kernel_ms / 1e3) / 1e12,
+            "peak": VALU_LANE_OPS / 1e12, "unit": "Tops/s",
+            "traffic": measured_traffic("batch", "batch_mallows_E%d" % E)}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    out = {
+        "metric": "closure Gop/s (max-min) + elections/sec; learned-verify vs full-closure speedup",
+        "value": E / (ms_per_step / 1e3),
+        "unit": "elections/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i32",
+        "data": "synthetic",
+        "config": {"workload": "batch_mallows_E%d" % E, "elections": E, "m": "U{8..512}", "n": "U{50..20000}",
+                   "phi": "U[0.5,1.0]", "seed": 1004, "weight_mode": "winning_votes", "parallelism": "single GPU",
+                   "launch": "one persistent kernel per step, replayed from a captured HIP graph"},
+        "elections_per_s_per_election_calls": E / t_per,
+        "speedup_vs_per_election_calls": t_per / (ms_per_step / 1e3),
+        "ms_per_election_calls_pass": t_per * 1e3,
+        "identical_to_per_election_calls": exact,
+        "graph_ms": kernel_ms,
+        "count_comparisons": count_ops,
+        "closure_updates": closure_ops,
+        "closure_schedule_by_bucket": tuned,
+        "roofline": roof,
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        import oracle
+        print("[bench] timing the CPU oracle on a sample of elections", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        k = 0
+        while k < E and time.perf_counter() - t0 < 20.0:
+            b = workload.batch_election(1004, k, int(ms[k]), int(ns[k]), float(phis[k]))
+            oracle.schulze(b, int(ms[k]))
+            k += 1
+        t_cpu = time.perf_counter() - t0
+        cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+        out["cpu_baseline"] = {"value": k / t_cpu, "unit": "elections/s", "cores": cores, "kind": "oracle",
+                               "sample": f"the first {k} of the {E} elections, whole path per election "
+                                         f"({t_cpu:.1f} s; ballot generation excluded)"}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(wl, sample_voters):
     """Oracle on a bounded sample: the count over the first `sample_voters`
     ballots (scaled to all n), then weights, closure and ranking at full m."""
@@ -180,6 +320,9 @@ def main():
         sys.exit(2)
     if args.workload == "learned":
         bench_learned(args)
+        return
+    if args.workload == "batch":
+        bench_batch(args)
         return
 
     import numpy as np

@@ -21,11 +21,12 @@
 //           one election in one workgroup, started by the workgroup that
 //           completes the election's last count item.
 //
-// The queue holds every scan before every count.  A count item waits only
-// for the scans of its own election, whose tickets are smaller and are held
-// by workgroups that are already running and never wait, so every wait ends
-// however many workgroups are resident.  A bounded spin turns anything else
-// into a device error.
+// The scans of an election come before its counts in the queue (a few
+// elections ahead, so that memory-bound scans overlap VALU-bound counts).  A
+// count item waits only for the scans of its own election, whose tickets are
+// smaller and are held by workgroups that are already running and never
+// wait, so every wait ends however many workgroups are resident.  A bounded
+// spin turns anything else into a device error.
 //
 // The closure of the finish runs on a per-workgroup scratch matrix of uint16
 // (counts of elections with at most 65535 voters) or int32, padded with zero
@@ -49,12 +50,12 @@ constexpr int BT = 256;                          // threads per workgroup
 constexpr int STAGE_WORDS = 16384;               // count staging: VC x cols words
 constexpr int SRED_WORDS = SCHULZE_BATCH_MAX_M;  // column sums of a count item
 constexpr int SMEM_WORDS = STAGE_WORDS + SRED_WORDS + 64;
-constexpr size_t SMEM_BYTES = sizeof(uint32_t) * SMEM_WORDS;
 constexpr int SEG_PAIRS = 32767;           // at most 65534 voters per exact sum
 constexpr int64_t SCAN_WORDS = 1 << 20;    // rank-pair words written per scan item
-constexpr int SCAN_GROUP_WORDS = 8192;     // rank-pair words staged at once by a scan
+constexpr int SCAN_GROUP_WORDS = 16384;    // rank-pair words staged at once by a scan
+constexpr int SCAN_UNROLL = 64;            // ballot loads in flight per thread
 constexpr int SCAN_GROUP_PAIRS = 32;      // voter pairs staged at once by a scan, at most
-constexpr int MAX_PF = 16;                 // 16-byte loads per thread per count chunk
+constexpr int MAX_PF = 8;                  // 16-byte loads per thread per count chunk
 constexpr uint16_t UNSET = 0xFFFF;
 constexpr int64_t SPIN_LIMIT = (int64_t)1 << 24;
 
@@ -111,14 +112,22 @@ struct BatchArgs {
     int32_t *err;
 };
 
-__device__ inline int32_t read_ballot(const void *ballots, int32_t dtype32, int64_t idx) {
-    if (dtype32) {
-        const int32_t v = static_cast<const int32_t *>(ballots)[idx];
-        return v < 0 ? -1 : v;
-    }
-    const uint16_t v = static_cast<const uint16_t *>(ballots)[idx];
-    return v == 0xFFFF ? -1 : (int32_t)v;
+// Every device-memory access of this file goes through FW_GLOBAL pointers, so
+// that it compiles to global_* instructions: flat ones would also count as
+// LDS operations and every LDS wait would then wait for them too.
+template <typename T>
+__device__ __forceinline__ FW_GLOBAL T *gmem(T *p) {
+    return (FW_GLOBAL T *)p;
 }
+
+// LDS of the persistent kernel, used by every function below.  Static (not
+// dynamic) so that its address is a constant in every function; a dynamic
+// array is located through a table lookup in functions that are not kernels.
+__shared__ __attribute__((aligned(16))) uint32_t batch_smem[SMEM_WORDS];
+
+// Candidate id of a ballot entry, -1 for padding.
+__device__ inline int32_t ballot_id(int32_t v) { return v < 0 ? -1 : v; }
+__device__ inline int32_t ballot_id(uint16_t v) { return v == 0xFFFF ? -1 : (int32_t)v; }
 
 // floor(x / d) for 0 <= x < 2^16 and 1 <= d <= 2^16, with inv = ceil(2^32 / d):
 // the error x * (inv - 2^32/d) / 2^32 < 2^-16 <= 1/d never crosses an integer.
@@ -129,7 +138,7 @@ __host__ __device__ inline int32_t scan_group_pairs(int32_t pitch) {
 }
 
 __device__ inline void abort_all(const BatchArgs &a) {
-    __hip_atomic_store(&a.ctr[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(gmem(a.ctr) + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     set_device_error(a.err, SCHULZE_EDEVICE);
 }
 
@@ -139,7 +148,13 @@ __device__ inline void abort_all(const BatchArgs &a) {
 // valid iff no id follows a padding entry, every listed id is < m, and the
 // listed ids leave exactly m - k candidates unset (no repeats).  Complete
 // elections (L >= m - 1) also need k >= m - 1: their unset candidate is last.
-__device__ void scan_item(const BatchArgs &a, const BElec &el, int64_t q0, int64_t nq, uint32_t *smem) {
+template <typename Id>
+__device__ __attribute__((noinline)) void scan_item(const BatchArgs &a, const BElec &el_in, int64_t q0, int64_t nq) {
+    // Local copies: a re-read through the references would be a flat load,
+    // and every flat load waits for all outstanding global loads.
+    const BElec el = el_in;
+    uint32_t *smem = batch_smem;
+    const FW_GLOBAL Id *ballots = gmem(static_cast<const Id *>(a.ballots));
     const int tid = threadIdx.x;
     const int32_t m = el.m, L = el.L, pitch = el.pitch;
     const bool complete = (el.flags & EF_SQUARE) == 0;
@@ -150,10 +165,10 @@ __device__ void scan_item(const BatchArgs &a, const BElec &el, int64_t q0, int64
     int32_t *unset = npads + 64;
     const uint32_t inv_l = L > 1 ? (uint32_t)((0x100000000ull + (uint64_t)L - 1) / (uint64_t)L) : 0u;
     const uint32_t inv_p = (uint32_t)((0x100000000ull + (uint64_t)pitch - 1) / (uint64_t)pitch);
-    uint32_t *pos = a.pos + el.pos_off;
+    FW_GLOBAL uint32_t *pos = gmem(a.pos + el.pos_off);
 
     if ((el.flags & EF_MULTI) && q0 == 0) {  // counts accumulate with atomics: start at zero
-        int32_t *D = a.d + el.mat_off;
+        FW_GLOBAL int32_t *D = gmem(a.d + el.mat_off);
         for (int64_t i = tid; i < (int64_t)m * m; i += BT) D[i] = 0;
     }
     bool bad = false;
@@ -161,8 +176,10 @@ __device__ void scan_item(const BatchArgs &a, const BElec &el, int64_t q0, int64
         const int32_t npg = (int32_t)min((int64_t)vpb, q0 + nq - g);
         const int64_t v0 = 2 * g;  // first voter of the group
         const int32_t nballots = (int32_t)min((int64_t)2 * npg, el.n - v0);
+        const int32_t nquads = npg * pitch / 4;  // pitch is a multiple of 8
         __syncthreads();
-        for (int32_t w = tid; w < npg * pitch; w += BT) smem[w] = 0xFFFFFFFFu;
+        for (int32_t w4 = tid; w4 < nquads; w4 += BT)
+            reinterpret_cast<v4u32 *>(smem)[w4] = v4u32{0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
         if (tid < 2 * vpb) {
             first_pad[tid] = L;
             npads[tid] = 0;
@@ -171,38 +188,60 @@ __device__ void scan_item(const BatchArgs &a, const BElec &el, int64_t q0, int64
         __syncthreads();
         const int64_t base = el.ballot_off + v0 * (int64_t)L;  // ballots of the group are contiguous
         const int32_t entries = nballots * L;                // < 2^16
-        for (int32_t f = tid; f < entries; f += BT) {
-            const int32_t b = L == 1 ? f : (int32_t)div_small((uint32_t)f, inv_l);
-            const int32_t t = f - b * L;
-            const int32_t id = read_ballot(a.ballots, a.dtype32, base + f);
-            if (id < 0) {
-                atomicAdd(&npads[b], 1);
-                atomicMin(&first_pad[b], t);
-            } else if (id >= m) {
-                bad = true;
-            } else {
-                buf[(b >> 1) * 2 * pitch + 2 * id + (b & 1)] = (uint16_t)t;
+        // SCAN_UNROLL unconditional loads in flight per thread (entries past the
+        // group re-read its last entry and are skipped), then their scatter
+        for (int32_t f0 = tid; f0 < entries; f0 += BT * SCAN_UNROLL) {
+            Id raw[SCAN_UNROLL];
+#pragma unroll
+            for (int j = 0; j < SCAN_UNROLL; ++j) {
+                const int32_t f = f0 + BT * j;
+                raw[j] = ballots[base + (f < entries ? f : entries - 1)];
+            }
+#pragma unroll
+            for (int j = 0; j < SCAN_UNROLL; ++j) {
+                const int32_t f = f0 + BT * j;
+                const bool in = f < entries;  // else past the group's entries (b, t unused)
+                const int32_t id = ballot_id(raw[j]);
+                const int32_t b = (int32_t)div_small((uint32_t)f, inv_l) + (L == 1 ? f : 0);  // inv_l = 0 if L = 1
+                const int32_t t = f - b * L;
+                bad |= in && id >= m;
+                if (in && (uint32_t)id < (uint32_t)m) buf[(b >> 1) * 2 * pitch + 2 * id + (b & 1)] = (uint16_t)t;
+                if (in && id < 0) {  // padding: rare, and never in complete elections' valid ballots
+                    atomicAdd(&npads[b], 1);
+                    atomicMin(&first_pad[b], t);
+                }
             }
         }
         __syncthreads();
-        for (int32_t w = tid; w < npg * pitch; w += BT) {
+        // four words per thread: one voter pair's columns c .. c+3 (pitch is a multiple of 8)
+        for (int32_t w4 = tid; w4 < nquads; w4 += BT) {
+            const int32_t w = 4 * w4;
             const int32_t q = (int32_t)div_small((uint32_t)w, inv_p);
-            const int32_t c = w - q * pitch;
-            const uint32_t word = smem[w];
-            uint32_t lo = word & 0xFFFFu, hi = word >> 16;
+            const int32_t c0 = w - q * pitch;
             const bool has_hi = 2 * q + 1 < nballots;
-            if (c < m) {
-                if (lo == UNSET) atomicAdd(&unset[2 * q], 1);
-                if (has_hi && hi == UNSET) atomicAdd(&unset[2 * q + 1], 1);
-                if (complete) {
-                    if (lo == UNSET) lo = (uint32_t)(m - 1);
-                    if (hi == UNSET) hi = (uint32_t)(m - 1);
+            const v4u32 in4 = reinterpret_cast<const v4u32 *>(smem)[w4];
+            const uint32_t words[4] = {in4.x, in4.y, in4.z, in4.w};
+            uint32_t out[4];
+            int32_t un_lo = 0, un_hi = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                uint32_t lo = words[e] & 0xFFFFu, hi = words[e] >> 16;
+                if (c0 + e < m) {
+                    un_lo += lo == UNSET ? 1 : 0;
+                    un_hi += (has_hi && hi == UNSET) ? 1 : 0;
+                    if (complete) {
+                        if (lo == UNSET) lo = (uint32_t)(m - 1);
+                        if (hi == UNSET) hi = (uint32_t)(m - 1);
+                    }
+                } else {
+                    lo = hi = 0u;
                 }
-            } else {
-                lo = hi = 0u;
+                if (!has_hi) hi = 0u;  // missing partner of an odd count: equal ranks, counts nothing
+                out[e] = lo | (hi << 16);
             }
-            if (!has_hi) hi = 0u;  // missing partner of an odd count: equal ranks, counts nothing
-            pos[(g + q) * (int64_t)pitch + c] = lo | (hi << 16);
+            if (un_lo) atomicAdd(&unset[2 * q], un_lo);
+            if (un_hi) atomicAdd(&unset[2 * q + 1], un_hi);
+            *(FW_GLOBAL v4u32 *)(pos + (g + q) * (int64_t)pitch + c0) = v4u32{out[0], out[1], out[2], out[3]};
         }
         __syncthreads();
         if (tid < nballots) {
@@ -231,14 +270,17 @@ __device__ inline void sub_coords(int32_t s, int32_t nb8, bool square, int32_t &
 
 typedef __attribute__((ext_vector_type(2))) unsigned short cus2;
 
-__device__ void finish(const BatchArgs &a, const BElec &el, int32_t e, uint32_t *smem);
+__device__ void finish(const BatchArgs &a, const BElec &el, int32_t e);
 
 // Sub-blocks [run * per_phase, ...) of election e over voter pairs of range
 // `range`.  Staged rows hold columns c0 .. 8 nb8 - 1 of VC voter pairs, each
 // 8-column block split into two 16-byte halves stored in separate row
 // halves so that neighbouring sub-blocks read neighbouring 16 bytes.
-__device__ void count_item(const BatchArgs &a, const BElec &el, int32_t e, int32_t run, int32_t range,
-                           uint32_t *smem) {
+__device__ __attribute__((noinline)) void count_item(const BatchArgs &a, const BElec &el_in, int32_t e, int32_t run,
+                                                    int32_t range) {
+    const BElec el = el_in;  // local copy (see scan_item)
+    const int64_t pitch = el.pitch;
+    uint32_t *smem = batch_smem;
     __shared__ int32_t sh_flag;
     const int tid = threadIdx.x;
     const bool square = (el.flags & EF_SQUARE) != 0;
@@ -260,12 +302,12 @@ __device__ void count_item(const BatchArgs &a, const BElec &el, int32_t e, int32
     const int32_t half = cols / 2;
     const int32_t nq = cols / 4;  // 16-byte quads per staged row
     const int32_t ng = el.ng, lg = ng == 1 ? 0 : (ng == 2 ? 1 : 2);
-    const int32_t VC = el.vc;  // 64 / ng: VC * cols <= STAGE_WORDS, ng * VC / 4 == MAX_PF
+    const int32_t VC = el.vc;  // 4 MAX_PF / ng: VC * cols <= STAGE_WORDS, ng * VC / 4 == MAX_PF
     const int64_t pairs = (el.n + 1) / 2;
     const int64_t p0 = (int64_t)range * el.range_pairs;
     const int64_t p1 = min(pairs, p0 + el.range_pairs);
     const uint32_t nv = (uint32_t)(min(el.n, 2 * p1) - 2 * p0);
-    const uint32_t *pos = a.pos + el.pos_off;
+    const FW_GLOBAL uint32_t *pos = gmem(a.pos + el.pos_off);
     uint32_t *stage = smem;
     uint32_t *sred = smem + STAGE_WORDS;
     const int32_t qlane = tid & 63, prow = tid >> 6;
@@ -274,8 +316,9 @@ __device__ void count_item(const BatchArgs &a, const BElec &el, int32_t e, int32
     if (tid == 0) {
         int32_t ok = 1;
         int64_t spins = 0;
-        while (__hip_atomic_load(&a.ctr[2 + e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < el.n_scan) {
-            if (__hip_atomic_load(&a.ctr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > SPIN_LIMIT) {
+        FW_GLOBAL int32_t *ctr = gmem(a.ctr);
+        while (__hip_atomic_load(ctr + 2 + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < el.n_scan) {
+            if (__hip_atomic_load(ctr + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > SPIN_LIMIT) {
                 abort_all(a);
                 ok = 0;
                 break;
@@ -290,7 +333,7 @@ __device__ void count_item(const BatchArgs &a, const BElec &el, int32_t e, int32
 
     uint32_t acc[8][8];
     uint32_t scol[4][4];
-    uint4 pf[MAX_PF];
+    v4u32 pf[MAX_PF];
 #pragma unroll
     for (int i = 0; i < 8; ++i)
 #pragma unroll
@@ -301,28 +344,35 @@ __device__ void count_item(const BatchArgs &a, const BElec &el, int32_t e, int32
         for (int j = 0; j < 4; ++j) scol[i][j] = 0u;
 
     // slot k holds quad qlane + 64 (k & (ng-1)) of voter pair prow + 4 (k >> lg)
+    // Unconditional loads, so that all MAX_PF are in flight at once: a slot
+    // outside the chunk reads the election's first word, and stage_store
+    // writes zeros for it instead.
+    auto slot_ok = [&](int k, int64_t q0) {
+        return qlane + 64 * (k & (ng - 1)) < nq && q0 + prow + 4 * (k >> lg) < p1;
+    };
     auto prefetch = [&](int64_t q0) {
 #pragma unroll
         for (int k = 0; k < MAX_PF; ++k) {
             const int32_t qd = qlane + 64 * (k & (ng - 1));
             const int64_t pr = q0 + prow + 4 * (k >> lg);
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (qd < nq && pr < p1) v = *reinterpret_cast<const uint4 *>(pos + pr * el.pitch + c0 + 4 * qd);
-            pf[k] = v;
+            pf[k] = *(const FW_GLOBAL v4u32 *)(pos + (slot_ok(k, q0) ? pr * pitch + c0 + 4 * qd : 0));
         }
     };
     const cus2 ones = {1, 1};
-    auto stage_store = [&]() {
+    auto stage_store = [&](int64_t q0) {
 #pragma unroll
         for (int k = 0; k < MAX_PF; ++k) {
             const int32_t qd = qlane + 64 * (k & (ng - 1));
             const int32_t vp = prow + 4 * (k >> lg);
             if (qd < nq) {
-                *reinterpret_cast<uint4 *>(stage + vp * cols + (qd & 1) * half + (qd >> 1) * 4) = pf[k];
-                scol[k & 3][0] = __builtin_amdgcn_udot2(__builtin_bit_cast(cus2, pf[k].x), ones, scol[k & 3][0], false);
-                scol[k & 3][1] = __builtin_amdgcn_udot2(__builtin_bit_cast(cus2, pf[k].y), ones, scol[k & 3][1], false);
-                scol[k & 3][2] = __builtin_amdgcn_udot2(__builtin_bit_cast(cus2, pf[k].z), ones, scol[k & 3][2], false);
-                scol[k & 3][3] = __builtin_amdgcn_udot2(__builtin_bit_cast(cus2, pf[k].w), ones, scol[k & 3][3], false);
+                const v4u32 v = slot_ok(k, q0) ? pf[k] : v4u32{0u, 0u, 0u, 0u};
+                *reinterpret_cast<v4u32 *>(stage + vp * cols + (qd & 1) * half + (qd >> 1) * 4) = v;
+                // words through scalars: a bit_cast of an element of a vector value
+                // has compiled to the first element here
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    scol[k & 3][q] = __builtin_amdgcn_udot2(__builtin_bit_cast(cus2, w[q]), ones, scol[k & 3][q], false);
             }
         }
     };
@@ -331,7 +381,7 @@ __device__ void count_item(const BatchArgs &a, const BElec &el, int32_t e, int32
     prefetch(p0);
     for (int64_t q0 = p0; q0 < p1; q0 += VC) {
         __syncthreads();  // previous chunk's compute is done with the stage
-        stage_store();
+        stage_store(q0);
         __syncthreads();
         if (q0 + VC < p1) prefetch(q0 + VC);  // overlaps the compute below
         const int32_t vend = (int32_t)min((int64_t)VC, p1 - q0);
@@ -392,7 +442,7 @@ __device__ void count_item(const BatchArgs &a, const BElec &el, int32_t e, int32
         for (int i = 0; i < 8; ++i) sx[i] = sred[8 * (bx - cb0) + i];
 #pragma unroll
         for (int j = 0; j < 8; ++j) sy[j] = sred[8 * (by - cb0) + j];
-        int32_t *D = a.d + el.mat_off;
+        FW_GLOBAL int32_t *D = gmem(a.d + el.mat_off);
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int32_t x = 8 * bx + i;
@@ -406,14 +456,17 @@ __device__ void count_item(const BatchArgs &a, const BElec &el, int32_t e, int32
                     if (x == y) {
                         if (!multi) D[(int64_t)x * m + y] = 0;
                     } else if (multi) {
-                        atomicAdd(&D[(int64_t)x * m + y], (int32_t)cnt);
+                        __hip_atomic_fetch_add(D + (int64_t)x * m + y, (int32_t)cnt, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
                     } else {
                         D[(int64_t)x * m + y] = (int32_t)cnt;
                     }
                 } else if (x < y) {
                     if (multi) {
-                        atomicAdd(&D[(int64_t)x * m + y], (int32_t)cnt);
-                        atomicAdd(&D[(int64_t)y * m + x], (int32_t)(nv - cnt));
+                        __hip_atomic_fetch_add(D + (int64_t)x * m + y, (int32_t)cnt, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_fetch_add(D + (int64_t)y * m + x, (int32_t)(nv - cnt), __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
                     } else {
                         D[(int64_t)x * m + y] = (int32_t)cnt;
                         D[(int64_t)y * m + x] = (int32_t)(nv - cnt);
@@ -428,11 +481,13 @@ __device__ void count_item(const BatchArgs &a, const BElec &el, int32_t e, int32
     // completion: the workgroup that finishes the election's last count item runs its finish
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    if (tid == 0) sh_flag = atomicAdd(&a.ctr[2 + a.n_elec + e], 1) == el.n_count - 1;
+    if (tid == 0)
+        sh_flag = __hip_atomic_fetch_add(gmem(a.ctr) + 2 + a.n_elec + e, 1, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT) == el.n_count - 1;
     __syncthreads();
     if (sh_flag) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        finish(a, el, e, smem);
+        finish(a, el, e);
     }
 }
 
@@ -442,7 +497,9 @@ __device__ void count_item(const BatchArgs &a, const BElec &el, int32_t e, int32
 // row and column r, then the rest; every tile becomes
 // max(P[I][J], P[I][r] (x) P[r][J]).
 template <typename E, int B>
-__device__ __attribute__((noinline)) void closure_tiled(E *P, int32_t mp, E *lds) {
+__device__ __attribute__((noinline)) void closure_tiled(E *P_, int32_t mp) {
+    FW_GLOBAL E *P = gmem(P_);
+    E *lds = reinterpret_cast<E *>(batch_smem);
     const int32_t nb = mp / B;
     auto tile = [&](int32_t I, int32_t J) { return P + (int64_t)I * B * mp + (int64_t)J * B; };
     for (int32_t r = 0; r < nb; ++r) {
@@ -477,35 +534,35 @@ __device__ __attribute__((noinline)) void closure_tiled(E *P, int32_t mp, E *lds
 // Each schedule is its own function: inlined together, their register
 // demands would be allocated as one and spill.
 template <typename E, int B>
-__device__ __attribute__((noinline)) void closure_reg(E *P, int32_t mp, E *lds) {
-    diag_close<E, B>(P, mp, P, mp, nullptr, 0, lds);
+__device__ __attribute__((noinline)) void closure_reg(E *P_, int32_t mp) {
+    FW_GLOBAL E *P = gmem(P_);
+    diag_close<E, B>(P, mp, P, mp, nullptr, 0, reinterpret_cast<E *>(batch_smem));
 }
 
 template <typename E>
-__device__ void closure_dispatch(E *P, int32_t mp, int32_t variant, uint32_t *smem) {
-    E *lds = reinterpret_cast<E *>(smem);
+__device__ void closure_dispatch(E *P, int32_t mp, int32_t variant) {
     if (variant == SCHULZE_BATCH_CLOSURE_REGISTERS) {
         switch (mp) {
-            case 32: closure_reg<E, 32>(P, mp, lds); break;
-            case 64: closure_reg<E, 64>(P, mp, lds); break;
-            case 96: closure_reg<E, 96>(P, mp, lds); break;
-            case 128: closure_reg<E, 128>(P, mp, lds); break;
+            case 32: closure_reg<E, 32>(P, mp); break;
+            case 64: closure_reg<E, 64>(P, mp); break;
+            case 96: closure_reg<E, 96>(P, mp); break;
+            case 128: closure_reg<E, 128>(P, mp); break;
             default:
                 if constexpr (sizeof(E) == 2) {
                     switch (mp) {
-                        case 160: closure_reg<E, 160>(P, mp, lds); break;
-                        case 192: closure_reg<E, 192>(P, mp, lds); break;
+                        case 160: closure_reg<E, 160>(P, mp); break;
+                        case 192: closure_reg<E, 192>(P, mp); break;
                         default: break;
                     }
                 }
                 break;
         }
     } else if (variant == SCHULZE_BATCH_CLOSURE_TILED32) {
-        if constexpr (sizeof(E) == 2) closure_tiled<E, 32>(P, mp, lds);
+        if constexpr (sizeof(E) == 2) closure_tiled<E, 32>(P, mp);
     } else if (variant == SCHULZE_BATCH_CLOSURE_TILED64) {
-        closure_tiled<E, 64>(P, mp, lds);
+        closure_tiled<E, 64>(P, mp);
     } else {
-        if constexpr (sizeof(E) == 2) closure_tiled<E, 128>(P, mp, lds);
+        if constexpr (sizeof(E) == 2) closure_tiled<E, 128>(P, mp);
     }
 }
 
@@ -513,8 +570,14 @@ template <typename E>
 __device__ void finish_t(const BatchArgs &a, const BElec &el, int32_t e, uint32_t *smem) {
     const int tid = threadIdx.x;
     const int32_t m = el.m, mp = el.mp;
-    E *P = reinterpret_cast<E *>(a.scratch + (int64_t)blockIdx.x * a.scratch_bytes);
-    int32_t *D = a.d + el.mat_off;
+    const int32_t mode = a.mode;
+    FW_GLOBAL uint8_t *is_winner = gmem(a.is_winner);
+    FW_GLOBAL int32_t *beaten_by = a.beaten_by ? gmem(a.beaten_by) : nullptr;
+    FW_GLOBAL int32_t *order = a.order ? gmem(a.order) : nullptr;
+    FW_GLOBAL int32_t *p_out = a.p ? gmem(a.p) : nullptr;
+    E *Pv = reinterpret_cast<E *>(a.scratch + (int64_t)blockIdx.x * a.scratch_bytes);
+    FW_GLOBAL E *P = gmem(Pv);
+    FW_GLOBAL int32_t *D = gmem(a.d + el.mat_off);
     if ((el.flags & EF_ZERO_D) && !a.closure_only) {  // no voters: d = 0
         for (int64_t i = tid; i < (int64_t)m * m; i += BT) D[i] = 0;
         __syncthreads();
@@ -542,7 +605,7 @@ __device__ void finish_t(const BatchArgs &a, const BElec &el, int32_t e, uint32_
                 if (i >= mp || j >= mp) continue;
                 const int32_t x = ta[r * 65 + c], y = tb[c * 65 + r];  // d[i][j], d[j][i]
                 int32_t w = 0;
-                if (i != j && i < m && j < m && x > y) w = a.mode == SCHULZE_MARGIN ? x - y : x;
+                if (i != j && i < m && j < m && x > y) w = mode == SCHULZE_MARGIN ? x - y : x;
                 if constexpr (sizeof(E) == 2) {
                     if ((uint32_t)w > 65535u) {  // counts above the bound the plan assumed
                         too_big = true;
@@ -556,7 +619,7 @@ __device__ void finish_t(const BatchArgs &a, const BElec &el, int32_t e, uint32_
     if (too_big) set_device_error(a.err, SCHULZE_ERANGE);
     __syncthreads();
 
-    closure_dispatch<E>(P, mp, el.variant, smem);
+    closure_dispatch<E>(Pv, mp, el.variant);
     __syncthreads();
 
     // beaten_by[x] = #{y : P[y][x] > P[x][y]}
@@ -589,44 +652,45 @@ __device__ void finish_t(const BatchArgs &a, const BElec &el, int32_t e, uint32_
         const int32_t bx = bb[x];
         const bool win = bx == 0;
         wins += win ? 1 : 0;
-        a.is_winner[el.vec_off + x] = win ? 1 : 0;
-        if (a.beaten_by) a.beaten_by[el.vec_off + x] = bx;
-        if (a.order) {
+        is_winner[el.vec_off + x] = win ? 1 : 0;
+        if (beaten_by) beaten_by[el.vec_off + x] = bx;
+        if (order) {
             int32_t rank = 0;
             for (int32_t y = 0; y < m; ++y) {
                 const int32_t by = bb[y];
                 rank += (by < bx || (by == bx && y < x)) ? 1 : 0;
             }
-            a.order[el.vec_off + rank] = x;
+            order[el.vec_off + rank] = x;
         }
     }
     if (wins) atomicAdd(&sh_wins, wins);
-    if (a.p) {
-        int32_t *Pout = a.p + el.mat_off;
+    if (p_out) {
+        FW_GLOBAL int32_t *Pout = p_out + el.mat_off;
         for (int32_t x = 0; x < m; ++x)
             for (int32_t y = tid; y < m; y += BT)
                 Pout[(int64_t)x * m + y] = x == y ? 0 : (int32_t)P[(int64_t)x * mp + y];
     }
     __syncthreads();
-    if (tid == 0 && a.n_winners) a.n_winners[e] = sh_wins;
+    if (tid == 0 && a.n_winners) gmem(a.n_winners)[e] = sh_wins;
     __syncthreads();
 }
 
-__device__ void finish(const BatchArgs &a, const BElec &el, int32_t e, uint32_t *smem) {
+__device__ __attribute__((noinline)) void finish(const BatchArgs &a, const BElec &el_in, int32_t e) {
+    const BElec el = el_in;  // local copy (see scan_item)
     if (el.flags & EF_VAL16)
-        finish_t<uint16_t>(a, el, e, smem);
+        finish_t<uint16_t>(a, el, e, batch_smem);
     else
-        finish_t<int32_t>(a, el, e, smem);
+        finish_t<int32_t>(a, el, e, batch_smem);
 }
 
 __global__ __launch_bounds__(BT, 2) void k_batch(BatchArgs a) {
-    extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
     __shared__ int32_t sh_item;
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) {
-            int32_t t = atomicAdd(&a.ctr[0], 1);
-            if (__hip_atomic_load(&a.ctr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) t = a.n_items;
+            FW_GLOBAL int32_t *ctr = gmem(a.ctr);
+            int32_t t = __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (__hip_atomic_load(ctr + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) t = a.n_items;
             sh_item = t;
         }
         __syncthreads();
@@ -635,14 +699,18 @@ __global__ __launch_bounds__(BT, 2) void k_batch(BatchArgs a) {
         const BItem it = a.items[t];
         const BElec el = a.elec[it.e];
         if (it.kind == IT_SCAN) {
-            scan_item(a, el, it.a, it.b, smem);
+            if (a.dtype32)
+                scan_item<int32_t>(a, el, it.a, it.b);
+            else
+                scan_item<uint16_t>(a, el, it.a, it.b);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __syncthreads();
-            if (threadIdx.x == 0) atomicAdd(&a.ctr[2 + it.e], 1);
+            if (threadIdx.x == 0)
+                __hip_atomic_fetch_add(gmem(a.ctr) + 2 + it.e, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else if (it.kind == IT_COUNT) {
-            count_item(a, el, it.e, it.a, it.b, smem);
+            count_item(a, el, it.e, it.a, it.b);
         } else {
-            finish(a, el, it.e, smem);
+            finish(a, el, it.e);
         }
     }
 }
@@ -727,15 +795,8 @@ int32_t padded_size(int variant, int32_t m) {
 }
 
 int batch_grid(schulze_ctx *ctx, int32_t *grid) {
-    static bool attr_set = false;
-    if (!attr_set) {
-        if (hipFuncSetAttribute((const void *)k_batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)SMEM_BYTES) !=
-            hipSuccess)
-            return SCHULZE_EDEVICE;
-        attr_set = true;
-    }
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, BT, SMEM_BYTES) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, BT, 0) != hipSuccess || per_cu < 1)
         return SCHULZE_EDEVICE;
     *grid = per_cu * ctx->num_cus;
     return SCHULZE_OK;
@@ -814,7 +875,7 @@ int build_plan(schulze_ctx *ctx, const schulze_election *desc, int32_t E, int ba
         const int32_t nq = el.pitch / 4;
         const int32_t groups = (int32_t)ceil_div(nq, 64);
         el.ng = groups <= 1 ? 1 : (groups <= 2 ? 2 : 4);
-        el.vc = 64 / el.ng;
+        el.vc = 4 * MAX_PF / el.ng;
         el.range_pairs = max_range;
         const int64_t ranges = pairs > 0 ? ceil_div(pairs, max_range) : 0;
         el.flags = (square ? EF_SQUARE : 0) | (ranges > 1 ? EF_MULTI : 0) | (val16 ? EF_VAL16 : 0) |
@@ -836,19 +897,26 @@ int build_plan(schulze_ctx *ctx, const schulze_election *desc, int32_t E, int ba
     std::vector<int32_t> order(E);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cost[x] > cost[y]; });
+    int rc = batch_grid(ctx, &pl->grid);
     std::vector<BItem> full, fin;
-    if (!closure_only) {
-        for (int32_t e : order) {
+    if (!closure_only && rc == SCHULZE_OK) {
+        // Scans (memory-bound) run ahead of the counts (VALU-bound) by `ahead`
+        // elections, so that the two overlap; every scan of an election still
+        // precedes its counts in the queue.
+        auto push_scans = [&](int32_t e) {
             const BElec &el = pl->elec[e];
             const int64_t pairs = (el.n + 1) / 2;
             for (int64_t q = 0; q < pairs; q += el.scan_pairs)
                 full.push_back(BItem{IT_SCAN, e, (int32_t)q, (int32_t)std::min<int64_t>(el.scan_pairs, pairs - q)});
-        }
-        for (int32_t e : order) {
-            const BElec &el = pl->elec[e];
-            if (el.n_count == 0) continue;
+        };
+        int32_t ahead = 0;
+        for (int64_t items = 0; ahead < E && items < 2 * (int64_t)pl->grid; ++ahead) items += pl->elec[order[ahead]].n_count;
+        for (int32_t i = 0; i < ahead; ++i) push_scans(order[i]);
+        for (int32_t i = 0; i < E; ++i) {
+            const int32_t e = order[i];
             for (int32_t r = 0; r < ranges_of[e]; ++r)
                 for (int32_t u = 0; u < runs_of[e]; ++u) full.push_back(BItem{IT_COUNT, e, u, r});
+            if (i + ahead < E) push_scans(order[i + ahead]);
         }
         for (int32_t e : order)
             if (pl->elec[e].n_count == 0) full.push_back(BItem{IT_FINISH, e, 0, 0});
@@ -857,7 +925,6 @@ int build_plan(schulze_ctx *ctx, const schulze_election *desc, int32_t E, int ba
     pl->n_full = (int32_t)full.size();
     pl->n_closure = (int32_t)fin.size();
 
-    int rc = batch_grid(ctx, &pl->grid);
     if (rc == SCHULZE_OK) rc = upload(&pl->elec_dev, pl->elec);
     if (rc == SCHULZE_OK) rc = upload(&pl->items_full, full);
     if (rc == SCHULZE_OK) rc = upload(&pl->items_closure, fin);
@@ -884,7 +951,7 @@ int enqueue(schulze_batch *pl, hipStream_t s, const BatchArgs &args) {
     int rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(pl->ctr), (size_t)(2 + 2 * (int64_t)pl->E), 0u);
     if (rc != SCHULZE_OK) return rc;
     if (args.n_items == 0) return SCHULZE_OK;
-    SCHULZE_LAUNCH(ctx, K_BATCH, s, k_batch<<<dim3((unsigned)pl->grid), dim3(BT), SMEM_BYTES, s>>>(args));
+    SCHULZE_LAUNCH(ctx, K_BATCH, s, k_batch<<<dim3((unsigned)pl->grid), dim3(BT), 0, s>>>(args));
     return SCHULZE_OK;
 }
 

@@ -10,6 +10,21 @@ namespace fw {
 
 typedef __attribute__((ext_vector_type(2))) unsigned short us2;
 
+// Tile operands in device memory may be plain pointers or pointers qualified
+// with the global address space (then every access is a global_* instruction
+// rather than a flat one).  retype<U>(p) reinterprets p as a pointer to U in
+// the same address space.
+#define FW_GLOBAL __attribute__((address_space(1)))
+typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));  // 16 bytes, not a class type
+template <typename U, typename T>
+__device__ __forceinline__ U *retype(T *p) {
+    return reinterpret_cast<U *>(p);
+}
+template <typename U, typename T>
+__device__ __forceinline__ FW_GLOBAL U *retype(FW_GLOBAL T *p) {
+    return (FW_GLOBAL U *)p;
+}
+
 template <typename E>
 struct Lane;
 template <>
@@ -50,36 +65,36 @@ struct Acc {
     typename Lane<E>::W c[Cfg<E, B>::TM][Cfg<E, B>::WN];
 };
 
-template <typename E>
-__device__ inline void copy_block(E *__restrict__ dst, int dst_pitch, const E *__restrict__ src, int64_t src_pitch,
-                                  int rows, int cols) {
+template <typename E, typename SrcP>
+__device__ inline void copy_block(E *__restrict__ dst, int dst_pitch, SrcP src, int64_t src_pitch, int rows,
+                                  int cols) {
     // cols * sizeof(E) is a multiple of 16; rows of src and dst are 16-byte aligned
     const int vpr = cols * (int)sizeof(E) / 16;
     for (int v = threadIdx.x; v < rows * vpr; v += 256) {
         const int rr = v / vpr, cv = v % vpr;
-        const uint4 x = *reinterpret_cast<const uint4 *>(src + rr * src_pitch + cv * (16 / sizeof(E)));
-        *reinterpret_cast<uint4 *>(dst + rr * dst_pitch + cv * (16 / sizeof(E))) = x;
+        const v4u32 x = *retype<const v4u32>(src + rr * src_pitch + cv * (16 / sizeof(E)));
+        *reinterpret_cast<v4u32 *>(dst + rr * dst_pitch + cv * (16 / sizeof(E))) = x;
     }
 }
 
-template <typename E, int B>
-__device__ inline void acc_load(Acc<E, B> &a, const E *__restrict__ src, int64_t ld) {
+template <typename E, int B, typename SrcP>
+__device__ inline void acc_load(Acc<E, B> &a, SrcP src, int64_t ld) {
     using C = Cfg<E, B>;
     using W = typename Lane<E>::W;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     for (int ii = 0; ii < C::TM; ++ii) {
-        const W *row = reinterpret_cast<const W *>(src + (int64_t)(ty * C::TM + ii) * ld + tx * C::TN);
+        const auto row = retype<const W>(src + (int64_t)(ty * C::TM + ii) * ld + tx * C::TN);
         for (int jj = 0; jj < C::WN; ++jj) a.c[ii][jj] = row[jj];
     }
 }
 
-template <typename E, int B>
-__device__ inline void acc_store(const Acc<E, B> &a, E *__restrict__ dst, int64_t ld) {
+template <typename E, int B, typename DstP>
+__device__ inline void acc_store(const Acc<E, B> &a, DstP dst, int64_t ld) {
     using C = Cfg<E, B>;
     using W = typename Lane<E>::W;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     for (int ii = 0; ii < C::TM; ++ii) {
-        W *row = reinterpret_cast<W *>(dst + (int64_t)(ty * C::TM + ii) * ld + tx * C::TN);
+        const auto row = retype<W>(dst + (int64_t)(ty * C::TM + ii) * ld + tx * C::TN);
         for (int jj = 0; jj < C::WN; ++jj) row[jj] = a.c[ii][jj];
     }
 }
@@ -87,9 +102,8 @@ __device__ inline void acc_store(const Acc<E, B> &a, E *__restrict__ dst, int64_
 // a = max(a, A (x) Bm) with A, Bm B x B tiles in global memory (row pitches
 // lda, ldb).  lds holds Cfg::LDS_ELEMS elements.  Starts and ends with a
 // barrier, so A or Bm may be the tile that the caller overwrites afterwards.
-template <typename E, int B>
-__device__ inline void acc_product(Acc<E, B> &a, const E *__restrict__ A, int64_t lda, const E *__restrict__ Bm,
-                                   int64_t ldb, E *lds) {
+template <typename E, int B, typename PA, typename PB>
+__device__ inline void acc_product(Acc<E, B> &a, PA A, int64_t lda, PB Bm, int64_t ldb, E *lds) {
     using C = Cfg<E, B>;
     using L = Lane<E>;
     using W = typename L::W;
@@ -212,9 +226,9 @@ struct Diag {
     }
 };
 
-template <typename E, int B>
-__device__ inline void diag_close(const E *__restrict__ src, int64_t lds_, E *__restrict__ dst, int64_t ldd_,
-                                  E *__restrict__ dst2, int64_t ldd2, E *buf) {
+template <typename E, int B, typename SrcP, typename DstP>
+__device__ inline void diag_close(SrcP src, int64_t lds_, DstP dst, int64_t ldd_, E *__restrict__ dst2, int64_t ldd2,
+                                  E *buf) {
     using D = Diag<E, B>;
     using W = typename D::W;
     E *rowbuf = buf;          // [2][B]: thread tx's columns at tx*CW ..
@@ -222,7 +236,7 @@ __device__ inline void diag_close(const E *__restrict__ src, int64_t lds_, E *__
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     W v[D::RA][D::WC];
     for (int a = 0; a < D::RA; ++a) {
-        const E *row = src + (int64_t)(ty + 16 * a) * lds_ + tx;
+        const auto row = src + (int64_t)(ty + 16 * a) * lds_ + tx;
         for (int c = 0; c < D::WC; ++c) {
             if constexpr (sizeof(E) == 4) {
                 v[a][c] = row[16 * c];
@@ -234,7 +248,7 @@ __device__ inline void diag_close(const E *__restrict__ src, int64_t lds_, E *__
     D::template publish<0>(v, 0, 0, tx, ty, rowbuf, colbuf);
     D::template steps<0>(v, tx, ty, rowbuf, colbuf);
     for (int a = 0; a < D::RA; ++a) {
-        E *row = dst + (int64_t)(ty + 16 * a) * ldd_ + tx;
+        const auto row = dst + (int64_t)(ty + 16 * a) * ldd_ + tx;
         E *row2 = dst2 ? dst2 + (int64_t)(ty + 16 * a) * ldd2 + tx : nullptr;
         for (int b = 0; b < D::CW; ++b) {
             const E x = lane_get<E>(v[a], b);

@@ -79,16 +79,22 @@ int gen_permutation(uint64_t seed, uint64_t stream, int32_t m, int32_t *perm) {
     return GEN_OK;
 }
 
-/* Draw k in {0..i-1} with P(k) proportional to phi^k (truncated geometric). */
-static inline int32_t trunc_geom(uint64_t *s, double phi, int32_t i) {
+/* Draw k in {0..i-1} with P(k) proportional to phi^k (truncated geometric),
+ * by inverting its distribution function.  tail = phi^i and log_phi =
+ * log(phi) are passed in so that callers can compute them once. */
+static inline int32_t trunc_geom_t(uint64_t *s, double phi, int32_t i, double tail, double log_phi) {
     double u = u01(s);
     if (phi >= 1.0) return (int32_t)(u * (double)i);
     if (phi <= 0.0) return 0;
-    double tail = pow(phi, (double)i);
-    double k = floor(log1p(-u * (1.0 - tail)) / log(phi));
+    double k = floor(log1p(-u * (1.0 - tail)) / log_phi);
     if (k < 0) k = 0;
     if (k > (double)(i - 1)) k = (double)(i - 1);
     return (int32_t)k;
+}
+
+static inline int32_t trunc_geom(uint64_t *s, double phi, int32_t i) {
+    if (phi >= 1.0 || phi <= 0.0) return trunc_geom_t(s, phi, i, 0.0, 0.0);
+    return trunc_geom_t(s, phi, i, pow(phi, (double)i), log(phi));
 }
 
 static void store_id(void *out, int dtype32, int64_t idx, int32_t id) {
@@ -103,10 +109,10 @@ static void store_pad(void *out, int dtype32, int64_t idx) {
 
 /* One Mallows ranking of m items around ref_order, written as ids best first.
  * scratch: m int32 (Fenwick tree) + m int32 (insertion offsets). */
-static void mallows_one(uint64_t *s, int32_t m, double phi, const int32_t *ref_order,
-                        int32_t *fen, int32_t *jpos, int32_t *out_ids) {
+static void mallows_one(uint64_t *s, int32_t m, double phi, const int32_t *ref_order, const double *tails,
+                        double log_phi, int32_t *fen, int32_t *jpos, int32_t *out_ids) {
     /* insertion positions, 1-based: item i goes to slot j_i = i - k_i */
-    for (int32_t i = 1; i <= m; ++i) jpos[i - 1] = i - trunc_geom(s, phi, i);
+    for (int32_t i = 1; i <= m; ++i) jpos[i - 1] = i - trunc_geom_t(s, phi, i, tails[i - 1], log_phi);
     /* Fenwick tree over m free slots (all ones) */
     for (int32_t i = 1; i <= m; ++i) fen[i - 1] = 0;
     for (int32_t i = 1; i <= m; ++i) {
@@ -143,6 +149,11 @@ int gen_mallows(uint64_t seed, uint64_t election, int64_t n, int32_t m, double p
     if (any_full && L < m) return GEN_EINVAL;
     if (trunc_mod > 0 && trunc_lt > 0 && (trunc_k < 0 || trunc_k > L)) return GEN_EINVAL;
     int err = GEN_OK;
+    /* phi^i for i = 1..m and log(phi), shared by every voter */
+    double *tails = (double *)malloc(sizeof(double) * (size_t)m);
+    if (!tails) return GEN_ENOMEM;
+    const double log_phi = (phi > 0.0 && phi < 1.0) ? log(phi) : 0.0;
+    for (int32_t i = 1; i <= m; ++i) tails[i - 1] = (phi > 0.0 && phi < 1.0) ? pow(phi, (double)i) : 0.0;
 #pragma omp parallel
     {
         int32_t *scr = (int32_t *)malloc(sizeof(int32_t) * (size_t)m * 3);
@@ -154,7 +165,7 @@ int gen_mallows(uint64_t seed, uint64_t election, int64_t n, int32_t m, double p
         for (int64_t v = 0; v < n; ++v) {
             if (!scr) continue;
             uint64_t s = stream_key(seed, election, (uint64_t)v);
-            mallows_one(&s, m, phi, ref_order, scr, scr + m, scr + 2 * (size_t)m);
+            mallows_one(&s, m, phi, ref_order, tails, log_phi, scr, scr + m, scr + 2 * (size_t)m);
             int32_t keep = m;
             if (trunc_mod > 0 && (v % trunc_mod) < trunc_lt) keep = trunc_k;
             int64_t base = v * (int64_t)L;
@@ -165,6 +176,7 @@ int gen_mallows(uint64_t seed, uint64_t election, int64_t n, int32_t m, double p
         }
         free(scr);
     }
+    free(tails);
     return err;
 }
 
