@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-voters", type=int, default=3000)
     ap.add_argument("--batch-elections", type=int, default=4096)
+    ap.add_argument("--no-per-election", action="store_true",
+                    help="batch workload: skip the pass of per-election calls (profiling runs)")
     ap.add_argument("--closure-schedule", choices=("auto", "phased"), default="auto")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, copy a 1 GiB buffer once (a known-size reference "
@@ -218,17 +220,19 @@ def bench_batch(args):
             o_ref[vo:vo + m].copy_(order)
             bb_ref[vo:vo + m].copy_(beaten)
 
-    per_election()  # warm-up (workspace growth)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    per_election()
-    torch.cuda.synchronize()
-    t_per = time.perf_counter() - t0
-    exact = bool(torch.equal(d_ref, outs["d"]) and torch.equal(p_ref, outs["p"]) and
-                 torch.equal(w_ref, outs["is_winner"]) and torch.equal(o_ref, outs["order"]) and
-                 torch.equal(bb_ref, outs["beaten_by"]))
-    print(f"[bench] per-election calls: {t_per * 1e3:.1f} ms, identical outputs: {exact}", file=sys.stderr,
-          flush=True)
+    t_per, exact = None, None
+    if not args.no_per_election:
+        per_election()  # warm-up (workspace growth)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        per_election()
+        torch.cuda.synchronize()
+        t_per = time.perf_counter() - t0
+        exact = bool(torch.equal(d_ref, outs["d"]) and torch.equal(p_ref, outs["p"]) and
+                     torch.equal(w_ref, outs["is_winner"]) and torch.equal(o_ref, outs["order"]) and
+                     torch.equal(bb_ref, outs["beaten_by"]))
+        print(f"[bench] per-election calls: {t_per * 1e3:.1f} ms, identical outputs: {exact}", file=sys.stderr,
+              flush=True)
     if ctx.device_error() != 0:
         raise RuntimeError("device error")
 
@@ -257,9 +261,9 @@ def bench_batch(args):
         "config": {"workload": "batch_mallows_E%d" % E, "elections": E, "m": "U{8..512}", "n": "U{50..20000}",
                    "phi": "U[0.5,1.0]", "seed": 1004, "weight_mode": "winning_votes", "parallelism": "single GPU",
                    "launch": "one persistent kernel per step, replayed from a captured HIP graph"},
-        "elections_per_s_per_election_calls": E / t_per,
-        "speedup_vs_per_election_calls": t_per / (ms_per_step / 1e3),
-        "ms_per_election_calls_pass": t_per * 1e3,
+        "elections_per_s_per_election_calls": E / t_per if t_per else None,
+        "speedup_vs_per_election_calls": t_per / (ms_per_step / 1e3) if t_per else None,
+        "ms_per_election_calls_pass": t_per * 1e3 if t_per else None,
         "identical_to_per_election_calls": exact,
         "graph_ms": kernel_ms,
         "count_comparisons": count_ops,

@@ -269,6 +269,34 @@ int schulze_winners_learned(schulze_ctx *ctx, void *stream, const void *d, int64
                             int32_t max_climb, int32_t max_tied, uint8_t *is_winner,
                             int32_t *n_winners, schulze_learned_stats *stats);
 
+/* Statistics of one schulze_winners_propagate call. */
+typedef struct {
+    int32_t rounds;     /* rounds of preprocessing, propagation and postprocessing */
+    int32_t sweeps;     /* propagation sweeps over all rounds, both directions */
+    int32_t n_winners;
+} schulze_propagate_stats;
+
+/*
+ * Schulze winners by the paper's own winners-only algorithm (Section 4):
+ * the initialisation filter, then rounds of forward/backward propagation of
+ * the smallest label reaching (reached by) each vertex together with the
+ * widest-path width from (to) that label's candidate, and postprocessing of
+ * the labels, until no candidate is undecided.  Labels follow Borda scores
+ * descending (ties by id) when borda_order != 0, else candidate ids.  Each
+ * propagation runs to its fixpoint in one cooperative launch of dense
+ * (max, min) sweeps over the weight matrix.  The result equals
+ * schulze_winners on the closure.  Synchronises the stream (the rounds are
+ * driven from the host).
+ *
+ * d, ldd, m, dtype, mode  as for schulze_closure (m <= 65534).
+ * is_winner  m device bytes.   n_winners: NULL or one device int32.
+ * stats      NULL or host struct.
+ * Workspace: 2 m^2 elements of dtype plus O(m).
+ */
+int schulze_winners_propagate(schulze_ctx *ctx, void *stream, const void *d, int64_t ldd, int32_t m,
+                              int dtype, int mode, int borda_order, uint8_t *is_winner,
+                              int32_t *n_winners, schulze_propagate_stats *stats);
+
 /*
  * Closure schedule.  AUTO (default): one persistent cooperative launch whose
  * workgroups exchange the diagonal and panel tiles of each round through
@@ -400,7 +428,9 @@ int schulze_batch_autotune(schulze_ctx *ctx, void *stream, int32_t value_bits, i
  * "fw_rest", "fw_persist", "fw_store", "beaten_by", "rank_sort",
  * "winners", "fill", "widest", "verdict", "features", "mlp_prepare",
  * "mlp_forward", "mlp_backward", "mlp_loss", "mlp_adam", "propose", "batch"
- * (a batch run: the persistent launch, or the whole graph when captured).
+ * (a batch run: the persistent launch, or the whole graph when captured),
+ * "label_post" (schulze_winners_propagate's filter, order and
+ * postprocessing kernels), "label_sweep" (its propagation launches).
  */
 int schulze_set_timing(schulze_ctx *ctx, int enable);
 int schulze_kernel_time(schulze_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms);

@@ -32,8 +32,15 @@ EXPORTS = (
     "schulze_mlp_param_count", "schulze_mlp_forward", "schulze_mlp_loss", "schulze_mlp_backward", "schulze_mlp_adam",
     "schulze_winners_learned",
     "schulze_batch_plan", "schulze_batch_destroy", "schulze_batch_run", "schulze_batch_set_closure",
-    "schulze_batch_get_closure", "schulze_batch_autotune",
+    "schulze_batch_get_closure", "schulze_batch_autotune", "schulze_winners_propagate",
 )
+
+
+class PropagateStats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("sweeps", ctypes.c_int32), ("n_winners", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 class LearnedStats(ctypes.Structure):
@@ -111,6 +118,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                      ctypes.c_float, c_i32]
     lib.schulze_batch_plan.argtypes = [vp, ctypes.POINTER(Election), c_i32, c_int, c_int,
                                        ctypes.POINTER(BatchOptions), ctypes.POINTER(vp)]
+    lib.schulze_winners_propagate.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_int, c_int, vp, vp,
+                                              ctypes.POINTER(PropagateStats)]
     lib.schulze_batch_destroy.argtypes = [vp]
     lib.schulze_batch_destroy.restype = None
     lib.schulze_batch_run.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, c_int]
@@ -368,6 +377,21 @@ class Context:
                                                self._dev(w, "is_winner"), self._dev(nw, "n_winners"),
                                                ctypes.byref(st))
         _check(rc, "schulze_winners_learned")
+        return w, nw, st.as_dict()
+
+    def winners_propagate(self, d, mode="winning_votes", borda_order=True):
+        """(is_winner uint8[m], n_winners int32[1], stats dict): winners by
+        the paper's label-propagation algorithm (synchronises)."""
+        import torch
+        m = d.shape[0]
+        w = torch.empty(m, dtype=torch.uint8, device=self._torch_device)
+        nw = torch.empty(1, dtype=torch.int32, device=self._torch_device)
+        st = PropagateStats()
+        rc = self._lib.schulze_winners_propagate(self._h, self._stream(), self._dev(d, "d"), d.stride(0), m,
+                                                 _dtype_code(d.dtype), _mode_code(mode), int(bool(borda_order)),
+                                                 self._dev(w, "is_winner"), self._dev(nw, "n_winners"),
+                                                 ctypes.byref(st))
+        _check(rc, "schulze_winners_propagate")
         return w, nw, st.as_dict()
 
     # -------------------------------------------------------------- batches

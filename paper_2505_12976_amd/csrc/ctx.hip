@@ -10,7 +10,8 @@ const char *const kKernelNames[K_NUM_KERNELS] = {
     "fw_diag",     "fw_panel",       "fw_rest",     "fw_store",     "beaten_by",    "rank_sort",
     "winners",     "fill",           "fw_persist",  "route",        "count_trunc",
     "widest",      "verdict",        "features",    "mlp_prepare",  "mlp_forward",
-    "mlp_backward", "mlp_loss",      "mlp_adam",    "propose",     "batch"};
+    "mlp_backward", "mlp_loss",      "mlp_adam",    "propose",     "batch",
+    "label_post",   "label_sweep"};
 
 extern "C" const char *schulze_strerror(int code) {
     switch (code) {

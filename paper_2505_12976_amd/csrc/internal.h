@@ -28,6 +28,7 @@ enum WsSlot {
     WS_MLP_PARTIAL,      // per-workgroup gradient partials
     WS_LEARNED,          // learned path: weights, transposed weights, features, scores
     WS_LEARNED_P,        // learned path: closure for the fallback
+    WS_PROPAGATE,        // label propagation: weights, keys, frontiers, statuses
     WS_NUM_SLOTS
 };
 
@@ -87,6 +88,8 @@ enum KernelId {
     K_MLP_ADAM,
     K_PROPOSE,
     K_BATCH,
+    K_PROP,
+    K_PROP_SWEEP,
     K_NUM_KERNELS
 };
 extern const char *const kKernelNames[K_NUM_KERNELS];

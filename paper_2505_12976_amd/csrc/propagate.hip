@@ -1,0 +1,458 @@
+// Schulze winners by forward/backward propagation of minimum labels with
+// path widths: the paper's own winners-only algorithm (Section 4: the
+// initialisation filter, then rounds of preprocessing, forward-backward
+// propagation and postprocessing until no candidate is undecided), run as
+// dense data-parallel sweeps over the weight matrix instead of Pregel
+// messages.
+//
+// Labels.  Every undecided candidate carries a label, its position in the
+// chosen vertex order (Borda scores descending, ties by id, as Section 4
+// suggests; or plain ids).  Forward, each vertex keeps the smallest label
+// that reaches it with the width of the widest path from that candidate;
+// backward, the smallest label it reaches with the widest path width to it.
+// Decided candidates carry no label but pass labels on.  A label and a width
+// are packed into one key -- (LABEL_MAX - label) in the high half, the width
+// in the low half -- so "smaller label, then wider path" is a plain max of
+// keys, and along an edge of weight w > 0 a key k becomes
+// (k & HIGH) | min(k & LOW, w).  Sweeps run to the fixpoint; only vertices
+// whose key grew in a sweep send in the next one.  At the fixpoint, for a
+// vertex with label s, every vertex on a path from s has label s as well, so
+// its width is the widest-path width p(s, c).
+//
+// Postprocessing of a vertex c with forward (s, ws) and backward (t, wt):
+//   s < t   c is reached from s but does not reach it: s beats c;
+//   s > t   c reaches t and t does not reach c: c beats t;
+//   s = t   c and s share a strongly connected component (the vertices with
+//           (s, t) = (x, x) are exactly x's component); ws > wt: s beats c,
+//           ws < wt: c beats s;
+//   an edge v -> c whose (s, t) differ from c's crosses components (vertices
+//   of one component share (s, t)), so c does not reach v and v beats c,
+//   and every vertex of c's component when s = t.
+// After all marks of a round, an undecided c whose own label is s = t (the
+// smallest undecided vertex of its component) and that is still undecided
+// has no beater: nobody outside its component reaches it and nobody inside
+// beats it.  It wins.  Every round decides at least the smallest undecided
+// label, so there are at most m rounds.
+#include "grid.h"
+
+namespace {
+
+using grid::GridBar;
+using grid::grid_sync;
+
+enum : uint8_t { ST_UNKNOWN = 0, ST_LOSER = 1, ST_WINNER = 2 };
+
+template <typename E>
+struct Key;
+template <>
+struct Key<uint16_t> {
+    using K = uint32_t;
+    static constexpr int SH = 16;
+    static constexpr uint32_t WMAX = 0xFFFFu;    // width of the empty path
+    static constexpr uint32_t LMAX = 0xFFFFu;    // labels are < LMAX
+    static constexpr K LOW = 0xFFFFu;
+};
+template <>
+struct Key<int32_t> {
+    using K = unsigned long long;
+    static constexpr int SH = 32;
+    static constexpr uint32_t WMAX = 0x7FFFFFFFu;
+    static constexpr uint32_t LMAX = 0xFFFFFFFFu;
+    static constexpr K LOW = 0xFFFFFFFFull;
+};
+
+template <typename E>
+__device__ inline typename Key<E>::K make_key(uint32_t label) {
+    using KT = Key<E>;
+    return ((typename KT::K)(KT::LMAX - label) << KT::SH) | (typename KT::K)KT::WMAX;
+}
+
+// label of a key, or 0xFFFFFFFF for none
+template <typename E>
+__device__ inline uint32_t key_label(typename Key<E>::K k) {
+    using KT = Key<E>;
+    const uint32_t code = (uint32_t)(k >> KT::SH);
+    return code == 0 ? 0xFFFFFFFFu : KT::LMAX - code;
+}
+
+template <typename E>
+__device__ inline uint32_t key_width(typename Key<E>::K k) {
+    return (uint32_t)(k & Key<E>::LOW);
+}
+
+// ------------------------------------------------------------------ per-vertex statistics
+// Row x of w and of wt: largest outgoing and incoming edge weight (the
+// initialisation filter), and the Borda score sum_y d[x][y].
+template <typename E>
+__global__ __launch_bounds__(256) void k_prop_rows(const E *__restrict__ d, int64_t ldd, const E *__restrict__ w,
+                                                   const E *__restrict__ wt, int64_t ld, int32_t m,
+                                                   uint8_t *__restrict__ status, unsigned long long *__restrict__ borda) {
+    __shared__ uint32_t smax_out[256], smax_in[256];
+    __shared__ unsigned long long sb[256];
+    const int32_t x = blockIdx.x;
+    uint32_t mo = 0, mi = 0;
+    unsigned long long b = 0;
+    for (int32_t y = threadIdx.x; y < m; y += 256) {
+        mo = max(mo, (uint32_t)w[(int64_t)x * ld + y]);
+        mi = max(mi, (uint32_t)wt[(int64_t)x * ld + y]);
+        if (y != x) b += (unsigned long long)(uint32_t)d[(int64_t)x * ldd + y];
+    }
+    smax_out[threadIdx.x] = mo;
+    smax_in[threadIdx.x] = mi;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            smax_out[threadIdx.x] = max(smax_out[threadIdx.x], smax_out[threadIdx.x + off]);
+            smax_in[threadIdx.x] = max(smax_in[threadIdx.x], smax_in[threadIdx.x + off]);
+            sb[threadIdx.x] += sb[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        status[x] = smax_in[0] > smax_out[0] ? ST_LOSER : ST_UNKNOWN;  // initialisation filter
+        borda[x] = sb[0];
+    }
+}
+
+// label[x] = position of x in the order (Borda descending, then id), or x;
+// vertex[label] = x.
+__global__ __launch_bounds__(256) void k_prop_order(const unsigned long long *__restrict__ borda, int32_t m,
+                                                    int use_borda, int32_t *__restrict__ label,
+                                                    int32_t *__restrict__ vertex) {
+    __shared__ int32_t part[256];
+    const int32_t x = blockIdx.x;
+    int32_t r = 0;
+    if (use_borda) {
+        const unsigned long long bx = borda[x];
+        for (int32_t y = threadIdx.x; y < m; y += 256) {
+            const unsigned long long by = borda[y];
+            r += (by > bx || (by == bx && y < x)) ? 1 : 0;
+        }
+    }
+    part[threadIdx.x] = r;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int32_t lx = use_borda ? part[0] : x;
+        label[x] = lx;
+        vertex[lx] = x;
+    }
+}
+
+// ------------------------------------------------------------------ propagation sweeps
+template <typename E>
+struct SweepArgs {
+    using K = typename Key<E>::K;
+    const E *w;  // rows = edge sources: w for forward, wt for backward
+    int64_t ld;
+    int32_t m;
+    const uint8_t *status;
+    const int32_t *label;
+    K *x[2];            // ping-pong keys
+    int32_t *front[2];  // frontier lists
+    int32_t *fcount;    // [0], [1] frontier sizes, [2] sweeps run
+    K *out;
+    GridBar *bar;
+    int32_t *err;
+    int64_t spin_limit;
+};
+
+template <typename E>
+__global__ __launch_bounds__(256) void k_prop_sweep(SweepArgs<E> a) {
+    using K = typename Key<E>::K;
+    __shared__ K part[4][64];
+    const int32_t m = a.m, G = gridDim.x, g = blockIdx.x;
+    const int32_t c0 = (int32_t)((int64_t)m * g / G), c1 = (int32_t)((int64_t)m * (g + 1) / G);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr K HIGH = ~Key<E>::LOW;
+
+    // preprocessing: undecided vertices start with their own label and the
+    // empty path; they form the first frontier
+    for (int32_t j = c0 + threadIdx.x; j < c1; j += 256) {
+        const bool u = a.status[j] == ST_UNKNOWN;
+        a.x[0][j] = u ? make_key<E>((uint32_t)a.label[j]) : (K)0;
+        if (u) a.front[0][atomicAdd(&a.fcount[0], 1)] = j;
+    }
+    if (!grid_sync(a.bar, a.spin_limit)) goto stuck;
+    {
+        int cur = 0;
+        int32_t sweeps = 0;
+        for (;;) {
+            const int32_t nf = __hip_atomic_load(&a.fcount[cur], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (nf == 0) break;
+            if (++sweeps > 2 * m + 2) {  // keys only grow, so this cannot happen
+                if (threadIdx.x == 0) set_device_error(a.err, SCHULZE_EDEVICE);
+                break;
+            }
+            const K *xc = a.x[cur];
+            K *xn = a.x[cur ^ 1];
+            const int32_t *F = a.front[cur];
+            int32_t *Fn = a.front[cur ^ 1];
+            for (int32_t cb = c0; cb < c1; cb += 64) {
+                const int32_t j = cb + lane;
+                K best = 0;
+                if (j < c1) {
+                    for (int32_t q = wave; q < nf; q += 4) {
+                        const int32_t i = F[q];
+                        const uint32_t wij = (uint32_t)a.w[(int64_t)i * a.ld + j];
+                        const K ki = xc[i];
+                        if (wij != 0 && ki != 0) {
+                            const K lo = (K)min((uint32_t)(ki & Key<E>::LOW), wij);
+                            best = max(best, (ki & HIGH) | lo);
+                        }
+                    }
+                }
+                part[wave][lane] = best;
+                __syncthreads();
+                if (wave == 0 && j < c1) {
+                    const K old = xc[j];
+                    const K nv = max(max(old, part[0][lane]), max(part[1][lane], max(part[2][lane], part[3][lane])));
+                    xn[j] = nv;
+                    if (nv > old) Fn[atomicAdd(&a.fcount[cur ^ 1], 1)] = j;
+                }
+                __syncthreads();
+            }
+            if (!grid_sync(a.bar, a.spin_limit)) goto stuck;
+            if (g == 0 && threadIdx.x == 0) a.fcount[cur] = 0;  // the consumed list is the next target
+            cur ^= 1;
+            if (!grid_sync(a.bar, a.spin_limit)) goto stuck;
+        }
+        for (int32_t j = c0 + threadIdx.x; j < c1; j += 256) a.out[j] = a.x[cur][j];
+        if (g == 0 && threadIdx.x == 0) a.fcount[2] = sweeps;
+        return;
+    }
+stuck:
+    if (threadIdx.x == 0) set_device_error(a.err, SCHULZE_EDEVICE);
+}
+
+// ------------------------------------------------------------------ postprocessing
+// Marks from each vertex's own (s, ws, t, wt).  mark[v] = 1: v is beaten;
+// dead[x] = 1: the component labelled x is beaten.
+template <typename E>
+__global__ __launch_bounds__(256) void k_prop_post(const typename Key<E>::K *__restrict__ kf,
+                                                   const typename Key<E>::K *__restrict__ kb, int32_t m,
+                                                   const int32_t *__restrict__ vertex, uint8_t *__restrict__ mark) {
+    const int32_t c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= m) return;
+    const uint32_t s = key_label<E>(kf[c]), t = key_label<E>(kb[c]);
+    if (s == 0xFFFFFFFFu && t == 0xFFFFFFFFu) return;  // joined to no undecided vertex
+    if (s < t) {
+        mark[c] = 1;
+    } else if (s > t) {
+        mark[vertex[t]] = 1;
+    } else {
+        const uint32_t ws = key_width<E>(kf[c]), wt = key_width<E>(kb[c]);
+        if (ws > wt)
+            mark[c] = 1;
+        else if (ws < wt)
+            mark[vertex[s]] = 1;
+    }
+}
+
+// Edges v -> c between vertices with different (s, t): one wavefront per c
+// walks column c of w (row c of wt).
+template <typename E>
+__global__ __launch_bounds__(256) void k_prop_cross(const E *__restrict__ wt, int64_t ld,
+                                                    const typename Key<E>::K *__restrict__ kf,
+                                                    const typename Key<E>::K *__restrict__ kb, int32_t m,
+                                                    uint8_t *__restrict__ mark, uint8_t *__restrict__ dead) {
+    const int32_t c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (c >= m) return;
+    const uint32_t s = key_label<E>(kf[c]), t = key_label<E>(kb[c]);
+    bool cross = false;
+    for (int32_t v = lane; v < m; v += 64) {
+        if (wt[(int64_t)c * ld + v] == 0) continue;
+        cross |= key_label<E>(kf[v]) != s || key_label<E>(kb[v]) != t;
+    }
+    if (__ballot(cross) && lane == 0) {
+        if (s == t) {
+            if (s != 0xFFFFFFFFu) dead[s] = 1;
+        } else {
+            mark[c] = 1;
+        }
+    }
+}
+
+// Apply the marks to undecided vertices; then count the undecided ones.
+template <typename E>
+__global__ __launch_bounds__(256) void k_prop_apply(const typename Key<E>::K *__restrict__ kf,
+                                                    const typename Key<E>::K *__restrict__ kb, int32_t m,
+                                                    const uint8_t *__restrict__ mark, const uint8_t *__restrict__ dead,
+                                                    uint8_t *__restrict__ status) {
+    const int32_t c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= m || status[c] != ST_UNKNOWN) return;
+    const uint32_t s = key_label<E>(kf[c]), t = key_label<E>(kb[c]);
+    if (mark[c] || (s == t && s != 0xFFFFFFFFu && dead[s])) status[c] = ST_LOSER;
+}
+
+// Winners: undecided vertices whose own label is their (s, t).  counts[0]
+// receives the number still undecided after this round.
+template <typename E>
+__global__ __launch_bounds__(256) void k_prop_decide(const typename Key<E>::K *__restrict__ kf,
+                                                     const typename Key<E>::K *__restrict__ kb, int32_t m,
+                                                     const int32_t *__restrict__ label, uint8_t *__restrict__ status,
+                                                     int32_t *__restrict__ counts) {
+    const int32_t c = blockIdx.x * 256 + threadIdx.x;
+    int32_t undecided = 0;
+    if (c < m && status[c] == ST_UNKNOWN) {
+        const uint32_t s = key_label<E>(kf[c]), t = key_label<E>(kb[c]);
+        if (s == (uint32_t)label[c] && t == s)
+            status[c] = ST_WINNER;
+        else
+            undecided = 1;
+    }
+    const uint64_t bal = __ballot(undecided);
+    if ((threadIdx.x & 63) == 0 && bal) atomicAdd(&counts[0], (int32_t)__popcll(bal));
+}
+
+__global__ __launch_bounds__(256) void k_prop_out(const uint8_t *__restrict__ status, int32_t m,
+                                                  uint8_t *__restrict__ is_winner, int32_t *__restrict__ counts) {
+    const int32_t c = blockIdx.x * 256 + threadIdx.x;
+    int32_t win = 0;
+    if (c < m) {
+        win = status[c] == ST_WINNER ? 1 : 0;
+        is_winner[c] = (uint8_t)win;
+    }
+    const uint64_t bal = __ballot(win);
+    if ((threadIdx.x & 63) == 0 && bal) atomicAdd(&counts[1], (int32_t)__popcll(bal));
+}
+
+template <typename E>
+int run_propagate(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32_t m, int mode, int use_borda,
+                  uint8_t *is_winner, int32_t *n_winners, schulze_propagate_stats *stats) {
+    using K = typename Key<E>::K;
+    const size_t mat = round_up(sizeof(E) * (size_t)m * m, 256);
+    const size_t kvec = round_up(sizeof(K) * (size_t)m, 256);
+    const size_t ivec = round_up(sizeof(int32_t) * (size_t)m, 256);
+    const size_t bvec = round_up((size_t)m, 256);
+    const size_t u64vec = round_up(sizeof(unsigned long long) * (size_t)m, 256);
+    // w | wt | keys x2 | kf | kb | fronts x2 | label | vertex | borda | status | mark | dead | tail
+    const size_t need = 2 * mat + 4 * kvec + 4 * ivec + u64vec + 3 * bvec + 256;
+    int rc = ws_reserve(ctx, WS_PROPAGATE, need);
+    if (rc != SCHULZE_OK) return rc;
+    char *p = static_cast<char *>(ctx->ws[WS_PROPAGATE]);
+    auto take = [&](size_t bytes) {
+        char *q = p;
+        p += bytes;
+        return q;
+    };
+    E *w = reinterpret_cast<E *>(take(mat));
+    E *wt = reinterpret_cast<E *>(take(mat));
+    K *x0 = reinterpret_cast<K *>(take(kvec));
+    K *x1 = reinterpret_cast<K *>(take(kvec));
+    K *kf = reinterpret_cast<K *>(take(kvec));
+    K *kb = reinterpret_cast<K *>(take(kvec));
+    int32_t *f0 = reinterpret_cast<int32_t *>(take(ivec));
+    int32_t *f1 = reinterpret_cast<int32_t *>(take(ivec));
+    int32_t *label = reinterpret_cast<int32_t *>(take(ivec));
+    int32_t *vertex = reinterpret_cast<int32_t *>(take(ivec));
+    unsigned long long *borda = reinterpret_cast<unsigned long long *>(take(u64vec));
+    uint8_t *status = reinterpret_cast<uint8_t *>(take(bvec));
+    uint8_t *mark = reinterpret_cast<uint8_t *>(take(bvec));
+    uint8_t *dead = reinterpret_cast<uint8_t *>(take(bvec));
+    int32_t *tail = reinterpret_cast<int32_t *>(take(256));  // [0..2] sweep counters, [8..10] barrier, [16..17] counts
+
+    const int dtype = sizeof(E) == 2 ? SCHULZE_U16 : SCHULZE_I32;
+    if ((rc = schulze_weights(ctx, s, d, ldd, m, dtype, mode, w, m, wt, m)) != SCHULZE_OK) return rc;
+    SCHULZE_LAUNCH(ctx, K_PROP, s,
+                   k_prop_rows<E><<<dim3((unsigned)m), dim3(256), 0, s>>>(d, ldd, w, wt, m, m, status, borda));
+    SCHULZE_LAUNCH(ctx, K_PROP, s,
+                   k_prop_order<<<dim3((unsigned)m), dim3(256), 0, s>>>(borda, m, use_borda, label, vertex));
+
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_prop_sweep<E>, 256, 0) != hipSuccess || per_cu < 1)
+        return SCHULZE_EDEVICE;
+    int64_t G = (int64_t)ctx->num_cus * std::min(per_cu, 2);
+    G = std::min<int64_t>(G, ceil_div(m, 64));
+    if (G < 1) G = 1;
+    const unsigned vb = (unsigned)ceil_div(m, 256);
+
+    schulze_propagate_stats st{};
+    int32_t counts[2] = {0, 0};
+    for (int32_t round = 0; round < m; ++round) {
+        for (int dir = 0; dir < 2; ++dir) {
+            if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(tail), 16, 0u)) != SCHULZE_OK) return rc;
+            SweepArgs<E> a;
+            a.w = dir == 0 ? w : wt;
+            a.ld = m;
+            a.m = m;
+            a.status = status;
+            a.label = label;
+            a.x[0] = x0;
+            a.x[1] = x1;
+            a.front[0] = f0;
+            a.front[1] = f1;
+            a.fcount = tail;
+            a.out = dir == 0 ? kf : kb;
+            a.bar = reinterpret_cast<GridBar *>(tail + 8);
+            a.err = ctx->err;
+            a.spin_limit = (int64_t)1 << 24;
+            void *args[] = {&a};
+            int tok;
+            timing_begin(ctx, K_PROP_SWEEP, s, &tok);
+            const hipError_t e =
+                hipLaunchCooperativeKernel((const void *)k_prop_sweep<E>, dim3((unsigned)G), dim3(256), args, 0, s);
+            timing_end(ctx, tok, s);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return SCHULZE_EDEVICE;
+            }
+            int32_t sweeps = 0;
+            if (hipMemcpyAsync(&sweeps, tail + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return SCHULZE_EDEVICE;
+            st.sweeps += sweeps;
+        }
+        // mark and dead are adjacent: clear both
+        if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(mark), 2 * bvec / 4, 0u)) != SCHULZE_OK) return rc;
+        if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(tail + 16), 2, 0u)) != SCHULZE_OK) return rc;
+        SCHULZE_LAUNCH(ctx, K_PROP, s, k_prop_post<E><<<dim3(vb), dim3(256), 0, s>>>(kf, kb, m, vertex, mark));
+        SCHULZE_LAUNCH(ctx, K_PROP, s,
+                       k_prop_cross<E><<<dim3((unsigned)ceil_div(m, 4)), dim3(256), 0, s>>>(wt, m, kf, kb, m, mark,
+                                                                                            dead));
+        SCHULZE_LAUNCH(ctx, K_PROP, s, k_prop_apply<E><<<dim3(vb), dim3(256), 0, s>>>(kf, kb, m, mark, dead, status));
+        SCHULZE_LAUNCH(ctx, K_PROP, s,
+                       k_prop_decide<E><<<dim3(vb), dim3(256), 0, s>>>(kf, kb, m, label, status, tail + 16));
+        if (hipMemcpyAsync(counts, tail + 16, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return SCHULZE_EDEVICE;
+        ++st.rounds;
+        if (counts[0] == 0) break;
+    }
+    if (counts[0] != 0) return SCHULZE_EDEVICE;  // more rounds than candidates: cannot happen
+    SCHULZE_LAUNCH(ctx, K_PROP, s, k_prop_out<<<dim3(vb), dim3(256), 0, s>>>(status, m, is_winner, tail + 16));
+    if (hipMemcpyAsync(counts, tail + 16, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return SCHULZE_EDEVICE;
+    st.n_winners = counts[1];
+    if (n_winners &&
+        (hipMemcpyAsync(n_winners, &st.n_winners, sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+         hipStreamSynchronize(s) != hipSuccess))
+        return SCHULZE_EDEVICE;
+    if (stats) *stats = st;
+    return SCHULZE_OK;
+}
+
+}  // namespace
+
+extern "C" int schulze_winners_propagate(schulze_ctx *ctx, void *stream, const void *d, int64_t ldd, int32_t m,
+                                         int dtype, int mode, int borda_order, uint8_t *is_winner,
+                                         int32_t *n_winners, schulze_propagate_stats *stats) {
+    if (!ctx || !d || !is_winner) return SCHULZE_EINVAL;
+    if (m < 1 || ldd < m) return SCHULZE_EINVAL;
+    if (dtype != SCHULZE_U16 && dtype != SCHULZE_I32) return SCHULZE_EINVAL;
+    if (mode != SCHULZE_WINNING_VOTES && mode != SCHULZE_MARGIN) return SCHULZE_EINVAL;
+    if (m > 65534) return SCHULZE_EUNSUPPORTED;
+    if (bind_device(ctx) != SCHULZE_OK) return SCHULZE_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == SCHULZE_U16)
+        return run_propagate<uint16_t>(ctx, s, static_cast<const uint16_t *>(d), ldd, m, mode, borda_order != 0,
+                                       is_winner, n_winners, stats);
+    return run_propagate<int32_t>(ctx, s, static_cast<const int32_t *>(d), ldd, m, mode, borda_order != 0, is_winner,
+                                  n_winners, stats);
+}

@@ -280,3 +280,60 @@ def test_batch_of_the_batched_workload_shape(ctx):
         want.append(oracle.schulze(flat[bo:bo + n * m].reshape(n, m), m))
     assert_matches(packed, outs, want, "workload-shape")
     plan.destroy()
+
+
+@pytest.mark.slow
+def test_batch_full_workload_sampled():
+    """The 4096-election workload in the configuration the benchmark times
+    (autotuned schedules, graph replay): structural properties on every
+    election, the oracle on sampled elections including the largest ones."""
+    import torch
+    import paper_2505_12976_amd as sz
+    from paper_2505_12976_amd.batch import Packed
+    flat, desc, (ms, ns, phis) = workload.batch_mallows(1004, 4096)
+    packed = Packed(flat, desc, int(np.sum(ms * ms)), int(np.sum(ms)))
+    log(f"[case] batch full workload: {flat.nbytes / 1e9:.1f} GB of ballots")
+    ctx = sz.Context(0)
+    try:
+        ctx.batch_autotune(16, int(ms.max()))
+        plan = ctx.batch_plan(desc, "u16", "winning_votes")
+        dev = torch.device("cuda", 0)
+        ballots = torch.from_numpy(flat).to(dev)
+        outs = alloc_outputs(packed, dev)
+        for _ in range(2):  # capture, then replay
+            ctx.batch_run(plan, ballots, outs["d"], outs["is_winner"], p=outs["p"], n_winners=outs["n_winners"],
+                          beaten_by=outs["beaten_by"], order=outs["order"], graph=True)
+        torch.cuda.synchronize()
+        assert ctx.device_error() == 0
+        d_all = outs["d"].cpu().numpy().astype(np.int64)
+        p_all = outs["p"].cpu().numpy().astype(np.int64)
+        w_all = outs["is_winner"].cpu().numpy().astype(bool)
+        bb_all = outs["beaten_by"].cpu().numpy()
+        o_all = outs["order"].cpu().numpy()
+        nw_all = outs["n_winners"].cpu().numpy()
+        for e, (bo, n, L, m, mo, vo) in enumerate(desc):
+            d = d_all[mo:mo + m * m].reshape(m, m)
+            p = p_all[mo:mo + m * m].reshape(m, m)
+            off = ~np.eye(m, dtype=bool)
+            assert (np.diag(d) == 0).all() and ((d + d.T)[off] == n).all(), e  # complete rankings
+            w = np.where(off & (d > d.T), d, 0)
+            assert (p >= w).all() and (np.diag(p) == 0).all(), e
+            bb = (p.T > p).sum(axis=1)
+            assert (bb_all[vo:vo + m] == bb).all(), e
+            assert (w_all[vo:vo + m] == (bb == 0)).all() and nw_all[e] == (bb == 0).sum() >= 1, e
+            want_order = np.lexsort((np.arange(m), bb))
+            assert (o_all[vo:vo + m] == want_order).all(), e
+        # the oracle on the largest elections and a seeded sample
+        big = list(np.argsort(-(ms * ms * ns))[:3])
+        rng = np.random.default_rng(7)
+        sample = sorted(set(big) | set(rng.choice(4096, 5, replace=False).tolist()))
+        for e in sample:
+            bo, n, L, m, mo, vo = desc[e]
+            log(f"[case] oracle election {e}: m={m} n={n}")
+            want = oracle.schulze(flat[bo:bo + n * m].reshape(n, m), m)
+            np.testing.assert_array_equal(d_all[mo:mo + m * m].reshape(m, m), want["d"])
+            np.testing.assert_array_equal(p_all[mo:mo + m * m].reshape(m, m), want["p"])
+            np.testing.assert_array_equal(o_all[vo:vo + m], want["order"])
+        plan.destroy()
+    finally:
+        ctx.close()
