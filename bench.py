@@ -124,8 +124,32 @@ def bench_learned(args):
         w_f = full()
         t_full.append(time.perf_counter() - t0)
         print(f"[bench] full closure {t_full[-1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
-    exact = bool((w_l.cpu().numpy() == w_f.cpu().numpy()).all())
+    # the label-propagation winners algorithm of Section 4 on the same counts
+    def propagate():
+        w, nw, st = ctx.winners_propagate(d)
+        torch.cuda.synchronize()
+        return w, st
+
+    propagate()  # warm-up
+    t_prop = []
+    for _ in range(max(args.steps, 1)):
+        t0 = time.perf_counter()
+        w_p, st_p = propagate()
+        t_prop.append(time.perf_counter() - t0)
+    print(f"[bench] label propagation {np.median(t_prop) * 1e3:.2f} ms, {st_p}", file=sys.stderr, flush=True)
+    # the closure without value ranking (int32 arithmetic throughout)
+    ctx.set_value_ranking(False)
+    t0 = time.perf_counter()
+    w_i = full()
+    t_full_i32 = time.perf_counter() - t0
+    ctx.set_value_ranking(True)
+    print(f"[bench] full closure, int32 values {t_full_i32 * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    w_f_np = w_f.cpu().numpy()
+    exact = bool((w_l.cpu().numpy() == w_f_np).all())
+    exact_prop = bool((w_p.cpu().numpy() == w_f_np).all())
+    exact_i32 = bool((w_i.cpu().numpy() == w_f_np).all())
     tl, tf = float(np.median(t_learned)), float(min(t_full))
+    tp = float(np.median(t_prop))
     out = {
         "metric": "learned-verify vs full-closure speedup",
         "value": tf / tl,
@@ -140,7 +164,12 @@ def bench_learned(args):
         "ms_full_closure_and_winners": tf * 1e3,
         "ms_count": t_count * 1e3,
         "closure_gops": m ** 3 / tf / 1e9,
+        "ms_full_closure_int32_values": t_full_i32 * 1e3,
+        "ms_label_propagation": tp * 1e3,
+        "label_propagation_stats": st_p,
         "exact": exact,
+        "exact_label_propagation": exact_prop,
+        "exact_int32_closure": exact_i32,
         "winners": np.nonzero(w_l.cpu().numpy())[0].tolist(),
         "learned_stats": st,
     }
@@ -379,8 +408,8 @@ def main():
 
     names = ["ballot_scan", "route", "ballot_scatter", "count_dense", "count_trunc", "count_sparse", "count_finish",
              "weights",
-             "fw_diag", "fw_panel", "fw_rest", "fw_persist", "fw_store", "beaten_by", "rank_sort", "winners",
-             "fill"]
+             "fw_diag", "fw_panel", "fw_rest", "fw_persist", "fw_store", "value_rank", "beaten_by", "rank_sort",
+             "winners", "fill"]
     kern = {}
     for nm in names:
         launches, total = ctx.kernel_time(nm)
@@ -388,7 +417,7 @@ def main():
             kern[nm] = {"launches_per_step": launches / args.steps, "ms_per_step": total / args.steps,
                         "avg_launch_ms": total / launches}
     closure_ms = sum(kern.get(k, {}).get("ms_per_step", 0.0) for k in
-                     ("weights", "fw_diag", "fw_panel", "fw_rest", "fw_persist", "fw_store"))
+                     ("weights", "fw_diag", "fw_panel", "fw_rest", "fw_persist", "fw_store", "value_rank"))
     count_ms = sum(kern.get(k, {}).get("ms_per_step", 0.0) for k in
                    ("ballot_scan", "route", "ballot_scatter", "count_dense", "count_trunc", "count_sparse",
                     "count_finish"))
@@ -398,6 +427,10 @@ def main():
     n_full = int(np.count_nonzero((wl.ballots != (0xFFFF if wl.ballots.dtype == np.uint16 else -1)).sum(axis=1)
                                   >= m - 1)) if wl.ballots.shape[1] >= m - 1 else 0
     roof = None
+    # an int32 closure whose weights were ranked runs its updates in packed uint16
+    # (six ranking launches per step: mark, block sums, scan, word ranks, apply, store)
+    ranked = dcode == "i32" and kern.get("value_rank", {}).get("launches_per_step", 0) == 6
+    closure_bits = 16 if (dcode == "u16" or ranked) else 32
     if dominant == "count_dense":
         # one comparison per (full ranking, unordered pair): one VALU lane-op each
         work = n_full * m * (m - 1) / 2
@@ -406,7 +439,7 @@ def main():
                 "peak": VALU_LANE_OPS / 1e12, "unit": "Tops/s",
                 "traffic": measured_traffic("count_dense", wl.name)}
     elif dominant in ("fw_rest", "fw_panel", "fw_diag", "fw_persist"):
-        ops_per_update = 1 if dcode == "u16" else 2
+        ops_per_update = 1 if closure_bits == 16 else 2
         work = m ** 3 * ops_per_update
         roof = {"bound": "alu", "kernel": "closure", "achieved": work / (closure_ms / 1e3) / 1e12,
                 "peak": VALU_LANE_OPS / 1e12, "unit": "Tops/s",
@@ -417,12 +450,14 @@ def main():
                 "unit": "GB/s", "traffic": None}
     if roof.get("achieved") is not None:
         roof["frac"] = roof["achieved"] / roof["peak"]
-    ops_per_update = 1 if dcode == "u16" else 2
+    ops_per_update = 1 if closure_bits == 16 else 2
     closure_roof = {"bound": "alu", "achieved": m ** 3 * ops_per_update / (closure_ms / 1e3) / 1e12,
                     "peak": VALU_LANE_OPS / 1e12, "unit": "Tops/s",
                     "updates_per_s": m ** 3 / (closure_ms / 1e3)}
     closure_roof["frac"] = closure_roof["achieved"] / closure_roof["peak"]
     closure_roof["traffic"] = measured_traffic("fw_persist", wl.name)
+    closure_roof["value_bits"] = closure_bits
+    closure_roof["value_ranked"] = ranked
 
     out = {
         "metric": "closure Gop/s (max-min) + elections/sec; learned-verify vs full-closure speedup",

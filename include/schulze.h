@@ -308,6 +308,20 @@ enum { SCHULZE_SCHEDULE_AUTO = 0, SCHULZE_SCHEDULE_PHASED = 1 };
 int schulze_set_closure_schedule(schulze_ctx *ctx, int schedule);
 
 /*
+ * Value ranking of int32 closures (default on).  The (max, min) recurrence
+ * of Section 2.1 commutes with every strictly increasing map of the weights
+ * that keeps 0, so when the weights of an int32 closure with m >= 1024 take
+ * at most 65535 distinct nonzero values, all below 2^24, the closure runs on
+ * the ranks of the values in packed uint16 and maps the result back: same
+ * output, about a third less arithmetic per update.  Deciding costs one
+ * synchronisation of the stream (a 2 MB bitmap of the values and a count).
+ * With ranking off, or when the values do not fit, the int32 closure runs.
+ * Workspace when ranking: 2 m_p^2 + 4.2 MB bytes on top of the closure's
+ * (m_p = m rounded up to the tile size).
+ */
+int schulze_set_value_ranking(schulze_ctx *ctx, int enable);
+
+/*
  * Batches of independent elections (Section 2.1 applied to each election of
  * the batch), run by one persistent launch whose workgroups take work items
  * from a queue: ballot scans, pairwise counts split into runs of candidate

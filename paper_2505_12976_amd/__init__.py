@@ -28,6 +28,7 @@ EXPORTS = (
     "schulze_create", "schulze_destroy", "schulze_strerror", "schulze_get_device_error",
     "schulze_pairwise", "schulze_closure", "schulze_winners", "schulze_ranking",
     "schulze_set_timing", "schulze_kernel_time", "schulze_reset_timing", "schulze_set_closure_schedule",
+    "schulze_set_value_ranking",
     "schulze_weights", "schulze_widest_from", "schulze_verify", "schulze_features",
     "schulze_mlp_param_count", "schulze_mlp_forward", "schulze_mlp_loss", "schulze_mlp_backward", "schulze_mlp_adam",
     "schulze_winners_learned",
@@ -104,6 +105,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.schulze_kernel_time.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(c_i64), ctypes.POINTER(ctypes.c_double)]
     lib.schulze_reset_timing.argtypes = [vp]
     lib.schulze_set_closure_schedule.argtypes = [vp, c_int]
+    lib.schulze_set_value_ranking.argtypes = [vp, c_int]
     lib.schulze_weights.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_int, vp, c_i64, vp, c_i64]
     lib.schulze_widest_from.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_i32, vp]
     lib.schulze_verify.argtypes = [vp, vp, vp, c_i64, vp, c_i64, c_i32, c_int, c_i32, vp, vp, vp, vp, vp]
@@ -462,6 +464,10 @@ class Context:
         """"auto" (one persistent launch) or "phased" (three launches per round)."""
         code = {"auto": SCHEDULE_AUTO, "phased": SCHEDULE_PHASED}[schedule]
         _check(self._lib.schulze_set_closure_schedule(self._h, code), "schulze_set_closure_schedule")
+
+    def set_value_ranking(self, enable: bool) -> None:
+        """Run int32 closures of m >= 1024 on value ranks in uint16 when the values fit (default on)."""
+        _check(self._lib.schulze_set_value_ranking(self._h, int(bool(enable))), "schulze_set_value_ranking")
 
     # -------------------------------------------------------------- timing
     def set_timing(self, enable: bool) -> None:

@@ -257,17 +257,12 @@ __global__ __launch_bounds__(256) void k_fw_rest(E *__restrict__ P, int64_t ld, 
     acc_store<E, B>(acc, Ct, ld);
 }
 
+// Close the padded matrix P (pitch ld, nb x nb tiles of B) in place: one
+// persistent dataflow launch, or three launches per round when the device
+// refuses a cooperative launch or the phased schedule is forced.
 template <typename E, int B>
-int run_closure(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32_t m, int mode, E *p, int64_t ldp) {
-    const int32_t mp = (int32_t)round_up(m, B);
-    const int32_t nb = mp / B;
-    const int64_t ld = mp;
-    int rc = ws_reserve(ctx, WS_CLOSURE, sizeof(E) * (size_t)mp * mp);
-    if (rc != SCHULZE_OK) return rc;
-    E *P = static_cast<E *>(ctx->ws[WS_CLOSURE]);
-    dim3 wgrid((unsigned)ceil_div(mp, 64), (unsigned)ceil_div(mp, 64));
-    SCHULZE_LAUNCH(ctx, K_WEIGHTS, s, k_weights<E><<<wgrid, dim3(256), 0, s>>>(d, ldd, m, mode, P, ld, mp));
-
+int close_padded(schulze_ctx *ctx, hipStream_t s, E *P, int64_t ld, int32_t nb) {
+    int rc;
     bool done = false;
     if (nb > 1 && !ctx->force_phased) {
         // persistent dataflow launch
@@ -313,8 +308,209 @@ int run_closure(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32_
             }
         }
     }
+    return SCHULZE_OK;
+}
+
+template <typename E, int B>
+int run_closure(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32_t m, int mode, E *p, int64_t ldp) {
+    const int32_t mp = (int32_t)round_up(m, B);
+    const int32_t nb = mp / B;
+    const int64_t ld = mp;
+    int rc = ws_reserve(ctx, WS_CLOSURE, sizeof(E) * (size_t)mp * mp);
+    if (rc != SCHULZE_OK) return rc;
+    E *P = static_cast<E *>(ctx->ws[WS_CLOSURE]);
+    dim3 wgrid((unsigned)ceil_div(mp, 64), (unsigned)ceil_div(mp, 64));
+    SCHULZE_LAUNCH(ctx, K_WEIGHTS, s, k_weights<E><<<wgrid, dim3(256), 0, s>>>(d, ldd, m, mode, P, ld, mp));
+    if ((rc = close_padded<E, B>(ctx, s, P, ld, nb)) != SCHULZE_OK) return rc;
     dim3 sgrid((unsigned)(ceil_div(m, 256) * m));
     SCHULZE_LAUNCH(ctx, K_FW_STORE, s, k_fw_store<E><<<sgrid, dim3(256), 0, s>>>(P, ld, m, p, ldp));
+    return SCHULZE_OK;
+}
+
+// ------------------------------------------------------------------ ranked int32 closures
+// The (max, min) recurrence commutes with every strictly increasing map of
+// the values (the max and min of mapped values are the mapped max and min),
+// and such a map can fix 0.  So when the int32 weights take at most 65535
+// distinct nonzero values, all below RANK_CAP, the closure runs on their
+// ranks (1 = smallest nonzero value) in packed uint16 -- one instruction per
+// update instead of one and a half -- and the result is mapped back through
+// the table of ranked values.  Exact; otherwise the int32 closure runs.
+constexpr int32_t RANK_CAP = 1 << 24;           // values ranked below this bound
+constexpr int32_t RANK_WORDS = RANK_CAP / 32;   // bitmap words
+constexpr int32_t RANK_BLOCK = 1024;            // bitmap words per scan block
+constexpr int32_t RANK_BLOCKS = RANK_WORDS / RANK_BLOCK;
+constexpr int32_t RANK_MIN_M = 1024;            // below this the decision's synchronisation is not worth it
+
+// Mark every nonzero value of P in the bitmap; flags[0] = 1 if a value is >= RANK_CAP.
+__global__ __launch_bounds__(256) void k_rank_mark(const int32_t *__restrict__ P, int64_t count,
+                                                   uint32_t *__restrict__ bitmap, int32_t *__restrict__ flags) {
+    bool wide = false;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256) {
+        const int32_t v = P[e];
+        if (v == 0) continue;
+        if (v >= RANK_CAP || v < 0) {
+            wide = true;
+            continue;
+        }
+        const uint32_t bit = 1u << (v & 31);
+        uint32_t *word = bitmap + (v >> 5);
+        if (!(*word & bit)) atomicOr(word, bit);  // most values repeat: read before the atomic
+    }
+    if (wide) flags[0] = 1;
+}
+
+// Per block of RANK_BLOCK words: number of marked values.
+__global__ __launch_bounds__(256) void k_rank_blocks(const uint32_t *__restrict__ bitmap,
+                                                     uint32_t *__restrict__ block_sum) {
+    __shared__ uint32_t part[256];
+    const uint32_t *w = bitmap + (int64_t)blockIdx.x * RANK_BLOCK;
+    uint32_t c = 0;
+    for (int i = threadIdx.x; i < RANK_BLOCK; i += 256) c += __popc(w[i]);
+    part[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) block_sum[blockIdx.x] = part[0];
+}
+
+// Exclusive scan of the block sums (one workgroup); flags[1] = number of distinct nonzero values.
+__global__ __launch_bounds__(256) void k_rank_top(uint32_t *__restrict__ block_sum, int32_t *__restrict__ flags) {
+    __shared__ uint32_t part[256];
+    constexpr int PER = RANK_BLOCKS / 256;
+    uint32_t v[PER];
+    uint32_t c = 0;
+    for (int i = 0; i < PER; ++i) {
+        v[i] = block_sum[threadIdx.x * PER + i];
+        c += v[i];
+    }
+    part[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {  // inclusive scan
+        const uint32_t add = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    uint32_t run = part[threadIdx.x] - c;
+    for (int i = 0; i < PER; ++i) {
+        block_sum[threadIdx.x * PER + i] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == 255) flags[1] = (int32_t)part[255];
+}
+
+// word_rank[w] = number of marked values below word w; value_of[r] = the
+// value of rank r (1-based) while r <= 65535.
+__global__ __launch_bounds__(256) void k_rank_words(const uint32_t *__restrict__ bitmap,
+                                                    const uint32_t *__restrict__ block_off,
+                                                    uint32_t *__restrict__ word_rank, int32_t *__restrict__ value_of) {
+    __shared__ uint32_t part[256];
+    constexpr int PER = RANK_BLOCK / 256;
+    const int64_t w0 = (int64_t)blockIdx.x * RANK_BLOCK + threadIdx.x * PER;
+    uint32_t words[PER], c = 0;
+    for (int i = 0; i < PER; ++i) {
+        words[i] = bitmap[w0 + i];
+        c += __popc(words[i]);
+    }
+    part[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint32_t add = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    uint32_t run = block_off[blockIdx.x] + part[threadIdx.x] - c;
+    for (int i = 0; i < PER; ++i) {
+        word_rank[w0 + i] = run;
+        uint32_t bits = words[i];
+        while (bits) {
+            const int b = __builtin_ctz(bits);
+            bits &= bits - 1;
+            ++run;
+            if (run <= 65535u) value_of[run] = (int32_t)((w0 + i) * 32 + b);
+        }
+    }
+}
+
+// P16 = rank of P (0 for 0).
+__global__ __launch_bounds__(256) void k_rank_apply(const int32_t *__restrict__ P, int64_t count,
+                                                    const uint32_t *__restrict__ bitmap,
+                                                    const uint32_t *__restrict__ word_rank,
+                                                    uint16_t *__restrict__ P16) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256) {
+        const int32_t v = P[e];
+        uint32_t r = 0;
+        if (v != 0) {
+            const uint32_t below = bitmap[v >> 5] & ((1u << (v & 31)) - 1u);
+            r = word_rank[v >> 5] + __popc(below) + 1u;
+        }
+        P16[e] = (uint16_t)r;
+    }
+}
+
+// p[i][j] = value_of[P16[i][j]] for i != j, 0 on the diagonal.
+__global__ __launch_bounds__(256) void k_rank_store(const uint16_t *__restrict__ P16, int64_t ld, int32_t m,
+                                                    const int32_t *__restrict__ value_of, int32_t *__restrict__ p,
+                                                    int64_t ldp) {
+    const int32_t col_blocks = (m + 255) / 256;
+    const int32_t i = blockIdx.x / col_blocks;
+    const int32_t j = (blockIdx.x % col_blocks) * 256 + threadIdx.x;
+    if (j >= m) return;
+    p[(int64_t)i * ldp + j] = i == j ? 0 : value_of[P16[(int64_t)i * ld + j]];
+}
+
+template <int B>
+int run_closure_ranked(schulze_ctx *ctx, hipStream_t s, const int32_t *d, int64_t ldd, int32_t m, int mode, int32_t *p,
+                       int64_t ldp) {
+    static_assert(B % 64 == 0, "the ranked matrix is closed with 64 x 64 tiles");
+    const int32_t mp = (int32_t)round_up(m, B);
+    const int64_t ld = mp;
+    const int64_t count = (int64_t)mp * mp;
+    int rc = ws_reserve(ctx, WS_CLOSURE, sizeof(int32_t) * (size_t)count);
+    if (rc != SCHULZE_OK) return rc;
+    int32_t *P = static_cast<int32_t *>(ctx->ws[WS_CLOSURE]);
+    dim3 wgrid((unsigned)ceil_div(mp, 64), (unsigned)ceil_div(mp, 64));
+    SCHULZE_LAUNCH(ctx, K_WEIGHTS, s, k_weights<int32_t><<<wgrid, dim3(256), 0, s>>>(d, ldd, m, mode, P, ld, mp));
+
+    // rank tables: bitmap | word ranks | block offsets | value table | flags, then the uint16 matrix
+    const size_t bm = sizeof(uint32_t) * RANK_WORDS;
+    const size_t bo = sizeof(uint32_t) * RANK_BLOCKS;
+    const size_t vt = sizeof(int32_t) * 65536;
+    const size_t head = 2 * bm + bo + vt + 256;
+    if ((rc = ws_reserve(ctx, WS_RANKED, head + sizeof(uint16_t) * (size_t)count)) != SCHULZE_OK) return rc;
+    char *q = static_cast<char *>(ctx->ws[WS_RANKED]);
+    uint32_t *bitmap = reinterpret_cast<uint32_t *>(q);
+    uint32_t *word_rank = reinterpret_cast<uint32_t *>(q + bm);
+    uint32_t *block_off = reinterpret_cast<uint32_t *>(q + 2 * bm);
+    int32_t *value_of = reinterpret_cast<int32_t *>(q + 2 * bm + bo);
+    int32_t *flags = reinterpret_cast<int32_t *>(q + 2 * bm + bo + vt);
+    uint16_t *P16 = reinterpret_cast<uint16_t *>(q + head);
+    if ((rc = fill_u32(ctx, s, bitmap, RANK_WORDS, 0u)) != SCHULZE_OK) return rc;
+    if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(value_of), 1, 0u)) != SCHULZE_OK) return rc;
+    if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(flags), 2, 0u)) != SCHULZE_OK) return rc;
+    const unsigned egrid = (unsigned)std::min<int64_t>(ceil_div(count, 256), (int64_t)ctx->num_cus * 16);
+    SCHULZE_LAUNCH(ctx, K_RANK, s, k_rank_mark<<<dim3(egrid), dim3(256), 0, s>>>(P, count, bitmap, flags));
+    SCHULZE_LAUNCH(ctx, K_RANK, s, k_rank_blocks<<<dim3(RANK_BLOCKS), dim3(256), 0, s>>>(bitmap, block_off));
+    SCHULZE_LAUNCH(ctx, K_RANK, s, k_rank_top<<<dim3(1), dim3(256), 0, s>>>(block_off, flags));
+    int32_t host_flags[2] = {0, 0};
+    if (hipMemcpyAsync(host_flags, flags, sizeof(host_flags), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return SCHULZE_EDEVICE;
+    if (host_flags[0] != 0 || host_flags[1] > 65535) {  // too wide or too many values: int32 closure
+        if ((rc = close_padded<int32_t, B>(ctx, s, P, ld, mp / B)) != SCHULZE_OK) return rc;
+        dim3 sgrid((unsigned)(ceil_div(m, 256) * m));
+        SCHULZE_LAUNCH(ctx, K_FW_STORE, s, k_fw_store<int32_t><<<sgrid, dim3(256), 0, s>>>(P, ld, m, p, ldp));
+        return SCHULZE_OK;
+    }
+    SCHULZE_LAUNCH(ctx, K_RANK, s,
+                   k_rank_words<<<dim3(RANK_BLOCKS), dim3(256), 0, s>>>(bitmap, block_off, word_rank, value_of));
+    SCHULZE_LAUNCH(ctx, K_RANK, s, k_rank_apply<<<dim3(egrid), dim3(256), 0, s>>>(P, count, bitmap, word_rank, P16));
+    if ((rc = close_padded<uint16_t, 64>(ctx, s, P16, ld, mp / 64)) != SCHULZE_OK) return rc;
+    dim3 sgrid((unsigned)(ceil_div(m, 256) * m));
+    SCHULZE_LAUNCH(ctx, K_RANK, s, k_rank_store<<<sgrid, dim3(256), 0, s>>>(P16, ld, m, value_of, p, ldp));
     return SCHULZE_OK;
 }
 
@@ -339,6 +535,11 @@ extern "C" int schulze_closure(schulze_ctx *ctx, void *stream, const void *d, in
     if (dtype == SCHULZE_U16)
         return run_closure<uint16_t, 64>(ctx, s, static_cast<const uint16_t *>(d), ldd, m, mode,
                                          static_cast<uint16_t *>(p), ldp);
+    if (m >= RANK_MIN_M && ctx->value_ranking)
+        return m >= 2048 ? run_closure_ranked<128>(ctx, s, static_cast<const int32_t *>(d), ldd, m, mode,
+                                                   static_cast<int32_t *>(p), ldp)
+                         : run_closure_ranked<64>(ctx, s, static_cast<const int32_t *>(d), ldd, m, mode,
+                                                  static_cast<int32_t *>(p), ldp);
     if (m >= 2048)
         return run_closure<int32_t, 128>(ctx, s, static_cast<const int32_t *>(d), ldd, m, mode,
                                          static_cast<int32_t *>(p), ldp);

@@ -11,7 +11,7 @@ const char *const kKernelNames[K_NUM_KERNELS] = {
     "winners",     "fill",           "fw_persist",  "route",        "count_trunc",
     "widest",      "verdict",        "features",    "mlp_prepare",  "mlp_forward",
     "mlp_backward", "mlp_loss",      "mlp_adam",    "propose",     "batch",
-    "label_post",   "label_sweep"};
+    "label_post",   "label_sweep", "value_rank"};
 
 extern "C" const char *schulze_strerror(int code) {
     switch (code) {
@@ -193,6 +193,12 @@ static int drain_timing(schulze_ctx *ctx) {
 extern "C" int schulze_set_closure_schedule(schulze_ctx *ctx, int schedule) {
     if (!ctx || (schedule != SCHULZE_SCHEDULE_AUTO && schedule != SCHULZE_SCHEDULE_PHASED)) return SCHULZE_EINVAL;
     ctx->force_phased = schedule == SCHULZE_SCHEDULE_PHASED;
+    return SCHULZE_OK;
+}
+
+extern "C" int schulze_set_value_ranking(schulze_ctx *ctx, int enable) {
+    if (!ctx) return SCHULZE_EINVAL;
+    ctx->value_ranking = enable != 0;
     return SCHULZE_OK;
 }
 

@@ -29,6 +29,7 @@ enum WsSlot {
     WS_LEARNED,          // learned path: weights, transposed weights, features, scores
     WS_LEARNED_P,        // learned path: closure for the fallback
     WS_PROPAGATE,        // label propagation: weights, keys, frontiers, statuses
+    WS_RANKED,           // ranked closure: value bitmap, rank tables, uint16 matrix
     WS_NUM_SLOTS
 };
 
@@ -51,6 +52,8 @@ struct schulze_ctx {
     std::vector<double> total_ms;
     // closure schedule: false = one persistent launch when possible
     bool force_phased = false;
+    // int32 closures of m >= 1024 run on value ranks in uint16 when the values allow it
+    bool value_ranking = true;
     // batch closure schedule per value width (16, 32) and bucket of 32 candidates; -1 = built-in
     int8_t batch_variant[2][SCHULZE_BATCH_MAX_M / 32];
     schulze_ctx() {
@@ -90,6 +93,7 @@ enum KernelId {
     K_BATCH,
     K_PROP,
     K_PROP_SWEEP,
+    K_RANK,
     K_NUM_KERNELS
 };
 extern const char *const kKernelNames[K_NUM_KERNELS];

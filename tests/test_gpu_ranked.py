@@ -1,0 +1,140 @@
+"""Value-ranked int32 closures against the oracle.
+
+An int32 closure of m >= 1024 candidates runs on the ranks of the weight
+values in packed uint16 when there are at most 65535 distinct nonzero values,
+all below 2^24, and on int32 otherwise.  The widest-path recurrence of
+Section 2.1 only compares values, so both give the oracle's widths exactly.
+Each case checks the output against the oracle and records, from the launch
+counts of the ranking kernels, which of the two paths ran.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+RANKED_LAUNCHES = 6    # mark, block sums, scan, word ranks, apply, store
+FALLBACK_LAUNCHES = 3  # mark, block sums, scan
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_2505_12976_amd as sz
+    assert torch.cuda.is_available()
+    c = sz.Context(0)
+    yield c
+    c.set_value_ranking(True)
+    c.close()
+
+
+def oriented(rng, m, values):
+    """Count matrix with d[x][y] = values[k] for one orientation of each pair and 0 the other way."""
+    iu, ju = np.triu_indices(m, 1)
+    flip = rng.random(iu.size) < 0.5
+    a, b = np.where(flip, ju, iu), np.where(flip, iu, ju)
+    d = np.zeros((m, m), dtype=np.int64)
+    d[a, b] = values
+    return d
+
+
+def run(ctx, d, mode, ranking):
+    import torch
+    ctx.set_value_ranking(ranking)
+    ctx.set_timing(True)
+    ctx.reset_timing()
+    dt = torch.from_numpy(np.ascontiguousarray(d, dtype=np.int32)).cuda()
+    p = ctx.closure(dt, mode)
+    torch.cuda.synchronize()
+    launches, _ = ctx.kernel_time("value_rank")
+    ctx.set_timing(False)
+    assert ctx.device_error() == 0
+    return p.cpu().numpy().astype(np.int64), launches
+
+
+def check(ctx, d, mode, expect_launches, tag):
+    want = oracle.closure(oracle.weights(d, oracle.MARGIN if mode == "margin" else oracle.WINNING_VOTES))
+    log(f"[case] {tag} m={d.shape[0]} mode={mode} distinct={len(np.unique(d))}")
+    got, launches = run(ctx, d, mode, True)
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, f"{tag}: ranked closure differs at {len(bad)} places, first {bad[:5].tolist()}"
+    assert launches == expect_launches, f"{tag}: {launches} ranking launches, expected {expect_launches}"
+    off, launches_off = run(ctx, d, mode, False)
+    assert launches_off == 0
+    assert np.array_equal(off, want), f"{tag}: int32 closure differs"
+
+
+@pytest.mark.parametrize("m", [1024, 1100, 2048, 2100])
+def test_few_values_take_ranks(ctx, m):
+    rng = np.random.default_rng(70 + m)
+    d = rng.integers(0, 4000, size=(m, m), dtype=np.int64)
+    np.fill_diagonal(d, 0)
+    check(ctx, d, "winning_votes", RANKED_LAUNCHES, "few-values")
+
+
+def test_margins_take_ranks(ctx):
+    rng = np.random.default_rng(71)
+    m = 1500
+    d = rng.integers(0, 100000, size=(m, m), dtype=np.int64)
+    d = np.minimum(d, d.T + rng.integers(0, 300, size=(m, m)))  # small margins, few distinct
+    np.fill_diagonal(d, 0)
+    check(ctx, d, "margin", RANKED_LAUNCHES, "margins")
+
+
+def test_largest_rankable_value(ctx):
+    rng = np.random.default_rng(72)
+    m = 1024
+    vals = rng.choice(np.array([1, 2, 1000, (1 << 24) - 2, (1 << 24) - 1], dtype=np.int64), size=m * (m - 1) // 2)
+    check(ctx, oriented(rng, m, vals), "winning_votes", RANKED_LAUNCHES, "max-value")
+
+
+def test_value_too_wide_falls_back(ctx):
+    rng = np.random.default_rng(73)
+    m = 1024
+    vals = rng.integers(1, 50, size=m * (m - 1) // 2)
+    vals[rng.integers(0, vals.size)] = 1 << 24
+    check(ctx, oriented(rng, m, vals), "winning_votes", FALLBACK_LAUNCHES, "value-2^24")
+    vals[rng.integers(0, vals.size)] = (1 << 31) - 1
+    check(ctx, oriented(rng, m, vals), "winning_votes", FALLBACK_LAUNCHES, "value-int32-max")
+
+
+@pytest.mark.parametrize("distinct,launches", [(65535, RANKED_LAUNCHES), (65536, FALLBACK_LAUNCHES)])
+def test_distinct_value_limit(ctx, distinct, launches):
+    rng = np.random.default_rng(74 + distinct)
+    m = 1024
+    pool = rng.choice(np.arange(1, 1 << 24, dtype=np.int64), size=distinct, replace=False)
+    vals = np.concatenate([pool, rng.choice(pool, size=m * (m - 1) // 2 - distinct)])
+    rng.shuffle(vals)
+    check(ctx, oriented(rng, m, vals), "winning_votes", launches, f"distinct-{distinct}")
+
+
+def test_many_values_fall_back(ctx):
+    rng = np.random.default_rng(75)
+    m = 1100
+    d = rng.integers(0, 1 << 23, size=(m, m), dtype=np.int64)
+    np.fill_diagonal(d, 0)
+    check(ctx, d, "winning_votes", FALLBACK_LAUNCHES, "many-values")
+
+
+def test_all_zero_and_one_value(ctx):
+    m = 1024
+    d = np.zeros((m, m), dtype=np.int64)
+    check(ctx, d, "winning_votes", RANKED_LAUNCHES, "all-zero")
+    rng = np.random.default_rng(76)
+    check(ctx, oriented(rng, m, np.full(m * (m - 1) // 2, 12345)), "winning_votes", RANKED_LAUNCHES, "one-value")
+
+
+def test_below_threshold_runs_int32(ctx):
+    rng = np.random.default_rng(77)
+    m = 1023
+    d = rng.integers(0, 4000, size=(m, m), dtype=np.int64)
+    np.fill_diagonal(d, 0)
+    check(ctx, d, "winning_votes", 0, "m-1023")
