@@ -18,6 +18,9 @@ the paper's voting preliminaries (Section 2.1):
 * :func:`widest_from` / :func:`widest_to` -- single-source/target widest
   paths by dense Dijkstra (the path problems of the NL-membership proof,
   Section 3).
+* :func:`topk_levels` -- top-k by repeatedly taking the Schulze winners of
+  the candidates not yet ranked and removing them (the closing remark of
+  Section 4).
 """
 from __future__ import annotations
 
@@ -175,6 +178,32 @@ def widest_to(w: np.ndarray, t: int) -> np.ndarray:
     out = np.empty(w.shape[0], dtype=np.int64)
     _check(_load().oracle_widest_to(w.ctypes.data, w.shape[0], t, out.ctypes.data), "oracle_widest_to")
     return out
+
+
+def topk_levels(w: np.ndarray, k: int) -> np.ndarray:
+    """level[c] = the round in which c is a Schulze winner of the candidates
+    left after removing the winners of all earlier rounds, for the rounds
+    needed to rank at least k candidates (all rounds when k >= m); -1 for
+    candidates not reached.  Removing a candidate deletes its edges, so each
+    round's widths come from the closure of the subgraph induced by the
+    candidates still in (Section 4, last remark of the algorithm's
+    description; the winners of a round are those no remaining candidate
+    beats, Section 2.1)."""
+    w = np.asarray(w, dtype=np.int64)
+    m = w.shape[0]
+    level = np.full(m, -1, dtype=np.int32)
+    alive = np.ones(m, dtype=bool)
+    ranked, rnd = 0, 0
+    while ranked < k and alive.any():
+        idx = np.nonzero(alive)[0]
+        p = closure(w[np.ix_(idx, idx)])
+        beaten = (p.T > p).any(axis=1)  # some remaining y with p(y, x) > p(x, y)
+        win = idx[~beaten]
+        level[win] = rnd
+        alive[win] = False
+        ranked += len(win)
+        rnd += 1
+    return level
 
 
 def schulze(ballots: np.ndarray, m: int, mode: int = WINNING_VOTES, weight=None) -> dict:

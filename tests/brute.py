@@ -213,3 +213,20 @@ def nl_reduction(m: int, edges, a: int, b: int):
         W[u, v] = 4
     W[r_of[a], a] = 2
     return W
+
+
+def topk_by_removal(w: np.ndarray, k: int) -> list[list[int]]:
+    """Levels of top-k by iterated winner removal, as lists of candidate ids:
+    the Schulze winners of the candidates left (widths by path enumeration
+    on the subgraph they induce), removed, again, until at least k are
+    ranked or none is left.  Exponential: only for m <= 7."""
+    left = list(range(w.shape[0]))
+    levels: list[list[int]] = []
+    ranked = 0
+    while left and ranked < k:
+        sub = np.array([[int(w[a, b]) for b in left] for a in left], dtype=np.int64).reshape(len(left), len(left))
+        win = sorted(left[i] for i in schulze_winners_from_p(widest_by_paths(sub)))
+        levels.append(win)
+        ranked += len(win)
+        left = [c for c in left if c not in win]
+    return levels

@@ -198,6 +198,85 @@ def test_weights_modes_distinguish_on_truncated():
     assert res[oracle.MARGIN] == {0, 1, 2}
 
 
+def test_figure1_topk_by_removal():
+    """Top-k by iterated winner removal (Section 4's closing remark) on the
+    Figure 1 graph, derived by hand from its edges: a wins; without a the
+    cycle b->c (10), c->d (8), d->b (12) gives p(d,b) = 12 > p(b,d) = 8 and
+    p(d,c) = 10 > p(c,d) = 8, so d wins; then b (edge b->c); then c."""
+    g, idx, w, table = figure1()
+    level = oracle.topk_levels(w, 4)
+    assert [int(level[idx[c]]) for c in "abcd"] == [0, 2, 3, 1]
+    assert [int(x) for x in oracle.topk_levels(w, 2)] == [0, -1, -1, 1]
+
+
+# ---------------------------------------------------------------- top-k by winner removal
+
+def _levels_as_lists(level):
+    n = int(level.max()) + 1 if (level >= 0).any() else 0
+    return [sorted(int(c) for c in np.nonzero(level == i)[0]) for i in range(n)]
+
+
+def test_topk_brute_force_small():
+    rng = np.random.default_rng(31)
+    n_checked = 0
+    for m, b, wts in _random_profiles(300, max_m=7, seed=29):
+        d = oracle.pairwise(b, m, wts)
+        for mode in (oracle.WINNING_VOTES, oracle.MARGIN):
+            w = oracle.weights(d, mode)
+            k = int(rng.integers(1, m + 1))
+            assert _levels_as_lists(oracle.topk_levels(w, k)) == brute.topk_by_removal(w, k)
+            n_checked += 1
+    assert n_checked == 600
+
+
+def test_topk_removal_deletes_paths():
+    """Edges 0->1 (5), 0->2 (3), 2->3 (1), 3->0 (3).  Candidate 3 beats all
+    (p(3,0) = 3 > p(0,3) = 1, p(3,1) = 3, p(3,2) = 3 > p(2,3) = 1): level 0.
+    Without 3, candidate 0 reaches 1 and 2 and nothing reaches 0: level 1.
+    Without 3 and 0, 1 and 2 have no edges: both level 2.  On the full graph
+    2 beats 1 through 3 and 0 (width 1 > 0), so the full ranking puts 2
+    above 1: removal is a different order."""
+    w = np.zeros((4, 4), dtype=np.int64)
+    w[0, 1], w[0, 2], w[2, 3], w[3, 0] = 5, 3, 1, 3
+    assert oracle.topk_levels(w, 4).tolist() == [1, 2, 2, 0]
+    beaten, _, order = oracle.rank(oracle.closure(w))
+    assert order.tolist() == [3, 0, 2, 1]
+
+
+def test_topk_first_level_is_the_winner_set():
+    for m, b, wts in _random_profiles(200, max_m=12, seed=37):
+        w = oracle.weights(oracle.pairwise(b, m, wts), oracle.WINNING_VOTES)
+        _, win, _ = oracle.rank(oracle.closure(w))
+        level = oracle.topk_levels(w, 1)
+        assert ((level == 0) == win).all()
+        assert ((level == -1) == ~win).all()
+
+
+def test_topk_single_full_ranking_is_that_ranking():
+    rng = np.random.default_rng(41)
+    for m in (1, 2, 5, 17, 40):
+        order = rng.permutation(m).astype(np.int32)
+        d = oracle.pairwise(order[None, :], m)
+        level = oracle.topk_levels(oracle.weights(d, oracle.WINNING_VOTES), m)
+        assert [int(level[c]) for c in order] == list(range(m))
+
+
+def test_topk_levels_partition_and_stop_at_k():
+    for m, b, wts in _random_profiles(150, max_m=14, seed=43):
+        w = oracle.weights(oracle.pairwise(b, m, wts), oracle.MARGIN)
+        full = oracle.topk_levels(w, m)
+        assert (full >= 0).all()  # every candidate gets a level
+        assert set(full.tolist()) == set(range(int(full.max()) + 1))  # no empty level
+        for k in range(1, m + 1):
+            part = oracle.topk_levels(w, k)
+            reached = part >= 0
+            assert reached.sum() >= k
+            assert (part[reached] == full[reached]).all()
+            last = int(part.max())
+            assert (reached == (full <= last)).all()
+            assert (full <= last - 1).sum() < k  # the last level was needed
+
+
 # ---------------------------------------------------------------- closure
 
 def test_closure_brute_force_small():
