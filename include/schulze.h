@@ -297,6 +297,36 @@ int schulze_winners_propagate(schulze_ctx *ctx, void *stream, const void *d, int
                               int dtype, int mode, int borda_order, uint8_t *is_winner,
                               int32_t *n_winners, schulze_propagate_stats *stats);
 
+/* Statistics of one schulze_topk_propagate call. */
+typedef struct {
+    int32_t levels;  /* rounds of winner removal run */
+    int32_t ranked;  /* candidates with a level (>= k unless fewer than k exist) */
+    int32_t rounds;  /* propagation rounds over all levels */
+    int32_t sweeps;  /* propagation sweeps over all levels, both directions */
+} schulze_topk_stats;
+
+/*
+ * Top-k by iterated winner removal (the closing remark of Section 4):
+ * level 0 is the set of Schulze winners; the winners are then taken out of
+ * the election (their edges deleted) and level 1 is the set of Schulze
+ * winners of the candidates left, and so on, until at least k candidates
+ * have a level or none is left.  Each level runs the algorithm of
+ * schulze_winners_propagate on the candidates still in.  Widest paths of a
+ * later level avoid the removed candidates, so this order can differ from
+ * the ranking of schulze_ranking (which orders by the full graph's widths).
+ * Synchronises the stream.
+ *
+ * d, ldd, m, dtype, mode, borda_order  as for schulze_winners_propagate.
+ * k       >= 1 (k >= m ranks everyone).
+ * level   m device int32: the level of each candidate, -1 if not reached.
+ * stats   NULL or host struct.
+ * Errors: EINVAL for k < 1 or bad arguments; EUNSUPPORTED for m > 65534.
+ * Workspace: as schulze_winners_propagate.
+ */
+int schulze_topk_propagate(schulze_ctx *ctx, void *stream, const void *d, int64_t ldd, int32_t m,
+                           int dtype, int mode, int borda_order, int32_t k, int32_t *level,
+                           schulze_topk_stats *stats);
+
 /*
  * Closure schedule.  AUTO (default): one persistent cooperative launch whose
  * workgroups exchange the diagonal and panel tiles of each round through
@@ -306,6 +336,17 @@ int schulze_winners_propagate(schulze_ctx *ctx, void *stream, const void *d, int
  */
 enum { SCHULZE_SCHEDULE_AUTO = 0, SCHULZE_SCHEDULE_PHASED = 1 };
 int schulze_set_closure_schedule(schulze_ctx *ctx, int schedule);
+
+/*
+ * Tile size B of the blocked closure (Section 5.2's recurrence cut into
+ * B x B tiles): 0 (default) picks by value width and m (uint16: 128 from
+ * m = 8192 on, else 64; int32: 128 from m = 2048 on, else 64), 64 or 128
+ * force it.
+ * Every B gives the same p; a larger B does more work per tile and round
+ * and has fewer rounds, a smaller one more parallelism per round.  Returns
+ * SCHULZE_EINVAL for other values.
+ */
+int schulze_set_closure_tile(schulze_ctx *ctx, int tile);
 
 /*
  * Value ranking of int32 closures (default on).  The (max, min) recurrence

@@ -28,17 +28,26 @@ EXPORTS = (
     "schulze_create", "schulze_destroy", "schulze_strerror", "schulze_get_device_error",
     "schulze_pairwise", "schulze_closure", "schulze_winners", "schulze_ranking",
     "schulze_set_timing", "schulze_kernel_time", "schulze_reset_timing", "schulze_set_closure_schedule",
-    "schulze_set_value_ranking",
+    "schulze_set_value_ranking", "schulze_set_closure_tile",
     "schulze_weights", "schulze_widest_from", "schulze_verify", "schulze_features",
     "schulze_mlp_param_count", "schulze_mlp_forward", "schulze_mlp_loss", "schulze_mlp_backward", "schulze_mlp_adam",
     "schulze_winners_learned",
     "schulze_batch_plan", "schulze_batch_destroy", "schulze_batch_run", "schulze_batch_set_closure",
     "schulze_batch_get_closure", "schulze_batch_autotune", "schulze_winners_propagate",
+    "schulze_topk_propagate",
 )
 
 
 class PropagateStats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int32), ("sweeps", ctypes.c_int32), ("n_winners", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class TopkStats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("ranked", ctypes.c_int32), ("rounds", ctypes.c_int32),
+                ("sweeps", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -106,6 +115,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.schulze_reset_timing.argtypes = [vp]
     lib.schulze_set_closure_schedule.argtypes = [vp, c_int]
     lib.schulze_set_value_ranking.argtypes = [vp, c_int]
+    lib.schulze_set_closure_tile.argtypes = [vp, c_int]
     lib.schulze_weights.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_int, vp, c_i64, vp, c_i64]
     lib.schulze_widest_from.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_i32, vp]
     lib.schulze_verify.argtypes = [vp, vp, vp, c_i64, vp, c_i64, c_i32, c_int, c_i32, vp, vp, vp, vp, vp]
@@ -122,6 +132,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                        ctypes.POINTER(BatchOptions), ctypes.POINTER(vp)]
     lib.schulze_winners_propagate.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_int, c_int, vp, vp,
                                               ctypes.POINTER(PropagateStats)]
+    lib.schulze_topk_propagate.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_int, c_int, c_i32, vp,
+                                           ctypes.POINTER(TopkStats)]
     lib.schulze_batch_destroy.argtypes = [vp]
     lib.schulze_batch_destroy.restype = None
     lib.schulze_batch_run.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, c_int]
@@ -396,6 +408,19 @@ class Context:
         _check(rc, "schulze_winners_propagate")
         return w, nw, st.as_dict()
 
+    def topk_propagate(self, d, k, mode="winning_votes", borda_order=True):
+        """(level int32[m], stats dict): top-k by iterated winner removal,
+        each level by the label-propagation algorithm (synchronises)."""
+        import torch
+        m = d.shape[0]
+        level = torch.empty(m, dtype=torch.int32, device=self._torch_device)
+        st = TopkStats()
+        rc = self._lib.schulze_topk_propagate(self._h, self._stream(), self._dev(d, "d"), d.stride(0), m,
+                                              _dtype_code(d.dtype), _mode_code(mode), int(bool(borda_order)),
+                                              int(k), self._dev(level, "level"), ctypes.byref(st))
+        _check(rc, "schulze_topk_propagate")
+        return level, st.as_dict()
+
     # -------------------------------------------------------------- batches
     def batch_plan(self, elections, ballot_dtype="u16", mode="winning_votes", max_range_pairs=0,
                    closure_only=False):
@@ -464,6 +489,10 @@ class Context:
         """"auto" (one persistent launch) or "phased" (three launches per round)."""
         code = {"auto": SCHEDULE_AUTO, "phased": SCHEDULE_PHASED}[schedule]
         _check(self._lib.schulze_set_closure_schedule(self._h, code), "schulze_set_closure_schedule")
+
+    def set_closure_tile(self, tile: int) -> None:
+        """Closure tile size: 0 (by value width and m), 64 or 128."""
+        _check(self._lib.schulze_set_closure_tile(self._h, int(tile)), "schulze_set_closure_tile")
 
     def set_value_ranking(self, enable: bool) -> None:
         """Run int32 closures of m >= 1024 on value ranks in uint16 when the values fit (default on)."""

@@ -20,11 +20,15 @@
 // (its state never leaves that workgroup's XCD).  An owner publishes the
 // round-r diagonal and panel tiles into a write-once buffer (one slot per
 // round and tile) and raises a flag; consumers wait on the flags they need.
-// Each workgroup works through its tiles round by round -- diagonal, then
-// panels, then the rest tiles that feed the next round's diagonal and panels,
-// then the others -- so round r+1 starts while round r is still finishing.
-// Every wait is on an item of an earlier (round, role) than the waiter's, and
-// a cooperative launch keeps all workgroups resident, so every wait ends;
+// Each workgroup works through its tiles round by round with a lookahead of
+// one round: panels of round r, then (for its owner) tile (r+1, r+1) and at
+// once round r+1's diagonal, then the other tiles that feed round r+1, then
+// round r+1's panels if that diagonal is out already, then the other rest
+// tiles of round r.  Round r+1 thus starts while round r is still running.
+// Order the items diag(0), panels(0), diag(1), panels(1), ...: a workgroup
+// only waits for an item earlier in that order than every item it has yet to
+// publish, and a cooperative launch keeps all workgroups resident, so every
+// wait ends;
 // a bounded spin turns anything else into a device error instead of a hang.
 //
 // uint16 matrices run two columns per 32-bit lane with v_pk_min_u16 and
@@ -88,6 +92,7 @@ struct PersistArgs {
     int32_t *abort;     // zero on entry
     int32_t *err;       // device error word
     int64_t spin_limit; // polls before a wait is declared stuck
+    int32_t early_panels; // run round r+1's panels ahead of round r's last tiles when possible
 };
 
 constexpr int MAX_OWNED = 512;
@@ -124,6 +129,16 @@ __device__ inline bool wait_flags(const int32_t *f0, const int32_t *f1, int32_t 
     }
     __syncthreads();
     const bool res = ok != 0;
+    __syncthreads();
+    return res;
+}
+
+// Whether a flag is raised already (no waiting); uniform over the workgroup.
+__device__ inline bool probe_flag(const int32_t *f) {
+    __shared__ int32_t seen;
+    if (threadIdx.x == 0) seen = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const bool res = seen != 0;
     __syncthreads();
     return res;
 }
@@ -168,44 +183,83 @@ __global__ __launch_bounds__(256, (sizeof(E) == 2 || B < 128) ? 2 : 1) void k_fw
     auto ring = [&](int32_t r, int32_t slot) { return a.ring + slot_index(r, slot, nb) * tile_elems; };
     auto flag = [&](int32_t r, int32_t slot) { return a.flags + slot_index(r, slot, nb); };
 
+    // One panel of round r (a tile of block row or column r, updated in place
+    // and published).
+    auto do_panel = [&](int32_t r, int32_t I, int32_t J) {
+        Acc<E, B> acc;
+        acc_load<E, B>(acc, tileP(I, J), a.ld);
+        int32_t slot;
+        if (I == r) {  // row panel: D* (x) P[r][J]
+            acc_product<E, B>(acc, ring(r, 0), B, tileP(I, J), a.ld, lds);
+            slot = 1 + J;
+        } else {       // column panel: P[I][r] (x) D*
+            acc_product<E, B>(acc, tileP(I, J), a.ld, ring(r, 0), B, lds);
+            slot = 1 + nb + I;
+        }
+        acc_store<E, B>(acc, tileP(I, J), a.ld);
+        acc_store<E, B>(acc, ring(r, slot), B);
+        raise_flag(flag(r, slot));
+    };
+    auto do_rest = [&](int32_t r, int32_t I, int32_t J) -> bool {
+        if (!wait_flags(flag(r, 1 + J), flag(r, 1 + nb + I), a.abort, a.spin_limit)) return false;
+        Acc<E, B> acc;
+        acc_load<E, B>(acc, tileP(I, J), a.ld);
+        acc_product<E, B>(acc, ring(r, 1 + nb + I), B, ring(r, 1 + J), B, lds);
+        acc_store<E, B>(acc, tileP(I, J), a.ld);
+        return true;
+    };
+
+    // Lookahead: the owner of tile (r+1, r+1) updates it first among its
+    // round-r rest tiles and closes it as round r+1's diagonal at once.  With
+    // few tiles per workgroup and round (early_panels), a workgroup whose
+    // round-r tiles that feed round r+1 are done also runs its round-(r+1)
+    // panels before its other round-r tiles when that diagonal is already
+    // published, so that round r+1 starts while round r's rest tiles are
+    // still running.  With many tiles per round there is no idle time to
+    // fill, and mixing two rounds' panels only costs cache.
+    if (tile_owner(0, 0, nb, G) == w) {
+        diag_close<E, B>(tileP(0, 0), a.ld, tileP(0, 0), a.ld, ring(0, 0), B, lds);
+        raise_flag(flag(0, 0));
+    }
+    int32_t panels_done = -1;  // round whose panels this workgroup already ran
     for (int32_t r = 0; r < nb; ++r) {
-        // diagonal
-        if (tile_owner(r, r, nb, G) == w) {
-            diag_close<E, B>(tileP(r, r), a.ld, tileP(r, r), a.ld, ring(r, 0), B, lds);
-            raise_flag(flag(r, 0));
-        }
         // panels
-        for (int32_t q = 0; q < no; ++q) {
-            const int32_t I = owned[q] / nb, J = owned[q] % nb;
-            if ((I == r) == (J == r)) continue;
-            if (!wait_flags(flag(r, 0), nullptr, a.abort, a.spin_limit)) goto stuck;
-            Acc<E, B> acc;
-            acc_load<E, B>(acc, tileP(I, J), a.ld);
-            int32_t slot;
-            if (I == r) {  // row panel: D* (x) P[r][J]
-                acc_product<E, B>(acc, ring(r, 0), B, tileP(I, J), a.ld, lds);
-                slot = 1 + J;
-            } else {       // column panel: P[I][r] (x) D*
-                acc_product<E, B>(acc, tileP(I, J), a.ld, ring(r, 0), B, lds);
-                slot = 1 + nb + I;
-            }
-            acc_store<E, B>(acc, tileP(I, J), a.ld);
-            acc_store<E, B>(acc, ring(r, slot), B);
-            raise_flag(flag(r, slot));
-        }
-        // rest tiles: those that feed round r+1's diagonal and panels first
-        for (int pass = 0; pass < 2; ++pass) {
+        if (panels_done != r) {
             for (int32_t q = 0; q < no; ++q) {
                 const int32_t I = owned[q] / nb, J = owned[q] % nb;
-                if (I == r || J == r) continue;
-                const bool next = I == r + 1 || J == r + 1;
-                if (next != (pass == 0)) continue;
-                if (!wait_flags(flag(r, 1 + J), flag(r, 1 + nb + I), a.abort, a.spin_limit)) goto stuck;
-                Acc<E, B> acc;
-                acc_load<E, B>(acc, tileP(I, J), a.ld);
-                acc_product<E, B>(acc, ring(r, 1 + nb + I), B, ring(r, 1 + J), B, lds);
-                acc_store<E, B>(acc, tileP(I, J), a.ld);
+                if ((I == r) == (J == r)) continue;
+                if (!wait_flags(flag(r, 0), nullptr, a.abort, a.spin_limit)) goto stuck;
+                do_panel(r, I, J);
             }
+        }
+        if (r + 1 < nb) {
+            // the next diagonal tile
+            if (tile_owner(r + 1, r + 1, nb, G) == w) {
+                if (!do_rest(r, r + 1, r + 1)) goto stuck;
+                diag_close<E, B>(tileP(r + 1, r + 1), a.ld, tileP(r + 1, r + 1), a.ld, ring(r + 1, 0), B, lds);
+                raise_flag(flag(r + 1, 0));
+            }
+            // the other tiles that feed round r+1
+            for (int32_t q = 0; q < no; ++q) {
+                const int32_t I = owned[q] / nb, J = owned[q] % nb;
+                if (I == r || J == r || (I != r + 1 && J != r + 1) || (I == r + 1 && J == r + 1)) continue;
+                if (!do_rest(r, I, J)) goto stuck;
+            }
+            // round r+1's panels, if its diagonal is out already
+            if (a.early_panels && probe_flag(flag(r + 1, 0))) {
+                for (int32_t q = 0; q < no; ++q) {
+                    const int32_t I = owned[q] / nb, J = owned[q] % nb;
+                    if ((I == r + 1) == (J == r + 1)) continue;
+                    do_panel(r + 1, I, J);
+                }
+                panels_done = r + 1;
+            }
+        }
+        // the remaining rest tiles of round r
+        for (int32_t q = 0; q < no; ++q) {
+            const int32_t I = owned[q] / nb, J = owned[q] % nb;
+            if (I == r || J == r || I == r + 1 || J == r + 1) continue;
+            if (!do_rest(r, I, J)) goto stuck;
         }
     }
     return;
@@ -281,8 +335,9 @@ int close_padded(schulze_ctx *ctx, hipStream_t s, E *P, int64_t ld, int32_t nb) 
             int32_t *flags = static_cast<int32_t *>(ctx->ws[WS_FLAGS]);
             if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(flags), (size_t)(nslots + 64), 0u)) != SCHULZE_OK)
                 return rc;
-            PersistArgs<E> pa{P, ld, nb, static_cast<E *>(ctx->ws[WS_RING]), flags, flags + nslots, ctx->err,
-                              (int64_t)1 << 22};
+            const int32_t early = (int64_t)nb * nb <= 8 * G ? 1 : 0;  // at most 8 tiles per workgroup and round
+            PersistArgs<E> pa{P,     ld,    nb, static_cast<E *>(ctx->ws[WS_RING]), flags, flags + nslots, ctx->err,
+                              (int64_t)1 << 22, early};
             void *args[] = {&pa};
             int tok;
             timing_begin(ctx, K_FW_PERSIST, s, &tok);
@@ -462,10 +517,13 @@ __global__ __launch_bounds__(256) void k_rank_store(const uint16_t *__restrict__
     p[(int64_t)i * ldp + j] = i == j ? 0 : value_of[P16[(int64_t)i * ld + j]];
 }
 
-template <int B>
+// BI: tile of the int32 closure (when the values cannot be ranked); BU: tile
+// of the uint16 closure on the ranks.
+template <int BI, int BU>
 int run_closure_ranked(schulze_ctx *ctx, hipStream_t s, const int32_t *d, int64_t ldd, int32_t m, int mode, int32_t *p,
                        int64_t ldp) {
-    static_assert(B % 64 == 0, "the ranked matrix is closed with 64 x 64 tiles");
+    constexpr int B = BI > BU ? BI : BU;
+    static_assert(B % BI == 0 && B % BU == 0, "both tiles divide the padded size");
     const int32_t mp = (int32_t)round_up(m, B);
     const int64_t ld = mp;
     const int64_t count = (int64_t)mp * mp;
@@ -500,7 +558,7 @@ int run_closure_ranked(schulze_ctx *ctx, hipStream_t s, const int32_t *d, int64_
         hipStreamSynchronize(s) != hipSuccess)
         return SCHULZE_EDEVICE;
     if (host_flags[0] != 0 || host_flags[1] > 65535) {  // too wide or too many values: int32 closure
-        if ((rc = close_padded<int32_t, B>(ctx, s, P, ld, mp / B)) != SCHULZE_OK) return rc;
+        if ((rc = close_padded<int32_t, BI>(ctx, s, P, ld, mp / BI)) != SCHULZE_OK) return rc;
         dim3 sgrid((unsigned)(ceil_div(m, 256) * m));
         SCHULZE_LAUNCH(ctx, K_FW_STORE, s, k_fw_store<int32_t><<<sgrid, dim3(256), 0, s>>>(P, ld, m, p, ldp));
         return SCHULZE_OK;
@@ -508,7 +566,7 @@ int run_closure_ranked(schulze_ctx *ctx, hipStream_t s, const int32_t *d, int64_
     SCHULZE_LAUNCH(ctx, K_RANK, s,
                    k_rank_words<<<dim3(RANK_BLOCKS), dim3(256), 0, s>>>(bitmap, block_off, word_rank, value_of));
     SCHULZE_LAUNCH(ctx, K_RANK, s, k_rank_apply<<<dim3(egrid), dim3(256), 0, s>>>(P, count, bitmap, word_rank, P16));
-    if ((rc = close_padded<uint16_t, 64>(ctx, s, P16, ld, mp / 64)) != SCHULZE_OK) return rc;
+    if ((rc = close_padded<uint16_t, BU>(ctx, s, P16, ld, mp / BU)) != SCHULZE_OK) return rc;
     dim3 sgrid((unsigned)(ceil_div(m, 256) * m));
     SCHULZE_LAUNCH(ctx, K_RANK, s, k_rank_store<<<sgrid, dim3(256), 0, s>>>(P16, ld, m, value_of, p, ldp));
     return SCHULZE_OK;
@@ -532,17 +590,23 @@ extern "C" int schulze_closure(schulze_ctx *ctx, void *stream, const void *d, in
     }
     if (bind_device(ctx) != SCHULZE_OK) return SCHULZE_EDEVICE;
     hipStream_t s = (hipStream_t)stream;
+    const int tile = ctx->closure_tile;
+    const int bu = tile ? tile : (m >= 8192 ? 128 : 64);  // uint16 tile
+    const int bi = tile ? tile : (m >= 2048 ? 128 : 64);  // int32 tile
+    const int32_t *di = static_cast<const int32_t *>(d);
+    int32_t *pi = static_cast<int32_t *>(p);
     if (dtype == SCHULZE_U16)
-        return run_closure<uint16_t, 64>(ctx, s, static_cast<const uint16_t *>(d), ldd, m, mode,
-                                         static_cast<uint16_t *>(p), ldp);
-    if (m >= RANK_MIN_M && ctx->value_ranking)
-        return m >= 2048 ? run_closure_ranked<128>(ctx, s, static_cast<const int32_t *>(d), ldd, m, mode,
-                                                   static_cast<int32_t *>(p), ldp)
-                         : run_closure_ranked<64>(ctx, s, static_cast<const int32_t *>(d), ldd, m, mode,
-                                                  static_cast<int32_t *>(p), ldp);
-    if (m >= 2048)
-        return run_closure<int32_t, 128>(ctx, s, static_cast<const int32_t *>(d), ldd, m, mode,
-                                         static_cast<int32_t *>(p), ldp);
-    return run_closure<int32_t, 64>(ctx, s, static_cast<const int32_t *>(d), ldd, m, mode,
-                                    static_cast<int32_t *>(p), ldp);
+        return bu == 128 ? run_closure<uint16_t, 128>(ctx, s, static_cast<const uint16_t *>(d), ldd, m, mode,
+                                                      static_cast<uint16_t *>(p), ldp)
+                         : run_closure<uint16_t, 64>(ctx, s, static_cast<const uint16_t *>(d), ldd, m, mode,
+                                                     static_cast<uint16_t *>(p), ldp);
+    if (m >= RANK_MIN_M && ctx->value_ranking) {
+        if (bi == 128)
+            return bu == 128 ? run_closure_ranked<128, 128>(ctx, s, di, ldd, m, mode, pi, ldp)
+                             : run_closure_ranked<128, 64>(ctx, s, di, ldd, m, mode, pi, ldp);
+        return bu == 128 ? run_closure_ranked<64, 128>(ctx, s, di, ldd, m, mode, pi, ldp)
+                         : run_closure_ranked<64, 64>(ctx, s, di, ldd, m, mode, pi, ldp);
+    }
+    return bi == 128 ? run_closure<int32_t, 128>(ctx, s, di, ldd, m, mode, pi, ldp)
+                     : run_closure<int32_t, 64>(ctx, s, di, ldd, m, mode, pi, ldp);
 }

@@ -196,6 +196,12 @@ extern "C" int schulze_set_closure_schedule(schulze_ctx *ctx, int schedule) {
     return SCHULZE_OK;
 }
 
+extern "C" int schulze_set_closure_tile(schulze_ctx *ctx, int tile) {
+    if (!ctx || (tile != 0 && tile != 64 && tile != 128)) return SCHULZE_EINVAL;
+    ctx->closure_tile = tile;
+    return SCHULZE_OK;
+}
+
 extern "C" int schulze_set_value_ranking(schulze_ctx *ctx, int enable) {
     if (!ctx) return SCHULZE_EINVAL;
     ctx->value_ranking = enable != 0;

@@ -234,6 +234,9 @@ __device__ inline void diag_close(SrcP src, int64_t lds_, DstP dst, int64_t ldd_
     E *rowbuf = buf;          // [2][B]: thread tx's columns at tx*CW ..
     E *colbuf = buf + 2 * B;  // [2][B]: thread ty's rows at ty*RA ..
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    // the tile may just have been stored by other threads of the workgroup
+    // (with another thread-to-element map)
+    __syncthreads();
     W v[D::RA][D::WC];
     for (int a = 0; a < D::RA; ++a) {
         const auto row = src + (int64_t)(ty + 16 * a) * lds_ + tx;

@@ -54,6 +54,8 @@ struct schulze_ctx {
     bool force_phased = false;
     // int32 closures of m >= 1024 run on value ranks in uint16 when the values allow it
     bool value_ranking = true;
+    // closure tile size: 0 = by value width and m, else 64 or 128
+    int closure_tile = 0;
     // batch closure schedule per value width (16, 32) and bucket of 32 candidates; -1 = built-in
     int8_t batch_variant[2][SCHULZE_BATCH_MAX_M / 32];
     schulze_ctx() {

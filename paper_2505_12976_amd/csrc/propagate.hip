@@ -40,7 +40,9 @@ namespace {
 using grid::GridBar;
 using grid::grid_sync;
 
-enum : uint8_t { ST_UNKNOWN = 0, ST_LOSER = 1, ST_WINNER = 2 };
+// ST_REMOVED: taken out of the election (top-k: a winner of an earlier
+// round); such a vertex has no edges, so it neither holds nor relays labels.
+enum : uint8_t { ST_UNKNOWN = 0, ST_LOSER = 1, ST_WINNER = 2, ST_REMOVED = 3 };
 
 template <typename E>
 struct Key;
@@ -81,21 +83,29 @@ __device__ inline uint32_t key_width(typename Key<E>::K k) {
 }
 
 // ------------------------------------------------------------------ per-vertex statistics
-// Row x of w and of wt: largest outgoing and incoming edge weight (the
-// initialisation filter), and the Borda score sum_y d[x][y].
+// Row x of w and of wt among the vertices still in (rem[y] = 0): largest
+// outgoing and incoming edge weight (the initialisation filter) and, when
+// with_borda, the Borda score sum_y d[x][y].  Every vertex still in starts
+// undecided unless the filter rules it out; removed vertices get ST_REMOVED.
 template <typename E>
 __global__ __launch_bounds__(256) void k_prop_rows(const E *__restrict__ d, int64_t ldd, const E *__restrict__ w,
                                                    const E *__restrict__ wt, int64_t ld, int32_t m,
+                                                   const uint8_t *__restrict__ rem, int with_borda,
                                                    uint8_t *__restrict__ status, unsigned long long *__restrict__ borda) {
     __shared__ uint32_t smax_out[256], smax_in[256];
     __shared__ unsigned long long sb[256];
     const int32_t x = blockIdx.x;
+    if (rem[x]) {
+        if (threadIdx.x == 0) status[x] = ST_REMOVED;
+        return;
+    }
     uint32_t mo = 0, mi = 0;
     unsigned long long b = 0;
     for (int32_t y = threadIdx.x; y < m; y += 256) {
+        if (rem[y]) continue;
         mo = max(mo, (uint32_t)w[(int64_t)x * ld + y]);
         mi = max(mi, (uint32_t)wt[(int64_t)x * ld + y]);
-        if (y != x) b += (unsigned long long)(uint32_t)d[(int64_t)x * ldd + y];
+        if (with_borda && y != x) b += (unsigned long long)(uint32_t)d[(int64_t)x * ldd + y];
     }
     smax_out[threadIdx.x] = mo;
     smax_in[threadIdx.x] = mi;
@@ -111,7 +121,7 @@ __global__ __launch_bounds__(256) void k_prop_rows(const E *__restrict__ d, int6
     }
     if (threadIdx.x == 0) {
         status[x] = smax_in[0] > smax_out[0] ? ST_LOSER : ST_UNKNOWN;  // initialisation filter
-        borda[x] = sb[0];
+        if (with_borda) borda[x] = sb[0];
     }
 }
 
@@ -210,7 +220,8 @@ __global__ __launch_bounds__(256) void k_prop_sweep(SweepArgs<E> a) {
                 __syncthreads();
                 if (wave == 0 && j < c1) {
                     const K old = xc[j];
-                    const K nv = max(max(old, part[0][lane]), max(part[1][lane], max(part[2][lane], part[3][lane])));
+                    K nv = max(max(old, part[0][lane]), max(part[1][lane], max(part[2][lane], part[3][lane])));
+                    if (a.status[j] == ST_REMOVED) nv = 0;  // no edges: receives nothing
                     xn[j] = nv;
                     if (nv > old) Fn[atomicAdd(&a.fcount[cur ^ 1], 1)] = j;
                 }
@@ -259,14 +270,15 @@ template <typename E>
 __global__ __launch_bounds__(256) void k_prop_cross(const E *__restrict__ wt, int64_t ld,
                                                     const typename Key<E>::K *__restrict__ kf,
                                                     const typename Key<E>::K *__restrict__ kb, int32_t m,
-                                                    uint8_t *__restrict__ mark, uint8_t *__restrict__ dead) {
+                                                    const uint8_t *__restrict__ status, uint8_t *__restrict__ mark,
+                                                    uint8_t *__restrict__ dead) {
     const int32_t c = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (c >= m) return;
+    if (c >= m || status[c] == ST_REMOVED) return;
     const uint32_t s = key_label<E>(kf[c]), t = key_label<E>(kb[c]);
     bool cross = false;
     for (int32_t v = lane; v < m; v += 64) {
-        if (wt[(int64_t)c * ld + v] == 0) continue;
+        if (wt[(int64_t)c * ld + v] == 0 || status[v] == ST_REMOVED) continue;
         cross |= key_label<E>(kf[v]) != s || key_label<E>(kb[v]) != t;
     }
     if (__ballot(cross) && lane == 0) {
@@ -322,17 +334,57 @@ __global__ __launch_bounds__(256) void k_prop_out(const uint8_t *__restrict__ st
     if ((threadIdx.x & 63) == 0 && bal) atomicAdd(&counts[1], (int32_t)__popcll(bal));
 }
 
+// Top-k: the winners of this round leave the election (level = round);
+// everyone else still in becomes undecided again.  counts[0] += winners,
+// counts[1] += vertices still in.
+__global__ __launch_bounds__(256) void k_prop_remove(uint8_t *__restrict__ status, int32_t m, int32_t round,
+                                                     int32_t *__restrict__ level, uint8_t *__restrict__ rem,
+                                                     int32_t *__restrict__ counts) {
+    const int32_t c = blockIdx.x * 256 + threadIdx.x;
+    int32_t win = 0, in = 0;
+    if (c < m) {
+        const uint8_t st = status[c];
+        if (st == ST_WINNER) {
+            level[c] = round;
+            rem[c] = 1;
+            win = 1;
+        } else if (st != ST_REMOVED) {
+            in = 1;
+        }
+    }
+    const uint64_t bw = __ballot(win), bi = __ballot(in);
+    if ((threadIdx.x & 63) == 0) {
+        if (bw) atomicAdd(&counts[0], (int32_t)__popcll(bw));
+        if (bi) atomicAdd(&counts[1], (int32_t)__popcll(bi));
+    }
+}
+
+// Device buffers of one propagation run (slices of the WS_PROPAGATE slot).
 template <typename E>
-int run_propagate(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32_t m, int mode, int use_borda,
-                  uint8_t *is_winner, int32_t *n_winners, schulze_propagate_stats *stats) {
+struct PropBufs {
+    using K = typename Key<E>::K;
+    E *w, *wt;
+    K *x0, *x1, *kf, *kb;
+    int32_t *f0, *f1, *label, *vertex;
+    unsigned long long *borda;
+    uint8_t *status, *mark, *dead, *rem;
+    int32_t *tail;  // [0..2] sweep counters, [8..10] barrier, [16..17] counts
+    size_t bvec;
+    int64_t G;      // sweep grid
+};
+
+// Weights, the removal mask cleared, the filter, the Borda scores and the labels.
+template <typename E>
+int prop_prepare(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32_t m, int mode, int use_borda,
+                 PropBufs<E> &b) {
     using K = typename Key<E>::K;
     const size_t mat = round_up(sizeof(E) * (size_t)m * m, 256);
     const size_t kvec = round_up(sizeof(K) * (size_t)m, 256);
     const size_t ivec = round_up(sizeof(int32_t) * (size_t)m, 256);
     const size_t bvec = round_up((size_t)m, 256);
     const size_t u64vec = round_up(sizeof(unsigned long long) * (size_t)m, 256);
-    // w | wt | keys x2 | kf | kb | fronts x2 | label | vertex | borda | status | mark | dead | tail
-    const size_t need = 2 * mat + 4 * kvec + 4 * ivec + u64vec + 3 * bvec + 256;
+    // w | wt | keys x2 | kf | kb | fronts x2 | label | vertex | borda | status | mark | dead | rem | tail
+    const size_t need = 2 * mat + 4 * kvec + 4 * ivec + u64vec + 4 * bvec + 256;
     int rc = ws_reserve(ctx, WS_PROPAGATE, need);
     if (rc != SCHULZE_OK) return rc;
     char *p = static_cast<char *>(ctx->ws[WS_PROPAGATE]);
@@ -341,92 +393,116 @@ int run_propagate(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int3
         p += bytes;
         return q;
     };
-    E *w = reinterpret_cast<E *>(take(mat));
-    E *wt = reinterpret_cast<E *>(take(mat));
-    K *x0 = reinterpret_cast<K *>(take(kvec));
-    K *x1 = reinterpret_cast<K *>(take(kvec));
-    K *kf = reinterpret_cast<K *>(take(kvec));
-    K *kb = reinterpret_cast<K *>(take(kvec));
-    int32_t *f0 = reinterpret_cast<int32_t *>(take(ivec));
-    int32_t *f1 = reinterpret_cast<int32_t *>(take(ivec));
-    int32_t *label = reinterpret_cast<int32_t *>(take(ivec));
-    int32_t *vertex = reinterpret_cast<int32_t *>(take(ivec));
-    unsigned long long *borda = reinterpret_cast<unsigned long long *>(take(u64vec));
-    uint8_t *status = reinterpret_cast<uint8_t *>(take(bvec));
-    uint8_t *mark = reinterpret_cast<uint8_t *>(take(bvec));
-    uint8_t *dead = reinterpret_cast<uint8_t *>(take(bvec));
-    int32_t *tail = reinterpret_cast<int32_t *>(take(256));  // [0..2] sweep counters, [8..10] barrier, [16..17] counts
+    b.w = reinterpret_cast<E *>(take(mat));
+    b.wt = reinterpret_cast<E *>(take(mat));
+    b.x0 = reinterpret_cast<K *>(take(kvec));
+    b.x1 = reinterpret_cast<K *>(take(kvec));
+    b.kf = reinterpret_cast<K *>(take(kvec));
+    b.kb = reinterpret_cast<K *>(take(kvec));
+    b.f0 = reinterpret_cast<int32_t *>(take(ivec));
+    b.f1 = reinterpret_cast<int32_t *>(take(ivec));
+    b.label = reinterpret_cast<int32_t *>(take(ivec));
+    b.vertex = reinterpret_cast<int32_t *>(take(ivec));
+    b.borda = reinterpret_cast<unsigned long long *>(take(u64vec));
+    b.status = reinterpret_cast<uint8_t *>(take(bvec));
+    b.mark = reinterpret_cast<uint8_t *>(take(bvec));
+    b.dead = reinterpret_cast<uint8_t *>(take(bvec));
+    b.rem = reinterpret_cast<uint8_t *>(take(bvec));
+    b.tail = reinterpret_cast<int32_t *>(take(256));
+    b.bvec = bvec;
 
     const int dtype = sizeof(E) == 2 ? SCHULZE_U16 : SCHULZE_I32;
-    if ((rc = schulze_weights(ctx, s, d, ldd, m, dtype, mode, w, m, wt, m)) != SCHULZE_OK) return rc;
+    if ((rc = schulze_weights(ctx, s, d, ldd, m, dtype, mode, b.w, m, b.wt, m)) != SCHULZE_OK) return rc;
+    if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(b.rem), bvec / 4, 0u)) != SCHULZE_OK) return rc;
     SCHULZE_LAUNCH(ctx, K_PROP, s,
-                   k_prop_rows<E><<<dim3((unsigned)m), dim3(256), 0, s>>>(d, ldd, w, wt, m, m, status, borda));
+                   k_prop_rows<E><<<dim3((unsigned)m), dim3(256), 0, s>>>(d, ldd, b.w, b.wt, m, m, b.rem, 1, b.status,
+                                                                         b.borda));
     SCHULZE_LAUNCH(ctx, K_PROP, s,
-                   k_prop_order<<<dim3((unsigned)m), dim3(256), 0, s>>>(borda, m, use_borda, label, vertex));
+                   k_prop_order<<<dim3((unsigned)m), dim3(256), 0, s>>>(b.borda, m, use_borda, b.label, b.vertex));
 
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_prop_sweep<E>, 256, 0) != hipSuccess || per_cu < 1)
         return SCHULZE_EDEVICE;
     int64_t G = (int64_t)ctx->num_cus * std::min(per_cu, 2);
     G = std::min<int64_t>(G, ceil_div(m, 64));
-    if (G < 1) G = 1;
-    const unsigned vb = (unsigned)ceil_div(m, 256);
+    b.G = G < 1 ? 1 : G;
+    return SCHULZE_OK;
+}
 
-    schulze_propagate_stats st{};
+// Rounds of forward/backward propagation, postprocessing and decisions
+// until no vertex still in is undecided.
+template <typename E>
+int prop_decide_all(schulze_ctx *ctx, hipStream_t s, int32_t m, PropBufs<E> &b, schulze_propagate_stats &st) {
+    int rc;
+    const unsigned vb = (unsigned)ceil_div(m, 256);
     int32_t counts[2] = {0, 0};
     for (int32_t round = 0; round < m; ++round) {
         for (int dir = 0; dir < 2; ++dir) {
-            if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(tail), 16, 0u)) != SCHULZE_OK) return rc;
+            if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(b.tail), 16, 0u)) != SCHULZE_OK) return rc;
             SweepArgs<E> a;
-            a.w = dir == 0 ? w : wt;
+            a.w = dir == 0 ? b.w : b.wt;
             a.ld = m;
             a.m = m;
-            a.status = status;
-            a.label = label;
-            a.x[0] = x0;
-            a.x[1] = x1;
-            a.front[0] = f0;
-            a.front[1] = f1;
-            a.fcount = tail;
-            a.out = dir == 0 ? kf : kb;
-            a.bar = reinterpret_cast<GridBar *>(tail + 8);
+            a.status = b.status;
+            a.label = b.label;
+            a.x[0] = b.x0;
+            a.x[1] = b.x1;
+            a.front[0] = b.f0;
+            a.front[1] = b.f1;
+            a.fcount = b.tail;
+            a.out = dir == 0 ? b.kf : b.kb;
+            a.bar = reinterpret_cast<GridBar *>(b.tail + 8);
             a.err = ctx->err;
             a.spin_limit = (int64_t)1 << 24;
             void *args[] = {&a};
             int tok;
             timing_begin(ctx, K_PROP_SWEEP, s, &tok);
             const hipError_t e =
-                hipLaunchCooperativeKernel((const void *)k_prop_sweep<E>, dim3((unsigned)G), dim3(256), args, 0, s);
+                hipLaunchCooperativeKernel((const void *)k_prop_sweep<E>, dim3((unsigned)b.G), dim3(256), args, 0, s);
             timing_end(ctx, tok, s);
             if (e != hipSuccess) {
                 (void)hipGetLastError();
                 return SCHULZE_EDEVICE;
             }
             int32_t sweeps = 0;
-            if (hipMemcpyAsync(&sweeps, tail + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            if (hipMemcpyAsync(&sweeps, b.tail + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess)
                 return SCHULZE_EDEVICE;
             st.sweeps += sweeps;
         }
         // mark and dead are adjacent: clear both
-        if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(mark), 2 * bvec / 4, 0u)) != SCHULZE_OK) return rc;
-        if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(tail + 16), 2, 0u)) != SCHULZE_OK) return rc;
-        SCHULZE_LAUNCH(ctx, K_PROP, s, k_prop_post<E><<<dim3(vb), dim3(256), 0, s>>>(kf, kb, m, vertex, mark));
+        if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(b.mark), 2 * b.bvec / 4, 0u)) != SCHULZE_OK) return rc;
+        if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(b.tail + 16), 2, 0u)) != SCHULZE_OK) return rc;
+        SCHULZE_LAUNCH(ctx, K_PROP, s, k_prop_post<E><<<dim3(vb), dim3(256), 0, s>>>(b.kf, b.kb, m, b.vertex, b.mark));
         SCHULZE_LAUNCH(ctx, K_PROP, s,
-                       k_prop_cross<E><<<dim3((unsigned)ceil_div(m, 4)), dim3(256), 0, s>>>(wt, m, kf, kb, m, mark,
-                                                                                            dead));
-        SCHULZE_LAUNCH(ctx, K_PROP, s, k_prop_apply<E><<<dim3(vb), dim3(256), 0, s>>>(kf, kb, m, mark, dead, status));
+                       k_prop_cross<E><<<dim3((unsigned)ceil_div(m, 4)), dim3(256), 0, s>>>(b.wt, m, b.kf, b.kb, m,
+                                                                                            b.status, b.mark, b.dead));
         SCHULZE_LAUNCH(ctx, K_PROP, s,
-                       k_prop_decide<E><<<dim3(vb), dim3(256), 0, s>>>(kf, kb, m, label, status, tail + 16));
-        if (hipMemcpyAsync(counts, tail + 16, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                       k_prop_apply<E><<<dim3(vb), dim3(256), 0, s>>>(b.kf, b.kb, m, b.mark, b.dead, b.status));
+        SCHULZE_LAUNCH(ctx, K_PROP, s,
+                       k_prop_decide<E><<<dim3(vb), dim3(256), 0, s>>>(b.kf, b.kb, m, b.label, b.status, b.tail + 16));
+        if (hipMemcpyAsync(counts, b.tail + 16, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return SCHULZE_EDEVICE;
         ++st.rounds;
-        if (counts[0] == 0) break;
+        if (counts[0] == 0) return SCHULZE_OK;
     }
-    if (counts[0] != 0) return SCHULZE_EDEVICE;  // more rounds than candidates: cannot happen
-    SCHULZE_LAUNCH(ctx, K_PROP, s, k_prop_out<<<dim3(vb), dim3(256), 0, s>>>(status, m, is_winner, tail + 16));
-    if (hipMemcpyAsync(counts, tail + 16, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+    return SCHULZE_EDEVICE;  // more rounds than candidates: cannot happen
+}
+
+template <typename E>
+int run_propagate(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32_t m, int mode, int use_borda,
+                  uint8_t *is_winner, int32_t *n_winners, schulze_propagate_stats *stats) {
+    PropBufs<E> b;
+    int rc = prop_prepare<E>(ctx, s, d, ldd, m, mode, use_borda, b);
+    if (rc != SCHULZE_OK) return rc;
+    schulze_propagate_stats st{};
+    if ((rc = prop_decide_all<E>(ctx, s, m, b, st)) != SCHULZE_OK) return rc;
+    const unsigned vb = (unsigned)ceil_div(m, 256);
+    int32_t counts[2] = {0, 0};
+    if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(b.tail + 16), 2, 0u)) != SCHULZE_OK) return rc;
+    SCHULZE_LAUNCH(ctx, K_PROP, s, k_prop_out<<<dim3(vb), dim3(256), 0, s>>>(b.status, m, is_winner, b.tail + 16));
+    if (hipMemcpyAsync(counts, b.tail + 16, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return SCHULZE_EDEVICE;
     st.n_winners = counts[1];
@@ -435,6 +511,41 @@ int run_propagate(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int3
          hipStreamSynchronize(s) != hipSuccess))
         return SCHULZE_EDEVICE;
     if (stats) *stats = st;
+    return SCHULZE_OK;
+}
+
+// Top-k: winners of the candidates still in, removed, again, until at least
+// k candidates have a level or none is left.
+template <typename E>
+int run_topk(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32_t m, int mode, int use_borda, int32_t k,
+             int32_t *level, schulze_topk_stats *stats) {
+    PropBufs<E> b;
+    int rc = prop_prepare<E>(ctx, s, d, ldd, m, mode, use_borda, b);
+    if (rc != SCHULZE_OK) return rc;
+    if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(level), (size_t)m, 0xFFFFFFFFu)) != SCHULZE_OK) return rc;
+    const unsigned vb = (unsigned)ceil_div(m, 256);
+    schulze_topk_stats out{};
+    schulze_propagate_stats st{};
+    for (int32_t lv = 0;; ++lv) {
+        if ((rc = prop_decide_all<E>(ctx, s, m, b, st)) != SCHULZE_OK) return rc;
+        if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(b.tail + 16), 2, 0u)) != SCHULZE_OK) return rc;
+        SCHULZE_LAUNCH(ctx, K_PROP, s,
+                       k_prop_remove<<<dim3(vb), dim3(256), 0, s>>>(b.status, m, lv, level, b.rem, b.tail + 16));
+        int32_t counts[2] = {0, 0};
+        if (hipMemcpyAsync(counts, b.tail + 16, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return SCHULZE_EDEVICE;
+        if (counts[0] < 1) return SCHULZE_EDEVICE;  // every nonempty election has a winner
+        out.levels = lv + 1;
+        out.ranked += counts[0];
+        if (out.ranked >= k || counts[1] == 0) break;
+        SCHULZE_LAUNCH(ctx, K_PROP, s,
+                       k_prop_rows<E><<<dim3((unsigned)m), dim3(256), 0, s>>>(d, ldd, b.w, b.wt, m, m, b.rem, 0,
+                                                                             b.status, b.borda));
+    }
+    out.rounds = st.rounds;
+    out.sweeps = st.sweeps;
+    if (stats) *stats = out;
     return SCHULZE_OK;
 }
 
@@ -455,4 +566,20 @@ extern "C" int schulze_winners_propagate(schulze_ctx *ctx, void *stream, const v
                                        is_winner, n_winners, stats);
     return run_propagate<int32_t>(ctx, s, static_cast<const int32_t *>(d), ldd, m, mode, borda_order != 0, is_winner,
                                   n_winners, stats);
+}
+
+extern "C" int schulze_topk_propagate(schulze_ctx *ctx, void *stream, const void *d, int64_t ldd, int32_t m,
+                                      int dtype, int mode, int borda_order, int32_t k, int32_t *level,
+                                      schulze_topk_stats *stats) {
+    if (!ctx || !d || !level) return SCHULZE_EINVAL;
+    if (m < 1 || ldd < m || k < 1) return SCHULZE_EINVAL;
+    if (dtype != SCHULZE_U16 && dtype != SCHULZE_I32) return SCHULZE_EINVAL;
+    if (mode != SCHULZE_WINNING_VOTES && mode != SCHULZE_MARGIN) return SCHULZE_EINVAL;
+    if (m > 65534) return SCHULZE_EUNSUPPORTED;
+    if (bind_device(ctx) != SCHULZE_OK) return SCHULZE_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == SCHULZE_U16)
+        return run_topk<uint16_t>(ctx, s, static_cast<const uint16_t *>(d), ldd, m, mode, borda_order != 0, k, level,
+                                  stats);
+    return run_topk<int32_t>(ctx, s, static_cast<const int32_t *>(d), ldd, m, mode, borda_order != 0, k, level, stats);
 }

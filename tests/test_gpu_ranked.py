@@ -138,3 +138,29 @@ def test_below_threshold_runs_int32(ctx):
     d = rng.integers(0, 4000, size=(m, m), dtype=np.int64)
     np.fill_diagonal(d, 0)
     check(ctx, d, "winning_votes", 0, "m-1023")
+
+
+@pytest.mark.parametrize("tile", [64, 128])
+def test_closure_tile_sizes(ctx, tile):
+    """Every tile size gives the oracle's widths, for both value widths, ranked or not."""
+    import torch
+    rng = np.random.default_rng(78 + tile)
+    try:
+        ctx.set_closure_tile(tile)
+        for m in (130, 1100):
+            d = rng.integers(0, 3000, size=(m, m), dtype=np.int64)
+            np.fill_diagonal(d, 0)
+            want = oracle.closure(oracle.weights(d, oracle.WINNING_VOTES))
+            log(f"[case] tile={tile} m={m}")
+            for dt in (np.uint16, np.int32):
+                for ranking in (True, False):
+                    ctx.set_value_ranking(ranking)
+                    dd = torch.from_numpy(d.astype(dt)).cuda()
+                    p = ctx.closure(dd, "winning_votes")
+                    torch.cuda.synchronize()
+                    assert ctx.device_error() == 0
+                    got = p.cpu().numpy().astype(np.int64)
+                    assert np.array_equal(got, want), f"tile={tile} m={m} dtype={dt} ranking={ranking}"
+    finally:
+        ctx.set_closure_tile(0)
+        ctx.set_value_ranking(True)
