@@ -380,13 +380,15 @@ typedef struct {
     int32_t L;          /* entries per ballot, 1 <= L <= m */
     int32_t m;          /* candidates, 1 <= m <= SCHULZE_BATCH_MAX_M */
     int64_t mat_off;    /* first element of the election's m x m blocks (row pitch m) in d and p */
-    int64_t vec_off;    /* first element of its m-entry blocks in is_winner, beaten_by and order */
+    int64_t vec_off;    /* first element of its m-entry blocks in is_winner, beaten_by, order, level */
 } schulze_election;
 
 typedef struct {
     int32_t max_range_pairs; /* 0 = automatic; else at most this many voter pairs per counting range */
     int32_t closure_only;    /* 1 = the plan only serves runs without ballots (no rank-pair buffer) */
-    int32_t reserved[6];     /* zero */
+    int32_t topk;            /* 0 = no levels; k > 0: runs given a level array rank at least k candidates
+                                per election by iterated winner removal (as schulze_topk_propagate) */
+    int32_t reserved[5];     /* zero */
 } schulze_batch_options;
 
 typedef struct schulze_batch schulze_batch;
@@ -429,6 +431,12 @@ enum { SCHULZE_BATCH_GRAPH = 1 };
  * is_winner  1 for Schulze winners, else 0.     n_winners: NULL or E int32.
  * beaten_by  NULL or int32 (candidates beating x).  order: NULL or int32
  *            (candidates by beaten_by, then id), as schulze_ranking.
+ * level      NULL or int32 top-k levels (plans made with topk > 0 only, else
+ *            SCHULZE_EINVAL): level 0 = the winners; then, with the ranked
+ *            candidates and their edges taken out, the winners of the rest
+ *            (closing remark of Section 4), until at least topk candidates of
+ *            the election are ranked; -1 for candidates not reached.  Each
+ *            level closes the election's weights once more.
  * All are device pointers that the descriptors' offsets index; the caller
  * sizes them.  Invalid ballots set the device error word to SCHULZE_EBALLOT.
  * flags      SCHULZE_BATCH_GRAPH: capture the reset of the plan's counters and
@@ -438,7 +446,7 @@ enum { SCHULZE_BATCH_GRAPH = 1 };
  */
 int schulze_batch_run(schulze_ctx *ctx, void *stream, schulze_batch *plan, const void *ballots,
                       int32_t *d, int32_t *p, uint8_t *is_winner, int32_t *n_winners,
-                      int32_t *beaten_by, int32_t *order, int flags);
+                      int32_t *beaten_by, int32_t *order, int32_t *level, int flags);
 
 /*
  * Closure schedules of a batch election, chosen per value width (16 or 32

@@ -76,8 +76,8 @@ class Election(ctypes.Structure):
 
 
 class BatchOptions(ctypes.Structure):
-    _fields_ = [("max_range_pairs", ctypes.c_int32), ("closure_only", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+    _fields_ = [("max_range_pairs", ctypes.c_int32), ("closure_only", ctypes.c_int32), ("topk", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class SchulzeError(RuntimeError):
@@ -136,7 +136,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                            ctypes.POINTER(TopkStats)]
     lib.schulze_batch_destroy.argtypes = [vp]
     lib.schulze_batch_destroy.restype = None
-    lib.schulze_batch_run.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, c_int]
+    lib.schulze_batch_run.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, c_int]
     lib.schulze_batch_set_closure.argtypes = [vp, c_i32, c_i32, c_i32, c_i32]
     lib.schulze_batch_get_closure.argtypes = [vp, c_i32, c_i32, ctypes.POINTER(c_i32)]
     lib.schulze_batch_autotune.argtypes = [vp, vp, c_i32, c_i32, ctypes.POINTER(ctypes.c_float)]
@@ -423,9 +423,10 @@ class Context:
 
     # -------------------------------------------------------------- batches
     def batch_plan(self, elections, ballot_dtype="u16", mode="winning_votes", max_range_pairs=0,
-                   closure_only=False):
+                   closure_only=False, topk=0):
         """Plan a batch.  elections: sequence of (ballot_off, n, L, m, mat_off,
-        vec_off) tuples (element offsets) or of Election structs."""
+        vec_off) tuples (element offsets) or of Election structs.  topk > 0:
+        runs given a level array compute top-k levels by winner removal."""
         import torch
         bcode = U16 if ballot_dtype in ("u16", U16, torch.uint16) else (
             I32 if ballot_dtype in ("i32", I32, torch.int32) else None)
@@ -435,7 +436,7 @@ class Context:
         arr = (Election * max(E, 1))()
         for i, el in enumerate(elections):
             arr[i] = el if isinstance(el, Election) else Election(*[int(v) for v in el])
-        opt = BatchOptions(int(max_range_pairs), int(bool(closure_only)))
+        opt = BatchOptions(int(max_range_pairs), int(bool(closure_only)), int(topk))
         h = ctypes.c_void_p()
         rc = self._lib.schulze_batch_plan(self._h, arr, E, bcode, _mode_code(mode), ctypes.byref(opt), ctypes.byref(h))
         _check(rc, "schulze_batch_plan")
@@ -444,7 +445,7 @@ class Context:
         return BatchPlan(self, h, E, bcode, d_elems, vec_elems)
 
     def batch_run(self, plan, ballots, d, is_winner, p=None, n_winners=None, beaten_by=None, order=None,
-                  graph=False):
+                  graph=False, level=None):
         """Run a planned batch (ballots None: d is the input counts)."""
         import torch
 
@@ -462,7 +463,8 @@ class Context:
             self._h, self._stream(), plan._h, bp, ptr(d, "d", torch.int32, plan.d_elems),
             ptr(p, "p", torch.int32, plan.d_elems), ptr(is_winner, "is_winner", torch.uint8, plan.vec_elems),
             ptr(n_winners, "n_winners", torch.int32, plan.E), ptr(beaten_by, "beaten_by", torch.int32, plan.vec_elems),
-            ptr(order, "order", torch.int32, plan.vec_elems), BATCH_GRAPH if graph else 0)
+            ptr(order, "order", torch.int32, plan.vec_elems), ptr(level, "level", torch.int32, plan.vec_elems),
+            BATCH_GRAPH if graph else 0)
         _check(rc, "schulze_batch_run")
 
     def batch_set_closure(self, value_bits: int, m_lo: int, m_hi: int, variant) -> None:

@@ -106,6 +106,9 @@ struct BatchArgs {
     int32_t *n_winners;
     int32_t *beaten_by;
     int32_t *order;
+    int32_t *level;  // NULL or top-k levels (-1 = not reached)
+    int32_t topk;    // rank at least this many candidates per election (0: no levels)
+    int32_t pad1;
     int32_t *ctr;  // [0] ticket, [1] abort, [2, 2+E) scans done, [2+E, 2+2E) counts done
     char *scratch;
     int64_t scratch_bytes;  // per workgroup
@@ -583,69 +586,79 @@ __device__ void finish_t(const BatchArgs &a, const BElec &el, int32_t e, uint32_
         __syncthreads();
     }
 
-    // edge weights into the padded scratch matrix, 64 x 64 tiles through LDS
+    // edge weights into the padded scratch matrix, 64 x 64 tiles through LDS;
+    // candidates with gone[x] >= 0 (removed for top-k) lose all their edges
     int32_t *ta = reinterpret_cast<int32_t *>(smem);  // [64][65]
     int32_t *tb = ta + 64 * 65;                       // [64][65]
+    int32_t *bb = tb + 64 * 65;                       // [SCHULZE_BATCH_MAX_M]
+    int32_t *lvl = bb + SCHULZE_BATCH_MAX_M;          // [SCHULZE_BATCH_MAX_M]
     const int32_t nt = (mp + 63) / 64;
-    bool too_big = false;
-    for (int32_t I = 0; I < nt; ++I) {
-        for (int32_t J = 0; J < nt; ++J) {
-            __syncthreads();
-            for (int q = tid; q < 64 * 64; q += BT) {
-                const int r = q >> 6, c = q & 63;
-                const int32_t i = I * 64 + r, j = J * 64 + c;
-                ta[r * 65 + c] = (i < m && j < m) ? D[(int64_t)i * m + j] : 0;
-                const int32_t i2 = J * 64 + r, j2 = I * 64 + c;
-                tb[r * 65 + c] = (i2 < m && j2 < m) ? D[(int64_t)i2 * m + j2] : 0;
-            }
-            __syncthreads();
-            for (int q = tid; q < 64 * 64; q += BT) {
-                const int r = q >> 6, c = q & 63;
-                const int32_t i = I * 64 + r, j = J * 64 + c;
-                if (i >= mp || j >= mp) continue;
-                const int32_t x = ta[r * 65 + c], y = tb[c * 65 + r];  // d[i][j], d[j][i]
-                int32_t w = 0;
-                if (i != j && i < m && j < m && x > y) w = mode == SCHULZE_MARGIN ? x - y : x;
-                if constexpr (sizeof(E) == 2) {
-                    if ((uint32_t)w > 65535u) {  // counts above the bound the plan assumed
-                        too_big = true;
-                        w = 65535;
-                    }
+    auto weights = [&](const int32_t *gone) {
+        bool too_big = false;
+        for (int32_t I = 0; I < nt; ++I) {
+            for (int32_t J = 0; J < nt; ++J) {
+                __syncthreads();
+                for (int q = tid; q < 64 * 64; q += BT) {
+                    const int r = q >> 6, c = q & 63;
+                    const int32_t i = I * 64 + r, j = J * 64 + c;
+                    ta[r * 65 + c] = (i < m && j < m) ? D[(int64_t)i * m + j] : 0;
+                    const int32_t i2 = J * 64 + r, j2 = I * 64 + c;
+                    tb[r * 65 + c] = (i2 < m && j2 < m) ? D[(int64_t)i2 * m + j2] : 0;
                 }
-                P[(int64_t)i * mp + j] = (E)w;
+                __syncthreads();
+                for (int q = tid; q < 64 * 64; q += BT) {
+                    const int r = q >> 6, c = q & 63;
+                    const int32_t i = I * 64 + r, j = J * 64 + c;
+                    if (i >= mp || j >= mp) continue;
+                    const int32_t x = ta[r * 65 + c], y = tb[c * 65 + r];  // d[i][j], d[j][i]
+                    int32_t w = 0;
+                    if (i != j && i < m && j < m && x > y) w = mode == SCHULZE_MARGIN ? x - y : x;
+                    if (gone && w && (gone[i] >= 0 || gone[j] >= 0)) w = 0;
+                    if constexpr (sizeof(E) == 2) {
+                        if ((uint32_t)w > 65535u) {  // counts above the bound the plan assumed
+                            too_big = true;
+                            w = 65535;
+                        }
+                    }
+                    P[(int64_t)i * mp + j] = (E)w;
+                }
             }
         }
-    }
-    if (too_big) set_device_error(a.err, SCHULZE_ERANGE);
-    __syncthreads();
+        if (too_big) set_device_error(a.err, SCHULZE_ERANGE);
+        __syncthreads();
+    };
+    // bb[x] = #{y : P[y][x] > P[x][y]}
+    auto beaten = [&]() {
+        for (int32_t x = tid; x < m; x += BT) bb[x] = 0;
+        const int32_t mt = (m + 63) / 64;
+        for (int32_t I = 0; I < mt; ++I) {      // block of x
+            for (int32_t J = 0; J < mt; ++J) {  // block of y
+                __syncthreads();
+                for (int q = tid; q < 64 * 64; q += BT) {
+                    const int r = q >> 6, c = q & 63;
+                    const int32_t y = J * 64 + r, x = I * 64 + c;    // ta[y][x] = P[y][x]
+                    const int32_t x2 = I * 64 + r, y2 = J * 64 + c;  // tb[x][y] = P[x][y]
+                    ta[r * 65 + c] = (y < m && x < m) ? (int32_t)P[(int64_t)y * mp + x] : 0;
+                    tb[r * 65 + c] = (x2 < m && y2 < m) ? (int32_t)P[(int64_t)x2 * mp + y2] : 0;
+                }
+                __syncthreads();
+                const int32_t xl = tid & 63, g = tid >> 6;
+                const int32_t x = I * 64 + xl;
+                int32_t cnt = 0;
+                for (int32_t yl = g; yl < 64; yl += 4) cnt += ta[yl * 65 + xl] > tb[xl * 65 + yl] ? 1 : 0;
+                if (x < m && cnt) atomicAdd(&bb[x], cnt);
+            }
+        }
+        __syncthreads();
+    };
 
+    weights(nullptr);
     closure_dispatch<E>(Pv, mp, el.variant);
     __syncthreads();
+    beaten();
 
-    // beaten_by[x] = #{y : P[y][x] > P[x][y]}
-    int32_t *bb = reinterpret_cast<int32_t *>(smem) + 2 * 64 * 65;  // [m]
     __shared__ int32_t sh_wins;
-    for (int32_t x = tid; x < m; x += BT) bb[x] = 0;
     if (tid == 0) sh_wins = 0;
-    const int32_t mt = (m + 63) / 64;
-    for (int32_t I = 0; I < mt; ++I) {      // block of x
-        for (int32_t J = 0; J < mt; ++J) {  // block of y
-            __syncthreads();
-            for (int q = tid; q < 64 * 64; q += BT) {
-                const int r = q >> 6, c = q & 63;
-                const int32_t y = J * 64 + r, x = I * 64 + c;      // ta[y][x] = P[y][x]
-                const int32_t x2 = I * 64 + r, y2 = J * 64 + c;    // tb[x][y] = P[x][y]
-                ta[r * 65 + c] = (y < m && x < m) ? (int32_t)P[(int64_t)y * mp + x] : 0;
-                tb[r * 65 + c] = (x2 < m && y2 < m) ? (int32_t)P[(int64_t)x2 * mp + y2] : 0;
-            }
-            __syncthreads();
-            const int32_t xl = tid & 63, g = tid >> 6;
-            const int32_t x = I * 64 + xl;
-            int32_t cnt = 0;
-            for (int32_t yl = g; yl < 64; yl += 4) cnt += ta[yl * 65 + xl] > tb[xl * 65 + yl] ? 1 : 0;
-            if (x < m && cnt) atomicAdd(&bb[x], cnt);
-        }
-    }
     __syncthreads();
     int32_t wins = 0;
     for (int32_t x = tid; x < m; x += BT) {
@@ -672,6 +685,37 @@ __device__ void finish_t(const BatchArgs &a, const BElec &el, int32_t e, uint32_
     }
     __syncthreads();
     if (tid == 0 && a.n_winners) gmem(a.n_winners)[e] = sh_wins;
+
+    // top-k by iterated winner removal: level 0 = the winners; each further
+    // level closes the weights with the ranked candidates' edges deleted and
+    // takes the winners among the candidates left
+    if (a.level && a.topk > 0) {
+        __shared__ int32_t sh_ranked, sh_new;
+        for (int32_t x = tid; x < m; x += BT) lvl[x] = bb[x] == 0 ? 0 : -1;
+        if (tid == 0) sh_ranked = sh_wins;
+        __syncthreads();
+        // every nonempty set of candidates has a winner, so each level ranks at least one
+        for (int32_t level = 1; level < m && sh_ranked < a.topk && sh_ranked < m; ++level) {
+            weights(lvl);
+            closure_dispatch<E>(Pv, mp, el.variant);
+            __syncthreads();
+            beaten();
+            if (tid == 0) sh_new = 0;
+            __syncthreads();
+            int32_t got = 0;
+            for (int32_t x = tid; x < m; x += BT)
+                if (lvl[x] < 0 && bb[x] == 0) {  // removed candidates have no edges: skip them
+                    lvl[x] = level;
+                    ++got;
+                }
+            if (got) atomicAdd(&sh_new, got);
+            __syncthreads();
+            if (tid == 0) sh_ranked += sh_new;
+            __syncthreads();
+        }
+        FW_GLOBAL int32_t *lv = gmem(a.level);
+        for (int32_t x = tid; x < m; x += BT) lv[el.vec_off + x] = lvl[x];
+    }
     __syncthreads();
 }
 
@@ -744,6 +788,7 @@ struct schulze_batch {
     int ballot_dtype = SCHULZE_U16;
     int mode = SCHULZE_WINNING_VOTES;
     bool closure_only = false;
+    int32_t topk = 0;
     std::vector<BElec> elec;
     BElec *elec_dev = nullptr;
     BItem *items_full = nullptr, *items_closure = nullptr;
@@ -833,6 +878,7 @@ int build_plan(schulze_ctx *ctx, const schulze_election *desc, int32_t E, int ba
         if (opt->max_range_pairs < 0) return SCHULZE_EINVAL;
         if (opt->max_range_pairs > 0) max_range = std::min(max_range, opt->max_range_pairs);
         closure_only = opt->closure_only != 0;
+        if (opt->topk < 0) return SCHULZE_EINVAL;
     }
     schulze_batch *pl = new (std::nothrow) schulze_batch();
     if (!pl) return SCHULZE_ENOMEM;
@@ -842,6 +888,7 @@ int build_plan(schulze_ctx *ctx, const schulze_election *desc, int32_t E, int ba
     pl->ballot_dtype = ballot_dtype;
     pl->mode = mode;
     pl->closure_only = closure_only;
+    pl->topk = opt ? opt->topk : 0;
     pl->elec.resize(E);
     std::vector<double> cost(E);
     std::vector<int32_t> runs_of(E), ranges_of(E);
@@ -958,7 +1005,7 @@ int enqueue(schulze_batch *pl, hipStream_t s, const BatchArgs &args) {
 bool same_args(const BatchArgs &x, const BatchArgs &y) {
     return x.ballots == y.ballots && x.d == y.d && x.p == y.p && x.is_winner == y.is_winner &&
            x.n_winners == y.n_winners && x.beaten_by == y.beaten_by && x.order == y.order &&
-           x.closure_only == y.closure_only && x.err == y.err;
+           x.level == y.level && x.topk == y.topk && x.closure_only == y.closure_only && x.err == y.err;
 }
 
 }  // namespace
@@ -985,8 +1032,9 @@ extern "C" void schulze_batch_destroy(schulze_batch *plan) { free_plan(plan); }
 
 extern "C" int schulze_batch_run(schulze_ctx *ctx, void *stream, schulze_batch *plan, const void *ballots, int32_t *d,
                                  int32_t *p, uint8_t *is_winner, int32_t *n_winners, int32_t *beaten_by,
-                                 int32_t *order, int flags) {
+                                 int32_t *order, int32_t *level, int flags) {
     if (!ctx || !plan || plan->ctx != ctx || !d || !is_winner) return SCHULZE_EINVAL;
+    if (level && plan->topk == 0) return SCHULZE_EINVAL;
     if (flags & ~SCHULZE_BATCH_GRAPH) return SCHULZE_EINVAL;
     const bool closure_only = ballots == nullptr;
     if (!closure_only && plan->closure_only) return SCHULZE_EINVAL;
@@ -1008,6 +1056,8 @@ extern "C" int schulze_batch_run(schulze_ctx *ctx, void *stream, schulze_batch *
     args.n_winners = n_winners;
     args.beaten_by = beaten_by;
     args.order = order;
+    args.level = level;
+    args.topk = level ? plan->topk : 0;
     args.ctr = plan->ctr;
     args.scratch = plan->scratch;
     args.scratch_bytes = plan->scratch_bytes;
@@ -1114,12 +1164,12 @@ extern "C" int schulze_batch_autotune(schulze_ctx *ctx, void *stream, int32_t va
                 SCHULZE_OK)
                 break;
             float t = 0.f;
-            rc = schulze_batch_run(ctx, stream, pl, nullptr, d, nullptr, win, nullptr, nullptr, nullptr, 0);
+            rc = schulze_batch_run(ctx, stream, pl, nullptr, d, nullptr, win, nullptr, nullptr, nullptr, nullptr, 0);
             for (int rep = 0; rep < 2 && rc == SCHULZE_OK; ++rep) {
                 float tr = 0.f;
                 if (hipEventRecord(t0, s) != hipSuccess) rc = SCHULZE_EDEVICE;
                 if (rc == SCHULZE_OK)
-                    rc = schulze_batch_run(ctx, stream, pl, nullptr, d, nullptr, win, nullptr, nullptr, nullptr, 0);
+                    rc = schulze_batch_run(ctx, stream, pl, nullptr, d, nullptr, win, nullptr, nullptr, nullptr, nullptr, 0);
                 if (rc == SCHULZE_OK &&
                     (hipEventRecord(t1, s) != hipSuccess || hipEventSynchronize(t1) != hipSuccess ||
                      hipEventElapsedTime(&tr, t0, t1) != hipSuccess))

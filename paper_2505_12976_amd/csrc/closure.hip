@@ -44,29 +44,35 @@ namespace {
 using namespace fw;
 
 // ------------------------------------------------------------------ weights
-// P[i][j] = edge weight from d (winning votes or margin); zero padding.
+// P[i][j] = edge weight from d (winning votes or margin); zero padding.  A
+// workgroup takes the pair of 64 x 64 tiles (I, J) and (J, I), I <= J: both
+// need the same two blocks of d, so every count is read once.
 template <typename E>
 __global__ __launch_bounds__(256) void k_weights(const E *__restrict__ d, int64_t ldd, int32_t m, int mode,
                                                  E *__restrict__ P, int64_t ld, int32_t mp) {
-    __shared__ E a[64][65];
-    __shared__ E b[64][65];
+    __shared__ E a[64][65];  // a[r][c] = d[I0 + r][J0 + c]
+    __shared__ E b[64][65];  // b[r][c] = d[J0 + r][I0 + c]
+    if (blockIdx.y > blockIdx.x) return;
     const int32_t I0 = blockIdx.y * 64, J0 = blockIdx.x * 64;
     for (int e = threadIdx.x; e < 64 * 64; e += 256) {
         const int r = e >> 6, c = e & 63;
-        const int32_t i = I0 + r, j = J0 + c;
-        a[r][c] = (i < m && j < m) ? d[(int64_t)i * ldd + j] : (E)0;
-        const int32_t i2 = J0 + r, j2 = I0 + c;  // block (J, I)
-        b[r][c] = (i2 < m && j2 < m) ? d[(int64_t)i2 * ldd + j2] : (E)0;
+        a[r][c] = (I0 + r < m && J0 + c < m) ? d[(int64_t)(I0 + r) * ldd + J0 + c] : (E)0;
+        b[r][c] = (J0 + r < m && I0 + c < m) ? d[(int64_t)(J0 + r) * ldd + I0 + c] : (E)0;
     }
     __syncthreads();
+    auto weight = [&](E x, E y, bool diag) -> E {  // edge weight given d[i][j] = x, d[j][i] = y
+        if (diag || x <= y) return (E)0;
+        return mode == SCHULZE_MARGIN ? (E)(x - y) : x;
+    };
     for (int e = threadIdx.x; e < 64 * 64; e += 256) {
         const int r = e >> 6, c = e & 63;
-        const int32_t i = I0 + r, j = J0 + c;
-        if (i >= mp || j >= mp) continue;
-        const E x = a[r][c], y = b[c][r];  // d[i][j], d[j][i]
-        E w = 0;
-        if (i != j && i < m && j < m && x > y) w = mode == SCHULZE_MARGIN ? (E)(x - y) : x;
-        P[(int64_t)i * ld + j] = w;
+        int32_t i = I0 + r, j = J0 + c;
+        if (i < mp && j < mp) P[(int64_t)i * ld + j] = weight(a[r][c], b[c][r], i == j);
+        if (I0 != J0) {  // the mirrored tile (J, I)
+            i = J0 + r;
+            j = I0 + c;
+            if (i < mp && j < mp) P[(int64_t)i * ld + j] = weight(b[r][c], a[c][r], false);
+        }
     }
 }
 
@@ -396,22 +402,51 @@ constexpr int32_t RANK_BLOCK = 1024;            // bitmap words per scan block
 constexpr int32_t RANK_BLOCKS = RANK_WORDS / RANK_BLOCK;
 constexpr int32_t RANK_MIN_M = 1024;            // below this the decision's synchronisation is not worth it
 
-// Mark every nonzero value of P in the bitmap; flags[0] = 1 if a value is >= RANK_CAP.
+// Mark every nonzero value of P in the bitmap; flags[0] = 1 if a value is
+// >= RANK_CAP.  Values below RANK_LDS_BITS (the frequent small ones) are
+// first gathered in a workgroup bitmap in LDS and merged once per workgroup,
+// so that the global bitmap sees one atomic per set word and workgroup
+// instead of one per repeated value.
+constexpr int32_t RANK_LDS_WORDS = 8192;  // 32 KB: values below 2^18
+constexpr int32_t RANK_LDS_BITS = RANK_LDS_WORDS * 32;
 __global__ __launch_bounds__(256) void k_rank_mark(const int32_t *__restrict__ P, int64_t count,
                                                    uint32_t *__restrict__ bitmap, int32_t *__restrict__ flags) {
+    __shared__ uint32_t local[RANK_LDS_WORDS];
+    for (int i = threadIdx.x; i < RANK_LDS_WORDS; i += 256) local[i] = 0u;
+    __syncthreads();
     bool wide = false;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256) {
-        const int32_t v = P[e];
-        if (v == 0) continue;
+    auto mark = [&](int32_t v) {
+        if (v == 0) return;
         if (v >= RANK_CAP || v < 0) {
             wide = true;
-            continue;
+            return;
         }
         const uint32_t bit = 1u << (v & 31);
-        uint32_t *word = bitmap + (v >> 5);
-        if (!(*word & bit)) atomicOr(word, bit);  // most values repeat: read before the atomic
+        if (v < RANK_LDS_BITS) {
+            if (!(local[v >> 5] & bit)) atomicOr(&local[v >> 5], bit);
+        } else {
+            uint32_t *word = bitmap + (v >> 5);
+            if (!(*word & bit)) atomicOr(word, bit);
+        }
+    };
+    // count is a multiple of 4 and P 16-byte aligned: four 16-byte loads in
+    // flight per thread and step
+    const int4 *P4 = reinterpret_cast<const int4 *>(P);
+    const int64_t n4 = count / 4, stride = (int64_t)gridDim.x * 256;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n4; e += 4 * stride) {
+        int4 q[4];
+        for (int u = 0; u < 4; ++u) q[u] = e + u * stride < n4 ? P4[e + u * stride] : make_int4(0, 0, 0, 0);
+        for (int u = 0; u < 4; ++u) {
+            mark(q[u].x);
+            mark(q[u].y);
+            mark(q[u].z);
+            mark(q[u].w);
+        }
     }
     if (wide) flags[0] = 1;
+    __syncthreads();
+    for (int i = threadIdx.x; i < RANK_LDS_WORDS; i += 256)
+        if (local[i]) atomicOr(&bitmap[i], local[i]);
 }
 
 // Per block of RANK_BLOCK words: number of marked values.
@@ -490,31 +525,39 @@ __global__ __launch_bounds__(256) void k_rank_words(const uint32_t *__restrict__
     }
 }
 
-// P16 = rank of P (0 for 0).
+// P16 = rank of P (0 for 0); four elements per thread (count is a multiple
+// of 4, both arrays 16-byte aligned).
 __global__ __launch_bounds__(256) void k_rank_apply(const int32_t *__restrict__ P, int64_t count,
                                                     const uint32_t *__restrict__ bitmap,
                                                     const uint32_t *__restrict__ word_rank,
                                                     uint16_t *__restrict__ P16) {
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256) {
-        const int32_t v = P[e];
-        uint32_t r = 0;
-        if (v != 0) {
-            const uint32_t below = bitmap[v >> 5] & ((1u << (v & 31)) - 1u);
-            r = word_rank[v >> 5] + __popc(below) + 1u;
-        }
-        P16[e] = (uint16_t)r;
+    auto rank_of = [&](int32_t v) -> uint16_t {
+        if (v == 0) return 0;
+        const uint32_t below = bitmap[v >> 5] & ((1u << (v & 31)) - 1u);
+        return (uint16_t)(word_rank[v >> 5] + __popc(below) + 1u);
+    };
+    const int4 *P4 = reinterpret_cast<const int4 *>(P);
+    ushort4 *Q4 = reinterpret_cast<ushort4 *>(P16);
+    const int64_t n4 = count / 4;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n4; e += (int64_t)gridDim.x * 256) {
+        const int4 q = P4[e];
+        Q4[e] = make_ushort4(rank_of(q.x), rank_of(q.y), rank_of(q.z), rank_of(q.w));
     }
 }
 
-// p[i][j] = value_of[P16[i][j]] for i != j, 0 on the diagonal.
+// p[i][j] = value_of[P16[i][j]] for i != j, 0 on the diagonal; four
+// columns per thread (ld is a multiple of 64).
 __global__ __launch_bounds__(256) void k_rank_store(const uint16_t *__restrict__ P16, int64_t ld, int32_t m,
                                                     const int32_t *__restrict__ value_of, int32_t *__restrict__ p,
                                                     int64_t ldp) {
-    const int32_t col_blocks = (m + 255) / 256;
+    const int32_t col_blocks = (m + 1023) / 1024;
     const int32_t i = blockIdx.x / col_blocks;
-    const int32_t j = (blockIdx.x % col_blocks) * 256 + threadIdx.x;
-    if (j >= m) return;
-    p[(int64_t)i * ldp + j] = i == j ? 0 : value_of[P16[(int64_t)i * ld + j]];
+    const int32_t j0 = (blockIdx.x % col_blocks) * 1024 + threadIdx.x * 4;
+    if (j0 >= m) return;
+    const ushort4 r = *reinterpret_cast<const ushort4 *>(P16 + (int64_t)i * ld + j0);
+    const uint16_t rr[4] = {r.x, r.y, r.z, r.w};
+    int32_t *row = p + (int64_t)i * ldp;
+    for (int u = 0; u < 4 && j0 + u < m; ++u) row[j0 + u] = i == j0 + u ? 0 : value_of[rr[u]];
 }
 
 // BI: tile of the int32 closure (when the values cannot be ranked); BU: tile
@@ -550,7 +593,9 @@ int run_closure_ranked(schulze_ctx *ctx, hipStream_t s, const int32_t *d, int64_
     if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(value_of), 1, 0u)) != SCHULZE_OK) return rc;
     if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(flags), 2, 0u)) != SCHULZE_OK) return rc;
     const unsigned egrid = (unsigned)std::min<int64_t>(ceil_div(count, 256), (int64_t)ctx->num_cus * 16);
-    SCHULZE_LAUNCH(ctx, K_RANK, s, k_rank_mark<<<dim3(egrid), dim3(256), 0, s>>>(P, count, bitmap, flags));
+    // two marking workgroups per CU: each merges its LDS bitmap once
+    const unsigned mgrid = (unsigned)std::min<int64_t>(ceil_div(count, 1024), (int64_t)ctx->num_cus * 2);
+    SCHULZE_LAUNCH(ctx, K_RANK, s, k_rank_mark<<<dim3(mgrid), dim3(256), 0, s>>>(P, count, bitmap, flags));
     SCHULZE_LAUNCH(ctx, K_RANK, s, k_rank_blocks<<<dim3(RANK_BLOCKS), dim3(256), 0, s>>>(bitmap, block_off));
     SCHULZE_LAUNCH(ctx, K_RANK, s, k_rank_top<<<dim3(1), dim3(256), 0, s>>>(block_off, flags));
     int32_t host_flags[2] = {0, 0};
@@ -567,7 +612,7 @@ int run_closure_ranked(schulze_ctx *ctx, hipStream_t s, const int32_t *d, int64_
                    k_rank_words<<<dim3(RANK_BLOCKS), dim3(256), 0, s>>>(bitmap, block_off, word_rank, value_of));
     SCHULZE_LAUNCH(ctx, K_RANK, s, k_rank_apply<<<dim3(egrid), dim3(256), 0, s>>>(P, count, bitmap, word_rank, P16));
     if ((rc = close_padded<uint16_t, BU>(ctx, s, P16, ld, mp / BU)) != SCHULZE_OK) return rc;
-    dim3 sgrid((unsigned)(ceil_div(m, 256) * m));
+    dim3 sgrid((unsigned)(ceil_div(m, 1024) * m));
     SCHULZE_LAUNCH(ctx, K_RANK, s, k_rank_store<<<sgrid, dim3(256), 0, s>>>(P16, ld, m, value_of, p, ldp));
     return SCHULZE_OK;
 }

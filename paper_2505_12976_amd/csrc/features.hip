@@ -30,6 +30,9 @@ struct RawStats {
     long long *min_marg, *max_marg;
 };
 
+// Partial statistics of 64 candidates (rows X0 ..) over the column blocks
+// Y0 = 64 (blockIdx.y + k gridDim.y); slice s = blockIdx.y writes entry
+// s * m + x of every array of st.
 template <typename E>
 __global__ __launch_bounds__(256) void k_feature_rows(const E *__restrict__ d, int64_t ldd, int32_t m, int mode,
                                                       RawStats st) {
@@ -41,7 +44,7 @@ __global__ __launch_bounds__(256) void k_feature_rows(const E *__restrict__ d, i
     int32_t cope = 0, ties = 0, mx_out = 0, mx_in = 0;
     unsigned long long borda = 0, s_out = 0, s_in = 0;
     long long mn = LLONG_MAX, mxm = LLONG_MIN;
-    for (int32_t Y0 = 0; Y0 < m; Y0 += 64) {
+    for (int32_t Y0 = 64 * blockIdx.y; Y0 < m; Y0 += 64 * gridDim.y) {
         __syncthreads();
         for (int e = threadIdx.x; e < 64 * 64; e += 256) {
             const int rr = e >> 6, cc = e & 63;
@@ -81,16 +84,47 @@ __global__ __launch_bounds__(256) void k_feature_rows(const E *__restrict__ d, i
         mxm = max(mxm, (long long)__shfl_xor(mxm, off));
     }
     if (part == 0 && x < m) {
-        st.cope[x] = cope;
-        st.ties[x] = ties;
-        st.borda[x] = borda;
-        st.sum_out[x] = s_out;
-        st.sum_in[x] = s_in;
-        st.max_out[x] = mx_out;
-        st.max_in[x] = mx_in;
-        st.min_marg[x] = m > 1 ? mn : 0;
-        st.max_marg[x] = m > 1 ? mxm : 0;
+        const int64_t q = (int64_t)blockIdx.y * m + x;
+        st.cope[q] = cope;
+        st.ties[q] = ties;
+        st.borda[q] = borda;
+        st.sum_out[q] = s_out;
+        st.sum_in[q] = s_in;
+        st.max_out[q] = mx_out;
+        st.max_in[q] = mx_in;
+        st.min_marg[q] = mn;
+        st.max_marg[q] = mxm;
     }
+}
+
+// Combine the S slices' partial statistics of each candidate.
+__global__ __launch_bounds__(256) void k_feature_reduce(int32_t m, int32_t S, RawStats part, RawStats st) {
+    const int32_t x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= m) return;
+    int32_t cope = 0, ties = 0, mx_out = 0, mx_in = 0;
+    unsigned long long borda = 0, s_out = 0, s_in = 0;
+    long long mn = LLONG_MAX, mxm = LLONG_MIN;
+    for (int32_t sl = 0; sl < S; ++sl) {
+        const int64_t q = (int64_t)sl * m + x;
+        cope += part.cope[q];
+        ties += part.ties[q];
+        borda += part.borda[q];
+        s_out += part.sum_out[q];
+        s_in += part.sum_in[q];
+        mx_out = max(mx_out, part.max_out[q]);
+        mx_in = max(mx_in, part.max_in[q]);
+        mn = min(mn, part.min_marg[q]);
+        mxm = max(mxm, part.max_marg[q]);
+    }
+    st.cope[x] = cope;
+    st.ties[x] = ties;
+    st.borda[x] = borda;
+    st.sum_out[x] = s_out;
+    st.sum_in[x] = s_in;
+    st.max_out[x] = mx_out;
+    st.max_in[x] = mx_in;
+    st.min_marg[x] = m > 1 ? mn : 0;
+    st.max_marg[x] = m > 1 ? mxm : 0;
 }
 
 // Normalise: one workgroup finds the maxima, every thread writes rows.
@@ -138,13 +172,9 @@ __global__ __launch_bounds__(256) void k_feature_norm(int32_t m, RawStats st, fl
     }
 }
 
-template <typename E>
-int run_features(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32_t m, int mode, float n_voters,
-                 float *feat) {
-    const size_t i4 = round_up(sizeof(int32_t) * (size_t)m, 256), i8 = round_up(8 * (size_t)m, 256);
-    int rc = ws_reserve(ctx, WS_FEATURES, 4 * i4 + 5 * i8);
-    if (rc != SCHULZE_OK) return rc;
-    char *p = static_cast<char *>(ctx->ws[WS_FEATURES]);
+// Carve the nine statistic arrays of n entries each out of p.
+RawStats carve(char *p, size_t n, size_t *bytes) {
+    const size_t i4 = round_up(sizeof(int32_t) * n, 256), i8 = round_up(8 * n, 256);
     RawStats st;
     st.cope = reinterpret_cast<int32_t *>(p);
     st.ties = reinterpret_cast<int32_t *>(p + i4);
@@ -155,8 +185,28 @@ int run_features(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32
     st.sum_in = reinterpret_cast<unsigned long long *>(p + 4 * i4 + 2 * i8);
     st.min_marg = reinterpret_cast<long long *>(p + 4 * i4 + 3 * i8);
     st.max_marg = reinterpret_cast<long long *>(p + 4 * i4 + 4 * i8);
+    *bytes = 4 * i4 + 5 * i8;
+    return st;
+}
+
+template <typename E>
+int run_features(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32_t m, int mode, float n_voters,
+                 float *feat) {
+    // column slices per block of 64 rows: enough workgroups to keep HBM busy
+    const int32_t nbx = (int32_t)ceil_div(m, 64);
+    const int32_t S = std::max(1, std::min<int32_t>(nbx, (int32_t)ceil_div(16 * (int64_t)ctx->num_cus, nbx)));
+    size_t fin_bytes = 0, part_bytes = 0;
+    (void)carve(nullptr, (size_t)m, &fin_bytes);
+    (void)carve(nullptr, (size_t)m * S, &part_bytes);
+    int rc = ws_reserve(ctx, WS_FEATURES, fin_bytes + part_bytes);
+    if (rc != SCHULZE_OK) return rc;
+    char *p = static_cast<char *>(ctx->ws[WS_FEATURES]);
+    RawStats st = carve(p, (size_t)m, &fin_bytes);
+    RawStats part = carve(p + fin_bytes, (size_t)m * S, &part_bytes);
     SCHULZE_LAUNCH(ctx, K_FEATURES, s,
-                   k_feature_rows<E><<<dim3((unsigned)ceil_div(m, 64)), dim3(256), 0, s>>>(d, ldd, m, mode, st));
+                   k_feature_rows<E><<<dim3((unsigned)nbx, (unsigned)S), dim3(256), 0, s>>>(d, ldd, m, mode, part));
+    SCHULZE_LAUNCH(ctx, K_FEATURES, s,
+                   k_feature_reduce<<<dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s>>>(m, S, part, st));
     SCHULZE_LAUNCH(ctx, K_FEATURES, s, k_feature_norm<<<dim3(1), dim3(256), 0, s>>>(m, st, n_voters, feat));
     return SCHULZE_OK;
 }

@@ -5,13 +5,15 @@
 
 namespace {
 
-// beaten_by[x] += #{y in tile : p[y][x] > p[x][y]} for one 64 x 64 tile of
-// (y, x) pairs; the transposed tile comes through LDS.
+// beaten_by[x] += #{y : p[y][x] > p[x][y]} over one pair of 64 x 64 blocks
+// of candidates (X, Y), X <= Y: both directions need the same two tiles of
+// p, so p is read once.
 template <typename E>
 __global__ __launch_bounds__(256) void k_beaten_by(const E *__restrict__ p, int64_t ldp, int32_t m,
                                                    int32_t *__restrict__ beaten) {
     __shared__ E py[64][65];  // py[a][b] = p[Y0 + a][X0 + b]
     __shared__ E px[64][65];  // px[a][b] = p[X0 + a][Y0 + b]
+    if (blockIdx.x > blockIdx.y) return;
     const int32_t X0 = blockIdx.x * 64, Y0 = blockIdx.y * 64;
     for (int e = threadIdx.x; e < 64 * 64; e += 256) {
         const int a = e >> 6, b = e & 63;
@@ -19,10 +21,14 @@ __global__ __launch_bounds__(256) void k_beaten_by(const E *__restrict__ p, int6
         px[a][b] = (X0 + a < m && Y0 + b < m) ? p[(int64_t)(X0 + a) * ldp + Y0 + b] : (E)0;
     }
     __syncthreads();
-    const int xl = threadIdx.x & 63, part = threadIdx.x >> 6;
-    int32_t cnt = 0;
-    for (int yl = part * 16; yl < part * 16 + 16; ++yl) cnt += py[yl][xl] > px[xl][yl] ? 1 : 0;
-    if (cnt && X0 + xl < m) atomicAdd(&beaten[X0 + xl], cnt);
+    const int l = threadIdx.x & 63, part = threadIdx.x >> 6;
+    int32_t cx = 0, cy = 0;
+    for (int o = part * 16; o < part * 16 + 16; ++o) {
+        cx += py[o][l] > px[l][o] ? 1 : 0;  // y = Y0 + o beats x = X0 + l
+        cy += px[o][l] > py[l][o] ? 1 : 0;  // x = X0 + o beats y = Y0 + l
+    }
+    if (cx && X0 + l < m) atomicAdd(&beaten[X0 + l], cx);
+    if (X0 != Y0 && cy && Y0 + l < m) atomicAdd(&beaten[Y0 + l], cy);
 }
 
 __global__ __launch_bounds__(256) void k_winners(const int32_t *__restrict__ beaten, int32_t m,

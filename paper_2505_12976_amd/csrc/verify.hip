@@ -28,13 +28,15 @@ __device__ inline E max_value() {
 
 // ------------------------------------------------------------------ weights
 // w[i][j] and wt[j][i] = edge weight of (i, j) from d (winning votes or
-// margin), one 64 x 64 block of (i, j) and its transpose per workgroup.
+// margin).  A workgroup takes the 64 x 64 blocks (I, J) and (J, I), I <= J,
+// of both outputs: they need the same two blocks of d, read once.
 template <typename E>
 __global__ __launch_bounds__(256) void k_weights_pair(const E *__restrict__ d, int64_t ldd, int32_t m, int mode,
                                                       E *__restrict__ w, int64_t ldw, E *__restrict__ wt,
                                                       int64_t ldwt) {
     __shared__ E a[64][65];  // a[r][c] = d[I0 + r][J0 + c]
     __shared__ E b[64][65];  // b[r][c] = d[J0 + r][I0 + c]
+    if (blockIdx.y > blockIdx.x) return;
     const int32_t I0 = blockIdx.y * 64, J0 = blockIdx.x * 64;
     for (int e = threadIdx.x; e < 64 * 64; e += 256) {
         const int r = e >> 6, c = e & 63;
@@ -42,17 +44,21 @@ __global__ __launch_bounds__(256) void k_weights_pair(const E *__restrict__ d, i
         b[r][c] = (J0 + r < m && I0 + c < m) ? d[(int64_t)(J0 + r) * ldd + I0 + c] : (E)0;
     }
     __syncthreads();
-    auto weight = [&](E x, E y, bool diag) -> E {
+    auto weight = [&](E x, E y, bool diag) -> E {  // weight of edge (i, j) given d[i][j] = x, d[j][i] = y
         if (diag || x <= y) return (E)0;
         return mode == SCHULZE_MARGIN ? (E)(x - y) : x;
     };
+    const bool mirror = I0 != J0;
     for (int e = threadIdx.x; e < 64 * 64; e += 256) {
         const int r = e >> 6, c = e & 63;
-        const int32_t i = I0 + r, j = J0 + c;
-        if (w && i < m && j < m) w[(int64_t)i * ldw + j] = weight(a[r][c], b[c][r], i == j);
-        // wt row (J0 + r), column (I0 + c) holds the weight of edge (I0 + c, J0 + r)
-        const int32_t ti = J0 + r, tj = I0 + c;
-        if (wt && ti < m && tj < m) wt[(int64_t)ti * ldwt + tj] = weight(a[c][r], b[r][c], ti == tj);
+        // edges (I0 + r, J0 + c) into w, and (I0 + c, J0 + r) into wt row J0 + r
+        if (w && I0 + r < m && J0 + c < m) w[(int64_t)(I0 + r) * ldw + J0 + c] = weight(a[r][c], b[c][r], I0 + r == J0 + c);
+        if (wt && J0 + r < m && I0 + c < m)
+            wt[(int64_t)(J0 + r) * ldwt + I0 + c] = weight(a[c][r], b[r][c], I0 + c == J0 + r);
+        if (!mirror) continue;
+        // edges (J0 + r, I0 + c) into w, and (J0 + c, I0 + r) into wt row I0 + r
+        if (w && J0 + r < m && I0 + c < m) w[(int64_t)(J0 + r) * ldw + I0 + c] = weight(b[r][c], a[c][r], false);
+        if (wt && I0 + r < m && J0 + c < m) wt[(int64_t)(I0 + r) * ldwt + J0 + c] = weight(b[c][r], a[r][c], false);
     }
 }
 

@@ -61,7 +61,7 @@ def test_null_handles_are_rejected_on_the_host():
     assert lib.schulze_batch_plan(None, ctypes.byref(el), 1, sz.U16, 0, None, ctypes.byref(h)) == sz.EINVAL
     assert lib.schulze_batch_plan(None, ctypes.byref(el), 1, sz.U16, 0, None, None) == sz.EINVAL
     assert not h.value
-    assert lib.schulze_batch_run(None, None, None, None, None, None, None, None, None, None, 0) == sz.EINVAL
+    assert lib.schulze_batch_run(None, None, None, None, None, None, None, None, None, None, None, 0) == sz.EINVAL
     assert lib.schulze_batch_set_closure(None, 16, 1, 32, 0) == sz.EINVAL
     v = ctypes.c_int32()
     assert lib.schulze_batch_get_closure(None, 16, 32, ctypes.byref(v)) == sz.EINVAL

@@ -204,7 +204,19 @@ def test_batch_int32_closure_for_large_electorates(ctx):
     log("[case] batch int32 values")
     packed, plan, outs = run_batch(ctx, els)
     assert ctx.device_error() == 0
-    assert_matches(packed, outs, expected(els, "winning_votes"), "int32")
+    want = expected(els, "winning_votes")
+    assert_matches(packed, outs, want, "int32")
+    plan.destroy()
+    # top-k levels on int32 values too
+    import torch
+    plan = ctx.batch_plan(packed.elections, "u16", "winning_votes", topk=20)
+    dev = torch.device("cuda", 0)
+    level = torch.full((packed.vec_elems,), -7, dtype=torch.int32, device=dev)
+    ctx.batch_run(plan, torch.from_numpy(packed.ballots).to(dev), outs["d"], outs["is_winner"], level=level)
+    torch.cuda.synchronize()
+    assert ctx.device_error() == 0
+    for e, w in enumerate(want):
+        np.testing.assert_array_equal(packed.vec(level, e).cpu().numpy(), oracle.topk_levels(w["w"], 20))
     plan.destroy()
 
 
@@ -337,3 +349,46 @@ def test_batch_full_workload_sampled():
         plan.destroy()
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("topk", [1, 3, 1000])
+@pytest.mark.parametrize("mode", ["winning_votes", "margin"])
+def test_batch_topk_levels(ctx, topk, mode):
+    """Top-k levels by iterated winner removal, per election, equal the
+    oracle's; the other outputs are unchanged; graph replays agree."""
+    import torch
+    els = mixed_elections(3011)
+    packed = pack([b for b, _ in els], [m for _, m in els])
+    plan = ctx.batch_plan(packed.elections, "u16", mode, topk=topk)
+    dev = torch.device("cuda", 0)
+    ballots = torch.from_numpy(packed.ballots).to(dev)
+    outs = alloc_outputs(packed, dev)
+    level = torch.full((packed.vec_elems,), -7, dtype=torch.int32, device=dev)
+    want = expected(els, mode)
+    for graph in (False, True, True):
+        log(f"[case] batch topk={topk} mode={mode} graph={graph}")
+        level.fill_(-7)
+        ctx.batch_run(plan, ballots, outs["d"], outs["is_winner"], p=outs["p"], n_winners=outs["n_winners"],
+                      beaten_by=outs["beaten_by"], order=outs["order"], graph=graph, level=level)
+        torch.cuda.synchronize()
+        assert ctx.device_error() == 0
+        assert_matches(packed, outs, want, f"topk={topk}")
+        for e, w in enumerate(want):
+            lv = packed.vec(level, e).cpu().numpy()
+            ref = oracle.topk_levels(w["w"], topk)
+            np.testing.assert_array_equal(lv, ref, err_msg=f"topk={topk} election {e} m={packed.elections[e][3]}")
+    plan.destroy()
+
+
+def test_batch_level_needs_topk_plan(ctx):
+    import torch
+    import paper_2505_12976_amd as sz
+    els = mixed_elections(3013)[:3]
+    packed = pack([b for b, _ in els], [m for _, m in els])
+    plan = ctx.batch_plan(packed.elections, "u16")
+    dev = torch.device("cuda", 0)
+    outs = alloc_outputs(packed, dev)
+    level = torch.zeros(packed.vec_elems, dtype=torch.int32, device=dev)
+    with pytest.raises(sz.SchulzeError):
+        ctx.batch_run(plan, torch.from_numpy(packed.ballots).to(dev), outs["d"], outs["is_winner"], level=level)
+    plan.destroy()

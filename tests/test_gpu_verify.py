@@ -36,6 +36,32 @@ def profile(m, seed):
     return workload.pl_zipf(seed, 501, m, 1.0, min(m, 12))
 
 
+@pytest.mark.parametrize("m", [63, 200, 1100])
+@pytest.mark.parametrize("dtype", ["u16", "i32"])
+def test_weights_strided_and_single_output(ctx, m, dtype):
+    """d as a view with row pitch m + 7; w alone and w^T alone."""
+    import torch
+    b = profile(m, 11 + m)
+    dn = oracle.pairwise(b, m)
+    wn = oracle.weights(dn, oracle.WINNING_VOTES)
+    npdt = np.uint16 if dtype == "u16" else np.int32
+    big = np.zeros((m, m + 7), dtype=npdt)
+    big[:, :m] = dn.astype(npdt)
+    d = torch.from_numpy(big).cuda()[:, :m]
+    assert d.stride(0) == m + 7
+    w, wt = ctx.weights(d, "winning_votes")
+    assert (to_np(w) == wn).all() and (to_np(wt) == wn.T).all()
+    w_only, none_t = ctx.weights(d, "winning_votes", transposed=False)
+    assert none_t is None and (to_np(w_only) == wn).all()
+    none_w, wt_only = ctx.weights(d, "winning_votes", direct=False)
+    assert none_w is None and (to_np(wt_only) == wn.T).all()
+    p = ctx.closure(d)
+    assert (to_np(p) == oracle.closure(wn)).all()
+    beaten, win, _ = oracle.rank(oracle.closure(wn))
+    order, beaten_gpu = ctx.ranking(p)
+    assert (to_np(beaten_gpu) == beaten).all()
+
+
 @pytest.mark.parametrize("m", [1, 2, 5, 64, 65, 300, 1000])
 @pytest.mark.parametrize("dtype,mode", [("u16", "winning_votes"), ("i32", "margin")])
 def test_weights_and_widest(ctx, m, dtype, mode):
