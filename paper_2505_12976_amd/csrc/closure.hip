@@ -37,6 +37,7 @@
 // columns to a multiple of B; padded vertices have no edges and change
 // nothing.
 #include "fw_tiles.h"
+#include "tile_io.h"
 
 
 namespace {
@@ -49,31 +50,22 @@ using namespace fw;
 // need the same two blocks of d, so every count is read once.
 template <typename E>
 __global__ __launch_bounds__(256) void k_weights(const E *__restrict__ d, int64_t ldd, int32_t m, int mode,
-                                                 E *__restrict__ P, int64_t ld, int32_t mp) {
+                                                 E *__restrict__ P, int64_t ld, int32_t mp, int dvec) {
     __shared__ E a[64][65];  // a[r][c] = d[I0 + r][J0 + c]
     __shared__ E b[64][65];  // b[r][c] = d[J0 + r][I0 + c]
     if (blockIdx.y > blockIdx.x) return;
     const int32_t I0 = blockIdx.y * 64, J0 = blockIdx.x * 64;
-    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-        const int r = e >> 6, c = e & 63;
-        a[r][c] = (I0 + r < m && J0 + c < m) ? d[(int64_t)(I0 + r) * ldd + J0 + c] : (E)0;
-        b[r][c] = (J0 + r < m && I0 + c < m) ? d[(int64_t)(J0 + r) * ldd + I0 + c] : (E)0;
-    }
+    tio::load<E>(a, d, ldd, I0, J0, m, m, dvec != 0);
+    tio::load<E>(b, d, ldd, J0, I0, m, m, dvec != 0);
     __syncthreads();
     auto weight = [&](E x, E y, bool diag) -> E {  // edge weight given d[i][j] = x, d[j][i] = y
         if (diag || x <= y) return (E)0;
         return mode == SCHULZE_MARGIN ? (E)(x - y) : x;
     };
-    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-        const int r = e >> 6, c = e & 63;
-        int32_t i = I0 + r, j = J0 + c;
-        if (i < mp && j < mp) P[(int64_t)i * ld + j] = weight(a[r][c], b[c][r], i == j);
-        if (I0 != J0) {  // the mirrored tile (J, I)
-            i = J0 + r;
-            j = I0 + c;
-            if (i < mp && j < mp) P[(int64_t)i * ld + j] = weight(b[r][c], a[c][r], false);
-        }
-    }
+    // the workspace matrix is 16-byte aligned with a pitch that is a multiple of 64
+    tio::store<E>(P, ld, I0, J0, mp, mp, true, [&](int r, int c) { return weight(a[r][c], b[c][r], I0 + r == J0 + c); });
+    if (I0 != J0)  // the mirrored tile (J, I)
+        tio::store<E>(P, ld, J0, I0, mp, mp, true, [&](int r, int c) { return weight(b[r][c], a[c][r], false); });
 }
 
 // p[i][j] = P[i][j] for i != j, 0 on the diagonal.
@@ -381,7 +373,8 @@ int run_closure(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32_
     if (rc != SCHULZE_OK) return rc;
     E *P = static_cast<E *>(ctx->ws[WS_CLOSURE]);
     dim3 wgrid((unsigned)ceil_div(mp, 64), (unsigned)ceil_div(mp, 64));
-    SCHULZE_LAUNCH(ctx, K_WEIGHTS, s, k_weights<E><<<wgrid, dim3(256), 0, s>>>(d, ldd, m, mode, P, ld, mp));
+    SCHULZE_LAUNCH(ctx, K_WEIGHTS, s, k_weights<E><<<wgrid, dim3(256), 0, s>>>(d, ldd, m, mode, P, ld, mp,
+                                                                          tio::vec_ok<E>(d, ldd) ? 1 : 0));
     if ((rc = close_padded<E, B>(ctx, s, P, ld, nb)) != SCHULZE_OK) return rc;
     dim3 sgrid((unsigned)(ceil_div(m, 256) * m));
     SCHULZE_LAUNCH(ctx, K_FW_STORE, s, k_fw_store<E><<<sgrid, dim3(256), 0, s>>>(P, ld, m, p, ldp));
@@ -574,7 +567,8 @@ int run_closure_ranked(schulze_ctx *ctx, hipStream_t s, const int32_t *d, int64_
     if (rc != SCHULZE_OK) return rc;
     int32_t *P = static_cast<int32_t *>(ctx->ws[WS_CLOSURE]);
     dim3 wgrid((unsigned)ceil_div(mp, 64), (unsigned)ceil_div(mp, 64));
-    SCHULZE_LAUNCH(ctx, K_WEIGHTS, s, k_weights<int32_t><<<wgrid, dim3(256), 0, s>>>(d, ldd, m, mode, P, ld, mp));
+    SCHULZE_LAUNCH(ctx, K_WEIGHTS, s, k_weights<int32_t><<<wgrid, dim3(256), 0, s>>>(d, ldd, m, mode, P, ld, mp,
+                                                                                tio::vec_ok<int32_t>(d, ldd) ? 1 : 0));
 
     // rank tables: bitmap | word ranks | block offsets | value table | flags, then the uint16 matrix
     const size_t bm = sizeof(uint32_t) * RANK_WORDS;

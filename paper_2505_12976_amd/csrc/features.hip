@@ -18,6 +18,7 @@
 //   15 1 (bias input)
 // n is the number of voters (any positive scale works; it keeps features O(1)).
 #include "internal.h"
+#include "tile_io.h"
 
 namespace {
 
@@ -35,7 +36,7 @@ struct RawStats {
 // s * m + x of every array of st.
 template <typename E>
 __global__ __launch_bounds__(256) void k_feature_rows(const E *__restrict__ d, int64_t ldd, int32_t m, int mode,
-                                                      RawStats st) {
+                                                      RawStats st, int vec) {
     __shared__ E a[64][65];  // a[r][c] = d[X0 + r][Y0 + c]
     __shared__ E b[64][65];  // b[r][c] = d[Y0 + r][X0 + c]
     const int32_t X0 = blockIdx.x * 64;
@@ -46,11 +47,8 @@ __global__ __launch_bounds__(256) void k_feature_rows(const E *__restrict__ d, i
     long long mn = LLONG_MAX, mxm = LLONG_MIN;
     for (int32_t Y0 = 64 * blockIdx.y; Y0 < m; Y0 += 64 * gridDim.y) {
         __syncthreads();
-        for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-            const int rr = e >> 6, cc = e & 63;
-            a[rr][cc] = (X0 + rr < m && Y0 + cc < m) ? d[(int64_t)(X0 + rr) * ldd + Y0 + cc] : (E)0;
-            b[rr][cc] = (Y0 + rr < m && X0 + cc < m) ? d[(int64_t)(Y0 + rr) * ldd + X0 + cc] : (E)0;
-        }
+        tio::load<E>(a, d, ldd, X0, Y0, m, m, vec != 0);
+        tio::load<E>(b, d, ldd, Y0, X0, m, m, vec != 0);
         __syncthreads();
         if (x >= m) continue;
         for (int c = part * 16; c < part * 16 + 16; ++c) {
@@ -204,7 +202,8 @@ int run_features(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32
     RawStats st = carve(p, (size_t)m, &fin_bytes);
     RawStats part = carve(p + fin_bytes, (size_t)m * S, &part_bytes);
     SCHULZE_LAUNCH(ctx, K_FEATURES, s,
-                   k_feature_rows<E><<<dim3((unsigned)nbx, (unsigned)S), dim3(256), 0, s>>>(d, ldd, m, mode, part));
+                   k_feature_rows<E><<<dim3((unsigned)nbx, (unsigned)S), dim3(256), 0, s>>>(
+                       d, ldd, m, mode, part, tio::vec_ok<E>(d, ldd) ? 1 : 0));
     SCHULZE_LAUNCH(ctx, K_FEATURES, s,
                    k_feature_reduce<<<dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s>>>(m, S, part, st));
     SCHULZE_LAUNCH(ctx, K_FEATURES, s, k_feature_norm<<<dim3(1), dim3(256), 0, s>>>(m, st, n_voters, feat));

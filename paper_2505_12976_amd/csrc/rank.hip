@@ -2,6 +2,7 @@
 // p[y][x] > p[x][y]; x is a Schulze winner iff nobody beats it; the ranking
 // orders candidates by how many candidates beat them, then by id.
 #include "internal.h"
+#include "tile_io.h"
 
 namespace {
 
@@ -10,16 +11,13 @@ namespace {
 // p, so p is read once.
 template <typename E>
 __global__ __launch_bounds__(256) void k_beaten_by(const E *__restrict__ p, int64_t ldp, int32_t m,
-                                                   int32_t *__restrict__ beaten) {
+                                                   int32_t *__restrict__ beaten, int vec) {
     __shared__ E py[64][65];  // py[a][b] = p[Y0 + a][X0 + b]
     __shared__ E px[64][65];  // px[a][b] = p[X0 + a][Y0 + b]
     if (blockIdx.x > blockIdx.y) return;
     const int32_t X0 = blockIdx.x * 64, Y0 = blockIdx.y * 64;
-    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-        const int a = e >> 6, b = e & 63;
-        py[a][b] = (Y0 + a < m && X0 + b < m) ? p[(int64_t)(Y0 + a) * ldp + X0 + b] : (E)0;
-        px[a][b] = (X0 + a < m && Y0 + b < m) ? p[(int64_t)(X0 + a) * ldp + Y0 + b] : (E)0;
-    }
+    tio::load<E>(py, p, ldp, Y0, X0, m, m, vec != 0);
+    tio::load<E>(px, p, ldp, X0, Y0, m, m, vec != 0);
     __syncthreads();
     const int l = threadIdx.x & 63, part = threadIdx.x >> 6;
     int32_t cx = 0, cy = 0;
@@ -68,7 +66,8 @@ int beaten_by(schulze_ctx *ctx, hipStream_t s, const E *p, int64_t ldp, int32_t 
     int rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(beaten), (size_t)m, 0u);
     if (rc != SCHULZE_OK) return rc;
     dim3 grid((unsigned)ceil_div(m, 64), (unsigned)ceil_div(m, 64));
-    SCHULZE_LAUNCH(ctx, K_BEATEN_BY, s, k_beaten_by<E><<<grid, dim3(256), 0, s>>>(p, ldp, m, beaten));
+    SCHULZE_LAUNCH(ctx, K_BEATEN_BY, s, k_beaten_by<E><<<grid, dim3(256), 0, s>>>(p, ldp, m, beaten,
+                                                                                tio::vec_ok<E>(p, ldp) ? 1 : 0));
     return SCHULZE_OK;
 }
 

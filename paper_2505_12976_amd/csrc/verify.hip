@@ -15,6 +15,7 @@
 // One persistent cooperative launch runs all sweeps; workgroups own column
 // ranges and meet at a grid barrier between sweeps.
 #include "grid.h"
+#include "tile_io.h"
 
 namespace {
 
@@ -33,33 +34,26 @@ __device__ inline E max_value() {
 template <typename E>
 __global__ __launch_bounds__(256) void k_weights_pair(const E *__restrict__ d, int64_t ldd, int32_t m, int mode,
                                                       E *__restrict__ w, int64_t ldw, E *__restrict__ wt,
-                                                      int64_t ldwt) {
+                                                      int64_t ldwt, int vec) {
     __shared__ E a[64][65];  // a[r][c] = d[I0 + r][J0 + c]
     __shared__ E b[64][65];  // b[r][c] = d[J0 + r][I0 + c]
     if (blockIdx.y > blockIdx.x) return;
     const int32_t I0 = blockIdx.y * 64, J0 = blockIdx.x * 64;
-    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-        const int r = e >> 6, c = e & 63;
-        a[r][c] = (I0 + r < m && J0 + c < m) ? d[(int64_t)(I0 + r) * ldd + J0 + c] : (E)0;
-        b[r][c] = (J0 + r < m && I0 + c < m) ? d[(int64_t)(J0 + r) * ldd + I0 + c] : (E)0;
-    }
+    tio::load<E>(a, d, ldd, I0, J0, m, m, vec & 1);
+    tio::load<E>(b, d, ldd, J0, I0, m, m, vec & 1);
     __syncthreads();
     auto weight = [&](E x, E y, bool diag) -> E {  // weight of edge (i, j) given d[i][j] = x, d[j][i] = y
         if (diag || x <= y) return (E)0;
         return mode == SCHULZE_MARGIN ? (E)(x - y) : x;
     };
-    const bool mirror = I0 != J0;
-    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-        const int r = e >> 6, c = e & 63;
-        // edges (I0 + r, J0 + c) into w, and (I0 + c, J0 + r) into wt row J0 + r
-        if (w && I0 + r < m && J0 + c < m) w[(int64_t)(I0 + r) * ldw + J0 + c] = weight(a[r][c], b[c][r], I0 + r == J0 + c);
-        if (wt && J0 + r < m && I0 + c < m)
-            wt[(int64_t)(J0 + r) * ldwt + I0 + c] = weight(a[c][r], b[r][c], I0 + c == J0 + r);
-        if (!mirror) continue;
-        // edges (J0 + r, I0 + c) into w, and (J0 + c, I0 + r) into wt row I0 + r
-        if (w && J0 + r < m && I0 + c < m) w[(int64_t)(J0 + r) * ldw + I0 + c] = weight(b[r][c], a[c][r], false);
-        if (wt && I0 + r < m && J0 + c < m) wt[(int64_t)(I0 + r) * ldwt + J0 + c] = weight(b[c][r], a[r][c], false);
-    }
+    const bool wv = (vec & 2) != 0, wtv = (vec & 4) != 0;
+    // edges (I0 + r, J0 + c) into w; edges (I0 + c, J0 + r) into wt row J0 + r
+    if (w) tio::store<E>(w, ldw, I0, J0, m, m, wv, [&](int r, int c) { return weight(a[r][c], b[c][r], I0 + r == J0 + c); });
+    if (wt) tio::store<E>(wt, ldwt, J0, I0, m, m, wtv, [&](int r, int c) { return weight(a[c][r], b[r][c], I0 + c == J0 + r); });
+    if (I0 == J0) return;
+    // edges (J0 + r, I0 + c) into w; edges (J0 + c, I0 + r) into wt row I0 + r
+    if (w) tio::store<E>(w, ldw, J0, I0, m, m, wv, [&](int r, int c) { return weight(b[r][c], a[c][r], false); });
+    if (wt) tio::store<E>(wt, ldwt, I0, J0, m, m, wtv, [&](int r, int c) { return weight(b[c][r], a[r][c], false); });
 }
 
 // ------------------------------------------------------------------ grid barrier
@@ -252,15 +246,19 @@ extern "C" int schulze_weights(schulze_ctx *ctx, void *stream, const void *d, in
     hipStream_t s = (hipStream_t)stream;
     dim3 grid((unsigned)ceil_div(m, 64), (unsigned)ceil_div(m, 64));
     if (dtype == SCHULZE_U16) {
+        const int vec = (tio::vec_ok<uint16_t>(d, ldd) ? 1 : 0) | (tio::vec_ok<uint16_t>(w, ldw) ? 2 : 0) |
+                        (tio::vec_ok<uint16_t>(wt, ldwt) ? 4 : 0);
         SCHULZE_LAUNCH(ctx, K_WEIGHTS, s,
                        k_weights_pair<uint16_t><<<grid, dim3(256), 0, s>>>(
                            static_cast<const uint16_t *>(d), ldd, m, mode, static_cast<uint16_t *>(w), ldw,
-                           static_cast<uint16_t *>(wt), ldwt));
+                           static_cast<uint16_t *>(wt), ldwt, vec));
     } else {
+        const int vec = (tio::vec_ok<int32_t>(d, ldd) ? 1 : 0) | (tio::vec_ok<int32_t>(w, ldw) ? 2 : 0) |
+                        (tio::vec_ok<int32_t>(wt, ldwt) ? 4 : 0);
         SCHULZE_LAUNCH(ctx, K_WEIGHTS, s,
                        k_weights_pair<int32_t><<<grid, dim3(256), 0, s>>>(
                            static_cast<const int32_t *>(d), ldd, m, mode, static_cast<int32_t *>(w), ldw,
-                           static_cast<int32_t *>(wt), ldwt));
+                           static_cast<int32_t *>(wt), ldwt, vec));
     }
     return SCHULZE_OK;
 }
