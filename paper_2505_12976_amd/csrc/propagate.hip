@@ -34,6 +34,7 @@
 // beats it.  It wins.  Every round decides at least the smallest undecided
 // label, so there are at most m rounds.
 #include "grid.h"
+#include "sweep.h"
 
 namespace {
 
@@ -90,7 +91,7 @@ __device__ inline uint32_t key_width(typename Key<E>::K k) {
 template <typename E>
 __global__ __launch_bounds__(256) void k_prop_rows(const E *__restrict__ d, int64_t ldd, const E *__restrict__ w,
                                                    const E *__restrict__ wt, int64_t ld, int32_t m,
-                                                   const uint8_t *__restrict__ rem, int with_borda,
+                                                   const uint8_t *__restrict__ rem, int with_borda, int vec,
                                                    uint8_t *__restrict__ status, unsigned long long *__restrict__ borda) {
     __shared__ uint32_t smax_out[256], smax_in[256];
     __shared__ unsigned long long sb[256];
@@ -101,11 +102,33 @@ __global__ __launch_bounds__(256) void k_prop_rows(const E *__restrict__ d, int6
     }
     uint32_t mo = 0, mi = 0;
     unsigned long long b = 0;
-    for (int32_t y = threadIdx.x; y < m; y += 256) {
-        if (rem[y]) continue;
-        mo = max(mo, (uint32_t)w[(int64_t)x * ld + y]);
-        mi = max(mi, (uint32_t)wt[(int64_t)x * ld + y]);
-        if (with_borda && y != x) b += (unsigned long long)(uint32_t)d[(int64_t)x * ldd + y];
+    const E *wr = w + (int64_t)x * ld, *wtr = wt + (int64_t)x * ld, *dr = d + (int64_t)x * ldd;
+    // four columns per thread and step: 8- or 16-byte accesses where the rows allow them
+    const bool wv = (vec & 1) != 0, dv = (vec & 2) != 0;
+    for (int32_t y0 = threadIdx.x * 4; y0 < m; y0 += 1024) {
+        uint32_t a[4], at[4], ad[4] = {0u, 0u, 0u, 0u};
+        uint8_t r[4];
+        const bool full = y0 + 4 <= m;
+        if (full && wv) {
+            sweep::load4<E>(wr + y0, true, 4, a);
+            sweep::load4<E>(wtr + y0, true, 4, at);
+            const uint32_t rw = *reinterpret_cast<const uint32_t *>(rem + y0);
+            for (int u = 0; u < 4; ++u) r[u] = (uint8_t)(rw >> (8 * u));
+        } else {
+            for (int u = 0; u < 4; ++u) {
+                const bool in = y0 + u < m;
+                a[u] = in ? (uint32_t)wr[y0 + u] : 0u;
+                at[u] = in ? (uint32_t)wtr[y0 + u] : 0u;
+                r[u] = in ? rem[y0 + u] : (uint8_t)1;
+            }
+        }
+        if (with_borda) sweep::load4<E>(dr + y0, full && dv, full ? 4 : m - y0, ad);
+        for (int u = 0; u < 4; ++u) {
+            if (r[u]) continue;
+            mo = max(mo, a[u]);
+            mi = max(mi, at[u]);
+            if (y0 + u != x) b += (unsigned long long)ad[u];
+        }
     }
     smax_out[threadIdx.x] = mo;
     smax_in[threadIdx.x] = mi;
@@ -160,9 +183,11 @@ struct SweepArgs {
     const E *w;  // rows = edge sources: w for forward, wt for backward
     int64_t ld;
     int32_t m;
+    int32_t vec;        // rows allow 8/16-byte accesses
     const uint8_t *status;
     const int32_t *label;
-    K *x[2];            // ping-pong keys
+    K *x;               // keys, updated in place
+    uint8_t *changed;   // m flags
     int32_t *front[2];  // frontier lists
     int32_t *fcount;    // [0], [1] frontier sizes, [2] sweeps run
     K *out;
@@ -174,66 +199,31 @@ struct SweepArgs {
 template <typename E>
 __global__ __launch_bounds__(256) void k_prop_sweep(SweepArgs<E> a) {
     using K = typename Key<E>::K;
-    __shared__ K part[4][64];
-    const int32_t m = a.m, G = gridDim.x, g = blockIdx.x;
-    const int32_t c0 = (int32_t)((int64_t)m * g / G), c1 = (int32_t)((int64_t)m * (g + 1) / G);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int32_t m = a.m;
     constexpr K HIGH = ~Key<E>::LOW;
 
     // preprocessing: undecided vertices start with their own label and the
     // empty path; they form the first frontier
-    for (int32_t j = c0 + threadIdx.x; j < c1; j += 256) {
+    for (int32_t j = blockIdx.x * 256 + threadIdx.x; j < m; j += gridDim.x * 256) {
         const bool u = a.status[j] == ST_UNKNOWN;
-        a.x[0][j] = u ? make_key<E>((uint32_t)a.label[j]) : (K)0;
+        a.x[j] = u ? make_key<E>((uint32_t)a.label[j]) : (K)0;
+        a.changed[j] = 0;
         if (u) a.front[0][atomicAdd(&a.fcount[0], 1)] = j;
     }
     if (!grid_sync(a.bar, a.spin_limit)) goto stuck;
     {
-        int cur = 0;
-        int32_t sweeps = 0;
-        for (;;) {
-            const int32_t nf = __hip_atomic_load(&a.fcount[cur], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (nf == 0) break;
-            if (++sweeps > 2 * m + 2) {  // keys only grow, so this cannot happen
-                if (threadIdx.x == 0) set_device_error(a.err, SCHULZE_EDEVICE);
-                break;
-            }
-            const K *xc = a.x[cur];
-            K *xn = a.x[cur ^ 1];
-            const int32_t *F = a.front[cur];
-            int32_t *Fn = a.front[cur ^ 1];
-            for (int32_t cb = c0; cb < c1; cb += 64) {
-                const int32_t j = cb + lane;
-                K best = 0;
-                if (j < c1) {
-                    for (int32_t q = wave; q < nf; q += 4) {
-                        const int32_t i = F[q];
-                        const uint32_t wij = (uint32_t)a.w[(int64_t)i * a.ld + j];
-                        const K ki = xc[i];
-                        if (wij != 0 && ki != 0) {
-                            const K lo = (K)min((uint32_t)(ki & Key<E>::LOW), wij);
-                            best = max(best, (ki & HIGH) | lo);
-                        }
-                    }
-                }
-                part[wave][lane] = best;
-                __syncthreads();
-                if (wave == 0 && j < c1) {
-                    const K old = xc[j];
-                    K nv = max(max(old, part[0][lane]), max(part[1][lane], max(part[2][lane], part[3][lane])));
-                    if (a.status[j] == ST_REMOVED) nv = 0;  // no edges: receives nothing
-                    xn[j] = nv;
-                    if (nv > old) Fn[atomicAdd(&a.fcount[cur ^ 1], 1)] = j;
-                }
-                __syncthreads();
-            }
-            if (!grid_sync(a.bar, a.spin_limit)) goto stuck;
-            if (g == 0 && threadIdx.x == 0) a.fcount[cur] = 0;  // the consumed list is the next target
-            cur ^= 1;
-            if (!grid_sync(a.bar, a.spin_limit)) goto stuck;
-        }
-        for (int32_t j = c0 + threadIdx.x; j < c1; j += 256) a.out[j] = a.x[cur][j];
-        if (g == 0 && threadIdx.x == 0) a.fcount[2] = sweeps;
+        sweep::Buffers<K> b{a.x, {a.front[0], a.front[1]}, a.fcount, a.changed, a.bar, a.err, a.spin_limit,
+                            2 * m + 2};
+        const uint8_t *status = a.status;
+        const bool ok = sweep::run<K, E>(
+            a.w, a.ld, m, a.vec != 0, b,
+            [](K k, uint32_t wij) -> K {
+                if (wij == 0 || k == 0) return (K)0;
+                return (k & HIGH) | (K)min((uint32_t)(k & Key<E>::LOW), wij);
+            },
+            [status](int32_t j) { return status[j] != ST_REMOVED; });  // removed vertices have no edges
+        if (!ok) goto stuck;
+        for (int32_t j = blockIdx.x * 256 + threadIdx.x; j < m; j += gridDim.x * 256) a.out[j] = a.x[j];
         return;
     }
 stuck:
@@ -264,26 +254,59 @@ __global__ __launch_bounds__(256) void k_prop_post(const typename Key<E>::K *__r
     }
 }
 
+// Each vertex's (s, t) in one word: labels are below 65534, "no label" is
+// PAIR_NONE, and a removed vertex (no edges) gets PAIR_OUT in both halves.
+constexpr uint32_t PAIR_NONE = 0xFFFEu;
+constexpr uint32_t PAIR_OUT = 0xFFFFFFFFu;
+
+template <typename E>
+__global__ __launch_bounds__(256) void k_prop_pair(const typename Key<E>::K *__restrict__ kf,
+                                                   const typename Key<E>::K *__restrict__ kb, int32_t m,
+                                                   const uint8_t *__restrict__ status, uint32_t *__restrict__ pair) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v >= m) return;
+    const uint32_t s = key_label<E>(kf[v]), t = key_label<E>(kb[v]);
+    pair[v] = status[v] == ST_REMOVED ? PAIR_OUT
+                                       : ((s == 0xFFFFFFFFu ? PAIR_NONE : s) << 16) | (t == 0xFFFFFFFFu ? PAIR_NONE : t);
+}
+
 // Edges v -> c between vertices with different (s, t): one wavefront per c
-// walks column c of w (row c of wt).
+// walks column c of w (row c of wt), four entries per lane and step.
 template <typename E>
 __global__ __launch_bounds__(256) void k_prop_cross(const E *__restrict__ wt, int64_t ld,
-                                                    const typename Key<E>::K *__restrict__ kf,
-                                                    const typename Key<E>::K *__restrict__ kb, int32_t m,
-                                                    const uint8_t *__restrict__ status, uint8_t *__restrict__ mark,
-                                                    uint8_t *__restrict__ dead) {
+                                                    const uint32_t *__restrict__ pair, int32_t m, int vec,
+                                                    uint8_t *__restrict__ mark, uint8_t *__restrict__ dead) {
     const int32_t c = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (c >= m || status[c] == ST_REMOVED) return;
-    const uint32_t s = key_label<E>(kf[c]), t = key_label<E>(kb[c]);
+    if (c >= m) return;
+    const uint32_t pc = pair[c];
+    if (pc == PAIR_OUT) return;
+    const E *row = wt + (int64_t)c * ld;
     bool cross = false;
-    for (int32_t v = lane; v < m; v += 64) {
-        if (wt[(int64_t)c * ld + v] == 0 || status[v] == ST_REMOVED) continue;
-        cross |= key_label<E>(kf[v]) != s || key_label<E>(kb[v]) != t;
+    for (int32_t v0 = lane * 4; v0 < m; v0 += 256) {
+        uint32_t e[4], pv[4];
+        if (vec && v0 + 4 <= m) {
+            if constexpr (sizeof(E) == 4) {
+                const uint4 q = *reinterpret_cast<const uint4 *>(row + v0);
+                e[0] = q.x, e[1] = q.y, e[2] = q.z, e[3] = q.w;
+            } else {
+                const uint2 q = *reinterpret_cast<const uint2 *>(row + v0);
+                e[0] = q.x & 0xFFFFu, e[1] = q.x >> 16, e[2] = q.y & 0xFFFFu, e[3] = q.y >> 16;
+            }
+            const uint4 p4 = *reinterpret_cast<const uint4 *>(pair + v0);
+            pv[0] = p4.x, pv[1] = p4.y, pv[2] = p4.z, pv[3] = p4.w;
+        } else {
+            for (int u = 0; u < 4; ++u) {
+                e[u] = v0 + u < m ? (uint32_t)row[v0 + u] : 0u;
+                pv[u] = v0 + u < m ? pair[v0 + u] : PAIR_OUT;
+            }
+        }
+        for (int u = 0; u < 4; ++u) cross |= e[u] != 0 && pv[u] != PAIR_OUT && pv[u] != pc;
     }
     if (__ballot(cross) && lane == 0) {
+        const uint32_t s = pc >> 16, t = pc & 0xFFFFu;
         if (s == t) {
-            if (s != 0xFFFFFFFFu) dead[s] = 1;
+            if (s != PAIR_NONE) dead[s] = 1;
         } else {
             mark[c] = 1;
         }
@@ -359,13 +382,24 @@ __global__ __launch_bounds__(256) void k_prop_remove(uint8_t *__restrict__ statu
     }
 }
 
+// Access widths for k_prop_rows: bit 0 = rows of w and w^T (pitch m, in the
+// workspace), bit 1 = rows of d.
+template <typename E>
+int rows_vec(const E *d, int64_t ldd, int32_t m) {
+    const bool wv = m % 4 == 0;
+    const bool dv = reinterpret_cast<uintptr_t>(d) % (4 * sizeof(E)) == 0 && ldd % 4 == 0;
+    return (wv ? 1 : 0) | (dv ? 2 : 0);
+}
+
 // Device buffers of one propagation run (slices of the WS_PROPAGATE slot).
 template <typename E>
 struct PropBufs {
     using K = typename Key<E>::K;
     E *w, *wt;
-    K *x0, *x1, *kf, *kb;
+    K *x, *kf, *kb;
+    uint8_t *changed;
     int32_t *f0, *f1, *label, *vertex;
+    uint32_t *pair;
     unsigned long long *borda;
     uint8_t *status, *mark, *dead, *rem;
     int32_t *tail;  // [0..2] sweep counters, [8..10] barrier, [16..17] counts
@@ -383,8 +417,8 @@ int prop_prepare(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32
     const size_t ivec = round_up(sizeof(int32_t) * (size_t)m, 256);
     const size_t bvec = round_up((size_t)m, 256);
     const size_t u64vec = round_up(sizeof(unsigned long long) * (size_t)m, 256);
-    // w | wt | keys x2 | kf | kb | fronts x2 | label | vertex | borda | status | mark | dead | rem | tail
-    const size_t need = 2 * mat + 4 * kvec + 4 * ivec + u64vec + 4 * bvec + 256;
+    // w | wt | keys | kf | kb | fronts x2 | label | vertex | borda | status | mark | dead | rem | changed | tail
+    const size_t need = 2 * mat + 3 * kvec + 5 * ivec + u64vec + 5 * bvec + 256;
     int rc = ws_reserve(ctx, WS_PROPAGATE, need);
     if (rc != SCHULZE_OK) return rc;
     char *p = static_cast<char *>(ctx->ws[WS_PROPAGATE]);
@@ -395,19 +429,20 @@ int prop_prepare(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32
     };
     b.w = reinterpret_cast<E *>(take(mat));
     b.wt = reinterpret_cast<E *>(take(mat));
-    b.x0 = reinterpret_cast<K *>(take(kvec));
-    b.x1 = reinterpret_cast<K *>(take(kvec));
+    b.x = reinterpret_cast<K *>(take(kvec));
     b.kf = reinterpret_cast<K *>(take(kvec));
     b.kb = reinterpret_cast<K *>(take(kvec));
     b.f0 = reinterpret_cast<int32_t *>(take(ivec));
     b.f1 = reinterpret_cast<int32_t *>(take(ivec));
     b.label = reinterpret_cast<int32_t *>(take(ivec));
     b.vertex = reinterpret_cast<int32_t *>(take(ivec));
+    b.pair = reinterpret_cast<uint32_t *>(take(ivec));
     b.borda = reinterpret_cast<unsigned long long *>(take(u64vec));
     b.status = reinterpret_cast<uint8_t *>(take(bvec));
     b.mark = reinterpret_cast<uint8_t *>(take(bvec));
     b.dead = reinterpret_cast<uint8_t *>(take(bvec));
     b.rem = reinterpret_cast<uint8_t *>(take(bvec));
+    b.changed = reinterpret_cast<uint8_t *>(take(bvec));
     b.tail = reinterpret_cast<int32_t *>(take(256));
     b.bvec = bvec;
 
@@ -415,17 +450,15 @@ int prop_prepare(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32
     if ((rc = schulze_weights(ctx, s, d, ldd, m, dtype, mode, b.w, m, b.wt, m)) != SCHULZE_OK) return rc;
     if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(b.rem), bvec / 4, 0u)) != SCHULZE_OK) return rc;
     SCHULZE_LAUNCH(ctx, K_PROP, s,
-                   k_prop_rows<E><<<dim3((unsigned)m), dim3(256), 0, s>>>(d, ldd, b.w, b.wt, m, m, b.rem, 1, b.status,
-                                                                         b.borda));
+                   k_prop_rows<E><<<dim3((unsigned)m), dim3(256), 0, s>>>(d, ldd, b.w, b.wt, m, m, b.rem, 1,
+                                                                         rows_vec<E>(d, ldd, m), b.status, b.borda));
     SCHULZE_LAUNCH(ctx, K_PROP, s,
                    k_prop_order<<<dim3((unsigned)m), dim3(256), 0, s>>>(b.borda, m, use_borda, b.label, b.vertex));
 
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_prop_sweep<E>, 256, 0) != hipSuccess || per_cu < 1)
         return SCHULZE_EDEVICE;
-    int64_t G = (int64_t)ctx->num_cus * std::min(per_cu, 2);
-    G = std::min<int64_t>(G, ceil_div(m, 64));
-    b.G = G < 1 ? 1 : G;
+    b.G = sweep::grid_size(m, (int64_t)ctx->num_cus * std::min(per_cu, 2));
     return SCHULZE_OK;
 }
 
@@ -443,10 +476,11 @@ int prop_decide_all(schulze_ctx *ctx, hipStream_t s, int32_t m, PropBufs<E> &b, 
             a.w = dir == 0 ? b.w : b.wt;
             a.ld = m;
             a.m = m;
+            a.vec = (reinterpret_cast<uintptr_t>(a.w) % (4 * sizeof(E)) == 0 && m % 4 == 0) ? 1 : 0;
             a.status = b.status;
             a.label = b.label;
-            a.x[0] = b.x0;
-            a.x[1] = b.x1;
+            a.x = b.x;
+            a.changed = b.changed;
             a.front[0] = b.f0;
             a.front[1] = b.f1;
             a.fcount = b.tail;
@@ -475,8 +509,11 @@ int prop_decide_all(schulze_ctx *ctx, hipStream_t s, int32_t m, PropBufs<E> &b, 
         if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(b.tail + 16), 2, 0u)) != SCHULZE_OK) return rc;
         SCHULZE_LAUNCH(ctx, K_PROP, s, k_prop_post<E><<<dim3(vb), dim3(256), 0, s>>>(b.kf, b.kb, m, b.vertex, b.mark));
         SCHULZE_LAUNCH(ctx, K_PROP, s,
-                       k_prop_cross<E><<<dim3((unsigned)ceil_div(m, 4)), dim3(256), 0, s>>>(b.wt, m, b.kf, b.kb, m,
-                                                                                            b.status, b.mark, b.dead));
+                       k_prop_pair<E><<<dim3(vb), dim3(256), 0, s>>>(b.kf, b.kb, m, b.status, b.pair));
+        const int cvec = (reinterpret_cast<uintptr_t>(b.wt) % (4 * sizeof(E)) == 0 && m % 4 == 0) ? 1 : 0;
+        SCHULZE_LAUNCH(ctx, K_PROP, s,
+                       k_prop_cross<E><<<dim3((unsigned)ceil_div(m, 4)), dim3(256), 0, s>>>(b.wt, m, b.pair, m, cvec,
+                                                                                            b.mark, b.dead));
         SCHULZE_LAUNCH(ctx, K_PROP, s,
                        k_prop_apply<E><<<dim3(vb), dim3(256), 0, s>>>(b.kf, b.kb, m, b.mark, b.dead, b.status));
         SCHULZE_LAUNCH(ctx, K_PROP, s,
@@ -541,7 +578,8 @@ int run_topk(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32_t m
         if (out.ranked >= k || counts[1] == 0) break;
         SCHULZE_LAUNCH(ctx, K_PROP, s,
                        k_prop_rows<E><<<dim3((unsigned)m), dim3(256), 0, s>>>(d, ldd, b.w, b.wt, m, m, b.rem, 0,
-                                                                             b.status, b.borda));
+                                                                             rows_vec<E>(d, ldd, m), b.status,
+                                                                             b.borda));
     }
     out.rounds = st.rounds;
     out.sweeps = st.sweeps;

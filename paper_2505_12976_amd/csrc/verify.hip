@@ -12,9 +12,10 @@
 // anything, so each sweep walks just that frontier.  The target direction
 // p[.][t] is the same computation on the transposed weights.
 //
-// One persistent cooperative launch runs all sweeps; workgroups own column
-// ranges and meet at a grid barrier between sweeps.
+// One persistent cooperative launch runs all sweeps (the column-block and
+// frontier-share layout of sweep.h), with a grid barrier between sweeps.
 #include "grid.h"
+#include "sweep.h"
 #include "tile_io.h"
 
 namespace {
@@ -60,14 +61,16 @@ __global__ __launch_bounds__(256) void k_weights_pair(const E *__restrict__ d, i
 // ------------------------------------------------------------------ sweeps
 template <typename E>
 struct WidestArgs {
-    const E *w;         // rows = sources of edges (w, or wt for the target direction)
+    const E *w;          // rows = sources of edges (w, or wt for the target direction)
     int64_t ldw;
     int32_t m;
-    int32_t s;          // source (or target) vertex
-    E *out;             // m widths, out[s] = 0
-    E *x[2];            // ping-pong value vectors
-    int32_t *front[2];  // frontier lists (m entries each)
-    int32_t *fcount;    // [0], [1]: frontier sizes; [2]: sweeps run
+    int32_t s;           // source (or target) vertex
+    int32_t vec;         // rows of w allow 8/16-byte accesses
+    E *out;              // m widths, out[s] = 0
+    uint32_t *x;         // m values, in place
+    uint8_t *changed;    // m flags
+    int32_t *front[2];   // frontier lists (m entries each)
+    int32_t *fcount;     // [0], [1]: frontier sizes; [2]: sweeps run
     GridBar *bar;
     int32_t *err;
     int64_t spin_limit;
@@ -75,61 +78,27 @@ struct WidestArgs {
 
 template <typename E>
 __global__ __launch_bounds__(256) void k_widest(WidestArgs<E> a) {
-    __shared__ E part[4][64];
-    const int32_t m = a.m, G = gridDim.x, g = blockIdx.x;
-    const int32_t c0 = (int32_t)((int64_t)m * g / G), c1 = (int32_t)((int64_t)m * (g + 1) / G);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-
-    // sweep 0: x = MAX at s, 0 elsewhere; frontier = {s}
-    for (int32_t j = c0 + threadIdx.x; j < c1; j += 256) a.x[0][j] = j == a.s ? max_value<E>() : (E)0;
-    if (g == 0 && threadIdx.x == 0) {
+    const int32_t m = a.m;
+    // x = MAX at s, 0 elsewhere; frontier = {s}
+    for (int32_t j = blockIdx.x * 256 + threadIdx.x; j < m; j += gridDim.x * 256) {
+        a.x[j] = j == a.s ? (uint32_t)max_value<E>() : 0u;
+        a.changed[j] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.front[0][0] = a.s;
         a.fcount[0] = 1;
         a.fcount[1] = 0;
     }
     if (!grid_sync(a.bar, a.spin_limit)) goto stuck;
     {
-        int cur = 0;
-        int32_t sweeps = 0;
-        for (;;) {
-            const int32_t nf = __hip_atomic_load(&a.fcount[cur], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (nf == 0) break;
-            if (++sweeps > m + 1) {  // cannot happen for a correct fixpoint iteration
-                if (threadIdx.x == 0) set_device_error(a.err, SCHULZE_EDEVICE);
-                break;
-            }
-            const E *xc = a.x[cur];
-            E *xn = a.x[cur ^ 1];
-            const int32_t *F = a.front[cur];
-            int32_t *Fn = a.front[cur ^ 1];
-            for (int32_t cb = c0; cb < c1; cb += 64) {
-                const int32_t j = cb + lane;
-                E best = 0;
-                if (j < c1) {
-                    for (int32_t q = wave; q < nf; q += 4) {
-                        const int32_t i = F[q];
-                        const E via = min(xc[i], a.w[(int64_t)i * a.ldw + j]);
-                        best = max(best, via);
-                    }
-                }
-                part[wave][lane] = best;
-                __syncthreads();
-                if (wave == 0 && j < c1) {
-                    const E old = xc[j];
-                    const E nv = max(max(old, part[0][lane]), max(part[1][lane], max(part[2][lane], part[3][lane])));
-                    xn[j] = nv;
-                    if (nv > old) Fn[atomicAdd(&a.fcount[cur ^ 1], 1)] = j;
-                }
-                __syncthreads();
-            }
-            if (!grid_sync(a.bar, a.spin_limit)) goto stuck;
-            // the list just consumed becomes the next target: reset its size
-            if (g == 0 && threadIdx.x == 0) a.fcount[cur] = 0;
-            cur ^= 1;
-            if (!grid_sync(a.bar, a.spin_limit)) goto stuck;
-        }
-        for (int32_t j = c0 + threadIdx.x; j < c1; j += 256) a.out[j] = j == a.s ? (E)0 : a.x[cur][j];
-        if (g == 0 && threadIdx.x == 0) a.fcount[2] = sweeps;
+        sweep::Buffers<uint32_t> b{a.x, {a.front[0], a.front[1]}, a.fcount, a.changed, a.bar, a.err, a.spin_limit,
+                                   m + 1};
+        const bool ok = sweep::run<uint32_t, E>(
+            a.w, a.ldw, m, a.vec != 0, b, [](uint32_t xi, uint32_t e) { return min(xi, e); },
+            [](int32_t) { return true; });
+        if (!ok) goto stuck;
+        for (int32_t j = blockIdx.x * 256 + threadIdx.x; j < m; j += gridDim.x * 256)
+            a.out[j] = j == a.s ? (E)0 : (E)a.x[j];
         return;
     }
 stuck:
@@ -183,12 +152,19 @@ __global__ __launch_bounds__(256) void k_verdict(const E *__restrict__ from, con
     }
 }
 
+// 8-byte (uint16) or 16-byte (int32) row accesses of a matrix at p, pitch ld.
+template <typename E>
+bool sweep_vec_ok(const void *p, int64_t ld) {
+    return (reinterpret_cast<uintptr_t>(p) % (4 * sizeof(E)) == 0) && (ld % 4 == 0);
+}
+
 template <typename E>
 int widest(schulze_ctx *ctx, hipStream_t s, const E *w, int64_t ldw, int32_t m, int32_t src, E *out) {
-    // workspace: two value vectors, two frontiers, counters, barrier
-    const size_t xbytes = round_up(sizeof(E) * (size_t)m, 256);
+    // workspace: values, flags, two frontiers, counters, barrier
+    const size_t xbytes = round_up(sizeof(uint32_t) * (size_t)m, 256);
+    const size_t cbytes = round_up((size_t)m, 256);
     const size_t fbytes = round_up(sizeof(int32_t) * (size_t)m, 256);
-    const size_t need = 2 * xbytes + 2 * fbytes + 256;
+    const size_t need = xbytes + cbytes + 2 * fbytes + 256;
     int rc = ws_reserve(ctx, WS_VERIFY, need);
     if (rc != SCHULZE_OK) return rc;
     char *base = static_cast<char *>(ctx->ws[WS_VERIFY]);
@@ -197,12 +173,13 @@ int widest(schulze_ctx *ctx, hipStream_t s, const E *w, int64_t ldw, int32_t m, 
     a.ldw = ldw;
     a.m = m;
     a.s = src;
+    a.vec = sweep_vec_ok<E>(w, ldw) ? 1 : 0;
     a.out = out;
-    a.x[0] = reinterpret_cast<E *>(base);
-    a.x[1] = reinterpret_cast<E *>(base + xbytes);
-    a.front[0] = reinterpret_cast<int32_t *>(base + 2 * xbytes);
-    a.front[1] = reinterpret_cast<int32_t *>(base + 2 * xbytes + fbytes);
-    int32_t *tail = reinterpret_cast<int32_t *>(base + 2 * xbytes + 2 * fbytes);
+    a.x = reinterpret_cast<uint32_t *>(base);
+    a.changed = reinterpret_cast<uint8_t *>(base + xbytes);
+    a.front[0] = reinterpret_cast<int32_t *>(base + xbytes + cbytes);
+    a.front[1] = reinterpret_cast<int32_t *>(base + xbytes + cbytes + fbytes);
+    int32_t *tail = reinterpret_cast<int32_t *>(base + xbytes + cbytes + 2 * fbytes);
     a.fcount = tail;
     a.bar = reinterpret_cast<GridBar *>(tail + 8);
     a.err = ctx->err;
@@ -211,9 +188,7 @@ int widest(schulze_ctx *ctx, hipStream_t s, const E *w, int64_t ldw, int32_t m, 
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_widest<E>, 256, 0) != hipSuccess || per_cu < 1)
         return SCHULZE_EDEVICE;
-    int64_t G = (int64_t)ctx->num_cus * std::min(per_cu, 2);
-    G = std::min<int64_t>(G, ceil_div(m, 64));
-    if (G < 1) G = 1;
+    const int64_t G = sweep::grid_size(m, (int64_t)ctx->num_cus * std::min(per_cu, 2));
     void *args[] = {&a};
     int tok;
     timing_begin(ctx, K_WIDEST, s, &tok);
