@@ -349,6 +349,17 @@ int schulze_set_closure_schedule(schulze_ctx *ctx, int schedule);
 int schulze_set_closure_tile(schulze_ctx *ctx, int tile);
 
 /*
+ * Counting of truncated ballots over many candidates (the sparse form
+ * d[x][y] = R_x - C[y][x] of Section 2.1's counts, chosen on the device when
+ * the listed candidates of truncated ballots are too many for a dense count):
+ * BUCKETED (default for m <= 32768 and n * L <= 2^27) sorts the listed
+ * entries by candidate and accumulates each candidate's row of C in LDS;
+ * ATOMIC adds every pair with a device-wide atomic.  Both give the same d.
+ */
+enum { SCHULZE_SPARSE_BUCKETED = 0, SCHULZE_SPARSE_ATOMIC = 1 };
+int schulze_set_sparse_count(schulze_ctx *ctx, int mode);
+
+/*
  * Value ranking of int32 closures (default on).  The (max, min) recurrence
  * of Section 2.1 commutes with every strictly increasing map of the weights
  * that keeps 0, so when the weights of an int32 closure with m >= 1024 take

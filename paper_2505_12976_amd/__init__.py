@@ -28,7 +28,7 @@ EXPORTS = (
     "schulze_create", "schulze_destroy", "schulze_strerror", "schulze_get_device_error",
     "schulze_pairwise", "schulze_closure", "schulze_winners", "schulze_ranking",
     "schulze_set_timing", "schulze_kernel_time", "schulze_reset_timing", "schulze_set_closure_schedule",
-    "schulze_set_value_ranking", "schulze_set_closure_tile",
+    "schulze_set_value_ranking", "schulze_set_closure_tile", "schulze_set_sparse_count",
     "schulze_weights", "schulze_widest_from", "schulze_verify", "schulze_features",
     "schulze_mlp_param_count", "schulze_mlp_forward", "schulze_mlp_loss", "schulze_mlp_backward", "schulze_mlp_adam",
     "schulze_winners_learned",
@@ -116,6 +116,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.schulze_set_closure_schedule.argtypes = [vp, c_int]
     lib.schulze_set_value_ranking.argtypes = [vp, c_int]
     lib.schulze_set_closure_tile.argtypes = [vp, c_int]
+    lib.schulze_set_sparse_count.argtypes = [vp, c_int]
     lib.schulze_weights.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_int, vp, c_i64, vp, c_i64]
     lib.schulze_widest_from.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_i32, vp]
     lib.schulze_verify.argtypes = [vp, vp, vp, c_i64, vp, c_i64, c_i32, c_int, c_i32, vp, vp, vp, vp, vp]
@@ -495,6 +496,11 @@ class Context:
     def set_closure_tile(self, tile: int) -> None:
         """Closure tile size: 0 (by value width and m), 64 or 128."""
         _check(self._lib.schulze_set_closure_tile(self._h, int(tile)), "schulze_set_closure_tile")
+
+    def set_sparse_count(self, mode: str) -> None:
+        """Truncated ballots over many candidates: "bucketed" (default) or "atomic"."""
+        code = {"bucketed": 0, "atomic": 1}[mode]
+        _check(self._lib.schulze_set_sparse_count(self._h, code), "schulze_set_sparse_count")
 
     def set_value_ranking(self, enable: bool) -> None:
         """Run int32 closures of m >= 1024 on value ranks in uint16 when the values fit (default on)."""

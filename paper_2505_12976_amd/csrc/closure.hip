@@ -68,15 +68,14 @@ __global__ __launch_bounds__(256) void k_weights(const E *__restrict__ d, int64_
         tio::store<E>(P, ld, J0, I0, mp, mp, true, [&](int r, int c) { return weight(b[r][c], a[c][r], false); });
 }
 
-// p[i][j] = P[i][j] for i != j, 0 on the diagonal.
+// p[i][j] = P[i][j] for i != j, 0 on the diagonal; one workgroup per row.
 template <typename E>
 __global__ __launch_bounds__(256) void k_fw_store(const E *__restrict__ P, int64_t ld, int32_t m, E *__restrict__ p,
                                                   int64_t ldp) {
-    const int32_t col_blocks = (m + 255) / 256;
-    const int32_t i = blockIdx.x / col_blocks;
-    const int32_t j = (blockIdx.x % col_blocks) * 256 + threadIdx.x;
-    if (j >= m) return;
-    p[(int64_t)i * ldp + j] = i == j ? (E)0 : P[(int64_t)i * ld + j];
+    const int32_t i = blockIdx.x;
+    const E *src = P + (int64_t)i * ld;
+    E *dst = p + (int64_t)i * ldp;
+    for (int32_t j = threadIdx.x; j < m; j += 256) dst[j] = i == j ? (E)0 : src[j];
 }
 
 // ------------------------------------------------------------------ persistent launch
@@ -376,8 +375,7 @@ int run_closure(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32_
     SCHULZE_LAUNCH(ctx, K_WEIGHTS, s, k_weights<E><<<wgrid, dim3(256), 0, s>>>(d, ldd, m, mode, P, ld, mp,
                                                                           tio::vec_ok<E>(d, ldd) ? 1 : 0));
     if ((rc = close_padded<E, B>(ctx, s, P, ld, nb)) != SCHULZE_OK) return rc;
-    dim3 sgrid((unsigned)(ceil_div(m, 256) * m));
-    SCHULZE_LAUNCH(ctx, K_FW_STORE, s, k_fw_store<E><<<sgrid, dim3(256), 0, s>>>(P, ld, m, p, ldp));
+    SCHULZE_LAUNCH(ctx, K_FW_STORE, s, k_fw_store<E><<<dim3((unsigned)m), dim3(256), 0, s>>>(P, ld, m, p, ldp));
     return SCHULZE_OK;
 }
 
@@ -538,19 +536,18 @@ __global__ __launch_bounds__(256) void k_rank_apply(const int32_t *__restrict__ 
     }
 }
 
-// p[i][j] = value_of[P16[i][j]] for i != j, 0 on the diagonal; four
-// columns per thread (ld is a multiple of 64).
+// p[i][j] = value_of[P16[i][j]] for i != j, 0 on the diagonal; one
+// workgroup per row, four columns per thread and step (ld is a multiple of 64).
 __global__ __launch_bounds__(256) void k_rank_store(const uint16_t *__restrict__ P16, int64_t ld, int32_t m,
                                                     const int32_t *__restrict__ value_of, int32_t *__restrict__ p,
                                                     int64_t ldp) {
-    const int32_t col_blocks = (m + 1023) / 1024;
-    const int32_t i = blockIdx.x / col_blocks;
-    const int32_t j0 = (blockIdx.x % col_blocks) * 1024 + threadIdx.x * 4;
-    if (j0 >= m) return;
-    const ushort4 r = *reinterpret_cast<const ushort4 *>(P16 + (int64_t)i * ld + j0);
-    const uint16_t rr[4] = {r.x, r.y, r.z, r.w};
+    const int32_t i = blockIdx.x;
     int32_t *row = p + (int64_t)i * ldp;
-    for (int u = 0; u < 4 && j0 + u < m; ++u) row[j0 + u] = i == j0 + u ? 0 : value_of[rr[u]];
+    for (int32_t j0 = threadIdx.x * 4; j0 < m; j0 += 1024) {
+        const ushort4 r = *reinterpret_cast<const ushort4 *>(P16 + (int64_t)i * ld + j0);
+        const uint16_t rr[4] = {r.x, r.y, r.z, r.w};
+        for (int u = 0; u < 4 && j0 + u < m; ++u) row[j0 + u] = i == j0 + u ? 0 : value_of[rr[u]];
+    }
 }
 
 // BI: tile of the int32 closure (when the values cannot be ranked); BU: tile
@@ -598,16 +595,16 @@ int run_closure_ranked(schulze_ctx *ctx, hipStream_t s, const int32_t *d, int64_
         return SCHULZE_EDEVICE;
     if (host_flags[0] != 0 || host_flags[1] > 65535) {  // too wide or too many values: int32 closure
         if ((rc = close_padded<int32_t, BI>(ctx, s, P, ld, mp / BI)) != SCHULZE_OK) return rc;
-        dim3 sgrid((unsigned)(ceil_div(m, 256) * m));
-        SCHULZE_LAUNCH(ctx, K_FW_STORE, s, k_fw_store<int32_t><<<sgrid, dim3(256), 0, s>>>(P, ld, m, p, ldp));
+        SCHULZE_LAUNCH(ctx, K_FW_STORE, s,
+                       k_fw_store<int32_t><<<dim3((unsigned)m), dim3(256), 0, s>>>(P, ld, m, p, ldp));
         return SCHULZE_OK;
     }
     SCHULZE_LAUNCH(ctx, K_RANK, s,
                    k_rank_words<<<dim3(RANK_BLOCKS), dim3(256), 0, s>>>(bitmap, block_off, word_rank, value_of));
     SCHULZE_LAUNCH(ctx, K_RANK, s, k_rank_apply<<<dim3(egrid), dim3(256), 0, s>>>(P, count, bitmap, word_rank, P16));
     if ((rc = close_padded<uint16_t, BU>(ctx, s, P16, ld, mp / BU)) != SCHULZE_OK) return rc;
-    dim3 sgrid((unsigned)(ceil_div(m, 1024) * m));
-    SCHULZE_LAUNCH(ctx, K_RANK, s, k_rank_store<<<sgrid, dim3(256), 0, s>>>(P16, ld, m, value_of, p, ldp));
+    SCHULZE_LAUNCH(ctx, K_RANK, s,
+                   k_rank_store<<<dim3((unsigned)m), dim3(256), 0, s>>>(P16, ld, m, value_of, p, ldp));
     return SCHULZE_OK;
 }
 

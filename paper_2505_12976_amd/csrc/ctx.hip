@@ -196,6 +196,12 @@ extern "C" int schulze_set_closure_schedule(schulze_ctx *ctx, int schedule) {
     return SCHULZE_OK;
 }
 
+extern "C" int schulze_set_sparse_count(schulze_ctx *ctx, int mode) {
+    if (!ctx || (mode != SCHULZE_SPARSE_BUCKETED && mode != SCHULZE_SPARSE_ATOMIC)) return SCHULZE_EINVAL;
+    ctx->legacy_pairs = mode == SCHULZE_SPARSE_ATOMIC;
+    return SCHULZE_OK;
+}
+
 extern "C" int schulze_set_closure_tile(schulze_ctx *ctx, int tile) {
     if (!ctx || (tile != 0 && tile != 64 && tile != 128)) return SCHULZE_EINVAL;
     ctx->closure_tile = tile;

@@ -34,9 +34,13 @@ struct RawStats {
 // Partial statistics of 64 candidates (rows X0 ..) over the column blocks
 // Y0 = 64 (blockIdx.y + k gridDim.y); slice s = blockIdx.y writes entry
 // s * m + x of every array of st.
+// With w / wt given, the same pass also writes the edge weights of the
+// tiles it holds: w[X0 + r][Y0 + c] and wt[Y0 + r][X0 + c] (each tile of w
+// and of its transpose exactly once over the grid).
 template <typename E>
 __global__ __launch_bounds__(256) void k_feature_rows(const E *__restrict__ d, int64_t ldd, int32_t m, int mode,
-                                                      RawStats st, int vec) {
+                                                      RawStats st, int vec, E *__restrict__ w, int64_t ldw,
+                                                      E *__restrict__ wt, int64_t ldwt) {
     __shared__ E a[64][65];  // a[r][c] = d[X0 + r][Y0 + c]
     __shared__ E b[64][65];  // b[r][c] = d[Y0 + r][X0 + c]
     const int32_t X0 = blockIdx.x * 64;
@@ -47,9 +51,21 @@ __global__ __launch_bounds__(256) void k_feature_rows(const E *__restrict__ d, i
     long long mn = LLONG_MAX, mxm = LLONG_MIN;
     for (int32_t Y0 = 64 * blockIdx.y; Y0 < m; Y0 += 64 * gridDim.y) {
         __syncthreads();
-        tio::load<E>(a, d, ldd, X0, Y0, m, m, vec != 0);
-        tio::load<E>(b, d, ldd, Y0, X0, m, m, vec != 0);
+        tio::load<E>(a, d, ldd, X0, Y0, m, m, (vec & 1) != 0);
+        tio::load<E>(b, d, ldd, Y0, X0, m, m, (vec & 1) != 0);
         __syncthreads();
+        if (w || wt) {
+            auto weight = [&](E xy, E yx, bool diag) -> E {  // edge weight given d[i][j] = xy, d[j][i] = yx
+                if (diag || xy <= yx) return (E)0;
+                return mode == SCHULZE_MARGIN ? (E)(xy - yx) : xy;
+            };
+            if (w)
+                tio::store<E>(w, ldw, X0, Y0, m, m, (vec & 2) != 0,
+                              [&](int rr, int cc) { return weight(a[rr][cc], b[cc][rr], X0 + rr == Y0 + cc); });
+            if (wt)
+                tio::store<E>(wt, ldwt, Y0, X0, m, m, (vec & 4) != 0,
+                              [&](int rr, int cc) { return weight(a[cc][rr], b[rr][cc], X0 + cc == Y0 + rr); });
+        }
         if (x >= m) continue;
         for (int c = part * 16; c < part * 16 + 16; ++c) {
             const int32_t y = Y0 + c;
@@ -125,49 +141,58 @@ __global__ __launch_bounds__(256) void k_feature_reduce(int32_t m, int32_t S, Ra
     st.max_marg[x] = m > 1 ? mxm : 0;
 }
 
-// Normalise: one workgroup finds the maxima, every thread writes rows.
-__global__ __launch_bounds__(256) void k_feature_norm(int32_t m, RawStats st, float n_voters,
-                                                      float *__restrict__ feat) {
-    __shared__ int32_t mcope, mout;
-    __shared__ unsigned long long mborda;
+// Maxima over candidates of the Copeland score, the largest outgoing weight
+// and the Borda score: mx[0], mx[1] (int32 as uint32) and mx[2] (64 bits at
+// mx + 2); zero on entry.
+__global__ __launch_bounds__(256) void k_feature_max(int32_t m, RawStats st, uint32_t *__restrict__ mx) {
+    __shared__ uint32_t sc, so;
+    __shared__ unsigned long long sb;
     if (threadIdx.x == 0) {
-        mcope = 0;
-        mout = 0;
-        mborda = 0;
+        sc = 0;
+        so = 0;
+        sb = 0;
     }
     __syncthreads();
-    int32_t c = 0, o = 0;
-    unsigned long long bd = 0;
-    for (int32_t x = threadIdx.x; x < m; x += 256) {
-        c = max(c, st.cope[x]);
-        o = max(o, st.max_out[x]);
-        bd = max(bd, st.borda[x]);
+    const int32_t x = blockIdx.x * 256 + threadIdx.x;
+    if (x < m) {
+        atomicMax(&sc, (uint32_t)st.cope[x]);
+        atomicMax(&so, (uint32_t)st.max_out[x]);
+        atomicMax(&sb, st.borda[x]);
     }
-    atomicMax(&mcope, c);
-    atomicMax(&mout, o);
-    atomicMax(&mborda, bd);
     __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicMax(&mx[0], sc);
+        atomicMax(&mx[1], so);
+        atomicMax(reinterpret_cast<unsigned long long *>(mx + 2), sb);
+    }
+}
+
+// Normalise: one thread per candidate.
+__global__ __launch_bounds__(256) void k_feature_norm(int32_t m, RawStats st, float n_voters,
+                                                      const uint32_t *__restrict__ mx, float *__restrict__ feat) {
+    const int32_t x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= m) return;
+    const uint32_t mcope = mx[0], mout = mx[1];
+    const unsigned long long mborda = *reinterpret_cast<const unsigned long long *>(mx + 2);
     const float inv_m1 = m > 1 ? 1.0f / (float)(m - 1) : 0.0f;
     const float inv_n = n_voters > 0.f ? 1.0f / n_voters : 1.0f;
-    for (int32_t x = threadIdx.x; x < m; x += 256) {
-        float *f = feat + (int64_t)x * NF;
-        f[0] = (float)st.cope[x] * inv_m1;
-        f[1] = (float)st.ties[x] * inv_m1;
-        f[2] = (float)st.borda[x] * inv_m1 * inv_n;
-        f[3] = (float)st.max_out[x] * inv_n;
-        f[4] = (float)st.max_in[x] * inv_n;
-        f[5] = st.max_in[x] > st.max_out[x] ? 1.0f : 0.0f;
-        f[6] = (float)st.sum_out[x] * inv_m1 * inv_n;
-        f[7] = (float)st.sum_in[x] * inv_m1 * inv_n;
-        f[8] = (float)st.min_marg[x] * inv_n;
-        f[9] = (float)st.max_marg[x] * inv_n;
-        f[10] = logf((float)m) * 0.1f;
-        f[11] = mcope > 0 ? (float)st.cope[x] / (float)mcope : 0.0f;
-        f[12] = mborda > 0 ? (float)((double)st.borda[x] / (double)mborda) : 0.0f;
-        f[13] = mout > 0 ? (float)st.max_out[x] / (float)mout : 0.0f;
-        f[14] = ((float)st.max_out[x] - (float)st.max_in[x]) * inv_n;
-        f[15] = 1.0f;
-    }
+    float *f = feat + (int64_t)x * NF;
+    f[0] = (float)st.cope[x] * inv_m1;
+    f[1] = (float)st.ties[x] * inv_m1;
+    f[2] = (float)st.borda[x] * inv_m1 * inv_n;
+    f[3] = (float)st.max_out[x] * inv_n;
+    f[4] = (float)st.max_in[x] * inv_n;
+    f[5] = st.max_in[x] > st.max_out[x] ? 1.0f : 0.0f;
+    f[6] = (float)st.sum_out[x] * inv_m1 * inv_n;
+    f[7] = (float)st.sum_in[x] * inv_m1 * inv_n;
+    f[8] = (float)st.min_marg[x] * inv_n;
+    f[9] = (float)st.max_marg[x] * inv_n;
+    f[10] = logf((float)m) * 0.1f;
+    f[11] = mcope > 0 ? (float)st.cope[x] / (float)mcope : 0.0f;
+    f[12] = mborda > 0 ? (float)((double)st.borda[x] / (double)mborda) : 0.0f;
+    f[13] = mout > 0 ? (float)st.max_out[x] / (float)mout : 0.0f;
+    f[14] = ((float)st.max_out[x] - (float)st.max_in[x]) * inv_n;
+    f[15] = 1.0f;
 }
 
 // Carve the nine statistic arrays of n entries each out of p.
@@ -189,24 +214,30 @@ RawStats carve(char *p, size_t n, size_t *bytes) {
 
 template <typename E>
 int run_features(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32_t m, int mode, float n_voters,
-                 float *feat) {
+                 float *feat, E *w = nullptr, int64_t ldw = 0, E *wt = nullptr, int64_t ldwt = 0) {
     // column slices per block of 64 rows: enough workgroups to keep HBM busy
     const int32_t nbx = (int32_t)ceil_div(m, 64);
     const int32_t S = std::max(1, std::min<int32_t>(nbx, (int32_t)ceil_div(16 * (int64_t)ctx->num_cus, nbx)));
     size_t fin_bytes = 0, part_bytes = 0;
     (void)carve(nullptr, (size_t)m, &fin_bytes);
     (void)carve(nullptr, (size_t)m * S, &part_bytes);
-    int rc = ws_reserve(ctx, WS_FEATURES, fin_bytes + part_bytes);
+    int rc = ws_reserve(ctx, WS_FEATURES, fin_bytes + part_bytes + 256);
     if (rc != SCHULZE_OK) return rc;
     char *p = static_cast<char *>(ctx->ws[WS_FEATURES]);
     RawStats st = carve(p, (size_t)m, &fin_bytes);
     RawStats part = carve(p + fin_bytes, (size_t)m * S, &part_bytes);
+    uint32_t *mx = reinterpret_cast<uint32_t *>(p + fin_bytes + part_bytes);
+    if ((rc = fill_u32(ctx, s, mx, 4, 0u)) != SCHULZE_OK) return rc;
+    const int vec = (tio::vec_ok<E>(d, ldd) ? 1 : 0) | (tio::vec_ok<E>(w, ldw) ? 2 : 0) |
+                    (tio::vec_ok<E>(wt, ldwt) ? 4 : 0);
     SCHULZE_LAUNCH(ctx, K_FEATURES, s,
                    k_feature_rows<E><<<dim3((unsigned)nbx, (unsigned)S), dim3(256), 0, s>>>(
-                       d, ldd, m, mode, part, tio::vec_ok<E>(d, ldd) ? 1 : 0));
+                       d, ldd, m, mode, part, vec, w, ldw, wt, ldwt));
     SCHULZE_LAUNCH(ctx, K_FEATURES, s,
                    k_feature_reduce<<<dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s>>>(m, S, part, st));
-    SCHULZE_LAUNCH(ctx, K_FEATURES, s, k_feature_norm<<<dim3(1), dim3(256), 0, s>>>(m, st, n_voters, feat));
+    const dim3 vg((unsigned)ceil_div(m, 256));
+    SCHULZE_LAUNCH(ctx, K_FEATURES, s, k_feature_max<<<vg, dim3(256), 0, s>>>(m, st, mx));
+    SCHULZE_LAUNCH(ctx, K_FEATURES, s, k_feature_norm<<<vg, dim3(256), 0, s>>>(m, st, n_voters, mx, feat));
     return SCHULZE_OK;
 }
 
@@ -224,4 +255,15 @@ extern "C" int schulze_features(schulze_ctx *ctx, void *stream, const void *d, i
     if (dtype == SCHULZE_U16)
         return run_features(ctx, s, static_cast<const uint16_t *>(d), ldd, m, mode, n_voters, feat);
     return run_features(ctx, s, static_cast<const int32_t *>(d), ldd, m, mode, n_voters, feat);
+}
+
+// Internal: features and both weight matrices in one pass over d (the
+// learned path needs all three).
+int weights_and_features(schulze_ctx *ctx, hipStream_t s, const void *d, int64_t ldd, int32_t m, int dtype, int mode,
+                         float n_voters, float *feat, void *w, int64_t ldw, void *wt, int64_t ldwt) {
+    if (dtype == SCHULZE_U16)
+        return run_features(ctx, s, static_cast<const uint16_t *>(d), ldd, m, mode, n_voters, feat,
+                            static_cast<uint16_t *>(w), ldw, static_cast<uint16_t *>(wt), ldwt);
+    return run_features(ctx, s, static_cast<const int32_t *>(d), ldd, m, mode, n_voters, feat,
+                        static_cast<int32_t *>(w), ldw, static_cast<int32_t *>(wt), ldwt);
 }

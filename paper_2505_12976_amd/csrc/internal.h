@@ -30,6 +30,7 @@ enum WsSlot {
     WS_LEARNED_P,        // learned path: closure for the fallback
     WS_PROPAGATE,        // label propagation: weights, keys, frontiers, statuses
     WS_RANKED,           // ranked closure: value bitmap, rank tables, uint16 matrix
+    WS_OCC,              // bucketed pair counting: histograms, offsets, occurrences
     WS_NUM_SLOTS
 };
 
@@ -56,6 +57,8 @@ struct schulze_ctx {
     bool value_ranking = true;
     // closure tile size: 0 = by value width and m, else 64 or 128
     int closure_tile = 0;
+    // truncated ballots: pair scattering with device-wide atomics instead of bucketing
+    bool legacy_pairs = false;
     // batch closure schedule per value width (16, 32) and bucket of 32 candidates; -1 = built-in
     int8_t batch_variant[2][SCHULZE_BATCH_MAX_M / 32];
     schulze_ctx() {
@@ -117,6 +120,11 @@ int launch_status();
 
 // Zero `words` 32-bit words with a fill kernel (graph-capture friendly).
 int fill_u32(schulze_ctx *ctx, hipStream_t s, uint32_t *ptr, size_t words, uint32_t value);
+
+// Per-candidate features (as schulze_features) and the weight matrices w and
+// w^T (as schulze_weights) in one pass over d; arguments already checked.
+int weights_and_features(schulze_ctx *ctx, hipStream_t s, const void *d, int64_t ldd, int32_t m, int dtype, int mode,
+                         float n_voters, float *feat, void *w, int64_t ldw, void *wt, int64_t ldwt);
 
 // Bind the context's device to the calling thread.
 int bind_device(schulze_ctx *ctx);

@@ -66,8 +66,9 @@ extern "C" int schulze_winners_learned(schulze_ctx *ctx, void *stream, const voi
 
     schulze_learned_stats st{};
     st.proposal = -1;
-    if ((rc = schulze_weights(ctx, stream, d, ldd, m, dtype, mode, w, m, wt, m)) != SCHULZE_OK) return rc;
-    if ((rc = schulze_features(ctx, stream, d, ldd, m, dtype, mode, n_voters, feat)) != SCHULZE_OK) return rc;
+    // weights, transposed weights and features in one pass over d
+    if ((rc = weights_and_features(ctx, s, d, ldd, m, dtype, mode, n_voters, feat, w, m, wt, m)) != SCHULZE_OK)
+        return rc;
     if ((rc = schulze_mlp_forward(ctx, stream, params, feat, m, score)) != SCHULZE_OK) return rc;
     SCHULZE_LAUNCH(ctx, K_PROPOSE, s, k_propose<<<dim3(1), dim3(256), 0, s>>>(score, feat, m, 1, small + 4));
     int32_t cand = -1;

@@ -507,6 +507,235 @@ __global__ __launch_bounds__(256) void k_count_pairs(const void *__restrict__ ba
     if (__ballot(dup) && lane == 0) set_device_error(err, SCHULZE_EBALLOT);
 }
 
+// ------------------------------------------------------------------ bucketed pair counting
+// The same sums as k_count_pairs without its random device-wide atomics into
+// the m x m accumulator: the listed entries ("occurrences") of truncated
+// ballots are first bucketed by candidate (a counting sort: per-workgroup
+// histograms in LDS, offsets, placement), and then each candidate's row of
+// C^T is accumulated in LDS from the ballot prefixes ahead of its
+// occurrences and subtracted from the accumulator row at once.  A row with
+// more than OCC_CHUNK occurrences is split over several workgroups that add
+// their partial rows with atomics.
+constexpr int OCC_CHUNK = 2048;            // occurrences per accumulation item
+constexpr int32_t OCC_MAX_M = 32768;       // an LDS row of uint32 counts
+constexpr int64_t OCC_MAX = (int64_t)1 << 27;  // occurrence buffer limit (entries)
+
+struct OccArgs {
+    const void *ballots;
+    int dtype32;
+    int32_t L, m;
+    const uint32_t *weight;
+    Meta meta;
+    uint32_t *hist;      // G x m: per-workgroup counts, then their exclusive prefix over workgroups
+    uint32_t *row_start; // m + 1: occurrences per candidate, then the exclusive scan (total at [m])
+    uint32_t *item_start;// m + 1: accumulation items per candidate, then the exclusive scan
+    uint32_t *occ_v;     // ballot of each placed occurrence
+    uint16_t *occ_t;     // its position in the ballot
+    uint32_t *acc;
+    int64_t lda;
+    uint32_t *rsum;
+    int32_t *err;
+};
+
+// Truncated-ballot slots of workgroup g: [lo, hi).
+__device__ inline void occ_slots(const Meta &meta, int32_t &lo, int32_t &hi) {
+    const int64_t nt = meta.ctr[1];
+    lo = (int32_t)(nt * blockIdx.x / gridDim.x);
+    hi = (int32_t)(nt * (blockIdx.x + 1) / gridDim.x);
+}
+
+// PLACE = false: hist[g][c] = occurrences of c in workgroup g's ballots.
+// PLACE = true:  write them to occ_v / occ_t at row_start[c] + hist[g][c] + k.
+// One wavefront per ballot, one lane per listed entry.
+template <int MAXM, bool PLACE>
+__global__ __launch_bounds__(256) void k_occ_bucket(OccArgs a) {
+    __shared__ uint32_t cnt[MAXM];
+    if (a.meta.ctr[2] != MODE_SPARSE) return;
+    const int32_t m = a.m;
+    const int64_t hrow = (int64_t)blockIdx.x * m;
+    for (int32_t c = threadIdx.x; c < m; c += 256) cnt[c] = PLACE ? a.row_start[c] + a.hist[hrow + c] : 0u;
+    __syncthreads();
+    int32_t lo, hi;
+    occ_slots(a.meta, lo, hi);
+    const int lane = threadIdx.x & 63;
+    for (int32_t slot = lo + (threadIdx.x >> 6); slot < hi; slot += 4) {
+        const int32_t v = a.meta.trunc_src[slot];
+        const int32_t k = a.meta.len[v];
+        const int64_t base = (int64_t)v * a.L;
+        for (int t = lane; t < k; t += 64) {
+            const int32_t c = read_id(a.ballots, a.dtype32, base + t);
+            if (c < 0 || c >= m) continue;  // reported by the scan
+            const uint32_t q = atomicAdd(&cnt[c], 1u);
+            if (PLACE) {
+                a.occ_v[q] = (uint32_t)v;
+                a.occ_t[q] = (uint16_t)t;
+            }
+        }
+    }
+    if (!PLACE) {
+        __syncthreads();
+        for (int32_t c = threadIdx.x; c < m; c += 256) a.hist[hrow + c] = cnt[c];
+    }
+}
+
+// Per candidate c: total occurrences (row_start[c]) and the exclusive prefix
+// of hist[.][c] over workgroups.
+__global__ __launch_bounds__(256) void k_occ_columns(OccArgs a, int32_t G) {
+    if (a.meta.ctr[2] != MODE_SPARSE) return;
+    const int32_t c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= a.m) return;
+    uint32_t run = 0;
+    for (int32_t g = 0; g < G; ++g) {
+        const uint32_t h = a.hist[(int64_t)g * a.m + c];
+        a.hist[(int64_t)g * a.m + c] = run;
+        run += h;
+    }
+    a.row_start[c] = run;
+    a.item_start[c] = (run + OCC_CHUNK - 1) / OCC_CHUNK;
+}
+
+// One workgroup: exclusive scans of the occurrence totals and item counts.
+__global__ __launch_bounds__(256) void k_occ_scan(OccArgs a) {
+    __shared__ uint32_t part[2][256];
+    if (a.meta.ctr[2] != MODE_SPARSE) return;
+    const int32_t m = a.m;
+    const int32_t per = (m + 255) / 256;
+    const int32_t c0 = threadIdx.x * per, c1 = min(m, c0 + per);
+    uint32_t so = 0, si = 0;
+    for (int32_t c = c0; c < c1; ++c) {
+        so += a.row_start[c];
+        si += a.item_start[c];
+    }
+    part[0][threadIdx.x] = so;
+    part[1][threadIdx.x] = si;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint32_t ao = (int)threadIdx.x >= off ? part[0][threadIdx.x - off] : 0u;
+        const uint32_t ai = (int)threadIdx.x >= off ? part[1][threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[0][threadIdx.x] += ao;
+        part[1][threadIdx.x] += ai;
+        __syncthreads();
+    }
+    uint32_t ro = part[0][threadIdx.x] - so, ri = part[1][threadIdx.x] - si;
+    for (int32_t c = c0; c < c1; ++c) {
+        const uint32_t o = a.row_start[c], it = a.item_start[c];
+        a.row_start[c] = ro;
+        a.item_start[c] = ri;
+        ro += o;
+        ri += it;
+    }
+    if (threadIdx.x == 255) {
+        a.row_start[m] = part[0][255];
+        a.item_start[m] = part[1][255];
+    }
+}
+
+// Accumulation item `blockIdx.x`: a chunk of one candidate's occurrences.
+// For an occurrence of candidate r at position t of ballot v, every id ahead
+// of it gains the voter's weight in row r of C^T (acc[r][.] -= w), and r
+// gains it in R (rsum[r]).  PACKED (unit weights): two 16-bit counts per LDS
+// word -- an item adds at most OCC_CHUNK to a column, so halves never carry
+// -- which halves the LDS row and doubles the resident workgroups.
+template <int MAXM, bool PACKED, typename T>
+__global__ __launch_bounds__(256) void k_occ_accumulate(OccArgs a, T *__restrict__ d, int64_t ldd, uint32_t limit,
+                                                        uint8_t *__restrict__ row_done, int acc_zero) {
+    constexpr int WORDS = PACKED ? MAXM / 2 : MAXM;
+    __shared__ __attribute__((aligned(16))) uint32_t row[WORDS];
+    __shared__ uint32_t wsum;
+    __shared__ int32_t sh_r, sh_nitems;
+    __shared__ uint32_t sh_b, sh_e;
+    if (a.meta.ctr[2] != MODE_SPARSE) return;
+    const int32_t m = a.m;
+    const uint32_t item = blockIdx.x;
+    if (item >= a.item_start[m]) return;
+    if (threadIdx.x == 0) {
+        // the candidate whose item range holds `item` (binary search)
+        int32_t lo = 0, hi = m - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (a.item_start[mid] <= item) lo = mid; else hi = mid - 1;
+        }
+        const uint32_t k = item - a.item_start[lo];
+        const uint32_t b = a.row_start[lo] + k * OCC_CHUNK;
+        sh_r = lo;
+        sh_nitems = (int32_t)(a.item_start[lo + 1] - a.item_start[lo]);
+        sh_b = b;
+        sh_e = min(a.row_start[lo + 1], b + (uint32_t)OCC_CHUNK);
+        wsum = 0;
+    }
+    const int32_t words = PACKED ? (m + 1) / 2 : m;
+    const int32_t words4 = (words + 3) / 4;
+    uint4 *row4 = reinterpret_cast<uint4 *>(row);
+    for (int32_t c = threadIdx.x; c < words4; c += 256) row4[c] = make_uint4(0u, 0u, 0u, 0u);
+    __syncthreads();
+    const int32_t r = sh_r;
+    uint32_t wpart = 0;
+    bool dup = false;
+    for (uint32_t q = sh_b + threadIdx.x; q < sh_e; q += 256) {
+        const uint32_t v = a.occ_v[q];
+        const int32_t t = a.occ_t[q];
+        const uint32_t w = PACKED ? 1u : (a.weight ? a.weight[v] : 1u);
+        wpart += w;
+        if (w == 0) continue;
+        const int64_t base = (int64_t)v * a.L;
+        for (int32_t i0 = 0; i0 < t; i0 += 8) {  // eight ids in flight
+            int32_t id[8];
+            for (int u = 0; u < 8; ++u) id[u] = i0 + u < t ? read_id(a.ballots, a.dtype32, base + i0 + u) : -1;
+            for (int u = 0; u < 8; ++u) {
+                if (id[u] == r) dup = true;
+                if (id[u] < 0 || id[u] >= m) continue;
+                if (PACKED)
+                    atomicAdd(&row[id[u] >> 1], 1u << ((id[u] & 1) * 16));
+                else
+                    atomicAdd(&row[id[u]], w);
+            }
+        }
+    }
+    if (wpart) atomicAdd(&wsum, wpart);
+    if (__ballot(dup) && (threadIdx.x & 63) == 0) set_device_error(a.err, SCHULZE_EBALLOT);
+    __syncthreads();
+    uint32_t *arow = a.acc + (int64_t)r * a.lda;
+    if (sh_nitems == 1) {
+        // the row's only item: finish it here, d[r][y] = acc[r][y] - C[y][r] + R[r]
+        // (acc holds the counts of full rankings, or nothing), and skip it in k_count_finish
+        const uint32_t R = wsum;
+        bool over = false;
+        T *drow = d + (int64_t)r * ldd;
+        for (int32_t y = threadIdx.x; y < m; y += 256) {
+            const uint32_t cnt = PACKED ? (row[y >> 1] >> ((y & 1) * 16)) & 0xFFFFu : row[y];
+            uint32_t v = 0u;
+            if (y != r) v = (acc_zero ? 0u : arow[y]) - cnt + R;
+            if (v > limit) {
+                over = true;
+                v = limit;
+            }
+            drow[y] = (T)v;
+        }
+        if (over) set_device_error(a.err, SCHULZE_ERANGE);
+        if (threadIdx.x == 0) row_done[r] = 1;
+        return;
+    }
+    auto flush = [&](int32_t c, uint32_t x) { atomicSub(&arow[c], x); };
+    for (int32_t c4 = threadIdx.x; c4 < words4; c4 += 256) {
+        const uint4 q = row4[c4];
+        if ((q.x | q.y | q.z | q.w) == 0u) continue;
+        const uint32_t wv[4] = {q.x, q.y, q.z, q.w};
+        for (int u = 0; u < 4; ++u) {
+            if (!wv[u]) continue;
+            const int32_t wi = 4 * c4 + u;
+            if (PACKED) {
+                const int32_t c = 2 * wi;
+                if ((wv[u] & 0xFFFFu) && c < m) flush(c, wv[u] & 0xFFFFu);
+                if ((wv[u] >> 16) && c + 1 < m) flush(c + 1, wv[u] >> 16);
+            } else if (wi < m) {
+                flush(wi, wv[u]);
+            }
+        }
+    }
+    if (threadIdx.x == 0 && wsum) atomicAdd(&a.rsum[r], wsum);
+}
+
 // ------------------------------------------------------------------ weighted full rankings
 // Full rankings with voter weights: plain compare-and-add per voter (the
 // modular trick needs unit weights to bound a segment's total).
@@ -535,24 +764,30 @@ __global__ __launch_bounds__(256) void k_count_full_weighted(const uint32_t *__r
 template <typename T>
 __global__ __launch_bounds__(256) void k_count_finish(const uint32_t *__restrict__ acc, int64_t lda,
                                                       const uint32_t *__restrict__ rsum, Meta meta, int32_t m,
-                                                      T *__restrict__ d, int64_t ldd, uint32_t limit, int32_t *err) {
-    const int32_t col_blocks = (m + 255) / 256;
-    const int32_t x = blockIdx.x / col_blocks;
-    const int32_t y = (blockIdx.x % col_blocks) * 256 + threadIdx.x;
-    if (y >= m) return;
+                                                      T *__restrict__ d, int64_t ldd, uint32_t limit, int32_t *err,
+                                                      const uint8_t *__restrict__ row_done) {
+    // one workgroup per row x
+    const int32_t x = blockIdx.x;
+    if (row_done && meta.ctr[2] == MODE_SPARSE && row_done[x]) return;  // written by the bucketed count
     const bool dense_u = meta.ctr[2] == MODE_DENSE_U;
-    uint32_t v = 0u;
-    if (x != y) {
-        v = acc[(int64_t)x * lda + y];
-        // pair scattering: acc holds -C^T, add R[x]; dense over U: U x U is
-        // complete, x in U beats every y outside U on the R[x] ballots
-        if (!dense_u || (meta.in_u[x] && !meta.in_u[y])) v += rsum[x];
+    const uint32_t rx = rsum[x];
+    const bool in_x = dense_u && meta.in_u[x];
+    bool over = false;
+    for (int32_t y = threadIdx.x; y < m; y += 256) {
+        uint32_t v = 0u;
+        if (x != y) {
+            v = acc[(int64_t)x * lda + y];
+            // pair scattering: acc holds -C^T, add R[x]; dense over U: U x U is
+            // complete, x in U beats every y outside U on the R[x] ballots
+            if (!dense_u || (in_x && !meta.in_u[y])) v += rx;
+        }
+        if (v > limit) {
+            over = true;
+            v = limit;
+        }
+        d[(int64_t)x * ldd + y] = (T)v;
     }
-    if (v > limit) {
-        set_device_error(err, SCHULZE_ERANGE);
-        v = limit;
-    }
-    d[(int64_t)x * ldd + y] = (T)v;
+    if (over) set_device_error(err, SCHULZE_ERANGE);
 }
 
 // Byte layout of WS_BALLOT_META for n ballots and m candidates.
@@ -576,6 +811,50 @@ struct MetaLayout {
         total = o;
     }
 };
+
+// Byte layout of WS_OCC for G bucketing workgroups, m candidates and at
+// most cap occurrences.
+struct OccLayout {
+    size_t hist, row_start, item_start, occ_v, occ_t, row_done, total;
+    OccLayout(int64_t G, int32_t m, int64_t cap) {
+        size_t o = 0;
+        auto take = [&](size_t bytes) {
+            size_t at = o;
+            o += (bytes + 255) / 256 * 256;
+            return at;
+        };
+        hist = take(sizeof(uint32_t) * (size_t)G * m);
+        row_start = take(sizeof(uint32_t) * ((size_t)m + 1));
+        item_start = take(sizeof(uint32_t) * ((size_t)m + 1));
+        occ_v = take(sizeof(uint32_t) * (size_t)cap);
+        occ_t = take(sizeof(uint16_t) * (size_t)cap);
+        row_done = take((size_t)m);
+        total = o;
+    }
+};
+
+// The accumulation launch for the counter type T of d: packed 16-bit LDS
+// counts for unit weights, 32-bit ones otherwise; the LDS row fits m.
+template <typename T>
+int occ_accumulate(schulze_ctx *ctx, hipStream_t s, const OccArgs &oa, dim3 grid, int32_t m, bool weighted, T *d,
+                   int64_t ldd, uint32_t limit, uint8_t *row_done, bool acc_zero) {
+    const dim3 b(256);
+    const int az = acc_zero ? 1 : 0;
+    if (!weighted && m <= OCC_MAX_M / 2) {
+        SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
+                       (k_occ_accumulate<OCC_MAX_M / 2, true, T><<<grid, b, 0, s>>>(oa, d, ldd, limit, row_done, az)));
+    } else if (!weighted) {
+        SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
+                       (k_occ_accumulate<OCC_MAX_M, true, T><<<grid, b, 0, s>>>(oa, d, ldd, limit, row_done, az)));
+    } else if (m <= OCC_MAX_M / 2) {
+        SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
+                       (k_occ_accumulate<OCC_MAX_M / 2, false, T><<<grid, b, 0, s>>>(oa, d, ldd, limit, row_done, az)));
+    } else {
+        SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
+                       (k_occ_accumulate<OCC_MAX_M, false, T><<<grid, b, 0, s>>>(oa, d, ldd, limit, row_done, az)));
+    }
+    return SCHULZE_OK;
+}
 
 // Truncated positions in U space are reserved up to this many bytes; beyond
 // it the route decision falls back to pair scattering.
@@ -614,6 +893,12 @@ extern "C" int schulze_pairwise(schulze_ctx *ctx, void *stream, const void *ball
         (rc = ws_reserve(ctx, WS_POSITIONS, sizeof(uint32_t) * (size_t)max_pairs * pitch)) != SCHULZE_OK)
         return rc;
     if (tpos_bytes && (rc = ws_reserve(ctx, WS_TRUNC_POS, tpos_bytes)) != SCHULZE_OK) return rc;
+    // bucketed pair counting: an LDS row of counts per candidate and a bounded occurrence buffer
+    const int64_t occ_cap = n * (int64_t)L;
+    const bool occ_ok = n > 0 && m <= OCC_MAX_M && occ_cap <= OCC_MAX && !ctx->legacy_pairs;
+    const int64_t occ_grid = (int64_t)ctx->num_cus * (m <= OCC_MAX_M / 2 ? 2 : 1);
+    const OccLayout ol(occ_ok ? occ_grid : 0, m, occ_ok ? occ_cap : 0);
+    if (occ_ok && (rc = ws_reserve(ctx, WS_OCC, ol.total)) != SCHULZE_OK) return rc;
 
     char *mb = static_cast<char *>(ctx->ws[WS_BALLOT_META]);
     Meta meta{reinterpret_cast<int32_t *>(mb + lay.ctr),
@@ -638,6 +923,7 @@ extern "C" int schulze_pairwise(schulze_ctx *ctx, void *stream, const void *ball
     if ((rc = fill_u32(ctx, s, acc, (size_t)m * m, 0u)) != SCHULZE_OK) return rc;
     if ((rc = fill_u32(ctx, s, rsum, (size_t)m, 0u)) != SCHULZE_OK) return rc;
 
+    uint8_t *row_done = nullptr;  // rows finished by the bucketed count
     if (n > 0) {
         if (L <= 64) {
             constexpr int per_wg = 4 * SHORT_PER_WAVE;
@@ -676,19 +962,59 @@ extern "C" int schulze_pairwise(schulze_ctx *ctx, void *stream, const void *ball
             DenseArgs da{tpos, 0, m, meta, acc, lda, rsum};
             SCHULZE_LAUNCH(ctx, K_COUNT_TRUNC, s, k_count_pos<true><<<dim3(cgrid), dim3(CNT_THREADS), 0, s>>>(da));
         }
-        SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
-                       k_count_pairs<<<dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, s>>>(
-                           ballots, dtype32, L, m, voter_weight, meta, acc, lda, rsum, ctx->err));
+        if (occ_ok) {
+            // bucketed pair counting (runs only if the device chose pair scattering)
+            char *ob = static_cast<char *>(ctx->ws[WS_OCC]);
+            OccArgs oa{ballots, dtype32, L, m, voter_weight, meta,
+                       reinterpret_cast<uint32_t *>(ob + ol.hist),
+                       reinterpret_cast<uint32_t *>(ob + ol.row_start),
+                       reinterpret_cast<uint32_t *>(ob + ol.item_start),
+                       reinterpret_cast<uint32_t *>(ob + ol.occ_v),
+                       reinterpret_cast<uint16_t *>(ob + ol.occ_t),
+                       acc, lda, rsum, ctx->err};
+            const dim3 g(occ_grid), b(256);
+            row_done = reinterpret_cast<uint8_t *>(ob + ol.row_done);
+            if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(row_done), (size_t)ceil_div(m, 4), 0u)) !=
+                SCHULZE_OK)
+                return rc;
+            if (m <= OCC_MAX_M / 2) {
+                SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s, k_occ_bucket<OCC_MAX_M / 2, false><<<g, b, 0, s>>>(oa));
+            } else {
+                SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s, k_occ_bucket<OCC_MAX_M, false><<<g, b, 0, s>>>(oa));
+            }
+            SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
+                           k_occ_columns<<<dim3((unsigned)ceil_div(m, 256)), b, 0, s>>>(oa, (int32_t)occ_grid));
+            SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s, k_occ_scan<<<dim3(1), b, 0, s>>>(oa));
+            const dim3 ig((unsigned)(m + ceil_div(occ_cap, OCC_CHUNK)));
+            if (m <= OCC_MAX_M / 2) {
+                SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s, k_occ_bucket<OCC_MAX_M / 2, true><<<g, b, 0, s>>>(oa));
+            } else {
+                SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s, k_occ_bucket<OCC_MAX_M, true><<<g, b, 0, s>>>(oa));
+            }
+            if (d_dtype == SCHULZE_U16) {
+                if ((rc = occ_accumulate<uint16_t>(ctx, s, oa, ig, m, voter_weight != nullptr, (uint16_t *)d, ldd,
+                                                   65535u, row_done, !may_have_full)) != SCHULZE_OK)
+                    return rc;
+            } else {
+                if ((rc = occ_accumulate<int32_t>(ctx, s, oa, ig, m, voter_weight != nullptr, (int32_t *)d, ldd,
+                                                  (uint32_t)INT32_MAX, row_done, !may_have_full)) != SCHULZE_OK)
+                    return rc;
+            }
+        } else {
+            SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
+                           k_count_pairs<<<dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, s>>>(
+                               ballots, dtype32, L, m, voter_weight, meta, acc, lda, rsum, ctx->err));
+        }
     }
-    dim3 fgrid((unsigned)(ceil_div(m, 256) * m));
+    dim3 fgrid((unsigned)m);
     if (d_dtype == SCHULZE_U16) {
         SCHULZE_LAUNCH(ctx, K_COUNT_FINISH, s,
                        k_count_finish<uint16_t><<<fgrid, dim3(256), 0, s>>>(acc, lda, rsum, meta, m, (uint16_t *)d, ldd,
-                                                                            65535u, ctx->err));
+                                                                            65535u, ctx->err, row_done));
     } else {
         SCHULZE_LAUNCH(ctx, K_COUNT_FINISH, s,
                        k_count_finish<int32_t><<<fgrid, dim3(256), 0, s>>>(acc, lda, rsum, meta, m, (int32_t *)d, ldd,
-                                                                           (uint32_t)INT32_MAX, ctx->err));
+                                                                           (uint32_t)INT32_MAX, ctx->err, row_done));
     }
     return SCHULZE_OK;
 }
