@@ -113,11 +113,34 @@ def bench_learned(args):
 
     learned()  # warm-up
     t_learned = []
+    ctx.reset_timing()
+    ctx.set_timing(True)
     for _ in range(max(args.steps, 1)):
         t0 = time.perf_counter()
         w_l, st = learned()
         t_learned.append(time.perf_counter() - t0)
+    ctx.set_timing(False)
     print(f"[bench] learned {np.median(t_learned) * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    # per-kernel times of the learned path (HIP events on the launch stream)
+    kern = {}
+    for nm in ("weights", "feature_rows", "features", "mlp_prepare", "mlp_forward", "propose", "widest", "verdict",
+               "fill"):
+        launches, total = ctx.kernel_time(nm)
+        if launches:
+            kern[nm] = {"launches_per_call": launches / len(t_learned), "ms_per_call": total / len(t_learned),
+                        "avg_launch_ms": total / launches}
+    # dominant kernel: the pass that reads d and writes w, w^T and the
+    # per-candidate statistics (HBM-bound): d read once, w and w^T written once
+    es = 4
+    w_bytes = 3 * es * m * m
+    roof = None
+    if "feature_rows" in kern:
+        ach = w_bytes / (kern["feature_rows"]["avg_launch_ms"] / 1e3) / 1e9
+        roof = {"bound": "hbm", "kernel": "feature_rows (weights, transposed weights, statistics)",
+                "achieved": ach, "peak": HBM_BYTES / 1e9, "unit": "GB/s",
+                "frac": ach * 1e9 / HBM_BYTES, "traffic": None, "algorithmic_bytes": w_bytes}
+    if "widest" in kern:
+        kern["widest"]["note"] = "one launch per direction runs all sweeps to the fixpoint"
     t_full = []
     for _ in range(2):
         t0 = time.perf_counter()
@@ -166,6 +189,8 @@ def bench_learned(args):
         "closure_gops": m ** 3 / tf / 1e9,
         "ms_full_closure_int32_values": t_full_i32 * 1e3,
         "ms_label_propagation": tp * 1e3,
+        "kernels_learned": kern,
+        "roofline": roof,
         "label_propagation_stats": st_p,
         "exact": exact,
         "exact_label_propagation": exact_prop,
@@ -321,6 +346,8 @@ def bench_batch(args):
 def cpu_baseline(wl, sample_voters):
     """Oracle on a bounded sample: the count over the first `sample_voters`
     ballots (scaled to all n), then weights, closure and ranking at full m."""
+    import numpy as np
+
     import oracle
     ns = min(sample_voters, wl.n)
     sample = wl.ballots[:ns]
@@ -334,6 +361,22 @@ def cpu_baseline(wl, sample_voters):
     t_rest = time.perf_counter() - t0
     t_step = t_count + t_rest
     cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    # one thread, as the paper times its sequential baseline: count over a
+    # smaller sample, closure at m1 = min(m, 1024) extrapolated by (m / m1)^3
+    prev = oracle.set_threads(1)
+    try:
+        ns1 = min(max(1, sample_voters // 10), wl.n)
+        t0 = time.perf_counter()
+        oracle.pairwise(wl.ballots[:ns1], wl.m)
+        t_count1 = (time.perf_counter() - t0) * (wl.n / ns1)
+        m1 = min(wl.m, 1024)
+        w1 = np.ascontiguousarray(w[:m1, :m1])
+        t0 = time.perf_counter()
+        oracle.closure(w1)
+        t_close1 = (time.perf_counter() - t0) * (wl.m / m1) ** 3
+    finally:
+        oracle.set_threads(prev)
+    t_step1 = t_count1 + t_close1
     return {
         "value": wl.m ** 3 / t_step / 1e9,
         "unit": "Gop/s",
@@ -342,6 +385,12 @@ def cpu_baseline(wl, sample_voters):
         "sample": (f"count over the first {ns} of {wl.n} ballots scaled by n/{ns} "
                    f"({t_count:.1f} s scaled); weights+closure+ranking at full m={wl.m} ({t_rest:.1f} s)"),
         "seconds_per_step": t_step,
+        "single_thread": {
+            "value": wl.m ** 3 / t_step1 / 1e9, "unit": "Gop/s", "cores": 1,
+            "seconds_per_step": t_step1, "extrapolated": True,
+            "sample": (f"count over the first {ns1} ballots scaled by n/{ns1} ({t_count1:.1f} s scaled); "
+                       f"closure of the leading {m1} x {m1} block of w scaled by (m/{m1})^3 ({t_close1:.1f} s)"),
+        },
     }
 
 

@@ -68,8 +68,9 @@ def _load():
     lib.oracle_rank.argtypes = [vp, i32, vp, vp, vp]
     lib.oracle_widest_from.argtypes = [vp, i32, i32, vp]
     lib.oracle_widest_to.argtypes = [vp, i32, i32, vp]
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
     for name in ("oracle_pairwise", "oracle_pairwise_rows", "oracle_pairwise_cols", "oracle_weights",
-                 "oracle_closure", "oracle_rank", "oracle_widest_from", "oracle_widest_to"):
+                 "oracle_closure", "oracle_rank", "oracle_widest_from", "oracle_widest_to", "oracle_set_threads"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -204,6 +205,11 @@ def topk_levels(w: np.ndarray, k: int) -> np.ndarray:
         ranked += len(win)
         rnd += 1
     return level
+
+
+def set_threads(threads: int) -> int:
+    """Threads of the oracle's parallel loops (timing only); returns the previous count."""
+    return int(_load().oracle_set_threads(int(threads)))
 
 
 def schulze(ballots: np.ndarray, m: int, mode: int = WINNING_VOTES, weight=None) -> dict:

@@ -34,6 +34,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 #define ORC_OK 0
 #define ORC_EINVAL -1
@@ -287,4 +288,12 @@ int oracle_widest_from(const int64_t *w, int32_t m, int32_t s, int64_t *out) {
 int oracle_widest_to(const int64_t *w, int32_t m, int32_t t, int64_t *out) {
     if (!w || !out || m < 1 || t < 0 || t >= m) return ORC_EINVAL;
     return widest_dijkstra(w, m, t, 1, out);
+}
+
+/* Threads used by the parallel loops above (timing only: results do not depend on it);
+ * returns the count in effect before the call. */
+int oracle_set_threads(int threads) {
+    const int before = omp_get_max_threads();
+    if (threads > 0) omp_set_num_threads(threads);
+    return before;
 }

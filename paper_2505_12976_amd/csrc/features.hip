@@ -230,7 +230,7 @@ int run_features(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32
     if ((rc = fill_u32(ctx, s, mx, 4, 0u)) != SCHULZE_OK) return rc;
     const int vec = (tio::vec_ok<E>(d, ldd) ? 1 : 0) | (tio::vec_ok<E>(w, ldw) ? 2 : 0) |
                     (tio::vec_ok<E>(wt, ldwt) ? 4 : 0);
-    SCHULZE_LAUNCH(ctx, K_FEATURES, s,
+    SCHULZE_LAUNCH(ctx, K_FEATURE_ROWS, s,
                    k_feature_rows<E><<<dim3((unsigned)nbx, (unsigned)S), dim3(256), 0, s>>>(
                        d, ldd, m, mode, part, vec, w, ldw, wt, ldwt));
     SCHULZE_LAUNCH(ctx, K_FEATURES, s,

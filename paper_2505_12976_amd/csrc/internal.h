@@ -99,6 +99,7 @@ enum KernelId {
     K_PROP,
     K_PROP_SWEEP,
     K_RANK,
+    K_FEATURE_ROWS,
     K_NUM_KERNELS
 };
 extern const char *const kKernelNames[K_NUM_KERNELS];

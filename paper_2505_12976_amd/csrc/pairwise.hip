@@ -175,12 +175,15 @@ __global__ __launch_bounds__(256) void k_scan_short(const void *__restrict__ bal
 // ------------------------------------------------------------------ route decision
 // One workgroup: U-space compaction (prefix sum over candidates) and the
 // choice between the dense route over U and pair scattering for truncated
-// ballots.  Costs: dense ~ (n_T / 2) * pitch^2 lane-ops, scattering
-// ~ sum k(k-1)/2 atomics, an atomic charged as ATOMIC_COST lane-ops (about
-// the measured ratio of the two rates on MI355X).
-constexpr double ATOMIC_COST = 1024.0;
+// ballots.  Costs: dense ~ (n_T / 2) * pitch^2 lane-ops, pair counting
+// ~ sum k(k-1)/2 pairs, a pair charged as pair_cost lane-ops (about the
+// measured ratio of the two rates on MI355X: 1024 for device-wide atomics,
+// 512 for the bucketed count).
+constexpr double ATOMIC_PAIR_COST = 1024.0;
+constexpr double BUCKETED_PAIR_COST = 512.0;
 
-__global__ __launch_bounds__(256) void k_route(int32_t m, Meta meta, int weighted, int64_t cap_words) {
+__global__ __launch_bounds__(256) void k_route(int32_t m, Meta meta, int weighted, int64_t cap_words,
+                                               double pair_cost) {
     __shared__ int32_t part[256];
     const int32_t per = (m + 255) / 256;
     const int32_t c0 = min(m, (int32_t)threadIdx.x * per), c1 = min(m, c0 + per);
@@ -212,7 +215,7 @@ __global__ __launch_bounds__(256) void k_route(int32_t m, Meta meta, int weighte
         const int64_t pairs = (n_t + 1) / 2;
         const double dense = (double)pairs * (double)pitch * (double)pitch;
         const bool fits = pairs * (int64_t)pitch <= cap_words;
-        const bool use_dense = !weighted && fits && n_t > 0 && dense <= ATOMIC_COST * (double)k2;
+        const bool use_dense = !weighted && fits && n_t > 0 && dense <= pair_cost * (double)k2;
         meta.ctr[2] = use_dense ? MODE_DENSE_U : MODE_SPARSE;
         meta.ctr[3] = nu;
         meta.ctr[4] = pitch;
@@ -937,7 +940,8 @@ extern "C" int schulze_pairwise(schulze_ctx *ctx, void *stream, const void *ball
         }
         SCHULZE_LAUNCH(ctx, K_ROUTE, s,
                        k_route<<<dim3(1), dim3(256), 0, s>>>(m, meta, voter_weight != nullptr,
-                                                             (int64_t)(tpos_bytes / sizeof(uint32_t))));
+                                                             (int64_t)(tpos_bytes / sizeof(uint32_t)),
+                                                             occ_ok ? BUCKETED_PAIR_COST : ATOMIC_PAIR_COST));
         const unsigned cgrid = (unsigned)ctx->num_cus * 2;
         if (may_have_full) {
             uint32_t *pos = static_cast<uint32_t *>(ctx->ws[WS_POSITIONS]);
