@@ -715,7 +715,8 @@ __global__ __launch_bounds__(256) void k_occ_accumulate(OccArgs a, T *__restrict
             }
             drow[y] = (T)v;
         }
-        if (over) set_device_error(a.err, SCHULZE_ERANGE);
+        // reported by k_count_finish, after every ballot error of this launch
+        if (over) row_done[m] = 1;
         if (threadIdx.x == 0) row_done[r] = 1;
         return;
     }
@@ -771,7 +772,11 @@ __global__ __launch_bounds__(256) void k_count_finish(const uint32_t *__restrict
                                                       const uint8_t *__restrict__ row_done) {
     // one workgroup per row x
     const int32_t x = blockIdx.x;
-    if (row_done && meta.ctr[2] == MODE_SPARSE && row_done[x]) return;  // written by the bucketed count
+    if (row_done && meta.ctr[2] == MODE_SPARSE) {
+        // rows written by the bucketed count; row_done[m]: one of them overflowed
+        if (x == 0 && threadIdx.x == 0 && row_done[m]) set_device_error(err, SCHULZE_ERANGE);
+        if (row_done[x]) return;
+    }
     const bool dense_u = meta.ctr[2] == MODE_DENSE_U;
     const uint32_t rx = rsum[x];
     const bool in_x = dense_u && meta.in_u[x];
@@ -831,7 +836,7 @@ struct OccLayout {
         item_start = take(sizeof(uint32_t) * ((size_t)m + 1));
         occ_v = take(sizeof(uint32_t) * (size_t)cap);
         occ_t = take(sizeof(uint16_t) * (size_t)cap);
-        row_done = take((size_t)m);
+        row_done = take((size_t)m + 1);  // one flag per row, then the overflow flag
         total = o;
     }
 };
@@ -978,7 +983,7 @@ extern "C" int schulze_pairwise(schulze_ctx *ctx, void *stream, const void *ball
                        acc, lda, rsum, ctx->err};
             const dim3 g(occ_grid), b(256);
             row_done = reinterpret_cast<uint8_t *>(ob + ol.row_done);
-            if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(row_done), (size_t)ceil_div(m, 4), 0u)) !=
+            if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(row_done), (size_t)ceil_div(m + 1, 4), 0u)) !=
                 SCHULZE_OK)
                 return rc;
             if (m <= OCC_MAX_M / 2) {
