@@ -53,7 +53,7 @@ constexpr int SMEM_WORDS = STAGE_WORDS + SRED_WORDS + 64;
 constexpr int SEG_PAIRS = 32767;           // at most 65534 voters per exact sum
 constexpr int64_t SCAN_WORDS = 1 << 20;    // rank-pair words written per scan item
 constexpr int SCAN_GROUP_WORDS = 16384;    // rank-pair words staged at once by a scan
-constexpr int SCAN_UNROLL = 64;            // ballot loads in flight per thread
+constexpr int SCAN_VEC = 16;              // 16-byte ballot loads in flight per thread
 constexpr int SCAN_GROUP_PAIRS = 32;      // voter pairs staged at once by a scan, at most
 constexpr int MAX_PF = 8;                  // 16-byte loads per thread per count chunk
 constexpr uint16_t UNSET = 0xFFFF;
@@ -191,29 +191,58 @@ __device__ __attribute__((noinline)) void scan_item(const BatchArgs &a, const BE
         __syncthreads();
         const int64_t base = el.ballot_off + v0 * (int64_t)L;  // ballots of the group are contiguous
         const int32_t entries = nballots * L;                // < 2^16
-        // SCAN_UNROLL unconditional loads in flight per thread (entries past the
-        // group re-read its last entry and are skipped), then their scatter
-        for (int32_t f0 = tid; f0 < entries; f0 += BT * SCAN_UNROLL) {
-            Id raw[SCAN_UNROLL];
+        // entry f of the group: id -> LDS (ballot b = f / L at position t)
+        auto take = [&](int32_t f, int32_t id) {
+            const int32_t b = (int32_t)div_small((uint32_t)f, inv_l) + (L == 1 ? f : 0);  // inv_l = 0 if L = 1
+            const int32_t t = f - b * L;
+            bad |= id >= m;
+            if ((uint32_t)id < (uint32_t)m) buf[(b >> 1) * 2 * pitch + 2 * id + (b & 1)] = (uint16_t)t;
+            if (id < 0) {  // padding: rare, and never in complete elections' valid ballots
+                atomicAdd(&npads[b], 1);
+                atomicMin(&first_pad[b], t);
+            }
+        };
+        // 16-byte loads over the aligned span that covers the entries (its
+        // head lies inside the ballot array before them and is skipped), the
+        // last partial vector entry by entry; SCAN_VEC loads in flight per
+        // thread, issued unconditionally (clamped) before any is used
+        constexpr int V = 16 / (int)sizeof(Id);
+        const int64_t a0 = base & ~(int64_t)(V - 1);
+        const int64_t end = base + entries;
+        const int64_t vend = end & ~(int64_t)(V - 1);
+        const int32_t nvec = vend > a0 ? (int32_t)((vend - a0) / V) : 0;
+        const FW_GLOBAL v4u32 *bv = (const FW_GLOBAL v4u32 *)(ballots + a0);
+        for (int32_t k0 = tid; k0 < nvec; k0 += BT * SCAN_VEC) {
+            v4u32 raw[SCAN_VEC];
 #pragma unroll
-            for (int j = 0; j < SCAN_UNROLL; ++j) {
-                const int32_t f = f0 + BT * j;
-                raw[j] = ballots[base + (f < entries ? f : entries - 1)];
+            for (int j = 0; j < SCAN_VEC; ++j) {
+                const int32_t k = k0 + BT * j;
+                raw[j] = bv[k < nvec ? k : nvec - 1];
             }
 #pragma unroll
-            for (int j = 0; j < SCAN_UNROLL; ++j) {
-                const int32_t f = f0 + BT * j;
-                const bool in = f < entries;  // else past the group's entries (b, t unused)
-                const int32_t id = ballot_id(raw[j]);
-                const int32_t b = (int32_t)div_small((uint32_t)f, inv_l) + (L == 1 ? f : 0);  // inv_l = 0 if L = 1
-                const int32_t t = f - b * L;
-                bad |= in && id >= m;
-                if (in && (uint32_t)id < (uint32_t)m) buf[(b >> 1) * 2 * pitch + 2 * id + (b & 1)] = (uint16_t)t;
-                if (in && id < 0) {  // padding: rare, and never in complete elections' valid ballots
-                    atomicAdd(&npads[b], 1);
-                    atomicMin(&first_pad[b], t);
+            for (int j = 0; j < SCAN_VEC; ++j) {
+                const int32_t k = k0 + BT * j;
+                if (k >= nvec) break;
+                const uint32_t w[4] = {raw[j].x, raw[j].y, raw[j].z, raw[j].w};
+                const int32_t f0 = (int32_t)(a0 + (int64_t)k * V - base);  // entry of the first id (may be < 0)
+#pragma unroll
+                for (int u = 0; u < V; ++u) {
+                    const int32_t f = f0 + u;
+                    if (f < 0 || f >= entries) continue;
+                    int32_t id;
+                    if constexpr (sizeof(Id) == 2)
+                        id = ballot_id((uint16_t)((w[u >> 1] >> ((u & 1) * 16)) & 0xFFFFu));
+                    else
+                        id = ballot_id((int32_t)w[u]);
+                    take(f, id);
                 }
             }
+        }
+        // entries after the last whole vector
+        {
+            const int64_t t0 = vend > base ? vend : base;
+            const int32_t nt = (int32_t)(end - t0);
+            if (tid < nt) take((int32_t)(t0 + tid - base), ballot_id(ballots[t0 + tid]));
         }
         __syncthreads();
         // four words per thread: one voter pair's columns c .. c+3 (pitch is a multiple of 8)
