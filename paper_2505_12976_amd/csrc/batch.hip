@@ -225,16 +225,36 @@ __device__ __attribute__((noinline)) void scan_item(const BatchArgs &a, const BE
                 if (k >= nvec) break;
                 const uint32_t w[4] = {raw[j].x, raw[j].y, raw[j].z, raw[j].w};
                 const int32_t f0 = (int32_t)(a0 + (int64_t)k * V - base);  // entry of the first id (may be < 0)
-#pragma unroll
-                for (int u = 0; u < V; ++u) {
-                    const int32_t f = f0 + u;
-                    if (f < 0 || f >= entries) continue;
-                    int32_t id;
+                auto id_of = [&](int u) -> int32_t {
                     if constexpr (sizeof(Id) == 2)
-                        id = ballot_id((uint16_t)((w[u >> 1] >> ((u & 1) * 16)) & 0xFFFFu));
+                        return ballot_id((uint16_t)((w[u >> 1] >> ((u & 1) * 16)) & 0xFFFFu));
                     else
-                        id = ballot_id((int32_t)w[u]);
-                    take(f, id);
+                        return ballot_id((int32_t)w[u]);
+                };
+                if (f0 >= 0 && f0 + V <= entries) {
+                    // whole vector inside the group: ballot and position once, then stepped
+                    int32_t b = (int32_t)div_small((uint32_t)f0, inv_l) + (L == 1 ? f0 : 0);
+                    int32_t t = f0 - b * L;
+                    int32_t row = (b >> 1) * 2 * pitch + (b & 1);
+#pragma unroll
+                    for (int u = 0; u < V; ++u) {
+                        const int32_t id = id_of(u);
+                        if ((uint32_t)id < (uint32_t)m)
+                            buf[row + 2 * id] = (uint16_t)t;
+                        else
+                            take(f0 + u, id);  // padding or out of range
+                        if (++t == L) {
+                            t = 0;
+                            ++b;
+                            row = (b >> 1) * 2 * pitch + (b & 1);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < V; ++u) {
+                        const int32_t f = f0 + u;
+                        if (f >= 0 && f < entries) take(f, id_of(u));
+                    }
                 }
             }
         }
@@ -255,21 +275,40 @@ __device__ __attribute__((noinline)) void scan_item(const BatchArgs &a, const BE
             const uint32_t words[4] = {in4.x, in4.y, in4.z, in4.w};
             uint32_t out[4];
             int32_t un_lo = 0, un_hi = 0;
+            if (c0 + 4 <= m) {  // all four columns are candidates
+                const uint32_t fill = complete ? (uint32_t)(m - 1) : UNSET;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                uint32_t lo = words[e] & 0xFFFFu, hi = words[e] >> 16;
-                if (c0 + e < m) {
-                    un_lo += lo == UNSET ? 1 : 0;
-                    un_hi += (has_hi && hi == UNSET) ? 1 : 0;
-                    if (complete) {
-                        if (lo == UNSET) lo = (uint32_t)(m - 1);
-                        if (hi == UNSET) hi = (uint32_t)(m - 1);
-                    }
-                } else {
-                    lo = hi = 0u;
+                for (int e = 0; e < 4; ++e) {
+                    uint32_t lo = words[e] & 0xFFFFu, hi = words[e] >> 16;
+                    const bool ul = lo == UNSET, uh = hi == UNSET;
+                    un_lo += ul ? 1 : 0;
+                    un_hi += uh ? 1 : 0;
+                    lo = ul ? fill : lo;
+                    hi = uh ? fill : hi;
+                    out[e] = lo | (hi << 16);
                 }
-                if (!has_hi) hi = 0u;  // missing partner of an odd count: equal ranks, counts nothing
-                out[e] = lo | (hi << 16);
+                if (!has_hi) {  // missing partner of an odd count: equal ranks, counts nothing
+                    un_hi = 0;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) out[e] &= 0xFFFFu;
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    uint32_t lo = words[e] & 0xFFFFu, hi = words[e] >> 16;
+                    if (c0 + e < m) {
+                        un_lo += lo == UNSET ? 1 : 0;
+                        un_hi += (has_hi && hi == UNSET) ? 1 : 0;
+                        if (complete) {
+                            if (lo == UNSET) lo = (uint32_t)(m - 1);
+                            if (hi == UNSET) hi = (uint32_t)(m - 1);
+                        }
+                    } else {
+                        lo = hi = 0u;
+                    }
+                    if (!has_hi) hi = 0u;
+                    out[e] = lo | (hi << 16);
+                }
             }
             if (un_lo) atomicAdd(&unset[2 * q], un_lo);
             if (un_hi) atomicAdd(&unset[2 * q + 1], un_hi);
