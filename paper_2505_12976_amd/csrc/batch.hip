@@ -666,12 +666,27 @@ __device__ void finish_t(const BatchArgs &a, const BElec &el, int32_t e, uint32_
         for (int32_t I = 0; I < nt; ++I) {
             for (int32_t J = 0; J < nt; ++J) {
                 __syncthreads();
-                for (int q = tid; q < 64 * 64; q += BT) {
+                // all 32 loads in flight at once: addresses clamped into the matrix
+                // (a conditional load would wait for the ones before it)
+                constexpr int PER = 64 * 64 / BT;
+                int32_t va[PER], vb[PER];
+#pragma unroll
+                for (int k = 0; k < PER; ++k) {
+                    const int q = tid + k * BT;
                     const int r = q >> 6, c = q & 63;
-                    const int32_t i = I * 64 + r, j = J * 64 + c;
-                    ta[r * 65 + c] = (i < m && j < m) ? D[(int64_t)i * m + j] : 0;
-                    const int32_t i2 = J * 64 + r, j2 = I * 64 + c;
-                    tb[r * 65 + c] = (i2 < m && j2 < m) ? D[(int64_t)i2 * m + j2] : 0;
+                    const int32_t i = min(I * 64 + r, m - 1), j = min(J * 64 + c, m - 1);
+                    const int32_t i2 = min(J * 64 + r, m - 1), j2 = min(I * 64 + c, m - 1);
+                    va[k] = D[(int64_t)i * m + j];
+                    vb[k] = D[(int64_t)i2 * m + j2];
+                }
+#pragma unroll
+                for (int k = 0; k < PER; ++k) {
+                    const int q = tid + k * BT;
+                    const int r = q >> 6, c = q & 63;
+                    const bool in_a = I * 64 + r < m && J * 64 + c < m;
+                    const bool in_b = J * 64 + r < m && I * 64 + c < m;
+                    ta[r * 65 + c] = in_a ? va[k] : 0;
+                    tb[r * 65 + c] = in_b ? vb[k] : 0;
                 }
                 __syncthreads();
                 for (int q = tid; q < 64 * 64; q += BT) {
@@ -702,12 +717,23 @@ __device__ void finish_t(const BatchArgs &a, const BElec &el, int32_t e, uint32_
         for (int32_t I = 0; I < mt; ++I) {      // block of x
             for (int32_t J = 0; J < mt; ++J) {  // block of y
                 __syncthreads();
-                for (int q = tid; q < 64 * 64; q += BT) {
+                constexpr int PER = 64 * 64 / BT;
+                int32_t va[PER], vb[PER];
+#pragma unroll
+                for (int k = 0; k < PER; ++k) {  // clamped, unconditional loads
+                    const int q = tid + k * BT;
                     const int r = q >> 6, c = q & 63;
-                    const int32_t y = J * 64 + r, x = I * 64 + c;    // ta[y][x] = P[y][x]
-                    const int32_t x2 = I * 64 + r, y2 = J * 64 + c;  // tb[x][y] = P[x][y]
-                    ta[r * 65 + c] = (y < m && x < m) ? (int32_t)P[(int64_t)y * mp + x] : 0;
-                    tb[r * 65 + c] = (x2 < m && y2 < m) ? (int32_t)P[(int64_t)x2 * mp + y2] : 0;
+                    const int32_t y = min(J * 64 + r, m - 1), x = min(I * 64 + c, m - 1);    // ta[y][x] = P[y][x]
+                    const int32_t x2 = min(I * 64 + r, m - 1), y2 = min(J * 64 + c, m - 1);  // tb[x][y] = P[x][y]
+                    va[k] = (int32_t)P[(int64_t)y * mp + x];
+                    vb[k] = (int32_t)P[(int64_t)x2 * mp + y2];
+                }
+#pragma unroll
+                for (int k = 0; k < PER; ++k) {
+                    const int q = tid + k * BT;
+                    const int r = q >> 6, c = q & 63;
+                    ta[r * 65 + c] = (J * 64 + r < m && I * 64 + c < m) ? va[k] : 0;
+                    tb[r * 65 + c] = (I * 64 + r < m && J * 64 + c < m) ? vb[k] : 0;
                 }
                 __syncthreads();
                 const int32_t xl = tid & 63, g = tid >> 6;
@@ -746,10 +772,24 @@ __device__ void finish_t(const BatchArgs &a, const BElec &el, int32_t e, uint32_
     }
     if (wins) atomicAdd(&sh_wins, wins);
     if (p_out) {
+        // eight rows at a time, their loads (clamped) before their stores
         FW_GLOBAL int32_t *Pout = p_out + el.mat_off;
-        for (int32_t x = 0; x < m; ++x)
-            for (int32_t y = tid; y < m; y += BT)
-                Pout[(int64_t)x * m + y] = x == y ? 0 : (int32_t)P[(int64_t)x * mp + y];
+        constexpr int R = 8, H = SCHULZE_BATCH_MAX_M / BT;
+        for (int32_t x0 = 0; x0 < m; x0 += R) {
+            int32_t v[R][H];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int h = 0; h < H; ++h)
+                    v[r][h] = (int32_t)P[(int64_t)min(x0 + r, m - 1) * mp + min(tid + h * BT, m - 1)];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int h = 0; h < H; ++h) {
+                    const int32_t x = x0 + r, y = tid + h * BT;
+                    if (x < m && y < m) Pout[(int64_t)x * m + y] = x == y ? 0 : v[r][h];
+                }
+        }
     }
     __syncthreads();
     if (tid == 0 && a.n_winners) gmem(a.n_winners)[e] = sh_wins;
