@@ -602,6 +602,9 @@ __device__ __attribute__((noinline)) void closure_tiled(E *P_, int32_t mp) {
     }
 }
 
+static_assert(diag_lds_elems<uint16_t, 192>() * 2 <= SMEM_WORDS * 4 && diag_lds_elems<int32_t, 128>() * 4 <= SMEM_WORDS * 4,
+              "diagonal closure LDS");
+
 // Each schedule is its own function: inlined together, their register
 // demands would be allocated as one and spill.
 template <typename E, int B>

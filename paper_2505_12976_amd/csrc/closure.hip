@@ -140,19 +140,41 @@ __device__ inline bool probe_flag(const int32_t *f) {
     return res;
 }
 
-// Make this workgroup's stores of a published tile visible device-wide, then
-// raise its flag.  Published slots are written once per launch and read only
-// after their flag is seen, so no reader can hold an older copy of them.
+// Raise the flag of a published tile once this workgroup's stores of it are
+// visible device-wide.  Published slots are written with agent-scope stores
+// (they do not stay in this XCD's L2), so it suffices that every thread's
+// stores have been acknowledged (vmcnt 0) before the barrier and the flag
+// store; an agent-scope release fence would also write back every dirty line
+// of the L2, which takes microseconds on the critical path.  Tiles of P are
+// only ever read by their owner within the launch.  Published slots are
+// written once per launch and read only after their flag is seen, so no
+// reader can hold an older copy of them.
+constexpr int16_t WAIT_VMCNT0 = 0x0F70;  // s_waitcnt vmcnt(0) expcnt(7) lgkmcnt(15) (gfx9 encoding)
 __device__ inline void raise_flag(int32_t *f) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0);
     __syncthreads();
     if (threadIdx.x == 0) __hip_atomic_store(f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// acc_store with stores coherent at agent scope (not held in this XCD's L2),
+// for the published tiles.
+template <typename E, int B>
+__device__ inline void acc_store_agent(const Acc<E, B> &a, E *dst, int64_t ld) {
+    using C = Cfg<E, B>;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    for (int ii = 0; ii < C::TM; ++ii) {
+        uint32_t *row = reinterpret_cast<uint32_t *>(dst + (int64_t)(ty * C::TM + ii) * ld + tx * C::TN);
+        for (int jj = 0; jj < C::WN; ++jj)
+            __hip_atomic_store(row + jj, __builtin_bit_cast(uint32_t, a.c[ii][jj]), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 template <typename E, int B>
 __global__ __launch_bounds__(256, (sizeof(E) == 2 || B < 128) ? 2 : 1) void k_fw_persist(PersistArgs<E> a) {
     using C = Cfg<E, B>;
-    __shared__ __attribute__((aligned(16))) E lds[C::LDS_ELEMS > 4 * B ? C::LDS_ELEMS : 4 * B];
+    __shared__ __attribute__((aligned(16))) E lds[C::LDS_ELEMS > diag_lds_elems<E, B>() ? C::LDS_ELEMS
+                                                                                        : diag_lds_elems<E, B>()];
     __shared__ int32_t owned[MAX_OWNED];
     __shared__ int32_t n_owned;
     const int32_t nb = a.nb, G = gridDim.x, w = blockIdx.x;
@@ -194,69 +216,124 @@ __global__ __launch_bounds__(256, (sizeof(E) == 2 || B < 128) ? 2 : 1) void k_fw
             slot = 1 + nb + I;
         }
         acc_store<E, B>(acc, tileP(I, J), a.ld);
-        acc_store<E, B>(acc, ring(r, slot), B);
+        acc_store_agent<E, B>(acc, ring(r, slot), B);
         raise_flag(flag(r, slot));
     };
-    auto do_rest = [&](int32_t r, int32_t I, int32_t J) -> bool {
+    // A rest tile of round r.  When `probe` is given, thread 0 also reads
+    // that flag (issued before the product, so its latency hides behind the
+    // tile) and the workgroup learns whether it was raised.
+    __shared__ int32_t probe_seen;
+    auto do_rest = [&](int32_t r, int32_t I, int32_t J, const int32_t *probe) -> bool {
         if (!wait_flags(flag(r, 1 + J), flag(r, 1 + nb + I), a.abort, a.spin_limit)) return false;
+        int32_t seen = 0;
+        if (probe && threadIdx.x == 0) seen = __hip_atomic_load(probe, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         Acc<E, B> acc;
         acc_load<E, B>(acc, tileP(I, J), a.ld);
         acc_product<E, B>(acc, ring(r, 1 + nb + I), B, ring(r, 1 + J), B, lds);
         acc_store<E, B>(acc, tileP(I, J), a.ld);
+        if (probe) {
+            if (threadIdx.x == 0) probe_seen = seen;
+            __syncthreads();
+        }
         return true;
     };
-
-    // Lookahead: the owner of tile (r+1, r+1) updates it first among its
-    // round-r rest tiles and closes it as round r+1's diagonal at once.  With
-    // few tiles per workgroup and round (early_panels), a workgroup whose
-    // round-r tiles that feed round r+1 are done also runs its round-(r+1)
-    // panels before its other round-r tiles when that diagonal is already
-    // published, so that round r+1 starts while round r's rest tiles are
-    // still running.  With many tiles per round there is no idle time to
-    // fill, and mixing two rounds' panels only costs cache.
-    if (tile_owner(0, 0, nb, G) == w) {
-        diag_close<E, B>(tileP(0, 0), a.ld, tileP(0, 0), a.ld, ring(0, 0), B, lds);
-        raise_flag(flag(0, 0));
-    }
-    int32_t panels_done = -1;  // round whose panels this workgroup already ran
-    for (int32_t r = 0; r < nb; ++r) {
-        // panels
-        if (panels_done != r) {
-            for (int32_t q = 0; q < no; ++q) {
-                const int32_t I = owned[q] / nb, J = owned[q] % nb;
-                if ((I == r) == (J == r)) continue;
-                if (!wait_flags(flag(r, 0), nullptr, a.abort, a.spin_limit)) goto stuck;
-                do_panel(r, I, J);
-            }
+    auto has_panels = [&](int32_t r) {
+        for (int32_t q = 0; q < no; ++q) {
+            const int32_t I = owned[q] / nb, J = owned[q] % nb;
+            if ((I == r) != (J == r)) return true;
         }
+        return false;
+    };
+    // All of this workgroup's panels of round r (its diagonal is published).
+    // Panels gate every rest tile of their round, so their waves take the
+    // SIMDs first.
+    auto run_panels = [&](int32_t r) {
+        __builtin_amdgcn_s_setprio(3);
+        for (int32_t q = 0; q < no; ++q) {
+            const int32_t I = owned[q] / nb, J = owned[q] % nb;
+            if ((I == r) == (J == r)) continue;
+            do_panel(r, I, J);
+        }
+        __builtin_amdgcn_s_setprio(0);
+    };
+
+    // Lookahead.  Round r+1 can start as soon as its diagonal tile has its
+    // round-r update, so the owner of tile (r+1, r+1) updates it first and
+    // closes it at once, and the owners of the other tiles of block row and
+    // column r+1 update those next.  The chain diagonal -> panels next to it
+    // -> next diagonal is the critical path of the recurrence: its tiles run
+    // at raised wave priority, and the owner of a panel that feeds the next
+    // diagonal waits for its diagonal and computes it right away.  Other
+    // workgroups, with early_panels, look at the round-(r+1) diagonal flag
+    // while they run their remaining round-r tiles and compute their
+    // round-(r+1) panels as soon as it is up, so that round r+1's tiles find
+    // their panels ready.
+    // (Round -1 only closes diagonal tile 0.)
+    int32_t panels_done = -1;  // round whose panels this workgroup already ran
+    int32_t diag_done = -1;    // last diagonal tile this workgroup closed
+    for (int32_t r = -1; r < nb; ++r) {
+        if (r >= 0 && panels_done != r) {
+            if (has_panels(r)) {
+                if (!wait_flags(flag(r, 0), nullptr, a.abort, a.spin_limit)) goto stuck;
+                run_panels(r);
+            }
+            panels_done = r;
+        }
+        bool next_panels = false;  // round r+1's panels are still to do
         if (r + 1 < nb) {
             // the next diagonal tile
-            if (tile_owner(r + 1, r + 1, nb, G) == w) {
-                if (!do_rest(r, r + 1, r + 1)) goto stuck;
+            if (tile_owner(r + 1, r + 1, nb, G) == w && diag_done < r + 1) {
+                __builtin_amdgcn_s_setprio(3);
+                if (r >= 0 && !do_rest(r, r + 1, r + 1, nullptr)) goto stuck;
                 diag_close<E, B>(tileP(r + 1, r + 1), a.ld, tileP(r + 1, r + 1), a.ld, ring(r + 1, 0), B, lds);
                 raise_flag(flag(r + 1, 0));
+                __builtin_amdgcn_s_setprio(0);
+                diag_done = r + 1;
             }
+            if (r < 0) continue;
             // the other tiles that feed round r+1
             for (int32_t q = 0; q < no; ++q) {
                 const int32_t I = owned[q] / nb, J = owned[q] % nb;
                 if (I == r || J == r || (I != r + 1 && J != r + 1) || (I == r + 1 && J == r + 1)) continue;
-                if (!do_rest(r, I, J)) goto stuck;
+                if (!do_rest(r, I, J, nullptr)) goto stuck;
             }
-            // round r+1's panels, if its diagonal is out already
-            if (a.early_panels && probe_flag(flag(r + 1, 0))) {
-                for (int32_t q = 0; q < no; ++q) {
-                    const int32_t I = owned[q] / nb, J = owned[q] % nb;
-                    if ((I == r + 1) == (J == r + 1)) continue;
-                    do_panel(r + 1, I, J);
-                }
+            next_panels = a.early_panels && has_panels(r + 1);
+            const bool critical = r + 2 < nb && (tile_owner(r + 1, r + 2, nb, G) == w ||
+                                                 tile_owner(r + 2, r + 1, nb, G) == w);
+            if (next_panels && (critical || probe_flag(flag(r + 1, 0)))) {
+                if (!wait_flags(flag(r + 1, 0), nullptr, a.abort, a.spin_limit)) goto stuck;
+                run_panels(r + 1);
                 panels_done = r + 1;
+                next_panels = false;
             }
         }
+        // Two rounds ahead: the owner of tile (r+2, r+2) gives it its
+        // round-r update now, waits for the round-(r+1) panels next to it
+        // and closes it as round r+2's diagonal, instead of reaching it
+        // after its other round-r tiles.
+        int32_t ahead = -1;
+        if (a.early_panels && nb <= G && r + 2 < nb && tile_owner(r + 2, r + 2, nb, G) == w) {
+            __builtin_amdgcn_s_setprio(3);
+            if (!do_rest(r, r + 2, r + 2, nullptr)) goto stuck;
+            if (!do_rest(r + 1, r + 2, r + 2, nullptr)) goto stuck;
+            diag_close<E, B>(tileP(r + 2, r + 2), a.ld, tileP(r + 2, r + 2), a.ld, ring(r + 2, 0), B, lds);
+            raise_flag(flag(r + 2, 0));
+            __builtin_amdgcn_s_setprio(0);
+            diag_done = r + 2;
+            ahead = (r + 2) * nb + (r + 2);
+        }
         // the remaining rest tiles of round r
+        if (threadIdx.x == 0) probe_seen = 0;
+        __syncthreads();
         for (int32_t q = 0; q < no; ++q) {
             const int32_t I = owned[q] / nb, J = owned[q] % nb;
-            if (I == r || J == r || I == r + 1 || J == r + 1) continue;
-            if (!do_rest(r, I, J)) goto stuck;
+            if (I == r || J == r || I == r + 1 || J == r + 1 || owned[q] == ahead) continue;
+            if (next_panels && probe_seen) {  // (uniform: written before a barrier)
+                run_panels(r + 1);
+                panels_done = r + 1;
+                next_panels = false;
+            }
+            if (!do_rest(r, I, J, next_panels ? flag(r + 1, 0) : nullptr)) goto stuck;
         }
     }
     return;
@@ -268,7 +345,7 @@ stuck:
 // Used when a cooperative launch is not available: three launches per round.
 template <typename E, int B>
 __global__ __launch_bounds__(256) void k_fw_diag(E *__restrict__ P, int64_t ld, int32_t r) {
-    __shared__ __attribute__((aligned(16))) E buf[4 * B];
+    __shared__ __attribute__((aligned(16))) E buf[diag_lds_elems<E, B>()];
     E *t = P + (int64_t)r * B * ld + (int64_t)r * B;
     diag_close<E, B>(t, ld, t, ld, nullptr, 0, buf);
 }

@@ -166,11 +166,16 @@ __device__ inline void acc_product(Acc<E, B> &a, PA A, int64_t lda, PB Bm, int64
 // ------------------------------------------------------------------ diagonal tile
 // Plain recurrence over the tile's own vertices, elements held in registers:
 // thread (ty, tx) owns rows ty + 16a and columns tx + 16b (a, b < B/16).
-// Before step k the owners of row k and column k put them into LDS (double
-// buffered, in thread order so each thread reads its values contiguously);
-// row and column k do not change in step k, so one barrier per step
-// suffices.  Steps run as B/16 unrolled groups of 16 so that the register
-// index of row/column k (= k / 16) is a compile-time constant.
+// The steps run in blocks of S (4, or 2 for the larger tiles) with one
+// barrier per block: before block k0 .. k0+S-1 the owners put rows and
+// columns k0 .. k0+S-1 and the S x S block where they cross into LDS (double
+// buffered), and every thread then runs the S steps on its own elements,
+// carrying its private copies of those rows (at its columns), columns (at
+// its rows) and the block through the same steps, so that step k0+s sees
+// row and column k0+s as the earlier steps of the block left them.  The
+// result is that of the plain recurrence, step by step.  Blocks run in B/16
+// groups of 16 steps so that the register index of rows and columns k
+// (= k / 16) is a compile-time constant.
 template <typename E>
 __device__ inline E lane_get(const typename Lane<E>::W *v, int b) {
     if constexpr (sizeof(E) == 4) {
@@ -180,59 +185,141 @@ __device__ inline E lane_get(const typename Lane<E>::W *v, int b) {
     }
 }
 
+// Steps per barrier of the diagonal closure: 4 where the tile's registers
+// leave room for the copies, else 2.
 template <typename E, int B>
+constexpr int diag_steps() {
+    return B <= 64 ? 4 : 2;
+}
+
+template <typename E, int B, int S_ = diag_steps<E, B>()>
 struct Diag {
     using L = Lane<E>;
     using W = typename L::W;
+    static constexpr int PER = L::PER;
     static constexpr int RA = B / 16;       // rows per thread
     static constexpr int CW = B / 16;       // columns per thread
-    static constexpr int WC = CW / L::PER;  // lanes per row
+    static constexpr int WC = CW / PER;     // lanes per row slice
+    static constexpr int RP = RA / PER;     // lanes per column slice
+    static constexpr int S = S_;            // steps per barrier
+    // one LDS slot: S rows (thread tx's columns at tx*CW ..), S columns
+    // (thread ty's rows at ty*RA ..), the S x S block
+    static constexpr int SLOT = 2 * S * B + S * S;
+    static constexpr int LDS_ELEMS = 2 * SLOT;
 
-    // row and column 16 * KB + kk go to LDS slot `slot`
+    // rows and columns 16 KB + kk .. + S-1 into the slot at q
     template <int KB>
-    __device__ __attribute__((always_inline)) static void publish(const W (&v)[RA][WC], int kk, int slot, int tx,
-                                                                  int ty, E *rowbuf, E *colbuf) {
-        if (ty == kk) {
-            W *rb = reinterpret_cast<W *>(rowbuf + slot * B + tx * CW);
+    __device__ __attribute__((always_inline)) static void publish(const W (&v)[RA][WC], int kk, E *q, int tx,
+                                                                  int ty) {
+        const int sr = ty - kk, sc = tx - kk;
+        const bool row_owner = sr >= 0 && sr < S, col_owner = sc >= 0 && sc < S;
+        if (row_owner) {
+            W *rb = reinterpret_cast<W *>(q + sr * B + tx * CW);
+#pragma unroll
             for (int c = 0; c < WC; ++c) rb[c] = v[KB][c];
         }
-        if (tx == kk) {
-            for (int a = 0; a < RA; ++a) colbuf[slot * B + ty * RA + a] = lane_get<E>(v[a], KB);
+        if (col_owner) {
+            W *cb = reinterpret_cast<W *>(q + S * B + sc * B + ty * RA);
+#pragma unroll
+            for (int p = 0; p < RP; ++p) {
+                if constexpr (sizeof(E) == 4) {
+                    cb[p] = v[p][KB];
+                } else {
+                    cb[p] = W{lane_get<E>(v[2 * p], KB), lane_get<E>(v[2 * p + 1], KB)};
+                }
+            }
+            if (row_owner) q[2 * S * B + sr * S + sc] = lane_get<E>(v[KB], KB);
         }
     }
 
-    // steps k = 16 * KB .. 16 * KB + 15, then the next group
-    template <int KB>
-    __device__ __attribute__((always_inline)) static void steps(W (&v)[RA][WC], int tx, int ty, E *rowbuf,
-                                                                E *colbuf) {
-#pragma unroll 1
-        for (int kk = 0; kk < 16; ++kk) {
-            const int slot = kk & 1;  // k = 16 KB + kk has the parity of kk
-            __syncthreads();
-            W rk[WC];
-            const W *rb = reinterpret_cast<const W *>(rowbuf + slot * B + tx * CW);
-            for (int c = 0; c < WC; ++c) rk[c] = rb[c];
-            for (int a = 0; a < RA; ++a) {
-                const W ck = L::splat(colbuf[slot * B + ty * RA + a]);
-                for (int c = 0; c < WC; ++c) v[a][c] = L::relax(v[a][c], ck, rk[c]);
+    // the S steps of one block, from the slot at q
+    __device__ __attribute__((always_inline)) static void block(W (&v)[RA][WC], const E *q, int tx, int ty) {
+        W cv[S][RP];  // columns k0 + s at this thread's rows
+        W rv[S][WC];  // rows k0 + s at this thread's columns
+        E d[S][S];    // the block
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const W *cb = reinterpret_cast<const W *>(q + S * B + s * B + ty * RA);
+#pragma unroll
+            for (int p = 0; p < RP; ++p) cv[s][p] = cb[p];
+            const W *rb = reinterpret_cast<const W *>(q + s * B + tx * CW);
+#pragma unroll
+            for (int c = 0; c < WC; ++c) rv[s][c] = rb[c];
+        }
+        if constexpr (S > 1) {
+            constexpr int NV = S * S * (int)sizeof(E) / 8;  // 8-byte words of the block
+            uint32_t wv[2 * NV];
+            const uint2 *db = reinterpret_cast<const uint2 *>(q + 2 * S * B);
+#pragma unroll
+            for (int u = 0; u < NV; ++u) {
+                const uint2 x = db[u];
+                wv[2 * u] = x.x, wv[2 * u + 1] = x.y;
             }
-            if (kk < 15) {
-                publish<KB>(v, kk + 1, slot ^ 1, tx, ty, rowbuf, colbuf);
-            } else {
-                if constexpr (KB + 1 < B / 16) publish<KB + 1>(v, 0, slot ^ 1, tx, ty, rowbuf, colbuf);
+#pragma unroll
+            for (int i = 0; i < S * S; ++i) {
+                if constexpr (sizeof(E) == 4) {
+                    d[i / S][i % S] = (E)wv[i];
+                } else {
+                    d[i / S][i % S] = (E)((i & 1) ? (wv[i >> 1] >> 16) : (wv[i >> 1] & 0xFFFFu));
+                }
             }
         }
-        if constexpr (KB + 1 < B / 16) steps<KB + 1>(v, tx, ty, rowbuf, colbuf);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+#pragma unroll
+            for (int a = 0; a < RA; ++a) {
+                const W ck = L::splat(lane_get<E>(cv[s], a));
+#pragma unroll
+                for (int c = 0; c < WC; ++c) v[a][c] = L::relax(v[a][c], ck, rv[s][c]);
+            }
+#pragma unroll
+            for (int s2 = s + 1; s2 < S; ++s2) {
+                const W x = L::splat(d[s][s2]);
+#pragma unroll
+                for (int p = 0; p < RP; ++p) cv[s2][p] = L::relax(cv[s2][p], x, cv[s][p]);
+                const W y = L::splat(d[s2][s]);
+#pragma unroll
+                for (int c = 0; c < WC; ++c) rv[s2][c] = L::relax(rv[s2][c], y, rv[s][c]);
+            }
+#pragma unroll
+            for (int s2 = s + 1; s2 < S; ++s2)
+#pragma unroll
+                for (int s3 = s + 1; s3 < S; ++s3)
+                    if (s2 != s3)
+                        d[s2][s3] = (E)max((int32_t)d[s2][s3], min((int32_t)d[s2][s], (int32_t)d[s][s3]));
+            __builtin_amdgcn_sched_barrier(0);  // one step at a time: bounded register demand
+        }
+    }
+
+    // blocks k0 = 16 KB, 16 KB + 4, .., then the next group
+    template <int KB>
+    __device__ __attribute__((always_inline)) static void steps(W (&v)[RA][WC], int tx, int ty, E *buf) {
+#pragma unroll 1
+        for (int g = 0; g < 16 / S; ++g) {
+            const int slot = g & 1;  // block (16 / S) KB + g has the parity of g
+            __syncthreads();
+            block(v, buf + slot * SLOT, tx, ty);
+            if (g + 1 < 16 / S) {
+                publish<KB>(v, S * (g + 1), buf + (slot ^ 1) * SLOT, tx, ty);
+            } else {
+                if constexpr (KB + 1 < B / 16) publish<KB + 1>(v, 0, buf + (slot ^ 1) * SLOT, tx, ty);
+            }
+        }
+        if constexpr (KB + 1 < B / 16) steps<KB + 1>(v, tx, ty, buf);
     }
 };
 
-template <typename E, int B, typename SrcP, typename DstP>
-__device__ inline void diag_close(SrcP src, int64_t lds_, DstP dst, int64_t ldd_, E *__restrict__ dst2, int64_t ldd2,
-                                  E *buf) {
-    using D = Diag<E, B>;
+// LDS elements diag_close<E, B, S> needs (8-byte aligned).
+template <typename E, int B, int S = diag_steps<E, B>()>
+constexpr int diag_lds_elems() {
+    return Diag<E, B, S>::LDS_ELEMS;
+}
+
+template <typename E, int B, int S, typename SrcP, typename DstP>
+__device__ __attribute__((always_inline)) inline void diag_close_body(SrcP src, int64_t lds_, DstP dst, int64_t ldd_,
+                                                                 E *__restrict__ dst2, int64_t ldd2, E *buf) {
+    using D = Diag<E, B, S>;
     using W = typename D::W;
-    E *rowbuf = buf;          // [2][B]: thread tx's columns at tx*CW ..
-    E *colbuf = buf + 2 * B;  // [2][B]: thread ty's rows at ty*RA ..
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     // the tile may just have been stored by other threads of the workgroup
     // (with another thread-to-element map)
@@ -248,18 +335,38 @@ __device__ inline void diag_close(SrcP src, int64_t lds_, DstP dst, int64_t ldd_
             }
         }
     }
-    D::template publish<0>(v, 0, 0, tx, ty, rowbuf, colbuf);
-    D::template steps<0>(v, tx, ty, rowbuf, colbuf);
+    D::template publish<0>(v, 0, buf, tx, ty);
+    D::template steps<0>(v, tx, ty, buf);
     for (int a = 0; a < D::RA; ++a) {
         const auto row = dst + (int64_t)(ty + 16 * a) * ldd_ + tx;
         E *row2 = dst2 ? dst2 + (int64_t)(ty + 16 * a) * ldd2 + tx : nullptr;
         for (int b = 0; b < D::CW; ++b) {
             const E x = lane_get<E>(v[a], b);
             row[16 * b] = x;
-            if (row2) row2[16 * b] = x;
+            if (row2) __hip_atomic_store(row2 + 16 * b, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
     __syncthreads();
+}
+
+template <typename E, int B, int S, typename SrcP, typename DstP>
+__device__ __attribute__((noinline)) void diag_close_call(SrcP src, int64_t lds_, DstP dst, int64_t ldd_,
+                                                          E *__restrict__ dst2, int64_t ldd2, E *buf) {
+    diag_close_body<E, B, S>(src, lds_, dst, ldd_, dst2, ldd2, buf);
+}
+
+// Close the B x B tile at src (row pitch lds_) and write it to dst, and to
+// dst2 when given (with agent-scope stores: dst2 is a tile that other
+// workgroups read); buf holds diag_lds_elems<E, B, S>() elements of LDS.  Small
+// tiles are inlined; the larger ones are a call of their own, so that their
+// register demand is not added to the caller's.
+template <typename E, int B, int S = diag_steps<E, B>(), typename SrcP, typename DstP>
+__device__ __attribute__((always_inline)) inline void diag_close(SrcP src, int64_t lds_, DstP dst, int64_t ldd_,
+                                                            E *__restrict__ dst2, int64_t ldd2, E *buf) {
+    if constexpr (B >= 128)
+        diag_close_call<E, B, S>(src, lds_, dst, ldd_, dst2, ldd2, buf);
+    else
+        diag_close_body<E, B, S>(src, lds_, dst, ldd_, dst2, ldd2, buf);
 }
 
 }  // namespace fw
