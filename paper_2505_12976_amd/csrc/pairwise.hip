@@ -398,8 +398,10 @@ __global__ __launch_bounds__(CNT_THREADS, 2) void k_count_pos(DenseArgs a) {
         }
         const int64_t hi = min((int64_t)nvoters, 2 * seg_p1);
         const uint32_t nv = (uint32_t)max((int64_t)0, hi - 2 * seg_p0);
+#pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int32_t x = X * CT + ty * 8 + i;
+#pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int32_t y = Y * CT + tx * 8 + j;
                 const uint32_t cnt = (acc[i][j] - sx[i] + sy[j]) >> 16;
@@ -448,14 +450,19 @@ __global__ __launch_bounds__(CNT_THREADS, 2) void k_count_pos(DenseArgs a) {
         __syncthreads();
         if (u + 1 < u1) load_unit(u + 1, stage);  // overlaps the compute below
 
-#pragma unroll 1
-        for (int v = 0; v < VC; ++v) {
-            const uint4 xa = *reinterpret_cast<const uint4 *>(&xs[v][ty * 8]);
-            const uint4 xb = *reinterpret_cast<const uint4 *>(&xs[v][ty * 8 + 4]);
-            const uint4 ya = *reinterpret_cast<const uint4 *>(&ys[v][tx * 8]);
-            const uint4 yb = *reinterpret_cast<const uint4 *>(&ys[v][tx * 8 + 4]);
-            const uint32_t xv[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
-            const uint32_t yv[8] = {ya.x, ya.y, ya.z, ya.w, yb.x, yb.y, yb.z, yb.w};
+        // Two voter pairs per iteration, the LDS reads of each pair issued
+        // before the products of the previous one (scheduling barriers keep
+        // them there), so that their latency hides behind 128 VALU
+        // instructions.
+        auto read_pair = [&](int v, uint4 (&q)[4]) {
+            q[0] = *reinterpret_cast<const uint4 *>(&xs[v][ty * 8]);
+            q[1] = *reinterpret_cast<const uint4 *>(&xs[v][ty * 8 + 4]);
+            q[2] = *reinterpret_cast<const uint4 *>(&ys[v][tx * 8]);
+            q[3] = *reinterpret_cast<const uint4 *>(&ys[v][tx * 8 + 4]);
+        };
+        auto count_pair = [&](const uint4 (&q)[4]) {
+            const uint32_t xv[8] = {q[0].x, q[0].y, q[0].z, q[0].w, q[1].x, q[1].y, q[1].z, q[1].w};
+            const uint32_t yv[8] = {q[2].x, q[2].y, q[2].z, q[2].w, q[3].x, q[3].y, q[3].z, q[3].w};
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const us2 xi = __builtin_bit_cast(us2, xv[i]);
@@ -465,6 +472,18 @@ __global__ __launch_bounds__(CNT_THREADS, 2) void k_count_pos(DenseArgs a) {
 #pragma unroll
                 for (int j = 0; j < 8; ++j) acc[i][j] = __builtin_amdgcn_udot2(diff[j], ones, acc[i][j], false);
             }
+        };
+        static_assert(VC % 2 == 0 && (VC & (VC - 1)) == 0, "voter pairs per chunk");
+        uint4 qa[4], qb[4];
+        read_pair(0, qa);
+#pragma unroll 1
+        for (int v = 0; v < VC; v += 2) {
+            read_pair(v + 1, qb);
+            __builtin_amdgcn_sched_barrier(0);
+            count_pair(qa);
+            read_pair((v + 2) & (VC - 1), qa);  // (after the last pair: pair 0 again, unused)
+            __builtin_amdgcn_sched_barrier(0);
+            count_pair(qb);
         }
 
         const bool last = u + 1 >= u1;
