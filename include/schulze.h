@@ -504,11 +504,28 @@ int schulze_batch_autotune(schulze_ctx *ctx, void *stream, int32_t value_bits, i
  * "mlp_forward", "mlp_backward", "mlp_loss", "mlp_adam", "propose", "batch"
  * (a batch run: the persistent launch, or the whole graph when captured),
  * "label_post" (schulze_winners_propagate's filter, order and
- * postprocessing kernels), "label_sweep" (its propagation launches).
+ * postprocessing kernels), "label_sweep" (its propagation launches),
+ * "value_rank" (the value-ranking kernels of int32 closures),
+ * "feature_rows" (the row pass of the per-candidate features),
+ * "valu_probe".
  */
 int schulze_set_timing(schulze_ctx *ctx, int enable);
 int schulze_kernel_time(schulze_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms);
 int schulze_reset_timing(schulze_ctx *ctx);
+
+/*
+ * Integer VALU throughput probe (a measurement aid for the rooflines of the
+ * count and closure kernels, which are bound by the vector ALU): one launch
+ * of `workgroups` workgroups of 256 threads, each lane running `trips` x 160
+ * packed-uint16 max, min, add and subtract instructions on eight
+ * independent chains.  *lane_ops (host) receives the number of lane
+ * operations launched (workgroups x 256 x trips x 160); time the launch on
+ * `stream` with events.  out: one device uint32 that the kernel may write
+ * (it keeps the chains' results live).  EINVAL for null pointers or
+ * non-positive sizes.
+ */
+int schulze_valu_probe(schulze_ctx *ctx, void *stream, int32_t workgroups, int64_t trips, uint32_t *out,
+                       int64_t *lane_ops);
 
 #ifdef __cplusplus
 }

@@ -34,7 +34,7 @@ EXPORTS = (
     "schulze_winners_learned",
     "schulze_batch_plan", "schulze_batch_destroy", "schulze_batch_run", "schulze_batch_set_closure",
     "schulze_batch_get_closure", "schulze_batch_autotune", "schulze_winners_propagate",
-    "schulze_topk_propagate",
+    "schulze_topk_propagate", "schulze_valu_probe",
 )
 
 
@@ -117,6 +117,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.schulze_set_value_ranking.argtypes = [vp, c_int]
     lib.schulze_set_closure_tile.argtypes = [vp, c_int]
     lib.schulze_set_sparse_count.argtypes = [vp, c_int]
+    lib.schulze_valu_probe.argtypes = [vp, vp, c_i32, c_i64, vp, ctypes.POINTER(c_i64)]
     lib.schulze_weights.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_int, vp, c_i64, vp, c_i64]
     lib.schulze_widest_from.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_i32, vp]
     lib.schulze_verify.argtypes = [vp, vp, vp, c_i64, vp, c_i64, c_i32, c_int, c_i32, vp, vp, vp, vp, vp]
@@ -507,6 +508,16 @@ class Context:
         _check(self._lib.schulze_set_value_ranking(self._h, int(bool(enable))), "schulze_set_value_ranking")
 
     # -------------------------------------------------------------- timing
+    def valu_probe(self, workgroups: int, trips: int) -> int:
+        """Launch the integer VALU throughput probe on the current stream;
+        returns the lane operations it issues (time it with events)."""
+        import torch
+        out = torch.zeros(1, dtype=torch.int32, device=self._torch_device)
+        n = ctypes.c_int64(0)
+        _check(self._lib.schulze_valu_probe(self._h, self._stream(), int(workgroups), int(trips),
+                                            self._dev(out, "out"), ctypes.byref(n)), "schulze_valu_probe")
+        return n.value
+
     def set_timing(self, enable: bool) -> None:
         _check(self._lib.schulze_set_timing(self._h, int(bool(enable))), "schulze_set_timing")
 

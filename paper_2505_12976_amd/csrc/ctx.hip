@@ -11,7 +11,7 @@ const char *const kKernelNames[K_NUM_KERNELS] = {
     "winners",     "fill",           "fw_persist",  "route",        "count_trunc",
     "widest",      "verdict",        "features",    "mlp_prepare",  "mlp_forward",
     "mlp_backward", "mlp_loss",      "mlp_adam",    "propose",     "batch",
-    "label_post",   "label_sweep", "value_rank", "feature_rows"};
+    "label_post",   "label_sweep", "value_rank", "feature_rows", "valu_probe"};
 
 extern "C" const char *schulze_strerror(int code) {
     switch (code) {

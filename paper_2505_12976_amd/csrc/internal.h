@@ -100,6 +100,7 @@ enum KernelId {
     K_PROP_SWEEP,
     K_RANK,
     K_FEATURE_ROWS,
+    K_VALU_PROBE,
     K_NUM_KERNELS
 };
 extern const char *const kKernelNames[K_NUM_KERNELS];

@@ -67,6 +67,8 @@ def test_null_handles_are_rejected_on_the_host():
     assert lib.schulze_batch_get_closure(None, 16, 32, ctypes.byref(v)) == sz.EINVAL
     assert lib.schulze_batch_autotune(None, None, 16, 64, None) == sz.EINVAL
     lib.schulze_batch_destroy(vp(None))  # accepted
+    ops = ctypes.c_int64(0)
+    assert lib.schulze_valu_probe(None, None, 1, 1, None, ctypes.byref(ops)) == sz.EINVAL
 
 
 def test_create_without_a_device_fails_cleanly():
