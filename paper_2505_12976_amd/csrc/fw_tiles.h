@@ -140,16 +140,24 @@ __device__ inline void acc_product(Acc<E, B> &a, PA A, int64_t lda, PB Bm, int64
                 }
             }
         } else {
-            // four k per step: A values come as one 8-byte read per row
+            // four k per step: A values come as one 8-byte read per row; the
+            // B row of step k+1 is read before the products of step k (the
+            // scheduling barrier keeps it there), so that only the first read
+            // of each step waits
 #pragma unroll 1
             for (int k = 0; k < KC; k += 4) {
                 uint2 av[TM];
                 for (int ii = 0; ii < TM; ++ii) av[ii] = *reinterpret_cast<const uint2 *>(&As[(ty * TM + ii) * LA + k]);
+                W bq[2][WN];
+                for (int jj = 0; jj < WN; ++jj) bq[0][jj] = *reinterpret_cast<const W *>(&Bs[k * LB + tx * TN + 2 * jj]);
 #pragma unroll
                 for (int kk = 0; kk < 4; ++kk) {
-                    W bp[WN];
-                    for (int jj = 0; jj < WN; ++jj)
-                        bp[jj] = *reinterpret_cast<const W *>(&Bs[(k + kk) * LB + tx * TN + 2 * jj]);
+                    if (kk + 1 < 4) {
+                        for (int jj = 0; jj < WN; ++jj)
+                            bq[(kk + 1) & 1][jj] = *reinterpret_cast<const W *>(&Bs[(k + kk + 1) * LB + tx * TN + 2 * jj]);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                    const W *bp = bq[kk & 1];
                     for (int ii = 0; ii < TM; ++ii) {
                         const uint32_t word = kk < 2 ? av[ii].x : av[ii].y;
                         const unsigned short av16 = (kk & 1) ? (unsigned short)(word >> 16) : (unsigned short)word;
