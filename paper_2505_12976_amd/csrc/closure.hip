@@ -173,8 +173,9 @@ __device__ inline void acc_store_agent(const Acc<E, B> &a, E *dst, int64_t ld) {
 template <typename E, int B>
 __global__ __launch_bounds__(256, (sizeof(E) == 2 || B < 128) ? 2 : 1) void k_fw_persist(PersistArgs<E> a) {
     using C = Cfg<E, B>;
-    __shared__ __attribute__((aligned(16))) E lds[C::LDS_ELEMS > diag_lds_elems<E, B>() ? C::LDS_ELEMS
-                                                                                        : diag_lds_elems<E, B>()];
+    constexpr int DS = diag_steps<E, B>();
+    constexpr int DIAG_LDS = diag_lds_elems<E, B, DS, true>();
+    __shared__ __attribute__((aligned(16))) E lds[C::LDS_ELEMS > DIAG_LDS ? C::LDS_ELEMS : DIAG_LDS];
     __shared__ int32_t owned[MAX_OWNED];
     __shared__ int32_t n_owned;
     const int32_t nb = a.nb, G = gridDim.x, w = blockIdx.x;
@@ -285,7 +286,8 @@ __global__ __launch_bounds__(256, (sizeof(E) == 2 || B < 128) ? 2 : 1) void k_fw
             if (tile_owner(r + 1, r + 1, nb, G) == w && diag_done < r + 1) {
                 __builtin_amdgcn_s_setprio(3);
                 if (r >= 0 && !do_rest(r, r + 1, r + 1, nullptr)) goto stuck;
-                diag_close<E, B>(tileP(r + 1, r + 1), a.ld, tileP(r + 1, r + 1), a.ld, ring(r + 1, 0), B, lds);
+                diag_close<E, B, DS, true>(tileP(r + 1, r + 1), a.ld, tileP(r + 1, r + 1), a.ld, ring(r + 1, 0), B,
+                                           lds);
                 raise_flag(flag(r + 1, 0));
                 __builtin_amdgcn_s_setprio(0);
                 diag_done = r + 1;
@@ -316,7 +318,7 @@ __global__ __launch_bounds__(256, (sizeof(E) == 2 || B < 128) ? 2 : 1) void k_fw
             __builtin_amdgcn_s_setprio(3);
             if (!do_rest(r, r + 2, r + 2, nullptr)) goto stuck;
             if (!do_rest(r + 1, r + 2, r + 2, nullptr)) goto stuck;
-            diag_close<E, B>(tileP(r + 2, r + 2), a.ld, tileP(r + 2, r + 2), a.ld, ring(r + 2, 0), B, lds);
+            diag_close<E, B, DS, true>(tileP(r + 2, r + 2), a.ld, tileP(r + 2, r + 2), a.ld, ring(r + 2, 0), B, lds);
             raise_flag(flag(r + 2, 0));
             __builtin_amdgcn_s_setprio(0);
             diag_done = r + 2;
@@ -345,9 +347,9 @@ stuck:
 // Used when a cooperative launch is not available: three launches per round.
 template <typename E, int B>
 __global__ __launch_bounds__(256) void k_fw_diag(E *__restrict__ P, int64_t ld, int32_t r) {
-    __shared__ __attribute__((aligned(16))) E buf[diag_lds_elems<E, B>()];
+    __shared__ __attribute__((aligned(16))) E buf[diag_lds_elems<E, B, diag_steps<E, B>(), true>()];
     E *t = P + (int64_t)r * B * ld + (int64_t)r * B;
-    diag_close<E, B>(t, ld, t, ld, nullptr, 0, buf);
+    diag_close<E, B, diag_steps<E, B>(), true>(t, ld, t, ld, nullptr, 0, buf);
 }
 
 template <typename E, int B>

@@ -15,6 +15,7 @@ typedef __attribute__((ext_vector_type(2))) unsigned short us2;
 // rather than a flat one).  retype<U>(p) reinterprets p as a pointer to U in
 // the same address space.
 #define FW_GLOBAL __attribute__((address_space(1)))
+#define FW_LDS __attribute__((address_space(3)))
 typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));  // 16 bytes, not a class type
 template <typename U, typename T>
 __device__ __forceinline__ U *retype(T *p) {
@@ -217,17 +218,17 @@ struct Diag {
 
     // rows and columns 16 KB + kk .. + S-1 into the slot at q
     template <int KB>
-    __device__ __attribute__((always_inline)) static void publish(const W (&v)[RA][WC], int kk, E *q, int tx,
+    __device__ __attribute__((always_inline)) static void publish(const W (&v)[RA][WC], int kk, FW_LDS E *q, int tx,
                                                                   int ty) {
         const int sr = ty - kk, sc = tx - kk;
         const bool row_owner = sr >= 0 && sr < S, col_owner = sc >= 0 && sc < S;
         if (row_owner) {
-            W *rb = reinterpret_cast<W *>(q + sr * B + tx * CW);
+            FW_LDS W *rb = (FW_LDS W *)(q + sr * B + tx * CW);
 #pragma unroll
             for (int c = 0; c < WC; ++c) rb[c] = v[KB][c];
         }
         if (col_owner) {
-            W *cb = reinterpret_cast<W *>(q + S * B + sc * B + ty * RA);
+            FW_LDS W *cb = (FW_LDS W *)(q + S * B + sc * B + ty * RA);
 #pragma unroll
             for (int p = 0; p < RP; ++p) {
                 if constexpr (sizeof(E) == 4) {
@@ -241,28 +242,25 @@ struct Diag {
     }
 
     // the S steps of one block, from the slot at q
-    __device__ __attribute__((always_inline)) static void block(W (&v)[RA][WC], const E *q, int tx, int ty) {
+    __device__ __attribute__((always_inline)) static void block(W (&v)[RA][WC], const FW_LDS E *q, int tx, int ty) {
         W cv[S][RP];  // columns k0 + s at this thread's rows
         W rv[S][WC];  // rows k0 + s at this thread's columns
         E d[S][S];    // the block
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            const W *cb = reinterpret_cast<const W *>(q + S * B + s * B + ty * RA);
+            const FW_LDS W *cb = (const FW_LDS W *)(q + S * B + s * B + ty * RA);
 #pragma unroll
             for (int p = 0; p < RP; ++p) cv[s][p] = cb[p];
-            const W *rb = reinterpret_cast<const W *>(q + s * B + tx * CW);
+            const FW_LDS W *rb = (const FW_LDS W *)(q + s * B + tx * CW);
 #pragma unroll
             for (int c = 0; c < WC; ++c) rv[s][c] = rb[c];
         }
         if constexpr (S > 1) {
-            constexpr int NV = S * S * (int)sizeof(E) / 8;  // 8-byte words of the block
-            uint32_t wv[2 * NV];
-            const uint2 *db = reinterpret_cast<const uint2 *>(q + 2 * S * B);
+            constexpr int NW = S * S * (int)sizeof(E) / 4;  // 4-byte words of the block (8-byte aligned)
+            uint32_t wv[NW];
+            const FW_LDS uint32_t *db = (const FW_LDS uint32_t *)(q + 2 * S * B);
 #pragma unroll
-            for (int u = 0; u < NV; ++u) {
-                const uint2 x = db[u];
-                wv[2 * u] = x.x, wv[2 * u + 1] = x.y;
-            }
+            for (int u = 0; u < NW; ++u) wv[u] = db[u];
 #pragma unroll
             for (int i = 0; i < S * S; ++i) {
                 if constexpr (sizeof(E) == 4) {
@@ -301,7 +299,7 @@ struct Diag {
 
     // blocks k0 = 16 KB, 16 KB + 4, .., then the next group
     template <int KB>
-    __device__ __attribute__((always_inline)) static void steps(W (&v)[RA][WC], int tx, int ty, E *buf) {
+    __device__ __attribute__((always_inline)) static void steps(W (&v)[RA][WC], int tx, int ty, FW_LDS E *buf) {
 #pragma unroll 1
         for (int g = 0; g < 16 / S; ++g) {
             const int slot = g & 1;  // block (16 / S) KB + g has the parity of g
@@ -317,64 +315,117 @@ struct Diag {
     }
 };
 
-// LDS elements diag_close<E, B, S> needs (8-byte aligned).
-template <typename E, int B, int S = diag_steps<E, B>()>
-constexpr int diag_lds_elems() {
-    return Diag<E, B, S>::LDS_ELEMS;
-}
-
-template <typename E, int B, int S, typename SrcP, typename DstP>
+template <typename E, int B, int S, bool STAGE, typename SrcP, typename DstP>
 __device__ __attribute__((always_inline)) inline void diag_close_body(SrcP src, int64_t lds_, DstP dst, int64_t ldd_,
                                                                  E *__restrict__ dst2, int64_t ldd2, E *buf) {
     using D = Diag<E, B, S>;
     using W = typename D::W;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    FW_LDS E *lb = (FW_LDS E *)buf;  // (an LDS address: local accesses, also in an outlined call)
     // the tile may just have been stored by other threads of the workgroup
     // (with another thread-to-element map)
     __syncthreads();
     W v[D::RA][D::WC];
-    for (int a = 0; a < D::RA; ++a) {
-        const auto row = src + (int64_t)(ty + 16 * a) * lds_ + tx;
-        for (int c = 0; c < D::WC; ++c) {
-            if constexpr (sizeof(E) == 4) {
-                v[a][c] = row[16 * c];
-            } else {
-                v[a][c] = us2{row[16 * (2 * c)], row[16 * (2 * c + 1)]};
+    if constexpr (STAGE) {
+        // through LDS: 16-byte loads of the tile, then each thread takes its
+        // strided elements (few registers in flight)
+        {
+            constexpr int V = 16 / (int)sizeof(E);
+            constexpr int VPR = B / V;
+            for (int q = threadIdx.x; q < B * VPR; q += 256) {
+                const int r = q / VPR, cv = q % VPR;
+                *(FW_LDS v4u32 *)(lb + r * B + cv * V) = *retype<const v4u32>(src + (int64_t)r * lds_ + cv * V);
+            }
+        }
+        __syncthreads();
+        for (int a = 0; a < D::RA; ++a) {
+            const FW_LDS E *row = lb + (ty + 16 * a) * B + tx;
+            for (int c = 0; c < D::WC; ++c) {
+                if constexpr (sizeof(E) == 4) {
+                    v[a][c] = row[16 * c];
+                } else {
+                    v[a][c] = us2{row[16 * (2 * c)], row[16 * (2 * c + 1)]};
+                }
+            }
+        }
+        __syncthreads();
+    } else {
+        for (int a = 0; a < D::RA; ++a) {
+            const auto row = src + (int64_t)(ty + 16 * a) * lds_ + tx;
+            for (int c = 0; c < D::WC; ++c) {
+                if constexpr (sizeof(E) == 4) {
+                    v[a][c] = row[16 * c];
+                } else {
+                    v[a][c] = us2{row[16 * (2 * c)], row[16 * (2 * c + 1)]};
+                }
             }
         }
     }
-    D::template publish<0>(v, 0, buf, tx, ty);
-    D::template steps<0>(v, tx, ty, buf);
-    for (int a = 0; a < D::RA; ++a) {
-        const auto row = dst + (int64_t)(ty + 16 * a) * ldd_ + tx;
-        E *row2 = dst2 ? dst2 + (int64_t)(ty + 16 * a) * ldd2 + tx : nullptr;
-        for (int b = 0; b < D::CW; ++b) {
-            const E x = lane_get<E>(v[a], b);
-            row[16 * b] = x;
-            if (row2) __hip_atomic_store(row2 + 16 * b, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    D::template publish<0>(v, 0, lb, tx, ty);
+    D::template steps<0>(v, tx, ty, lb);
+    if constexpr (STAGE) {
+        __syncthreads();  // every thread is done with the last block's slot
+        for (int a = 0; a < D::RA; ++a) {
+            FW_LDS E *row = lb + (ty + 16 * a) * B + tx;
+            for (int b = 0; b < D::CW; ++b) row[16 * b] = lane_get<E>(v[a], b);
+        }
+        __syncthreads();
+        constexpr int V = 16 / (int)sizeof(E);
+        constexpr int VPR = B / V;
+        for (int q = threadIdx.x; q < B * VPR; q += 256) {
+            const int r = q / VPR, cv = q % VPR;
+            const v4u32 x = *(const FW_LDS v4u32 *)(lb + r * B + cv * V);
+            *retype<v4u32>(dst + (int64_t)r * ldd_ + cv * V) = x;
+            if (dst2) {
+                uint32_t *d2 = reinterpret_cast<uint32_t *>(dst2 + (int64_t)r * ldd2 + cv * V);
+                __hip_atomic_store(d2 + 0, x.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(d2 + 1, x.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(d2 + 2, x.z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(d2 + 3, x.w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    } else {
+        for (int a = 0; a < D::RA; ++a) {
+            const auto row = dst + (int64_t)(ty + 16 * a) * ldd_ + tx;
+            E *row2 = dst2 ? dst2 + (int64_t)(ty + 16 * a) * ldd2 + tx : nullptr;
+            for (int b = 0; b < D::CW; ++b) {
+                const E x = lane_get<E>(v[a], b);
+                row[16 * b] = x;
+                if (row2) __hip_atomic_store(row2 + 16 * b, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
     }
     __syncthreads();
 }
 
-template <typename E, int B, int S, typename SrcP, typename DstP>
+template <typename E, int B, int S, bool STAGE, typename SrcP, typename DstP>
 __device__ __attribute__((noinline)) void diag_close_call(SrcP src, int64_t lds_, DstP dst, int64_t ldd_,
                                                           E *__restrict__ dst2, int64_t ldd2, E *buf) {
-    diag_close_body<E, B, S>(src, lds_, dst, ldd_, dst2, ldd2, buf);
+    diag_close_body<E, B, S, STAGE>(src, lds_, dst, ldd_, dst2, ldd2, buf);
+}
+
+// LDS elements diag_close<E, B, S, STAGE> needs (16-byte aligned): the
+// blocks' slots, and with STAGE the whole tile.
+template <typename E, int B, int S = diag_steps<E, B>(), bool STAGE = false>
+constexpr int diag_lds_elems() {
+    return STAGE && B * B > Diag<E, B, S>::LDS_ELEMS ? B * B : Diag<E, B, S>::LDS_ELEMS;
 }
 
 // Close the B x B tile at src (row pitch lds_) and write it to dst, and to
 // dst2 when given (with agent-scope stores: dst2 is a tile that other
-// workgroups read); buf holds diag_lds_elems<E, B, S>() elements of LDS.  Small
-// tiles are inlined; the larger ones are a call of their own, so that their
-// register demand is not added to the caller's.
-template <typename E, int B, int S = diag_steps<E, B>(), typename SrcP, typename DstP>
+// workgroups read); buf holds diag_lds_elems<E, B, S, STAGE>() elements of
+// LDS.  With STAGE the tile moves between memory and registers through LDS
+// as 16-byte vectors (src, dst and dst2 rows 16-byte aligned); without, each
+// thread reads and writes its own strided elements.  Small tiles are
+// inlined; the larger ones are a call of their own, so that their register
+// demand is not added to the caller's.
+template <typename E, int B, int S = diag_steps<E, B>(), bool STAGE = false, typename SrcP, typename DstP>
 __device__ __attribute__((always_inline)) inline void diag_close(SrcP src, int64_t lds_, DstP dst, int64_t ldd_,
                                                             E *__restrict__ dst2, int64_t ldd2, E *buf) {
     if constexpr (B >= 128)
-        diag_close_call<E, B, S>(src, lds_, dst, ldd_, dst2, ldd2, buf);
+        diag_close_call<E, B, S, STAGE>(src, lds_, dst, ldd_, dst2, ldd2, buf);
     else
-        diag_close_body<E, B, S>(src, lds_, dst, ldd_, dst2, ldd2, buf);
+        diag_close_body<E, B, S, STAGE>(src, lds_, dst, ldd_, dst2, ldd2, buf);
 }
 
 }  // namespace fw
