@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 VALU_LANE_OPS = 256 * 64 * 2.4e9
 HBM_BYTES = 8.0e12
 
-WORKLOADS = ("mid", "small", "large", "learned", "batch")
+WORKLOADS = ("mid", "small", "large", "learned", "batch", "paper")
 
 
 def measured_traffic(kernel, workload_name):
@@ -75,6 +75,20 @@ def valu_probe(ctx):
             "what": "packed uint16 max/min/add/sub, 8 independent chains per lane, 8 waves per SIMD"}
 
 
+def host_cpu():
+    """The host CPU the oracle ran on: model name and logical CPUs."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count()}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,7 +110,7 @@ def parse():
 def make_workload(name):
     import workload
     return {"mid": workload.plain_mid, "small": workload.plain_small, "large": workload.plain_large,
-            "learned": workload.plain_learned}[name]()
+            "learned": workload.plain_learned, "paper": workload.plain_paper}[name]()
 
 
 def bench_learned(args):
@@ -362,6 +376,7 @@ def bench_batch(args):
         t_cpu = time.perf_counter() - t0
         cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
         out["cpu_baseline"] = {"value": k / t_cpu, "unit": "elections/s", "cores": cores, "kind": "oracle",
+                               **host_cpu(),
                                "sample": f"the first {k} of the {E} elections, whole path per election "
                                          f"({t_cpu:.1f} s; ballot generation excluded)"}
     print(json.dumps(out), flush=True)
@@ -405,6 +420,7 @@ def cpu_baseline(wl, sample_voters):
         "value": wl.m ** 3 / t_step / 1e9,
         "unit": "Gop/s",
         "cores": cores,
+        **host_cpu(),
         "kind": "oracle",
         "sample": (f"count over the first {ns} of {wl.n} ballots scaled by n/{ns} "
                    f"({t_count:.1f} s scaled); weights+closure+ranking at full m={wl.m} ({t_rest:.1f} s)"),
@@ -556,6 +572,20 @@ def main():
         "roofline": roof,
         "roofline_closure": closure_roof,
     }
+    if args.workload == "paper":
+        # the paper's own algorithm (winners only) on the same counts, and its
+        # published single-core timings at this shape, for context
+        ctx.winners_propagate(d)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, st = ctx.winners_propagate(d)
+        torch.cuda.synchronize()
+        out["label_propagation_ms"] = (time.perf_counter() - t0) * 1e3
+        out["label_propagation_stats"] = st
+        out["paper_context"] = {"closure_and_ranking_single_core_min": 221,
+                                "winners_only_single_core_min": 64,
+                                "shape": "Global150 chart data: m=14187, n=15553, top-150",
+                                "note": "the paper's own hardware and data; not a target"}
     if args.calibrate_copy:
         src = torch.empty(1 << 28, dtype=torch.int32, device=dev).fill_(1)
         dst = torch.empty_like(src)

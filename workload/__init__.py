@@ -206,6 +206,16 @@ def plain_large(seed: int = 1003, n: int = 1_000_000, m: int = 16384) -> Workloa
                     "Plackett-Luce Zipf s=1.1, top-20, m=%d, n=%d, seed %d" % (m, n, seed))
 
 
+def plain_paper(seed: int = 1006, n: int = 15553, m: int = 14187) -> Workload:
+    """The paper's largest chart shape (m=14187 candidates, n=15553 voters,
+    top-150 lists; Table 1), drawn here as Plackett-Luce with Zipf(1.0)
+    weights; uint16 counts.  For context next to the paper's single-core
+    timings; no chart data is used."""
+    b = pl_zipf(seed, n, m, 1.0, 150)
+    return Workload("plzipf_m%d_n%d_top150" % (m, n), m, n, b, "u16",
+                    "Plackett-Luce Zipf s=1.0, top-150, m=%d, n=%d, seed %d" % (m, n, seed))
+
+
 def plain_learned(seed: int = 1005, n: int = 200_000, m: int = 32768) -> Workload:
     """m=32768, n=200000 top-30 Plackett-Luce with Zipf(1.0) weights; int32 counts."""
     b = pl_zipf(seed, n, m, 1.0, 30)
