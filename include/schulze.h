@@ -340,7 +340,7 @@ int schulze_set_closure_schedule(schulze_ctx *ctx, int schedule);
 /*
  * Tile size B of the blocked closure (Section 5.2's recurrence cut into
  * B x B tiles): 0 (default) picks by value width and m (uint16: 128 from
- * m = 8192 on, else 64; int32: 128 from m = 2048 on, else 64), 64 or 128
+ * m = 6144 on, else 64; int32: 128 from m = 2048 on, else 64), 64 or 128
  * force it.
  * Every B gives the same p; a larger B does more work per tile and round
  * and has fewer rounds, a smaller one more parallelism per round.  Returns

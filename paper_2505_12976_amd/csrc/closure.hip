@@ -706,7 +706,7 @@ extern "C" int schulze_closure(schulze_ctx *ctx, void *stream, const void *d, in
     if (bind_device(ctx) != SCHULZE_OK) return SCHULZE_EDEVICE;
     hipStream_t s = (hipStream_t)stream;
     const int tile = ctx->closure_tile;
-    const int bu = tile ? tile : (m >= 8192 ? 128 : 64);  // uint16 tile
+    const int bu = tile ? tile : (m >= 6144 ? 128 : 64);  // uint16 tile
     const int bi = tile ? tile : (m >= 2048 ? 128 : 64);  // int32 tile
     const int32_t *di = static_cast<const int32_t *>(d);
     int32_t *pi = static_cast<int32_t *>(p);
