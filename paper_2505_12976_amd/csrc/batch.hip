@@ -430,14 +430,14 @@ __device__ __attribute__((noinline)) void count_item(const BatchArgs &a, const B
         }
     };
     const cus2 ones = {1, 1};
-    auto stage_store = [&](int64_t q0) {
+    auto stage_store = [&](int64_t q0, uint32_t *stb) {
 #pragma unroll
         for (int k = 0; k < MAX_PF; ++k) {
             const int32_t qd = qlane + 64 * (k & (ng - 1));
             const int32_t vp = prow + 4 * (k >> lg);
             if (qd < nq) {
                 const v4u32 v = slot_ok(k, q0) ? pf[k] : v4u32{0u, 0u, 0u, 0u};
-                *reinterpret_cast<v4u32 *>(stage + vp * cols + (qd & 1) * half + (qd >> 1) * 4) = v;
+                *reinterpret_cast<v4u32 *>(stb + vp * cols + (qd & 1) * half + (qd >> 1) * 4) = v;
                 // words through scalars: a bit_cast of an element of a vector value
                 // has compiled to the first element here
                 const uint32_t w[4] = {v.x, v.y, v.z, v.w};
@@ -448,18 +448,24 @@ __device__ __attribute__((noinline)) void count_item(const BatchArgs &a, const B
         }
     };
 
+    // Two stage buffers (VC * cols <= 8192 words each): chunk c is counted
+    // from one while chunk c+1 is written to the other, one barrier per chunk.
     const int32_t xo = (bx - cb0) * 4, yo = (by - cb0) * 4;
+    uint32_t *const stage_b[2] = {stage, stage + VC * cols};
     prefetch(p0);
+    __syncthreads();  // the stage is free (a previous item of this workgroup may have used it)
+    stage_store(p0, stage_b[0]);
+    __syncthreads();
+    int cur = 0;
     for (int64_t q0 = p0; q0 < p1; q0 += VC) {
-        __syncthreads();  // previous chunk's compute is done with the stage
-        stage_store(q0);
-        __syncthreads();
-        if (q0 + VC < p1) prefetch(q0 + VC);  // overlaps the compute below
+        const bool more = q0 + VC < p1;
+        if (more) prefetch(q0 + VC);  // overlaps the compute below
+        const uint32_t *st = cur ? stage_b[1] : stage_b[0];  // (select: a dynamically indexed array would live in scratch)
         const int32_t vend = (int32_t)min((int64_t)VC, p1 - q0);
         if (active) {
 #pragma unroll 1
             for (int32_t v = phase; v < vend; v += vs) {
-                const uint32_t *row = stage + v * cols;
+                const uint32_t *row = st + v * cols;
                 const uint4 xa = *reinterpret_cast<const uint4 *>(row + xo);
                 const uint4 xb = *reinterpret_cast<const uint4 *>(row + half + xo);
                 const uint4 ya = *reinterpret_cast<const uint4 *>(row + yo);
@@ -477,6 +483,9 @@ __device__ __attribute__((noinline)) void count_item(const BatchArgs &a, const B
                 }
             }
         }
+        if (more) stage_store(q0 + VC, cur ? stage_b[0] : stage_b[1]);
+        __syncthreads();  // the next chunk is staged; everyone is done with this one
+        cur ^= 1;
     }
 
     // column sums of the range, then the counts
@@ -602,6 +611,7 @@ __device__ __attribute__((noinline)) void closure_tiled(E *P_, int32_t mp) {
     }
 }
 
+static_assert(2 * 4 * MAX_PF * 64 * 4 <= STAGE_WORDS, "two count stage buffers: VC * cols <= 32 / ng * 256 ng words each");
 static_assert(diag_lds_elems<uint16_t, 192>() * 2 <= SMEM_WORDS * 4 && diag_lds_elems<int32_t, 128>() * 4 <= SMEM_WORDS * 4,
               "diagonal closure LDS");
 
