@@ -324,8 +324,8 @@ __device__ inline void tri_coords(int32_t t, int32_t nb, int32_t &X, int32_t &Y)
 
 template <bool SQUARE>
 __global__ __launch_bounds__(CNT_THREADS, 2) void k_count_pos(DenseArgs a) {
-    __shared__ __attribute__((aligned(16))) uint32_t xs[VC][CT];
-    __shared__ __attribute__((aligned(16))) uint32_t ys[VC][CT];
+    __shared__ __attribute__((aligned(16))) uint32_t xs[2][VC][CT];  // two buffers: the chunk counted
+    __shared__ __attribute__((aligned(16))) uint32_t ys[2][VC][CT];  // and the next one being staged
     __shared__ uint32_t sred[4][2 * CT];
 
     if (SQUARE && a.meta.ctr[2] != MODE_DENSE_U) return;
@@ -423,7 +423,27 @@ __global__ __launch_bounds__(CNT_THREADS, 2) void k_count_pos(DenseArgs a) {
         for (int e = 0; e < 4; ++e) s4[e] = 0u;
     };
 
+    const us2 ones = {1, 1};
+    // staged words into LDS buffer sb, their column sums added to sadd
+    auto stage_write = [&](int sb, uint32_t (&sadd)[4]) {
+        for (int q = 0; q < 8; ++q) {
+            const int pr = prow + 4 * q;
+            uint32_t *dst = col4 < 32 ? &xs[sb][pr][col4 * 4] : &ys[sb][pr][(col4 - 32) * 4];
+            *reinterpret_cast<uint4 *>(dst) = stage[q];
+            sadd[0] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, stage[q].x), ones, sadd[0], false);
+            sadd[1] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, stage[q].y), ones, sadd[1], false);
+            sadd[2] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, stage[q].z), ones, sadd[2], false);
+            sadd[3] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, stage[q].w), ones, sadd[3], false);
+        }
+    };
+
+    // Unit u is counted from one LDS buffer while unit u+1 is staged into the
+    // other: one barrier per unit.  The next unit's column sums wait in s4n
+    // until the current segment has been flushed.
     load_unit(u0, stage);
+    stage_write(0, s4);
+    __syncthreads();
+    int cur = 0;
     for (int64_t u = u0; u < u1; ++u) {
         const int32_t t = (int32_t)(u / cpt);
         const int64_t chunk = u % cpt;
@@ -435,30 +455,20 @@ __global__ __launch_bounds__(CNT_THREADS, 2) void k_count_pos(DenseArgs a) {
             seg_p0 = chunk * VC;
         }
         seg_p1 = min(n_pairs, (chunk + 1) * VC);
-
-        __syncthreads();  // previous compute done with xs/ys
-        const us2 ones = {1, 1};
-        for (int q = 0; q < 8; ++q) {
-            const int pr = prow + 4 * q;
-            uint32_t *dst = col4 < 32 ? &xs[pr][col4 * 4] : &ys[pr][(col4 - 32) * 4];
-            *reinterpret_cast<uint4 *>(dst) = stage[q];
-            s4[0] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, stage[q].x), ones, s4[0], false);
-            s4[1] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, stage[q].y), ones, s4[1], false);
-            s4[2] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, stage[q].z), ones, s4[2], false);
-            s4[3] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, stage[q].w), ones, s4[3], false);
-        }
-        __syncthreads();
-        if (u + 1 < u1) load_unit(u + 1, stage);  // overlaps the compute below
+        const bool more = u + 1 < u1;
+        if (more) load_unit(u + 1, stage);  // overlaps the compute below
 
         // Two voter pairs per iteration, the LDS reads of each pair issued
         // before the products of the previous one (scheduling barriers keep
         // them there), so that their latency hides behind 128 VALU
         // instructions.
+        const uint32_t(*xb)[CT] = cur ? xs[1] : xs[0];  // (selects: no dynamically indexed arrays)
+        const uint32_t(*yb)[CT] = cur ? ys[1] : ys[0];
         auto read_pair = [&](int v, uint4 (&q)[4]) {
-            q[0] = *reinterpret_cast<const uint4 *>(&xs[v][ty * 8]);
-            q[1] = *reinterpret_cast<const uint4 *>(&xs[v][ty * 8 + 4]);
-            q[2] = *reinterpret_cast<const uint4 *>(&ys[v][tx * 8]);
-            q[3] = *reinterpret_cast<const uint4 *>(&ys[v][tx * 8 + 4]);
+            q[0] = *reinterpret_cast<const uint4 *>(&xb[v][ty * 8]);
+            q[1] = *reinterpret_cast<const uint4 *>(&xb[v][ty * 8 + 4]);
+            q[2] = *reinterpret_cast<const uint4 *>(&yb[v][tx * 8]);
+            q[3] = *reinterpret_cast<const uint4 *>(&yb[v][tx * 8 + 4]);
         };
         auto count_pair = [&](const uint4 (&q)[4]) {
             const uint32_t xv[8] = {q[0].x, q[0].y, q[0].z, q[0].w, q[1].x, q[1].y, q[1].z, q[1].w};
@@ -485,15 +495,19 @@ __global__ __launch_bounds__(CNT_THREADS, 2) void k_count_pos(DenseArgs a) {
             __builtin_amdgcn_sched_barrier(0);
             count_pair(qb);
         }
+        uint32_t s4n[4] = {0u, 0u, 0u, 0u};
+        if (more) stage_write(cur ^ 1, s4n);
+        __syncthreads();  // the next unit is staged; everyone is done with this one
 
-        const bool last = u + 1 >= u1;
-        bool boundary = last;
-        if (!last) {
+        bool boundary = !more;
+        if (more) {
             const int32_t tn = (int32_t)((u + 1) / cpt);
             const int64_t cn = (u + 1) % cpt;
             boundary = tn != t || cn % SEGC == 0;
         }
         if (boundary) flush();
+        for (int e = 0; e < 4; ++e) s4[e] += s4n[e];
+        cur ^= 1;
     }
 }
 
