@@ -243,6 +243,10 @@ __global__ __launch_bounds__(256) void k_scatter(const void *__restrict__ ballot
     const int32_t *srcs = FULL ? meta.full_src : meta.trunc_src;
     const bool has_hi = 2 * q + 1 < count;
     const int32_t src[2] = {srcs[2 * q], has_hi ? srcs[2 * q + 1] : -1};
+    // 16-byte ballot reads (uint16 ids, rows 16-byte aligned) and position
+    // stores (rows and chunks in multiples of four words)
+    const bool vec16 = !dtype32 && (L % 8) == 0 && (reinterpret_cast<uintptr_t>(ballots) % 16) == 0;
+    const bool vec_out = (pitch % 4) == 0 && (reinterpret_cast<uintptr_t>(pos) % 16) == 0;
     if (threadIdx.x < 2) unset_cnt[threadIdx.x] = 0;
     for (int32_t c0 = 0; c0 < pitch; c0 += SCATTER_CH) {
         const int32_t cn = min(SCATTER_CH, pitch - c0);
@@ -253,16 +257,29 @@ __global__ __launch_bounds__(256) void k_scatter(const void *__restrict__ ballot
             if (src[h] < 0) continue;
             const int32_t k = meta.len[src[h]];
             const int64_t base = (int64_t)src[h] * L;
-            for (int t = threadIdx.x; t < k; t += 256) {
-                const int32_t id = read_id(ballots, dtype32, base + t);
-                if (id < 0 || id >= m) continue;  // reported by the scan
+            auto place = [&](int32_t t, int32_t id) {
+                if (id < 0 || id >= m) return;  // reported by the scan
                 const int32_t col = FULL ? id : meta.umap[id];
                 if (col >= c0 && col < c0 + cn) buf[2 * (col - c0) + h] = (uint16_t)t;
+            };
+            if (vec16) {
+                // eight uint16 ids per 16-byte load
+                const uint4 *row = reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(ballots) + base);
+                for (int32_t t8 = 8 * threadIdx.x; t8 < k; t8 += 8 * 256) {
+                    const uint4 v = row[t8 >> 3];
+                    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+                    for (int e = 0; e < 8; ++e) {
+                        const uint32_t raw = (e & 1) ? (w[e >> 1] >> 16) : (w[e >> 1] & 0xFFFFu);
+                        if (t8 + e < k) place(t8 + e, raw == 0xFFFFu ? -1 : (int32_t)raw);
+                    }
+                }
+            } else {
+                for (int t = threadIdx.x; t < k; t += 256) place(t, read_id(ballots, dtype32, base + t));
             }
         }
         __syncthreads();
         int32_t un0 = 0, un1 = 0;
-        for (int i = threadIdx.x; i < cn; i += 256) {
+        auto word = [&](int i) -> uint32_t {
             const int32_t col = c0 + i;
             uint16_t lo = buf[2 * i], hi = buf[2 * i + 1];
             if (col < ncols) {
@@ -278,7 +295,16 @@ __global__ __launch_bounds__(256) void k_scatter(const void *__restrict__ ballot
                 // unlisted (and the sentinel column): one shared position
                 if (!has_hi) hi = 0;
             }
-            pos[q * (int64_t)pitch + c0 + i] = (uint32_t)lo | ((uint32_t)hi << 16);
+            return (uint32_t)lo | ((uint32_t)hi << 16);
+        };
+        if (vec_out) {
+            // four words per 16-byte store
+            for (int i4 = 4 * threadIdx.x; i4 < cn; i4 += 4 * 256) {
+                const uint4 o = make_uint4(word(i4), word(i4 + 1), word(i4 + 2), word(i4 + 3));
+                *reinterpret_cast<uint4 *>(pos + q * (int64_t)pitch + c0 + i4) = o;
+            }
+        } else {
+            for (int i = threadIdx.x; i < cn; i += 256) pos[q * (int64_t)pitch + c0 + i] = word(i);
         }
         if (un0) atomicAdd(&unset_cnt[0], un0);
         if (un1) atomicAdd(&unset_cnt[1], un1);
