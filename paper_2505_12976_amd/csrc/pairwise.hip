@@ -131,6 +131,73 @@ __global__ __launch_bounds__(256) void k_scan_long(const void *__restrict__ ball
     record_ballots(meta, nf, lf, nt, lt);
 }
 
+// Long rows of uint16 ids (L a multiple of 8, 16-byte aligned rows): one
+// wavefront per ballot, eight ids per 16-byte load; the first padding entry
+// is a wavefront minimum, so no workgroup barrier is needed per ballot.  The
+// full and truncated lists keep ballot order, as in k_scan_long.
+__global__ __launch_bounds__(256) void k_scan_long_vec(const uint16_t *__restrict__ ballots, int64_t n, int32_t L,
+                                                       int32_t m, Meta meta, int32_t *err) {
+    __shared__ int32_t lf[LONG_CHUNK], lt[LONG_CHUNK];
+    __shared__ uint8_t kind[LONG_CHUNK];  // 0 none, 1 full, 2 truncated
+    __shared__ int32_t nf, nt;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t v0 = (int64_t)blockIdx.x * LONG_CHUNK;
+    const int32_t L8 = L / 8;
+    bool bad = false;
+    unsigned long long k2 = 0;
+    for (int q = wave; q < LONG_CHUNK; q += 4) {
+        const int64_t v = v0 + q;
+        if (v >= n) {
+            if (lane == 0) kind[q] = 0;
+            continue;
+        }
+        const uint4 *row = reinterpret_cast<const uint4 *>(ballots + v * (int64_t)L);
+        int32_t first = L;
+        for (int32_t j = lane; j < L8; j += 64) {
+            const uint4 x = row[j];
+            const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+            for (int e = 7; e >= 0; --e) {  // the lowest padding index of the eight wins
+                const uint32_t raw = (e & 1) ? (w[e >> 1] >> 16) : (w[e >> 1] & 0xFFFFu);
+                if (raw == 0xFFFFu) first = min(first, 8 * j + e);
+            }
+        }
+        for (int off = 32; off >= 1; off >>= 1) first = min(first, __shfl_xor(first, off));
+        const int32_t k = first;
+        const bool trunc = k < m - 1;
+        for (int32_t j = lane; 8 * j < k; j += 64) {
+            const uint4 x = row[j];
+            const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+            for (int e = 0; e < 8; ++e) {
+                if (8 * j + e >= k) break;
+                const int32_t c = (int32_t)((e & 1) ? (w[e >> 1] >> 16) : (w[e >> 1] & 0xFFFFu));
+                if (c >= m)
+                    bad = true;
+                else if (trunc)
+                    meta.in_u[c] = 1;
+            }
+        }
+        if (lane == 0) {
+            meta.len[v] = k;
+            kind[q] = trunc ? 2 : 1;
+            if (trunc) k2 += (unsigned long long)k * (k - 1) / 2;
+        }
+    }
+    if (bad) set_device_error(err, SCHULZE_EBALLOT);
+    if (lane == 0 && k2) atomicAdd(&meta.k2[blockIdx.x % NPART], k2);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t a = 0, b = 0;
+        for (int q = 0; q < LONG_CHUNK; ++q) {
+            if (kind[q] == 1) lf[a++] = (int32_t)(v0 + q);
+            if (kind[q] == 2) lt[b++] = (int32_t)(v0 + q);
+        }
+        nf = a;
+        nt = b;
+    }
+    __syncthreads();
+    record_ballots(meta, nf, lf, nt, lt);
+}
+
 // Short rows (L <= 64): one lane per entry, SHORT_PER_WAVE ballots per wave.
 __global__ __launch_bounds__(256) void k_scan_short(const void *__restrict__ ballots, int dtype32, int64_t n, int32_t L,
                                                     int32_t m, Meta meta, int32_t *err) {
@@ -997,6 +1064,10 @@ extern "C" int schulze_pairwise(schulze_ctx *ctx, void *stream, const void *ball
             SCHULZE_LAUNCH(ctx, K_BALLOT_SCAN, s,
                            k_scan_short<<<dim3((unsigned)ceil_div(n, per_wg)), dim3(256), 0, s>>>(
                                ballots, dtype32, n, L, m, meta, ctx->err));
+        } else if (!dtype32 && L % 8 == 0 && reinterpret_cast<uintptr_t>(ballots) % 16 == 0) {
+            SCHULZE_LAUNCH(ctx, K_BALLOT_SCAN, s,
+                           k_scan_long_vec<<<dim3((unsigned)ceil_div(n, LONG_CHUNK)), dim3(256), 0, s>>>(
+                               static_cast<const uint16_t *>(ballots), n, L, m, meta, ctx->err));
         } else {
             SCHULZE_LAUNCH(ctx, K_BALLOT_SCAN, s,
                            k_scan_long<<<dim3((unsigned)ceil_div(n, LONG_CHUNK)), dim3(256), 0, s>>>(

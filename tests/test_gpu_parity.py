@@ -176,9 +176,18 @@ def test_invalid_ballots_set_device_error(ctx):
     import paper_2505_12976_amd as sz
     long_dup = np.full((1, 66), -1, dtype=np.int32)
     long_dup[0, :5] = [3, 1, 2, 3, 0]
+    # uint16 rows of 72 entries take the 16-byte scan and scatter
+    u16_range = np.full((3, 72), 0xFFFF, dtype=np.uint16)
+    u16_range[:, :70] = np.arange(70, dtype=np.uint16)
+    u16_range[1, 40] = 80
+    u16_dup = np.full((3, 72), 0xFFFF, dtype=np.uint16)
+    u16_dup[:, :71] = np.arange(71, dtype=np.uint16)
+    u16_dup[2, 9] = 3
     cases = [(np.array([[0, 1, 1, 2]], dtype=np.int32), 4),      # repeated id
              (np.array([[0, 9, -1, -1]], dtype=np.int32), 4),    # id out of range
-             (long_dup, 66)]                                      # repeated id, long row
+             (long_dup, 66),                                      # repeated id, long row
+             (u16_range, 72),                                     # id out of range, uint16 long rows
+             (u16_dup, 72)]                                       # repeated id, uint16 long rows
     for bad, m in cases:
         log(f"[case] invalid ballot {bad[0, :6].tolist()} m={m}")
         got = gpu_path(ctx, bad, m, "i32")
