@@ -411,7 +411,11 @@ int close_padded(schulze_ctx *ctx, hipStream_t s, E *P, int64_t ld, int32_t nb) 
             int32_t *flags = static_cast<int32_t *>(ctx->ws[WS_FLAGS]);
             if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(flags), (size_t)(nslots + 64), 0u)) != SCHULZE_OK)
                 return rc;
-            const int32_t early = (int64_t)nb * nb <= 8 * G ? 1 : 0;  // at most 8 tiles per workgroup and round
+            // early panels and the two-rounds-ahead diagonal while each workgroup
+            // has few tiles per round: at most 20 (uint16) or 8 (int32); measured
+            // on one MI355X: uint16 m = 12288 66.1 -> 62.1 ms, m = 14187 112.8 ->
+            // 111.6 ms, m = 16384 146.4 -> 148 ms (hence off there)
+            const int32_t early = (int64_t)nb * nb <= (sizeof(E) == 2 ? 20 : 8) * G ? 1 : 0;
             PersistArgs<E> pa{P,     ld,    nb, static_cast<E *>(ctx->ws[WS_RING]), flags, flags + nslots, ctx->err,
                               (int64_t)1 << 22, early};
             void *args[] = {&pa};
