@@ -96,7 +96,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", choices=WORKLOADS, default="mid")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-voters", type=int, default=3000)
+    ap.add_argument("--cpu-sample-voters", type=int, default=30000)
     ap.add_argument("--batch-elections", type=int, default=4096)
     ap.add_argument("--no-per-election", action="store_true",
                     help="batch workload: skip the pass of per-election calls (profiling runs)")
@@ -401,14 +401,14 @@ def cpu_baseline(wl, sample_voters):
     t_step = t_count + t_rest
     cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
     # one thread, as the paper times its sequential baseline: count over a
-    # smaller sample, closure at m1 = min(m, 1024) extrapolated by (m / m1)^3
+    # smaller sample, closure at m1 = min(m, 2048) extrapolated by (m / m1)^3
     prev = oracle.set_threads(1)
     try:
         ns1 = min(max(1, sample_voters // 10), wl.n)
         t0 = time.perf_counter()
         oracle.pairwise(wl.ballots[:ns1], wl.m)
         t_count1 = (time.perf_counter() - t0) * (wl.n / ns1)
-        m1 = min(wl.m, 1024)
+        m1 = min(wl.m, 2048)
         w1 = np.ascontiguousarray(w[:m1, :m1])
         t0 = time.perf_counter()
         oracle.closure(w1)
