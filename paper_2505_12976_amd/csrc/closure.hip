@@ -94,12 +94,15 @@ struct PersistArgs {
 
 constexpr int MAX_OWNED = 512;
 
-// Owner of tile (I, J): every block row and block column spreads over
-// distinct workgroups (so the panels of a round are computed in parallel).
+// Owner of tile (I, J): tile (I, J) is number I nb + (I + J) mod nb (block
+// rows in order, each rotated by its index) and the numbers are dealt to the
+// G workgroups in turn.  Every workgroup owns floor or ceil of nb^2 / G
+// tiles (all of them take part whatever nb is), a block row spreads over
+// distinct workgroups when nb <= G, and a block column too when G is a
+// multiple of nb, so that the panels of a round are computed in parallel.
+// (32-bit arithmetic: the host launches the kernel only for nb^2 <= MAX_OWNED G)
 __device__ inline int32_t tile_owner(int32_t I, int32_t J, int32_t nb, int32_t G) {
-    int32_t q = G / nb;
-    if (q < 1) q = 1;
-    return (((I + J) % nb) + nb * (I % q)) % G;
+    return (int32_t)(((uint32_t)I * (uint32_t)nb + (uint32_t)((I + J) % nb)) % (uint32_t)G);
 }
 
 // slot of a published tile within a round: 0 diag, 1+J row panel, 1+nb+I column panel

@@ -17,14 +17,14 @@ import oracle
 
 
 def owner(I, J, nb, G):
-    q = max(1, G // nb)
-    return (((I + J) % nb) + nb * (I % q)) % G
+    return (I * nb + (I + J) % nb) % G
 
 
-def wg_program(w, nb, G, flags):
-    """The order in which workgroup w takes its items: ('diag'|'panel'|'rest'|'probe', round, I, J, flags waited on)."""
+def wg_program(w, nb, G, flags, gate):
+    """The order in which workgroup w takes its items: ('diag'|'panel'|'rest'|'probe', round, I, J, flags waited on).
+    gate: early steps while nb^2 <= gate * G (20 for uint16, 8 for int32)."""
     owned = [t for t in range(nb * nb) if owner(t // nb, t % nb, nb, G) == w]
-    early = nb * nb <= 8 * G
+    early = nb * nb <= gate * G
     has_panels = lambda r: any(((t // nb) == r) != ((t % nb) == r) for t in owned)
 
     def panels(r):
@@ -82,12 +82,12 @@ def maxmin(A, Bm):
     return np.max(np.minimum(A[:, :, None], Bm[None, :, :]), axis=1)
 
 
-def simulate(w0, B, G, rng):
+def simulate(w0, B, G, rng, gate):
     m = w0.shape[0]
     nb = m // B
     P = w0.copy()
     ring, flags = {}, set()
-    progs = [wg_program(w, nb, G, flags) for w in range(G)]
+    progs = [wg_program(w, nb, G, flags, gate) for w in range(G)]
     pending = [next(p, None) for p in progs]
     tile = lambda a, b: P[a * B:(a + 1) * B, b * B:(b + 1) * B]
     while any(x is not None for x in pending):
@@ -119,13 +119,31 @@ def simulate(w0, B, G, rng):
     return P
 
 
-# (m, B, G): early steps on and off, G >= nb and G < nb, one to several tiles per workgroup
+# (m, B, G): early steps on and off, G a multiple of nb, G >= nb but not a
+# multiple (G = nb + 1 gives tile (r+2, r+2) and panel (r+1, r+2) one owner),
+# G < nb, one to several tiles per workgroup
 @pytest.mark.parametrize("m,B,G", [(16, 4, 3), (24, 4, 7), (32, 8, 5), (32, 4, 64), (40, 4, 16), (64, 8, 8),
-                                   (48, 4, 12), (64, 4, 40), (36, 4, 9), (44, 4, 11)])
-def test_schedule_never_deadlocks_and_closes_exactly(m, B, G):
+                                   (48, 4, 12), (64, 4, 40), (36, 4, 9), (44, 4, 11), (36, 4, 10), (44, 4, 12),
+                                   (44, 4, 13), (40, 4, 23), (44, 4, 7)])
+@pytest.mark.parametrize("gate", [8, 20])
+def test_schedule_never_deadlocks_and_closes_exactly(m, B, G, gate):
     rng = np.random.default_rng(m * 1000 + G)
     w = rng.integers(0, 9, size=(m, m)).astype(np.int64) * (rng.random((m, m)) < 0.5)
     np.fill_diagonal(w, 0)
     want = oracle.closure(w)
     for _ in range(4):
-        assert (simulate(w, B, G, rng) == want).all()
+        assert (simulate(w, B, G, rng, gate) == want).all()
+
+
+@pytest.mark.parametrize("nb,G", [(111, 768), (64, 1280), (96, 768), (100, 768), (9, 10), (13, 5), (520, 768)])
+def test_owner_map_balance(nb, G):
+    """Every workgroup owns floor or ceil of nb^2 / G tiles; block rows spread
+    over distinct workgroups when nb <= G, block columns too when nb divides G."""
+    I, J = np.meshgrid(np.arange(nb), np.arange(nb), indexing="ij")
+    o = owner(I, J, nb, G)
+    cnt = np.bincount(o.ravel(), minlength=G)
+    assert cnt.max() - cnt.min() <= 1 and cnt.sum() == nb * nb
+    if nb <= G:
+        assert all(len(set(o[i, :])) == nb for i in range(nb))
+        if G % nb == 0:
+            assert all(len(set(o[:, j])) == nb for j in range(nb))
