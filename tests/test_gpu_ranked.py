@@ -164,3 +164,29 @@ def test_closure_tile_sizes(ctx, tile):
     finally:
         ctx.set_closure_tile(0)
         ctx.set_value_ranking(True)
+
+
+@pytest.mark.parametrize("m", [3000, 6200])
+def test_closure_grid_not_a_multiple_of_tiles(ctx, m):
+    """Sizes whose count of block rows does not divide the persistent grid
+    (uint16: 47 rows of 64-wide tiles over 1280 workgroups, 49 rows of
+    128-wide tiles over 768; int32: 24 rows over 256), so that the owner
+    map deals the tiles unevenly over block columns."""
+    import torch
+    rng = np.random.default_rng(m)
+    d = rng.integers(0, 3000, size=(m, m), dtype=np.int64)
+    np.fill_diagonal(d, 0)
+    want = oracle.closure(oracle.weights(d, oracle.WINNING_VOTES))
+    cases = [(np.uint16, True)] + ([(np.int32, True), (np.int32, False)] if m == 3000 else [])
+    try:
+        for dt, ranking in cases:
+            log(f"[case] grid m={m} dtype={np.dtype(dt).name} ranking={ranking}")
+            ctx.set_value_ranking(ranking)
+            p = ctx.closure(torch.from_numpy(d.astype(dt)).cuda(), "winning_votes")
+            torch.cuda.synchronize()
+            assert ctx.device_error() == 0
+            got = p.cpu().numpy().astype(np.int64)
+            bad = np.argwhere(got != want)
+            assert bad.size == 0, f"m={m} dtype={dt} ranking={ranking}: {len(bad)} differences, first {bad[:5].tolist()}"
+    finally:
+        ctx.set_value_ranking(True)
