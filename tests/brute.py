@@ -230,3 +230,66 @@ def topk_by_removal(w: np.ndarray, k: int) -> list[list[int]]:
         ranked += len(win)
         left = [c for c in left if c not in win]
     return levels
+
+
+def features(ballots, m: int, n_voters: float, mode: int) -> np.ndarray:
+    """The 16 per-candidate feature columns, one candidate at a time from
+    pair-list counts (Python integers, exact), scaled in float64 at the end.
+
+    Columns (x = the candidate, y over the other m-1 candidates; "edge
+    weight" is the tournament graph's, winning votes for mode 0, positive
+    margin for mode 1, Section 2.1):
+      0 wins (d[x][y] > d[y][x]) / (m-1)    1 ties (d[x][y] = d[y][x]) / (m-1)
+      2 sum d[x][y] / (m-1) / n             3 largest out-weight / n
+      4 largest in-weight / n               5 1 if in-weight max > out-weight max
+      6 sum out-weights / (m-1) / n         7 sum in-weights / (m-1) / n
+      8 smallest d[x][y]-d[y][x] / n        9 largest d[x][y]-d[y][x] / n
+      10 ln(m) / 10                         11 wins / most wins of any candidate
+      12 sum d[x][y] / the largest such sum 13 largest out-weight / its largest value
+      14 (largest out - largest in) / n     15 1
+    Ratios over a zero maximum are 0; with m = 1 every sum and extreme is 0."""
+    d = count_pairs(ballots, m)
+
+    def edge(a, b):
+        da, db = int(d[a, b]), int(d[b, a])
+        if da <= db:
+            return 0
+        return da if mode == 0 else da - db
+
+    rows = []
+    for x in range(m):
+        wins = ties = borda = 0
+        out_w, in_w = [], []
+        margins = []
+        for y in range(m):
+            if y == x:
+                continue
+            a, b = int(d[x, y]), int(d[y, x])
+            wins += a > b
+            ties += a == b
+            borda += a
+            out_w.append(edge(x, y))
+            in_w.append(edge(y, x))
+            margins.append(a - b)
+        rows.append({"wins": wins, "ties": ties, "borda": borda,
+                     "out_max": max(out_w, default=0), "in_max": max(in_w, default=0),
+                     "out_sum": sum(out_w), "in_sum": sum(in_w),
+                     "mg_min": min(margins, default=0), "mg_max": max(margins, default=0)})
+    den = (m - 1) if m > 1 else None
+    n = float(n_voters) if n_voters > 0 else 1.0
+    top_wins = max(r["wins"] for r in rows)
+    top_borda = max(r["borda"] for r in rows)
+    top_out = max(r["out_max"] for r in rows)
+    F = np.zeros((m, 16), dtype=np.float64)
+    for x, r in enumerate(rows):
+        per = (lambda v: v / den) if den else (lambda v: 0.0)
+        F[x] = [per(r["wins"]), per(r["ties"]), per(r["borda"]) / n,
+                r["out_max"] / n, r["in_max"] / n, 1.0 if r["in_max"] > r["out_max"] else 0.0,
+                per(r["out_sum"]) / n, per(r["in_sum"]) / n,
+                r["mg_min"] / n, r["mg_max"] / n,
+                np.log(m) / 10.0,
+                r["wins"] / top_wins if top_wins else 0.0,
+                r["borda"] / top_borda if top_borda else 0.0,
+                r["out_max"] / top_out if top_out else 0.0,
+                (r["out_max"] - r["in_max"]) / n, 1.0]
+    return F

@@ -77,20 +77,100 @@ def test_rounded_forward_close_to_exact():
     assert np.linalg.norm(a - b) / np.linalg.norm(b) < 2e-2
 
 
+FEATURE_CASES = [(1, 7, 25, 1), (2, 12, 25, 1), (3, 1, 25, 1), (4, 30, 25, 1), (5, 2, 4, 0), (6, 9, 10, 0),
+                 (7, 16, 6, 3), (8, 5, 40, 5)]
+
+
+def _feature_profile(seed, m, n, min_len):
+    return workload.uniform_ballots(seed, n, m, min_len=min(min_len, m), dtype=np.int32)
+
+
 def test_features_brute_force():
-    for seed, m in ((1, 7), (2, 12), (3, 1), (4, 30)):
-        b = workload.uniform_ballots(seed, 25, m, min_len=1, dtype=np.int32)
+    """Every one of the 16 columns against pair-list brute force, both weight
+    modes, on profiles with ties, truncation, m = 1 and m = 2."""
+    seen_ties = seen_neg = seen_filter = False
+    for seed, m, n, min_len in FEATURE_CASES:
+        b = _feature_profile(seed, m, n, min_len)
         d = oracle.pairwise(b, m)
         for mode in (oracle.WINNING_VOTES, oracle.MARGIN):
-            F = oracle.features(d, 25.0, mode)
-            w = oracle.weights(d, mode)
-            for x in range(m):
-                others = [y for y in range(m) if y != x]
-                assert F[x, 0] == np.float32(sum(d[x, y] > d[y, x] for y in others) / max(m - 1, 1))
-                assert F[x, 5] == float(max([w[y, x] for y in others], default=0) >
-                                        max([w[x, y] for y in others], default=0))
-                assert np.isclose(F[x, 2], sum(d[x, y] for y in others) / max(m - 1, 1) / 25.0)
-                assert np.isclose(F[x, 6], sum(w[x, y] for y in others) / max(m - 1, 1) / 25.0)
+            F = oracle.features(d, float(n), mode)
+            want = brute.features(b, m, float(n), mode)
+            assert F.dtype == np.float32 and F.shape == (m, 16)
+            np.testing.assert_allclose(F, want.astype(np.float32), rtol=2e-7, atol=1e-9,
+                                       err_msg=f"seed={seed} m={m} mode={mode}")
+            seen_ties |= bool((want[:, 1] > 0).any())
+            seen_neg |= bool((want[:, 8] < 0).any())
+            seen_filter |= bool((want[:, 5] == 1).any())
             # the filter flag never marks a winner (Section 4)
+            w = oracle.weights(d, mode)
             _, win, _ = oracle.rank(oracle.closure(w))
             assert not (win & (F[:, 5] == 1)).any()
+    assert seen_ties and seen_neg and seen_filter
+
+
+def _features_margin_over_w(d, n, mode):
+    """Planted: smallest/largest margin taken over the edge weights."""
+    F = oracle.features(d, n, mode).astype(np.float64)
+    w = oracle.weights(d, mode)
+    m = d.shape[0]
+    off = ~np.eye(m, dtype=bool)
+    F[:, 8] = np.where(off, w, np.iinfo(np.int64).max).min(axis=1) / n
+    F[:, 9] = np.where(off, w, -1).max(axis=1) / n
+    return F
+
+
+def _features_in_out_swapped(d, n, mode):
+    """Planted: largest in- and out-weight exchanged (columns 3 and 4)."""
+    F = oracle.features(d, n, mode).astype(np.float64)
+    F[:, [3, 4]] = F[:, [4, 3]]
+    return F
+
+
+def _features_diagonal_counted(d, n, mode):
+    """Planted: ties counted with the diagonal (x against itself)."""
+    F = oracle.features(d, n, mode).astype(np.float64)
+    m = d.shape[0]
+    F[:, 1] = (((d == d.T)).sum(axis=1)) / max(m - 1, 1)
+    return F
+
+
+def _features_mean_over_m(d, n, mode):
+    """Planted: mean in-weight divided by m instead of m - 1."""
+    F = oracle.features(d, n, mode).astype(np.float64)
+    w = oracle.weights(d, mode)
+    F[:, 7] = w.sum(axis=0) / d.shape[0] / n
+    return F
+
+
+def _features_margin_transposed(d, n, mode):
+    """Planted: margins read as d[y][x] - d[x][y]."""
+    F = oracle.features(d, n, mode).astype(np.float64)
+    m = d.shape[0]
+    off = ~np.eye(m, dtype=bool)
+    mg = d.T - d
+    F[:, 8] = np.where(off, mg, np.iinfo(np.int64).max).min(axis=1) / n
+    F[:, 9] = np.where(off, mg, np.iinfo(np.int64).min).max(axis=1) / n
+    return F
+
+
+def _features_ratio_of_sum(d, n, mode):
+    """Planted: normalised out-weight over the column's sum instead of its maximum."""
+    F = oracle.features(d, n, mode).astype(np.float64)
+    F[:, 13] = F[:, 3] / F[:, 3].sum() if F[:, 3].sum() > 0 else 0.0
+    return F
+
+
+@pytest.mark.parametrize("bad", [_features_margin_over_w, _features_in_out_swapped, _features_diagonal_counted,
+                                 _features_mean_over_m, _features_margin_transposed, _features_ratio_of_sum])
+def test_feature_pins_catch_planted_mistakes(bad):
+    caught = False
+    for seed, m, n, min_len in FEATURE_CASES:
+        if m < 3:
+            continue
+        b = _feature_profile(seed, m, n, min_len)
+        d = oracle.pairwise(b, m)
+        for mode in (oracle.WINNING_VOTES, oracle.MARGIN):
+            want = brute.features(b, m, float(n), mode)
+            got = bad(d, float(n), mode)
+            caught |= not np.allclose(got, want, rtol=2e-7, atol=1e-9)
+    assert caught
