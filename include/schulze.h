@@ -100,7 +100,9 @@ int schulze_get_device_error(schulze_ctx *ctx, void *stream, int32_t *err_host);
  *               voter_weight == NULL this is checked on the host (n > 65535
  *               -> SCHULZE_ERANGE); with weights, an overflowing count sets
  *               the device error word to SCHULZE_ERANGE.  SCHULZE_I32 requires
- *               counts < 2^31 (device error SCHULZE_ERANGE otherwise).
+ *               counts < 2^31 (device error SCHULZE_ERANGE otherwise).  With
+ *               weights the total weight must also stay below 2^32 (counts
+ *               accumulate in 32 bits); a larger total sets SCHULZE_ERANGE.
  * d, ldd        output m x m matrix, d[x][x] = 0.
  *
  * Workspace: up to m*m*4 bytes plus about n*m*2 bytes for full rankings.
@@ -118,6 +120,9 @@ int schulze_pairwise(schulze_ctx *ctx, void *stream, const void *ballots, int ba
  * p, ldp   output m x m: p[x][y] = width of a widest x->y path, 0 if y is
  *          unreachable from x; p[x][x] = 0.  p must not overlap d.
  * Exact integer arithmetic; results are independent of blocking.
+ * Never waits on the host, so it can be captured in a HIP graph, provided an
+ * earlier call of at least the same m and dtype has sized the context's
+ * workspace (growing it synchronises the device, which capture forbids).
  */
 int schulze_closure(schulze_ctx *ctx, void *stream, const void *d, int64_t ldd, int32_t m,
                     int dtype, int mode, void *p, int64_t ldp);
@@ -237,6 +242,44 @@ int schulze_mlp_adam(schulze_ctx *ctx, void *stream, float *params, const float 
                      float *adam_m, float *adam_v, float lr, float beta1, float beta2, float eps,
                      int32_t step);
 
+/* The network and its optimizer state for schulze_mlp_train_step.  Every
+ * pointer is device memory the caller owns; params, adam_m, adam_v and grad
+ * hold schulze_mlp_param_count() floats each. */
+typedef struct {
+    float *params;        /* FP32 master parameters (updated in place) */
+    float *adam_m;        /* Adam first moments (zero before the first step) */
+    float *adam_v;        /* Adam second moments (zero before the first step) */
+    float *grad;          /* output: the step's gradient of the mean loss */
+    int32_t *step;        /* one int32: Adam steps taken so far; each train step adds 1 and
+                             uses the new value for the bias correction */
+    float lr, beta1, beta2, eps;  /* lr > 0, 0 <= beta < 1, eps > 0 */
+} schulze_mlp;
+
+/* A minibatch of whole elections for schulze_mlp_train_step (device memory). */
+typedef struct {
+    const float *feat;      /* M x 16 feature rows (schulze_features), elections back to back */
+    const int64_t *offsets; /* E + 1 row offsets: election e is rows offsets[e] .. offsets[e+1]-1,
+                               offsets[0] = 0, offsets[E] = M */
+    const uint8_t *winner;  /* M bytes: 1 for the election's Schulze winners */
+    int64_t M;              /* rows, >= 1 */
+    int32_t E;              /* elections, >= 1 */
+} schulze_train_batch;
+
+/*
+ * One training step of the proposer: forward, the segmented loss of
+ * schulze_mlp_loss (loss: E device floats, per election), backward to
+ * net->grad, then Adam with the step counter advanced on the device.  The
+ * same kernels as the separate calls, in the same order, so the result is
+ * bitwise that of forward -> loss -> backward -> adam.  Nothing waits on the
+ * host and the step count lives on the device, so a step can be captured in
+ * a HIP graph once and replayed on new minibatches copied into the same
+ * buffers (an earlier call with at least the same M must have sized the
+ * workspace: 8 M bytes for scores and their gradient, plus the backward's
+ * partials).
+ */
+int schulze_mlp_train_step(schulze_ctx *ctx, void *stream, const schulze_mlp *net,
+                           const schulze_train_batch *b, float *loss);
+
 /* Statistics of one schulze_winners_learned call. */
 typedef struct {
     int32_t proposal;      /* first candidate the network proposed */
@@ -250,13 +293,17 @@ typedef struct {
 /*
  * Exact Schulze winners via a learned proposal.  The network (params, see
  * schulze_mlp_param_count) scores the features of d; the best candidate the
- * initialisation filter of Section 4 keeps is checked with schulze_verify.
+ * initialisation filter of Section 4 keeps is checked with schulze_verify
+ * (schulze_set_proposer replaces the network by a plain score).
  * If it is beaten, the check moves to the highest-scored beater (at most
  * max_climb times); once a winner is found the candidates tied with it are
  * checked too (every winner is tied with every other winner).  If no winner
  * is found or more than max_tied candidates are tied, schulze_closure and
  * schulze_winners decide.  The result equals schulze_winners on the closure
  * for any network.  Synchronises the stream (the search runs on the host).
+ * Returns SCHULZE_EDEVICE, with no winner set written, when the device error
+ * word is set after a check (a widest-path launch gave up on its bounded
+ * wait, or an earlier call left an error unread).
  *
  * n_voters   feature scale (number of voters).
  * is_winner  m device bytes.   n_winners: NULL or one device int32.
@@ -268,6 +315,26 @@ int schulze_winners_learned(schulze_ctx *ctx, void *stream, const void *d, int64
                             int dtype, int mode, float n_voters, const float *params,
                             int32_t max_climb, int32_t max_tied, uint8_t *is_winner,
                             int32_t *n_winners, schulze_learned_stats *stats);
+
+/*
+ * Proposer of schulze_winners_learned (the verification that follows is the
+ * same for every proposer, so the winner set is too):
+ *   NETWORK       the trained network's scores, best candidate the Section 4
+ *                 initialisation filter keeps (default);
+ *   BORDA         the Borda score, the vertex order Section 4 suggests;
+ *   COPELAND      the Copeland score (pairwise wins);
+ *   FILTER_BORDA  the filter of Section 4, then Borda.
+ * The proposer's scores also pick the beater a failed check moves to (ties:
+ * lowest id).  With a proposer other than NETWORK, params may be NULL.
+ * Returns SCHULZE_EINVAL for other values.
+ */
+enum {
+    SCHULZE_PROPOSER_NETWORK = 0,
+    SCHULZE_PROPOSER_BORDA = 1,
+    SCHULZE_PROPOSER_COPELAND = 2,
+    SCHULZE_PROPOSER_FILTER_BORDA = 3
+};
+int schulze_set_proposer(schulze_ctx *ctx, int proposer);
 
 /* Statistics of one schulze_winners_propagate call. */
 typedef struct {
@@ -365,13 +432,23 @@ int schulze_set_sparse_count(schulze_ctx *ctx, int mode);
  * that keeps 0, so when the weights of an int32 closure with m >= 1024 take
  * at most 65535 distinct nonzero values, all below 2^24, the closure runs on
  * the ranks of the values in packed uint16 and maps the result back: same
- * output, about a third less arithmetic per update.  Deciding costs one
- * synchronisation of the stream (a 2 MB bitmap of the values and a count).
- * With ranking off, or when the values do not fit, the int32 closure runs.
+ * output, about a third less arithmetic per update.  The decision is taken
+ * on the device (a 2 MB bitmap of the values and a count): both variants are
+ * queued and the one not needed returns at once, so the call stays
+ * asynchronous and can be captured in a HIP graph.  With ranking off, or
+ * when the values do not fit, the int32 closure runs.
  * Workspace when ranking: 2 m_p^2 + 4.2 MB bytes on top of the closure's
- * (m_p = m rounded up to the tile size).
+ * (m_p = m rounded up to the tile size), reserved before any work is queued.
  */
 int schulze_set_value_ranking(schulze_ctx *ctx, int enable);
+
+/*
+ * Value width the last schulze_closure call on this context ran the
+ * recurrence in: 16 (uint16 counts, or int32 weights replaced by their
+ * ranks), 32 (int32), or 0 if no closure has run.  Synchronises `stream`
+ * when the decision was taken on the device.
+ */
+int schulze_closure_value_bits(schulze_ctx *ctx, void *stream, int32_t *value_bits);
 
 /*
  * Batches of independent elections (Section 2.1 applied to each election of

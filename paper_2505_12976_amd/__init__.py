@@ -31,10 +31,11 @@ EXPORTS = (
     "schulze_set_value_ranking", "schulze_set_closure_tile", "schulze_set_sparse_count",
     "schulze_weights", "schulze_widest_from", "schulze_verify", "schulze_features",
     "schulze_mlp_param_count", "schulze_mlp_forward", "schulze_mlp_loss", "schulze_mlp_backward", "schulze_mlp_adam",
+    "schulze_mlp_train_step",
     "schulze_winners_learned",
     "schulze_batch_plan", "schulze_batch_destroy", "schulze_batch_run", "schulze_batch_set_closure",
     "schulze_batch_get_closure", "schulze_batch_autotune", "schulze_winners_propagate",
-    "schulze_topk_propagate", "schulze_valu_probe",
+    "schulze_topk_propagate", "schulze_valu_probe", "schulze_closure_value_bits", "schulze_set_proposer",
 )
 
 
@@ -59,7 +60,21 @@ class LearnedStats(ctypes.Structure):
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
+class MlpState(ctypes.Structure):
+    """schulze_mlp: parameters, Adam moments, gradient, device step counter, hyperparameters."""
+    _fields_ = [("params", ctypes.c_void_p), ("adam_m", ctypes.c_void_p), ("adam_v", ctypes.c_void_p),
+                ("grad", ctypes.c_void_p), ("step", ctypes.c_void_p), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
+class TrainBatch(ctypes.Structure):
+    """schulze_train_batch: feature rows, election offsets, winner marks."""
+    _fields_ = [("feat", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("winner", ctypes.c_void_p),
+                ("M", ctypes.c_int64), ("E", ctypes.c_int32)]
+
+
 SCHEDULE_AUTO, SCHEDULE_PHASED = 0, 1
+PROPOSERS = {"network": 0, "borda": 1, "copeland": 2, "filter+borda": 3}
 
 _lib = None
 
@@ -115,6 +130,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.schulze_reset_timing.argtypes = [vp]
     lib.schulze_set_closure_schedule.argtypes = [vp, c_int]
     lib.schulze_set_value_ranking.argtypes = [vp, c_int]
+    lib.schulze_closure_value_bits.argtypes = [vp, vp, ctypes.POINTER(c_i32)]
+    lib.schulze_set_proposer.argtypes = [vp, c_int]
     lib.schulze_set_closure_tile.argtypes = [vp, c_int]
     lib.schulze_set_sparse_count.argtypes = [vp, c_int]
     lib.schulze_valu_probe.argtypes = [vp, vp, c_i32, c_i64, vp, ctypes.POINTER(c_i64)]
@@ -130,6 +147,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.schulze_mlp_backward.argtypes = [vp, vp, vp, vp, c_i64, vp, vp]
     lib.schulze_mlp_adam.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                      ctypes.c_float, c_i32]
+    lib.schulze_mlp_train_step.argtypes = [vp, vp, ctypes.POINTER(MlpState), ctypes.POINTER(TrainBatch), vp]
     lib.schulze_batch_plan.argtypes = [vp, ctypes.POINTER(Election), c_i32, c_int, c_int,
                                        ctypes.POINTER(BatchOptions), ctypes.POINTER(vp)]
     lib.schulze_winners_propagate.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_int, c_int, vp, vp,
@@ -379,6 +397,28 @@ class Context:
                                         float(beta2), float(eps), int(step))
         _check(rc, "schulze_mlp_adam")
 
+    def mlp_train_step(self, params, adam_m, adam_v, grad, step, feat, offsets, winner, lr=1e-3, beta1=0.9,
+                       beta2=0.999, eps=1e-8, loss=None):
+        """One step (forward, segmented loss, backward, Adam); step: one
+        int32 CUDA tensor that counts Adam steps (advanced on the device).
+        Returns the per-election losses (a CUDA tensor)."""
+        import torch
+        E = offsets.shape[0] - 1
+        if offsets.dtype != torch.int64 or winner.dtype != torch.uint8 or step.dtype != torch.int32:
+            raise ValueError("offsets must be int64, winner uint8, step int32")
+        if feat.dim() != 2 or feat.shape[1] != 16 or winner.shape != (feat.shape[0],):
+            raise ValueError("feat must be (M, 16) and winner (M,)")
+        loss = loss if loss is not None else torch.empty(E, dtype=torch.float32, device=self._torch_device)
+        net = MlpState(self._dev(params, "params").value, self._dev(adam_m, "adam_m").value,
+                       self._dev(adam_v, "adam_v").value, self._dev(grad, "grad").value,
+                       self._dev(step, "step").value, float(lr), float(beta1), float(beta2), float(eps))
+        b = TrainBatch(self._dev(feat, "feat").value, self._dev(offsets, "offsets").value,
+                       self._dev(winner, "winner").value, int(feat.shape[0]), int(E))
+        rc = self._lib.schulze_mlp_train_step(self._h, self._stream(), ctypes.byref(net), ctypes.byref(b),
+                                              self._dev(loss, "loss"))
+        _check(rc, "schulze_mlp_train_step")
+        return loss
+
     def winners_learned(self, d, n_voters: float, params, mode="winning_votes", max_climb=8, max_tied=64):
         """(is_winner uint8[m], n_winners int32[1], stats dict): exact winners
         found through the proposer network (synchronises)."""
@@ -389,7 +429,8 @@ class Context:
         st = LearnedStats()
         rc = self._lib.schulze_winners_learned(self._h, self._stream(), self._dev(d, "d"), d.stride(0), m,
                                                _dtype_code(d.dtype), _mode_code(mode), float(n_voters),
-                                               self._dev(params, "params"), int(max_climb), int(max_tied),
+                                               None if params is None else self._dev(params, "params"),
+                                               int(max_climb), int(max_tied),
                                                self._dev(w, "is_winner"), self._dev(nw, "n_winners"),
                                                ctypes.byref(st))
         _check(rc, "schulze_winners_learned")
@@ -506,6 +547,18 @@ class Context:
     def set_value_ranking(self, enable: bool) -> None:
         """Run int32 closures of m >= 1024 on value ranks in uint16 when the values fit (default on)."""
         _check(self._lib.schulze_set_value_ranking(self._h, int(bool(enable))), "schulze_set_value_ranking")
+
+    def set_proposer(self, proposer: str) -> None:
+        """First proposal of winners_learned: "network" (default), "borda", "copeland" or "filter+borda"."""
+        code = PROPOSERS[proposer]
+        _check(self._lib.schulze_set_proposer(self._h, code), "schulze_set_proposer")
+
+    def closure_value_bits(self) -> int:
+        """Value width (16 or 32) the last closure ran its recurrence in; 0 if none ran (synchronises)."""
+        v = ctypes.c_int32(0)
+        _check(self._lib.schulze_closure_value_bits(self._h, self._stream(), ctypes.byref(v)),
+               "schulze_closure_value_bits")
+        return v.value
 
     # -------------------------------------------------------------- timing
     def valu_probe(self, workgroups: int, trips: int) -> int:

@@ -44,6 +44,12 @@ namespace {
 
 using namespace fw;
 
+// A launch can be gated on a device word: it runs only when *gate == want
+// (gate == nullptr: always).  The int32 closure decides on the device
+// whether its values can be ranked, and both variants are queued with
+// opposite gates, so the host never waits for the decision.
+__device__ inline bool gated_off(const int32_t *gate, int32_t want) { return gate && *gate != want; }
+
 // ------------------------------------------------------------------ weights
 // P[i][j] = edge weight from d (winning votes or margin); zero padding.  A
 // workgroup takes the pair of 64 x 64 tiles (I, J) and (J, I), I <= J: both
@@ -71,7 +77,8 @@ __global__ __launch_bounds__(256) void k_weights(const E *__restrict__ d, int64_
 // p[i][j] = P[i][j] for i != j, 0 on the diagonal; one workgroup per row.
 template <typename E>
 __global__ __launch_bounds__(256) void k_fw_store(const E *__restrict__ P, int64_t ld, int32_t m, E *__restrict__ p,
-                                                  int64_t ldp) {
+                                                  int64_t ldp, const int32_t *gate, int32_t want) {
+    if (gated_off(gate, want)) return;
     const int32_t i = blockIdx.x;
     const E *src = P + (int64_t)i * ld;
     E *dst = p + (int64_t)i * ldp;
@@ -90,6 +97,8 @@ struct PersistArgs {
     int32_t *err;       // device error word
     int64_t spin_limit; // polls before a wait is declared stuck
     int32_t early_panels; // run round r+1's panels ahead of round r's last tiles when possible
+    const int32_t *gate;  // run only if *gate == gate_want (nullptr: always)
+    int32_t gate_want;
 };
 
 constexpr int MAX_OWNED = 512;
@@ -183,17 +192,19 @@ __global__ __launch_bounds__(256, (sizeof(E) == 2 || B < 128) ? 2 : 1) void k_fw
     __shared__ int32_t n_owned;
     const int32_t nb = a.nb, G = gridDim.x, w = blockIdx.x;
     const int64_t tile_elems = (int64_t)B * B;
+    if (gated_off(a.gate, a.gate_want)) return;  // uniform over the grid: every workgroup leaves
 
-    if (threadIdx.x == 0) n_owned = 0;
-    __syncthreads();
-    for (int32_t t = threadIdx.x; t < nb * nb; t += 256) {
-        if (tile_owner(t / nb, t % nb, nb, G) == w) {
-            const int32_t q = atomicAdd(&n_owned, 1);
-            if (q < MAX_OWNED) owned[q] = t;
-        }
-    }
+    // Tiles this workgroup owns, in ascending tile number: the numbers
+    // k = w, w + G, w + 2G, ... stand for block row I = k / nb and column
+    // J = (k mod nb - I) mod nb (the inverse of the owner map below).
+    if (threadIdx.x == 0) n_owned = (int32_t)((nb * nb - w + G - 1) / G);
     __syncthreads();
     const int32_t no = n_owned;
+    for (int32_t q = threadIdx.x; q < no && q < MAX_OWNED; q += 256) {
+        const int32_t k = w + q * G, I = k / nb;
+        owned[q] = I * nb + ((k % nb) - I + nb) % nb;
+    }
+    __syncthreads();
     if (no > MAX_OWNED) {  // the host sizes the grid so that this cannot happen
         if (threadIdx.x == 0) {
             set_device_error(a.err, SCHULZE_EDEVICE);
@@ -349,14 +360,18 @@ stuck:
 // ------------------------------------------------------------------ per-phase launches
 // Used when a cooperative launch is not available: three launches per round.
 template <typename E, int B>
-__global__ __launch_bounds__(256) void k_fw_diag(E *__restrict__ P, int64_t ld, int32_t r) {
+__global__ __launch_bounds__(256) void k_fw_diag(E *__restrict__ P, int64_t ld, int32_t r, const int32_t *gate,
+                                                 int32_t want) {
+    if (gated_off(gate, want)) return;
     __shared__ __attribute__((aligned(16))) E buf[diag_lds_elems<E, B, diag_steps<E, B>(), true>()];
     E *t = P + (int64_t)r * B * ld + (int64_t)r * B;
     diag_close<E, B, diag_steps<E, B>(), true>(t, ld, t, ld, nullptr, 0, buf);
 }
 
 template <typename E, int B>
-__global__ __launch_bounds__(256) void k_fw_panel(E *__restrict__ P, int64_t ld, int32_t nb, int32_t r) {
+__global__ __launch_bounds__(256) void k_fw_panel(E *__restrict__ P, int64_t ld, int32_t nb, int32_t r,
+                                                  const int32_t *gate, int32_t want) {
+    if (gated_off(gate, want)) return;
     __shared__ __attribute__((aligned(16))) E lds[Cfg<E, B>::LDS_ELEMS];
     const int32_t t = blockIdx.x;
     int32_t I, J;
@@ -377,7 +392,9 @@ __global__ __launch_bounds__(256) void k_fw_panel(E *__restrict__ P, int64_t ld,
 }
 
 template <typename E, int B>
-__global__ __launch_bounds__(256) void k_fw_rest(E *__restrict__ P, int64_t ld, int32_t nb, int32_t r) {
+__global__ __launch_bounds__(256) void k_fw_rest(E *__restrict__ P, int64_t ld, int32_t nb, int32_t r,
+                                                 const int32_t *gate, int32_t want) {
+    if (gated_off(gate, want)) return;
     __shared__ __attribute__((aligned(16))) E lds[Cfg<E, B>::LDS_ELEMS];
     const int32_t t = blockIdx.x;
     const int32_t i = t / (nb - 1), j = t % (nb - 1);
@@ -390,11 +407,37 @@ __global__ __launch_bounds__(256) void k_fw_rest(E *__restrict__ P, int64_t ld, 
     acc_store<E, B>(acc, Ct, ld);
 }
 
+// Device memory of the persistent launch: published tiles and their flags.
+template <typename E, int B>
+size_t ring_bytes(int32_t nb) {
+    return sizeof(E) * (size_t)nb * (2 * (size_t)nb + 1) * B * B;
+}
+inline size_t flag_bytes(int32_t nb) { return sizeof(int32_t) * ((size_t)nb * (2 * (size_t)nb + 1) + 64); }
+
+// Launch the persistent kernel.  Outside stream capture it is a cooperative
+// launch (all workgroups resident).  Under capture it is captured as a
+// cooperative launch when the runtime allows; otherwise as a plain launch of
+// the same occupancy-sized grid, whose workgroups are all resident whenever
+// the device is not running other work, and whose bounded waits report
+// SCHULZE_EDEVICE instead of hanging if they ever are not.
+inline hipError_t launch_persistent(const void *fn, unsigned G, void **args, hipStream_t s) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess) cap = hipStreamCaptureStatusNone;
+    hipError_t e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(256), args, 0, s);
+    if (e == hipSuccess || cap != hipStreamCaptureStatusActive) return e;
+    (void)hipGetLastError();
+    hipStreamCaptureStatus now = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &now) != hipSuccess || now != hipStreamCaptureStatusActive) return e;
+    return hipLaunchKernel(fn, dim3(G), dim3(256), args, 0, s);
+}
+
 // Close the padded matrix P (pitch ld, nb x nb tiles of B) in place: one
 // persistent dataflow launch, or three launches per round when the device
-// refuses a cooperative launch or the phased schedule is forced.
+// refuses a cooperative launch or the phased schedule is forced.  Every
+// launch is gated on (gate, want) (see gated_off).
 template <typename E, int B>
-int close_padded(schulze_ctx *ctx, hipStream_t s, E *P, int64_t ld, int32_t nb) {
+int close_padded(schulze_ctx *ctx, hipStream_t s, E *P, int64_t ld, int32_t nb, const int32_t *gate = nullptr,
+                 int32_t want = 0) {
     int rc;
     bool done = false;
     if (nb > 1 && !ctx->force_phased) {
@@ -407,10 +450,8 @@ int close_padded(schulze_ctx *ctx, hipStream_t s, E *P, int64_t ld, int32_t nb) 
         const int64_t tiles_per_wg = ceil_div((int64_t)nb * nb, G > 0 ? G : 1);
         if (G >= 1 && tiles_per_wg <= MAX_OWNED) {
             const int64_t nslots = (int64_t)nb * (2 * nb + 1);
-            const size_t ring_bytes = sizeof(E) * (size_t)nslots * B * B;
-            const size_t flag_bytes = sizeof(int32_t) * (size_t)(nslots + 64);
-            if ((rc = ws_reserve(ctx, WS_RING, ring_bytes)) != SCHULZE_OK) return rc;
-            if ((rc = ws_reserve(ctx, WS_FLAGS, flag_bytes)) != SCHULZE_OK) return rc;
+            if ((rc = ws_reserve(ctx, WS_RING, ring_bytes<E, B>(nb))) != SCHULZE_OK) return rc;
+            if ((rc = ws_reserve(ctx, WS_FLAGS, flag_bytes(nb))) != SCHULZE_OK) return rc;
             int32_t *flags = static_cast<int32_t *>(ctx->ws[WS_FLAGS]);
             if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(flags), (size_t)(nslots + 64), 0u)) != SCHULZE_OK)
                 return rc;
@@ -420,12 +461,11 @@ int close_padded(schulze_ctx *ctx, hipStream_t s, E *P, int64_t ld, int32_t nb) 
             // 111.6 ms, m = 16384 146.4 -> 148 ms (hence off there)
             const int32_t early = (int64_t)nb * nb <= (sizeof(E) == 2 ? 20 : 8) * G ? 1 : 0;
             PersistArgs<E> pa{P,     ld,    nb, static_cast<E *>(ctx->ws[WS_RING]), flags, flags + nslots, ctx->err,
-                              (int64_t)1 << 22, early};
+                              (int64_t)1 << 22, early, gate, want};
             void *args[] = {&pa};
             int tok;
             timing_begin(ctx, K_FW_PERSIST, s, &tok);
-            hipError_t e = hipLaunchCooperativeKernel((const void *)k_fw_persist<E, B>, dim3((unsigned)G), dim3(256),
-                                                      args, 0, s);
+            hipError_t e = launch_persistent((const void *)k_fw_persist<E, B>, (unsigned)G, args, s);
             timing_end(ctx, tok, s);
             if (e == hipSuccess) {
                 done = true;
@@ -436,13 +476,14 @@ int close_padded(schulze_ctx *ctx, hipStream_t s, E *P, int64_t ld, int32_t nb) 
     }
     if (!done) {
         for (int32_t r = 0; r < nb; ++r) {
-            SCHULZE_LAUNCH(ctx, K_FW_DIAG, s, k_fw_diag<E, B><<<dim3(1), dim3(256), 0, s>>>(P, ld, r));
+            SCHULZE_LAUNCH(ctx, K_FW_DIAG, s, k_fw_diag<E, B><<<dim3(1), dim3(256), 0, s>>>(P, ld, r, gate, want));
             if (nb > 1) {
                 SCHULZE_LAUNCH(ctx, K_FW_PANEL, s,
-                               k_fw_panel<E, B><<<dim3((unsigned)(2 * (nb - 1))), dim3(256), 0, s>>>(P, ld, nb, r));
+                               k_fw_panel<E, B><<<dim3((unsigned)(2 * (nb - 1))), dim3(256), 0, s>>>(P, ld, nb, r,
+                                                                                                     gate, want));
                 SCHULZE_LAUNCH(ctx, K_FW_REST, s,
-                               k_fw_rest<E, B><<<dim3((unsigned)((nb - 1) * (nb - 1))), dim3(256), 0, s>>>(P, ld, nb,
-                                                                                                           r));
+                               k_fw_rest<E, B><<<dim3((unsigned)((nb - 1) * (nb - 1))), dim3(256), 0, s>>>(
+                                   P, ld, nb, r, gate, want));
             }
         }
     }
@@ -461,7 +502,9 @@ int run_closure(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32_
     SCHULZE_LAUNCH(ctx, K_WEIGHTS, s, k_weights<E><<<wgrid, dim3(256), 0, s>>>(d, ldd, m, mode, P, ld, mp,
                                                                           tio::vec_ok<E>(d, ldd) ? 1 : 0));
     if ((rc = close_padded<E, B>(ctx, s, P, ld, nb)) != SCHULZE_OK) return rc;
-    SCHULZE_LAUNCH(ctx, K_FW_STORE, s, k_fw_store<E><<<dim3((unsigned)m), dim3(256), 0, s>>>(P, ld, m, p, ldp));
+    SCHULZE_LAUNCH(ctx, K_FW_STORE, s,
+                   k_fw_store<E><<<dim3((unsigned)m), dim3(256), 0, s>>>(P, ld, m, p, ldp, nullptr, 0));
+    ctx->closure_bits = sizeof(E) * 8;
     return SCHULZE_OK;
 }
 
@@ -542,7 +585,9 @@ __global__ __launch_bounds__(256) void k_rank_blocks(const uint32_t *__restrict_
     if (threadIdx.x == 0) block_sum[blockIdx.x] = part[0];
 }
 
-// Exclusive scan of the block sums (one workgroup); flags[1] = number of distinct nonzero values.
+// Exclusive scan of the block sums (one workgroup); flags[1] = number of
+// distinct nonzero values; flags[2] = 1 if the closure runs on ranks (no
+// value at or above RANK_CAP, at most 65535 distinct values), else 0.
 __global__ __launch_bounds__(256) void k_rank_top(uint32_t *__restrict__ block_sum, int32_t *__restrict__ flags) {
     __shared__ uint32_t part[256];
     constexpr int PER = RANK_BLOCKS / 256;
@@ -565,14 +610,19 @@ __global__ __launch_bounds__(256) void k_rank_top(uint32_t *__restrict__ block_s
         block_sum[threadIdx.x * PER + i] = run;
         run += v[i];
     }
-    if (threadIdx.x == 255) flags[1] = (int32_t)part[255];
+    if (threadIdx.x == 255) {
+        flags[1] = (int32_t)part[255];
+        flags[2] = (flags[0] == 0 && part[255] <= 65535u) ? 1 : 0;
+    }
 }
 
 // word_rank[w] = number of marked values below word w; value_of[r] = the
 // value of rank r (1-based) while r <= 65535.
 __global__ __launch_bounds__(256) void k_rank_words(const uint32_t *__restrict__ bitmap,
                                                     const uint32_t *__restrict__ block_off,
-                                                    uint32_t *__restrict__ word_rank, int32_t *__restrict__ value_of) {
+                                                    uint32_t *__restrict__ word_rank, int32_t *__restrict__ value_of,
+                                                    const int32_t *gate) {
+    if (gated_off(gate, 1)) return;
     __shared__ uint32_t part[256];
     constexpr int PER = RANK_BLOCK / 256;
     const int64_t w0 = (int64_t)blockIdx.x * RANK_BLOCK + threadIdx.x * PER;
@@ -607,7 +657,8 @@ __global__ __launch_bounds__(256) void k_rank_words(const uint32_t *__restrict__
 __global__ __launch_bounds__(256) void k_rank_apply(const int32_t *__restrict__ P, int64_t count,
                                                     const uint32_t *__restrict__ bitmap,
                                                     const uint32_t *__restrict__ word_rank,
-                                                    uint16_t *__restrict__ P16) {
+                                                    uint16_t *__restrict__ P16, const int32_t *gate) {
+    if (gated_off(gate, 1)) return;
     auto rank_of = [&](int32_t v) -> uint16_t {
         if (v == 0) return 0;
         const uint32_t below = bitmap[v >> 5] & ((1u << (v & 31)) - 1u);
@@ -626,7 +677,8 @@ __global__ __launch_bounds__(256) void k_rank_apply(const int32_t *__restrict__ 
 // workgroup per row, four columns per thread and step (ld is a multiple of 64).
 __global__ __launch_bounds__(256) void k_rank_store(const uint16_t *__restrict__ P16, int64_t ld, int32_t m,
                                                     const int32_t *__restrict__ value_of, int32_t *__restrict__ p,
-                                                    int64_t ldp) {
+                                                    int64_t ldp, const int32_t *gate) {
+    if (gated_off(gate, 1)) return;
     const int32_t i = blockIdx.x;
     int32_t *row = p + (int64_t)i * ldp;
     for (int32_t j0 = threadIdx.x * 4; j0 < m; j0 += 1024) {
@@ -646,19 +698,25 @@ int run_closure_ranked(schulze_ctx *ctx, hipStream_t s, const int32_t *d, int64_
     const int32_t mp = (int32_t)round_up(m, B);
     const int64_t ld = mp;
     const int64_t count = (int64_t)mp * mp;
-    int rc = ws_reserve(ctx, WS_CLOSURE, sizeof(int32_t) * (size_t)count);
-    if (rc != SCHULZE_OK) return rc;
-    int32_t *P = static_cast<int32_t *>(ctx->ws[WS_CLOSURE]);
-    dim3 wgrid((unsigned)ceil_div(mp, 64), (unsigned)ceil_div(mp, 64));
-    SCHULZE_LAUNCH(ctx, K_WEIGHTS, s, k_weights<int32_t><<<wgrid, dim3(256), 0, s>>>(d, ldd, m, mode, P, ld, mp,
-                                                                                tio::vec_ok<int32_t>(d, ldd) ? 1 : 0));
-
     // rank tables: bitmap | word ranks | block offsets | value table | flags, then the uint16 matrix
     const size_t bm = sizeof(uint32_t) * RANK_WORDS;
     const size_t bo = sizeof(uint32_t) * RANK_BLOCKS;
     const size_t vt = sizeof(int32_t) * 65536;
     const size_t head = 2 * bm + bo + vt + 256;
+    // all workspace up front, for both variants: nothing grows (and so
+    // nothing synchronises) once work is queued
+    int rc = ws_reserve(ctx, WS_CLOSURE, sizeof(int32_t) * (size_t)count);
+    if (rc != SCHULZE_OK) return rc;
     if ((rc = ws_reserve(ctx, WS_RANKED, head + sizeof(uint16_t) * (size_t)count)) != SCHULZE_OK) return rc;
+    if ((rc = ws_reserve(ctx, WS_RING, std::max(ring_bytes<int32_t, BI>(mp / BI), ring_bytes<uint16_t, BU>(mp / BU)))) !=
+        SCHULZE_OK)
+        return rc;
+    if ((rc = ws_reserve(ctx, WS_FLAGS, std::max(flag_bytes(mp / BI), flag_bytes(mp / BU)))) != SCHULZE_OK) return rc;
+    int32_t *P = static_cast<int32_t *>(ctx->ws[WS_CLOSURE]);
+    dim3 wgrid((unsigned)ceil_div(mp, 64), (unsigned)ceil_div(mp, 64));
+    SCHULZE_LAUNCH(ctx, K_WEIGHTS, s, k_weights<int32_t><<<wgrid, dim3(256), 0, s>>>(d, ldd, m, mode, P, ld, mp,
+                                                                                tio::vec_ok<int32_t>(d, ldd) ? 1 : 0));
+
     char *q = static_cast<char *>(ctx->ws[WS_RANKED]);
     uint32_t *bitmap = reinterpret_cast<uint32_t *>(q);
     uint32_t *word_rank = reinterpret_cast<uint32_t *>(q + bm);
@@ -668,29 +726,30 @@ int run_closure_ranked(schulze_ctx *ctx, hipStream_t s, const int32_t *d, int64_
     uint16_t *P16 = reinterpret_cast<uint16_t *>(q + head);
     if ((rc = fill_u32(ctx, s, bitmap, RANK_WORDS, 0u)) != SCHULZE_OK) return rc;
     if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(value_of), 1, 0u)) != SCHULZE_OK) return rc;
-    if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(flags), 2, 0u)) != SCHULZE_OK) return rc;
+    if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(flags), 3, 0u)) != SCHULZE_OK) return rc;
     const unsigned egrid = (unsigned)std::min<int64_t>(ceil_div(count, 256), (int64_t)ctx->num_cus * 16);
     // two marking workgroups per CU: each merges its LDS bitmap once
     const unsigned mgrid = (unsigned)std::min<int64_t>(ceil_div(count, 1024), (int64_t)ctx->num_cus * 2);
     SCHULZE_LAUNCH(ctx, K_RANK, s, k_rank_mark<<<dim3(mgrid), dim3(256), 0, s>>>(P, count, bitmap, flags));
     SCHULZE_LAUNCH(ctx, K_RANK, s, k_rank_blocks<<<dim3(RANK_BLOCKS), dim3(256), 0, s>>>(bitmap, block_off));
     SCHULZE_LAUNCH(ctx, K_RANK, s, k_rank_top<<<dim3(1), dim3(256), 0, s>>>(block_off, flags));
-    int32_t host_flags[2] = {0, 0};
-    if (hipMemcpyAsync(host_flags, flags, sizeof(host_flags), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return SCHULZE_EDEVICE;
-    if (host_flags[0] != 0 || host_flags[1] > 65535) {  // too wide or too many values: int32 closure
-        if ((rc = close_padded<int32_t, BI>(ctx, s, P, ld, mp / BI)) != SCHULZE_OK) return rc;
-        SCHULZE_LAUNCH(ctx, K_FW_STORE, s,
-                       k_fw_store<int32_t><<<dim3((unsigned)m), dim3(256), 0, s>>>(P, ld, m, p, ldp));
-        return SCHULZE_OK;
-    }
+    // flags[2] decides on the device; both variants are queued, each gated
+    const int32_t *ranked = flags + 2;
+    // values too wide or too many: the int32 closure on the weights
+    if ((rc = close_padded<int32_t, BI>(ctx, s, P, ld, mp / BI, ranked, 0)) != SCHULZE_OK) return rc;
+    SCHULZE_LAUNCH(ctx, K_FW_STORE, s,
+                   k_fw_store<int32_t><<<dim3((unsigned)m), dim3(256), 0, s>>>(P, ld, m, p, ldp, ranked, 0));
+    // otherwise the uint16 closure on the ranks
     SCHULZE_LAUNCH(ctx, K_RANK, s,
-                   k_rank_words<<<dim3(RANK_BLOCKS), dim3(256), 0, s>>>(bitmap, block_off, word_rank, value_of));
-    SCHULZE_LAUNCH(ctx, K_RANK, s, k_rank_apply<<<dim3(egrid), dim3(256), 0, s>>>(P, count, bitmap, word_rank, P16));
-    if ((rc = close_padded<uint16_t, BU>(ctx, s, P16, ld, mp / BU)) != SCHULZE_OK) return rc;
+                   k_rank_words<<<dim3(RANK_BLOCKS), dim3(256), 0, s>>>(bitmap, block_off, word_rank, value_of,
+                                                                        ranked));
     SCHULZE_LAUNCH(ctx, K_RANK, s,
-                   k_rank_store<<<dim3((unsigned)m), dim3(256), 0, s>>>(P16, ld, m, value_of, p, ldp));
+                   k_rank_apply<<<dim3(egrid), dim3(256), 0, s>>>(P, count, bitmap, word_rank, P16, ranked));
+    if ((rc = close_padded<uint16_t, BU>(ctx, s, P16, ld, mp / BU, ranked, 1)) != SCHULZE_OK) return rc;
+    SCHULZE_LAUNCH(ctx, K_RANK, s,
+                   k_rank_store<<<dim3((unsigned)m), dim3(256), 0, s>>>(P16, ld, m, value_of, p, ldp, ranked));
+    ctx->closure_bits = 0;
+    ctx->closure_ranked_flag = ranked;
     return SCHULZE_OK;
 }
 

@@ -214,6 +214,22 @@ extern "C" int schulze_set_value_ranking(schulze_ctx *ctx, int enable) {
     return SCHULZE_OK;
 }
 
+extern "C" int schulze_closure_value_bits(schulze_ctx *ctx, void *stream, int32_t *value_bits) {
+    if (!ctx || !value_bits) return SCHULZE_EINVAL;
+    if (ctx->closure_bits != 0 || !ctx->closure_ranked_flag) {
+        *value_bits = ctx->closure_bits;
+        return SCHULZE_OK;
+    }
+    if (bind_device(ctx) != SCHULZE_OK) return SCHULZE_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    int32_t ranked = 0;
+    if (hipMemcpyAsync(&ranked, ctx->closure_ranked_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return SCHULZE_EDEVICE;
+    *value_bits = ranked ? 16 : 32;
+    return SCHULZE_OK;
+}
+
 extern "C" int schulze_set_timing(schulze_ctx *ctx, int enable) {
     if (!ctx) return SCHULZE_EINVAL;
     ctx->timing = enable != 0;

@@ -1,7 +1,7 @@
 // Per-candidate features of the weighted tournament graph, the input of the
 // learned winner proposer.  All are read off the pairwise counts d in one
-// pass (each workgroup owns 64 candidates and walks their rows, taking the
-// transposed blocks through LDS):
+// pass that reads every block of d once (a workgroup takes a pair of
+// blocks and its transpose, see k_feature_rows):
 //   0  Copeland score: #{y : d[x][y] > d[y][x]} / (m-1)
 //   1  ties: #{y != x : d[x][y] = d[y][x]} / (m-1)
 //   2  Borda score: sum_y d[x][y] / ((m-1) n)   (the order Section 4 uses for vertex ids)
@@ -31,83 +31,165 @@ struct RawStats {
     long long *min_marg, *max_marg;
 };
 
-// Partial statistics of 64 candidates (rows X0 ..) over the column blocks
-// Y0 = 64 (blockIdx.y + k gridDim.y); slice s = blockIdx.y writes entry
-// s * m + x of every array of st.
-// With w / wt given, the same pass also writes the edge weights of the
-// tiles it holds: w[X0 + r][Y0 + c] and wt[Y0 + r][X0 + c] (each tile of w
-// and of its transpose exactly once over the grid).
+// Statistics of one candidate over a set of columns.
+struct Stat {
+    int32_t cope, ties, mx_out, mx_in;
+    unsigned long long borda, s_out, s_in;
+    long long mn, mxm;
+};
+
+__device__ inline void stat_init(Stat &s) {
+    s.cope = s.ties = s.mx_out = s.mx_in = 0;
+    s.borda = s.s_out = s.s_in = 0ull;
+    s.mn = LLONG_MAX;
+    s.mxm = LLONG_MIN;
+}
+
+// One column y of candidate x's row: dxy = d[x][y], dyx = d[y][x].
+__device__ inline void stat_add(Stat &s, int64_t dxy, int64_t dyx, int mode) {
+    s.cope += dxy > dyx;
+    s.ties += dxy == dyx;
+    s.borda += (unsigned long long)dxy;
+    const long long marg = dxy - dyx;
+    s.mn = min(s.mn, marg);
+    s.mxm = max(s.mxm, marg);
+    const int32_t wout = dxy > dyx ? (int32_t)(mode == SCHULZE_MARGIN ? dxy - dyx : dxy) : 0;
+    const int32_t win = dyx > dxy ? (int32_t)(mode == SCHULZE_MARGIN ? dyx - dxy : dyx) : 0;
+    s.mx_out = max(s.mx_out, wout);
+    s.mx_in = max(s.mx_in, win);
+    s.s_out += (unsigned long long)wout;
+    s.s_in += (unsigned long long)win;
+}
+
+__device__ inline void stat_merge(Stat &s, const Stat &o) {
+    s.cope += o.cope;
+    s.ties += o.ties;
+    s.borda += o.borda;
+    s.s_out += o.s_out;
+    s.s_in += o.s_in;
+    s.mx_out = max(s.mx_out, o.mx_out);
+    s.mx_in = max(s.mx_in, o.mx_in);
+    s.mn = min(s.mn, o.mn);
+    s.mxm = max(s.mxm, o.mxm);
+}
+
+// Combine the statistics of the 4 adjacent lanes that share a row.
+__device__ inline void stat_quad_reduce(Stat &s) {
+    for (int off = 1; off < 4; off <<= 1) {
+        s.cope += __shfl_xor(s.cope, off);
+        s.ties += __shfl_xor(s.ties, off);
+        s.borda += __shfl_xor(s.borda, off);
+        s.s_out += __shfl_xor(s.s_out, off);
+        s.s_in += __shfl_xor(s.s_in, off);
+        s.mx_out = max(s.mx_out, __shfl_xor(s.mx_out, off));
+        s.mx_in = max(s.mx_in, __shfl_xor(s.mx_in, off));
+        s.mn = min(s.mn, (long long)__shfl_xor(s.mn, off));
+        s.mxm = max(s.mxm, (long long)__shfl_xor(s.mxm, off));
+    }
+}
+
+__device__ inline void stat_store(const RawStats &st, int64_t q, const Stat &s) {
+    st.cope[q] = s.cope;
+    st.ties[q] = s.ties;
+    st.borda[q] = s.borda;
+    st.sum_out[q] = s.s_out;
+    st.sum_in[q] = s.s_in;
+    st.max_out[q] = s.mx_out;
+    st.max_in[q] = s.mx_in;
+    st.min_marg[q] = s.mn;
+    st.max_marg[q] = s.mxm;
+}
+
+constexpr int SB_MAX = 8;  // 64-tiles per side of a super-block
+
+// Partial statistics over pairs of super-blocks, reading every block of d
+// once.  The matrix is cut into super-blocks of sb x sb tiles of 64; the
+// workgroup of super-block pair (I, J), I <= J, walks the tile pairs
+// (X, Y) in I x J (in I x I only those with X <= Y) and loads d[X][Y] and
+// d[Y][X] together: rows of X gain the columns of Y (kept in registers over
+// the tiles of J) and, X != Y, rows of Y gain the columns of X (kept in LDS
+// per tile of J, over the tiles of I).  Slot s of each partial array holds a
+// candidate's statistics over the columns of super-block s: rows of I over
+// J and rows of J over I, each (row, slot) written by exactly one
+// workgroup.  With w / wt given, the same pass writes the edge weights of
+// both tiles of each pair to w and to its transpose wt.
 template <typename E>
 __global__ __launch_bounds__(256) void k_feature_rows(const E *__restrict__ d, int64_t ldd, int32_t m, int mode,
-                                                      RawStats st, int vec, E *__restrict__ w, int64_t ldw,
-                                                      E *__restrict__ wt, int64_t ldwt) {
+                                                      RawStats part, int vec, E *__restrict__ w, int64_t ldw,
+                                                      E *__restrict__ wt, int64_t ldwt, int32_t sb) {
     __shared__ E a[64][65];  // a[r][c] = d[X0 + r][Y0 + c]
     __shared__ E b[64][65];  // b[r][c] = d[Y0 + r][X0 + c]
-    const int32_t X0 = blockIdx.x * 64;
-    const int r = threadIdx.x >> 2, part = threadIdx.x & 3;  // 4 threads per row, 16 columns each
-    const int32_t x = X0 + r;
-    int32_t cope = 0, ties = 0, mx_out = 0, mx_in = 0;
-    unsigned long long borda = 0, s_out = 0, s_in = 0;
-    long long mn = LLONG_MAX, mxm = LLONG_MIN;
-    for (int32_t Y0 = 64 * blockIdx.y; Y0 < m; Y0 += 64 * gridDim.y) {
-        __syncthreads();
-        tio::load<E>(a, d, ldd, X0, Y0, m, m, (vec & 1) != 0);
-        tio::load<E>(b, d, ldd, Y0, X0, m, m, (vec & 1) != 0);
-        __syncthreads();
-        if (w || wt) {
-            auto weight = [&](E xy, E yx, bool diag) -> E {  // edge weight given d[i][j] = xy, d[j][i] = yx
-                if (diag || xy <= yx) return (E)0;
-                return mode == SCHULZE_MARGIN ? (E)(xy - yx) : xy;
-            };
-            if (w)
+    __shared__ Stat mir[SB_MAX][64];
+    const int32_t I = blockIdx.y, J = blockIdx.x;
+    if (J < I) return;
+    const int32_t nb = (m + 63) / 64;
+    const int r = threadIdx.x >> 2, part_c = threadIdx.x & 3;  // 4 threads per row, 16 columns each
+    if (part_c == 0)
+        for (int j = 0; j < SB_MAX; ++j) stat_init(mir[j][r]);
+    auto weight = [&](E xy, E yx, bool diag) -> E {  // edge weight given d[i][j] = xy, d[j][i] = yx
+        if (diag || xy <= yx) return (E)0;
+        return mode == SCHULZE_MARGIN ? (E)(xy - yx) : xy;
+    };
+    for (int32_t i = 0; i < sb; ++i) {
+        const int32_t X = I * sb + i;
+        if (X >= nb) break;
+        const int32_t X0 = X * 64, x = X0 + r;
+        Stat rs;
+        stat_init(rs);
+        for (int32_t j = I == J ? i : 0; j < sb; ++j) {
+            const int32_t Y = J * sb + j;
+            if (Y >= nb) break;
+            const int32_t Y0 = Y * 64;
+            __syncthreads();
+            tio::load<E>(a, d, ldd, X0, Y0, m, m, (vec & 1) != 0);
+            if (X != Y) tio::load<E>(b, d, ldd, Y0, X0, m, m, (vec & 1) != 0);
+            __syncthreads();
+            const E(*bb)[65] = X != Y ? b : a;  // d[Y0 + r][X0 + c]
+            if (w) {
                 tio::store<E>(w, ldw, X0, Y0, m, m, (vec & 2) != 0,
-                              [&](int rr, int cc) { return weight(a[rr][cc], b[cc][rr], X0 + rr == Y0 + cc); });
-            if (wt)
+                              [&](int rr, int cc) { return weight(a[rr][cc], bb[cc][rr], X0 + rr == Y0 + cc); });
+                if (X != Y)
+                    tio::store<E>(w, ldw, Y0, X0, m, m, (vec & 2) != 0,
+                                  [&](int rr, int cc) { return weight(bb[rr][cc], a[cc][rr], false); });
+            }
+            if (wt) {
                 tio::store<E>(wt, ldwt, Y0, X0, m, m, (vec & 4) != 0,
-                              [&](int rr, int cc) { return weight(a[cc][rr], b[rr][cc], X0 + cc == Y0 + rr); });
+                              [&](int rr, int cc) { return weight(a[cc][rr], bb[rr][cc], X0 + cc == Y0 + rr); });
+                if (X != Y)
+                    tio::store<E>(wt, ldwt, X0, Y0, m, m, (vec & 4) != 0,
+                                  [&](int rr, int cc) { return weight(bb[cc][rr], a[rr][cc], false); });
+            }
+            // rows of X over the columns of Y
+            if (x < m)
+                for (int c = part_c * 16; c < part_c * 16 + 16; ++c) {
+                    const int32_t y = Y0 + c;
+                    if (y < m && y != x) stat_add(rs, a[r][c], bb[c][r], mode);
+                }
+            if (X != Y) {  // rows of Y over the columns of X
+                Stat ms;
+                stat_init(ms);
+                const int32_t yr = Y0 + r;
+                if (yr < m)
+                    for (int c = part_c * 16; c < part_c * 16 + 16; ++c)
+                        if (X0 + c < m) stat_add(ms, bb[r][c], a[c][r], mode);
+                stat_quad_reduce(ms);
+                if (part_c == 0) stat_merge(mir[j][r], ms);  // only this thread touches mir[j][r]
+            }
         }
-        if (x >= m) continue;
-        for (int c = part * 16; c < part * 16 + 16; ++c) {
-            const int32_t y = Y0 + c;
-            if (y >= m || y == x) continue;
-            const int64_t dxy = a[r][c], dyx = b[c][r];
-            cope += dxy > dyx;
-            ties += dxy == dyx;
-            borda += (unsigned long long)dxy;
-            const long long marg = dxy - dyx;
-            mn = min(mn, marg);
-            mxm = max(mxm, marg);
-            const int32_t wout = dxy > dyx ? (int32_t)(mode == SCHULZE_MARGIN ? dxy - dyx : dxy) : 0;
-            const int32_t win = dyx > dxy ? (int32_t)(mode == SCHULZE_MARGIN ? dyx - dxy : dyx) : 0;
-            mx_out = max(mx_out, wout);
-            mx_in = max(mx_in, win);
-            s_out += (unsigned long long)wout;
-            s_in += (unsigned long long)win;
+        stat_quad_reduce(rs);
+        if (part_c == 0 && x < m) {
+            // on the diagonal super-block, tile X's rows also hold the columns of
+            // the tiles before it (gathered as mirrored rows)
+            if (I == J) stat_merge(rs, mir[i][r]);
+            stat_store(part, (int64_t)J * m + x, rs);
         }
     }
-    // combine the 4 threads of a row (adjacent lanes)
-    for (int off = 1; off < 4; off <<= 1) {
-        cope += __shfl_xor(cope, off);
-        ties += __shfl_xor(ties, off);
-        borda += __shfl_xor(borda, off);
-        s_out += __shfl_xor(s_out, off);
-        s_in += __shfl_xor(s_in, off);
-        mx_out = max(mx_out, __shfl_xor(mx_out, off));
-        mx_in = max(mx_in, __shfl_xor(mx_in, off));
-        mn = min(mn, (long long)__shfl_xor(mn, off));
-        mxm = max(mxm, (long long)__shfl_xor(mxm, off));
-    }
-    if (part == 0 && x < m) {
-        const int64_t q = (int64_t)blockIdx.y * m + x;
-        st.cope[q] = cope;
-        st.ties[q] = ties;
-        st.borda[q] = borda;
-        st.sum_out[q] = s_out;
-        st.sum_in[q] = s_in;
-        st.max_out[q] = mx_out;
-        st.max_in[q] = mx_in;
-        st.min_marg[q] = mn;
-        st.max_marg[q] = mxm;
+    if (I == J) return;
+    for (int32_t j = 0; j < sb; ++j) {
+        const int32_t Y = J * sb + j;
+        if (Y >= nb) break;
+        const int32_t y = Y * 64 + r;
+        if (part_c == 0 && y < m) stat_store(part, (int64_t)I * m + y, mir[j][r]);
     }
 }
 
@@ -215,9 +297,12 @@ RawStats carve(char *p, size_t n, size_t *bytes) {
 template <typename E>
 int run_features(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32_t m, int mode, float n_voters,
                  float *feat, E *w = nullptr, int64_t ldw = 0, E *wt = nullptr, int64_t ldwt = 0) {
-    // column slices per block of 64 rows: enough workgroups to keep HBM busy
+    // super-blocks of sb x sb tiles: at most 64 of them per side (a partial
+    // slot per super-block column), sb <= SB_MAX; S = super-blocks per side
     const int32_t nbx = (int32_t)ceil_div(m, 64);
-    const int32_t S = std::max(1, std::min<int32_t>(nbx, (int32_t)ceil_div(16 * (int64_t)ctx->num_cus, nbx)));
+    int32_t sb = 1;
+    while (sb < SB_MAX && ceil_div(nbx, sb) > 64) sb *= 2;
+    const int32_t S = (int32_t)ceil_div(nbx, sb);
     size_t fin_bytes = 0, part_bytes = 0;
     (void)carve(nullptr, (size_t)m, &fin_bytes);
     (void)carve(nullptr, (size_t)m * S, &part_bytes);
@@ -231,8 +316,8 @@ int run_features(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32
     const int vec = (tio::vec_ok<E>(d, ldd) ? 1 : 0) | (tio::vec_ok<E>(w, ldw) ? 2 : 0) |
                     (tio::vec_ok<E>(wt, ldwt) ? 4 : 0);
     SCHULZE_LAUNCH(ctx, K_FEATURE_ROWS, s,
-                   k_feature_rows<E><<<dim3((unsigned)nbx, (unsigned)S), dim3(256), 0, s>>>(
-                       d, ldd, m, mode, part, vec, w, ldw, wt, ldwt));
+                   k_feature_rows<E><<<dim3((unsigned)S, (unsigned)S), dim3(256), 0, s>>>(
+                       d, ldd, m, mode, part, vec, w, ldw, wt, ldwt, sb));
     SCHULZE_LAUNCH(ctx, K_FEATURES, s,
                    k_feature_reduce<<<dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s>>>(m, S, part, st));
     const dim3 vg((unsigned)ceil_div(m, 256));

@@ -31,6 +31,7 @@ enum WsSlot {
     WS_PROPAGATE,        // label propagation: weights, keys, frontiers, statuses
     WS_RANKED,           // ranked closure: value bitmap, rank tables, uint16 matrix
     WS_OCC,              // bucketed pair counting: histograms, offsets, occurrences
+    WS_MLP_TRAIN,        // train step: scores and their gradient
     WS_NUM_SLOTS
 };
 
@@ -57,6 +58,12 @@ struct schulze_ctx {
     bool value_ranking = true;
     // closure tile size: 0 = by value width and m, else 64 or 128
     int closure_tile = 0;
+    // value width of the last closure: 16 or 32, or 0 when the device decided
+    // (then *closure_ranked_flag is 1 for ranks in uint16, 0 for int32)
+    int closure_bits = 0;
+    const int32_t *closure_ranked_flag = nullptr;
+    // first proposal of the learned path (SCHULZE_PROPOSER_*)
+    int proposer = SCHULZE_PROPOSER_NETWORK;
     // truncated ballots: pair scattering with device-wide atomics instead of bucketing
     bool legacy_pairs = false;
     // batch closure schedule per value width (16, 32) and bucket of 32 candidates; -1 = built-in

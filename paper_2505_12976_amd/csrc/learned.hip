@@ -36,13 +36,28 @@ __global__ __launch_bounds__(256) void k_propose(const float *__restrict__ score
     if (threadIdx.x == 0) out[0] = best ? (int32_t)(0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull)) : -1;
 }
 
+// score[x] = feat[x][col]: the proposers that rank by one feature column.
+__global__ __launch_bounds__(256) void k_score_column(const float *__restrict__ feat, int32_t m, int32_t col,
+                                                      float *__restrict__ score) {
+    const int32_t x = blockIdx.x * 256 + threadIdx.x;
+    if (x < m) score[x] = feat[(int64_t)x * 16 + col];
+}
+
 }  // namespace
+
+extern "C" int schulze_set_proposer(schulze_ctx *ctx, int proposer) {
+    if (!ctx || proposer < SCHULZE_PROPOSER_NETWORK || proposer > SCHULZE_PROPOSER_FILTER_BORDA) return SCHULZE_EINVAL;
+    ctx->proposer = proposer;
+    return SCHULZE_OK;
+}
 
 extern "C" int schulze_winners_learned(schulze_ctx *ctx, void *stream, const void *d, int64_t ldd, int32_t m,
                                        int dtype, int mode, float n_voters, const float *params, int32_t max_climb,
                                        int32_t max_tied, uint8_t *is_winner, int32_t *n_winners,
                                        schulze_learned_stats *stats) {
-    if (!ctx || !d || !params || !is_winner) return SCHULZE_EINVAL;
+    if (!ctx || !d || !is_winner) return SCHULZE_EINVAL;
+    const int proposer = ctx->proposer;
+    if (proposer == SCHULZE_PROPOSER_NETWORK && !params) return SCHULZE_EINVAL;
     if (m < 1 || ldd < m || max_climb < 0 || max_tied < 0) return SCHULZE_EINVAL;
     if (dtype != SCHULZE_U16 && dtype != SCHULZE_I32) return SCHULZE_EINVAL;
     if (mode != SCHULZE_WINNING_VOTES && mode != SCHULZE_MARGIN) return SCHULZE_EINVAL;
@@ -69,8 +84,19 @@ extern "C" int schulze_winners_learned(schulze_ctx *ctx, void *stream, const voi
     // weights, transposed weights and features in one pass over d
     if ((rc = weights_and_features(ctx, s, d, ldd, m, dtype, mode, n_voters, feat, w, m, wt, m)) != SCHULZE_OK)
         return rc;
-    if ((rc = schulze_mlp_forward(ctx, stream, params, feat, m, score)) != SCHULZE_OK) return rc;
-    SCHULZE_LAUNCH(ctx, K_PROPOSE, s, k_propose<<<dim3(1), dim3(256), 0, s>>>(score, feat, m, 1, small + 4));
+    // scores: the network, or one feature column (Borda: column 2, the vertex
+    // order of Section 4; Copeland: column 0); the filter of Section 4 applies
+    // to the network and to filtered Borda
+    if (proposer == SCHULZE_PROPOSER_NETWORK) {
+        if ((rc = schulze_mlp_forward(ctx, stream, params, feat, m, score)) != SCHULZE_OK) return rc;
+    } else {
+        const int32_t col = proposer == SCHULZE_PROPOSER_COPELAND ? 0 : 2;
+        SCHULZE_LAUNCH(ctx, K_PROPOSE, s,
+                       k_score_column<<<dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s>>>(feat, m, col, score));
+    }
+    const int use_filter = proposer == SCHULZE_PROPOSER_NETWORK || proposer == SCHULZE_PROPOSER_FILTER_BORDA;
+    SCHULZE_LAUNCH(ctx, K_PROPOSE, s,
+                   k_propose<<<dim3(1), dim3(256), 0, s>>>(score, feat, m, use_filter, small + 4));
     int32_t cand = -1;
     if (hipMemcpyAsync(&cand, small + 4, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
@@ -83,14 +109,21 @@ extern "C" int schulze_winners_learned(schulze_ctx *ctx, void *stream, const voi
     }
     st.proposal = cand;
 
+    // One exact check.  The verdict is only used when the device error word
+    // is clear: a widest-path launch that gave up on its bounded grid
+    // barrier leaves its rows unwritten and sets the word, so the search
+    // stops with SCHULZE_EDEVICE (the word stays set for
+    // schulze_get_device_error) instead of deciding on stale rows.
     auto verify = [&](int32_t c, int32_t (&v)[4]) -> int {
         int r = schulze_verify(ctx, stream, w, m, wt, m, m, dtype, c, score, p_from, p_to, small, tied);
         if (r != SCHULZE_OK) return r;
         ++st.verify_calls;
+        int32_t err = 0;
         if (hipMemcpyAsync(v, small, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&err, ctx->err, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return SCHULZE_EDEVICE;
-        return SCHULZE_OK;
+        return err == SCHULZE_OK ? SCHULZE_OK : SCHULZE_EDEVICE;
     };
 
     int32_t v[4];

@@ -355,12 +355,14 @@ __global__ __launch_bounds__(256) void k_mlp_reduce(const float *__restrict__ pa
     grad[k] = s;
 }
 
-// Adam (FP32 master weights), bias-corrected, step t >= 1.
+// Adam (FP32 master weights), bias-corrected, step t >= 1: t_host, or the
+// device counter *t_dev when given (the train step advances it first).
 __global__ __launch_bounds__(256) void k_adam(float *__restrict__ p, const float *__restrict__ g,
                                               float *__restrict__ m1, float *__restrict__ m2, float lr, float b1,
-                                              float b2, float eps, int32_t t) {
+                                              float b2, float eps, int32_t t_host, const int32_t *__restrict__ t_dev) {
     const int k = blockIdx.x * 256 + threadIdx.x;
     if (k >= NPARAM) return;
+    const int32_t t = t_dev ? *t_dev : t_host;
     const float gk = g[k];
     const float a = b1 * m1[k] + (1.f - b1) * gk;
     const float v = b2 * m2[k] + (1.f - b2) * gk * gk;
@@ -369,6 +371,11 @@ __global__ __launch_bounds__(256) void k_adam(float *__restrict__ p, const float
     const float ah = a / (1.f - powf(b1, (float)t));
     const float vh = v / (1.f - powf(b2, (float)t));
     p[k] -= lr * ah / (sqrtf(vh) + eps);
+}
+
+// The train step's Adam counter: one more step.
+__global__ void k_step_next(int32_t *__restrict__ step) {
+    if (threadIdx.x == 0) step[0] += 1;
 }
 
 size_t bwd_lds_bytes() { return sizeof(BwdLds); }
@@ -407,14 +414,12 @@ extern "C" int schulze_mlp_forward(schulze_ctx *ctx, void *stream, const float *
     return SCHULZE_OK;
 }
 
-extern "C" int schulze_mlp_backward(schulze_ctx *ctx, void *stream, const float *params, const float *feat, int64_t M,
-                                    const float *dscore, float *grad) {
-    if (!ctx || !params || !feat || !dscore || !grad || M < 0) return SCHULZE_EINVAL;
-    if (bind_device(ctx) != SCHULZE_OK) return SCHULZE_EDEVICE;
-    hipStream_t s = (hipStream_t)stream;
-    NetBf16 q;
-    int rc = prepare(ctx, s, params, q);
-    if (rc != SCHULZE_OK) return rc;
+namespace {
+
+// Backward of the prepared network (q) into grad; arguments checked.
+int backward(schulze_ctx *ctx, hipStream_t s, const float *params, const NetBf16 &q, const float *feat, int64_t M,
+             const float *dscore, float *grad) {
+    int rc;
     const int G = grid_for(ctx, M);
     if ((rc = ws_reserve(ctx, WS_MLP_PARTIAL, sizeof(float) * (size_t)G * NPARAM)) != SCHULZE_OK) return rc;
     float *partial = static_cast<float *>(ctx->ws[WS_MLP_PARTIAL]);
@@ -427,6 +432,19 @@ extern "C" int schulze_mlp_backward(schulze_ctx *ctx, void *stream, const float 
     SCHULZE_LAUNCH(ctx, K_MLP_BWD, s,
                    k_mlp_reduce<<<dim3((unsigned)ceil_div(NPARAM, 256)), dim3(256), 0, s>>>(partial, G, grad));
     return SCHULZE_OK;
+}
+
+}  // namespace
+
+extern "C" int schulze_mlp_backward(schulze_ctx *ctx, void *stream, const float *params, const float *feat, int64_t M,
+                                    const float *dscore, float *grad) {
+    if (!ctx || !params || !feat || !dscore || !grad || M < 0) return SCHULZE_EINVAL;
+    if (bind_device(ctx) != SCHULZE_OK) return SCHULZE_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    NetBf16 q;
+    int rc = prepare(ctx, s, params, q);
+    if (rc != SCHULZE_OK) return rc;
+    return backward(ctx, s, params, q, feat, M, dscore, grad);
 }
 
 extern "C" int schulze_mlp_loss(schulze_ctx *ctx, void *stream, const float *score, const int64_t *offsets,
@@ -447,7 +465,41 @@ extern "C" int schulze_mlp_adam(schulze_ctx *ctx, void *stream, float *params, c
     hipStream_t s = (hipStream_t)stream;
     SCHULZE_LAUNCH(ctx, K_MLP_ADAM, s,
                    k_adam<<<dim3((unsigned)ceil_div(NPARAM, 256)), dim3(256), 0, s>>>(params, grad, adam_m, adam_v, lr,
-                                                                                     beta1, beta2, eps, step));
+                                                                                     beta1, beta2, eps, step,
+                                                                                     nullptr));
+    return SCHULZE_OK;
+}
+
+extern "C" int schulze_mlp_train_step(schulze_ctx *ctx, void *stream, const schulze_mlp *net,
+                                      const schulze_train_batch *b, float *loss) {
+    if (!ctx || !net || !b || !loss) return SCHULZE_EINVAL;
+    if (!net->params || !net->adam_m || !net->adam_v || !net->grad || !net->step) return SCHULZE_EINVAL;
+    if (!b->feat || !b->offsets || !b->winner || b->M < 1 || b->E < 1) return SCHULZE_EINVAL;
+    if (!(net->lr > 0.f) || !(net->beta1 >= 0.f && net->beta1 < 1.f) || !(net->beta2 >= 0.f && net->beta2 < 1.f) ||
+        !(net->eps > 0.f))
+        return SCHULZE_EINVAL;
+    if (bind_device(ctx) != SCHULZE_OK) return SCHULZE_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    // scores and their gradient live in the workspace
+    const size_t vec = round_up(sizeof(float) * (size_t)b->M, 256);
+    int rc = ws_reserve(ctx, WS_MLP_TRAIN, 2 * vec);
+    if (rc != SCHULZE_OK) return rc;
+    float *score = static_cast<float *>(ctx->ws[WS_MLP_TRAIN]);
+    float *dscore = reinterpret_cast<float *>(static_cast<char *>(ctx->ws[WS_MLP_TRAIN]) + vec);
+    NetBf16 q;
+    if ((rc = prepare(ctx, s, net->params, q)) != SCHULZE_OK) return rc;
+    SCHULZE_LAUNCH(ctx, K_MLP_FWD, s,
+                   k_mlp_fwd<<<dim3((unsigned)grid_for(ctx, b->M)), dim3(256), 0, s>>>(net->params, q, b->feat, b->M,
+                                                                                       score));
+    SCHULZE_LAUNCH(ctx, K_MLP_LOSS, s,
+                   k_seg_loss<<<dim3((unsigned)ceil_div(b->E, 4)), dim3(256), 0, s>>>(score, b->offsets, b->winner,
+                                                                                       b->E, dscore, loss));
+    if ((rc = backward(ctx, s, net->params, q, b->feat, b->M, dscore, net->grad)) != SCHULZE_OK) return rc;
+    SCHULZE_LAUNCH(ctx, K_MLP_ADAM, s, k_step_next<<<dim3(1), dim3(64), 0, s>>>(net->step));
+    SCHULZE_LAUNCH(ctx, K_MLP_ADAM, s,
+                   k_adam<<<dim3((unsigned)ceil_div(NPARAM, 256)), dim3(256), 0, s>>>(
+                       net->params, net->grad, net->adam_m, net->adam_v, net->lr, net->beta1, net->beta2, net->eps, 0,
+                       net->step));
     return SCHULZE_OK;
 }
 

@@ -49,7 +49,8 @@ typedef __attribute__((ext_vector_type(2))) unsigned short us2;
 // Workspace views (WS_BALLOT_META).
 struct Meta {
     int32_t *ctr;            // [0] full rankings [1] truncated ballots [2] route
-                             // [3] |U| [4] U-space pitch
+                             // [3] |U| [4] U-space pitch [32..33] total voter
+                             // weight (64 bits) [34] its workgroups done
     unsigned long long *k2;  // NPART partial sums of k(k-1)/2 over truncated ballots
     int32_t *len;            // listed length per ballot
     int32_t *full_src;       // slot -> ballot of a full ranking
@@ -925,6 +926,32 @@ __global__ __launch_bounds__(256) void k_count_finish(const uint32_t *__restrict
 }
 
 // Byte layout of WS_BALLOT_META for n ballots and m candidates.
+// Total voter weight in 64 bits: counts accumulate in 32-bit words, which
+// cannot wrap while the total stays below 2^32 (and then the finish checks
+// every count against the value type); a total of 2^32 or more sets
+// SCHULZE_ERANGE.  total and done start at zero; the last workgroup to add
+// its part decides.
+__global__ __launch_bounds__(256) void k_weight_total(const uint32_t *__restrict__ w, int64_t n,
+                                                      unsigned long long *total, int32_t *done, int32_t *err) {
+    __shared__ unsigned long long part[256];
+    unsigned long long acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) acc += w[i];
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd(total, part[0]);
+        __threadfence();
+        if (atomicAdd(done, 1) == (int32_t)gridDim.x - 1) {
+            __threadfence();
+            if (atomicAdd(total, 0ull) >> 32) set_device_error(err, SCHULZE_ERANGE);
+        }
+    }
+}
+
 struct MetaLayout {
     size_t ctr, k2, len, full_src, trunc_src, in_u, ulist, umap, total;
     MetaLayout(int64_t n, int32_t m) {
@@ -1077,6 +1104,14 @@ extern "C" int schulze_pairwise(schulze_ctx *ctx, void *stream, const void *ball
                        k_route<<<dim3(1), dim3(256), 0, s>>>(m, meta, voter_weight != nullptr,
                                                              (int64_t)(tpos_bytes / sizeof(uint32_t)),
                                                              occ_ok ? BUCKETED_PAIR_COST : ATOMIC_PAIR_COST));
+        if (voter_weight) {
+            // counters 32..33: the 64-bit total; 34: workgroups done (zeroed above)
+            const unsigned tg = (unsigned)std::min<int64_t>(ceil_div(n, 256), (int64_t)ctx->num_cus * 4);
+            SCHULZE_LAUNCH(ctx, K_ROUTE, s,
+                           k_weight_total<<<dim3(tg), dim3(256), 0, s>>>(
+                               voter_weight, n, reinterpret_cast<unsigned long long *>(meta.ctr + 32), meta.ctr + 34,
+                               ctx->err));
+        }
         const unsigned cgrid = (unsigned)ctx->num_cus * 2;
         if (may_have_full) {
             uint32_t *pos = static_cast<uint32_t *>(ctx->ws[WS_POSITIONS]);

@@ -64,6 +64,7 @@ class Trainer:
         self.m1 = torch.zeros_like(self.params)
         self.m2 = torch.zeros_like(self.params)
         self.grad = torch.zeros_like(self.params)
+        self.step_dev = torch.zeros(1, dtype=torch.int32, device=dev)  # Adam steps, advanced on the device
         self.step = 0
         self._feats, self._wins, self._sizes = [], [], []
         self.feat = self.win = self.offsets = None
@@ -101,21 +102,20 @@ class Trainer:
         for ep in range(epochs):
             shift = ep % max(1, len(starts))
             order = starts[shift:] + starts[:shift]
-            total, count = 0.0, 0
+            total = torch.zeros((), dtype=torch.float64, device=self.params.device)
+            count = 0
             for e0 in order:
                 e1 = min(E, e0 + batch)
                 r0, r1 = int(off[e0]), int(off[e1])
                 feat = self.feat[r0:r1]
                 win = self.win[r0:r1]
-                seg = self.offsets[e0:e1 + 1] - r0
-                score = self.ctx.mlp_forward(self.params, feat)
-                ds, loss = self.ctx.mlp_loss(score, seg.contiguous(), win)
-                self.ctx.mlp_backward(self.params, feat, ds, out=self.grad)
+                seg = (self.offsets[e0:e1 + 1] - r0).contiguous()
+                loss = self.ctx.mlp_train_step(self.params, self.m1, self.m2, self.grad, self.step_dev, feat, seg,
+                                               win, lr=lr)
                 self.step += 1
-                self.ctx.mlp_adam(self.params, self.grad, self.m1, self.m2, lr, self.step)
-                total += float(loss.sum().item())
+                total += loss.sum(dtype=torch.float64)
                 count += e1 - e0
-            history.append(total / max(count, 1))
+            history.append(float(total.item()) / max(count, 1))
             if log:
                 log(f"epoch {ep}: mean loss {history[-1]:.4f}")
         torch.cuda.synchronize()

@@ -20,10 +20,32 @@ def owner(I, J, nb, G):
     return (I * nb + (I + J) % nb) % G
 
 
+def owned_tiles(w, nb, G):
+    """Tiles of workgroup w in the kernel's order: numbers k = w, w + G, ...
+    below nb^2, each standing for block row I = k // nb and column
+    J = (k mod nb - I) mod nb; returned as tile ids I nb + J."""
+    out = []
+    for k in range(w, nb * nb, G):
+        I = k // nb
+        out.append(I * nb + (k % nb - I) % nb)
+    return out
+
+
+def test_owned_tiles_invert_the_owner_map():
+    for nb in (1, 2, 5, 8, 13, 32):
+        for G in (1, 3, nb, nb + 1, 2 * nb, 3 * nb + 2, 64):
+            seen = []
+            for w in range(G):
+                ts = owned_tiles(w, nb, G)
+                assert all(owner(t // nb, t % nb, nb, G) == w for t in ts)
+                seen += ts
+            assert sorted(seen) == list(range(nb * nb))
+
+
 def wg_program(w, nb, G, flags, gate):
     """The order in which workgroup w takes its items: ('diag'|'panel'|'rest'|'probe', round, I, J, flags waited on).
     gate: early steps while nb^2 <= gate * G (20 for uint16, 8 for int32)."""
-    owned = [t for t in range(nb * nb) if owner(t // nb, t % nb, nb, G) == w]
+    owned = owned_tiles(w, nb, G)
     early = nb * nb <= gate * G
     has_panels = lambda r: any(((t // nb) == r) != ((t % nb) == r) for t in owned)
 

@@ -7,6 +7,10 @@ d[y][x] = n - d[x][y]), ballots listing m-1 candidates, truncated ballots
 (every ordered sub-block), empty elections and sizes around the 8-candidate
 sub-block, the 32/64/128 closure paddings and the staging widths.
 """
+import hashlib
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -46,6 +50,18 @@ def mixed_elections(seed):
     out.append((workload.pl_zipf(seed, 301, 150, 1.0, 12, election=43), 150))
     out.append((workload.uniform_ballots(seed, 9, 5, 2, min_len=0, election=44), 5))
     return out
+
+
+def election_digests(d, p, beaten_by, is_winner, order):
+    """[d, p, ranking outputs] digests of one election, as the stored oracle
+    results hold them: the first 32 hex digits of SHA-256 over the int64
+    little-endian arrays."""
+    def dig(*arrays):
+        h = hashlib.sha256()
+        for a in arrays:
+            h.update(np.ascontiguousarray(a, dtype="<i8").tobytes())
+        return h.hexdigest()[:32]
+    return [dig(d), dig(p), dig(beaten_by, is_winner, order)]
 
 
 def expected(elections, mode):
@@ -335,6 +351,21 @@ def test_batch_full_workload_sampled():
             assert (w_all[vo:vo + m] == (bb == 0)).all() and nw_all[e] == (bb == 0).sum() >= 1, e
             want_order = np.lexsort((np.arange(m), bb))
             assert (o_all[vo:vo + m] == want_order).all(), e
+        # every election against the oracle's stored digests
+        gold_path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch_mallows_E4096.json")
+        if os.path.exists(gold_path):
+            with open(gold_path) as f:
+                gold = json.load(f)
+            assert gold["m"] == ms.tolist() and gold["n"] == ns.tolist()
+            bad = []
+            for e, (bo, n, L, m, mo, vo) in enumerate(desc):
+                dg = election_digests(d_all[mo:mo + m * m].reshape(m, m), p_all[mo:mo + m * m].reshape(m, m),
+                                      bb_all[vo:vo + m], w_all[vo:vo + m], o_all[vo:vo + m])
+                want = gold["elections"][e]
+                if dg != want[:3] or int(nw_all[e]) != want[3]:
+                    bad.append(e)
+            assert not bad, f"{len(bad)} elections differ from the oracle, first {bad[:10]}"
+            log("[case] batch full workload: all 4096 elections equal the oracle's digests")
         # the oracle on the largest elections and a seeded sample
         big = list(np.argsort(-(ms * ms * ns))[:3])
         rng = np.random.default_rng(7)

@@ -81,3 +81,26 @@ def test_learned_matches_closure_on_mid_workload(ctx):
         w, nw, st = ctx.winners_learned(d, float(wl.n), pt)
         log(f"[case] learned mid workload {which}: {st}")
         assert np.nonzero(w.cpu().numpy())[0].tolist() == gold["winners"]
+
+
+@pytest.mark.parametrize("proposer", ["borda", "copeland", "filter+borda"])
+def test_learned_winners_with_plain_proposers(ctx, proposer):
+    """Borda, Copeland or filtered Borda in place of the network: the same
+    exact winner sets (the proposal only decides where the search starts)."""
+    import torch
+    try:
+        ctx.set_proposer(proposer)
+        for name, b, m in elections():
+            log(f"[case] learned proposer={proposer} {name} m={m}")
+            want = oracle.schulze(b, m)["is_winner"]
+            d = ctx.pairwise(torch.from_numpy(b).cuda(), m, dtype="i32")
+            for max_climb, max_tied in ((8, 64), (0, 64), (8, 0)):
+                w, nw, st = ctx.winners_learned(d, float(b.shape[0]), None, max_climb=max_climb,
+                                                max_tied=max_tied)
+                got = w.cpu().numpy().astype(bool)
+                assert np.array_equal(got, want), (proposer, name, max_climb, max_tied, st)
+                assert int(nw.cpu()[0]) == int(want.sum())
+    finally:
+        ctx.set_proposer("network")
+    import paper_2505_12976_amd as sz
+    assert ctx._lib.schulze_set_proposer(ctx._h, 7) == sz.EINVAL

@@ -41,7 +41,7 @@ def cuda(a, dtype=None):
 
 @pytest.mark.parametrize("m,dtype,mode", [(1, "i32", "winning_votes"), (5, "u16", "margin"), (64, "i32", "margin"),
                                           (300, "u16", "winning_votes"), (1000, "i32", "winning_votes"),
-                                          (5000, "i32", "margin")])
+                                          (5000, "i32", "margin"), (9000, "u16", "winning_votes")])
 def test_features(ctx, m, dtype, mode):
     import torch
     b = workload.pl_zipf(m, 400, m, 1.0, min(m, 15))

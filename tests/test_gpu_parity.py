@@ -210,6 +210,37 @@ def test_u16_overflow_is_rejected(ctx):
     assert ctx.device_error() == sz.ERANGE
 
 
+@pytest.mark.parametrize("route", ["full", "truncated", "pairs"])
+def test_weighted_total_beyond_32_bits_is_rejected(ctx, route):
+    """Weighted counts accumulate in 32 bits: a total weight of 2^32 or more
+    sets ERANGE (it could wrap a count back into range); a total just below
+    2^32 with every count under 2^31 is counted exactly."""
+    import torch
+    import paper_2505_12976_amd as sz
+    m = {"full": 3, "truncated": 40, "pairs": 3000}[route]
+    fwd = np.full((1, m), -1, dtype=np.int32)
+    bwd = np.full((1, m), -1, dtype=np.int32)
+    k = m if route == "full" else 3
+    fwd[0, :k] = np.arange(k)
+    bwd[0, :k] = np.arange(k)[::-1]
+    b = np.concatenate([fwd, bwd])
+    # both ballots put the listed candidates above the unlisted ones, so
+    # there only totals below 2^31 fit; opposite full rankings split them
+    fits = [2 ** 31 - 1, 2 ** 31 - 1] if route == "full" else [2 ** 30, 2 ** 30 - 1]
+    for weights, ok in (([2 ** 31, 2 ** 31], False), ([2 ** 32 - 1, 1], False), (fits, True)):
+        log(f"[case] weighted total {sum(weights)} route={route} m={m}")
+        w = torch.from_numpy(np.array(weights, dtype=np.uint32)).cuda()
+        d = ctx.pairwise(torch.from_numpy(b).cuda(), m, voter_weight=w, dtype="i32")
+        torch.cuda.synchronize()
+        err = ctx.device_error()
+        if ok:
+            assert err == 0
+            want = oracle.pairwise(b, m, weight=np.array(weights, dtype=np.uint32))
+            assert (d.cpu().numpy().astype(np.int64) == want).all()
+        else:
+            assert err == sz.ERANGE
+
+
 def _digest(a):
     return hashlib.sha256(np.ascontiguousarray(a, dtype="<i8").tobytes()).hexdigest()
 
@@ -258,3 +289,65 @@ def test_plain_large_workload_full_size(ctx):
     wl = workload.plain_large()
     gold = _golden(wl.name)
     _check_against_golden(ctx, wl, gold)
+
+
+def _digest_chunked(a, rows=1024):
+    """SHA-256 of a (as int64 little-endian, row-major), hashed in row chunks."""
+    h = hashlib.sha256()
+    for i in range(0, a.shape[0], rows):
+        h.update(np.ascontiguousarray(a[i:i + rows], dtype="<i8").tobytes())
+    return h.hexdigest()
+
+
+@pytest.mark.slow
+def test_learned_workload_full_size(ctx):
+    """m=32768, n=200000 top-30 Plackett-Luce Zipf(1.0): d against the
+    oracle's digest; the winner set of the learned path, of label
+    propagation and of the full closure against the oracle's (certified by
+    single-source/target widest paths); rows and columns of the GPU closure
+    at the winners, the candidates tied with them and a seeded sample against
+    the oracle's widest paths; the verify kernel's rows at the winner too."""
+    import torch
+    from paper_2505_12976_amd.proposer import load_checkpoint
+    wl = workload.plain_learned()
+    gold = _golden(wl.name)
+    m, n = wl.m, wl.n
+    assert hashlib.sha256(np.ascontiguousarray(wl.ballots).tobytes()).hexdigest() == gold["ballots_sha256"]
+    dev = torch.device("cuda", 0)
+    log(f"[case] {wl.name}: count")
+    d = ctx.pairwise(torch.from_numpy(wl.ballots).to(dev), m, dtype="i32")
+    torch.cuda.synchronize()
+    assert ctx.device_error() == 0
+    d_host = d.cpu().numpy()
+    if _digest_chunked(d_host) != gold["d_sha256"]:
+        rows = np.nonzero(d_host.sum(axis=1, dtype=np.int64) != np.array(gold["d_row_sums"]))[0]
+        raise AssertionError(f"d differs; rows with other sums: {rows[:10].tolist()}")
+    del d_host
+    want = gold["winners"]
+    ckpt = os.path.join(os.path.dirname(GOLD), "..", "paper_2505_12976_amd", "data", "proposer.npz")
+    params = torch.from_numpy(load_checkpoint(ckpt)["params"]).to(dev)
+    log(f"[case] {wl.name}: learned path")
+    w, nw, st = ctx.winners_learned(d, float(n), params)
+    assert np.nonzero(w.cpu().numpy())[0].tolist() == want, st
+    log(f"[case] {wl.name}: label propagation")
+    w, nw, st = ctx.winners_propagate(d)
+    assert np.nonzero(w.cpu().numpy())[0].tolist() == want, st
+    log(f"[case] {wl.name}: verify at the first winner")
+    wgt, wgt_t = ctx.weights(d)
+    c0 = int(gold["first_winner"])
+    verdict, p_from, p_to, _ = ctx.verify(wgt, wgt_t, c0)
+    assert int(verdict[0].item()) == 1
+    ref = gold["p_rows_cols"][str(c0)]
+    assert _digest_chunked(p_from.cpu().numpy()) == ref["row_sha256"]
+    assert _digest_chunked(p_to.cpu().numpy()) == ref["col_sha256"]
+    del wgt, wgt_t
+    log(f"[case] {wl.name}: full closure")
+    p = ctx.closure(d)
+    iw, nw = ctx.winners(p)
+    torch.cuda.synchronize()
+    assert ctx.device_error() == 0
+    assert np.nonzero(iw.cpu().numpy())[0].tolist() == want
+    for c, ref in gold["p_rows_cols"].items():
+        c = int(c)
+        assert _digest_chunked(p[c].cpu().numpy()) == ref["row_sha256"], f"row {c}"
+        assert _digest_chunked(p[:, c].contiguous().cpu().numpy()) == ref["col_sha256"], f"column {c}"

@@ -4,8 +4,8 @@ An int32 closure of m >= 1024 candidates runs on the ranks of the weight
 values in packed uint16 when there are at most 65535 distinct nonzero values,
 all below 2^24, and on int32 otherwise.  The widest-path recurrence of
 Section 2.1 only compares values, so both give the oracle's widths exactly.
-Each case checks the output against the oracle and records, from the launch
-counts of the ranking kernels, which of the two paths ran.
+Each case checks the output against the oracle and, through
+schulze_closure_value_bits, which of the two paths the device chose.
 """
 import sys
 
@@ -16,8 +16,9 @@ import oracle
 
 pytestmark = pytest.mark.gpu
 
-RANKED_LAUNCHES = 6    # mark, block sums, scan, word ranks, apply, store
-FALLBACK_LAUNCHES = 3  # mark, block sums, scan
+RANKED = 16    # value width of the recurrence: ranks in packed uint16
+FALLBACK = 32  # int32 values
+RANK_LAUNCHES = 6  # mark, block sums, scan (deciding), word ranks, apply, store (gated on the decision)
 
 
 def log(msg):
@@ -57,18 +58,21 @@ def run(ctx, d, mode, ranking):
     launches, _ = ctx.kernel_time("value_rank")
     ctx.set_timing(False)
     assert ctx.device_error() == 0
-    return p.cpu().numpy().astype(np.int64), launches
+    return p.cpu().numpy().astype(np.int64), launches, ctx.closure_value_bits()
 
 
-def check(ctx, d, mode, expect_launches, tag):
+def check(ctx, d, mode, expect_bits, tag):
     want = oracle.closure(oracle.weights(d, oracle.MARGIN if mode == "margin" else oracle.WINNING_VOTES))
     log(f"[case] {tag} m={d.shape[0]} mode={mode} distinct={len(np.unique(d))}")
-    got, launches = run(ctx, d, mode, True)
+    got, launches, bits = run(ctx, d, mode, True)
     bad = np.argwhere(got != want)
     assert bad.size == 0, f"{tag}: ranked closure differs at {len(bad)} places, first {bad[:5].tolist()}"
-    assert launches == expect_launches, f"{tag}: {launches} ranking launches, expected {expect_launches}"
-    off, launches_off = run(ctx, d, mode, False)
-    assert launches_off == 0
+    # the ranking kernels run (and decide) from m = 1024 on; below that the int32 closure runs directly
+    want_launches = RANK_LAUNCHES if d.shape[0] >= 1024 else 0
+    assert launches == want_launches, f"{tag}: {launches} ranking launches, expected {want_launches}"
+    assert bits == expect_bits, f"{tag}: the recurrence ran on {bits}-bit values, expected {expect_bits}"
+    off, launches_off, bits_off = run(ctx, d, mode, False)
+    assert launches_off == 0 and bits_off == 32
     assert np.array_equal(off, want), f"{tag}: int32 closure differs"
 
 
@@ -77,7 +81,7 @@ def test_few_values_take_ranks(ctx, m):
     rng = np.random.default_rng(70 + m)
     d = rng.integers(0, 4000, size=(m, m), dtype=np.int64)
     np.fill_diagonal(d, 0)
-    check(ctx, d, "winning_votes", RANKED_LAUNCHES, "few-values")
+    check(ctx, d, "winning_votes", RANKED, "few-values")
 
 
 def test_margins_take_ranks(ctx):
@@ -86,14 +90,14 @@ def test_margins_take_ranks(ctx):
     d = rng.integers(0, 100000, size=(m, m), dtype=np.int64)
     d = np.minimum(d, d.T + rng.integers(0, 300, size=(m, m)))  # small margins, few distinct
     np.fill_diagonal(d, 0)
-    check(ctx, d, "margin", RANKED_LAUNCHES, "margins")
+    check(ctx, d, "margin", RANKED, "margins")
 
 
 def test_largest_rankable_value(ctx):
     rng = np.random.default_rng(72)
     m = 1024
     vals = rng.choice(np.array([1, 2, 1000, (1 << 24) - 2, (1 << 24) - 1], dtype=np.int64), size=m * (m - 1) // 2)
-    check(ctx, oriented(rng, m, vals), "winning_votes", RANKED_LAUNCHES, "max-value")
+    check(ctx, oriented(rng, m, vals), "winning_votes", RANKED, "max-value")
 
 
 def test_value_too_wide_falls_back(ctx):
@@ -101,19 +105,19 @@ def test_value_too_wide_falls_back(ctx):
     m = 1024
     vals = rng.integers(1, 50, size=m * (m - 1) // 2)
     vals[rng.integers(0, vals.size)] = 1 << 24
-    check(ctx, oriented(rng, m, vals), "winning_votes", FALLBACK_LAUNCHES, "value-2^24")
+    check(ctx, oriented(rng, m, vals), "winning_votes", FALLBACK, "value-2^24")
     vals[rng.integers(0, vals.size)] = (1 << 31) - 1
-    check(ctx, oriented(rng, m, vals), "winning_votes", FALLBACK_LAUNCHES, "value-int32-max")
+    check(ctx, oriented(rng, m, vals), "winning_votes", FALLBACK, "value-int32-max")
 
 
-@pytest.mark.parametrize("distinct,launches", [(65535, RANKED_LAUNCHES), (65536, FALLBACK_LAUNCHES)])
-def test_distinct_value_limit(ctx, distinct, launches):
+@pytest.mark.parametrize("distinct,bits", [(65535, RANKED), (65536, FALLBACK)])
+def test_distinct_value_limit(ctx, distinct, bits):
     rng = np.random.default_rng(74 + distinct)
     m = 1024
     pool = rng.choice(np.arange(1, 1 << 24, dtype=np.int64), size=distinct, replace=False)
     vals = np.concatenate([pool, rng.choice(pool, size=m * (m - 1) // 2 - distinct)])
     rng.shuffle(vals)
-    check(ctx, oriented(rng, m, vals), "winning_votes", launches, f"distinct-{distinct}")
+    check(ctx, oriented(rng, m, vals), "winning_votes", bits, f"distinct-{distinct}")
 
 
 def test_many_values_fall_back(ctx):
@@ -121,15 +125,15 @@ def test_many_values_fall_back(ctx):
     m = 1100
     d = rng.integers(0, 1 << 23, size=(m, m), dtype=np.int64)
     np.fill_diagonal(d, 0)
-    check(ctx, d, "winning_votes", FALLBACK_LAUNCHES, "many-values")
+    check(ctx, d, "winning_votes", FALLBACK, "many-values")
 
 
 def test_all_zero_and_one_value(ctx):
     m = 1024
     d = np.zeros((m, m), dtype=np.int64)
-    check(ctx, d, "winning_votes", RANKED_LAUNCHES, "all-zero")
+    check(ctx, d, "winning_votes", RANKED, "all-zero")
     rng = np.random.default_rng(76)
-    check(ctx, oriented(rng, m, np.full(m * (m - 1) // 2, 12345)), "winning_votes", RANKED_LAUNCHES, "one-value")
+    check(ctx, oriented(rng, m, np.full(m * (m - 1) // 2, 12345)), "winning_votes", RANKED, "one-value")
 
 
 def test_below_threshold_runs_int32(ctx):
@@ -137,7 +141,7 @@ def test_below_threshold_runs_int32(ctx):
     m = 1023
     d = rng.integers(0, 4000, size=(m, m), dtype=np.int64)
     np.fill_diagonal(d, 0)
-    check(ctx, d, "winning_votes", 0, "m-1023")
+    check(ctx, d, "winning_votes", FALLBACK, "m-1023")
 
 
 @pytest.mark.parametrize("tile", [64, 128])

@@ -239,12 +239,13 @@ def batch_election(seed: int, e: int, m: int, n: int, phi: float) -> np.ndarray:
     return mallows(seed, int(n), int(m), float(phi), election=int(e), dtype=np.uint16)
 
 
-def batch_mallows(seed: int = 1004, count: int = 4096, **size_kw):
+def batch_mallows(seed: int = 1004, count: int = 4096, progress=None, **size_kw):
     """A batch of `count` elections of full Mallows rankings with the sizes of
     batch_params, ballots written back to back into one flat uint16 array.
     Returns (flat ballots, descriptors, (ms, ns, phis)); a descriptor is
     (ballot_off, n, L, m, mat_off, vec_off) with L = m and the m x m and
-    m-entry output blocks laid out back to back."""
+    m-entry output blocks laid out back to back.  progress: None or a
+    callable given the number of elections generated, every 512."""
     ms, ns, phis = batch_params(seed, count, **size_kw)
     total = int(np.sum(ms * ns))
     flat = np.empty(max(total, 1), dtype=np.uint16)
@@ -258,6 +259,8 @@ def batch_mallows(seed: int = 1004, count: int = 4096, **size_kw):
                              flat.ctypes.data + 2 * bo)
         _check(rc, "gen_mallows")
         desc.append((bo, n, m, m, mo, vo))
+        if progress is not None and (e + 1) % 512 == 0:
+            progress(e + 1)
         bo += n * m
         mo += m * m
         vo += m
@@ -293,3 +296,17 @@ def training_mixture(seed: int, count: int, m_lo: int = 256, m_hi: int = 2048, f
             b = mallows(seed, n, m, float(phis[e]), election=e)
             kind = "mallows phi=%.3f" % phis[e]
         yield {"election": e, "m": m, "n": n, "kind": kind, "ballots": b}
+
+
+def near_impartial_mixture(seed: int, count: int, m_lo: int = 256, m_hi: int = 512):
+    """Elections of full Mallows rankings with phi ~ U[0.995, 1.0] (close to
+    impartial culture, where a Condorcet winner is rare): m ~ U{m_lo..m_hi},
+    n = round(rho m) with rho ~ U[3, 12].  Yields dicts like training_mixture."""
+    ms = uniform_int(seed, 1, count, m_lo, m_hi)
+    rhos = uniform_real(seed, 2, count, 3.0, 12.0)
+    phis = uniform_real(seed, 5, count, 0.995, 1.0)
+    for e in range(count):
+        m = int(ms[e])
+        n = int(round(rhos[e] * m))
+        b = mallows(seed, n, m, float(phis[e]), election=e)
+        yield {"election": e, "m": m, "n": n, "kind": "mallows phi=%.4f" % phis[e], "ballots": b}
