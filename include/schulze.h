@@ -196,6 +196,22 @@ int schulze_verify(schulze_ctx *ctx, void *stream, const void *w, int64_t ldw, c
                    void *p_from, void *p_to, int32_t *verdict, int32_t *tied);
 
 /*
+ * schulze_verify for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, outputs and errors as schulze_verify, but the sweep state
+ * lives in a static device array of 1 MiB per device, whose address the
+ * library looks up when a context is created, instead of the context's
+ * workspace; the call allocates nothing.  Limit: widest-path state of
+ * 13 m + 1.3 KB bytes, i.e. every m <= 65535 (larger m: SCHULZE_EUNSUPPORTED).
+ * All calls on one device share that array and leave the last call's state
+ * in it: calls that overlap on one device (other streams, other contexts,
+ * other host threads) race and must be serialised by the caller.
+ */
+int schulze_verify_noalloc(schulze_ctx *ctx, void *stream, const void *w, int64_t ldw, const void *wt,
+                           int64_t ldwt, int32_t m, int dtype, int32_t cand, const float *score,
+                           void *p_from, void *p_to, int32_t *verdict, int32_t *tied);
+
+/*
  * Per-candidate features of the weighted tournament graph (the learned
  * proposer's input), computed from d in one pass:
  *   feat[x][0..15] = Copeland score, ties, Borda score (the vertex-id order of

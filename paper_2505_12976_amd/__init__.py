@@ -35,7 +35,7 @@ EXPORTS = (
     "schulze_winners_learned",
     "schulze_batch_plan", "schulze_batch_destroy", "schulze_batch_run", "schulze_batch_set_closure",
     "schulze_batch_get_closure", "schulze_batch_autotune", "schulze_winners_propagate",
-    "schulze_topk_propagate", "schulze_valu_probe", "schulze_closure_value_bits", "schulze_set_proposer",
+    "schulze_topk_propagate", "schulze_valu_probe", "schulze_closure_value_bits", "schulze_set_proposer", "schulze_verify_noalloc",
 )
 
 
@@ -138,6 +138,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.schulze_weights.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_int, vp, c_i64, vp, c_i64]
     lib.schulze_widest_from.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_i32, vp]
     lib.schulze_verify.argtypes = [vp, vp, vp, c_i64, vp, c_i64, c_i32, c_int, c_i32, vp, vp, vp, vp, vp]
+    lib.schulze_verify_noalloc.argtypes = [vp, vp, vp, c_i64, vp, c_i64, c_i32, c_int, c_i32, vp, vp, vp, vp, vp]
     lib.schulze_features.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_int, ctypes.c_float, vp]
     lib.schulze_mlp_param_count.argtypes = []
     lib.schulze_winners_learned.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_int, ctypes.c_float, vp, c_i32, c_i32,
@@ -330,9 +331,22 @@ class Context:
         _check(rc, "schulze_widest_from")
         return out
 
-    def verify(self, w, wt, cand: int, score=None, want_tied=False):
-        """(verdict int32[4], p_from, p_to, tied or None); see schulze_verify."""
+    def verify(self, w, wt, cand: int, score=None, want_tied=False, noalloc=False, out=None):
+        """(verdict int32[4], p_from, p_to, tied or None); see schulze_verify.
+        noalloc: call schulze_verify_noalloc (sweep state in the library's
+        static device scratch).  out: optional (verdict, p_from, p_to, tied)
+        tensors to write into."""
         import torch
+        if out is not None:
+            verdict, p_from, p_to, tied = out
+            fn = self._lib.schulze_verify_noalloc if noalloc else self._lib.schulze_verify
+            m = w.shape[0]
+            sp = None if score is None else self._dev(score, "score")
+            rc = fn(self._h, self._stream(), self._dev(w, "w"), w.stride(0), self._dev(wt, "wt"), wt.stride(0), m,
+                    _dtype_code(w.dtype), cand, sp, self._dev(p_from, "p_from"), self._dev(p_to, "p_to"),
+                    self._dev(verdict, "verdict"), None if tied is None else self._dev(tied, "tied"))
+            _check(rc, "schulze_verify_noalloc" if noalloc else "schulze_verify")
+            return verdict, p_from, p_to, tied
         m = w.shape[0]
         p_from = torch.empty(m, dtype=w.dtype, device=self._torch_device)
         p_to = torch.empty(m, dtype=w.dtype, device=self._torch_device)
@@ -343,11 +357,12 @@ class Context:
             if score.dtype != torch.float32 or score.shape != (m,):
                 raise ValueError("score must be a float32 tensor of shape (m,)")
             sp = self._dev(score, "score")
-        rc = self._lib.schulze_verify(self._h, self._stream(), self._dev(w, "w"), w.stride(0),
-                                      self._dev(wt, "wt"), wt.stride(0), m, _dtype_code(w.dtype), cand, sp,
-                                      self._dev(p_from, "p_from"), self._dev(p_to, "p_to"),
-                                      self._dev(verdict, "verdict"), None if tied is None else self._dev(tied, "tied"))
-        _check(rc, "schulze_verify")
+        fn = self._lib.schulze_verify_noalloc if noalloc else self._lib.schulze_verify
+        rc = fn(self._h, self._stream(), self._dev(w, "w"), w.stride(0),
+                self._dev(wt, "wt"), wt.stride(0), m, _dtype_code(w.dtype), cand, sp,
+                self._dev(p_from, "p_from"), self._dev(p_to, "p_to"),
+                self._dev(verdict, "verdict"), None if tied is None else self._dev(tied, "tied"))
+        _check(rc, "schulze_verify_noalloc" if noalloc else "schulze_verify")
         return verdict, p_from, p_to, tied
 
     def features(self, d, n_voters: float, mode="winning_votes", out=None):

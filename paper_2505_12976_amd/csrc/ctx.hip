@@ -61,6 +61,11 @@ extern "C" int schulze_create(schulze_ctx **out, int device) {
     }
     ctx->launches.assign(K_NUM_KERNELS, 0);
     ctx->total_ms.assign(K_NUM_KERNELS, 0.0);
+    if (verify_scratch_init(device, &ctx->verify_scratch) != SCHULZE_OK) {
+        (void)hipFree(ctx->err);
+        delete ctx;
+        return SCHULZE_EDEVICE;
+    }
     *out = ctx;
     return SCHULZE_OK;
 }

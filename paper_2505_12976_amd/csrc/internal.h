@@ -62,6 +62,8 @@ struct schulze_ctx {
     // (then *closure_ranked_flag is 1 for ranks in uint16, 0 for int32)
     int closure_bits = 0;
     const int32_t *closure_ranked_flag = nullptr;
+    // device address of schulze_verify_noalloc's static scratch on this context's device
+    void *verify_scratch = nullptr;
     // first proposal of the learned path (SCHULZE_PROPOSER_*)
     int proposer = SCHULZE_PROPOSER_NETWORK;
     // truncated ballots: pair scattering with device-wide atomics instead of bucketing
@@ -134,6 +136,10 @@ int fill_u32(schulze_ctx *ctx, hipStream_t s, uint32_t *ptr, size_t words, uint3
 // w^T (as schulze_weights) in one pass over d; arguments already checked.
 int weights_and_features(schulze_ctx *ctx, hipStream_t s, const void *d, int64_t ldd, int32_t m, int dtype, int mode,
                          float n_voters, float *feat, void *w, int64_t ldw, void *wt, int64_t ldwt);
+
+// Device address of the static scratch of schulze_verify_noalloc on `device`
+// (looked up once per device; the device must be current).
+int verify_scratch_init(int device, void **ptr);
 
 // Bind the context's device to the calling thread.
 int bind_device(schulze_ctx *ctx);

@@ -14,9 +14,46 @@
 //
 // One persistent cooperative launch runs all sweeps (the column-block and
 // frontier-share layout of sweep.h), with a grid barrier between sweeps.
+#include <mutex>
+
 #include "grid.h"
 #include "sweep.h"
 #include "tile_io.h"
+
+// Device scratch of schulze_verify_noalloc: the sweeps' value vector, flags,
+// two frontier lists and counters for up to 65535 candidates (852 KB used
+// at that size).  Each device holds its own copy for the life of the
+// process.  In host code `scratch` only names the symbol; its device address
+// comes from hipGetSymbolAddress (verify_scratch_init) and is the only form
+// passed to kernels.
+constexpr size_t VERIFY_SCRATCH_BYTES = (size_t)1 << 20;
+static __device__ __align__(256) unsigned char scratch[VERIFY_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[MAX_DEVICES] = {};  // device address of `scratch`, per device
+
+}  // namespace
+
+// Look up this device's address of the scratch array (once per device; the
+// device must be current).
+int verify_scratch_init(int device, void **ptr) {
+    *ptr = nullptr;
+    if (device < 0 || device >= MAX_DEVICES) return SCHULZE_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return SCHULZE_EDEVICE;
+        }
+        g_scratch[device] = p;
+    }
+    *ptr = g_scratch[device];
+    return SCHULZE_OK;
+}
 
 namespace {
 
@@ -158,16 +195,25 @@ bool sweep_vec_ok(const void *p, int64_t ld) {
     return (reinterpret_cast<uintptr_t>(p) % (4 * sizeof(E)) == 0) && (ld % 4 == 0);
 }
 
-template <typename E>
-int widest(schulze_ctx *ctx, hipStream_t s, const E *w, int64_t ldw, int32_t m, int32_t src, E *out) {
-    // workspace: values, flags, two frontiers, counters, barrier
+// Scratch of one widest-path launch: values, flags, two frontiers, counters, barrier.
+size_t widest_scratch_bytes(int32_t m) {
     const size_t xbytes = round_up(sizeof(uint32_t) * (size_t)m, 256);
     const size_t cbytes = round_up((size_t)m, 256);
     const size_t fbytes = round_up(sizeof(int32_t) * (size_t)m, 256);
-    const size_t need = xbytes + cbytes + 2 * fbytes + 256;
-    int rc = ws_reserve(ctx, WS_VERIFY, need);
-    if (rc != SCHULZE_OK) return rc;
-    char *base = static_cast<char *>(ctx->ws[WS_VERIFY]);
+    return xbytes + cbytes + 2 * fbytes + 256;
+}
+
+// Widest paths from src over the rows of w, with the sweep state in `base`
+// (widest_scratch_bytes(m) bytes of device memory; the counters and barrier
+// are cleared here, everything else is written before it is read).  `timed`
+// brackets the launch with the context's timing events.
+template <typename E>
+int widest_in(schulze_ctx *ctx, hipStream_t s, const E *w, int64_t ldw, int32_t m, int32_t src, E *out, char *base,
+              bool timed) {
+    const size_t xbytes = round_up(sizeof(uint32_t) * (size_t)m, 256);
+    const size_t cbytes = round_up((size_t)m, 256);
+    const size_t fbytes = round_up(sizeof(int32_t) * (size_t)m, 256);
+    int rc;
     WidestArgs<E> a;
     a.w = w;
     a.ldw = ldw;
@@ -190,14 +236,40 @@ int widest(schulze_ctx *ctx, hipStream_t s, const E *w, int64_t ldw, int32_t m, 
         return SCHULZE_EDEVICE;
     const int64_t G = sweep::grid_size(m, (int64_t)ctx->num_cus * std::min(per_cu, 2));
     void *args[] = {&a};
-    int tok;
-    timing_begin(ctx, K_WIDEST, s, &tok);
+    int tok = -1;
+    if (timed) timing_begin(ctx, K_WIDEST, s, &tok);
     hipError_t e = hipLaunchCooperativeKernel((const void *)k_widest<E>, dim3((unsigned)G), dim3(256), args, 0, s);
-    timing_end(ctx, tok, s);
+    if (timed) timing_end(ctx, tok, s);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return SCHULZE_EDEVICE;
     }
+    return SCHULZE_OK;
+}
+
+template <typename E>
+int widest(schulze_ctx *ctx, hipStream_t s, const E *w, int64_t ldw, int32_t m, int32_t src, E *out) {
+    int rc = ws_reserve(ctx, WS_VERIFY, widest_scratch_bytes(m));
+    if (rc != SCHULZE_OK) return rc;
+    return widest_in<E>(ctx, s, w, ldw, m, src, out, static_cast<char *>(ctx->ws[WS_VERIFY]), true);
+}
+
+// Both widest-path directions and the verdict, with the sweep state in base
+// (nullptr: the context's workspace).
+template <typename E>
+int verify_all(schulze_ctx *ctx, hipStream_t s, const E *w, int64_t ldw, const E *wt, int64_t ldwt, int32_t m,
+               int32_t cand, const float *score, E *p_from, E *p_to, int32_t *verdict, int32_t *tied, char *base) {
+    int rc;
+    if (base) {
+        if ((rc = widest_in<E>(ctx, s, w, ldw, m, cand, p_from, base, false)) != SCHULZE_OK) return rc;
+        if ((rc = widest_in<E>(ctx, s, wt, ldwt, m, cand, p_to, base, false)) != SCHULZE_OK) return rc;
+        k_verdict<E><<<dim3(1), dim3(256), 0, s>>>(p_from, p_to, m, cand, score, verdict, tied);
+        return launch_status();
+    }
+    if ((rc = widest<E>(ctx, s, w, ldw, m, cand, p_from)) != SCHULZE_OK) return rc;
+    if ((rc = widest<E>(ctx, s, wt, ldwt, m, cand, p_to)) != SCHULZE_OK) return rc;
+    SCHULZE_LAUNCH(ctx, K_VERDICT, s,
+                   k_verdict<E><<<dim3(1), dim3(256), 0, s>>>(p_from, p_to, m, cand, score, verdict, tied));
     return SCHULZE_OK;
 }
 
@@ -258,24 +330,30 @@ extern "C" int schulze_verify(schulze_ctx *ctx, void *stream, const void *w, int
     hipStream_t s = (hipStream_t)stream;
     if (dtype == SCHULZE_U16) {
         using E = uint16_t;
-        if ((rc = widest<E>(ctx, s, static_cast<const E *>(w), ldw, m, cand, static_cast<E *>(p_from))) != SCHULZE_OK)
-            return rc;
-        if ((rc = widest<E>(ctx, s, static_cast<const E *>(wt), ldwt, m, cand, static_cast<E *>(p_to))) != SCHULZE_OK)
-            return rc;
-        SCHULZE_LAUNCH(ctx, K_VERDICT, s,
-                       k_verdict<E><<<dim3(1), dim3(256), 0, s>>>(static_cast<const E *>(p_from),
-                                                                  static_cast<const E *>(p_to), m, cand, score,
-                                                                  verdict, tied));
-    } else {
-        using E = int32_t;
-        if ((rc = widest<E>(ctx, s, static_cast<const E *>(w), ldw, m, cand, static_cast<E *>(p_from))) != SCHULZE_OK)
-            return rc;
-        if ((rc = widest<E>(ctx, s, static_cast<const E *>(wt), ldwt, m, cand, static_cast<E *>(p_to))) != SCHULZE_OK)
-            return rc;
-        SCHULZE_LAUNCH(ctx, K_VERDICT, s,
-                       k_verdict<E><<<dim3(1), dim3(256), 0, s>>>(static_cast<const E *>(p_from),
-                                                                  static_cast<const E *>(p_to), m, cand, score,
-                                                                  verdict, tied));
+        return verify_all<E>(ctx, s, static_cast<const E *>(w), ldw, static_cast<const E *>(wt), ldwt, m, cand, score,
+                             static_cast<E *>(p_from), static_cast<E *>(p_to), verdict, tied, nullptr);
     }
-    return SCHULZE_OK;
+    using E = int32_t;
+    return verify_all<E>(ctx, s, static_cast<const E *>(w), ldw, static_cast<const E *>(wt), ldwt, m, cand, score,
+                         static_cast<E *>(p_from), static_cast<E *>(p_to), verdict, tied, nullptr);
+}
+
+extern "C" int schulze_verify_noalloc(schulze_ctx *ctx, void *stream, const void *w, int64_t ldw, const void *wt,
+                                      int64_t ldwt, int32_t m, int dtype, int32_t cand, const float *score,
+                                      void *p_from, void *p_to, int32_t *verdict, int32_t *tied) {
+    int rc = check_square(ctx, w, ldw, m, dtype);
+    if (rc != SCHULZE_OK) return rc;
+    if (!wt || ldwt < m || !p_from || !p_to || !verdict || cand < 0 || cand >= m) return SCHULZE_EINVAL;
+    if (widest_scratch_bytes(m) > VERIFY_SCRATCH_BYTES) return SCHULZE_EUNSUPPORTED;
+    if (!ctx->verify_scratch) return SCHULZE_EDEVICE;  // set when the context was created
+    char *base = static_cast<char *>(ctx->verify_scratch);
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == SCHULZE_U16) {
+        using E = uint16_t;
+        return verify_all<E>(ctx, s, static_cast<const E *>(w), ldw, static_cast<const E *>(wt), ldwt, m, cand, score,
+                             static_cast<E *>(p_from), static_cast<E *>(p_to), verdict, tied, base);
+    }
+    using E = int32_t;
+    return verify_all<E>(ctx, s, static_cast<const E *>(w), ldw, static_cast<const E *>(wt), ldwt, m, cand, score,
+                         static_cast<E *>(p_from), static_cast<E *>(p_to), verdict, tied, base);
 }
