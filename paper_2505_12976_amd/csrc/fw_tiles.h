@@ -123,20 +123,21 @@ __device__ inline void acc_product(Acc<E, B> &a, PA A, int64_t lda, PB Bm, int64
             for (int k = 0; k < KC; k += 4) {
                 int4 av[TM];
                 for (int ii = 0; ii < TM; ++ii) av[ii] = *reinterpret_cast<const int4 *>(&As[(ty * TM + ii) * LA + k]);
-#pragma unroll
-                for (int kp = 0; kp < 4; kp += 2) {
-                    E b0[TN], b1[TN];
+                // c = max3(max3(c, m0, m1), m2, m3) with mi = min(a_i, b_i): the
+                // four k of a step as two v_max3_i32 and four v_min_i32
+                E bk[4][TN];
+                for (int kp = 0; kp < 4; ++kp)
                     for (int jj = 0; jj < TN; jj += 4) {
-                        const int4 x0 = *reinterpret_cast<const int4 *>(&Bs[(k + kp) * LB + tx * TN + jj]);
-                        const int4 x1 = *reinterpret_cast<const int4 *>(&Bs[(k + kp + 1) * LB + tx * TN + jj]);
-                        b0[jj] = x0.x, b0[jj + 1] = x0.y, b0[jj + 2] = x0.z, b0[jj + 3] = x0.w;
-                        b1[jj] = x1.x, b1[jj + 1] = x1.y, b1[jj + 2] = x1.z, b1[jj + 3] = x1.w;
+                        const int4 x = *reinterpret_cast<const int4 *>(&Bs[(k + kp) * LB + tx * TN + jj]);
+                        bk[kp][jj] = x.x, bk[kp][jj + 1] = x.y, bk[kp][jj + 2] = x.z, bk[kp][jj + 3] = x.w;
                     }
-                    for (int ii = 0; ii < TM; ++ii) {
-                        const E a0 = kp == 0 ? av[ii].x : av[ii].z;
-                        const E a1 = kp == 0 ? av[ii].y : av[ii].w;
-                        for (int jj = 0; jj < TN; ++jj)
-                            a.c[ii][jj] = max(a.c[ii][jj], max(min(a0, b0[jj]), min(a1, b1[jj])));
+                for (int ii = 0; ii < TM; ++ii) {
+                    const E a0 = av[ii].x, a1 = av[ii].y, a2 = av[ii].z, a3 = av[ii].w;
+                    for (int jj = 0; jj < TN; ++jj) {
+                        const E m0 = min(a0, bk[0][jj]), m1 = min(a1, bk[1][jj]);
+                        const E m2 = min(a2, bk[2][jj]), m3 = min(a3, bk[3][jj]);
+                        const E c1 = max(max(a.c[ii][jj], m0), m1);
+                        a.c[ii][jj] = max(max(c1, m2), m3);
                     }
                 }
             }
@@ -163,7 +164,12 @@ __device__ inline void acc_product(Acc<E, B> &a, PA A, int64_t lda, PB Bm, int64
                         const uint32_t word = kk < 2 ? av[ii].x : av[ii].y;
                         const unsigned short av16 = (kk & 1) ? (unsigned short)(word >> 16) : (unsigned short)word;
                         const W aa = L::splat(av16);
-                        for (int jj = 0; jj < WN; ++jj) a.c[ii][jj] = L::relax(a.c[ii][jj], aa, bp[jj]);
+                        // all mins of the row before its maxes: a max right after the
+                        // min it reads needs a wait state when that min takes the high
+                        // half of its operand (the compiler inserts an s_nop there)
+                        W t[WN];
+                        for (int jj = 0; jj < WN; ++jj) t[jj] = __builtin_elementwise_min(aa, bp[jj]);
+                        for (int jj = 0; jj < WN; ++jj) a.c[ii][jj] = __builtin_elementwise_max(a.c[ii][jj], t[jj]);
                     }
                 }
             }
