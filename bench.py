@@ -138,6 +138,9 @@ def parse():
     ap.add_argument("--batch-elections", type=int, default=4096)
     ap.add_argument("--no-per-election", action="store_true",
                     help="batch workload: skip the pass of per-election calls (profiling runs)")
+    ap.add_argument("--learned-path-only", action="store_true",
+                    help="learned workload: time the learned path only, no full closures or label propagation "
+                         "(profiling runs)")
     ap.add_argument("--closure-schedule", choices=("auto", "phased"), default="auto")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, copy a 1 GiB buffer once (a known-size reference "
@@ -470,6 +473,10 @@ def bench_learned(args):
                 "achieved": ach / 1e9, "peak": HBM_BYTES / 1e9, "unit": "GB/s", "frac": ach / HBM_BYTES,
                 "traffic": measured_traffic("feature_rows", wl.name), "algorithmic_bytes": alg,
                 "work": "d read once, w and w^T written once: 3 x 4 m^2 bytes"}
+    if args.learned_path_only:
+        ctx.close()
+        return {"metric": "learned path only (profiling run)", "ms_learned": float(np.median(t_learned)) * 1e3,
+                "ms_count": t_count * 1e3, "kernels_learned": kern, "roofline": roof, "learned_stats": st}
     ctx.reset_timing()
     full()  # warm-up (workspace)
     t_full = []

@@ -38,7 +38,7 @@ constexpr int SEG_PAIRS = 32767;  // at most 65534 voters per exact segment
 constexpr int SEGC = SEG_PAIRS / VC;
 constexpr int SCATTER_CH = 8192;  // columns per LDS chunk of the scatters
 constexpr int LONG_CHUNK = 32;    // ballots per workgroup of the long-row scan
-constexpr int SHORT_PER_WAVE = 8; // ballots per wavefront of the short-row scan
+constexpr int SHORT_PER_WAVE = 8; // steps (groups of ballots) per wavefront of the short-row scan
 constexpr int NPART = 64;         // partial sums of the pair-scattering cost
 constexpr uint16_t UNSET = 0xFFFF;
 
@@ -199,32 +199,45 @@ __global__ __launch_bounds__(256) void k_scan_long_vec(const uint16_t *__restric
     record_ballots(meta, nf, lf, nt, lt);
 }
 
-// Short rows (L <= 64): one lane per entry, SHORT_PER_WAVE ballots per wave.
+// Short rows (L <= 64): a wavefront takes 64 / L ballots at once (at most
+// SHORT_BPW), one lane per entry, SHORT_PER_WAVE such steps with all their
+// loads issued first; a ballot's listed length is the first padding lane of
+// its group (a wavefront ballot).
+constexpr int SHORT_BPW = 4;
 __global__ __launch_bounds__(256) void k_scan_short(const void *__restrict__ ballots, int dtype32, int64_t n, int32_t L,
                                                     int32_t m, Meta meta, int32_t *err) {
-    constexpr int PER_WG = 4 * SHORT_PER_WAVE;
+    constexpr int PER_WG = 4 * SHORT_PER_WAVE * SHORT_BPW;
     __shared__ int32_t lf[PER_WG], lt[PER_WG];
     __shared__ int32_t nf, nt;
     if (threadIdx.x == 0) nf = nt = 0;
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int32_t bpw = min(SHORT_BPW, 64 / L);
+    const int32_t sub = lane / L, t = lane - sub * L;
+    const bool lane_ok = sub < bpw;
+    const uint64_t group_bits = (L == 64) ? ~0ull : ((1ull << L) - 1ull);
+    const int64_t v0 = ((int64_t)blockIdx.x * 4 + wave) * SHORT_PER_WAVE * bpw;
+    int32_t c[SHORT_PER_WAVE];
+    for (int q = 0; q < SHORT_PER_WAVE; ++q) {  // every load first
+        const int64_t v = v0 + (int64_t)q * bpw + sub;
+        c[q] = (lane_ok && v < n) ? read_id(ballots, dtype32, v * L + t) : -2;
+    }
     bool bad = false;
     unsigned long long k2 = 0;
     for (int q = 0; q < SHORT_PER_WAVE; ++q) {
-        const int64_t v = (int64_t)blockIdx.x * PER_WG + wave * SHORT_PER_WAVE + q;
-        if (v >= n) break;
-        const int64_t base = v * (int64_t)L;
-        const int32_t c = lane < L ? read_id(ballots, dtype32, base + lane) : -1;
-        const uint64_t pad = __ballot(c < 0);
-        const int k = pad ? (int)__builtin_ctzll(pad) : 64;  // lanes >= L count as padding
+        const int64_t v = v0 + (int64_t)q * bpw + sub;
+        const uint64_t pad = __ballot(c[q] < 0);  // -1 padding, -2 no ballot
+        const uint64_t mine = lane_ok ? (pad >> (sub * L)) & group_bits : group_bits;
+        const int k = mine ? (int)__builtin_ctzll(mine) : L;
+        const bool live = lane_ok && v < n;
         const bool trunc = k < m - 1;
-        if (lane < k) {
-            if (c >= m)
+        if (live && t < k) {
+            if (c[q] >= m)
                 bad = true;
-            else if (trunc)
-                meta.in_u[c] = 1;
+            else if (trunc && !meta.in_u[c[q]])  // a read first: frequent candidates are set once per cache
+                meta.in_u[c[q]] = 1;
         }
-        if (lane == 0) {
+        if (live && t == 0) {
             meta.len[v] = k;
             if (trunc) {
                 lt[atomicAdd(&nt, 1)] = (int32_t)v;
@@ -235,6 +248,7 @@ __global__ __launch_bounds__(256) void k_scan_short(const void *__restrict__ bal
         }
     }
     if (__ballot(bad) && lane == 0) set_device_error(err, SCHULZE_EBALLOT);
+    for (int off = 32; off >= 1; off >>= 1) k2 += __shfl_xor(k2, off);
     if (lane == 0 && k2) atomicAdd(&meta.k2[(blockIdx.x * 4 + wave) % NPART], k2);
     __syncthreads();
     record_ballots(meta, nf, lf, nt, lt);
@@ -291,7 +305,7 @@ __global__ __launch_bounds__(256) void k_route(int32_t m, Meta meta, int weighte
 }
 
 // ------------------------------------------------------------------ scatters
-// One workgroup per voter pair q: positions of slots 2q (low half) and
+// A workgroup per voter pair q (grid-stride over the pairs): positions of slots 2q (low half) and
 // 2q+1 (high half; 0 for the missing partner of an odd count), staged in
 // LDS in chunks of SCATTER_CH columns and written as rows of `pitch` words.
 // A ballot lists distinct candidates iff its entries leave exactly
@@ -304,8 +318,7 @@ __global__ __launch_bounds__(256) void k_scatter(const void *__restrict__ ballot
     __shared__ int32_t unset_cnt[2];
     const int32_t count = FULL ? meta.ctr[0] : meta.ctr[1];
     if (!FULL && meta.ctr[2] != MODE_DENSE_U) return;
-    const int64_t q = blockIdx.x;
-    if (2 * q >= count) return;
+    for (int64_t q = blockIdx.x; 2 * q < count; q += gridDim.x) {
     const int32_t pitch = FULL ? full_pitch : meta.ctr[4];
     const int32_t ncols = FULL ? m : meta.ctr[3];  // real columns: candidates or U
     const int32_t *srcs = FULL ? meta.full_src : meta.trunc_src;
@@ -315,6 +328,7 @@ __global__ __launch_bounds__(256) void k_scatter(const void *__restrict__ ballot
     // stores (rows and chunks in multiples of four words)
     const bool vec16 = !dtype32 && (L % 8) == 0 && (reinterpret_cast<uintptr_t>(ballots) % 16) == 0;
     const bool vec_out = (pitch % 4) == 0 && (reinterpret_cast<uintptr_t>(pos) % 16) == 0;
+    __syncthreads();  // the previous pair's counts have been read
     if (threadIdx.x < 2) unset_cnt[threadIdx.x] = 0;
     for (int32_t c0 = 0; c0 < pitch; c0 += SCATTER_CH) {
         const int32_t cn = min(SCATTER_CH, pitch - c0);
@@ -383,6 +397,7 @@ __global__ __launch_bounds__(256) void k_scatter(const void *__restrict__ ballot
             if (src[h] < 0) continue;
             if (unset_cnt[h] != ncols - meta.len[src[h]]) set_device_error(err, SCHULZE_EBALLOT);
         }
+    }
     }
 }
 
@@ -639,66 +654,115 @@ __global__ __launch_bounds__(256) void k_count_pairs(const void *__restrict__ ba
 
 // ------------------------------------------------------------------ bucketed pair counting
 // The same sums as k_count_pairs without its random device-wide atomics into
-// the m x m accumulator: the listed entries ("occurrences") of truncated
-// ballots are first bucketed by candidate (a counting sort: per-workgroup
-// histograms in LDS, offsets, placement), and then each candidate's row of
-// C^T is accumulated in LDS from the ballot prefixes ahead of its
-// occurrences and subtracted from the accumulator row at once.  A row with
-// more than OCC_CHUNK occurrences is split over several workgroups that add
-// their partial rows with atomics.
-constexpr int OCC_CHUNK = 2048;            // occurrences per accumulation item
-constexpr int32_t OCC_MAX_M = 32768;       // an LDS row of uint32 counts
+// the m x m accumulator.  The listed entries ("occurrences") of truncated
+// ballots are bucketed by candidate (a counting sort: per-workgroup
+// histograms in LDS over fixed ballot ranges, column prefixes, placement),
+// and then each candidate r's row of C^T (C[y][r] = weight of ballots
+// listing y before r) is accumulated in LDS from the ballot prefixes ahead
+// of its occurrences; d[r][y] = R_r - C[y][r] (plus any full-ranking
+// counts).  A candidate with at most OCC_CHUNK occurrences is one work item
+// that writes its row of d at once; a heavier one is split into items that
+// write their partial rows to a buffer, summed by the finish.  Nothing here
+// needs the m x m accumulator unless full rankings are counted as well.
+constexpr int OCC_CHUNK = 8192;            // occurrences per accumulation item (<= 65535: packed counts)
+constexpr int32_t OCC_MAX_M = 32768;       // an LDS row of counts
 constexpr int64_t OCC_MAX = (int64_t)1 << 27;  // occurrence buffer limit (entries)
+constexpr int OCC_FIN_COLS = 2048;         // columns per unit of the finish
 
 struct OccArgs {
     const void *ballots;
     int dtype32;
     int32_t L, m;
+    int64_t n;
+    int32_t tbits;        // occurrence word: ballot << tbits | position
+    int32_t row_vec;      // uint16 ids, even L, 4-byte aligned rows: rows read as 32-bit words
     const uint32_t *weight;
     Meta meta;
-    uint32_t *hist;      // G x m: per-workgroup counts, then their exclusive prefix over workgroups
-    uint32_t *row_start; // m + 1: occurrences per candidate, then the exclusive scan (total at [m])
-    uint32_t *item_start;// m + 1: accumulation items per candidate, then the exclusive scan
-    uint32_t *occ_v;     // ballot of each placed occurrence
-    uint16_t *occ_t;     // its position in the ballot
+    uint32_t *hist;       // G x m: per-workgroup counts, then their exclusive prefix over workgroups
+    uint32_t *row_start;  // m + 1: occurrences per candidate, then the exclusive scan
+    uint32_t *item_start; // m + 1: accumulation items per candidate, then the exclusive scan
+    uint32_t *part_start; // m + 1: partial rows per candidate (its items if more than one), then the scan
+    uint32_t *occ;        // placed occurrences
+    void *partial;        // partial rows, pitch ppitch elements (uint16 for unit weights, else uint32)
+    int64_t ppitch;
     uint32_t *acc;
     int64_t lda;
     uint32_t *rsum;
     int32_t *err;
 };
 
-// Truncated-ballot slots of workgroup g: [lo, hi).
-__device__ inline void occ_slots(const Meta &meta, int32_t &lo, int32_t &hi) {
-    const int64_t nt = meta.ctr[1];
-    lo = (int32_t)(nt * blockIdx.x / gridDim.x);
-    hi = (int32_t)(nt * (blockIdx.x + 1) / gridDim.x);
+// Eight consecutive values of a row of d: 16-byte stores when the row is
+// aligned for them and all eight columns exist, else one at a time.
+template <typename T>
+__device__ inline void store8(T *__restrict__ drow, int32_t y, int32_t m, bool vec, const uint32_t (&v)[8]) {
+    if (vec && y + 8 <= m) {
+        if constexpr (sizeof(T) == 4) {
+            reinterpret_cast<uint4 *>(drow + y)[0] = make_uint4(v[0], v[1], v[2], v[3]);
+            reinterpret_cast<uint4 *>(drow + y)[1] = make_uint4(v[4], v[5], v[6], v[7]);
+        } else {
+            reinterpret_cast<uint4 *>(drow + y)[0] =
+                make_uint4(v[0] | (v[1] << 16), v[2] | (v[3] << 16), v[4] | (v[5] << 16), v[6] | (v[7] << 16));
+        }
+        return;
+    }
+    for (int u = 0; u < 8 && y + u < m; ++u) drow[y + u] = (T)v[u];
+}
+
+// Ballots of bucketing workgroup g: [v0, v1) (the same in both passes).
+__device__ inline void occ_range(int64_t n, int64_t &v0, int64_t &v1) {
+    v0 = n * blockIdx.x / gridDim.x;
+    v1 = n * (blockIdx.x + 1) / gridDim.x;
 }
 
 // PLACE = false: hist[g][c] = occurrences of c in workgroup g's ballots.
-// PLACE = true:  write them to occ_v / occ_t at row_start[c] + hist[g][c] + k.
-// One wavefront per ballot, one lane per listed entry.
+// PLACE = true:  write them to occ[] at row_start[c] + hist[g][c] + k.
+// Rows of L <= 64 entries: a wavefront takes 64 / L ballots at once, one
+// lane per entry; a ballot ends at its first padding entry (a wavefront
+// ballot of the padding lanes gives it), and full rankings (m - 1 or more
+// listed) are left to the dense count.  Longer rows: one ballot per
+// wavefront, 64 entries at a time.
 template <int MAXM, bool PLACE>
 __global__ __launch_bounds__(256) void k_occ_bucket(OccArgs a) {
     __shared__ uint32_t cnt[MAXM];
     if (a.meta.ctr[2] != MODE_SPARSE) return;
-    const int32_t m = a.m;
+    const int32_t m = a.m, L = a.L;
     const int64_t hrow = (int64_t)blockIdx.x * m;
     for (int32_t c = threadIdx.x; c < m; c += 256) cnt[c] = PLACE ? a.row_start[c] + a.hist[hrow + c] : 0u;
     __syncthreads();
-    int32_t lo, hi;
-    occ_slots(a.meta, lo, hi);
-    const int lane = threadIdx.x & 63;
-    for (int32_t slot = lo + (threadIdx.x >> 6); slot < hi; slot += 4) {
-        const int32_t v = a.meta.trunc_src[slot];
-        const int32_t k = a.meta.len[v];
-        const int64_t base = (int64_t)v * a.L;
-        for (int t = lane; t < k; t += 64) {
-            const int32_t c = read_id(a.ballots, a.dtype32, base + t);
-            if (c < 0 || c >= m) continue;  // reported by the scan
-            const uint32_t q = atomicAdd(&cnt[c], 1u);
-            if (PLACE) {
-                a.occ_v[q] = (uint32_t)v;
-                a.occ_t[q] = (uint16_t)t;
+    int64_t v0, v1;
+    occ_range(a.n, v0, v1);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    auto put = [&](int64_t v, int32_t t, int32_t c) {
+        const uint32_t q = atomicAdd(&cnt[c], 1u);
+        if (PLACE) a.occ[q] = ((uint32_t)v << a.tbits) | (uint32_t)t;
+    };
+    if (L <= 64) {
+        const int32_t bpw = 64 / L;  // ballots per wavefront step
+        const int32_t sub = lane / L, t = lane - sub * L;
+        const bool lane_ok = sub < bpw;
+        const uint64_t lane_bits = (L == 64) ? ~0ull : ((1ull << L) - 1ull);
+        constexpr int U = 4;  // steps in flight
+        for (int64_t vb = v0 + (int64_t)wave * bpw; vb < v1; vb += (int64_t)4 * bpw * U) {
+            int32_t c[U];
+            int64_t vv[U];
+            for (int u = 0; u < U; ++u) {
+                vv[u] = vb + (int64_t)4 * bpw * u + sub;
+                c[u] = (lane_ok && vv[u] < v1) ? read_id(a.ballots, a.dtype32, vv[u] * L + t) : -2;
+            }
+            for (int u = 0; u < U; ++u) {
+                const uint64_t pad = __ballot(c[u] < 0);  // -1 padding, -2 no ballot
+                const uint64_t mine = lane_ok ? (pad >> (sub * L)) & lane_bits : lane_bits;
+                const int32_t k = mine ? (int32_t)__builtin_ctzll(mine) : L;
+                if (c[u] >= 0 && c[u] < m && t < k && k < m - 1) put(vv[u], t, c[u]);
+            }
+        }
+    } else {
+        for (int64_t v = v0 + wave; v < v1; v += 4) {
+            const int32_t k = a.meta.len[v];
+            if (k >= m - 1) continue;
+            for (int32_t t = lane; t < k; t += 64) {
+                const int32_t c = read_id(a.ballots, a.dtype32, v * L + t);
+                if (c >= 0 && c < m) put(v, t, c);
             }
         }
     }
@@ -708,72 +772,113 @@ __global__ __launch_bounds__(256) void k_occ_bucket(OccArgs a) {
     }
 }
 
-// Per candidate c: total occurrences (row_start[c]) and the exclusive prefix
-// of hist[.][c] over workgroups.
+// 64 candidates per workgroup, the G histogram rows split over 4 thread
+// groups: hist[g][c] becomes its exclusive prefix over g; per candidate c,
+// row_start[c] = occurrences, item_start[c] = accumulation items,
+// part_start[c] = partial rows (its items when there are two or more).
 __global__ __launch_bounds__(256) void k_occ_columns(OccArgs a, int32_t G) {
+    __shared__ uint32_t part[4][64];
     if (a.meta.ctr[2] != MODE_SPARSE) return;
-    const int32_t c = blockIdx.x * 256 + threadIdx.x;
+    const int32_t c = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int grp = threadIdx.x >> 6;
+    const int32_t g0 = G * grp / 4, g1 = G * (grp + 1) / 4;
+    uint32_t sum = 0;
+    if (c < a.m)
+        for (int32_t g = g0; g < g1; ++g) sum += a.hist[(int64_t)g * a.m + c];
+    part[grp][threadIdx.x & 63] = sum;
+    __syncthreads();
     if (c >= a.m) return;
     uint32_t run = 0;
-    for (int32_t g = 0; g < G; ++g) {
+    for (int q = 0; q < grp; ++q) run += part[q][threadIdx.x & 63];
+    for (int32_t g = g0; g < g1; ++g) {
         const uint32_t h = a.hist[(int64_t)g * a.m + c];
         a.hist[(int64_t)g * a.m + c] = run;
         run += h;
     }
-    a.row_start[c] = run;
-    a.item_start[c] = (run + OCC_CHUNK - 1) / OCC_CHUNK;
+    if (grp == 3) {
+        const uint32_t items = (run + OCC_CHUNK - 1) / OCC_CHUNK;
+        a.row_start[c] = run;
+        a.item_start[c] = items;
+        a.part_start[c] = items > 1 ? items : 0u;
+    }
 }
 
-// One workgroup: exclusive scans of the occurrence totals and item counts.
-__global__ __launch_bounds__(256) void k_occ_scan(OccArgs a) {
-    __shared__ uint32_t part[2][256];
+// One workgroup of 1024 threads: exclusive scans of the three per-candidate
+// counts, totals at [m].  A thread takes `per` consecutive candidates, read
+// and written as 16-byte vectors when per is a multiple of 4 (at most
+// SCAN_VEC of them per array in registers), else one at a time.
+constexpr int SCAN_VEC = 8;
+__global__ __launch_bounds__(1024) void k_occ_scan(OccArgs a) {
+    __shared__ uint32_t part[3][1024];
     if (a.meta.ctr[2] != MODE_SPARSE) return;
     const int32_t m = a.m;
-    const int32_t per = (m + 255) / 256;
-    const int32_t c0 = threadIdx.x * per, c1 = min(m, c0 + per);
-    uint32_t so = 0, si = 0;
-    for (int32_t c = c0; c < c1; ++c) {
-        so += a.row_start[c];
-        si += a.item_start[c];
+    const int32_t per = (m + 1023) / 1024;
+    const int32_t c0 = min(m, (int32_t)threadIdx.x * per), c1 = min(m, c0 + per);
+    uint32_t *arr[3] = {a.row_start, a.item_start, a.part_start};
+    uint32_t s[3] = {0u, 0u, 0u};
+    const bool vec = per % 4 == 0 && per / 4 <= SCAN_VEC && c1 - c0 == per;
+    uint4 v[3][SCAN_VEC];
+    if (vec) {
+        for (int q = 0; q < 3; ++q)
+            for (int k = 0; k < SCAN_VEC; ++k)
+                if (k < per / 4) v[q][k] = reinterpret_cast<const uint4 *>(arr[q] + c0)[k];
+        for (int q = 0; q < 3; ++q)
+            for (int k = 0; k < SCAN_VEC; ++k)
+                if (k < per / 4) s[q] += v[q][k].x + v[q][k].y + v[q][k].z + v[q][k].w;
+    } else {
+        for (int q = 0; q < 3; ++q)
+            for (int32_t c = c0; c < c1; ++c) s[q] += arr[q][c];
     }
-    part[0][threadIdx.x] = so;
-    part[1][threadIdx.x] = si;
+    for (int q = 0; q < 3; ++q) part[q][threadIdx.x] = s[q];
     __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        const uint32_t ao = (int)threadIdx.x >= off ? part[0][threadIdx.x - off] : 0u;
-        const uint32_t ai = (int)threadIdx.x >= off ? part[1][threadIdx.x - off] : 0u;
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t add[3];
+        for (int q = 0; q < 3; ++q) add[q] = (int)threadIdx.x >= off ? part[q][threadIdx.x - off] : 0u;
         __syncthreads();
-        part[0][threadIdx.x] += ao;
-        part[1][threadIdx.x] += ai;
+        for (int q = 0; q < 3; ++q) part[q][threadIdx.x] += add[q];
         __syncthreads();
     }
-    uint32_t ro = part[0][threadIdx.x] - so, ri = part[1][threadIdx.x] - si;
-    for (int32_t c = c0; c < c1; ++c) {
-        const uint32_t o = a.row_start[c], it = a.item_start[c];
-        a.row_start[c] = ro;
-        a.item_start[c] = ri;
-        ro += o;
-        ri += it;
-    }
-    if (threadIdx.x == 255) {
-        a.row_start[m] = part[0][255];
-        a.item_start[m] = part[1][255];
+    for (int q = 0; q < 3; ++q) {
+        uint32_t run = part[q][threadIdx.x] - s[q];
+        if (vec) {
+            for (int k = 0; k < SCAN_VEC; ++k) {
+                if (k >= per / 4) break;
+                uint4 o;
+                o.x = run, run += v[q][k].x;
+                o.y = run, run += v[q][k].y;
+                o.z = run, run += v[q][k].z;
+                o.w = run, run += v[q][k].w;
+                reinterpret_cast<uint4 *>(arr[q] + c0)[k] = o;
+            }
+        } else {
+            for (int32_t c = c0; c < c1; ++c) {
+                const uint32_t x = arr[q][c];
+                arr[q][c] = run;
+                run += x;
+            }
+        }
+        if (threadIdx.x == 1023) arr[q][m] = part[q][1023];
     }
 }
 
-// Accumulation item `blockIdx.x`: a chunk of one candidate's occurrences.
-// For an occurrence of candidate r at position t of ballot v, every id ahead
-// of it gains the voter's weight in row r of C^T (acc[r][.] -= w), and r
-// gains it in R (rsum[r]).  PACKED (unit weights): two 16-bit counts per LDS
-// word -- an item adds at most OCC_CHUNK to a column, so halves never carry
-// -- which halves the LDS row and doubles the resident workgroups.
-template <int MAXM, bool PACKED, typename T>
+// Accumulation item `blockIdx.x`: a chunk of one candidate r's occurrences.
+// For an occurrence of r at position t of ballot v, every id ahead of it
+// gains the voter's weight in the LDS row (C[id][r]), and r gains it in R.
+// PACKED (unit weights): two 16-bit counts per LDS word (an item adds at
+// most OCC_CHUNK to a column).  A thread takes its occurrences B at a time
+// and, for rows read as 32-bit words, issues every row load of the batch
+// before the first LDS update, so that many loads are in flight.  The only
+// item of a row writes the row of d (d[r][y] = base + R - C[y][r], base =
+// full-ranking counts in acc or 0); an item of a heavier row writes its
+// counts to its partial row and adds its part of R to rsum[r].
+template <int MAXM, bool PACKED, typename T, int WMAX>
 __global__ __launch_bounds__(256) void k_occ_accumulate(OccArgs a, T *__restrict__ d, int64_t ldd, uint32_t limit,
-                                                        uint8_t *__restrict__ row_done, int acc_zero) {
+                                                        uint8_t *__restrict__ row_done, int acc_zero, int dvec) {
     constexpr int WORDS = PACKED ? MAXM / 2 : MAXM;
+    constexpr int B = WMAX <= 16 ? 2 : 1;  // occurrences per batch
     __shared__ __attribute__((aligned(16))) uint32_t row[WORDS];
     __shared__ uint32_t wsum;
-    __shared__ int32_t sh_r, sh_nitems;
+    __shared__ int32_t sh_r, sh_nitems, sh_k;
     __shared__ uint32_t sh_b, sh_e;
     if (a.meta.ctr[2] != MODE_SPARSE) return;
     const int32_t m = a.m;
@@ -789,6 +894,7 @@ __global__ __launch_bounds__(256) void k_occ_accumulate(OccArgs a, T *__restrict
         const uint32_t k = item - a.item_start[lo];
         const uint32_t b = a.row_start[lo] + k * OCC_CHUNK;
         sh_r = lo;
+        sh_k = (int32_t)k;
         sh_nitems = (int32_t)(a.item_start[lo + 1] - a.item_start[lo]);
         sh_b = b;
         sh_e = min(a.row_start[lo + 1], b + (uint32_t)OCC_CHUNK);
@@ -800,71 +906,173 @@ __global__ __launch_bounds__(256) void k_occ_accumulate(OccArgs a, T *__restrict
     for (int32_t c = threadIdx.x; c < words4; c += 256) row4[c] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
     const int32_t r = sh_r;
+    const uint32_t tmask = (1u << a.tbits) - 1u;
     uint32_t wpart = 0;
     bool dup = false;
-    for (uint32_t q = sh_b + threadIdx.x; q < sh_e; q += 256) {
-        const uint32_t v = a.occ_v[q];
-        const int32_t t = a.occ_t[q];
-        const uint32_t w = PACKED ? 1u : (a.weight ? a.weight[v] : 1u);
-        wpart += w;
-        if (w == 0) continue;
-        const int64_t base = (int64_t)v * a.L;
-        for (int32_t i0 = 0; i0 < t; i0 += 8) {  // eight ids in flight
-            int32_t id[8];
-            for (int u = 0; u < 8; ++u) id[u] = i0 + u < t ? read_id(a.ballots, a.dtype32, base + i0 + u) : -1;
-            for (int u = 0; u < 8; ++u) {
-                if (id[u] == r) dup = true;
-                if (id[u] < 0 || id[u] >= m) continue;
-                if (PACKED)
-                    atomicAdd(&row[id[u] >> 1], 1u << ((id[u] & 1) * 16));
-                else
-                    atomicAdd(&row[id[u]], w);
+    auto add = [&](int32_t id, uint32_t w) {
+        if (id == r) dup = true;
+        if (id < 0 || id >= m) return;
+        if (PACKED)
+            atomicAdd(&row[id >> 1], 1u << ((id & 1) * 16));
+        else
+            atomicAdd(&row[id], w);
+    };
+    constexpr int WN = WMAX > 0 ? WMAX : 1;
+    if (WMAX > 0 && a.row_vec) {
+        // uint16 ids, rows of even length read as 32-bit words (two ids each)
+        const uint32_t *words32 = static_cast<const uint32_t *>(a.ballots);
+        const int64_t wrow = a.L / 2;
+        for (uint32_t q0 = sh_b + threadIdx.x; q0 < sh_e; q0 += 256 * B) {
+            uint32_t ov[B];
+            for (int u = 0; u < B; ++u) ov[u] = q0 + 256 * u < sh_e ? a.occ[q0 + 256 * u] : 0u;
+            uint32_t wd[B][WN];
+            int32_t tt[B];
+            uint32_t ww[B];
+            for (int u = 0; u < B; ++u) {
+                const bool ok = q0 + 256 * u < sh_e;
+                const int64_t v = ov[u] >> a.tbits;
+                tt[u] = ok ? (int32_t)(ov[u] & tmask) : 0;
+                ww[u] = ok ? (PACKED ? 1u : (a.weight ? a.weight[v] : 1u)) : 0u;
+                const int32_t nw = (tt[u] + 1) / 2;
+                const uint32_t *rw = words32 + v * wrow;
+                for (int j = 0; j < WN; ++j) wd[u][j] = j < nw ? rw[j] : 0xFFFFFFFFu;
+            }
+            for (int u = 0; u < B; ++u) {
+                wpart += ww[u];
+                if (ww[u] == 0) continue;
+                for (int j = 0; j < WN; ++j) {
+                    if (2 * j >= tt[u]) break;
+                    const uint32_t x = wd[u][j];
+                    add((int32_t)(x & 0xFFFFu), ww[u]);
+                    if (2 * j + 1 < tt[u]) add((int32_t)(x >> 16), ww[u]);
+                }
+            }
+        }
+    } else {
+        for (uint32_t q = sh_b + threadIdx.x; q < sh_e; q += 256) {
+            const uint32_t ovq = a.occ[q];
+            const int64_t v = ovq >> a.tbits;
+            const int32_t t = (int32_t)(ovq & tmask);
+            const uint32_t w = PACKED ? 1u : (a.weight ? a.weight[v] : 1u);
+            wpart += w;
+            if (w == 0) continue;
+            const int64_t base = v * a.L;
+            for (int32_t i0 = 0; i0 < t; i0 += 8) {  // eight ids in flight
+                int32_t id[8];
+                for (int u = 0; u < 8; ++u) id[u] = i0 + u < t ? read_id(a.ballots, a.dtype32, base + i0 + u) : -1;
+                for (int u = 0; u < 8; ++u)
+                    if (i0 + u < t) add(id[u], w);
             }
         }
     }
     if (wpart) atomicAdd(&wsum, wpart);
     if (__ballot(dup) && (threadIdx.x & 63) == 0) set_device_error(a.err, SCHULZE_EBALLOT);
     __syncthreads();
-    uint32_t *arow = a.acc + (int64_t)r * a.lda;
     if (sh_nitems == 1) {
-        // the row's only item: finish it here, d[r][y] = acc[r][y] - C[y][r] + R[r]
-        // (acc holds the counts of full rankings, or nothing), and skip it in k_count_finish
+        // the row's only item: d[r][y] = base + R - C[y][r]; the finish skips the row
         const uint32_t R = wsum;
+        const uint32_t *arow = a.acc + (int64_t)r * a.lda;
         bool over = false;
         T *drow = d + (int64_t)r * ldd;
-        for (int32_t y = threadIdx.x; y < m; y += 256) {
-            const uint32_t cnt = PACKED ? (row[y >> 1] >> ((y & 1) * 16)) & 0xFFFFu : row[y];
-            uint32_t v = 0u;
-            if (y != r) v = (acc_zero ? 0u : arow[y]) - cnt + R;
-            if (v > limit) {
-                over = true;
-                v = limit;
+        for (int32_t y = 8 * threadIdx.x; y < m; y += 8 * 256) {  // eight columns per thread and step
+            uint32_t v[8];
+            for (int e = 0; e < 8; ++e) {
+                const int32_t yy = y + e;
+                v[e] = 0u;
+                if (yy >= m || yy == r) continue;
+                const uint32_t cnt = PACKED ? (row[yy >> 1] >> ((yy & 1) * 16)) & 0xFFFFu : row[yy];
+                v[e] = (acc_zero ? 0u : arow[yy]) - cnt + R;
+                if (v[e] > limit) {
+                    over = true;
+                    v[e] = limit;
+                }
             }
-            drow[y] = (T)v;
+            store8<T>(drow, y, m, dvec != 0, v);
         }
-        // reported by k_count_finish, after every ballot error of this launch
+        // reported by the finish, after every ballot error of this launch
         if (over) row_done[m] = 1;
         if (threadIdx.x == 0) row_done[r] = 1;
         return;
     }
-    auto flush = [&](int32_t c, uint32_t x) { atomicSub(&arow[c], x); };
-    for (int32_t c4 = threadIdx.x; c4 < words4; c4 += 256) {
-        const uint4 q = row4[c4];
-        if ((q.x | q.y | q.z | q.w) == 0u) continue;
-        const uint32_t wv[4] = {q.x, q.y, q.z, q.w};
-        for (int u = 0; u < 4; ++u) {
-            if (!wv[u]) continue;
-            const int32_t wi = 4 * c4 + u;
-            if (PACKED) {
-                const int32_t c = 2 * wi;
-                if ((wv[u] & 0xFFFFu) && c < m) flush(c, wv[u] & 0xFFFFu);
-                if ((wv[u] >> 16) && c + 1 < m) flush(c + 1, wv[u] >> 16);
-            } else if (wi < m) {
-                flush(wi, wv[u]);
+    // an item of a heavier row: its partial row (same element layout as the LDS row)
+    uint4 *prow = reinterpret_cast<uint4 *>(static_cast<uint32_t *>(a.partial) +
+                                            (int64_t)(a.part_start[r] + sh_k) * (a.ppitch * (PACKED ? 1 : 2) / 2));
+    for (int32_t c = threadIdx.x; c < words4; c += 256) prow[c] = row4[c];
+    if (threadIdx.x == 0 && wsum) atomicAdd(&a.rsum[r], wsum);
+}
+
+// Rows the accumulation items did not finish: candidates without
+// occurrences (d[r][y] = base) and heavier candidates (d[r][y] = base + R_r
+// - sum of their partial rows).  Persistent: units (row, block of
+// OCC_FIN_COLS columns) dealt to the workgroups in turn, rows already done
+// skipped; a thread takes eight consecutive columns (one 16-byte read per
+// partial row of unit weights), four partial rows in flight.  Also reports
+// an overflow found by the accumulation.
+template <typename T, bool PACKED>
+__global__ __launch_bounds__(256) void k_occ_finish(OccArgs a, T *__restrict__ d, int64_t ldd, uint32_t limit,
+                                                    const uint8_t *__restrict__ row_done, int acc_zero, int dvec) {
+    static_assert(OCC_FIN_COLS == 8 * 256, "a thread takes eight columns");
+    if (a.meta.ctr[2] != MODE_SPARSE) return;
+    const int32_t m = a.m;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && row_done[m]) set_device_error(a.err, SCHULZE_ERANGE);
+    const int32_t cb = (m + OCC_FIN_COLS - 1) / OCC_FIN_COLS;
+    const bool avec = (a.lda % 4) == 0;  // rows of acc 16-byte aligned
+    bool over = false;
+    for (int64_t u = blockIdx.x; u < (int64_t)m * cb; u += gridDim.x) {
+        const int32_t r = (int32_t)(u / cb);
+        if (row_done[r]) continue;
+        const int32_t y = (int32_t)(u % cb) * OCC_FIN_COLS + 8 * threadIdx.x;
+        if (y >= m) continue;
+        const uint32_t p0 = a.part_start[r], np = a.part_start[r + 1] - p0;
+        const uint32_t R = np ? a.rsum[r] : 0u;
+        uint32_t c[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+        // partial rows hold round_up(m, 8) columns: eight at y are always there
+        auto add_row = [&](uint32_t k) {
+            const int64_t off = (int64_t)(p0 + k) * a.ppitch + y;
+            if constexpr (PACKED) {
+                const uint4 x = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(a.partial) + off);
+                const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+                for (int e = 0; e < 4; ++e) {
+                    c[2 * e] += w[e] & 0xFFFFu;
+                    c[2 * e + 1] += w[e] >> 16;
+                }
+            } else {
+                const uint4 *q = reinterpret_cast<const uint4 *>(static_cast<const uint32_t *>(a.partial) + off);
+                const uint4 x0 = q[0], x1 = q[1];
+                c[0] += x0.x, c[1] += x0.y, c[2] += x0.z, c[3] += x0.w;
+                c[4] += x1.x, c[5] += x1.y, c[6] += x1.z, c[7] += x1.w;
+            }
+        };
+        uint32_t k = 0;
+        for (; k + 4 <= np; k += 4) {
+            add_row(k);
+            add_row(k + 1);
+            add_row(k + 2);
+            add_row(k + 3);
+        }
+        for (; k < np; ++k) add_row(k);
+        uint32_t base[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+        if (!acc_zero) {
+            const uint32_t *arow = a.acc + (int64_t)r * a.lda;
+            if (avec && y + 8 <= m) {
+                const uint4 b0 = *reinterpret_cast<const uint4 *>(arow + y), b1 = *reinterpret_cast<const uint4 *>(arow + y + 4);
+                base[0] = b0.x, base[1] = b0.y, base[2] = b0.z, base[3] = b0.w;
+                base[4] = b1.x, base[5] = b1.y, base[6] = b1.z, base[7] = b1.w;
+            } else {
+                for (int e = 0; e < 8 && y + e < m; ++e) base[e] = arow[y + e];
             }
         }
+        uint32_t v[8];
+        for (int e = 0; e < 8; ++e) {
+            v[e] = y + e == r ? 0u : base[e] - c[e] + R;
+            if (v[e] > limit) {
+                over = true;
+                v[e] = limit;
+            }
+        }
+        store8<T>(d + (int64_t)r * ldd, y, m, dvec != 0, v);
     }
-    if (threadIdx.x == 0 && wsum) atomicAdd(&a.rsum[r], wsum);
+    if (over) set_device_error(a.err, SCHULZE_ERANGE);
 }
 
 // ------------------------------------------------------------------ weighted full rankings
@@ -896,14 +1104,10 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_count_finish(const uint32_t *__restrict__ acc, int64_t lda,
                                                       const uint32_t *__restrict__ rsum, Meta meta, int32_t m,
                                                       T *__restrict__ d, int64_t ldd, uint32_t limit, int32_t *err,
-                                                      const uint8_t *__restrict__ row_done) {
-    // one workgroup per row x
+                                                      int bucketed) {
+    // one workgroup per row x; the bucketed route writes its own rows
     const int32_t x = blockIdx.x;
-    if (row_done && meta.ctr[2] == MODE_SPARSE) {
-        // rows written by the bucketed count; row_done[m]: one of them overflowed
-        if (x == 0 && threadIdx.x == 0 && row_done[m]) set_device_error(err, SCHULZE_ERANGE);
-        if (row_done[x]) return;
-    }
+    if (bucketed && meta.ctr[2] == MODE_SPARSE) return;
     const bool dense_u = meta.ctr[2] == MODE_DENSE_U;
     const uint32_t rx = rsum[x];
     const bool in_x = dense_u && meta.in_u[x];
@@ -952,6 +1156,18 @@ __global__ __launch_bounds__(256) void k_weight_total(const uint32_t *__restrict
     }
 }
 
+// Zero the m x m accumulator, unless skip_bucketed and the device chose the
+// bucketed route (which then does not read it).
+__global__ __launch_bounds__(256) void k_fill_acc(uint32_t *__restrict__ p, int64_t words, Meta meta,
+                                                  int skip_bucketed) {
+    if (skip_bucketed && meta.ctr[2] == MODE_SPARSE) return;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x, stride = (int64_t)gridDim.x * 256;
+    uint4 *p4 = reinterpret_cast<uint4 *>(p);  // workspace: 16-byte aligned
+    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+    for (int64_t j = i; j < words / 4; j += stride) p4[j] = z;
+    for (int64_t j = words / 4 * 4 + i; j < words; j += stride) p[j] = 0u;
+}
+
 struct MetaLayout {
     size_t ctr, k2, len, full_src, trunc_src, in_u, ulist, umap, total;
     MetaLayout(int64_t n, int32_t m) {
@@ -975,50 +1191,83 @@ struct MetaLayout {
 
 // Byte layout of WS_OCC for G bucketing workgroups, m candidates and at
 // most cap occurrences.
+// Partial rows: every item of a candidate with two or more items has one,
+// and such a candidate has more than OCC_CHUNK occurrences, so there are at
+// most 2 cap / OCC_CHUNK of them.
 struct OccLayout {
-    size_t hist, row_start, item_start, occ_v, occ_t, row_done, total;
-    OccLayout(int64_t G, int32_t m, int64_t cap) {
+    size_t hist, row_start, item_start, part_start, occ, partial, row_done, total;
+    int64_t ppitch, max_parts;
+    OccLayout(int64_t G, int32_t m, int64_t cap, size_t partial_elem) {
         size_t o = 0;
         auto take = [&](size_t bytes) {
             size_t at = o;
             o += (bytes + 255) / 256 * 256;
             return at;
         };
+        ppitch = round_up(m, 8);
+        max_parts = cap > 0 ? 2 * ceil_div(cap, OCC_CHUNK) + 1 : 0;
         hist = take(sizeof(uint32_t) * (size_t)G * m);
         row_start = take(sizeof(uint32_t) * ((size_t)m + 1));
         item_start = take(sizeof(uint32_t) * ((size_t)m + 1));
-        occ_v = take(sizeof(uint32_t) * (size_t)cap);
-        occ_t = take(sizeof(uint16_t) * (size_t)cap);
+        part_start = take(sizeof(uint32_t) * ((size_t)m + 1));
+        occ = take(sizeof(uint32_t) * (size_t)cap);
+        partial = take(partial_elem * (size_t)max_parts * (size_t)ppitch);
         row_done = take((size_t)m + 1);  // one flag per row, then the overflow flag
         total = o;
     }
 };
 
-// The accumulation launch for the counter type T of d: packed 16-bit LDS
-// counts for unit weights, 32-bit ones otherwise; the LDS row fits m.
+// The accumulation and finish launches for the counter type T of d: packed
+// 16-bit LDS counts for unit weights, 32-bit ones otherwise; the LDS row fits
+// m; rows read as 32-bit words when the layout allows (WMAX words at most).
+template <typename T, int MAXM, bool PACKED>
+int occ_accumulate_m(schulze_ctx *ctx, hipStream_t s, const OccArgs &oa, dim3 grid, T *d, int64_t ldd,
+                     uint32_t limit, uint8_t *row_done, int az, int dvec) {
+    const dim3 b(256);
+    if constexpr (PACKED) {
+        if (oa.row_vec && oa.L <= 32) {
+            SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
+                           (k_occ_accumulate<MAXM, PACKED, T, 16><<<grid, b, 0, s>>>(oa, d, ldd, limit, row_done, az, dvec)));
+            return SCHULZE_OK;
+        }
+        if (oa.row_vec && oa.L <= 64) {
+            SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
+                           (k_occ_accumulate<MAXM, PACKED, T, 32><<<grid, b, 0, s>>>(oa, d, ldd, limit, row_done, az, dvec)));
+            return SCHULZE_OK;
+        }
+    }
+    SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
+                   (k_occ_accumulate<MAXM, PACKED, T, 0><<<grid, b, 0, s>>>(oa, d, ldd, limit, row_done, az, dvec)));
+    return SCHULZE_OK;
+}
+
 template <typename T>
 int occ_accumulate(schulze_ctx *ctx, hipStream_t s, const OccArgs &oa, dim3 grid, int32_t m, bool weighted, T *d,
                    int64_t ldd, uint32_t limit, uint8_t *row_done, bool acc_zero) {
-    const dim3 b(256);
     const int az = acc_zero ? 1 : 0;
-    if (!weighted && m <= OCC_MAX_M / 2) {
-        SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
-                       (k_occ_accumulate<OCC_MAX_M / 2, true, T><<<grid, b, 0, s>>>(oa, d, ldd, limit, row_done, az)));
-    } else if (!weighted) {
-        SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
-                       (k_occ_accumulate<OCC_MAX_M, true, T><<<grid, b, 0, s>>>(oa, d, ldd, limit, row_done, az)));
-    } else if (m <= OCC_MAX_M / 2) {
-        SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
-                       (k_occ_accumulate<OCC_MAX_M / 2, false, T><<<grid, b, 0, s>>>(oa, d, ldd, limit, row_done, az)));
+    // rows of d 16-byte aligned: eight columns per 16-byte store (uint16) or two (int32)
+    const int dvec = reinterpret_cast<uintptr_t>(d) % 16 == 0 && (ldd * (int64_t)sizeof(T)) % 16 == 0;
+    int rc;
+    if (!weighted && m <= OCC_MAX_M / 2)
+        rc = occ_accumulate_m<T, OCC_MAX_M / 2, true>(ctx, s, oa, grid, d, ldd, limit, row_done, az, dvec);
+    else if (!weighted)
+        rc = occ_accumulate_m<T, OCC_MAX_M, true>(ctx, s, oa, grid, d, ldd, limit, row_done, az, dvec);
+    else if (m <= OCC_MAX_M / 2)
+        rc = occ_accumulate_m<T, OCC_MAX_M / 2, false>(ctx, s, oa, grid, d, ldd, limit, row_done, az, dvec);
+    else
+        rc = occ_accumulate_m<T, OCC_MAX_M, false>(ctx, s, oa, grid, d, ldd, limit, row_done, az, dvec);
+    if (rc != SCHULZE_OK) return rc;
+    const dim3 fg((unsigned)(ctx->num_cus * 4));
+    if (weighted) {
+        SCHULZE_LAUNCH(ctx, K_COUNT_FINISH, s,
+                       (k_occ_finish<T, false><<<fg, dim3(256), 0, s>>>(oa, d, ldd, limit, row_done, az, dvec)));
     } else {
-        SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
-                       (k_occ_accumulate<OCC_MAX_M, false, T><<<grid, b, 0, s>>>(oa, d, ldd, limit, row_done, az)));
+        SCHULZE_LAUNCH(ctx, K_COUNT_FINISH, s,
+                       (k_occ_finish<T, true><<<fg, dim3(256), 0, s>>>(oa, d, ldd, limit, row_done, az, dvec)));
     }
     return SCHULZE_OK;
 }
 
-// Truncated positions in U space are reserved up to this many bytes; beyond
-// it the route decision falls back to pair scattering.
 constexpr size_t TRUNC_POS_CAP = (size_t)1 << 30;
 
 }  // namespace
@@ -1058,7 +1307,7 @@ extern "C" int schulze_pairwise(schulze_ctx *ctx, void *stream, const void *ball
     const int64_t occ_cap = n * (int64_t)L;
     const bool occ_ok = n > 0 && m <= OCC_MAX_M && occ_cap <= OCC_MAX && !ctx->legacy_pairs;
     const int64_t occ_grid = (int64_t)ctx->num_cus * (m <= OCC_MAX_M / 2 ? 2 : 1);
-    const OccLayout ol(occ_ok ? occ_grid : 0, m, occ_ok ? occ_cap : 0);
+    const OccLayout ol(occ_ok ? occ_grid : 0, m, occ_ok ? occ_cap : 0, voter_weight ? 4 : 2);
     if (occ_ok && (rc = ws_reserve(ctx, WS_OCC, ol.total)) != SCHULZE_OK) return rc;
 
     char *mb = static_cast<char *>(ctx->ws[WS_BALLOT_META]);
@@ -1081,13 +1330,13 @@ extern "C" int schulze_pairwise(schulze_ctx *ctx, void *stream, const void *ball
     if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(mb + lay.in_u), (lay.ulist - lay.in_u) / 4, 0u)) !=
         SCHULZE_OK)
         return rc;
-    if ((rc = fill_u32(ctx, s, acc, (size_t)m * m, 0u)) != SCHULZE_OK) return rc;
+    if (n == 0 && (rc = fill_u32(ctx, s, acc, (size_t)m * m, 0u)) != SCHULZE_OK) return rc;
     if ((rc = fill_u32(ctx, s, rsum, (size_t)m, 0u)) != SCHULZE_OK) return rc;
 
     uint8_t *row_done = nullptr;  // rows finished by the bucketed count
     if (n > 0) {
         if (L <= 64) {
-            constexpr int per_wg = 4 * SHORT_PER_WAVE;
+            const int64_t per_wg = 4 * SHORT_PER_WAVE * std::min<int64_t>(SHORT_BPW, 64 / L);
             SCHULZE_LAUNCH(ctx, K_BALLOT_SCAN, s,
                            k_scan_short<<<dim3((unsigned)ceil_div(n, per_wg)), dim3(256), 0, s>>>(
                                ballots, dtype32, n, L, m, meta, ctx->err));
@@ -1104,6 +1353,15 @@ extern "C" int schulze_pairwise(schulze_ctx *ctx, void *stream, const void *ball
                        k_route<<<dim3(1), dim3(256), 0, s>>>(m, meta, voter_weight != nullptr,
                                                              (int64_t)(tpos_bytes / sizeof(uint32_t)),
                                                              occ_ok ? BUCKETED_PAIR_COST : ATOMIC_PAIR_COST));
+        {
+            // the m x m accumulator starts at zero unless the device chose the
+            // bucketed route and there are no full rankings: then nothing reads it
+            const int64_t words = (int64_t)m * m;
+            const unsigned fg = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(words / 4 + 1, 256),
+                                                                                 (int64_t)ctx->num_cus * 8));
+            SCHULZE_LAUNCH(ctx, K_FILL, s,
+                           k_fill_acc<<<dim3(fg), dim3(256), 0, s>>>(acc, words, meta, occ_ok && !may_have_full ? 1 : 0));
+        }
         if (voter_weight) {
             // counters 32..33: the 64-bit total; 34: workgroups done (zeroed above)
             const unsigned tg = (unsigned)std::min<int64_t>(ceil_div(n, 256), (int64_t)ctx->num_cus * 4);
@@ -1113,10 +1371,11 @@ extern "C" int schulze_pairwise(schulze_ctx *ctx, void *stream, const void *ball
                                ctx->err));
         }
         const unsigned cgrid = (unsigned)ctx->num_cus * 2;
+        const unsigned scatter_grid = (unsigned)std::min<int64_t>(max_pairs, (int64_t)ctx->num_cus * 16);
         if (may_have_full) {
             uint32_t *pos = static_cast<uint32_t *>(ctx->ws[WS_POSITIONS]);
             SCHULZE_LAUNCH(ctx, K_BALLOT_SCATTER, s,
-                           k_scatter<true><<<dim3((unsigned)max_pairs), dim3(256), 0, s>>>(
+                           k_scatter<true><<<dim3(scatter_grid), dim3(256), 0, s>>>(
                                ballots, dtype32, L, m, pitch, meta, pos, ctx->err));
             if (!voter_weight) {
                 DenseArgs da{pos, pitch, m, meta, acc, lda, rsum};
@@ -1131,7 +1390,7 @@ extern "C" int schulze_pairwise(schulze_ctx *ctx, void *stream, const void *ball
         if (tpos_bytes) {
             uint32_t *tpos = static_cast<uint32_t *>(ctx->ws[WS_TRUNC_POS]);
             SCHULZE_LAUNCH(ctx, K_BALLOT_SCATTER, s,
-                           k_scatter<false><<<dim3((unsigned)max_pairs), dim3(256), 0, s>>>(
+                           k_scatter<false><<<dim3(scatter_grid), dim3(256), 0, s>>>(
                                ballots, dtype32, L, m, 0, meta, tpos, ctx->err));
             DenseArgs da{tpos, 0, m, meta, acc, lda, rsum};
             SCHULZE_LAUNCH(ctx, K_COUNT_TRUNC, s, k_count_pos<true><<<dim3(cgrid), dim3(CNT_THREADS), 0, s>>>(da));
@@ -1139,12 +1398,16 @@ extern "C" int schulze_pairwise(schulze_ctx *ctx, void *stream, const void *ball
         if (occ_ok) {
             // bucketed pair counting (runs only if the device chose pair scattering)
             char *ob = static_cast<char *>(ctx->ws[WS_OCC]);
-            OccArgs oa{ballots, dtype32, L, m, voter_weight, meta,
+            int32_t tbits = 0;
+            while ((1 << tbits) < L) ++tbits;
+            const int row_vec = !dtype32 && L % 2 == 0 && reinterpret_cast<uintptr_t>(ballots) % 4 == 0;
+            OccArgs oa{ballots, dtype32, L, m, n, tbits, row_vec, voter_weight, meta,
                        reinterpret_cast<uint32_t *>(ob + ol.hist),
                        reinterpret_cast<uint32_t *>(ob + ol.row_start),
                        reinterpret_cast<uint32_t *>(ob + ol.item_start),
-                       reinterpret_cast<uint32_t *>(ob + ol.occ_v),
-                       reinterpret_cast<uint16_t *>(ob + ol.occ_t),
+                       reinterpret_cast<uint32_t *>(ob + ol.part_start),
+                       reinterpret_cast<uint32_t *>(ob + ol.occ),
+                       static_cast<void *>(ob + ol.partial), ol.ppitch,
                        acc, lda, rsum, ctx->err};
             const dim3 g(occ_grid), b(256);
             row_done = reinterpret_cast<uint8_t *>(ob + ol.row_done);
@@ -1157,8 +1420,8 @@ extern "C" int schulze_pairwise(schulze_ctx *ctx, void *stream, const void *ball
                 SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s, k_occ_bucket<OCC_MAX_M, false><<<g, b, 0, s>>>(oa));
             }
             SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
-                           k_occ_columns<<<dim3((unsigned)ceil_div(m, 256)), b, 0, s>>>(oa, (int32_t)occ_grid));
-            SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s, k_occ_scan<<<dim3(1), b, 0, s>>>(oa));
+                           k_occ_columns<<<dim3((unsigned)ceil_div(m, 64)), b, 0, s>>>(oa, (int32_t)occ_grid));
+            SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s, k_occ_scan<<<dim3(1), dim3(1024), 0, s>>>(oa));
             const dim3 ig((unsigned)(m + ceil_div(occ_cap, OCC_CHUNK)));
             if (m <= OCC_MAX_M / 2) {
                 SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s, k_occ_bucket<OCC_MAX_M / 2, true><<<g, b, 0, s>>>(oa));
@@ -1180,15 +1443,17 @@ extern "C" int schulze_pairwise(schulze_ctx *ctx, void *stream, const void *ball
                                ballots, dtype32, L, m, voter_weight, meta, acc, lda, rsum, ctx->err));
         }
     }
+    // rows of the bucketed route were written by it (row_done given)
     dim3 fgrid((unsigned)m);
     if (d_dtype == SCHULZE_U16) {
         SCHULZE_LAUNCH(ctx, K_COUNT_FINISH, s,
                        k_count_finish<uint16_t><<<fgrid, dim3(256), 0, s>>>(acc, lda, rsum, meta, m, (uint16_t *)d, ldd,
-                                                                            65535u, ctx->err, row_done));
+                                                                            65535u, ctx->err, row_done != nullptr));
     } else {
         SCHULZE_LAUNCH(ctx, K_COUNT_FINISH, s,
                        k_count_finish<int32_t><<<fgrid, dim3(256), 0, s>>>(acc, lda, rsum, meta, m, (int32_t *)d, ldd,
-                                                                           (uint32_t)INT32_MAX, ctx->err, row_done));
+                                                                           (uint32_t)INT32_MAX, ctx->err,
+                                                                           row_done != nullptr));
     }
     return SCHULZE_OK;
 }

@@ -96,3 +96,36 @@ def test_sparse_repeated_id_is_reported(ctx):
     for mode in ("bucketed", "atomic"):
         d, err = gpu_counts(ctx, b, 2000, mode)
         assert err == sz.EBALLOT, mode
+
+
+@pytest.mark.parametrize("case", ["odd-L", "int32-ids", "L-48", "L-80", "full-mixed", "weights-full-mixed"])
+def test_sparse_row_layouts(ctx, case):
+    """Ballot layouts of the bucketed count: rows read as 32-bit words
+    (uint16 ids, even L up to 64), one id at a time (odd L, int32 ids), rows
+    longer than a wavefront, and full rankings counted densely next to the
+    bucketed truncated ballots (counts added to the dense part)."""
+    rng = np.random.default_rng(731)
+    weight = None
+    if case == "odd-L":
+        m, b = 3000, workload.pl_zipf(731, 6000, 3000, 1.0, 7)
+    elif case == "int32-ids":
+        m, b = 3000, workload.pl_zipf(732, 6000, 3000, 1.0, 8, dtype=np.int32)
+    elif case == "L-48":
+        m, b = 4000, workload.pl_zipf(733, 3000, 4000, 1.0, 40, L=48)
+    elif case == "L-80":
+        m, b = 5000, workload.pl_zipf(734, 3000, 5000, 1.2, 70, L=80)
+    else:
+        m = 3000
+        trunc = workload.pl_zipf(735, 5000, m, 1.0, 6, L=m)
+        full = workload.mallows(736, 21, m, 0.9)
+        b = np.concatenate([trunc, full])
+        b = b[rng.permutation(len(b))]
+        if case == "weights-full-mixed":
+            weight = rng.integers(0, 5, size=len(b)).astype(np.uint32)
+    want = oracle.pairwise(b, m, weight)
+    log(f"[case] sparse layout {case}: m={m} n={len(b)} L={b.shape[1]}")
+    d, err = gpu_counts(ctx, b, m, "bucketed", weight=weight)
+    assert err == 0
+    got = d.cpu().numpy().astype(np.int64)
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, f"{case}: d differs at {len(bad)} places, first {bad[:5].tolist()}"
