@@ -169,8 +169,8 @@ int schulze_weights(schulze_ctx *ctx, void *stream, const void *d, int64_t ldd, 
  * source->v path (Section 2.1), out[source] = 0.  Given transposed weights
  * it yields the single-target widths p(v, source).  Exact: (max, min)
  * relaxation sweeps over the rows whose value grew, to the fixpoint, in one
- * cooperative launch.  Returns SCHULZE_EDEVICE if the device refuses a
- * cooperative launch.
+ * cooperative launch (after a plain launch that sets up the sweep state).
+ * Returns SCHULZE_EDEVICE if the device refuses a cooperative launch.
  */
 int schulze_widest_from(schulze_ctx *ctx, void *stream, const void *w, int64_t ldw, int32_t m,
                         int dtype, int32_t source, void *out);
@@ -199,10 +199,11 @@ int schulze_verify(schulze_ctx *ctx, void *stream, const void *w, int64_t ldw, c
  * schulze_verify for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * same arguments, outputs and errors as schulze_verify, but the sweep state
- * lives in a static device array of 1 MiB per device, whose address the
+ * lives in a static device array of 3 MiB per device, whose address the
  * library looks up when a context is created, instead of the context's
- * workspace; the call allocates nothing.  Limit: widest-path state of
- * 13 m + 1.3 KB bytes, i.e. every m <= 65535 (larger m: SCHULZE_EUNSUPPORTED).
+ * workspace; the call allocates nothing.  Limit: widest-path state of both
+ * directions, 32 m + 5 KB bytes, i.e. every m <= 65535 (larger m:
+ * SCHULZE_EUNSUPPORTED).
  * All calls on one device share that array and leave the last call's state
  * in it: calls that overlap on one device (other streams, other contexts,
  * other host threads) race and must be serialised by the caller.

@@ -24,172 +24,255 @@ namespace {
 
 constexpr int NF = 16;
 
+// Per-candidate statistics: one entry per candidate, or per candidate and
+// column super-block for the partials.  Counts are non-negative and below
+// 2^31, so every margin d[x][y] - d[y][x] fits in 32 bits.
 struct RawStats {
-    int32_t *cope, *ties;
+    int32_t *cope, *ties, *max_out, *max_in, *min_marg, *max_marg;
     unsigned long long *borda, *sum_out, *sum_in;
-    int32_t *max_out, *max_in;
-    long long *min_marg, *max_marg;
+};
+
+// Sums over the columns of one workgroup (at most 4 tiles of 64): 32 bits
+// hold them for 16-bit counts, int32 counts take 64.
+template <typename E>
+struct SumOf {
+    using type = unsigned long long;
+};
+template <>
+struct SumOf<uint16_t> {
+    using type = uint32_t;
 };
 
 // Statistics of one candidate over a set of columns.
-struct Stat {
-    int32_t cope, ties, mx_out, mx_in;
-    unsigned long long borda, s_out, s_in;
-    long long mn, mxm;
+template <typename E>
+struct Acc {
+    using S = typename SumOf<E>::type;
+    int32_t cope, ties, mx_out, mx_in, mn, mx;
+    S borda, s_out, s_in;
+
+    __device__ void init() {
+        cope = ties = mx_out = mx_in = 0;
+        mn = INT32_MAX;
+        mx = INT32_MIN;
+        borda = s_out = s_in = 0;
+    }
+    __device__ void merge(const Acc &o) {
+        cope += o.cope;
+        ties += o.ties;
+        borda += o.borda;
+        s_out += o.s_out;
+        s_in += o.s_in;
+        mx_out = max(mx_out, o.mx_out);
+        mx_in = max(mx_in, o.mx_in);
+        mn = min(mn, o.mn);
+        mx = max(mx, o.mx);
+    }
+    // Combine the 4 adjacent lanes that share a row.
+    __device__ void quad_reduce() {
+        for (int off = 1; off < 4; off <<= 1) {
+            cope += __shfl_xor(cope, off);
+            ties += __shfl_xor(ties, off);
+            borda += __shfl_xor(borda, off);
+            s_out += __shfl_xor(s_out, off);
+            s_in += __shfl_xor(s_in, off);
+            mx_out = max(mx_out, __shfl_xor(mx_out, off));
+            mx_in = max(mx_in, __shfl_xor(mx_in, off));
+            mn = min(mn, __shfl_xor(mn, off));
+            mx = max(mx, __shfl_xor(mx, off));
+        }
+    }
+    // An empty asm that takes and returns every field: sums of one column
+    // group are folded in here instead of being reassociated with those of
+    // the next groups (which would keep every LDS value of the tile live).
+    __device__ void pin() {
+        asm volatile("" : "+v"(cope), "+v"(ties), "+v"(mx_out), "+v"(mx_in), "+v"(mn), "+v"(mx), "+v"(borda),
+                     "+v"(s_out), "+v"(s_in));
+    }
+    __device__ void store(const RawStats &st, int64_t q) const {
+        st.cope[q] = cope;
+        st.ties[q] = ties;
+        st.max_out[q] = mx_out;
+        st.max_in[q] = mx_in;
+        st.min_marg[q] = mn;
+        st.max_marg[q] = mx;
+        st.borda[q] = borda;
+        st.sum_out[q] = s_out;
+        st.sum_in[q] = s_in;
+    }
 };
 
-__device__ inline void stat_init(Stat &s) {
-    s.cope = s.ties = s.mx_out = s.mx_in = 0;
-    s.borda = s.s_out = s.s_in = 0ull;
-    s.mn = LLONG_MAX;
-    s.mxm = LLONG_MIN;
-}
-
-// One column y of candidate x's row: dxy = d[x][y], dyx = d[y][x].
-__device__ inline void stat_add(Stat &s, int64_t dxy, int64_t dyx, int mode) {
-    s.cope += dxy > dyx;
-    s.ties += dxy == dyx;
-    s.borda += (unsigned long long)dxy;
-    const long long marg = dxy - dyx;
+// Column y of candidate x's row, xy = d[x][y], yx = d[y][x]; wo and wi are
+// the edge weights x -> y and y -> x (Section 3: d[x][y] when it beats
+// d[y][x], else 0, or the positive margin).
+template <typename E, bool MARGIN>
+__device__ __forceinline__ void acc_add(Acc<E> &s, int32_t xy, int32_t yx, int32_t &wo, int32_t &wi) {
+    using S = typename Acc<E>::S;
+    const int32_t marg = xy - yx;
+    s.cope += xy > yx;
+    s.ties += xy == yx;
+    s.borda += (S)(uint32_t)xy;
     s.mn = min(s.mn, marg);
-    s.mxm = max(s.mxm, marg);
-    const int32_t wout = dxy > dyx ? (int32_t)(mode == SCHULZE_MARGIN ? dxy - dyx : dxy) : 0;
-    const int32_t win = dyx > dxy ? (int32_t)(mode == SCHULZE_MARGIN ? dyx - dxy : dyx) : 0;
-    s.mx_out = max(s.mx_out, wout);
-    s.mx_in = max(s.mx_in, win);
-    s.s_out += (unsigned long long)wout;
-    s.s_in += (unsigned long long)win;
+    s.mx = max(s.mx, marg);
+    if (MARGIN) {
+        wo = max(marg, 0);
+        wi = max(-marg, 0);
+    } else {
+        wo = xy > yx ? xy : 0;
+        wi = yx > xy ? yx : 0;
+    }
+    s.mx_out = max(s.mx_out, wo);
+    s.mx_in = max(s.mx_in, wi);
+    s.s_out += (S)(uint32_t)wo;
+    s.s_in += (S)(uint32_t)wi;
 }
 
-__device__ inline void stat_merge(Stat &s, const Stat &o) {
-    s.cope += o.cope;
-    s.ties += o.ties;
-    s.borda += o.borda;
-    s.s_out += o.s_out;
-    s.s_in += o.s_in;
-    s.mx_out = max(s.mx_out, o.mx_out);
-    s.mx_in = max(s.mx_in, o.mx_in);
-    s.mn = min(s.mn, o.mn);
-    s.mxm = max(s.mxm, o.mxm);
-}
-
-// Combine the statistics of the 4 adjacent lanes that share a row.
-__device__ inline void stat_quad_reduce(Stat &s) {
-    for (int off = 1; off < 4; off <<= 1) {
-        s.cope += __shfl_xor(s.cope, off);
-        s.ties += __shfl_xor(s.ties, off);
-        s.borda += __shfl_xor(s.borda, off);
-        s.s_out += __shfl_xor(s.s_out, off);
-        s.s_in += __shfl_xor(s.s_in, off);
-        s.mx_out = max(s.mx_out, __shfl_xor(s.mx_out, off));
-        s.mx_in = max(s.mx_in, __shfl_xor(s.mx_in, off));
-        s.mn = min(s.mn, (long long)__shfl_xor(s.mn, off));
-        s.mxm = max(s.mxm, (long long)__shfl_xor(s.mxm, off));
+// One lane's share of a tile: row r of the rows starting at row0 over the
+// columns starting at col0, with A[r][c] = d[row0 + r][col0 + c] and
+// B[c][r] = d[col0 + c][row0 + r].  The lane takes columns
+// c = 4V k + V g + u (V elements per 16-byte vector), so that the four
+// lanes of a row write 64 contiguous bytes of w and of wt per store:
+// w[x][y] = wo and wt[x][y] = w[y][x] = wi come out of the same two LDS
+// reads as the statistics.  Interior tiles of aligned matrices, off the
+// diagonal.
+template <typename E, bool MARGIN>
+__device__ __forceinline__ void tile_rows(const E (*A)[tio::PITCH], const E (*B)[tio::PITCH], int r, int g,
+                                          int32_t row0, int32_t col0, Acc<E> &s, E *__restrict__ w, int64_t ldw,
+                                          E *__restrict__ wt, int64_t ldwt) {
+    constexpr int V = 16 / (int)sizeof(E), KV = tio::T / (4 * V);
+    const int64_t x = row0 + r;
+    for (int k = 0; k < KV; ++k) {
+        E ow[V], ot[V];
+        for (int u = 0; u < V; ++u) {
+            const int c = k * 4 * V + g * V + u;
+            int32_t wo, wi;
+            acc_add<E, MARGIN>(s, (int32_t)A[r][c], (int32_t)B[c][r], wo, wi);
+            ow[u] = (E)wo;
+            ot[u] = (E)wi;
+        }
+        s.pin();
+        const int32_t c0 = col0 + k * 4 * V + g * V;
+        if (w) *reinterpret_cast<uint4 *>(w + x * ldw + c0) = tio::pack<E>(ow);
+        if (wt) *reinterpret_cast<uint4 *>(wt + x * ldwt + c0) = tio::pack<E>(ot);
     }
 }
 
-__device__ inline void stat_store(const RawStats &st, int64_t q, const Stat &s) {
-    st.cope[q] = s.cope;
-    st.ties[q] = s.ties;
-    st.borda[q] = s.borda;
-    st.sum_out[q] = s.s_out;
-    st.sum_in[q] = s.s_in;
-    st.max_out[q] = s.mx_out;
-    st.max_in[q] = s.mx_in;
-    st.min_marg[q] = s.mn;
-    st.max_marg[q] = s.mxm;
+// The same for tiles at the matrix edge, on the diagonal or of unaligned
+// matrices: bounds and the diagonal checked, one element at a time (a
+// plain loop: these tiles are few, and unrolling them would cost the
+// interior loop registers).
+template <typename E, bool MARGIN>
+__device__ __forceinline__ void tile_rows_edge(const E (*A)[tio::PITCH], const E (*B)[tio::PITCH], int r, int g,
+                                            int32_t row0, int32_t col0, int32_t m, Acc<E> &s, E *__restrict__ w,
+                                            int64_t ldw, E *__restrict__ wt, int64_t ldwt) {
+    constexpr int V = 16 / (int)sizeof(E);
+    const int32_t x = row0 + r;
+    if (x >= m) return;
+#pragma unroll 1
+    for (int q = 0; q < tio::T / 4; ++q) {
+        const int c = (q / V) * 4 * V + g * V + q % V, y = col0 + c;
+        if (y >= m) continue;
+        int32_t wo = 0, wi = 0;
+        if (y != x) acc_add<E, MARGIN>(s, (int32_t)A[r][c], (int32_t)B[c][r], wo, wi);
+        if (w) w[(int64_t)x * ldw + y] = (E)wo;
+        if (wt) wt[(int64_t)x * ldwt + y] = (E)wi;
+    }
 }
 
-constexpr int SB_MAX = 8;  // 64-tiles per side of a super-block
-
-// Partial statistics over pairs of super-blocks, reading every block of d
-// once.  The matrix is cut into super-blocks of sb x sb tiles of 64; the
-// workgroup of super-block pair (I, J), I <= J, walks the tile pairs
-// (X, Y) in I x J (in I x I only those with X <= Y) and loads d[X][Y] and
-// d[Y][X] together: rows of X gain the columns of Y (kept in registers over
-// the tiles of J) and, X != Y, rows of Y gain the columns of X (kept in LDS
-// per tile of J, over the tiles of I).  Slot s of each partial array holds a
-// candidate's statistics over the columns of super-block s: rows of I over
-// J and rows of J over I, each (row, slot) written by exactly one
-// workgroup.  With w / wt given, the same pass writes the edge weights of
-// both tiles of each pair to w and to its transpose wt.
-template <typename E>
-__global__ __launch_bounds__(256) void k_feature_rows(const E *__restrict__ d, int64_t ldd, int32_t m, int mode,
-                                                      RawStats part, int vec, E *__restrict__ w, int64_t ldw,
-                                                      E *__restrict__ wt, int64_t ldwt, int32_t sb) {
-    __shared__ E a[64][65];  // a[r][c] = d[X0 + r][Y0 + c]
-    __shared__ E b[64][65];  // b[r][c] = d[Y0 + r][X0 + c]
-    __shared__ Stat mir[SB_MAX][64];
+// Partial statistics over pairs of super-blocks (SBV x SBV tiles of 64),
+// reading every block of d once.  The workgroup of super-block pair
+// (I, J), I <= J, walks the tile pairs (X, Y) of I x J (of I x I only those
+// with X <= Y), X outer, and loads d[X][Y] and d[Y][X] into LDS: the rows
+// of X gain the columns of Y (registers rs, stored when X is done) and,
+// X != Y, the rows of Y gain the columns of X (reduced over the four lanes
+// of a row and added to mir[j], in LDS, per tile of J; stored at the end).
+// Slot s of each partial array holds a candidate's statistics over the
+// columns of super-block s: rows of I over J and rows of J over I, each
+// (row, slot) written by exactly one workgroup (on the diagonal
+// super-block, row tile i adds what the tiles before it gave it as
+// mirrored rows).  With w / wt given, the same pass writes the edge weights
+// of both tiles to w and to its transpose wt.  VD: d is read in 16-byte
+// vectors (see tio::fetch); bits 1, 2 of vec: w, wt are vector-aligned (or
+// absent).
+template <typename E, bool MARGIN, int SBV, bool VD>
+__global__ __launch_bounds__(256) void k_feature_rows(const E *__restrict__ d, int64_t ldd, int32_t m, RawStats part,
+                                                      int vec, E *__restrict__ w, int64_t ldw, E *__restrict__ wt,
+                                                      int64_t ldwt) {
+    __shared__ E a[tio::T][tio::PITCH];  // a[r][c] = d[X0 + r][Y0 + c]
+    __shared__ E b[tio::T][tio::PITCH];  // b[r][c] = d[Y0 + r][X0 + c]
+    __shared__ Acc<E> mir[SBV][tio::T];
     const int32_t I = blockIdx.y, J = blockIdx.x;
     if (J < I) return;
     const int32_t nb = (m + 63) / 64;
-    const int r = threadIdx.x >> 2, part_c = threadIdx.x & 3;  // 4 threads per row, 16 columns each
-    if (part_c == 0)
-        for (int j = 0; j < SB_MAX; ++j) stat_init(mir[j][r]);
-    auto weight = [&](E xy, E yx, bool diag) -> E {  // edge weight given d[i][j] = xy, d[j][i] = yx
-        if (diag || xy <= yx) return (E)0;
-        return mode == SCHULZE_MARGIN ? (E)(xy - yx) : xy;
+    const int lane = threadIdx.x & 63;
+    const int r = (threadIdx.x >> 6) * 16 + (lane >> 2), g = lane & 3;  // 4 lanes per row
+    const bool vall = vec == 7;
+    if (g == 0)
+        for (int q = 0; q < SBV; ++q) mir[q][r].init();  // read and written by this lane only
+    // The tile pairs in order: i outer, j from i (diagonal super-block) or
+    // 0; the next pair's tiles are fetched into registers while the current
+    // pair is processed.
+    auto valid = [&](int32_t i, int32_t j) { return i < SBV && j < SBV && I * SBV + i < nb && J * SBV + j < nb; };
+    auto advance = [&](int32_t &i, int32_t &j) {  // the pair after (i, j); i = SBV when none is left
+        if (valid(i, j + 1)) {
+            ++j;
+            return;
+        }
+        ++i;
+        j = I == J ? i : 0;
+        if (!valid(i, j)) i = SBV;
     };
-    for (int32_t i = 0; i < sb; ++i) {
-        const int32_t X = I * sb + i;
-        if (X >= nb) break;
-        const int32_t X0 = X * 64, x = X0 + r;
-        Stat rs;
-        stat_init(rs);
-        for (int32_t j = I == J ? i : 0; j < sb; ++j) {
-            const int32_t Y = J * sb + j;
-            if (Y >= nb) break;
-            const int32_t Y0 = Y * 64;
-            __syncthreads();
-            tio::load<E>(a, d, ldd, X0, Y0, m, m, (vec & 1) != 0);
-            if (X != Y) tio::load<E>(b, d, ldd, Y0, X0, m, m, (vec & 1) != 0);
-            __syncthreads();
-            const E(*bb)[65] = X != Y ? b : a;  // d[Y0 + r][X0 + c]
-            if (w) {
-                tio::store<E>(w, ldw, X0, Y0, m, m, (vec & 2) != 0,
-                              [&](int rr, int cc) { return weight(a[rr][cc], bb[cc][rr], X0 + rr == Y0 + cc); });
-                if (X != Y)
-                    tio::store<E>(w, ldw, Y0, X0, m, m, (vec & 2) != 0,
-                                  [&](int rr, int cc) { return weight(bb[rr][cc], a[cc][rr], false); });
+    tio::Regs<E> ga, gb;
+    auto fetch_pair = [&](int32_t i, int32_t j) {
+        const int32_t X0 = (I * SBV + i) * 64, Y0 = (J * SBV + j) * 64;
+        tio::fetch<E, VD>(ga, d, ldd, X0, Y0, m, m);
+        if (X0 != Y0) tio::fetch<E, VD>(gb, d, ldd, Y0, X0, m, m);
+    };
+    int32_t i = 0, j = 0;
+    if (!valid(i, j)) i = SBV;
+    if (i < SBV) fetch_pair(i, j);
+    Acc<E> rs;
+    rs.init();
+    while (i < SBV) {
+        const int32_t X = I * SBV + i, Y = J * SBV + j;
+        const int32_t X0 = X * 64, Y0 = Y * 64;
+        __syncthreads();  // the previous tile pair's LDS reads are done
+        tio::put<E>(a, ga);
+        if (X != Y) tio::put<E>(b, gb);
+        int32_t ni = i, nj = j;
+        advance(ni, nj);
+        if (ni < SBV) fetch_pair(ni, nj);  // in flight during the work below
+        __syncthreads();
+        if (X == Y) {
+            tile_rows_edge<E, MARGIN>(a, a, r, g, X0, Y0, m, rs, w, ldw, wt, ldwt);
+        } else {
+            Acc<E> ms;
+            ms.init();
+            if (vall && X0 + 64 <= m && Y0 + 64 <= m) {
+                tile_rows<E, MARGIN>(a, b, r, g, X0, Y0, rs, w, ldw, wt, ldwt);
+                tile_rows<E, MARGIN>(b, a, r, g, Y0, X0, ms, w, ldw, wt, ldwt);
+            } else {
+                tile_rows_edge<E, MARGIN>(a, b, r, g, X0, Y0, m, rs, w, ldw, wt, ldwt);
+                tile_rows_edge<E, MARGIN>(b, a, r, g, Y0, X0, m, ms, w, ldw, wt, ldwt);
             }
-            if (wt) {
-                tio::store<E>(wt, ldwt, Y0, X0, m, m, (vec & 4) != 0,
-                              [&](int rr, int cc) { return weight(a[cc][rr], bb[rr][cc], X0 + cc == Y0 + rr); });
-                if (X != Y)
-                    tio::store<E>(wt, ldwt, X0, Y0, m, m, (vec & 4) != 0,
-                                  [&](int rr, int cc) { return weight(bb[cc][rr], a[rr][cc], false); });
-            }
-            // rows of X over the columns of Y
-            if (x < m)
-                for (int c = part_c * 16; c < part_c * 16 + 16; ++c) {
-                    const int32_t y = Y0 + c;
-                    if (y < m && y != x) stat_add(rs, a[r][c], bb[c][r], mode);
-                }
-            if (X != Y) {  // rows of Y over the columns of X
-                Stat ms;
-                stat_init(ms);
-                const int32_t yr = Y0 + r;
-                if (yr < m)
-                    for (int c = part_c * 16; c < part_c * 16 + 16; ++c)
-                        if (X0 + c < m) stat_add(ms, bb[r][c], a[c][r], mode);
-                stat_quad_reduce(ms);
-                if (part_c == 0) stat_merge(mir[j][r], ms);  // only this thread touches mir[j][r]
-            }
+            ms.quad_reduce();
+            if (g == 0) mir[j][r].merge(ms);
         }
-        stat_quad_reduce(rs);
-        if (part_c == 0 && x < m) {
-            // on the diagonal super-block, tile X's rows also hold the columns of
-            // the tiles before it (gathered as mirrored rows)
-            if (I == J) stat_merge(rs, mir[i][r]);
-            stat_store(part, (int64_t)J * m + x, rs);
+        if (ni != i) {  // the last pair of row tile X: its rows are complete over J
+            rs.quad_reduce();
+            if (g == 0 && X0 + r < m) {
+                if (I == J) rs.merge(mir[i][r]);  // what the tiles before X gave its rows as mirrored rows
+                rs.store(part, (int64_t)J * m + X0 + r);
+            }
+            rs.init();
         }
+        i = ni;
+        j = nj;
     }
-    if (I == J) return;
-    for (int32_t j = 0; j < sb; ++j) {
-        const int32_t Y = J * sb + j;
-        if (Y >= nb) break;
-        const int32_t y = Y * 64 + r;
-        if (part_c == 0 && y < m) stat_store(part, (int64_t)I * m + y, mir[j][r]);
+    if (I == J || g != 0) return;
+    for (int q = 0; q < SBV; ++q) {
+        const int32_t y = (J * SBV + q) * 64 + r;
+        if (y >= m) break;
+        mir[q][r].store(part, (int64_t)I * m + y);
     }
 }
 
@@ -197,9 +280,8 @@ __global__ __launch_bounds__(256) void k_feature_rows(const E *__restrict__ d, i
 __global__ __launch_bounds__(256) void k_feature_reduce(int32_t m, int32_t S, RawStats part, RawStats st) {
     const int32_t x = blockIdx.x * 256 + threadIdx.x;
     if (x >= m) return;
-    int32_t cope = 0, ties = 0, mx_out = 0, mx_in = 0;
+    int32_t cope = 0, ties = 0, mx_out = 0, mx_in = 0, mn = INT32_MAX, mxm = INT32_MIN;
     unsigned long long borda = 0, s_out = 0, s_in = 0;
-    long long mn = LLONG_MAX, mxm = LLONG_MIN;
     for (int32_t sl = 0; sl < S; ++sl) {
         const int64_t q = (int64_t)sl * m + x;
         cope += part.cope[q];
@@ -281,28 +363,50 @@ __global__ __launch_bounds__(256) void k_feature_norm(int32_t m, RawStats st, fl
 RawStats carve(char *p, size_t n, size_t *bytes) {
     const size_t i4 = round_up(sizeof(int32_t) * n, 256), i8 = round_up(8 * n, 256);
     RawStats st;
-    st.cope = reinterpret_cast<int32_t *>(p);
-    st.ties = reinterpret_cast<int32_t *>(p + i4);
-    st.max_out = reinterpret_cast<int32_t *>(p + 2 * i4);
-    st.max_in = reinterpret_cast<int32_t *>(p + 3 * i4);
-    st.borda = reinterpret_cast<unsigned long long *>(p + 4 * i4);
-    st.sum_out = reinterpret_cast<unsigned long long *>(p + 4 * i4 + i8);
-    st.sum_in = reinterpret_cast<unsigned long long *>(p + 4 * i4 + 2 * i8);
-    st.min_marg = reinterpret_cast<long long *>(p + 4 * i4 + 3 * i8);
-    st.max_marg = reinterpret_cast<long long *>(p + 4 * i4 + 4 * i8);
-    *bytes = 4 * i4 + 5 * i8;
+    int32_t *const i32[6] = {reinterpret_cast<int32_t *>(p), reinterpret_cast<int32_t *>(p + i4),
+                             reinterpret_cast<int32_t *>(p + 2 * i4), reinterpret_cast<int32_t *>(p + 3 * i4),
+                             reinterpret_cast<int32_t *>(p + 4 * i4), reinterpret_cast<int32_t *>(p + 5 * i4)};
+    st.cope = i32[0];
+    st.ties = i32[1];
+    st.max_out = i32[2];
+    st.max_in = i32[3];
+    st.min_marg = i32[4];
+    st.max_marg = i32[5];
+    st.borda = reinterpret_cast<unsigned long long *>(p + 6 * i4);
+    st.sum_out = reinterpret_cast<unsigned long long *>(p + 6 * i4 + i8);
+    st.sum_in = reinterpret_cast<unsigned long long *>(p + 6 * i4 + 2 * i8);
+    *bytes = 6 * i4 + 3 * i8;
     return st;
+}
+
+template <typename E, int SBV, bool VD>
+int launch_rows(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32_t m, int mode, RawStats part,
+                int vec, E *w, int64_t ldw, E *wt, int64_t ldwt, int32_t S) {
+    const dim3 grid((unsigned)S, (unsigned)S);
+    if (mode == SCHULZE_MARGIN)
+        SCHULZE_LAUNCH(ctx, K_FEATURE_ROWS, s,
+                       k_feature_rows<E, true, SBV, VD>
+                       <<<grid, dim3(256), 0, s>>>(d, ldd, m, part, vec, w, ldw, wt, ldwt));
+    else
+        SCHULZE_LAUNCH(ctx, K_FEATURE_ROWS, s,
+                       k_feature_rows<E, false, SBV, VD>
+                       <<<grid, dim3(256), 0, s>>>(d, ldd, m, part, vec, w, ldw, wt, ldwt));
+    return SCHULZE_OK;
+}
+
+// Tiles per super-block side: more tiles mean fewer partial slots to write
+// and reduce, fewer mean less LDS per workgroup (more workgroups per CU).
+template <typename E>
+constexpr int feature_sb() {
+    return 4;
 }
 
 template <typename E>
 int run_features(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32_t m, int mode, float n_voters,
                  float *feat, E *w = nullptr, int64_t ldw = 0, E *wt = nullptr, int64_t ldwt = 0) {
-    // super-blocks of sb x sb tiles: at most 64 of them per side (a partial
-    // slot per super-block column), sb <= SB_MAX; S = super-blocks per side
-    const int32_t nbx = (int32_t)ceil_div(m, 64);
-    int32_t sb = 1;
-    while (sb < SB_MAX && ceil_div(nbx, sb) > 64) sb *= 2;
-    const int32_t S = (int32_t)ceil_div(nbx, sb);
+    constexpr int SBV = feature_sb<E>();
+    // S super-blocks per side: a partial slot per super-block column
+    const int32_t S = (int32_t)ceil_div(ceil_div(m, 64), SBV);
     size_t fin_bytes = 0, part_bytes = 0;
     (void)carve(nullptr, (size_t)m, &fin_bytes);
     (void)carve(nullptr, (size_t)m * S, &part_bytes);
@@ -313,11 +417,11 @@ int run_features(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32
     RawStats part = carve(p + fin_bytes, (size_t)m * S, &part_bytes);
     uint32_t *mx = reinterpret_cast<uint32_t *>(p + fin_bytes + part_bytes);
     if ((rc = fill_u32(ctx, s, mx, 4, 0u)) != SCHULZE_OK) return rc;
-    const int vec = (tio::vec_ok<E>(d, ldd) ? 1 : 0) | (tio::vec_ok<E>(w, ldw) ? 2 : 0) |
-                    (tio::vec_ok<E>(wt, ldwt) ? 4 : 0);
-    SCHULZE_LAUNCH(ctx, K_FEATURE_ROWS, s,
-                   k_feature_rows<E><<<dim3((unsigned)S, (unsigned)S), dim3(256), 0, s>>>(
-                       d, ldd, m, mode, part, vec, w, ldw, wt, ldwt, sb));
+    const bool vd = tio::vec_ok<E>(d, ldd) && m % (16 / (int)sizeof(E)) == 0;
+    const int vec = (vd ? 1 : 0) | (!w || tio::vec_ok<E>(w, ldw) ? 2 : 0) | (!wt || tio::vec_ok<E>(wt, ldwt) ? 4 : 0);
+    rc = vd ? launch_rows<E, SBV, true>(ctx, s, d, ldd, m, mode, part, vec, w, ldw, wt, ldwt, S)
+            : launch_rows<E, SBV, false>(ctx, s, d, ldd, m, mode, part, vec, w, ldw, wt, ldwt, S);
+    if (rc != SCHULZE_OK) return rc;
     SCHULZE_LAUNCH(ctx, K_FEATURES, s,
                    k_feature_reduce<<<dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s>>>(m, S, part, st));
     const dim3 vg((unsigned)ceil_div(m, 256));

@@ -83,6 +83,24 @@ __device__ inline uint32_t key_width(typename Key<E>::K k) {
     return (uint32_t)(k & Key<E>::LOW);
 }
 
+// Four consecutive elements of a row starting at a multiple of 4 (one 8- or
+// 16-byte access when vec and all four are inside, else one at a time, 0
+// past `valid`).
+template <typename E>
+__device__ inline void load4(const E *__restrict__ p, bool vec, int32_t valid, uint32_t (&v)[4]) {
+    if (vec && valid >= 4) {
+        if constexpr (sizeof(E) == 4) {
+            const uint4 q = *reinterpret_cast<const uint4 *>(p);
+            v[0] = q.x, v[1] = q.y, v[2] = q.z, v[3] = q.w;
+        } else {
+            const uint2 q = *reinterpret_cast<const uint2 *>(p);
+            v[0] = q.x & 0xFFFFu, v[1] = q.x >> 16, v[2] = q.y & 0xFFFFu, v[3] = q.y >> 16;
+        }
+    } else {
+        for (int c = 0; c < 4; ++c) v[c] = c < valid ? (uint32_t)p[c] : 0u;
+    }
+}
+
 // ------------------------------------------------------------------ per-vertex statistics
 // Row x of w and of wt among the vertices still in (rem[y] = 0): largest
 // outgoing and incoming edge weight (the initialisation filter) and, when
@@ -110,8 +128,8 @@ __global__ __launch_bounds__(256) void k_prop_rows(const E *__restrict__ d, int6
         uint8_t r[4];
         const bool full = y0 + 4 <= m;
         if (full && wv) {
-            sweep::load4<E>(wr + y0, true, 4, a);
-            sweep::load4<E>(wtr + y0, true, 4, at);
+            load4<E>(wr + y0, true, 4, a);
+            load4<E>(wtr + y0, true, 4, at);
             const uint32_t rw = *reinterpret_cast<const uint32_t *>(rem + y0);
             for (int u = 0; u < 4; ++u) r[u] = (uint8_t)(rw >> (8 * u));
         } else {
@@ -122,7 +140,7 @@ __global__ __launch_bounds__(256) void k_prop_rows(const E *__restrict__ d, int6
                 r[u] = in ? rem[y0 + u] : (uint8_t)1;
             }
         }
-        if (with_borda) sweep::load4<E>(dr + y0, full && dv, full ? 4 : m - y0, ad);
+        if (with_borda) load4<E>(dr + y0, full && dv, full ? 4 : m - y0, ad);
         for (int u = 0; u < 4; ++u) {
             if (r[u]) continue;
             mo = max(mo, a[u]);
@@ -177,57 +195,55 @@ __global__ __launch_bounds__(256) void k_prop_order(const unsigned long long *__
 }
 
 // ------------------------------------------------------------------ propagation sweeps
+// Both directions in one launch: problem 0 propagates forward over the
+// rows of w into kf, problem 1 backward over the rows of wt into kb.
 template <typename E>
 struct SweepArgs {
-    using K = typename Key<E>::K;
-    const E *w;  // rows = edge sources: w for forward, wt for backward
-    int64_t ld;
+    sweep::Run<typename Key<E>::K, E, 2> run;
     int32_t m;
-    int32_t vec;        // rows allow 8/16-byte accesses
     const uint8_t *status;
     const int32_t *label;
-    K *x;               // keys, updated in place
-    uint8_t *changed;   // m flags
-    int32_t *front[2];  // frontier lists
-    int32_t *fcount;    // [0], [1] frontier sizes, [2] sweeps run
-    K *out;
-    GridBar *bar;
-    int32_t *err;
-    int64_t spin_limit;
 };
+
+// Undecided vertices start with their own label and the empty path; they
+// form the first frontier of both directions.  The counters and the barrier
+// are zero on entry.  A plain launch ahead of the sweeps.
+template <typename E>
+__global__ __launch_bounds__(256) void k_prop_init(SweepArgs<E> a) {
+    using K = typename Key<E>::K;
+    const int32_t m = a.m;
+    const int lane = threadIdx.x & 63;
+    for (int32_t j0 = blockIdx.x * 256; j0 < m; j0 += gridDim.x * 256) {
+        const int32_t j = j0 + threadIdx.x;
+        const bool u = j < m && a.status[j] == ST_UNKNOWN;
+        const uint64_t bal = __ballot(u);
+        for (int q = 0; q < 2; ++q) {
+            const sweep::Problem<K, E> &P = a.run.p[q];
+            if (j < m) {
+                P.x[j] = u ? make_key<E>((uint32_t)a.label[j]) : (K)0;
+                P.stamp[j] = 0;
+            }
+            int32_t base = 0;
+            if (lane == 0 && bal) base = atomicAdd(&P.count[0], (int32_t)__popcll(bal));
+            base = __shfl(base, 0);
+            if (u) P.front[0][base + (int32_t)__popcll(bal & ((1ull << lane) - 1ull))] = j;
+        }
+    }
+}
 
 template <typename E>
 __global__ __launch_bounds__(256) void k_prop_sweep(SweepArgs<E> a) {
     using K = typename Key<E>::K;
-    const int32_t m = a.m;
     constexpr K HIGH = ~Key<E>::LOW;
-
-    // preprocessing: undecided vertices start with their own label and the
-    // empty path; they form the first frontier
-    for (int32_t j = blockIdx.x * 256 + threadIdx.x; j < m; j += gridDim.x * 256) {
-        const bool u = a.status[j] == ST_UNKNOWN;
-        a.x[j] = u ? make_key<E>((uint32_t)a.label[j]) : (K)0;
-        a.changed[j] = 0;
-        if (u) a.front[0][atomicAdd(&a.fcount[0], 1)] = j;
-    }
-    if (!grid_sync(a.bar, a.spin_limit)) goto stuck;
-    {
-        sweep::Buffers<K> b{a.x, {a.front[0], a.front[1]}, a.fcount, a.changed, a.bar, a.err, a.spin_limit,
-                            2 * m + 2};
-        const uint8_t *status = a.status;
-        const bool ok = sweep::run<K, E>(
-            a.w, a.ld, m, a.vec != 0, b,
-            [](K k, uint32_t wij) -> K {
-                if (wij == 0 || k == 0) return (K)0;
-                return (k & HIGH) | (K)min((uint32_t)(k & Key<E>::LOW), wij);
-            },
-            [status](int32_t j) { return status[j] != ST_REMOVED; });  // removed vertices have no edges
-        if (!ok) goto stuck;
-        for (int32_t j = blockIdx.x * 256 + threadIdx.x; j < m; j += gridDim.x * 256) a.out[j] = a.x[j];
-        return;
-    }
-stuck:
-    if (threadIdx.x == 0) set_device_error(a.err, SCHULZE_EDEVICE);
+    const uint8_t *status = a.status;
+    const bool ok = sweep::run<K, E, 2>(
+        a.run, a.m,
+        [](K k, uint32_t wij) -> K {
+            if (wij == 0 || k == 0) return (K)0;
+            return (k & HIGH) | (K)min((uint32_t)(k & Key<E>::LOW), wij);
+        },
+        [status](int32_t j) { return status[j] != ST_REMOVED; });  // removed vertices have no edges
+    if (!ok && threadIdx.x == 0) set_device_error(a.run.err, SCHULZE_EDEVICE);
 }
 
 // ------------------------------------------------------------------ postprocessing
@@ -396,13 +412,14 @@ template <typename E>
 struct PropBufs {
     using K = typename Key<E>::K;
     E *w, *wt;
-    K *x, *kf, *kb;
-    uint8_t *changed;
-    int32_t *f0, *f1, *label, *vertex;
+    K *kf, *kb;
+    int32_t *front[4], *stamp[2], *label, *vertex;
     uint32_t *pair;
     unsigned long long *borda;
     uint8_t *status, *mark, *dead, *rem;
-    int32_t *tail;  // [0..2] sweep counters, [8..10] barrier, [16..17] counts
+    int32_t *cnt;   // sweep counters of the two directions, 64 words apart
+    GridBar *bar;
+    int32_t *tail;  // [16..17] counts
     size_t bvec;
     int64_t G;      // sweep grid
 };
@@ -417,8 +434,10 @@ int prop_prepare(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32
     const size_t ivec = round_up(sizeof(int32_t) * (size_t)m, 256);
     const size_t bvec = round_up((size_t)m, 256);
     const size_t u64vec = round_up(sizeof(unsigned long long) * (size_t)m, 256);
-    // w | wt | keys | kf | kb | fronts x2 | label | vertex | borda | status | mark | dead | rem | changed | tail
-    const size_t need = 2 * mat + 3 * kvec + 5 * ivec + u64vec + 5 * bvec + 256;
+    // w | wt | kf | kb | fronts x4 | stamps x2 | label | vertex | pair | borda | status | mark | dead | rem |
+    // counters | barrier | tail
+    const size_t barb = round_up(grid::BAR_BYTES, 256);
+    const size_t need = 2 * mat + 2 * kvec + 9 * ivec + u64vec + 4 * bvec + 512 + barb + 256;
     int rc = ws_reserve(ctx, WS_PROPAGATE, need);
     if (rc != SCHULZE_OK) return rc;
     char *p = static_cast<char *>(ctx->ws[WS_PROPAGATE]);
@@ -429,11 +448,10 @@ int prop_prepare(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32
     };
     b.w = reinterpret_cast<E *>(take(mat));
     b.wt = reinterpret_cast<E *>(take(mat));
-    b.x = reinterpret_cast<K *>(take(kvec));
     b.kf = reinterpret_cast<K *>(take(kvec));
     b.kb = reinterpret_cast<K *>(take(kvec));
-    b.f0 = reinterpret_cast<int32_t *>(take(ivec));
-    b.f1 = reinterpret_cast<int32_t *>(take(ivec));
+    for (int i = 0; i < 4; ++i) b.front[i] = reinterpret_cast<int32_t *>(take(ivec));
+    for (int i = 0; i < 2; ++i) b.stamp[i] = reinterpret_cast<int32_t *>(take(ivec));
     b.label = reinterpret_cast<int32_t *>(take(ivec));
     b.vertex = reinterpret_cast<int32_t *>(take(ivec));
     b.pair = reinterpret_cast<uint32_t *>(take(ivec));
@@ -442,7 +460,8 @@ int prop_prepare(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32
     b.mark = reinterpret_cast<uint8_t *>(take(bvec));
     b.dead = reinterpret_cast<uint8_t *>(take(bvec));
     b.rem = reinterpret_cast<uint8_t *>(take(bvec));
-    b.changed = reinterpret_cast<uint8_t *>(take(bvec));
+    b.cnt = reinterpret_cast<int32_t *>(take(512));
+    b.bar = reinterpret_cast<GridBar *>(take(barb));
     b.tail = reinterpret_cast<int32_t *>(take(256));
     b.bvec = bvec;
 
@@ -458,7 +477,7 @@ int prop_prepare(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_prop_sweep<E>, 256, 0) != hipSuccess || per_cu < 1)
         return SCHULZE_EDEVICE;
-    b.G = sweep::grid_size(m, (int64_t)ctx->num_cus * std::min(per_cu, 2));
+    b.G = sweep::grid_size(m, 2, (int64_t)ctx->num_cus * std::min(per_cu, 2));
     return SCHULZE_OK;
 }
 
@@ -466,43 +485,53 @@ int prop_prepare(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32
 // until no vertex still in is undecided.
 template <typename E>
 int prop_decide_all(schulze_ctx *ctx, hipStream_t s, int32_t m, PropBufs<E> &b, schulze_propagate_stats &st) {
+    using K = typename Key<E>::K;
     int rc;
     const unsigned vb = (unsigned)ceil_div(m, 256);
     int32_t counts[2] = {0, 0};
     for (int32_t round = 0; round < m; ++round) {
-        for (int dir = 0; dir < 2; ++dir) {
-            if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(b.tail), 16, 0u)) != SCHULZE_OK) return rc;
+        {
+            // counters and barrier cleared (adjacent), then the init and both directions' sweeps
+            const size_t words = (512 + round_up(grid::BAR_BYTES, 256)) / 4;
+            if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(b.cnt), words, 0u)) != SCHULZE_OK) return rc;
             SweepArgs<E> a;
-            a.w = dir == 0 ? b.w : b.wt;
-            a.ld = m;
+            for (int q = 0; q < 2; ++q) {
+                sweep::Problem<K, E> &P = a.run.p[q];
+                P.A = q == 0 ? b.w : b.wt;
+                P.ld = m;
+                P.vec = sweep::vec_ok<E>(P.A, m) ? 1 : 0;
+                P.x = q == 0 ? b.kf : b.kb;
+                P.stamp = b.stamp[q];
+                P.front[0] = b.front[2 * q];
+                P.front[1] = b.front[2 * q + 1];
+                P.count = b.cnt + 64 * q;
+            }
+            a.run.max_sweeps = 2 * m + 2;
+            a.run.bar = b.bar;
+            a.run.err = ctx->err;
+            a.run.spin_limit = (int64_t)1 << 24;
             a.m = m;
-            a.vec = (reinterpret_cast<uintptr_t>(a.w) % (4 * sizeof(E)) == 0 && m % 4 == 0) ? 1 : 0;
             a.status = b.status;
             a.label = b.label;
-            a.x = b.x;
-            a.changed = b.changed;
-            a.front[0] = b.f0;
-            a.front[1] = b.f1;
-            a.fcount = b.tail;
-            a.out = dir == 0 ? b.kf : b.kb;
-            a.bar = reinterpret_cast<GridBar *>(b.tail + 8);
-            a.err = ctx->err;
-            a.spin_limit = (int64_t)1 << 24;
-            void *args[] = {&a};
             int tok;
             timing_begin(ctx, K_PROP_SWEEP, s, &tok);
-            const hipError_t e =
-                hipLaunchCooperativeKernel((const void *)k_prop_sweep<E>, dim3((unsigned)b.G), dim3(256), args, 0, s);
+            k_prop_init<E><<<dim3((unsigned)std::min<int64_t>(vb, 1024)), dim3(256), 0, s>>>(a);
+            hipError_t e = hipGetLastError();
+            void *args[] = {&a};
+            if (e == hipSuccess)
+                e = hipLaunchCooperativeKernel((const void *)k_prop_sweep<E>, dim3((unsigned)b.G), dim3(256), args, 0,
+                                               s);
             timing_end(ctx, tok, s);
             if (e != hipSuccess) {
                 (void)hipGetLastError();
                 return SCHULZE_EDEVICE;
             }
-            int32_t sweeps = 0;
-            if (hipMemcpyAsync(&sweeps, b.tail + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            int32_t sweeps[2] = {0, 0};
+            if (hipMemcpyAsync(&sweeps[0], b.cnt + 3, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipMemcpyAsync(&sweeps[1], b.cnt + 64 + 3, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess)
                 return SCHULZE_EDEVICE;
-            st.sweeps += sweeps;
+            st.sweeps += sweeps[0] + sweeps[1];
         }
         // mark and dead are adjacent: clear both
         if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(b.mark), 2 * b.bvec / 4, 0u)) != SCHULZE_OK) return rc;

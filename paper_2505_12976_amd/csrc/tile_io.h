@@ -76,6 +76,49 @@ __device__ inline void load(E (*t)[PITCH], const E *__restrict__ src, int64_t ld
     }
 }
 
+// The same tile in two halves, so that the loads can be issued early and
+// the LDS written later: fetch() loads the tile into registers, put()
+// writes them to LDS.  VEC (the matrix is vector-aligned and its side a
+// multiple of the vector length): 16-byte loads, rows and vectors past the
+// edge read the tile's first row / vector instead, so that every tile takes
+// the same loads (what lands outside the matrix is garbage, to be ignored
+// by the caller).  Otherwise one element at a time, 0 outside.
+template <typename E>
+struct Regs {
+    static constexpr int PER = T * (T / (16 / (int)sizeof(E))) / 256;  // 16-byte vectors per thread
+    uint4 x[PER];
+};
+
+template <typename E, bool VEC>
+__device__ inline void fetch(Regs<E> &g, const E *__restrict__ src, int64_t ld, int32_t r0, int32_t c0, int32_t rows,
+                             int32_t cols) {
+    constexpr int V = 16 / (int)sizeof(E), VPR = T / V;
+    for (int k = 0; k < Regs<E>::PER; ++k) {
+        const int q = threadIdx.x + 256 * k;
+        int32_t r = r0 + q / VPR, c = c0 + (q % VPR) * V;
+        if (VEC) {
+            r = r < rows ? r : r0;
+            c = c < cols ? c : c0;
+            g.x[k] = *reinterpret_cast<const uint4 *>(src + (int64_t)r * ld + c);
+        } else {
+            E e[V];
+            for (int u = 0; u < V; ++u) e[u] = (r < rows && c + u < cols) ? src[(int64_t)r * ld + c + u] : (E)0;
+            g.x[k] = pack<E>(e);
+        }
+    }
+}
+
+template <typename E>
+__device__ inline void put(E (*t)[PITCH], const Regs<E> &g) {
+    constexpr int V = 16 / (int)sizeof(E), VPR = T / V;
+    for (int k = 0; k < Regs<E>::PER; ++k) {
+        const int q = threadIdx.x + 256 * k;
+        E e[V];
+        unpack<E>(g.x[k], e);
+        for (int u = 0; u < V; ++u) t[q / VPR][(q % VPR) * V + u] = e[u];
+    }
+}
+
 // dst[(r0 + r) ld + c0 + c] = f(r, c) for r0 + r < rows and c0 + c < cols.
 template <typename E, typename F>
 __device__ inline void store(E *__restrict__ dst, int64_t ld, int32_t r0, int32_t c0, int32_t rows, int32_t cols,

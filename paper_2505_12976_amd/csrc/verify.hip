@@ -12,21 +12,22 @@
 // anything, so each sweep walks just that frontier.  The target direction
 // p[.][t] is the same computation on the transposed weights.
 //
-// One persistent cooperative launch runs all sweeps (the column-block and
-// frontier-share layout of sweep.h), with a grid barrier between sweeps.
+// One persistent cooperative launch runs all sweeps of both directions (the
+// column-block and frontier-share layout of sweep.h), with one grid barrier
+// per sweep.
 #include <mutex>
 
 #include "grid.h"
 #include "sweep.h"
 #include "tile_io.h"
 
-// Device scratch of schulze_verify_noalloc: the sweeps' value vector, flags,
-// two frontier lists and counters for up to 65535 candidates (852 KB used
-// at that size).  Each device holds its own copy for the life of the
-// process.  In host code `scratch` only names the symbol; its device address
-// comes from hipGetSymbolAddress (verify_scratch_init) and is the only form
-// passed to kernels.
-constexpr size_t VERIFY_SCRATCH_BYTES = (size_t)1 << 20;
+// Device scratch of schulze_verify_noalloc: for both directions the sweeps'
+// values, stamps, two frontier lists and counters, then the barrier, for up
+// to 65535 candidates (2.1 MB used at that size).  Each device holds its own
+// copy for the life of the process.  In host code `scratch` only names the
+// symbol; its device address comes from hipGetSymbolAddress
+// (verify_scratch_init) and is the only form passed to kernels.
+constexpr size_t VERIFY_SCRATCH_BYTES = (size_t)3 << 20;
 static __device__ __align__(256) unsigned char scratch[VERIFY_SCRATCH_BYTES];
 
 namespace {
@@ -94,52 +95,48 @@ __global__ __launch_bounds__(256) void k_weights_pair(const E *__restrict__ d, i
     if (wt) tio::store<E>(wt, ldwt, I0, J0, m, m, wtv, [&](int r, int c) { return weight(b[c][r], a[r][c], false); });
 }
 
-// ------------------------------------------------------------------ grid barrier
 // ------------------------------------------------------------------ sweeps
-template <typename E>
+// NP widest-path problems from (to) one vertex s, side by side in one
+// launch: problem q relaxes over the rows of A[q] and writes out[q].
+template <typename E, int NP>
 struct WidestArgs {
-    const E *w;          // rows = sources of edges (w, or wt for the target direction)
-    int64_t ldw;
+    sweep::Run<uint32_t, E, NP> run;
     int32_t m;
-    int32_t s;           // source (or target) vertex
-    int32_t vec;         // rows of w allow 8/16-byte accesses
-    E *out;              // m widths, out[s] = 0
-    uint32_t *x;         // m values, in place
-    uint8_t *changed;    // m flags
-    int32_t *front[2];   // frontier lists (m entries each)
-    int32_t *fcount;     // [0], [1]: frontier sizes; [2]: sweeps run
-    GridBar *bar;
-    int32_t *err;
-    int64_t spin_limit;
+    int32_t s;   // source (target, with transposed weights)
+    E *out[NP];  // m widths each, out[q][s] = 0
 };
 
-template <typename E>
-__global__ __launch_bounds__(256) void k_widest(WidestArgs<E> a) {
+// x = MAX at s, 0 elsewhere; stamps 0; first frontier {s}; counters and
+// barrier cleared.  A plain launch ahead of the sweeps, so that the sweeps
+// need no barrier before their first step.
+template <typename E, int NP>
+__global__ __launch_bounds__(256) void k_widest_init(WidestArgs<E, NP> a) {
     const int32_t m = a.m;
-    // x = MAX at s, 0 elsewhere; frontier = {s}
-    for (int32_t j = blockIdx.x * 256 + threadIdx.x; j < m; j += gridDim.x * 256) {
-        a.x[j] = j == a.s ? (uint32_t)max_value<E>() : 0u;
-        a.changed[j] = 0;
+    for (int q = 0; q < NP; ++q) {
+        const sweep::Problem<uint32_t, E> &P = a.run.p[q];
+        for (int32_t j = blockIdx.x * 256 + threadIdx.x; j < m; j += gridDim.x * 256) {
+            P.x[j] = j == a.s ? (uint32_t)max_value<E>() : 0u;
+            P.stamp[j] = 0;
+        }
+        if (blockIdx.x == 0 && threadIdx.x < 4) P.count[threadIdx.x] = threadIdx.x == 0 ? 1 : 0;
+        if (blockIdx.x == 0 && threadIdx.x == 0) P.front[0][0] = a.s;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        a.front[0][0] = a.s;
-        a.fcount[0] = 1;
-        a.fcount[1] = 0;
-    }
-    if (!grid_sync(a.bar, a.spin_limit)) goto stuck;
-    {
-        sweep::Buffers<uint32_t> b{a.x, {a.front[0], a.front[1]}, a.fcount, a.changed, a.bar, a.err, a.spin_limit,
-                                   m + 1};
-        const bool ok = sweep::run<uint32_t, E>(
-            a.w, a.ldw, m, a.vec != 0, b, [](uint32_t xi, uint32_t e) { return min(xi, e); },
-            [](int32_t) { return true; });
-        if (!ok) goto stuck;
-        for (int32_t j = blockIdx.x * 256 + threadIdx.x; j < m; j += gridDim.x * 256)
-            a.out[j] = j == a.s ? (E)0 : (E)a.x[j];
+    uint32_t *bar = reinterpret_cast<uint32_t *>(a.run.bar);
+    for (size_t i = blockIdx.x * 256 + threadIdx.x; i < grid::BAR_WORDS; i += gridDim.x * 256) bar[i] = 0u;
+}
+
+template <typename E, int NP>
+__global__ __launch_bounds__(256) void k_widest(WidestArgs<E, NP> a) {
+    const int32_t m = a.m;
+    const bool ok = sweep::run<uint32_t, E, NP>(
+        a.run, m, [](uint32_t xi, uint32_t e) { return min(xi, e); }, [](int32_t) { return true; });
+    if (!ok) {
+        if (threadIdx.x == 0) set_device_error(a.run.err, SCHULZE_EDEVICE);
         return;
     }
-stuck:
-    if (threadIdx.x == 0) set_device_error(a.err, SCHULZE_EDEVICE);
+    for (int q = 0; q < NP; ++q)
+        for (int32_t j = blockIdx.x * 256 + threadIdx.x; j < m; j += gridDim.x * 256)
+            a.out[q][j] = j == a.s ? (E)0 : (E)a.run.p[q].x[j];
 }
 
 // ------------------------------------------------------------------ verdict
@@ -189,56 +186,52 @@ __global__ __launch_bounds__(256) void k_verdict(const E *__restrict__ from, con
     }
 }
 
-// 8-byte (uint16) or 16-byte (int32) row accesses of a matrix at p, pitch ld.
-template <typename E>
-bool sweep_vec_ok(const void *p, int64_t ld) {
-    return (reinterpret_cast<uintptr_t>(p) % (4 * sizeof(E)) == 0) && (ld % 4 == 0);
+// Scratch of one launch of np widest-path problems: per problem values,
+// stamps, two frontier lists and counters; then the barrier.
+size_t widest_scratch_bytes(int32_t m, int np) {
+    const size_t v = round_up(sizeof(uint32_t) * (size_t)m, 256);
+    return (size_t)np * (4 * v + 256) + round_up(grid::BAR_BYTES, 256);
 }
 
-// Scratch of one widest-path launch: values, flags, two frontiers, counters, barrier.
-size_t widest_scratch_bytes(int32_t m) {
-    const size_t xbytes = round_up(sizeof(uint32_t) * (size_t)m, 256);
-    const size_t cbytes = round_up((size_t)m, 256);
-    const size_t fbytes = round_up(sizeof(int32_t) * (size_t)m, 256);
-    return xbytes + cbytes + 2 * fbytes + 256;
-}
-
-// Widest paths from src over the rows of w, with the sweep state in `base`
-// (widest_scratch_bytes(m) bytes of device memory; the counters and barrier
-// are cleared here, everything else is written before it is read).  `timed`
-// brackets the launch with the context's timing events.
-template <typename E>
-int widest_in(schulze_ctx *ctx, hipStream_t s, const E *w, int64_t ldw, int32_t m, int32_t src, E *out, char *base,
-              bool timed) {
-    const size_t xbytes = round_up(sizeof(uint32_t) * (size_t)m, 256);
-    const size_t cbytes = round_up((size_t)m, 256);
-    const size_t fbytes = round_up(sizeof(int32_t) * (size_t)m, 256);
-    int rc;
-    WidestArgs<E> a;
-    a.w = w;
-    a.ldw = ldw;
+// Widest paths from src over the rows of A[q] (q < NP) into out[q], with
+// the sweep state in `base` (widest_scratch_bytes(m, NP) bytes of device
+// memory, all of it set by the init launch before it is read).  `timed`
+// brackets both launches with the context's timing events.
+template <typename E, int NP>
+int widest_in(schulze_ctx *ctx, hipStream_t s, const E *const (&A)[NP], const int64_t (&ld)[NP], int32_t m,
+              int32_t src, E *const (&out)[NP], char *base, bool timed) {
+    const size_t v = round_up(sizeof(uint32_t) * (size_t)m, 256);
+    WidestArgs<E, NP> a;
+    for (int q = 0; q < NP; ++q) {
+        char *p = base + (size_t)q * (4 * v + 256);
+        sweep::Problem<uint32_t, E> &P = a.run.p[q];
+        P.A = A[q];
+        P.ld = ld[q];
+        P.vec = sweep::vec_ok<E>(A[q], ld[q]) ? 1 : 0;
+        P.x = reinterpret_cast<uint32_t *>(p);
+        P.stamp = reinterpret_cast<int32_t *>(p + v);
+        P.front[0] = reinterpret_cast<int32_t *>(p + 2 * v);
+        P.front[1] = reinterpret_cast<int32_t *>(p + 3 * v);
+        P.count = reinterpret_cast<int32_t *>(p + 4 * v);
+        a.out[q] = out[q];
+    }
+    a.run.max_sweeps = m + 1;
+    a.run.bar = reinterpret_cast<GridBar *>(base + (size_t)NP * (4 * v + 256));
+    a.run.err = ctx->err;
+    a.run.spin_limit = (int64_t)1 << 24;
     a.m = m;
     a.s = src;
-    a.vec = sweep_vec_ok<E>(w, ldw) ? 1 : 0;
-    a.out = out;
-    a.x = reinterpret_cast<uint32_t *>(base);
-    a.changed = reinterpret_cast<uint8_t *>(base + xbytes);
-    a.front[0] = reinterpret_cast<int32_t *>(base + xbytes + cbytes);
-    a.front[1] = reinterpret_cast<int32_t *>(base + xbytes + cbytes + fbytes);
-    int32_t *tail = reinterpret_cast<int32_t *>(base + xbytes + cbytes + 2 * fbytes);
-    a.fcount = tail;
-    a.bar = reinterpret_cast<GridBar *>(tail + 8);
-    a.err = ctx->err;
-    a.spin_limit = (int64_t)1 << 24;
-    if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(tail), 64, 0u)) != SCHULZE_OK) return rc;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_widest<E>, 256, 0) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_widest<E, NP>, 256, 0) != hipSuccess || per_cu < 1)
         return SCHULZE_EDEVICE;
-    const int64_t G = sweep::grid_size(m, (int64_t)ctx->num_cus * std::min(per_cu, 2));
-    void *args[] = {&a};
+    const int64_t G = sweep::grid_size(m, NP, (int64_t)ctx->num_cus * std::min(per_cu, 2));
     int tok = -1;
     if (timed) timing_begin(ctx, K_WIDEST, s, &tok);
-    hipError_t e = hipLaunchCooperativeKernel((const void *)k_widest<E>, dim3((unsigned)G), dim3(256), args, 0, s);
+    k_widest_init<E, NP><<<dim3((unsigned)std::min<int64_t>(ceil_div(m, 256), 1024)), dim3(256), 0, s>>>(a);
+    hipError_t e = hipGetLastError();
+    void *args[] = {&a};
+    if (e == hipSuccess)
+        e = hipLaunchCooperativeKernel((const void *)k_widest<E, NP>, dim3((unsigned)G), dim3(256), args, 0, s);
     if (timed) timing_end(ctx, tok, s);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -249,25 +242,32 @@ int widest_in(schulze_ctx *ctx, hipStream_t s, const E *w, int64_t ldw, int32_t 
 
 template <typename E>
 int widest(schulze_ctx *ctx, hipStream_t s, const E *w, int64_t ldw, int32_t m, int32_t src, E *out) {
-    int rc = ws_reserve(ctx, WS_VERIFY, widest_scratch_bytes(m));
+    int rc = ws_reserve(ctx, WS_VERIFY, widest_scratch_bytes(m, 1));
     if (rc != SCHULZE_OK) return rc;
-    return widest_in<E>(ctx, s, w, ldw, m, src, out, static_cast<char *>(ctx->ws[WS_VERIFY]), true);
+    const E *const A[1] = {w};
+    const int64_t ld[1] = {ldw};
+    E *const o[1] = {out};
+    return widest_in<E, 1>(ctx, s, A, ld, m, src, o, static_cast<char *>(ctx->ws[WS_VERIFY]), true);
 }
 
-// Both widest-path directions and the verdict, with the sweep state in base
-// (nullptr: the context's workspace).
+// Both widest-path directions (one launch) and the verdict, with the sweep
+// state in base (nullptr: the context's workspace).
 template <typename E>
 int verify_all(schulze_ctx *ctx, hipStream_t s, const E *w, int64_t ldw, const E *wt, int64_t ldwt, int32_t m,
                int32_t cand, const float *score, E *p_from, E *p_to, int32_t *verdict, int32_t *tied, char *base) {
     int rc;
+    const E *const A[2] = {w, wt};
+    const int64_t ld[2] = {ldw, ldwt};
+    E *const out[2] = {p_from, p_to};
     if (base) {
-        if ((rc = widest_in<E>(ctx, s, w, ldw, m, cand, p_from, base, false)) != SCHULZE_OK) return rc;
-        if ((rc = widest_in<E>(ctx, s, wt, ldwt, m, cand, p_to, base, false)) != SCHULZE_OK) return rc;
+        if ((rc = widest_in<E, 2>(ctx, s, A, ld, m, cand, out, base, false)) != SCHULZE_OK) return rc;
         k_verdict<E><<<dim3(1), dim3(256), 0, s>>>(p_from, p_to, m, cand, score, verdict, tied);
         return launch_status();
     }
-    if ((rc = widest<E>(ctx, s, w, ldw, m, cand, p_from)) != SCHULZE_OK) return rc;
-    if ((rc = widest<E>(ctx, s, wt, ldwt, m, cand, p_to)) != SCHULZE_OK) return rc;
+    if ((rc = ws_reserve(ctx, WS_VERIFY, widest_scratch_bytes(m, 2))) != SCHULZE_OK) return rc;
+    if ((rc = widest_in<E, 2>(ctx, s, A, ld, m, cand, out, static_cast<char *>(ctx->ws[WS_VERIFY]), true)) !=
+        SCHULZE_OK)
+        return rc;
     SCHULZE_LAUNCH(ctx, K_VERDICT, s,
                    k_verdict<E><<<dim3(1), dim3(256), 0, s>>>(p_from, p_to, m, cand, score, verdict, tied));
     return SCHULZE_OK;
@@ -344,7 +344,7 @@ extern "C" int schulze_verify_noalloc(schulze_ctx *ctx, void *stream, const void
     int rc = check_square(ctx, w, ldw, m, dtype);
     if (rc != SCHULZE_OK) return rc;
     if (!wt || ldwt < m || !p_from || !p_to || !verdict || cand < 0 || cand >= m) return SCHULZE_EINVAL;
-    if (widest_scratch_bytes(m) > VERIFY_SCRATCH_BYTES) return SCHULZE_EUNSUPPORTED;
+    if (widest_scratch_bytes(m, 2) > VERIFY_SCRATCH_BYTES) return SCHULZE_EUNSUPPORTED;
     if (!ctx->verify_scratch) return SCHULZE_EDEVICE;  // set when the context was created
     char *base = static_cast<char *>(ctx->verify_scratch);
     hipStream_t s = (hipStream_t)stream;
