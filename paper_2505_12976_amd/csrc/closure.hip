@@ -183,7 +183,7 @@ __device__ inline void acc_store_agent(const Acc<E, B> &a, E *dst, int64_t ld) {
 }
 
 template <typename E, int B>
-__global__ __launch_bounds__(256, (sizeof(E) == 2 || B < 128) ? 2 : 1) void k_fw_persist(PersistArgs<E> a) {
+__global__ __launch_bounds__(256, sizeof(E) == 2 ? 3 : (B < 128 ? 2 : 1)) void k_fw_persist(PersistArgs<E> a) {
     using C = Cfg<E, B>;
     constexpr int DS = diag_steps<E, B>();
     constexpr int DIAG_LDS = diag_lds_elems<E, B, DS, true>();

@@ -17,6 +17,7 @@ typedef __attribute__((ext_vector_type(2))) unsigned short us2;
 #define FW_GLOBAL __attribute__((address_space(1)))
 #define FW_LDS __attribute__((address_space(3)))
 typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));  // 16 bytes, not a class type
+typedef uint32_t v2u32 __attribute__((ext_vector_type(2)));  // 8 bytes
 template <typename U, typename T>
 __device__ __forceinline__ U *retype(T *p) {
     return reinterpret_cast<U *>(p);
@@ -100,6 +101,70 @@ __device__ inline void acc_store(const Acc<E, B> &a, DstP dst, int64_t ld) {
     }
 }
 
+// The four k of one step of the 16-bit product: A values av (four k per
+// row, one 8-byte read each), B rows at bs (pitch ldb elements, this
+// thread's columns).  The B row of step k+1 is read before the products of
+// step k (the scheduling barrier keeps it there), so that only the first
+// read of each step waits.
+template <int B>
+__device__ __forceinline__ void step4_16(Acc<uint16_t, B> &a, const v2u32 (&av)[Cfg<uint16_t, B>::TM],
+                                         const FW_LDS uint16_t *bs, int ldb) {
+    using C = Cfg<uint16_t, B>;
+    using L = Lane<uint16_t>;
+    using W = typename L::W;
+    constexpr int TM = C::TM, WN = C::WN;
+    W bq[2][WN];
+    const FW_LDS W *b0 = (const FW_LDS W *)bs;
+    for (int jj = 0; jj < WN; ++jj) bq[0][jj] = b0[jj];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+        if (kk + 1 < 4) {
+            const FW_LDS W *bn = (const FW_LDS W *)(bs + (kk + 1) * ldb);
+            for (int jj = 0; jj < WN; ++jj) bq[(kk + 1) & 1][jj] = bn[jj];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        const W *bp = bq[kk & 1];
+        for (int ii = 0; ii < TM; ++ii) {
+            const uint32_t word = kk < 2 ? av[ii].x : av[ii].y;
+            const unsigned short av16 = (kk & 1) ? (unsigned short)(word >> 16) : (unsigned short)word;
+            const W aa = L::splat(av16);
+            // all mins of the row before its maxes: a max right after the
+            // min it reads needs a wait state when that min takes the high
+            // half of its operand (the compiler inserts an s_nop there)
+            W t[WN];
+            for (int jj = 0; jj < WN; ++jj) t[jj] = __builtin_elementwise_min(aa, bp[jj]);
+            for (int jj = 0; jj < WN; ++jj) a.c[ii][jj] = __builtin_elementwise_max(a.c[ii][jj], t[jj]);
+        }
+    }
+}
+
+// Direct-to-LDS staging of the 16-bit product with B = 128: chunks of 32 k
+// (an A chunk of B rows x 64 bytes and a B chunk of 32 rows x 256 bytes),
+// double buffered, so that the next chunk streams into LDS while the
+// current one is multiplied and no registers hold staged data.  Each
+// wavefront instruction moves one contiguous kilobyte (lane l to byte 16 l),
+// so the LDS rows are unpadded: the A reads of a wavefront hit four
+// addresses (broadcast) and the B reads sixteen consecutive 16-byte groups.
+struct Dma128 {
+    static constexpr int B = 128, KC = 32;
+    static constexpr int AS = B * KC, BS = KC * B;     // elements per chunk
+    static constexpr int LDS_ELEMS = 2 * (AS + BS);    // two buffers
+};
+
+template <typename PA, typename PB>
+__device__ __forceinline__ void dma_chunk128(PA A, int64_t lda, PB Bm, int64_t ldb, int kc, FW_LDS uint16_t *As,
+                                             FW_LDS uint16_t *Bs) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    // A: instruction i = rows 16 i .. 16 i + 15, four 16-byte pieces each
+    for (int i = w; i < 8; i += 4)
+        __builtin_amdgcn_global_load_lds(A + (int64_t)(16 * i + (l >> 2)) * lda + kc + (l & 3) * 8, As + i * 512, 16,
+                                         0, 0);
+    // B: instruction i = k rows 4 i .. 4 i + 3, sixteen 16-byte pieces each
+    for (int i = w; i < 8; i += 4)
+        __builtin_amdgcn_global_load_lds(Bm + (int64_t)(kc + 4 * i + (l >> 4)) * ldb + (l & 15) * 8, Bs + i * 512, 16,
+                                         0, 0);
+}
+
 // a = max(a, A (x) Bm) with A, Bm B x B tiles in global memory (row pitches
 // lda, ldb).  lds holds Cfg::LDS_ELEMS elements.  Starts and ends with a
 // barrier, so A or Bm may be the tile that the caller overwrites afterwards.
@@ -109,9 +174,35 @@ __device__ inline void acc_product(Acc<E, B> &a, PA A, int64_t lda, PB Bm, int64
     using L = Lane<E>;
     using W = typename L::W;
     constexpr int TM = C::TM, TN = C::TN, WN = C::WN, KC = C::KC, LA = C::LA, LB = C::LB;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    if constexpr (sizeof(E) == 2 && B == 128) {
+        using D = Dma128;
+        static_assert(D::LDS_ELEMS <= C::LDS_ELEMS, "LDS of the staged product");
+        FW_LDS uint16_t *buf = (FW_LDS uint16_t *)lds;
+        __syncthreads();  // the previous user of the LDS is done
+        dma_chunk128(A, lda, Bm, ldb, 0, buf, buf + D::AS);
+#pragma unroll 1
+        for (int c = 0; c < B / D::KC; ++c) {
+            FW_LDS uint16_t *As = buf + (c & 1) * (D::AS + D::BS);
+            FW_LDS uint16_t *Bs = As + D::AS;
+            __builtin_amdgcn_s_waitcnt(0);  // this wave's pieces of chunk c are in LDS
+            __syncthreads();                // everyone's are, and chunk c-1 is consumed
+            if (c + 1 < B / D::KC) {
+                FW_LDS uint16_t *An = buf + ((c + 1) & 1) * (D::AS + D::BS);
+                dma_chunk128(A, lda, Bm, ldb, (c + 1) * D::KC, An, An + D::AS);
+            }
+#pragma unroll 1
+            for (int k = 0; k < D::KC; k += 4) {
+                v2u32 av[TM];
+                for (int ii = 0; ii < TM; ++ii) av[ii] = *(const FW_LDS v2u32 *)(As + (ty * TM + ii) * D::KC + k);
+                step4_16<B>(a, av, &Bs[k * B + tx * TN], B);
+            }
+        }
+        __syncthreads();
+        return;
+    }
     E *As = lds;
     E *Bs = lds + B * LA;
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     for (int kc = 0; kc < B; kc += KC) {
         __syncthreads();
         copy_block<E>(As, LA, A + kc, lda, B, KC);
