@@ -173,7 +173,8 @@ __device__ inline void raise_flag(int32_t *f) {
 template <typename E, int B>
 __device__ inline void acc_store_agent(const Acc<E, B> &a, E *dst, int64_t ld) {
     using C = Cfg<E, B>;
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int t = lane_tid(), tx = t & 15, ty = t >> 4;
+    dst = scalar_ptr(dst);
     for (int ii = 0; ii < C::TM; ++ii) {
         uint32_t *row = reinterpret_cast<uint32_t *>(dst + (int64_t)(ty * C::TM + ii) * ld + tx * C::TN);
         for (int jj = 0; jj < C::WN; ++jj)
@@ -183,7 +184,7 @@ __device__ inline void acc_store_agent(const Acc<E, B> &a, E *dst, int64_t ld) {
 }
 
 template <typename E, int B>
-__global__ __launch_bounds__(256, sizeof(E) == 2 ? 3 : (B < 128 ? 2 : 1)) void k_fw_persist(PersistArgs<E> a) {
+__global__ __launch_bounds__(256, sizeof(E) == 2 ? 4 : (B < 128 ? 2 : 1)) void k_fw_persist(PersistArgs<E> a) {
     using C = Cfg<E, B>;
     constexpr int DS = diag_steps<E, B>();
     constexpr int DIAG_LDS = diag_lds_elems<E, B, DS, true>();
@@ -213,6 +214,10 @@ __global__ __launch_bounds__(256, sizeof(E) == 2 ? 3 : (B < 128 ? 2 : 1)) void k
         return;
     }
 
+    // owned[q] through a scalar register: tile numbers are uniform, and
+    // everything derived from them (tile addresses, flags) then stays in
+    // scalar registers rather than taking vector ones
+    auto tile_at = [&](int32_t q) { return __builtin_amdgcn_readfirstlane(owned[q]); };
     auto tileP = [&](int32_t I, int32_t J) { return a.P + (int64_t)I * B * a.ld + (int64_t)J * B; };
     auto ring = [&](int32_t r, int32_t slot) { return a.ring + slot_index(r, slot, nb) * tile_elems; };
     auto flag = [&](int32_t r, int32_t slot) { return a.flags + slot_index(r, slot, nb); };
@@ -254,7 +259,7 @@ __global__ __launch_bounds__(256, sizeof(E) == 2 ? 3 : (B < 128 ? 2 : 1)) void k
     };
     auto has_panels = [&](int32_t r) {
         for (int32_t q = 0; q < no; ++q) {
-            const int32_t I = owned[q] / nb, J = owned[q] % nb;
+            const int32_t t_ = tile_at(q), I = t_ / nb, J = t_ % nb;
             if ((I == r) != (J == r)) return true;
         }
         return false;
@@ -265,7 +270,7 @@ __global__ __launch_bounds__(256, sizeof(E) == 2 ? 3 : (B < 128 ? 2 : 1)) void k
     auto run_panels = [&](int32_t r) {
         __builtin_amdgcn_s_setprio(3);
         for (int32_t q = 0; q < no; ++q) {
-            const int32_t I = owned[q] / nb, J = owned[q] % nb;
+            const int32_t t_ = tile_at(q), I = t_ / nb, J = t_ % nb;
             if ((I == r) == (J == r)) continue;
             do_panel(r, I, J);
         }
@@ -309,7 +314,7 @@ __global__ __launch_bounds__(256, sizeof(E) == 2 ? 3 : (B < 128 ? 2 : 1)) void k
             if (r < 0) continue;
             // the other tiles that feed round r+1
             for (int32_t q = 0; q < no; ++q) {
-                const int32_t I = owned[q] / nb, J = owned[q] % nb;
+                const int32_t t_ = tile_at(q), I = t_ / nb, J = t_ % nb;
                 if (I == r || J == r || (I != r + 1 && J != r + 1) || (I == r + 1 && J == r + 1)) continue;
                 if (!do_rest(r, I, J, nullptr)) goto stuck;
             }
@@ -342,8 +347,8 @@ __global__ __launch_bounds__(256, sizeof(E) == 2 ? 3 : (B < 128 ? 2 : 1)) void k
         if (threadIdx.x == 0) probe_seen = 0;
         __syncthreads();
         for (int32_t q = 0; q < no; ++q) {
-            const int32_t I = owned[q] / nb, J = owned[q] % nb;
-            if (I == r || J == r || I == r + 1 || J == r + 1 || owned[q] == ahead) continue;
+            const int32_t t_ = tile_at(q), I = t_ / nb, J = t_ % nb;
+            if (I == r || J == r || I == r + 1 || J == r + 1 || t_ == ahead) continue;
             if (next_panels && probe_seen) {  // (uniform: written before a barrier)
                 run_panels(r + 1);
                 panels_done = r + 1;

@@ -79,11 +79,35 @@ __device__ inline void copy_block(E *__restrict__ dst, int dst_pitch, SrcP src, 
     }
 }
 
+// p through a scalar register: the per-lane addresses built from it are
+// rebuilt at each use instead of being kept live in vector registers
+// across the products in between.
+template <typename P>
+__device__ __forceinline__ P scalar_ptr(P p) {
+    const uint64_t u = (uint64_t)p;  // uniform: the same tile for every lane
+    // (readfirstlane returns int: widen through uint32_t, never sign-extend)
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    uint64_t v = ((uint64_t)hi << 32) | (uint64_t)lo;
+    asm volatile("" : "+s"(v));
+    return (P)v;
+}
+
+// The thread index, opaque to the optimiser: per-lane offsets built from it
+// are computed where they are used, not hoisted to the kernel's entry and
+// kept live in vector registers for its whole run.
+__device__ __forceinline__ int lane_tid() {
+    int t = (int)threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
 template <typename E, int B, typename SrcP>
 __device__ inline void acc_load(Acc<E, B> &a, SrcP src, int64_t ld) {
     using C = Cfg<E, B>;
     using W = typename Lane<E>::W;
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int t = lane_tid(), tx = t & 15, ty = t >> 4;
+    src = scalar_ptr(src);
     for (int ii = 0; ii < C::TM; ++ii) {
         const auto row = retype<const W>(src + (int64_t)(ty * C::TM + ii) * ld + tx * C::TN);
         for (int jj = 0; jj < C::WN; ++jj) a.c[ii][jj] = row[jj];
@@ -94,7 +118,8 @@ template <typename E, int B, typename DstP>
 __device__ inline void acc_store(const Acc<E, B> &a, DstP dst, int64_t ld) {
     using C = Cfg<E, B>;
     using W = typename Lane<E>::W;
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int t = lane_tid(), tx = t & 15, ty = t >> 4;
+    dst = scalar_ptr(dst);
     for (int ii = 0; ii < C::TM; ++ii) {
         const auto row = retype<W>(dst + (int64_t)(ty * C::TM + ii) * ld + tx * C::TN);
         for (int jj = 0; jj < C::WN; ++jj) row[jj] = a.c[ii][jj];
@@ -154,7 +179,7 @@ struct Dma128 {
 template <typename PA, typename PB>
 __device__ __forceinline__ void dma_chunk128(PA A, int64_t lda, PB Bm, int64_t ldb, int kc, FW_LDS uint16_t *As,
                                              FW_LDS uint16_t *Bs) {
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int t = lane_tid(), w = t >> 6, l = t & 63;
     // A: instruction i = rows 16 i .. 16 i + 15, four 16-byte pieces each
     for (int i = w; i < 8; i += 4)
         __builtin_amdgcn_global_load_lds(A + (int64_t)(16 * i + (l >> 2)) * lda + kc + (l & 3) * 8, As + i * 512, 16,
@@ -179,6 +204,10 @@ __device__ inline void acc_product(Acc<E, B> &a, PA A, int64_t lda, PB Bm, int64
         using D = Dma128;
         static_assert(D::LDS_ELEMS <= C::LDS_ELEMS, "LDS of the staged product");
         FW_LDS uint16_t *buf = (FW_LDS uint16_t *)lds;
+        // (scalar operand addresses: the per-lane load addresses are built
+        // here, not hoisted out of the caller's loops)
+        A = scalar_ptr(A);
+        Bm = scalar_ptr(Bm);
         __syncthreads();  // the previous user of the LDS is done
         dma_chunk128(A, lda, Bm, ldb, 0, buf, buf + D::AS);
 #pragma unroll 1
@@ -292,10 +321,11 @@ __device__ inline E lane_get(const typename Lane<E>::W *v, int b) {
 }
 
 // Steps per barrier of the diagonal closure: 4 where the tile's registers
-// leave room for the copies, else 2.
+// leave room for the copies, else 2; 1 for 16-bit tiles of 128, so that
+// the closure call fits the register budget of four workgroups per CU.
 template <typename E, int B>
 constexpr int diag_steps() {
-    return B <= 64 ? 4 : 2;
+    return B <= 64 ? 4 : (sizeof(E) == 2 ? 1 : 2);
 }
 
 template <typename E, int B, int S_ = diag_steps<E, B>()>
@@ -309,9 +339,12 @@ struct Diag {
     static constexpr int RP = RA / PER;     // lanes per column slice
     static constexpr int S = S_;            // steps per barrier
     // one LDS slot: S rows (thread tx's columns at tx*CW ..), S columns
-    // (thread ty's rows at ty*RA ..), the S x S block
-    static constexpr int SLOT = 2 * S * B + S * S;
+    // (thread ty's rows at ty*RA ..), the S x S block; padded to 16 bytes,
+    // so that the second slot keeps the rows' and columns' 4-byte (and
+    // wider) accesses aligned whatever S is
+    static constexpr int SLOT = (2 * S * B + S * S + 7) / 8 * 8;
     static constexpr int LDS_ELEMS = 2 * SLOT;
+    static_assert(SLOT * sizeof(E) % 16 == 0 && B * sizeof(E) % 16 == 0, "aligned LDS slots and rows");
 
     // rows and columns 16 KB + kk .. + S-1 into the slot at q
     template <int KB>
@@ -419,6 +452,7 @@ __device__ __attribute__((always_inline)) inline void diag_close_body(SrcP src, 
     using W = typename D::W;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     FW_LDS E *lb = (FW_LDS E *)buf;  // (an LDS address: local accesses, also in an outlined call)
+    src = scalar_ptr(src);
     // the tile may just have been stored by other threads of the workgroup
     // (with another thread-to-element map)
     __syncthreads();
@@ -429,6 +463,7 @@ __device__ __attribute__((always_inline)) inline void diag_close_body(SrcP src, 
         {
             constexpr int V = 16 / (int)sizeof(E);
             constexpr int VPR = B / V;
+#pragma unroll 4
             for (int q = threadIdx.x; q < B * VPR; q += 256) {
                 const int r = q / VPR, cv = q % VPR;
                 *(FW_LDS v4u32 *)(lb + r * B + cv * V) = *retype<const v4u32>(src + (int64_t)r * lds_ + cv * V);
@@ -469,6 +504,8 @@ __device__ __attribute__((always_inline)) inline void diag_close_body(SrcP src, 
         __syncthreads();
         constexpr int V = 16 / (int)sizeof(E);
         constexpr int VPR = B / V;
+        dst = scalar_ptr(dst);
+#pragma unroll 4
         for (int q = threadIdx.x; q < B * VPR; q += 256) {
             const int r = q / VPR, cv = q % VPR;
             const v4u32 x = *(const FW_LDS v4u32 *)(lb + r * B + cv * V);
