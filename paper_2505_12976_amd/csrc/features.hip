@@ -276,33 +276,54 @@ __global__ __launch_bounds__(256) void k_feature_rows(const E *__restrict__ d, i
     }
 }
 
-// Combine the S slices' partial statistics of each candidate.
+// Combine the S slices' partial statistics of each candidate: a workgroup
+// takes 64 candidates, its four wavefronts every fourth slice, and the four
+// partial results meet in LDS (a thread per candidate alone left too few
+// workgroups to keep the reads in flight).
 __global__ __launch_bounds__(256) void k_feature_reduce(int32_t m, int32_t S, RawStats part, RawStats st) {
-    const int32_t x = blockIdx.x * 256 + threadIdx.x;
-    if (x >= m) return;
-    int32_t cope = 0, ties = 0, mx_out = 0, mx_in = 0, mn = INT32_MAX, mxm = INT32_MIN;
-    unsigned long long borda = 0, s_out = 0, s_in = 0;
-    for (int32_t sl = 0; sl < S; ++sl) {
-        const int64_t q = (int64_t)sl * m + x;
-        cope += part.cope[q];
-        ties += part.ties[q];
-        borda += part.borda[q];
-        s_out += part.sum_out[q];
-        s_in += part.sum_in[q];
-        mx_out = max(mx_out, part.max_out[q]);
-        mx_in = max(mx_in, part.max_in[q]);
-        mn = min(mn, part.min_marg[q]);
-        mxm = max(mxm, part.max_marg[q]);
+    __shared__ int32_t si[3][64][6];
+    __shared__ unsigned long long su[3][64][3];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int32_t x = blockIdx.x * 64 + lane;
+    int32_t v[6] = {0, 0, 0, 0, INT32_MAX, INT32_MIN};  // cope, ties, max out, max in, min margin, max margin
+    unsigned long long u[3] = {0, 0, 0};                // borda, sum out, sum in
+    if (x < m)
+        for (int32_t sl = wv; sl < S; sl += 4) {
+            const int64_t q = (int64_t)sl * m + x;
+            v[0] += part.cope[q];
+            v[1] += part.ties[q];
+            v[2] = max(v[2], part.max_out[q]);
+            v[3] = max(v[3], part.max_in[q]);
+            v[4] = min(v[4], part.min_marg[q]);
+            v[5] = max(v[5], part.max_marg[q]);
+            u[0] += part.borda[q];
+            u[1] += part.sum_out[q];
+            u[2] += part.sum_in[q];
+        }
+    if (wv > 0) {
+        for (int k = 0; k < 6; ++k) si[wv - 1][lane][k] = v[k];
+        for (int k = 0; k < 3; ++k) su[wv - 1][lane][k] = u[k];
     }
-    st.cope[x] = cope;
-    st.ties[x] = ties;
-    st.borda[x] = borda;
-    st.sum_out[x] = s_out;
-    st.sum_in[x] = s_in;
-    st.max_out[x] = mx_out;
-    st.max_in[x] = mx_in;
-    st.min_marg[x] = m > 1 ? mn : 0;
-    st.max_marg[x] = m > 1 ? mxm : 0;
+    __syncthreads();
+    if (wv != 0 || x >= m) return;
+    for (int o = 0; o < 3; ++o) {
+        v[0] += si[o][lane][0];
+        v[1] += si[o][lane][1];
+        v[2] = max(v[2], si[o][lane][2]);
+        v[3] = max(v[3], si[o][lane][3]);
+        v[4] = min(v[4], si[o][lane][4]);
+        v[5] = max(v[5], si[o][lane][5]);
+        for (int k = 0; k < 3; ++k) u[k] += su[o][lane][k];
+    }
+    st.cope[x] = v[0];
+    st.ties[x] = v[1];
+    st.max_out[x] = v[2];
+    st.max_in[x] = v[3];
+    st.min_marg[x] = m > 1 ? v[4] : 0;
+    st.max_marg[x] = m > 1 ? v[5] : 0;
+    st.borda[x] = u[0];
+    st.sum_out[x] = u[1];
+    st.sum_in[x] = u[2];
 }
 
 // Maxima over candidates of the Copeland score, the largest outgoing weight
@@ -423,7 +444,7 @@ int run_features(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32
             : launch_rows<E, SBV, false>(ctx, s, d, ldd, m, mode, part, vec, w, ldw, wt, ldwt, S);
     if (rc != SCHULZE_OK) return rc;
     SCHULZE_LAUNCH(ctx, K_FEATURES, s,
-                   k_feature_reduce<<<dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s>>>(m, S, part, st));
+                   k_feature_reduce<<<dim3((unsigned)ceil_div(m, 64)), dim3(256), 0, s>>>(m, S, part, st));
     const dim3 vg((unsigned)ceil_div(m, 256));
     SCHULZE_LAUNCH(ctx, K_FEATURES, s, k_feature_max<<<vg, dim3(256), 0, s>>>(m, st, mx));
     SCHULZE_LAUNCH(ctx, K_FEATURES, s, k_feature_norm<<<vg, dim3(256), 0, s>>>(m, st, n_voters, mx, feat));

@@ -201,12 +201,14 @@ __global__ __launch_bounds__(256) void k_scan_long_vec(const uint16_t *__restric
 
 // Short rows (L <= 64): a wavefront takes 64 / L ballots at once (at most
 // SHORT_BPW), one lane per entry, SHORT_PER_WAVE such steps with all their
-// loads issued first; a ballot's listed length is the first padding lane of
-// its group (a wavefront ballot).
+// loads issued first, SHORT_ROUNDS times; a ballot's listed length is the
+// first padding lane of its group (a wavefront ballot).  (More ballots per
+// workgroup mean fewer list reservations on the two shared counters.)
 constexpr int SHORT_BPW = 4;
+constexpr int SHORT_ROUNDS = 4;
 __global__ __launch_bounds__(256) void k_scan_short(const void *__restrict__ ballots, int dtype32, int64_t n, int32_t L,
                                                     int32_t m, Meta meta, int32_t *err) {
-    constexpr int PER_WG = 4 * SHORT_PER_WAVE * SHORT_BPW;
+    constexpr int PER_WG = 4 * SHORT_PER_WAVE * SHORT_BPW * SHORT_ROUNDS;
     __shared__ int32_t lf[PER_WG], lt[PER_WG];
     __shared__ int32_t nf, nt;
     if (threadIdx.x == 0) nf = nt = 0;
@@ -216,34 +218,36 @@ __global__ __launch_bounds__(256) void k_scan_short(const void *__restrict__ bal
     const int32_t sub = lane / L, t = lane - sub * L;
     const bool lane_ok = sub < bpw;
     const uint64_t group_bits = (L == 64) ? ~0ull : ((1ull << L) - 1ull);
-    const int64_t v0 = ((int64_t)blockIdx.x * 4 + wave) * SHORT_PER_WAVE * bpw;
-    int32_t c[SHORT_PER_WAVE];
-    for (int q = 0; q < SHORT_PER_WAVE; ++q) {  // every load first
-        const int64_t v = v0 + (int64_t)q * bpw + sub;
-        c[q] = (lane_ok && v < n) ? read_id(ballots, dtype32, v * L + t) : -2;
-    }
     bool bad = false;
     unsigned long long k2 = 0;
-    for (int q = 0; q < SHORT_PER_WAVE; ++q) {
-        const int64_t v = v0 + (int64_t)q * bpw + sub;
-        const uint64_t pad = __ballot(c[q] < 0);  // -1 padding, -2 no ballot
-        const uint64_t mine = lane_ok ? (pad >> (sub * L)) & group_bits : group_bits;
-        const int k = mine ? (int)__builtin_ctzll(mine) : L;
-        const bool live = lane_ok && v < n;
-        const bool trunc = k < m - 1;
-        if (live && t < k) {
-            if (c[q] >= m)
-                bad = true;
-            else if (trunc && !meta.in_u[c[q]])  // a read first: frequent candidates are set once per cache
-                meta.in_u[c[q]] = 1;
+    for (int round = 0; round < SHORT_ROUNDS; ++round) {
+        const int64_t v0 = (((int64_t)blockIdx.x * SHORT_ROUNDS + round) * 4 + wave) * SHORT_PER_WAVE * bpw;
+        int32_t c[SHORT_PER_WAVE];
+        for (int q = 0; q < SHORT_PER_WAVE; ++q) {  // every load first
+            const int64_t v = v0 + (int64_t)q * bpw + sub;
+            c[q] = (lane_ok && v < n) ? read_id(ballots, dtype32, v * L + t) : -2;
         }
-        if (live && t == 0) {
-            meta.len[v] = k;
-            if (trunc) {
-                lt[atomicAdd(&nt, 1)] = (int32_t)v;
-                k2 += (unsigned long long)k * (k - 1) / 2;
-            } else {
-                lf[atomicAdd(&nf, 1)] = (int32_t)v;
+        for (int q = 0; q < SHORT_PER_WAVE; ++q) {
+            const int64_t v = v0 + (int64_t)q * bpw + sub;
+            const uint64_t pad = __ballot(c[q] < 0);  // -1 padding, -2 no ballot
+            const uint64_t mine = lane_ok ? (pad >> (sub * L)) & group_bits : group_bits;
+            const int k = mine ? (int)__builtin_ctzll(mine) : L;
+            const bool live = lane_ok && v < n;
+            const bool trunc = k < m - 1;
+            if (live && t < k) {
+                if (c[q] >= m)
+                    bad = true;
+                else if (trunc && !meta.in_u[c[q]])  // a read first: frequent candidates are set once per cache
+                    meta.in_u[c[q]] = 1;
+            }
+            if (live && t == 0) {
+                meta.len[v] = k;
+                if (trunc) {
+                    lt[atomicAdd(&nt, 1)] = (int32_t)v;
+                    k2 += (unsigned long long)k * (k - 1) / 2;
+                } else {
+                    lf[atomicAdd(&nf, 1)] = (int32_t)v;
+                }
             }
         }
     }
@@ -264,16 +268,17 @@ __global__ __launch_bounds__(256) void k_scan_short(const void *__restrict__ bal
 constexpr double ATOMIC_PAIR_COST = 1024.0;
 constexpr double BUCKETED_PAIR_COST = 512.0;
 
-__global__ __launch_bounds__(256) void k_route(int32_t m, Meta meta, int weighted, int64_t cap_words,
-                                               double pair_cost) {
-    __shared__ int32_t part[256];
-    const int32_t per = (m + 255) / 256;
+constexpr int ROUTE_THREADS = 1024;
+__global__ __launch_bounds__(ROUTE_THREADS) void k_route(int32_t m, Meta meta, int weighted, int64_t cap_words,
+                                                         double pair_cost) {
+    __shared__ int32_t part[ROUTE_THREADS];
+    const int32_t per = (m + ROUTE_THREADS - 1) / ROUTE_THREADS;
     const int32_t c0 = min(m, (int32_t)threadIdx.x * per), c1 = min(m, c0 + per);
     int32_t cnt = 0;
     for (int32_t c = c0; c < c1; ++c) cnt += meta.in_u[c] ? 1 : 0;
     part[threadIdx.x] = cnt;
     __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {  // inclusive scan
+    for (int off = 1; off < ROUTE_THREADS; off <<= 1) {  // inclusive scan
         const int32_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
         __syncthreads();
         part[threadIdx.x] += add;
@@ -289,7 +294,7 @@ __global__ __launch_bounds__(256) void k_route(int32_t m, Meta meta, int weighte
         }
     }
     if (threadIdx.x == 0) {
-        const int32_t nu = part[255];
+        const int32_t nu = part[ROUTE_THREADS - 1];
         const int32_t pitch = (nu + 1 + CT - 1) / CT * CT;  // room for one sentinel column
         const int64_t n_t = meta.ctr[1];
         unsigned long long k2 = 0;
@@ -1336,7 +1341,7 @@ extern "C" int schulze_pairwise(schulze_ctx *ctx, void *stream, const void *ball
     uint8_t *row_done = nullptr;  // rows finished by the bucketed count
     if (n > 0) {
         if (L <= 64) {
-            const int64_t per_wg = 4 * SHORT_PER_WAVE * std::min<int64_t>(SHORT_BPW, 64 / L);
+            const int64_t per_wg = 4 * SHORT_PER_WAVE * SHORT_ROUNDS * std::min<int64_t>(SHORT_BPW, 64 / L);
             SCHULZE_LAUNCH(ctx, K_BALLOT_SCAN, s,
                            k_scan_short<<<dim3((unsigned)ceil_div(n, per_wg)), dim3(256), 0, s>>>(
                                ballots, dtype32, n, L, m, meta, ctx->err));
@@ -1350,7 +1355,7 @@ extern "C" int schulze_pairwise(schulze_ctx *ctx, void *stream, const void *ball
                                ballots, dtype32, n, L, m, meta, ctx->err));
         }
         SCHULZE_LAUNCH(ctx, K_ROUTE, s,
-                       k_route<<<dim3(1), dim3(256), 0, s>>>(m, meta, voter_weight != nullptr,
+                       k_route<<<dim3(1), dim3(ROUTE_THREADS), 0, s>>>(m, meta, voter_weight != nullptr,
                                                              (int64_t)(tpos_bytes / sizeof(uint32_t)),
                                                              occ_ok ? BUCKETED_PAIR_COST : ATOMIC_PAIR_COST));
         {
