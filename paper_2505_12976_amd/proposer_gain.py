@@ -89,12 +89,18 @@ def study(ctx, params, no_condorcet=500, heldout=600, big=32, log=None):
     for el in workload.training_mixture(3005, heldout):
         r, cw, _ = run_election(ctx, params, el["ballots"], el["m"], el["n"])
         rows_mix.append((r, cw))
+        if log and len(rows_mix) % 200 == 0:
+            log(f"held-out mixture: {len(rows_mix)} elections")
     if log:
         log(f"held-out mixture: {len(rows_mix)} elections")
+    seen = 0
     for el in workload.near_impartial_mixture(3105, 10 * no_condorcet):
         r, cw, _ = run_election(ctx, params, el["ballots"], el["m"], el["n"])
+        seen += 1
         if not cw:
             rows_nc.append((r, cw))
+        if log and seen % 200 == 0:
+            log(f"near-impartial: {seen} elections, {len(rows_nc)} without a Condorcet winner")
         if len(rows_nc) >= no_condorcet:
             break
     if log:
