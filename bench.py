@@ -356,7 +356,7 @@ def bench_single(args, wl):
         out["roofline_count"] = {"bound": "hbm", "kernel": "count (scan, route, bucketed pairs, finish)",
                                  "achieved": ach / 1e9, "peak": HBM_BYTES / 1e9, "unit": "GB/s",
                                  "frac": ach / HBM_BYTES, "algorithmic_bytes": alg, "ms_per_step": count_ms,
-                                 "traffic": None}
+                                 "traffic": measured_traffic("count", wl.name)}
     if not args.no_oracle_check:
         gold = golden(wl.name)
         if gold is not None:
@@ -461,7 +461,8 @@ def bench_learned(args):
             kern[nm] = {"launches_per_call": launches / steps, "ms_per_call": total / steps,
                         "avg_launch_ms": total / launches}
     if "widest" in kern:
-        kern["widest"]["note"] = "one launch per direction runs all sweeps to the fixpoint"
+        kern["widest"]["note"] = ("one cooperative launch (after a plain init launch) runs the sweeps of both "
+                                  "directions to the fixpoint")
     # dominant kernel: the pass that reads d once and writes w, w^T and the
     # per-candidate statistics (HBM-bound)
     es = 4
