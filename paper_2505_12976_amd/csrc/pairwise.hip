@@ -60,13 +60,25 @@ struct Meta {
     int32_t *umap;           // candidate -> U-space index or -1
 };
 
-__device__ inline int32_t read_id(const void *ballots, int dtype32, int64_t idx) {
-    if (dtype32) {
-        int32_t v = static_cast<const int32_t *>(ballots)[idx];
-        return v < 0 ? -1 : v;
-    }
-    uint16_t v = static_cast<const uint16_t *>(ballots)[idx];
-    return v == 0xFFFF ? -1 : (int32_t)v;
+// Ballot entry idx, -1 for padding.  The id type is a template parameter:
+// a branch on it at every load made each load wait for the one before.
+template <bool I32>
+__device__ inline uint32_t load_raw(const void *ballots, int64_t idx) {
+    if constexpr (I32)
+        return static_cast<const uint32_t *>(ballots)[idx];
+    else
+        return static_cast<const uint16_t *>(ballots)[idx];
+}
+template <bool I32>
+__device__ inline int32_t raw_id(uint32_t raw) {
+    if constexpr (I32)
+        return (int32_t)raw < 0 ? -1 : (int32_t)raw;
+    else
+        return raw == 0xFFFFu ? -1 : (int32_t)raw;
+}
+template <bool I32>
+__device__ inline int32_t read_id(const void *ballots, int64_t idx) {
+    return raw_id<I32>(load_raw<I32>(ballots, idx));
 }
 
 // ------------------------------------------------------------------ scan
@@ -85,7 +97,8 @@ __device__ inline void record_ballots(Meta meta, int nf, const int32_t *lf, int 
 }
 
 // Long rows: one workgroup walks LONG_CHUNK ballots.
-__global__ __launch_bounds__(256) void k_scan_long(const void *__restrict__ ballots, int dtype32, int64_t n, int32_t L,
+template <bool I32>
+__global__ __launch_bounds__(256) void k_scan_long(const void *__restrict__ ballots, int64_t n, int32_t L,
                                                    int32_t m, Meta meta, int32_t *err) {
     __shared__ int32_t first_pad;
     __shared__ int32_t lf[LONG_CHUNK], lt[LONG_CHUNK];
@@ -102,7 +115,7 @@ __global__ __launch_bounds__(256) void k_scan_long(const void *__restrict__ ball
         __syncthreads();
         const int64_t base = v * (int64_t)L;
         for (int t = threadIdx.x; t < L; t += 256)
-            if (read_id(ballots, dtype32, base + t) < 0) {
+            if (read_id<I32>(ballots, base + t) < 0) {
                 atomicMin(&first_pad, t);
                 break;
             }
@@ -110,7 +123,7 @@ __global__ __launch_bounds__(256) void k_scan_long(const void *__restrict__ ball
         const int k = first_pad;
         const bool trunc = k < m - 1;
         for (int t = threadIdx.x; t < k; t += 256) {
-            const int32_t c = read_id(ballots, dtype32, base + t);
+            const int32_t c = read_id<I32>(ballots, base + t);
             if (c >= m)
                 bad = true;
             else if (trunc)
@@ -206,12 +219,22 @@ __global__ __launch_bounds__(256) void k_scan_long_vec(const uint16_t *__restric
 // workgroup mean fewer list reservations on the two shared counters.)
 constexpr int SHORT_BPW = 4;
 constexpr int SHORT_ROUNDS = 4;
-__global__ __launch_bounds__(256) void k_scan_short(const void *__restrict__ ballots, int dtype32, int64_t n, int32_t L,
+constexpr int32_t SEEN_BITS = 65536;
+template <bool I32>
+__global__ __launch_bounds__(256) void k_scan_short(const void *__restrict__ ballots, int64_t n, int32_t L,
                                                     int32_t m, Meta meta, int32_t *err) {
     constexpr int PER_WG = 4 * SHORT_PER_WAVE * SHORT_BPW * SHORT_ROUNDS;
     __shared__ int32_t lf[PER_WG], lt[PER_WG];
     __shared__ int32_t nf, nt;
+    // candidates listed by this workgroup's truncated ballots, as bits (for
+    // m <= SEEN_BITS; else marked in meta.in_u at once): one store per
+    // candidate and workgroup at the end instead of a read of in_u at every
+    // entry, which made each step wait for memory
+    __shared__ uint32_t seen[SEEN_BITS / 32];
+    const bool use_seen = m <= SEEN_BITS;
     if (threadIdx.x == 0) nf = nt = 0;
+    if (use_seen)
+        for (int32_t w = threadIdx.x; w < (m + 31) / 32; w += 256) seen[w] = 0u;
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int32_t bpw = min(SHORT_BPW, 64 / L);
@@ -225,7 +248,12 @@ __global__ __launch_bounds__(256) void k_scan_short(const void *__restrict__ bal
         int32_t c[SHORT_PER_WAVE];
         for (int q = 0; q < SHORT_PER_WAVE; ++q) {  // every load first
             const int64_t v = v0 + (int64_t)q * bpw + sub;
-            c[q] = (lane_ok && v < n) ? read_id(ballots, dtype32, v * L + t) : -2;
+            // (every lane loads: a load under a condition is waited for inside it)
+            c[q] = (int32_t)load_raw<I32>(ballots, lane_ok && v < n ? v * L + t : 0);
+        }
+        for (int q = 0; q < SHORT_PER_WAVE; ++q) {
+            const int64_t v = v0 + (int64_t)q * bpw + sub;
+            c[q] = lane_ok && v < n ? raw_id<I32>((uint32_t)c[q]) : -2;
         }
         for (int q = 0; q < SHORT_PER_WAVE; ++q) {
             const int64_t v = v0 + (int64_t)q * bpw + sub;
@@ -235,10 +263,16 @@ __global__ __launch_bounds__(256) void k_scan_short(const void *__restrict__ bal
             const bool live = lane_ok && v < n;
             const bool trunc = k < m - 1;
             if (live && t < k) {
-                if (c[q] >= m)
+                if (c[q] >= m) {
                     bad = true;
-                else if (trunc && !meta.in_u[c[q]])  // a read first: frequent candidates are set once per cache
-                    meta.in_u[c[q]] = 1;
+                } else if (trunc) {
+                    if (use_seen) {
+                        const uint32_t bit = 1u << (c[q] & 31);
+                        if (!(seen[c[q] >> 5] & bit)) atomicOr(&seen[c[q] >> 5], bit);
+                    } else if (!meta.in_u[c[q]]) {  // a read first: frequent candidates are set once per cache
+                        meta.in_u[c[q]] = 1;
+                    }
+                }
             }
             if (live && t == 0) {
                 meta.len[v] = k;
@@ -255,6 +289,9 @@ __global__ __launch_bounds__(256) void k_scan_short(const void *__restrict__ bal
     for (int off = 32; off >= 1; off >>= 1) k2 += __shfl_xor(k2, off);
     if (lane == 0 && k2) atomicAdd(&meta.k2[(blockIdx.x * 4 + wave) % NPART], k2);
     __syncthreads();
+    if (use_seen)
+        for (int32_t c = threadIdx.x; c < m; c += 256)
+            if ((seen[c >> 5] >> (c & 31)) & 1u) meta.in_u[c] = 1;
     record_ballots(meta, nf, lf, nt, lt);
 }
 
@@ -269,13 +306,31 @@ constexpr double ATOMIC_PAIR_COST = 1024.0;
 constexpr double BUCKETED_PAIR_COST = 512.0;
 
 constexpr int ROUTE_THREADS = 1024;
+constexpr int ROUTE_VEC = 4;  // 16-byte groups of flags per thread (m <= 65536)
 __global__ __launch_bounds__(ROUTE_THREADS) void k_route(int32_t m, Meta meta, int weighted, int64_t cap_words,
                                                          double pair_cost) {
     __shared__ int32_t part[ROUTE_THREADS];
-    const int32_t per = (m + ROUTE_THREADS - 1) / ROUTE_THREADS;
+    // A thread takes consecutive flags (0 or 1 bytes; zero past m up to the
+    // next 16 bytes), as ROUTE_VEC 16-byte loads issued together (a byte at
+    // a time waited for memory at every flag), else one byte at a time.
+    const bool vec = m <= ROUTE_THREADS * 16 * ROUTE_VEC;
+    const int32_t groups = (m + 15) / 16;
+    const int32_t gper = (groups + ROUTE_THREADS - 1) / ROUTE_THREADS;
+    const int32_t g0 = (int32_t)threadIdx.x * gper;
+    const int32_t per = vec ? 16 * gper : (m + ROUTE_THREADS - 1) / ROUTE_THREADS;
     const int32_t c0 = min(m, (int32_t)threadIdx.x * per), c1 = min(m, c0 + per);
+    uint4 f[ROUTE_VEC];
     int32_t cnt = 0;
-    for (int32_t c = c0; c < c1; ++c) cnt += meta.in_u[c] ? 1 : 0;
+    if (vec) {
+        const uint4 *in4 = reinterpret_cast<const uint4 *>(meta.in_u);
+        for (int k = 0; k < ROUTE_VEC; ++k) f[k] = in4[k < gper && g0 + k < groups ? g0 + k : 0];
+        for (int k = 0; k < ROUTE_VEC; ++k) {
+            if (!(k < gper && g0 + k < groups)) f[k] = make_uint4(0u, 0u, 0u, 0u);
+            cnt += __popc(f[k].x) + __popc(f[k].y) + __popc(f[k].z) + __popc(f[k].w);
+        }
+    } else {
+        for (int32_t c = c0; c < c1; ++c) cnt += meta.in_u[c] ? 1 : 0;
+    }
     part[threadIdx.x] = cnt;
     __syncthreads();
     for (int off = 1; off < ROUTE_THREADS; off <<= 1) {  // inclusive scan
@@ -285,13 +340,24 @@ __global__ __launch_bounds__(ROUTE_THREADS) void k_route(int32_t m, Meta meta, i
         __syncthreads();
     }
     int32_t idx = part[threadIdx.x] - cnt;
-    for (int32_t c = c0; c < c1; ++c) {
-        if (meta.in_u[c]) {
+    auto place = [&](int32_t c, bool in) {
+        if (in) {
             meta.ulist[idx] = c;
             meta.umap[c] = idx++;
         } else {
             meta.umap[c] = -1;
         }
+    };
+    if (vec) {
+        for (int k = 0; k < ROUTE_VEC; ++k) {
+            const uint32_t w[4] = {f[k].x, f[k].y, f[k].z, f[k].w};
+            for (int e = 0; e < 16; ++e) {
+                const int32_t c = 16 * (g0 + k) + e;
+                if (k < gper && c < m) place(c, (w[e >> 2] >> (8 * (e & 3))) & 1u);
+            }
+        }
+    } else {
+        for (int32_t c = c0; c < c1; ++c) place(c, meta.in_u[c] != 0);
     }
     if (threadIdx.x == 0) {
         const int32_t nu = part[ROUTE_THREADS - 1];
@@ -315,8 +381,8 @@ __global__ __launch_bounds__(ROUTE_THREADS) void k_route(int32_t m, Meta meta, i
 // LDS in chunks of SCATTER_CH columns and written as rows of `pitch` words.
 // A ballot lists distinct candidates iff its entries leave exactly
 // (columns - listed) positions unset; anything else is a repeated id.
-template <bool FULL>
-__global__ __launch_bounds__(256) void k_scatter(const void *__restrict__ ballots, int dtype32, int32_t L, int32_t m,
+template <bool FULL, bool I32>
+__global__ __launch_bounds__(256) void k_scatter(const void *__restrict__ ballots, int32_t L, int32_t m,
                                                  int32_t full_pitch, Meta meta, uint32_t *__restrict__ pos,
                                                  int32_t *err) {
     __shared__ uint16_t buf[2 * SCATTER_CH];
@@ -331,7 +397,7 @@ __global__ __launch_bounds__(256) void k_scatter(const void *__restrict__ ballot
     const int32_t src[2] = {srcs[2 * q], has_hi ? srcs[2 * q + 1] : -1};
     // 16-byte ballot reads (uint16 ids, rows 16-byte aligned) and position
     // stores (rows and chunks in multiples of four words)
-    const bool vec16 = !dtype32 && (L % 8) == 0 && (reinterpret_cast<uintptr_t>(ballots) % 16) == 0;
+    const bool vec16 = !I32 && (L % 8) == 0 && (reinterpret_cast<uintptr_t>(ballots) % 16) == 0;
     const bool vec_out = (pitch % 4) == 0 && (reinterpret_cast<uintptr_t>(pos) % 16) == 0;
     __syncthreads();  // the previous pair's counts have been read
     if (threadIdx.x < 2) unset_cnt[threadIdx.x] = 0;
@@ -361,7 +427,7 @@ __global__ __launch_bounds__(256) void k_scatter(const void *__restrict__ ballot
                     }
                 }
             } else {
-                for (int t = threadIdx.x; t < k; t += 256) place(t, read_id(ballots, dtype32, base + t));
+                for (int t = threadIdx.x; t < k; t += 256) place(t, read_id<I32>(ballots, base + t));
             }
         }
         __syncthreads();
@@ -630,7 +696,8 @@ __global__ __launch_bounds__(CNT_THREADS, 2) void k_count_pos(DenseArgs a) {
 // every earlier entry i < t the pair (c_i before c_t) adds the voter's
 // weight to C[c_i][c_t], i.e. subtracts it from acc[c_t][c_i]; every listed
 // entry adds the weight to R.  Equal entries are a repeated id.
-__global__ __launch_bounds__(256) void k_count_pairs(const void *__restrict__ ballots, int dtype32, int32_t L,
+template <bool I32>
+__global__ __launch_bounds__(256) void k_count_pairs(const void *__restrict__ ballots, int32_t L,
                                                      int32_t m, const uint32_t *__restrict__ weight, Meta meta,
                                                      uint32_t *__restrict__ acc, int64_t lda,
                                                      uint32_t *__restrict__ rsum, int32_t *err) {
@@ -644,12 +711,12 @@ __global__ __launch_bounds__(256) void k_count_pairs(const void *__restrict__ ba
     const int64_t base = (int64_t)v * L;
     bool dup = false;
     for (int t = lane; t < k; t += 64) {
-        const int32_t ct = read_id(ballots, dtype32, base + t);
+        const int32_t ct = read_id<I32>(ballots, base + t);
         if (ct < 0 || ct >= m) continue;  // reported by the scan
         if (w) atomicAdd(&rsum[ct], w);
         uint32_t *row = acc + (int64_t)ct * lda;
         for (int i = 0; i < t; ++i) {
-            const int32_t ci = read_id(ballots, dtype32, base + i);
+            const int32_t ci = read_id<I32>(ballots, base + i);
             if (ci == ct) dup = true;
             if (w && ci >= 0 && ci < m) atomicSub(&row[ci], w);
         }
@@ -673,6 +740,7 @@ constexpr int OCC_CHUNK = 8192;            // occurrences per accumulation item 
 constexpr int32_t OCC_MAX_M = 32768;       // an LDS row of counts
 constexpr int64_t OCC_MAX = (int64_t)1 << 27;  // occurrence buffer limit (entries)
 constexpr int OCC_FIN_COLS = 2048;         // columns per unit of the finish
+constexpr int FIN_COUNT = 5;               // meta.ctr slot: rows listed for the finish
 
 struct OccArgs {
     const void *ballots;
@@ -680,13 +748,16 @@ struct OccArgs {
     int32_t L, m;
     int64_t n;
     int32_t tbits;        // occurrence word: ballot << tbits | position
-    int32_t row_vec;      // uint16 ids, even L, 4-byte aligned rows: rows read as 32-bit words
+    int32_t row_vec;      // uint16 ids, even L, 4-byte aligned rows: rows read as 32-bit words (1), or as
+                          // 16-byte pieces (2: the ballots 16-byte aligned and n L ids whole pieces)
     const uint32_t *weight;
     Meta meta;
     uint32_t *hist;       // G x m: per-workgroup counts, then their exclusive prefix over workgroups
     uint32_t *row_start;  // m + 1: occurrences per candidate, then the exclusive scan
     uint32_t *item_start; // m + 1: accumulation items per candidate, then the exclusive scan
     uint32_t *part_start; // m + 1: partial rows per candidate (its items if more than one), then the scan
+    int32_t *fin;         // candidates whose rows the finish writes (no occurrences, or two or more items);
+                          // their number in meta.ctr[FIN_COUNT]
     uint32_t *occ;        // placed occurrences
     void *partial;        // partial rows, pitch ppitch elements (uint16 for unit weights, else uint32)
     int64_t ppitch;
@@ -726,7 +797,7 @@ __device__ inline void occ_range(int64_t n, int64_t &v0, int64_t &v1) {
 // ballot of the padding lanes gives it), and full rankings (m - 1 or more
 // listed) are left to the dense count.  Longer rows: one ballot per
 // wavefront, 64 entries at a time.
-template <int MAXM, bool PLACE>
+template <int MAXM, bool PLACE, bool I32>
 __global__ __launch_bounds__(256) void k_occ_bucket(OccArgs a) {
     __shared__ uint32_t cnt[MAXM];
     if (a.meta.ctr[2] != MODE_SPARSE) return;
@@ -752,8 +823,10 @@ __global__ __launch_bounds__(256) void k_occ_bucket(OccArgs a) {
             int64_t vv[U];
             for (int u = 0; u < U; ++u) {
                 vv[u] = vb + (int64_t)4 * bpw * u + sub;
-                c[u] = (lane_ok && vv[u] < v1) ? read_id(a.ballots, a.dtype32, vv[u] * L + t) : -2;
+                // (every lane loads: a load under a condition is waited for inside it)
+                c[u] = (int32_t)load_raw<I32>(a.ballots, lane_ok && vv[u] < v1 ? vv[u] * L + t : 0);
             }
+            for (int u = 0; u < U; ++u) c[u] = lane_ok && vv[u] < v1 ? raw_id<I32>((uint32_t)c[u]) : -2;
             for (int u = 0; u < U; ++u) {
                 const uint64_t pad = __ballot(c[u] < 0);  // -1 padding, -2 no ballot
                 const uint64_t mine = lane_ok ? (pad >> (sub * L)) & lane_bits : lane_bits;
@@ -766,7 +839,7 @@ __global__ __launch_bounds__(256) void k_occ_bucket(OccArgs a) {
             const int32_t k = a.meta.len[v];
             if (k >= m - 1) continue;
             for (int32_t t = lane; t < k; t += 64) {
-                const int32_t c = read_id(a.ballots, a.dtype32, v * L + t);
+                const int32_t c = read_id<I32>(a.ballots, v * L + t);
                 if (c >= 0 && c < m) put(v, t, c);
             }
         }
@@ -777,16 +850,19 @@ __global__ __launch_bounds__(256) void k_occ_bucket(OccArgs a) {
     }
 }
 
-// 64 candidates per workgroup, the G histogram rows split over 4 thread
-// groups: hist[g][c] becomes its exclusive prefix over g; per candidate c,
+// 64 candidates per workgroup, the G histogram rows split over COL_GROUPS
+// thread groups (enough loads in flight to stream the histograms):
+// hist[g][c] becomes its exclusive prefix over g; per candidate c,
 // row_start[c] = occurrences, item_start[c] = accumulation items,
-// part_start[c] = partial rows (its items when there are two or more).
-__global__ __launch_bounds__(256) void k_occ_columns(OccArgs a, int32_t G) {
-    __shared__ uint32_t part[4][64];
+// part_start[c] = partial rows (its items when there are two or more), and
+// the candidates whose rows the finish writes are listed.
+constexpr int COL_GROUPS = 16;
+__global__ __launch_bounds__(64 * COL_GROUPS) void k_occ_columns(OccArgs a, int32_t G) {
+    __shared__ uint32_t part[COL_GROUPS][64];
     if (a.meta.ctr[2] != MODE_SPARSE) return;
     const int32_t c = blockIdx.x * 64 + (threadIdx.x & 63);
     const int grp = threadIdx.x >> 6;
-    const int32_t g0 = G * grp / 4, g1 = G * (grp + 1) / 4;
+    const int32_t g0 = G * grp / COL_GROUPS, g1 = G * (grp + 1) / COL_GROUPS;
     uint32_t sum = 0;
     if (c < a.m)
         for (int32_t g = g0; g < g1; ++g) sum += a.hist[(int64_t)g * a.m + c];
@@ -800,11 +876,12 @@ __global__ __launch_bounds__(256) void k_occ_columns(OccArgs a, int32_t G) {
         a.hist[(int64_t)g * a.m + c] = run;
         run += h;
     }
-    if (grp == 3) {
+    if (grp == COL_GROUPS - 1) {
         const uint32_t items = (run + OCC_CHUNK - 1) / OCC_CHUNK;
         a.row_start[c] = run;
         a.item_start[c] = items;
         a.part_start[c] = items > 1 ? items : 0u;
+        if (items != 1) a.fin[atomicAdd(&a.meta.ctr[FIN_COUNT], 1)] = c;
     }
 }
 
@@ -824,9 +901,11 @@ __global__ __launch_bounds__(1024) void k_occ_scan(OccArgs a) {
     const bool vec = per % 4 == 0 && per / 4 <= SCAN_VEC && c1 - c0 == per;
     uint4 v[3][SCAN_VEC];
     if (vec) {
+        // every load at once (a load under a condition waits inside it):
+        // vectors past the thread's share repeat its last one and count zero
         for (int q = 0; q < 3; ++q)
             for (int k = 0; k < SCAN_VEC; ++k)
-                if (k < per / 4) v[q][k] = reinterpret_cast<const uint4 *>(arr[q] + c0)[k];
+                v[q][k] = reinterpret_cast<const uint4 *>(arr[q] + c0)[min(k, per / 4 - 1)];
         for (int q = 0; q < 3; ++q)
             for (int k = 0; k < SCAN_VEC; ++k)
                 if (k < per / 4) s[q] += v[q][k].x + v[q][k].y + v[q][k].z + v[q][k].w;
@@ -876,9 +955,9 @@ __global__ __launch_bounds__(1024) void k_occ_scan(OccArgs a) {
 // item of a row writes the row of d (d[r][y] = base + R - C[y][r], base =
 // full-ranking counts in acc or 0); an item of a heavier row writes its
 // counts to its partial row and adds its part of R to rsum[r].
-template <int MAXM, bool PACKED, typename T, int WMAX>
+template <int MAXM, bool PACKED, typename T, int WMAX, bool PIECES, bool I32>
 __global__ __launch_bounds__(256) void k_occ_accumulate(OccArgs a, T *__restrict__ d, int64_t ldd, uint32_t limit,
-                                                        uint8_t *__restrict__ row_done, int acc_zero, int dvec) {
+                                                        uint8_t *__restrict__ over_flag, int acc_zero, int dvec) {
     constexpr int WORDS = PACKED ? MAXM / 2 : MAXM;
     constexpr int B = WMAX <= 16 ? 2 : 1;  // occurrences per batch
     __shared__ __attribute__((aligned(16))) uint32_t row[WORDS];
@@ -923,7 +1002,62 @@ __global__ __launch_bounds__(256) void k_occ_accumulate(OccArgs a, T *__restrict
             atomicAdd(&row[id], w);
     };
     constexpr int WN = WMAX > 0 ? WMAX : 1;
-    if (WMAX > 0 && a.row_vec) {
+    if (WMAX > 0 && PIECES) {
+        // uint16 ids, rows of even length, ballots 16-byte aligned and a
+        // whole number of 16-byte pieces: a row's words (two ids each) are
+        // read as the 16-byte pieces that hold them.  A scattered load costs
+        // the load path about a cycle per lane whatever its width, so an
+        // occurrence takes about two wide loads instead of one per word.
+        constexpr int NCH = (WMAX + 3) / 4 + 1;  // pieces that hold WMAX words at any offset
+        const uint32_t *words32 = static_cast<const uint32_t *>(a.ballots);
+        const int64_t wrow = a.L / 2;
+        constexpr int PB = 2;  // occurrences per thread in flight
+        for (uint32_t q0 = sh_b + threadIdx.x; q0 < sh_e; q0 += 256 * PB) {
+            uint32_t ov[PB];
+#pragma unroll
+            for (int u = 0; u < PB; ++u) ov[u] = q0 + 256 * u < sh_e ? a.occ[q0 + 256 * u] : 0u;
+            uint32_t f[PB][4 * NCH];
+            int32_t tt[PB], sk[PB];
+#pragma unroll
+            for (int u = 0; u < PB; ++u) {
+                const int64_t v = ov[u] >> a.tbits;
+                tt[u] = q0 + 256 * u < sh_e ? (int32_t)(ov[u] & tmask) : 0;
+                const int32_t nw = (tt[u] + 1) / 2;
+                const uint32_t *rw = words32 + v * wrow;
+                sk[u] = (int32_t)((reinterpret_cast<uintptr_t>(rw) >> 2) & 3);  // words before the row
+                const uint4 *rc = reinterpret_cast<const uint4 *>(rw - sk[u]);
+                const int32_t nch = (sk[u] + nw + 3) >> 2;
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    uint4 x = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+                    if (c < nch) x = rc[c];
+                    f[u][4 * c] = x.x, f[u][4 * c + 1] = x.y, f[u][4 * c + 2] = x.z, f[u][4 * c + 3] = x.w;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < PB; ++u) {
+                const bool ok = q0 + 256 * u < sh_e;
+                const uint32_t w = !ok ? 0u : (PACKED ? 1u : (a.weight ? a.weight[ov[u] >> a.tbits] : 1u));
+                wpart += w;
+                // word j of the row to f[u][j]: shifts by one and by two words
+                // under masks (opaque to the compiler, which would otherwise
+                // index the array by the offset and move it to scratch memory)
+                uint32_t m1 = (sk[u] & 1) ? 0xFFFFFFFFu : 0u, m2 = (sk[u] & 2) ? 0xFFFFFFFFu : 0u;
+                asm volatile("" : "+v"(m1), "+v"(m2));
+#pragma unroll
+                for (int j = 0; j + 1 < 4 * NCH; ++j) f[u][j] = (f[u][j] & ~m1) | (f[u][j + 1] & m1);
+#pragma unroll
+                for (int j = 0; j + 2 < 4 * NCH; ++j) f[u][j] = (f[u][j] & ~m2) | (f[u][j + 2] & m2);
+#pragma unroll
+                for (int j = 0; j < WMAX; ++j) {
+                    if (2 * j < tt[u] && w != 0) {
+                        add((int32_t)(f[u][j] & 0xFFFFu), w);
+                        if (2 * j + 1 < tt[u]) add((int32_t)(f[u][j] >> 16), w);
+                    }
+                }
+            }
+        }
+    } else if (WMAX > 0 && a.row_vec) {
         // uint16 ids, rows of even length read as 32-bit words (two ids each)
         const uint32_t *words32 = static_cast<const uint32_t *>(a.ballots);
         const int64_t wrow = a.L / 2;
@@ -964,7 +1098,7 @@ __global__ __launch_bounds__(256) void k_occ_accumulate(OccArgs a, T *__restrict
             const int64_t base = v * a.L;
             for (int32_t i0 = 0; i0 < t; i0 += 8) {  // eight ids in flight
                 int32_t id[8];
-                for (int u = 0; u < 8; ++u) id[u] = i0 + u < t ? read_id(a.ballots, a.dtype32, base + i0 + u) : -1;
+                for (int u = 0; u < 8; ++u) id[u] = i0 + u < t ? read_id<I32>(a.ballots, base + i0 + u) : -1;
                 for (int u = 0; u < 8; ++u)
                     if (i0 + u < t) add(id[u], w);
             }
@@ -995,8 +1129,7 @@ __global__ __launch_bounds__(256) void k_occ_accumulate(OccArgs a, T *__restrict
             store8<T>(drow, y, m, dvec != 0, v);
         }
         // reported by the finish, after every ballot error of this launch
-        if (over) row_done[m] = 1;
-        if (threadIdx.x == 0) row_done[r] = 1;
+        if (over) over_flag[0] = 1;
         return;
     }
     // an item of a heavier row: its partial row (same element layout as the LDS row)
@@ -1008,24 +1141,25 @@ __global__ __launch_bounds__(256) void k_occ_accumulate(OccArgs a, T *__restrict
 
 // Rows the accumulation items did not finish: candidates without
 // occurrences (d[r][y] = base) and heavier candidates (d[r][y] = base + R_r
-// - sum of their partial rows).  Persistent: units (row, block of
-// OCC_FIN_COLS columns) dealt to the workgroups in turn, rows already done
-// skipped; a thread takes eight consecutive columns (one 16-byte read per
-// partial row of unit weights), four partial rows in flight.  Also reports
-// an overflow found by the accumulation.
+// - sum of their partial rows), as listed by the column pass.  Persistent:
+// units (listed row, block of OCC_FIN_COLS columns) dealt to the
+// workgroups in turn (a walk over every row that skipped the finished ones
+// waited for memory at each); a thread takes eight consecutive columns (one
+// 16-byte read per partial row of unit weights), four partial rows in
+// flight.  Also reports an overflow found by the accumulation.
 template <typename T, bool PACKED>
 __global__ __launch_bounds__(256) void k_occ_finish(OccArgs a, T *__restrict__ d, int64_t ldd, uint32_t limit,
-                                                    const uint8_t *__restrict__ row_done, int acc_zero, int dvec) {
+                                                    const uint8_t *__restrict__ over_flag, int acc_zero, int dvec) {
     static_assert(OCC_FIN_COLS == 8 * 256, "a thread takes eight columns");
     if (a.meta.ctr[2] != MODE_SPARSE) return;
     const int32_t m = a.m;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && row_done[m]) set_device_error(a.err, SCHULZE_ERANGE);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && over_flag[0]) set_device_error(a.err, SCHULZE_ERANGE);
     const int32_t cb = (m + OCC_FIN_COLS - 1) / OCC_FIN_COLS;
     const bool avec = (a.lda % 4) == 0;  // rows of acc 16-byte aligned
+    const int32_t nfin = a.meta.ctr[FIN_COUNT];
     bool over = false;
-    for (int64_t u = blockIdx.x; u < (int64_t)m * cb; u += gridDim.x) {
-        const int32_t r = (int32_t)(u / cb);
-        if (row_done[r]) continue;
+    for (int64_t u = blockIdx.x; u < (int64_t)nfin * cb; u += gridDim.x) {
+        const int32_t r = a.fin[u / cb];
         const int32_t y = (int32_t)(u % cb) * OCC_FIN_COLS + 8 * threadIdx.x;
         if (y >= m) continue;
         const uint32_t p0 = a.part_start[r], np = a.part_start[r + 1] - p0;
@@ -1200,7 +1334,7 @@ struct MetaLayout {
 // and such a candidate has more than OCC_CHUNK occurrences, so there are at
 // most 2 cap / OCC_CHUNK of them.
 struct OccLayout {
-    size_t hist, row_start, item_start, part_start, occ, partial, row_done, total;
+    size_t hist, row_start, item_start, part_start, fin, occ, partial, over_flag, total;
     int64_t ppitch, max_parts;
     OccLayout(int64_t G, int32_t m, int64_t cap, size_t partial_elem) {
         size_t o = 0;
@@ -1217,58 +1351,98 @@ struct OccLayout {
         part_start = take(sizeof(uint32_t) * ((size_t)m + 1));
         occ = take(sizeof(uint32_t) * (size_t)cap);
         partial = take(partial_elem * (size_t)max_parts * (size_t)ppitch);
-        row_done = take((size_t)m + 1);  // one flag per row, then the overflow flag
+        fin = take(sizeof(int32_t) * (size_t)m);
+        over_flag = take(sizeof(uint32_t));  // a count above the limit was clamped
         total = o;
     }
 };
+
+// The counting (PLACE = false) or placing pass of the bucketing, for the LDS
+// histogram that fits m and the ballots' id type.
+template <bool PLACE>
+int occ_bucket(schulze_ctx *ctx, hipStream_t s, const OccArgs &oa, dim3 g) {
+    const dim3 b(256);
+    if (oa.m <= OCC_MAX_M / 2) {
+        if (oa.dtype32)
+            SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s, (k_occ_bucket<OCC_MAX_M / 2, PLACE, true><<<g, b, 0, s>>>(oa)));
+        else
+            SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s, (k_occ_bucket<OCC_MAX_M / 2, PLACE, false><<<g, b, 0, s>>>(oa)));
+    } else {
+        if (oa.dtype32)
+            SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s, (k_occ_bucket<OCC_MAX_M, PLACE, true><<<g, b, 0, s>>>(oa)));
+        else
+            SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s, (k_occ_bucket<OCC_MAX_M, PLACE, false><<<g, b, 0, s>>>(oa)));
+    }
+    return SCHULZE_OK;
+}
 
 // The accumulation and finish launches for the counter type T of d: packed
 // 16-bit LDS counts for unit weights, 32-bit ones otherwise; the LDS row fits
 // m; rows read as 32-bit words when the layout allows (WMAX words at most).
 template <typename T, int MAXM, bool PACKED>
 int occ_accumulate_m(schulze_ctx *ctx, hipStream_t s, const OccArgs &oa, dim3 grid, T *d, int64_t ldd,
-                     uint32_t limit, uint8_t *row_done, int az, int dvec) {
+                     uint32_t limit, uint8_t *over_flag, int az, int dvec) {
     const dim3 b(256);
     if constexpr (PACKED) {
+        if (oa.row_vec == 2 && oa.L <= 32) {
+            SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
+                           (k_occ_accumulate<MAXM, PACKED, T, 16, true, false><<<grid, b, 0, s>>>(oa, d, ldd, limit, over_flag,
+                                                                                          az, dvec)));
+            return SCHULZE_OK;
+        }
+        if (oa.row_vec == 2 && oa.L <= 64) {
+            SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
+                           (k_occ_accumulate<MAXM, PACKED, T, 32, true, false><<<grid, b, 0, s>>>(oa, d, ldd, limit, over_flag,
+                                                                                          az, dvec)));
+            return SCHULZE_OK;
+        }
         if (oa.row_vec && oa.L <= 32) {
             SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
-                           (k_occ_accumulate<MAXM, PACKED, T, 16><<<grid, b, 0, s>>>(oa, d, ldd, limit, row_done, az, dvec)));
+                           (k_occ_accumulate<MAXM, PACKED, T, 16, false, false><<<grid, b, 0, s>>>(oa, d, ldd, limit, over_flag,
+                                                                                           az, dvec)));
             return SCHULZE_OK;
         }
         if (oa.row_vec && oa.L <= 64) {
             SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
-                           (k_occ_accumulate<MAXM, PACKED, T, 32><<<grid, b, 0, s>>>(oa, d, ldd, limit, row_done, az, dvec)));
+                           (k_occ_accumulate<MAXM, PACKED, T, 32, false, false><<<grid, b, 0, s>>>(oa, d, ldd, limit, over_flag,
+                                                                                           az, dvec)));
             return SCHULZE_OK;
         }
     }
-    SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
-                   (k_occ_accumulate<MAXM, PACKED, T, 0><<<grid, b, 0, s>>>(oa, d, ldd, limit, row_done, az, dvec)));
+    if (oa.dtype32)
+        SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
+                       (k_occ_accumulate<MAXM, PACKED, T, 0, false, true><<<grid, b, 0, s>>>(oa, d, ldd, limit,
+                                                                                             over_flag, az, dvec)));
+    else
+        SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
+                       (k_occ_accumulate<MAXM, PACKED, T, 0, false, false><<<grid, b, 0, s>>>(oa, d, ldd, limit,
+                                                                                              over_flag, az, dvec)));
     return SCHULZE_OK;
 }
 
 template <typename T>
 int occ_accumulate(schulze_ctx *ctx, hipStream_t s, const OccArgs &oa, dim3 grid, int32_t m, bool weighted, T *d,
-                   int64_t ldd, uint32_t limit, uint8_t *row_done, bool acc_zero) {
+                   int64_t ldd, uint32_t limit, uint8_t *over_flag, bool acc_zero) {
     const int az = acc_zero ? 1 : 0;
     // rows of d 16-byte aligned: eight columns per 16-byte store (uint16) or two (int32)
     const int dvec = reinterpret_cast<uintptr_t>(d) % 16 == 0 && (ldd * (int64_t)sizeof(T)) % 16 == 0;
     int rc;
     if (!weighted && m <= OCC_MAX_M / 2)
-        rc = occ_accumulate_m<T, OCC_MAX_M / 2, true>(ctx, s, oa, grid, d, ldd, limit, row_done, az, dvec);
+        rc = occ_accumulate_m<T, OCC_MAX_M / 2, true>(ctx, s, oa, grid, d, ldd, limit, over_flag, az, dvec);
     else if (!weighted)
-        rc = occ_accumulate_m<T, OCC_MAX_M, true>(ctx, s, oa, grid, d, ldd, limit, row_done, az, dvec);
+        rc = occ_accumulate_m<T, OCC_MAX_M, true>(ctx, s, oa, grid, d, ldd, limit, over_flag, az, dvec);
     else if (m <= OCC_MAX_M / 2)
-        rc = occ_accumulate_m<T, OCC_MAX_M / 2, false>(ctx, s, oa, grid, d, ldd, limit, row_done, az, dvec);
+        rc = occ_accumulate_m<T, OCC_MAX_M / 2, false>(ctx, s, oa, grid, d, ldd, limit, over_flag, az, dvec);
     else
-        rc = occ_accumulate_m<T, OCC_MAX_M, false>(ctx, s, oa, grid, d, ldd, limit, row_done, az, dvec);
+        rc = occ_accumulate_m<T, OCC_MAX_M, false>(ctx, s, oa, grid, d, ldd, limit, over_flag, az, dvec);
     if (rc != SCHULZE_OK) return rc;
     const dim3 fg((unsigned)(ctx->num_cus * 4));
     if (weighted) {
         SCHULZE_LAUNCH(ctx, K_COUNT_FINISH, s,
-                       (k_occ_finish<T, false><<<fg, dim3(256), 0, s>>>(oa, d, ldd, limit, row_done, az, dvec)));
+                       (k_occ_finish<T, false><<<fg, dim3(256), 0, s>>>(oa, d, ldd, limit, over_flag, az, dvec)));
     } else {
         SCHULZE_LAUNCH(ctx, K_COUNT_FINISH, s,
-                       (k_occ_finish<T, true><<<fg, dim3(256), 0, s>>>(oa, d, ldd, limit, row_done, az, dvec)));
+                       (k_occ_finish<T, true><<<fg, dim3(256), 0, s>>>(oa, d, ldd, limit, over_flag, az, dvec)));
     }
     return SCHULZE_OK;
 }
@@ -1338,21 +1512,29 @@ extern "C" int schulze_pairwise(schulze_ctx *ctx, void *stream, const void *ball
     if (n == 0 && (rc = fill_u32(ctx, s, acc, (size_t)m * m, 0u)) != SCHULZE_OK) return rc;
     if ((rc = fill_u32(ctx, s, rsum, (size_t)m, 0u)) != SCHULZE_OK) return rc;
 
-    uint8_t *row_done = nullptr;  // rows finished by the bucketed count
+    uint8_t *over_flag = nullptr;  // the bucketed count's overflow flag (set: it ran and wrote its rows)
     if (n > 0) {
         if (L <= 64) {
             const int64_t per_wg = 4 * SHORT_PER_WAVE * SHORT_ROUNDS * std::min<int64_t>(SHORT_BPW, 64 / L);
-            SCHULZE_LAUNCH(ctx, K_BALLOT_SCAN, s,
-                           k_scan_short<<<dim3((unsigned)ceil_div(n, per_wg)), dim3(256), 0, s>>>(
-                               ballots, dtype32, n, L, m, meta, ctx->err));
+            const dim3 sg((unsigned)ceil_div(n, per_wg));
+            if (dtype32)
+                SCHULZE_LAUNCH(ctx, K_BALLOT_SCAN, s,
+                               k_scan_short<true><<<sg, dim3(256), 0, s>>>(ballots, n, L, m, meta, ctx->err));
+            else
+                SCHULZE_LAUNCH(ctx, K_BALLOT_SCAN, s,
+                               k_scan_short<false><<<sg, dim3(256), 0, s>>>(ballots, n, L, m, meta, ctx->err));
         } else if (!dtype32 && L % 8 == 0 && reinterpret_cast<uintptr_t>(ballots) % 16 == 0) {
             SCHULZE_LAUNCH(ctx, K_BALLOT_SCAN, s,
                            k_scan_long_vec<<<dim3((unsigned)ceil_div(n, LONG_CHUNK)), dim3(256), 0, s>>>(
                                static_cast<const uint16_t *>(ballots), n, L, m, meta, ctx->err));
         } else {
-            SCHULZE_LAUNCH(ctx, K_BALLOT_SCAN, s,
-                           k_scan_long<<<dim3((unsigned)ceil_div(n, LONG_CHUNK)), dim3(256), 0, s>>>(
-                               ballots, dtype32, n, L, m, meta, ctx->err));
+            const dim3 lg((unsigned)ceil_div(n, LONG_CHUNK));
+            if (dtype32)
+                SCHULZE_LAUNCH(ctx, K_BALLOT_SCAN, s,
+                               k_scan_long<true><<<lg, dim3(256), 0, s>>>(ballots, n, L, m, meta, ctx->err));
+            else
+                SCHULZE_LAUNCH(ctx, K_BALLOT_SCAN, s,
+                               k_scan_long<false><<<lg, dim3(256), 0, s>>>(ballots, n, L, m, meta, ctx->err));
         }
         SCHULZE_LAUNCH(ctx, K_ROUTE, s,
                        k_route<<<dim3(1), dim3(ROUTE_THREADS), 0, s>>>(m, meta, voter_weight != nullptr,
@@ -1379,9 +1561,14 @@ extern "C" int schulze_pairwise(schulze_ctx *ctx, void *stream, const void *ball
         const unsigned scatter_grid = (unsigned)std::min<int64_t>(max_pairs, (int64_t)ctx->num_cus * 16);
         if (may_have_full) {
             uint32_t *pos = static_cast<uint32_t *>(ctx->ws[WS_POSITIONS]);
-            SCHULZE_LAUNCH(ctx, K_BALLOT_SCATTER, s,
-                           k_scatter<true><<<dim3(scatter_grid), dim3(256), 0, s>>>(
-                               ballots, dtype32, L, m, pitch, meta, pos, ctx->err));
+            if (dtype32)
+                SCHULZE_LAUNCH(ctx, K_BALLOT_SCATTER, s,
+                               k_scatter<true, true><<<dim3(scatter_grid), dim3(256), 0, s>>>(
+                                   ballots, L, m, pitch, meta, pos, ctx->err));
+            else
+                SCHULZE_LAUNCH(ctx, K_BALLOT_SCATTER, s,
+                               k_scatter<true, false><<<dim3(scatter_grid), dim3(256), 0, s>>>(
+                                   ballots, L, m, pitch, meta, pos, ctx->err));
             if (!voter_weight) {
                 DenseArgs da{pos, pitch, m, meta, acc, lda, rsum};
                 SCHULZE_LAUNCH(ctx, K_COUNT_DENSE, s, k_count_pos<false><<<dim3(cgrid), dim3(CNT_THREADS), 0, s>>>(da));
@@ -1394,9 +1581,14 @@ extern "C" int schulze_pairwise(schulze_ctx *ctx, void *stream, const void *ball
         }
         if (tpos_bytes) {
             uint32_t *tpos = static_cast<uint32_t *>(ctx->ws[WS_TRUNC_POS]);
-            SCHULZE_LAUNCH(ctx, K_BALLOT_SCATTER, s,
-                           k_scatter<false><<<dim3(scatter_grid), dim3(256), 0, s>>>(
-                               ballots, dtype32, L, m, 0, meta, tpos, ctx->err));
+            if (dtype32)
+                SCHULZE_LAUNCH(ctx, K_BALLOT_SCATTER, s,
+                               k_scatter<false, true><<<dim3(scatter_grid), dim3(256), 0, s>>>(
+                                   ballots, L, m, 0, meta, tpos, ctx->err));
+            else
+                SCHULZE_LAUNCH(ctx, K_BALLOT_SCATTER, s,
+                               k_scatter<false, false><<<dim3(scatter_grid), dim3(256), 0, s>>>(
+                                   ballots, L, m, 0, meta, tpos, ctx->err));
             DenseArgs da{tpos, 0, m, meta, acc, lda, rsum};
             SCHULZE_LAUNCH(ctx, K_COUNT_TRUNC, s, k_count_pos<true><<<dim3(cgrid), dim3(CNT_THREADS), 0, s>>>(da));
         }
@@ -1405,60 +1597,62 @@ extern "C" int schulze_pairwise(schulze_ctx *ctx, void *stream, const void *ball
             char *ob = static_cast<char *>(ctx->ws[WS_OCC]);
             int32_t tbits = 0;
             while ((1 << tbits) < L) ++tbits;
-            const int row_vec = !dtype32 && L % 2 == 0 && reinterpret_cast<uintptr_t>(ballots) % 4 == 0;
+            const bool pieces = reinterpret_cast<uintptr_t>(ballots) % 16 == 0 && (n * L) % 8 == 0;
+            const int row_vec =
+                !dtype32 && L % 2 == 0 && reinterpret_cast<uintptr_t>(ballots) % 4 == 0 ? (pieces ? 2 : 1) : 0;
             OccArgs oa{ballots, dtype32, L, m, n, tbits, row_vec, voter_weight, meta,
                        reinterpret_cast<uint32_t *>(ob + ol.hist),
                        reinterpret_cast<uint32_t *>(ob + ol.row_start),
                        reinterpret_cast<uint32_t *>(ob + ol.item_start),
                        reinterpret_cast<uint32_t *>(ob + ol.part_start),
+                       reinterpret_cast<int32_t *>(ob + ol.fin),
                        reinterpret_cast<uint32_t *>(ob + ol.occ),
                        static_cast<void *>(ob + ol.partial), ol.ppitch,
                        acc, lda, rsum, ctx->err};
-            const dim3 g(occ_grid), b(256);
-            row_done = reinterpret_cast<uint8_t *>(ob + ol.row_done);
-            if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(row_done), (size_t)ceil_div(m + 1, 4), 0u)) !=
+            const dim3 g(occ_grid);
+            over_flag = reinterpret_cast<uint8_t *>(ob + ol.over_flag);
+            if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(over_flag), 1, 0u)) !=
                 SCHULZE_OK)
                 return rc;
-            if (m <= OCC_MAX_M / 2) {
-                SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s, k_occ_bucket<OCC_MAX_M / 2, false><<<g, b, 0, s>>>(oa));
-            } else {
-                SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s, k_occ_bucket<OCC_MAX_M, false><<<g, b, 0, s>>>(oa));
-            }
+            if ((rc = occ_bucket<false>(ctx, s, oa, g)) != SCHULZE_OK) return rc;
             SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
-                           k_occ_columns<<<dim3((unsigned)ceil_div(m, 64)), b, 0, s>>>(oa, (int32_t)occ_grid));
+                           k_occ_columns<<<dim3((unsigned)ceil_div(m, 64)), dim3(64 * COL_GROUPS), 0, s>>>(
+                               oa, (int32_t)occ_grid));
             SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s, k_occ_scan<<<dim3(1), dim3(1024), 0, s>>>(oa));
             const dim3 ig((unsigned)(m + ceil_div(occ_cap, OCC_CHUNK)));
-            if (m <= OCC_MAX_M / 2) {
-                SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s, k_occ_bucket<OCC_MAX_M / 2, true><<<g, b, 0, s>>>(oa));
-            } else {
-                SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s, k_occ_bucket<OCC_MAX_M, true><<<g, b, 0, s>>>(oa));
-            }
+            if ((rc = occ_bucket<true>(ctx, s, oa, g)) != SCHULZE_OK) return rc;
             if (d_dtype == SCHULZE_U16) {
                 if ((rc = occ_accumulate<uint16_t>(ctx, s, oa, ig, m, voter_weight != nullptr, (uint16_t *)d, ldd,
-                                                   65535u, row_done, !may_have_full)) != SCHULZE_OK)
+                                                   65535u, over_flag, !may_have_full)) != SCHULZE_OK)
                     return rc;
             } else {
                 if ((rc = occ_accumulate<int32_t>(ctx, s, oa, ig, m, voter_weight != nullptr, (int32_t *)d, ldd,
-                                                  (uint32_t)INT32_MAX, row_done, !may_have_full)) != SCHULZE_OK)
+                                                  (uint32_t)INT32_MAX, over_flag, !may_have_full)) != SCHULZE_OK)
                     return rc;
             }
         } else {
-            SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
-                           k_count_pairs<<<dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, s>>>(
-                               ballots, dtype32, L, m, voter_weight, meta, acc, lda, rsum, ctx->err));
+            const dim3 pg((unsigned)ceil_div(n, 4));
+            if (dtype32)
+                SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
+                               k_count_pairs<true><<<pg, dim3(256), 0, s>>>(ballots, L, m, voter_weight, meta, acc, lda,
+                                                                            rsum, ctx->err));
+            else
+                SCHULZE_LAUNCH(ctx, K_COUNT_SPARSE, s,
+                               k_count_pairs<false><<<pg, dim3(256), 0, s>>>(ballots, L, m, voter_weight, meta, acc,
+                                                                             lda, rsum, ctx->err));
         }
     }
-    // rows of the bucketed route were written by it (row_done given)
+    // rows of the bucketed route were written by it (over_flag given)
     dim3 fgrid((unsigned)m);
     if (d_dtype == SCHULZE_U16) {
         SCHULZE_LAUNCH(ctx, K_COUNT_FINISH, s,
                        k_count_finish<uint16_t><<<fgrid, dim3(256), 0, s>>>(acc, lda, rsum, meta, m, (uint16_t *)d, ldd,
-                                                                            65535u, ctx->err, row_done != nullptr));
+                                                                            65535u, ctx->err, over_flag != nullptr));
     } else {
         SCHULZE_LAUNCH(ctx, K_COUNT_FINISH, s,
                        k_count_finish<int32_t><<<fgrid, dim3(256), 0, s>>>(acc, lda, rsum, meta, m, (int32_t *)d, ldd,
                                                                            (uint32_t)INT32_MAX, ctx->err,
-                                                                           row_done != nullptr));
+                                                                           over_flag != nullptr));
     }
     return SCHULZE_OK;
 }

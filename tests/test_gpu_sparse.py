@@ -98,15 +98,25 @@ def test_sparse_repeated_id_is_reported(ctx):
         assert err == sz.EBALLOT, mode
 
 
-@pytest.mark.parametrize("case", ["odd-L", "int32-ids", "L-48", "L-80", "full-mixed", "weights-full-mixed"])
+@pytest.mark.parametrize("case", ["odd-L", "int32-ids", "words", "pieces-L-10", "L-48", "L-80", "full-mixed",
+                                  "weights-full-mixed"])
 def test_sparse_row_layouts(ctx, case):
-    """Ballot layouts of the bucketed count: rows read as 32-bit words
-    (uint16 ids, even L up to 64), one id at a time (odd L, int32 ids), rows
-    longer than a wavefront, and full rankings counted densely next to the
-    bucketed truncated ballots (counts added to the dense part)."""
+    """Ballot layouts of the bucketed count: rows read as 16-byte pieces
+    (uint16 ids, even L up to 64, n L a multiple of 8; the last ballot ends
+    the buffer), as 32-bit words (even L, n L not a multiple of 8), one id at
+    a time (odd L, int32 ids), rows longer than a wavefront, and full
+    rankings counted densely next to the bucketed truncated ballots (counts
+    added to the dense part)."""
     rng = np.random.default_rng(731)
     weight = None
-    if case == "odd-L":
+    if case == "words":
+        m, b = 3000, workload.pl_zipf(737, 6001, 3000, 1.0, 12)
+        assert (b.size % 8) != 0 and b.shape[1] % 2 == 0
+    elif case == "pieces-L-10":
+        m, b = 3000, workload.pl_zipf(738, 6004, 3000, 1.1, 10)
+        assert b.size % 8 == 0
+        b[-1, :] = np.arange(10, dtype=b.dtype)  # the last ballot lists ten ids
+    elif case == "odd-L":
         m, b = 3000, workload.pl_zipf(731, 6000, 3000, 1.0, 7)
     elif case == "int32-ids":
         m, b = 3000, workload.pl_zipf(732, 6000, 3000, 1.0, 8, dtype=np.int32)
