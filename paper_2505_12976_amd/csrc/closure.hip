@@ -554,14 +554,18 @@ __global__ __launch_bounds__(256) void k_rank_mark(const int32_t *__restrict__ P
             if (!(*word & bit)) atomicOr(word, bit);
         }
     };
-    // count is a multiple of 4 and P 16-byte aligned: four 16-byte loads in
-    // flight per thread and step
+    // count is a multiple of 4 and P 16-byte aligned: MARK_STEP 16-byte
+    // loads in flight per thread and step, issued unconditionally (past the
+    // end they repeat the last vector and count as zero: a load under a
+    // condition is waited for inside it)
+    constexpr int MARK_STEP = 8;
     const int4 *P4 = reinterpret_cast<const int4 *>(P);
     const int64_t n4 = count / 4, stride = (int64_t)gridDim.x * 256;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n4; e += 4 * stride) {
-        int4 q[4];
-        for (int u = 0; u < 4; ++u) q[u] = e + u * stride < n4 ? P4[e + u * stride] : make_int4(0, 0, 0, 0);
-        for (int u = 0; u < 4; ++u) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n4; e += MARK_STEP * stride) {
+        int4 q[MARK_STEP];
+        for (int u = 0; u < MARK_STEP; ++u) q[u] = P4[min(e + u * stride, n4 - 1)];
+        for (int u = 0; u < MARK_STEP; ++u) {
+            if (e + u * stride >= n4) q[u] = make_int4(0, 0, 0, 0);
             mark(q[u].x);
             mark(q[u].y);
             mark(q[u].z);
@@ -664,17 +668,40 @@ __global__ __launch_bounds__(256) void k_rank_apply(const int32_t *__restrict__ 
                                                     const uint32_t *__restrict__ word_rank,
                                                     uint16_t *__restrict__ P16, const int32_t *gate) {
     if (gated_off(gate, 1)) return;
-    auto rank_of = [&](int32_t v) -> uint16_t {
-        if (v == 0) return 0;
-        const uint32_t below = bitmap[v >> 5] & ((1u << (v & 31)) - 1u);
-        return (uint16_t)(word_rank[v >> 5] + __popc(below) + 1u);
-    };
+    // rank of v: marked values below it plus one, 0 for 0 (both lookups
+    // unconditional, word 0 for the value 0: values are below RANK_CAP
+    // whenever this kernel runs)
+    // APPLY_STEP vectors per thread and step, each load issued
+    // unconditionally (past the end: the last vector again, not stored), so
+    // that the loads and then the table lookups of a step are in flight
+    // together
+    constexpr int APPLY_STEP = 4;
     const int4 *P4 = reinterpret_cast<const int4 *>(P);
     ushort4 *Q4 = reinterpret_cast<ushort4 *>(P16);
-    const int64_t n4 = count / 4;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n4; e += (int64_t)gridDim.x * 256) {
-        const int4 q = P4[e];
-        Q4[e] = make_ushort4(rank_of(q.x), rank_of(q.y), rank_of(q.z), rank_of(q.w));
+    const int64_t n4 = count / 4, stride = (int64_t)gridDim.x * 256;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n4; e += APPLY_STEP * stride) {
+        int4 q[APPLY_STEP];
+        for (int u = 0; u < APPLY_STEP; ++u) q[u] = P4[min(e + u * stride, n4 - 1)];
+        // every lookup of the step first, then the ranks
+        uint32_t bw[APPLY_STEP][4], wr[APPLY_STEP][4];
+        for (int u = 0; u < APPLY_STEP; ++u) {
+            const int32_t v[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
+            for (int c = 0; c < 4; ++c) {
+                bw[u][c] = bitmap[(uint32_t)v[c] >> 5];
+                wr[u][c] = word_rank[(uint32_t)v[c] >> 5];
+            }
+        }
+        ushort4 r[APPLY_STEP];
+        for (int u = 0; u < APPLY_STEP; ++u) {
+            const int32_t v[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
+            uint16_t k[4];
+            for (int c = 0; c < 4; ++c)
+                k[c] = v[c] == 0 ? (uint16_t)0
+                                 : (uint16_t)(wr[u][c] + __popc(bw[u][c] & ((1u << (v[c] & 31)) - 1u)) + 1u);
+            r[u] = make_ushort4(k[0], k[1], k[2], k[3]);
+        }
+        for (int u = 0; u < APPLY_STEP; ++u)
+            if (e + u * stride < n4) Q4[e + u * stride] = r[u];
     }
 }
 
@@ -686,10 +713,32 @@ __global__ __launch_bounds__(256) void k_rank_store(const uint16_t *__restrict__
     if (gated_off(gate, 1)) return;
     const int32_t i = blockIdx.x;
     int32_t *row = p + (int64_t)i * ldp;
-    for (int32_t j0 = threadIdx.x * 4; j0 < m; j0 += 1024) {
-        const ushort4 r = *reinterpret_cast<const ushort4 *>(P16 + (int64_t)i * ld + j0);
-        const uint16_t rr[4] = {r.x, r.y, r.z, r.w};
-        for (int u = 0; u < 4 && j0 + u < m; ++u) row[j0 + u] = i == j0 + u ? 0 : value_of[rr[u]];
+    // STORE_STEP groups of four columns per thread and step; every load and
+    // table lookup unconditional (P16 rows hold ld >= m columns, a multiple
+    // of 64; rank 0 looks up value_of[0] = 0), the stores under the bounds
+    constexpr int STORE_STEP = 4;
+    const bool vec = (ldp % 4) == 0 && (reinterpret_cast<uintptr_t>(p) % 16) == 0;
+    for (int32_t jb = threadIdx.x * 4; jb < m; jb += 1024 * STORE_STEP) {
+        ushort4 r[STORE_STEP];
+        for (int u = 0; u < STORE_STEP; ++u)
+            r[u] = *reinterpret_cast<const ushort4 *>(P16 + (int64_t)i * ld + min(jb + 1024 * u, (int32_t)ld - 4));
+        int32_t v[STORE_STEP][4];
+        for (int u = 0; u < STORE_STEP; ++u) {
+            v[u][0] = value_of[r[u].x];
+            v[u][1] = value_of[r[u].y];
+            v[u][2] = value_of[r[u].z];
+            v[u][3] = value_of[r[u].w];
+        }
+        for (int u = 0; u < STORE_STEP; ++u) {
+            const int32_t j0 = jb + 1024 * u;
+            if (j0 >= m) break;
+            for (int e = 0; e < 4; ++e)
+                if (j0 + e == i) v[u][e] = 0;
+            if (vec && j0 + 4 <= m)
+                *reinterpret_cast<int4 *>(row + j0) = make_int4(v[u][0], v[u][1], v[u][2], v[u][3]);
+            else
+                for (int e = 0; e < 4 && j0 + e < m; ++e) row[j0 + e] = v[u][e];
+        }
     }
 }
 

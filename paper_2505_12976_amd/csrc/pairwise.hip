@@ -803,7 +803,24 @@ __global__ __launch_bounds__(256) void k_occ_bucket(OccArgs a) {
     if (a.meta.ctr[2] != MODE_SPARSE) return;
     const int32_t m = a.m, L = a.L;
     const int64_t hrow = (int64_t)blockIdx.x * m;
-    for (int32_t c = threadIdx.x; c < m; c += 256) cnt[c] = PLACE ? a.row_start[c] + a.hist[hrow + c] : 0u;
+    if (PLACE) {
+        // the workgroup's first slot per candidate, PRO candidates per thread
+        // with every load in flight at once (one at a time, the loads took
+        // most of the pass)
+        constexpr int PRO = 16;
+        for (int32_t c0 = threadIdx.x; c0 < m; c0 += 256 * PRO) {
+            uint32_t rs[PRO], hs[PRO];
+            for (int u = 0; u < PRO; ++u) {
+                const int32_t c = c0 + 256 * u < m ? c0 + 256 * u : 0;
+                rs[u] = a.row_start[c];
+                hs[u] = a.hist[hrow + c];
+            }
+            for (int u = 0; u < PRO; ++u)
+                if (c0 + 256 * u < m) cnt[c0 + 256 * u] = rs[u] + hs[u];
+        }
+    } else {
+        for (int32_t c = threadIdx.x; c < m; c += 256) cnt[c] = 0u;
+    }
     __syncthreads();
     int64_t v0, v1;
     occ_range(a.n, v0, v1);

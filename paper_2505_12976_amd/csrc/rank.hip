@@ -41,24 +41,37 @@ __global__ __launch_bounds__(256) void k_winners(const int32_t *__restrict__ bea
 }
 
 // order[rank(x)] = x with rank(x) = #{y : (beaten[y], y) < (beaten[x], x)}.
-// Keys beaten*m + id are distinct and fit 32 bits for m <= 65535.
-__global__ __launch_bounds__(256) void k_rank_sort(const int32_t *__restrict__ beaten, int32_t m,
-                                                   int32_t *__restrict__ order) {
-    __shared__ uint32_t keys[1024];
-    const int32_t x = blockIdx.x * 256 + threadIdx.x;
-    const uint32_t kx = x < m ? (uint32_t)beaten[x] * (uint32_t)m + (uint32_t)x : 0xFFFFFFFFu;
+// Keys beaten*m + id are distinct and fit 32 bits for m <= 65535.  A
+// workgroup takes RS_X candidates; its RS_G wavefronts count over
+// interleaved shares of the keys (staged in LDS RS_CHUNK at a time, each
+// read a broadcast) and the shares are summed in LDS.  (One thread per
+// candidate over every key left most of the chip idle.)
+constexpr int RS_X = 64;
+constexpr int RS_G = 16;
+constexpr int RS_CHUNK = 4096;
+__global__ __launch_bounds__(64 * RS_G) void k_rank_sort(const int32_t *__restrict__ beaten, int32_t m,
+                                                         int32_t *__restrict__ order) {
+    __shared__ uint32_t keys[RS_CHUNK];
+    __shared__ int32_t part[RS_G][RS_X];
+    const int xl = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int32_t x = blockIdx.x * RS_X + xl;
+    auto key = [&](int32_t y) { return (uint32_t)beaten[y] * (uint32_t)m + (uint32_t)y; };
+    const uint32_t kx = x < m ? key(x) : 0xFFFFFFFFu;
     int32_t rank = 0;
-    for (int32_t y0 = 0; y0 < m; y0 += 1024) {
+    for (int32_t y0 = 0; y0 < m; y0 += RS_CHUNK) {
         __syncthreads();
-        for (int i = threadIdx.x; i < 1024; i += 256) {
-            const int32_t y = y0 + i;
-            keys[i] = y < m ? (uint32_t)beaten[y] * (uint32_t)m + (uint32_t)y : 0xFFFFFFFFu;
-        }
+        for (int i = threadIdx.x; i < RS_CHUNK; i += 64 * RS_G) keys[i] = y0 + i < m ? key(y0 + i) : 0xFFFFFFFFu;
         __syncthreads();
-        const int lim = min(1024, m - y0);
-        for (int i = 0; i < lim; ++i) rank += keys[i] < kx ? 1 : 0;
+        const int lim = min(RS_CHUNK, m - y0);
+        for (int i = grp; i < lim; i += RS_G) rank += keys[i] < kx ? 1 : 0;
     }
-    if (x < m) order[rank] = x;
+    part[grp][xl] = rank;
+    __syncthreads();
+    if (grp == 0 && x < m) {
+        int32_t r = 0;
+        for (int g = 0; g < RS_G; ++g) r += part[g][xl];
+        order[r] = x;
+    }
 }
 
 template <typename E>
@@ -116,6 +129,6 @@ extern "C" int schulze_ranking(schulze_ctx *ctx, void *stream, const void *p, in
     }
     if ((rc = beaten_any(ctx, s, p, ldp, m, dtype, beaten)) != SCHULZE_OK) return rc;
     SCHULZE_LAUNCH(ctx, K_RANK_SORT, s,
-                   k_rank_sort<<<dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s>>>(beaten, m, order));
+                   k_rank_sort<<<dim3((unsigned)ceil_div(m, RS_X)), dim3(64 * RS_G), 0, s>>>(beaten, m, order));
     return SCHULZE_OK;
 }
