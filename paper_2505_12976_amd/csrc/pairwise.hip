@@ -918,11 +918,9 @@ __global__ __launch_bounds__(1024) void k_occ_scan(OccArgs a) {
     const bool vec = per % 4 == 0 && per / 4 <= SCAN_VEC && c1 - c0 == per;
     uint4 v[3][SCAN_VEC];
     if (vec) {
-        // every load at once (a load under a condition waits inside it):
-        // vectors past the thread's share repeat its last one and count zero
         for (int q = 0; q < 3; ++q)
             for (int k = 0; k < SCAN_VEC; ++k)
-                v[q][k] = reinterpret_cast<const uint4 *>(arr[q] + c0)[min(k, per / 4 - 1)];
+                if (k < per / 4) v[q][k] = reinterpret_cast<const uint4 *>(arr[q] + c0)[k];
         for (int q = 0; q < 3; ++q)
             for (int k = 0; k < SCAN_VEC; ++k)
                 if (k < per / 4) s[q] += v[q][k].x + v[q][k].y + v[q][k].z + v[q][k].w;
