@@ -1111,11 +1111,13 @@ __global__ __launch_bounds__(256) void k_occ_accumulate(OccArgs a, T *__restrict
             wpart += w;
             if (w == 0) continue;
             const int64_t base = v * a.L;
-            for (int32_t i0 = 0; i0 < t; i0 += 8) {  // eight ids in flight
-                int32_t id[8];
-                for (int u = 0; u < 8; ++u) id[u] = i0 + u < t ? read_id<I32>(a.ballots, base + i0 + u) : -1;
-                for (int u = 0; u < 8; ++u)
-                    if (i0 + u < t) add(id[u], w);
+            // sixteen ids in flight, every load unconditional (positions past t
+            // repeat the last one and are not added)
+            for (int32_t i0 = 0; i0 < t; i0 += 16) {
+                uint32_t raw[16];
+                for (int u = 0; u < 16; ++u) raw[u] = load_raw<I32>(a.ballots, base + min(i0 + u, t - 1));
+                for (int u = 0; u < 16; ++u)
+                    if (i0 + u < t) add(raw_id<I32>(raw[u]), w);
             }
         }
     }
