@@ -560,7 +560,7 @@ def bench_batch(args):
 
     import paper_2505_12976_amd as sz
     import workload
-    from paper_2505_12976_amd.batch import Packed, alloc_outputs
+    from paper_2505_12976_amd.batch import Packed, alloc_outputs, tuned_closures
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
@@ -574,10 +574,9 @@ def bench_batch(args):
     ballots = torch.from_numpy(flat).to(dev)
     del flat
     t0 = time.time()
-    ctx.batch_autotune(16, int(ms.max()))
-    nbuckets = (int(ms.max()) + 31) // 32
-    tuned = [ctx.batch_get_closure(16, 32 * (b + 1)) for b in range(nbuckets)]
-    say(f"batch: autotuned closure schedules in {time.time() - t0:.1f}s: {tuned}")
+    tuned, from_file = tuned_closures(ctx, 16, int(ms.max()))
+    say(f"batch: closure schedules {'read from the tuning file' if from_file else 'autotuned'} "
+        f"in {time.time() - t0:.1f}s: {tuned}")
     plan = ctx.batch_plan(desc, "u16", "winning_votes")
     outs = alloc_outputs(packed, dev)
 
@@ -686,6 +685,7 @@ def bench_batch(args):
         "count_comparisons": count_ops,
         "closure_updates": closure_ops,
         "closure_schedule_by_bucket": tuned,
+        "closure_schedules_from_tuning_file": from_file,
         "roofline": roof,
     }
     plan.destroy()

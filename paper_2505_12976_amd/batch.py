@@ -61,3 +61,65 @@ def alloc_outputs(packed: Packed, device, with_p=True):
     bb = torch.empty(max(packed.vec_elems, 1), dtype=torch.int32, device=device)
     order = torch.empty_like(bb)
     return {"d": d, "p": p, "is_winner": w, "n_winners": nw, "beaten_by": bb, "order": order}
+
+
+# ------------------------------------------------------------------ persisted schedules
+def _library_digest() -> str:
+    import hashlib
+    from . import LIB_PATH
+    h = hashlib.sha256()
+    with open(LIB_PATH, "rb") as f:
+        for block in iter(lambda: f.read(1 << 20), b""):
+            h.update(block)
+    return h.hexdigest()[:16]
+
+
+def _device_key(ctx) -> str:
+    import torch
+    p = torch.cuda.get_device_properties(ctx._torch_device)
+    return f"{getattr(p, 'gcnArchName', '?')}|{p.name}|{p.multi_processor_count}"
+
+
+def default_tuning_path() -> str:
+    import os
+    base = os.environ.get("XDG_CACHE_HOME") or os.path.join(os.path.expanduser("~"), ".cache")
+    return os.path.join(base, "schulze_mi355x", "batch_closure.json")
+
+
+def tuned_closures(ctx, value_bits: int, m_max: int, path: str | None = None, device_key: str | None = None,
+                   library: str | None = None, retune: bool = False):
+    """Closure schedules of the batch kernel per bucket of 32 candidates up
+    to m_max, for values of value_bits bits.  The table is kept in a JSON
+    file (default: default_tuning_path()) keyed by the device (architecture,
+    name, compute units), the library build (a digest of libschulze.so) and
+    the value width: a hit sets the stored schedules, a miss (or retune, or
+    a stored table that stops below m_max) runs Context.batch_autotune and
+    stores its choice.  Returns (schedules per bucket, True if they came
+    from the file)."""
+    import json
+    import os
+    path = path or default_tuning_path()
+    key = "|".join([device_key or _device_key(ctx), library or _library_digest(), str(int(value_bits))])
+    nb = (int(m_max) + 31) // 32
+    table = {}
+    if os.path.exists(path):
+        try:
+            with open(path) as f:
+                table = json.load(f)
+        except (OSError, ValueError):
+            table = {}  # unreadable: tune again and rewrite it
+    entry = table.get(key)
+    if not retune and isinstance(entry, dict) and len(entry.get("schedules", [])) >= nb:
+        sched = list(entry["schedules"][:nb])
+        for b, v in enumerate(sched):
+            ctx.batch_set_closure(value_bits, 32 * b + 1, 32 * (b + 1), v)
+        return sched, True
+    ms = ctx.batch_autotune(value_bits, int(m_max))
+    sched = [ctx.batch_get_closure(value_bits, 32 * (b + 1)) for b in range(nb)]
+    table[key] = {"schedules": sched, "m_max": int(m_max), "ms": [[float(x) for x in row] for row in ms]}
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+    return sched, False

@@ -14,7 +14,7 @@ import numpy as np
 
 NF, NH = 16, 128
 N_PARAMS = NF * NH + NH + NH * NH + NH + NH + 1
-CHECKPOINT_VERSION = 1
+CHECKPOINT_VERSION = 2  # 2: a CRC-32 of every stored array and the step
 
 
 def init_params(seed: int = 0) -> np.ndarray:
@@ -30,22 +30,44 @@ def init_params(seed: int = 0) -> np.ndarray:
     return p
 
 
+def _checkpoint_crc(version: int, params, adam_m, adam_v, step: int, keys, values) -> int:
+    """CRC-32 over the stored arrays (little-endian bytes), the step and the
+    metadata strings, in a fixed order."""
+    import zlib
+    crc = zlib.crc32(np.int64(version).tobytes())
+    for a in (params, adam_m, adam_v):
+        crc = zlib.crc32(np.ascontiguousarray(a, dtype="<f4").tobytes(), crc)
+    crc = zlib.crc32(np.int64(step).tobytes(), crc)
+    for k, v in zip(keys, values):
+        crc = zlib.crc32(str(k).encode() + b"\0" + str(v).encode() + b"\0", crc)
+    return crc
+
+
 def save_checkpoint(path: str, params: np.ndarray, adam_m: np.ndarray, adam_v: np.ndarray, step: int,
                     meta: dict | None = None) -> None:
     meta = meta or {}
-    np.savez(path, version=np.int64(CHECKPOINT_VERSION), params=params.astype(np.float32),
-             adam_m=adam_m.astype(np.float32), adam_v=adam_v.astype(np.float32), step=np.int64(step),
-             meta_keys=np.array(list(meta.keys()), dtype=str), meta_values=np.array([str(v) for v in meta.values()],
-                                                                                      dtype=str))
+    keys = [str(k) for k in meta.keys()]
+    values = [str(v) for v in meta.values()]
+    p32, m32, v32 = (np.asarray(a, dtype=np.float32) for a in (params, adam_m, adam_v))
+    crc = _checkpoint_crc(CHECKPOINT_VERSION, p32, m32, v32, step, keys, values)
+    np.savez(path, version=np.int64(CHECKPOINT_VERSION), params=p32, adam_m=m32, adam_v=v32, step=np.int64(step),
+             meta_keys=np.array(keys, dtype=str), meta_values=np.array(values, dtype=str), crc32=np.int64(crc))
 
 
 def load_checkpoint(path: str) -> dict:
+    """Read a checkpoint written by save_checkpoint; ValueError if its version
+    is unknown, its CRC does not match its contents or its size is wrong."""
     with np.load(path, allow_pickle=False) as z:
         if int(z["version"]) != CHECKPOINT_VERSION:
             raise ValueError(f"unsupported checkpoint version {int(z['version'])}")
         out = {k: z[k] for k in ("params", "adam_m", "adam_v")}
         out["step"] = int(z["step"])
-        out["meta"] = dict(zip(z["meta_keys"].tolist(), z["meta_values"].tolist()))
+        keys, values = z["meta_keys"].tolist(), z["meta_values"].tolist()
+        stored = int(z["crc32"])
+    out["meta"] = dict(zip(keys, values))
+    if _checkpoint_crc(CHECKPOINT_VERSION, out["params"], out["adam_m"], out["adam_v"], out["step"], keys,
+                       values) != stored:
+        raise ValueError("checkpoint CRC mismatch: the file is damaged")
     if out["params"].shape != (N_PARAMS,):
         raise ValueError("checkpoint has the wrong number of parameters")
     return out

@@ -293,6 +293,25 @@ def test_batch_autotune_then_exact(ctx):
         ctx.batch_set_closure(bits, 1, 1024, "auto")
 
 
+def test_batch_tuned_schedules_persist(ctx, tmp_path):
+    """The tuned schedules are stored per device and library build: the
+    second call reads them back, sets them and tunes nothing."""
+    from paper_2505_12976_amd.batch import tuned_closures
+    path = str(tmp_path / "tuning.json")
+    s1, hit1 = tuned_closures(ctx, 16, 96, path=path)
+    ctx.batch_set_closure(16, 1, 1024, "auto")
+    s2, hit2 = tuned_closures(ctx, 16, 96, path=path)
+    log(f"[case] tuned schedules {s1} / {s2}")
+    assert not hit1 and hit2 and s1 == s2 and len(s1) == 3
+    assert [ctx.batch_get_closure(16, 32 * (b + 1)) for b in range(3)] == s2
+    els = [e for e in mixed_elections(3011) if e[1] <= 96]
+    packed, plan, outs = run_batch(ctx, els)
+    assert ctx.device_error() == 0
+    assert_matches(packed, outs, expected(els, "winning_votes"), "persisted schedules")
+    plan.destroy()
+    ctx.batch_set_closure(16, 1, 1024, "auto")
+
+
 def test_batch_of_the_batched_workload_shape(ctx):
     """64 elections drawn like the 4096-election workload (m ~ U{8..512},
     n ~ U{50..20000}, phi ~ U[0.5, 1]); the oracle checks every election."""
