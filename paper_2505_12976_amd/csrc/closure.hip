@@ -56,10 +56,11 @@ __device__ inline bool gated_off(const int32_t *gate, int32_t want) { return gat
 // need the same two blocks of d, so every count is read once.
 template <typename E>
 __global__ __launch_bounds__(256) void k_weights(const E *__restrict__ d, int64_t ldd, int32_t m, int mode,
-                                                 E *__restrict__ P, int64_t ld, int32_t mp, int dvec) {
+                                                 E *__restrict__ P, int64_t ld, int32_t mp, int dvec,
+                                                 const int32_t *gate = nullptr, int32_t want = 0) {
     __shared__ E a[64][65];  // a[r][c] = d[I0 + r][J0 + c]
     __shared__ E b[64][65];  // b[r][c] = d[J0 + r][I0 + c]
-    if (blockIdx.y > blockIdx.x) return;
+    if (blockIdx.y > blockIdx.x || gated_off(gate, want)) return;
     const int32_t I0 = blockIdx.y * 64, J0 = blockIdx.x * 64;
     tio::load<E>(a, d, ldd, I0, J0, m, m, dvec != 0);
     tio::load<E>(b, d, ldd, J0, I0, m, m, dvec != 0);
@@ -527,56 +528,12 @@ constexpr int32_t RANK_BLOCK = 1024;            // bitmap words per scan block
 constexpr int32_t RANK_BLOCKS = RANK_WORDS / RANK_BLOCK;
 constexpr int32_t RANK_MIN_M = 1024;            // below this the decision's synchronisation is not worth it
 
-// Mark every nonzero value of P in the bitmap; flags[0] = 1 if a value is
-// >= RANK_CAP.  Values below RANK_LDS_BITS (the frequent small ones) are
-// first gathered in a workgroup bitmap in LDS and merged once per workgroup,
-// so that the global bitmap sees one atomic per set word and workgroup
-// instead of one per repeated value.
+// Values below RANK_LDS_BITS (the frequent small ones) are gathered in a
+// workgroup bitmap in LDS and merged once per workgroup, so that the global
+// bitmap sees one atomic per set word and workgroup instead of one per
+// repeated value.
 constexpr int32_t RANK_LDS_WORDS = 8192;  // 32 KB: values below 2^18
 constexpr int32_t RANK_LDS_BITS = RANK_LDS_WORDS * 32;
-__global__ __launch_bounds__(256) void k_rank_mark(const int32_t *__restrict__ P, int64_t count,
-                                                   uint32_t *__restrict__ bitmap, int32_t *__restrict__ flags) {
-    __shared__ uint32_t local[RANK_LDS_WORDS];
-    for (int i = threadIdx.x; i < RANK_LDS_WORDS; i += 256) local[i] = 0u;
-    __syncthreads();
-    bool wide = false;
-    auto mark = [&](int32_t v) {
-        if (v == 0) return;
-        if (v >= RANK_CAP || v < 0) {
-            wide = true;
-            return;
-        }
-        const uint32_t bit = 1u << (v & 31);
-        if (v < RANK_LDS_BITS) {
-            if (!(local[v >> 5] & bit)) atomicOr(&local[v >> 5], bit);
-        } else {
-            uint32_t *word = bitmap + (v >> 5);
-            if (!(*word & bit)) atomicOr(word, bit);
-        }
-    };
-    // count is a multiple of 4 and P 16-byte aligned: MARK_STEP 16-byte
-    // loads in flight per thread and step, issued unconditionally (past the
-    // end they repeat the last vector and count as zero: a load under a
-    // condition is waited for inside it)
-    constexpr int MARK_STEP = 8;
-    const int4 *P4 = reinterpret_cast<const int4 *>(P);
-    const int64_t n4 = count / 4, stride = (int64_t)gridDim.x * 256;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n4; e += MARK_STEP * stride) {
-        int4 q[MARK_STEP];
-        for (int u = 0; u < MARK_STEP; ++u) q[u] = P4[min(e + u * stride, n4 - 1)];
-        for (int u = 0; u < MARK_STEP; ++u) {
-            if (e + u * stride >= n4) q[u] = make_int4(0, 0, 0, 0);
-            mark(q[u].x);
-            mark(q[u].y);
-            mark(q[u].z);
-            mark(q[u].w);
-        }
-    }
-    if (wide) flags[0] = 1;
-    __syncthreads();
-    for (int i = threadIdx.x; i < RANK_LDS_WORDS; i += 256)
-        if (local[i]) atomicOr(&bitmap[i], local[i]);
-}
 
 // Per block of RANK_BLOCK words: number of marked values.
 __global__ __launch_bounds__(256) void k_rank_blocks(const uint32_t *__restrict__ bitmap,
@@ -661,47 +618,134 @@ __global__ __launch_bounds__(256) void k_rank_words(const uint32_t *__restrict__
     }
 }
 
-// P16 = rank of P (0 for 0); four elements per thread (count is a multiple
-// of 4, both arrays 16-byte aligned).
-__global__ __launch_bounds__(256) void k_rank_apply(const int32_t *__restrict__ P, int64_t count,
-                                                    const uint32_t *__restrict__ bitmap,
-                                                    const uint32_t *__restrict__ word_rank,
-                                                    uint16_t *__restrict__ P16, const int32_t *gate) {
-    if (gated_off(gate, 1)) return;
-    // rank of v: marked values below it plus one, 0 for 0 (both lookups
-    // unconditional, word 0 for the value 0: values are below RANK_CAP
-    // whenever this kernel runs)
-    // APPLY_STEP vectors per thread and step, each load issued
-    // unconditionally (past the end: the last vector again, not stored), so
-    // that the loads and then the table lookups of a step are in flight
-    // together
-    constexpr int APPLY_STEP = 4;
-    const int4 *P4 = reinterpret_cast<const int4 *>(P);
-    ushort4 *Q4 = reinterpret_cast<ushort4 *>(P16);
-    const int64_t n4 = count / 4, stride = (int64_t)gridDim.x * 256;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n4; e += APPLY_STEP * stride) {
-        int4 q[APPLY_STEP];
-        for (int u = 0; u < APPLY_STEP; ++u) q[u] = P4[min(e + u * stride, n4 - 1)];
-        // every lookup of the step first, then the ranks
-        uint32_t bw[APPLY_STEP][4], wr[APPLY_STEP][4];
-        for (int u = 0; u < APPLY_STEP; ++u) {
-            const int32_t v[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
-            for (int c = 0; c < 4; ++c) {
-                bw[u][c] = bitmap[(uint32_t)v[c] >> 5];
-                wr[u][c] = word_rank[(uint32_t)v[c] >> 5];
+// Edge weight from d[i][j] = x and d[j][i] = y (0 on the diagonal and where
+// x <= y), as in k_weights.
+__device__ inline int32_t weight_of(int32_t x, int32_t y, bool diag, int mode) {
+    if (diag || x <= y) return 0;
+    return mode == SCHULZE_MARGIN ? x - y : x;
+}
+
+// (I, J), I <= J, of pair q in the order J = 0, 1, ... and I = 0..J.
+__device__ inline void pair_of(int64_t q, int32_t &I, int32_t &J) {
+    int64_t j = (int64_t)((sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
+    while (j * (j + 1) / 2 > q) --j;
+    while ((j + 1) * (j + 2) / 2 <= q) ++j;
+    J = (int32_t)j;
+    I = (int32_t)(q - j * (j + 1) / 2);
+}
+
+// Every nonzero weight value marked in the bitmap (flags[0] = 1 if a value
+// is >= RANK_CAP), straight from d: the weights of both tiles of each pair
+// of 64 x 64 blocks (I, J), (J, I) are computed as in k_weights and never
+// written (the ranked closure needs only their ranks; the int32 closure, if
+// the values cannot be ranked, writes its own weights).  Persistent over the
+// pairs, so that each workgroup merges its LDS bitmap once; the next pair's
+// tiles are loaded into registers while the current pair is marked (VEC:
+// 16-byte loads, d 16-byte aligned with m a multiple of 4; what they read
+// past m is ignored).
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_weights_mark(const int32_t *__restrict__ d, int64_t ldd, int32_t m,
+                                                      int mode, uint32_t *__restrict__ bitmap,
+                                                      int32_t *__restrict__ flags) {
+    __shared__ int32_t a[64][65];  // a[r][c] = d[I0 + r][J0 + c]
+    __shared__ int32_t b[64][65];  // b[r][c] = d[J0 + r][I0 + c]
+    __shared__ uint32_t local[RANK_LDS_WORDS];
+    for (int i = threadIdx.x; i < RANK_LDS_WORDS; i += 256) local[i] = 0u;
+    bool wide = false;
+    auto mark = [&](int32_t v) {
+        if (v == 0) return;
+        if (v >= RANK_CAP || v < 0) {
+            wide = true;
+            return;
+        }
+        const uint32_t bit = 1u << (v & 31);
+        if (v < RANK_LDS_BITS) {
+            if (!(local[v >> 5] & bit)) atomicOr(&local[v >> 5], bit);
+        } else {
+            uint32_t *word = bitmap + (v >> 5);
+            if (!(*word & bit)) atomicOr(word, bit);
+        }
+    };
+    const int32_t nt = (m + 63) / 64;
+    const int64_t npairs = (int64_t)nt * (nt + 1) / 2;
+    tio::Regs<int32_t> ga, gb;
+    auto fetch_pair = [&](int64_t q) {
+        int32_t I, J;
+        pair_of(q, I, J);
+        tio::fetch<int32_t, VEC>(ga, d, ldd, I * 64, J * 64, m, m);
+        tio::fetch<int32_t, VEC>(gb, d, ldd, J * 64, I * 64, m, m);
+    };
+    if (blockIdx.x < npairs) fetch_pair(blockIdx.x);
+    for (int64_t q = blockIdx.x; q < npairs; q += gridDim.x) {
+        int32_t I, J;
+        pair_of(q, I, J);
+        const int32_t I0 = I * 64, J0 = J * 64;
+        __syncthreads();  // the previous pair's tiles are read
+        tio::put<int32_t>(a, ga);
+        tio::put<int32_t>(b, gb);
+        __syncthreads();
+        if (q + gridDim.x < npairs) fetch_pair(q + gridDim.x);
+        for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+            const int r = e >> 6, c = e & 63;
+            // (each tile's own bounds: a partial tile's rows are the other's columns)
+            if (I0 + r < m && J0 + c < m) mark(weight_of(a[r][c], b[c][r], I0 + r == J0 + c, mode));
+            if (I != J && J0 + r < m && I0 + c < m) mark(weight_of(b[r][c], a[c][r], false, mode));
+        }
+    }
+    if (wide) flags[0] = 1;
+    __syncthreads();
+    for (int i = threadIdx.x; i < RANK_LDS_WORDS; i += 256)
+        if (local[i]) atomicOr(&bitmap[i], local[i]);
+}
+
+// P16 = rank of the weights of d (0 for 0), straight from d: one workgroup
+// per pair of 64 x 64 blocks (I, J), (J, I) of the padded mp x mp matrix
+// (zero past m); the table lookups of a thread's 32 elements are issued
+// together before the ranks are formed.
+__global__ __launch_bounds__(256) void k_rank_apply_d(const int32_t *__restrict__ d, int64_t ldd, int32_t m,
+                                                      int mode, int dvec, const uint32_t *__restrict__ bitmap,
+                                                      const uint32_t *__restrict__ word_rank,
+                                                      uint16_t *__restrict__ P16, int64_t ld, int32_t mp,
+                                                      const int32_t *gate) {
+    __shared__ int32_t a[64][65];
+    __shared__ int32_t b[64][65];
+    if (blockIdx.y > blockIdx.x || gated_off(gate, 1)) return;
+    const int32_t I0 = blockIdx.y * 64, J0 = blockIdx.x * 64;
+    tio::load<int32_t>(a, d, ldd, I0, J0, m, m, dvec != 0);
+    tio::load<int32_t>(b, d, ldd, J0, I0, m, m, dvec != 0);
+    __syncthreads();
+    // thread: rows r = t / 8 and r + 32, eight columns from c8 = 8 (t % 8); both tiles
+    const int r0 = threadIdx.x >> 3, c8 = (threadIdx.x & 7) * 8;
+    int32_t w[2][2][8];  // [tile][row][column]
+    for (int h = 0; h < 2; ++h)
+        for (int u = 0; u < 8; ++u) {
+            const int r = r0 + 32 * h, c = c8 + u;
+            w[0][h][u] = weight_of(a[r][c], b[c][r], I0 + r == J0 + c, mode);
+            w[1][h][u] = I0 != J0 ? weight_of(b[r][c], a[c][r], false, mode) : 0;
+        }
+    uint32_t bw[2][2][8], wr[2][2][8];
+    for (int t = 0; t < 2; ++t)
+        for (int h = 0; h < 2; ++h)
+            for (int u = 0; u < 8; ++u) {
+                const uint32_t wd = (uint32_t)w[t][h][u] >> 5;  // values are below RANK_CAP when this runs
+                bw[t][h][u] = bitmap[wd];
+                wr[t][h][u] = word_rank[wd];
             }
+    for (int t = 0; t < 2; ++t) {
+        if (t == 1 && I0 == J0) break;
+        const int32_t R0 = t ? J0 : I0, C0 = t ? I0 : J0;
+        for (int h = 0; h < 2; ++h) {
+            const int32_t row = R0 + r0 + 32 * h;
+            if (row >= mp) continue;
+            uint16_t k[8];
+            for (int u = 0; u < 8; ++u) {
+                const int32_t v = w[t][h][u];
+                k[u] = v == 0 ? (uint16_t)0
+                              : (uint16_t)(wr[t][h][u] + __popc(bw[t][h][u] & ((1u << (v & 31)) - 1u)) + 1u);
+            }
+            // mp and ld are multiples of 64 and P16 is 16-byte aligned: eight columns are one store
+            *reinterpret_cast<uint4 *>(P16 + (int64_t)row * ld + C0 + c8) = tio::pack<uint16_t>(k);
         }
-        ushort4 r[APPLY_STEP];
-        for (int u = 0; u < APPLY_STEP; ++u) {
-            const int32_t v[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
-            uint16_t k[4];
-            for (int c = 0; c < 4; ++c)
-                k[c] = v[c] == 0 ? (uint16_t)0
-                                 : (uint16_t)(wr[u][c] + __popc(bw[u][c] & ((1u << (v[c] & 31)) - 1u)) + 1u);
-            r[u] = make_ushort4(k[0], k[1], k[2], k[3]);
-        }
-        for (int u = 0; u < APPLY_STEP; ++u)
-            if (e + u * stride < n4) Q4[e + u * stride] = r[u];
     }
 }
 
@@ -767,9 +811,7 @@ int run_closure_ranked(schulze_ctx *ctx, hipStream_t s, const int32_t *d, int64_
         return rc;
     if ((rc = ws_reserve(ctx, WS_FLAGS, std::max(flag_bytes(mp / BI), flag_bytes(mp / BU)))) != SCHULZE_OK) return rc;
     int32_t *P = static_cast<int32_t *>(ctx->ws[WS_CLOSURE]);
-    dim3 wgrid((unsigned)ceil_div(mp, 64), (unsigned)ceil_div(mp, 64));
-    SCHULZE_LAUNCH(ctx, K_WEIGHTS, s, k_weights<int32_t><<<wgrid, dim3(256), 0, s>>>(d, ldd, m, mode, P, ld, mp,
-                                                                                tio::vec_ok<int32_t>(d, ldd) ? 1 : 0));
+    const int dvec = tio::vec_ok<int32_t>(d, ldd) ? 1 : 0;
 
     char *q = static_cast<char *>(ctx->ws[WS_RANKED]);
     uint32_t *bitmap = reinterpret_cast<uint32_t *>(q);
@@ -781,24 +823,34 @@ int run_closure_ranked(schulze_ctx *ctx, hipStream_t s, const int32_t *d, int64_
     if ((rc = fill_u32(ctx, s, bitmap, RANK_WORDS, 0u)) != SCHULZE_OK) return rc;
     if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(value_of), 1, 0u)) != SCHULZE_OK) return rc;
     if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(flags), 3, 0u)) != SCHULZE_OK) return rc;
-    const unsigned egrid = (unsigned)std::min<int64_t>(ceil_div(count, 256), (int64_t)ctx->num_cus * 16);
-    // two marking workgroups per CU: each merges its LDS bitmap once
-    const unsigned mgrid = (unsigned)std::min<int64_t>(ceil_div(count, 1024), (int64_t)ctx->num_cus * 2);
-    SCHULZE_LAUNCH(ctx, K_RANK, s, k_rank_mark<<<dim3(mgrid), dim3(256), 0, s>>>(P, count, bitmap, flags));
+    // The weights' values are marked straight from d (the weights are not
+    // written here): two marking workgroups per CU, each merging its LDS
+    // bitmap once.
+    const unsigned mgrid = (unsigned)std::min<int64_t>(ceil_div((int64_t)m * m, 8192), (int64_t)ctx->num_cus * 2);
+    if (dvec && m % 4 == 0)
+        SCHULZE_LAUNCH(ctx, K_WEIGHTS, s,
+                       k_weights_mark<true><<<dim3(mgrid), dim3(256), 0, s>>>(d, ldd, m, mode, bitmap, flags));
+    else
+        SCHULZE_LAUNCH(ctx, K_WEIGHTS, s,
+                       k_weights_mark<false><<<dim3(mgrid), dim3(256), 0, s>>>(d, ldd, m, mode, bitmap, flags));
     SCHULZE_LAUNCH(ctx, K_RANK, s, k_rank_blocks<<<dim3(RANK_BLOCKS), dim3(256), 0, s>>>(bitmap, block_off));
     SCHULZE_LAUNCH(ctx, K_RANK, s, k_rank_top<<<dim3(1), dim3(256), 0, s>>>(block_off, flags));
     // flags[2] decides on the device; both variants are queued, each gated
     const int32_t *ranked = flags + 2;
-    // values too wide or too many: the int32 closure on the weights
+    const dim3 wgrid((unsigned)ceil_div(mp, 64), (unsigned)ceil_div(mp, 64));
+    // values too wide or too many: the weights, then the int32 closure on them
+    SCHULZE_LAUNCH(ctx, K_WEIGHTS, s,
+                   k_weights<int32_t><<<wgrid, dim3(256), 0, s>>>(d, ldd, m, mode, P, ld, mp, dvec, ranked, 0));
     if ((rc = close_padded<int32_t, BI>(ctx, s, P, ld, mp / BI, ranked, 0)) != SCHULZE_OK) return rc;
     SCHULZE_LAUNCH(ctx, K_FW_STORE, s,
                    k_fw_store<int32_t><<<dim3((unsigned)m), dim3(256), 0, s>>>(P, ld, m, p, ldp, ranked, 0));
-    // otherwise the uint16 closure on the ranks
+    // otherwise the ranks of the weights (straight from d) and the uint16 closure on them
     SCHULZE_LAUNCH(ctx, K_RANK, s,
                    k_rank_words<<<dim3(RANK_BLOCKS), dim3(256), 0, s>>>(bitmap, block_off, word_rank, value_of,
                                                                         ranked));
     SCHULZE_LAUNCH(ctx, K_RANK, s,
-                   k_rank_apply<<<dim3(egrid), dim3(256), 0, s>>>(P, count, bitmap, word_rank, P16, ranked));
+                   k_rank_apply_d<<<wgrid, dim3(256), 0, s>>>(d, ldd, m, mode, dvec, bitmap, word_rank, P16, ld, mp,
+                                                              ranked));
     if ((rc = close_padded<uint16_t, BU>(ctx, s, P16, ld, mp / BU, ranked, 1)) != SCHULZE_OK) return rc;
     SCHULZE_LAUNCH(ctx, K_RANK, s,
                    k_rank_store<<<dim3((unsigned)m), dim3(256), 0, s>>>(P16, ld, m, value_of, p, ldp, ranked));

@@ -18,7 +18,9 @@ pytestmark = pytest.mark.gpu
 
 RANKED = 16    # value width of the recurrence: ranks in packed uint16
 FALLBACK = 32  # int32 values
-RANK_LAUNCHES = 6  # mark, block sums, scan (deciding), word ranks, apply, store (gated on the decision)
+# block sums, scan (deciding), word ranks, ranks from d, store (gated on the
+# decision); the marking of the values runs with the weights
+RANK_LAUNCHES = 5
 
 
 def log(msg):
@@ -82,6 +84,18 @@ def test_few_values_take_ranks(ctx, m):
     d = rng.integers(0, 4000, size=(m, m), dtype=np.int64)
     np.fill_diagonal(d, 0)
     check(ctx, d, "winning_votes", RANKED, "few-values")
+
+
+@pytest.mark.parametrize("m", [1100, 1027])
+def test_counts_with_rare_values_take_ranks(ctx, m):
+    """Counts of truncated ballots: thousands of distinct weight values, many
+    of them once only, in a matrix whose last block of 64 is partial (m = 1100:
+    16-byte reads of d; m = 1027: one element at a time) -- every value,
+    including those only in the partial blocks, must be ranked."""
+    import workload
+    b = workload.pl_zipf(74 + m, 3000, m, 1.0, 24)
+    d = oracle.pairwise(b, m)
+    check(ctx, d, "winning_votes", RANKED, "rare-values")
 
 
 def test_margins_take_ranks(ctx):
