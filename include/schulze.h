@@ -468,6 +468,22 @@ int schulze_set_value_ranking(schulze_ctx *ctx, int enable);
 int schulze_closure_value_bits(schulze_ctx *ctx, void *stream, int32_t *value_bits);
 
 /*
+ * Limits of the frontier sweeps' bounded waits, for tests of their failure
+ * paths (callers that test how a stuck or runaway sweep is reported; not
+ * for normal use).  The sweeps of schulze_widest_from, schulze_verify,
+ * schulze_verify_noalloc, schulze_winners_learned, schulze_winners_propagate
+ * and schulze_topk_propagate meet at a grid barrier once per sweep; a
+ * workgroup that polls the barrier more than spin_limit times, or a run
+ * that reaches max_sweeps sweeps with a frontier left (impossible for a
+ * correct run: widths only grow), stops every workgroup of the launch,
+ * leaves its outputs unwritten and sets SCHULZE_EDEVICE in the device error
+ * word; the learned and propagation calls then return SCHULZE_EDEVICE
+ * instead of deciding on the partial result.  0 restores a default (2^24
+ * polls; m + 1 or 2 m + 2 sweeps).  Negative values: SCHULZE_EINVAL.
+ */
+int schulze_set_sweep_limits(schulze_ctx *ctx, int64_t spin_limit, int32_t max_sweeps);
+
+/*
  * Batches of independent elections (Section 2.1 applied to each election of
  * the batch), run by one persistent launch whose workgroups take work items
  * from a queue: ballot scans, pairwise counts split into runs of candidate

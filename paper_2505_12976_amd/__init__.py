@@ -28,7 +28,7 @@ EXPORTS = (
     "schulze_create", "schulze_destroy", "schulze_strerror", "schulze_get_device_error",
     "schulze_pairwise", "schulze_closure", "schulze_winners", "schulze_ranking",
     "schulze_set_timing", "schulze_kernel_time", "schulze_reset_timing", "schulze_set_closure_schedule",
-    "schulze_set_value_ranking", "schulze_set_closure_tile", "schulze_set_sparse_count",
+    "schulze_set_value_ranking", "schulze_set_closure_tile", "schulze_set_sparse_count", "schulze_set_sweep_limits",
     "schulze_weights", "schulze_widest_from", "schulze_verify", "schulze_features",
     "schulze_mlp_param_count", "schulze_mlp_forward", "schulze_mlp_loss", "schulze_mlp_backward", "schulze_mlp_adam",
     "schulze_mlp_train_step",
@@ -130,6 +130,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.schulze_reset_timing.argtypes = [vp]
     lib.schulze_set_closure_schedule.argtypes = [vp, c_int]
     lib.schulze_set_value_ranking.argtypes = [vp, c_int]
+    lib.schulze_set_sweep_limits.argtypes = [vp, c_i64, c_i32]
     lib.schulze_closure_value_bits.argtypes = [vp, vp, ctypes.POINTER(c_i32)]
     lib.schulze_set_proposer.argtypes = [vp, c_int]
     lib.schulze_set_closure_tile.argtypes = [vp, c_int]
@@ -562,6 +563,11 @@ class Context:
     def set_value_ranking(self, enable: bool) -> None:
         """Run int32 closures of m >= 1024 on value ranks in uint16 when the values fit (default on)."""
         _check(self._lib.schulze_set_value_ranking(self._h, int(bool(enable))), "schulze_set_value_ranking")
+
+    def set_sweep_limits(self, spin_limit: int = 0, max_sweeps: int = 0) -> None:
+        """Limits of the frontier sweeps' bounded waits (0: defaults); for tests of the failure paths."""
+        _check(self._lib.schulze_set_sweep_limits(self._h, int(spin_limit), int(max_sweeps)),
+               "schulze_set_sweep_limits")
 
     def set_proposer(self, proposer: str) -> None:
         """First proposal of winners_learned: "network" (default), "borda", "copeland" or "filter+borda"."""

@@ -219,6 +219,13 @@ extern "C" int schulze_set_value_ranking(schulze_ctx *ctx, int enable) {
     return SCHULZE_OK;
 }
 
+extern "C" int schulze_set_sweep_limits(schulze_ctx *ctx, int64_t spin_limit, int32_t max_sweeps) {
+    if (!ctx || spin_limit < 0 || max_sweeps < 0) return SCHULZE_EINVAL;
+    ctx->sweep_spin_limit = spin_limit;
+    ctx->sweep_max_sweeps = max_sweeps;
+    return SCHULZE_OK;
+}
+
 extern "C" int schulze_closure_value_bits(schulze_ctx *ctx, void *stream, int32_t *value_bits) {
     if (!ctx || !value_bits) return SCHULZE_EINVAL;
     if (ctx->closure_bits != 0 || !ctx->closure_ranked_flag) {

@@ -40,6 +40,9 @@ struct PendingTiming {
     hipEvent_t start, stop;
 };
 
+// Polls of a frontier sweep's grid barrier before it is declared stuck.
+constexpr int64_t SWEEP_SPIN_LIMIT = (int64_t)1 << 24;
+
 struct schulze_ctx {
     int device = 0;
     int num_cus = 0;
@@ -66,6 +69,10 @@ struct schulze_ctx {
     void *verify_scratch = nullptr;
     // first proposal of the learned path (SCHULZE_PROPOSER_*)
     int proposer = SCHULZE_PROPOSER_NETWORK;
+    // limits of the frontier sweeps' bounded waits (0: the defaults), for
+    // tests of their failure paths (schulze_set_sweep_limits)
+    int64_t sweep_spin_limit = 0;
+    int32_t sweep_max_sweeps = 0;
     // truncated ballots: pair scattering with device-wide atomics instead of bucketing
     bool legacy_pairs = false;
     // batch closure schedule per value width (16, 32) and bucket of 32 candidates; -1 = built-in

@@ -506,10 +506,10 @@ int prop_decide_all(schulze_ctx *ctx, hipStream_t s, int32_t m, PropBufs<E> &b, 
                 P.front[1] = b.front[2 * q + 1];
                 P.count = b.cnt + 64 * q;
             }
-            a.run.max_sweeps = 2 * m + 2;
+            a.run.max_sweeps = ctx->sweep_max_sweeps > 0 ? ctx->sweep_max_sweeps : 2 * m + 2;
             a.run.bar = b.bar;
             a.run.err = ctx->err;
-            a.run.spin_limit = (int64_t)1 << 24;
+            a.run.spin_limit = ctx->sweep_spin_limit > 0 ? ctx->sweep_spin_limit : SWEEP_SPIN_LIMIT;
             a.m = m;
             a.status = b.status;
             a.label = b.label;
@@ -526,11 +526,15 @@ int prop_decide_all(schulze_ctx *ctx, hipStream_t s, int32_t m, PropBufs<E> &b, 
                 (void)hipGetLastError();
                 return SCHULZE_EDEVICE;
             }
-            int32_t sweeps[2] = {0, 0};
+            int32_t sweeps[2] = {0, 0}, err = 0;
             if (hipMemcpyAsync(&sweeps[0], b.cnt + 3, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipMemcpyAsync(&sweeps[1], b.cnt + 64 + 3, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipMemcpyAsync(&err, ctx->err, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess)
                 return SCHULZE_EDEVICE;
+            // a sweep that gave up (the word stays set for schulze_get_device_error)
+            // leaves no labels to decide on
+            if (err != SCHULZE_OK) return SCHULZE_EDEVICE;
             st.sweeps += sweeps[0] + sweeps[1];
         }
         // mark and dead are adjacent: clear both

@@ -215,10 +215,10 @@ int widest_in(schulze_ctx *ctx, hipStream_t s, const E *const (&A)[NP], const in
         P.count = reinterpret_cast<int32_t *>(p + 4 * v);
         a.out[q] = out[q];
     }
-    a.run.max_sweeps = m + 1;
+    a.run.max_sweeps = ctx->sweep_max_sweeps > 0 ? ctx->sweep_max_sweeps : m + 1;
     a.run.bar = reinterpret_cast<GridBar *>(base + (size_t)NP * (4 * v + 256));
     a.run.err = ctx->err;
-    a.run.spin_limit = (int64_t)1 << 24;
+    a.run.spin_limit = ctx->sweep_spin_limit > 0 ? ctx->sweep_spin_limit : SWEEP_SPIN_LIMIT;
     a.m = m;
     a.s = src;
     int per_cu = 0;

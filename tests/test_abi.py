@@ -69,6 +69,7 @@ def test_null_handles_are_rejected_on_the_host():
     lib.schulze_batch_destroy(vp(None))  # accepted
     ops = ctypes.c_int64(0)
     assert lib.schulze_valu_probe(None, None, 1, 1, None, ctypes.byref(ops)) == sz.EINVAL
+    assert lib.schulze_set_sweep_limits(None, 0, 0) == sz.EINVAL
 
 
 def test_create_without_a_device_fails_cleanly():
