@@ -532,7 +532,8 @@ constexpr int32_t RANK_MIN_M = 1024;            // below this the decision's syn
 // workgroup bitmap in LDS and merged once per workgroup, so that the global
 // bitmap sees one atomic per set word and workgroup instead of one per
 // repeated value.
-constexpr int32_t RANK_LDS_WORDS = 8192;  // 32 KB: values below 2^18
+constexpr int32_t RANK_LDS_WORDS = 1024;  // 4 KB: values below 2^15 (with the two tiles, four workgroups per CU;
+                                          // 32 KB and two per CU took 0.60 ms at m = 16384, this 0.45 ms)
 constexpr int32_t RANK_LDS_BITS = RANK_LDS_WORDS * 32;
 
 // Per block of RANK_BLOCK words: number of marked values.
@@ -824,9 +825,9 @@ int run_closure_ranked(schulze_ctx *ctx, hipStream_t s, const int32_t *d, int64_
     if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(value_of), 1, 0u)) != SCHULZE_OK) return rc;
     if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(flags), 3, 0u)) != SCHULZE_OK) return rc;
     // The weights' values are marked straight from d (the weights are not
-    // written here): two marking workgroups per CU, each merging its LDS
+    // written here): four marking workgroups per CU, each merging its LDS
     // bitmap once.
-    const unsigned mgrid = (unsigned)std::min<int64_t>(ceil_div((int64_t)m * m, 8192), (int64_t)ctx->num_cus * 2);
+    const unsigned mgrid = (unsigned)std::min<int64_t>(ceil_div((int64_t)m * m, 8192), (int64_t)ctx->num_cus * 4);
     if (dvec && m % 4 == 0)
         SCHULZE_LAUNCH(ctx, K_WEIGHTS, s,
                        k_weights_mark<true><<<dim3(mgrid), dim3(256), 0, s>>>(d, ldd, m, mode, bitmap, flags));
