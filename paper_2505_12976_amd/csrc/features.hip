@@ -23,6 +23,12 @@
 namespace {
 
 constexpr int NF = 16;
+// Lanes that share a row of a 64 x 64 tile: eight, so that each store of a
+// wavefront writes whole 128-byte lines (eight rows of eight 16-byte
+// pieces; four lanes per row wrote half lines, and the pass ran 13% slower);
+// a thread takes two rows, r and r + 32.
+constexpr int ROW_LANES = 8;
+constexpr int ROW_HALF = tio::T / 2;
 
 // Per-candidate statistics: one entry per candidate, or per candidate and
 // column super-block for the partials.  Counts are non-negative and below
@@ -67,9 +73,9 @@ struct Acc {
         mn = min(mn, o.mn);
         mx = max(mx, o.mx);
     }
-    // Combine the 4 adjacent lanes that share a row.
-    __device__ void quad_reduce() {
-        for (int off = 1; off < 4; off <<= 1) {
+    // Combine the ROW_LANES adjacent lanes that share a row.
+    __device__ void row_reduce() {
+        for (int off = 1; off < ROW_LANES; off <<= 1) {
             cope += __shfl_xor(cope, off);
             ties += __shfl_xor(ties, off);
             borda += __shfl_xor(borda, off);
@@ -129,8 +135,8 @@ __device__ __forceinline__ void acc_add(Acc<E> &s, int32_t xy, int32_t yx, int32
 // One lane's share of a tile: row r of the rows starting at row0 over the
 // columns starting at col0, with A[r][c] = d[row0 + r][col0 + c] and
 // B[c][r] = d[col0 + c][row0 + r].  The lane takes columns
-// c = 4V k + V g + u (V elements per 16-byte vector), so that the four
-// lanes of a row write 64 contiguous bytes of w and of wt per store:
+// c = 8V k + V g + u (V elements per 16-byte vector), so that the eight
+// lanes of a row write a 128-byte line of w and of wt per store:
 // w[x][y] = wo and wt[x][y] = w[y][x] = wi come out of the same two LDS
 // reads as the statistics.  Interior tiles of aligned matrices, off the
 // diagonal.
@@ -138,19 +144,19 @@ template <typename E, bool MARGIN>
 __device__ __forceinline__ void tile_rows(const E (*A)[tio::PITCH], const E (*B)[tio::PITCH], int r, int g,
                                           int32_t row0, int32_t col0, Acc<E> &s, E *__restrict__ w, int64_t ldw,
                                           E *__restrict__ wt, int64_t ldwt) {
-    constexpr int V = 16 / (int)sizeof(E), KV = tio::T / (4 * V);
+    constexpr int V = 16 / (int)sizeof(E), KV = tio::T / (ROW_LANES * V);
     const int64_t x = row0 + r;
     for (int k = 0; k < KV; ++k) {
         E ow[V], ot[V];
         for (int u = 0; u < V; ++u) {
-            const int c = k * 4 * V + g * V + u;
+            const int c = k * ROW_LANES * V + g * V + u;
             int32_t wo, wi;
             acc_add<E, MARGIN>(s, (int32_t)A[r][c], (int32_t)B[c][r], wo, wi);
             ow[u] = (E)wo;
             ot[u] = (E)wi;
         }
         s.pin();
-        const int32_t c0 = col0 + k * 4 * V + g * V;
+        const int32_t c0 = col0 + k * ROW_LANES * V + g * V;
         if (w) *reinterpret_cast<uint4 *>(w + x * ldw + c0) = tio::pack<E>(ow);
         if (wt) *reinterpret_cast<uint4 *>(wt + x * ldwt + c0) = tio::pack<E>(ot);
     }
@@ -168,8 +174,8 @@ __device__ __forceinline__ void tile_rows_edge(const E (*A)[tio::PITCH], const E
     const int32_t x = row0 + r;
     if (x >= m) return;
 #pragma unroll 1
-    for (int q = 0; q < tio::T / 4; ++q) {
-        const int c = (q / V) * 4 * V + g * V + q % V, y = col0 + c;
+    for (int q = 0; q < tio::T / ROW_LANES; ++q) {
+        const int c = (q / V) * ROW_LANES * V + g * V + q % V, y = col0 + c;
         if (y >= m) continue;
         int32_t wo = 0, wi = 0;
         if (y != x) acc_add<E, MARGIN>(s, (int32_t)A[r][c], (int32_t)B[c][r], wo, wi);
@@ -183,7 +189,7 @@ __device__ __forceinline__ void tile_rows_edge(const E (*A)[tio::PITCH], const E
 // (I, J), I <= J, walks the tile pairs (X, Y) of I x J (of I x I only those
 // with X <= Y), X outer, and loads d[X][Y] and d[Y][X] into LDS: the rows
 // of X gain the columns of Y (registers rs, stored when X is done) and,
-// X != Y, the rows of Y gain the columns of X (reduced over the four lanes
+// X != Y, the rows of Y gain the columns of X (reduced over the eight lanes
 // of a row and added to mir[j], in LDS, per tile of J; stored at the end).
 // Slot s of each partial array holds a candidate's statistics over the
 // columns of super-block s: rows of I over J and rows of J over I, each
@@ -204,10 +210,14 @@ __global__ __launch_bounds__(256) void k_feature_rows(const E *__restrict__ d, i
     if (J < I) return;
     const int32_t nb = (m + 63) / 64;
     const int lane = threadIdx.x & 63;
-    const int r = (threadIdx.x >> 6) * 16 + (lane >> 2), g = lane & 3;  // 4 lanes per row
+    // rows r and r + ROW_HALF, ROW_LANES lanes per row
+    const int r = (threadIdx.x >> 6) * (64 / ROW_LANES) + lane / ROW_LANES, g = lane % ROW_LANES;
     const bool vall = vec == 7;
     if (g == 0)
-        for (int q = 0; q < SBV; ++q) mir[q][r].init();  // read and written by this lane only
+        for (int q = 0; q < SBV; ++q) {  // read and written by this lane only
+            mir[q][r].init();
+            mir[q][r + ROW_HALF].init();
+        }
     // The tile pairs in order: i outer, j from i (diagonal super-block) or
     // 0; the next pair's tiles are fetched into registers while the current
     // pair is processed.
@@ -230,8 +240,9 @@ __global__ __launch_bounds__(256) void k_feature_rows(const E *__restrict__ d, i
     int32_t i = 0, j = 0;
     if (!valid(i, j)) i = SBV;
     if (i < SBV) fetch_pair(i, j);
-    Acc<E> rs;
-    rs.init();
+    Acc<E> rs[2];
+    rs[0].init();
+    rs[1].init();
     while (i < SBV) {
         const int32_t X = I * SBV + i, Y = J * SBV + j;
         const int32_t X0 = X * 64, Y0 = Y * 64;
@@ -243,37 +254,44 @@ __global__ __launch_bounds__(256) void k_feature_rows(const E *__restrict__ d, i
         if (ni < SBV) fetch_pair(ni, nj);  // in flight during the work below
         __syncthreads();
         if (X == Y) {
-            tile_rows_edge<E, MARGIN>(a, a, r, g, X0, Y0, m, rs, w, ldw, wt, ldwt);
+            for (int h = 0; h < 2; ++h)
+                tile_rows_edge<E, MARGIN>(a, a, r + h * ROW_HALF, g, X0, Y0, m, rs[h], w, ldw, wt, ldwt);
         } else {
-            Acc<E> ms;
-            ms.init();
-            if (vall && X0 + 64 <= m && Y0 + 64 <= m) {
-                tile_rows<E, MARGIN>(a, b, r, g, X0, Y0, rs, w, ldw, wt, ldwt);
-                tile_rows<E, MARGIN>(b, a, r, g, Y0, X0, ms, w, ldw, wt, ldwt);
-            } else {
-                tile_rows_edge<E, MARGIN>(a, b, r, g, X0, Y0, m, rs, w, ldw, wt, ldwt);
-                tile_rows_edge<E, MARGIN>(b, a, r, g, Y0, X0, m, ms, w, ldw, wt, ldwt);
+            for (int h = 0; h < 2; ++h) {
+                const int rr = r + h * ROW_HALF;
+                Acc<E> ms;
+                ms.init();
+                if (vall && X0 + 64 <= m && Y0 + 64 <= m) {
+                    tile_rows<E, MARGIN>(a, b, rr, g, X0, Y0, rs[h], w, ldw, wt, ldwt);
+                    tile_rows<E, MARGIN>(b, a, rr, g, Y0, X0, ms, w, ldw, wt, ldwt);
+                } else {
+                    tile_rows_edge<E, MARGIN>(a, b, rr, g, X0, Y0, m, rs[h], w, ldw, wt, ldwt);
+                    tile_rows_edge<E, MARGIN>(b, a, rr, g, Y0, X0, m, ms, w, ldw, wt, ldwt);
+                }
+                ms.row_reduce();
+                if (g == 0) mir[j][rr].merge(ms);
             }
-            ms.quad_reduce();
-            if (g == 0) mir[j][r].merge(ms);
         }
         if (ni != i) {  // the last pair of row tile X: its rows are complete over J
-            rs.quad_reduce();
-            if (g == 0 && X0 + r < m) {
-                if (I == J) rs.merge(mir[i][r]);  // what the tiles before X gave its rows as mirrored rows
-                rs.store(part, (int64_t)J * m + X0 + r);
+            for (int h = 0; h < 2; ++h) {
+                const int rr = r + h * ROW_HALF;
+                rs[h].row_reduce();
+                if (g == 0 && X0 + rr < m) {
+                    if (I == J) rs[h].merge(mir[i][rr]);  // what the tiles before X gave its rows as mirrored rows
+                    rs[h].store(part, (int64_t)J * m + X0 + rr);
+                }
+                rs[h].init();
             }
-            rs.init();
         }
         i = ni;
         j = nj;
     }
     if (I == J || g != 0) return;
-    for (int q = 0; q < SBV; ++q) {
-        const int32_t y = (J * SBV + q) * 64 + r;
-        if (y >= m) break;
-        mir[q][r].store(part, (int64_t)I * m + y);
-    }
+    for (int q = 0; q < SBV; ++q)
+        for (int h = 0; h < 2; ++h) {
+            const int32_t y = (J * SBV + q) * 64 + r + h * ROW_HALF;
+            if (y < m) mir[q][r + h * ROW_HALF].store(part, (int64_t)I * m + y);
+        }
 }
 
 // Combine the S slices' partial statistics of each candidate: a workgroup
