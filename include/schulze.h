@@ -325,8 +325,10 @@ typedef struct {
  * n_voters   feature scale (number of voters).
  * is_winner  m device bytes.   n_winners: NULL or one device int32.
  * stats      NULL or host struct.
- * Workspace: 2 m^2 elements of dtype (weights and transposed weights) plus
- * O(m); m^2 more if the fallback runs.
+ * Workspace: int32 counts: m^2 int32 signed weights w - w^T (both weight
+ * rules give a pair an edge in at most one direction, so w = max(S, 0) and
+ * w^T = max(-S, 0)); 16-bit counts: 2 m^2 elements (w and w^T); plus O(m);
+ * m^2 elements more if the fallback runs.
  */
 int schulze_winners_learned(schulze_ctx *ctx, void *stream, const void *d, int64_t ldd, int32_t m,
                             int dtype, int mode, float n_voters, const float *params,

@@ -139,10 +139,18 @@ int launch_status();
 // Zero `words` 32-bit words with a fill kernel (graph-capture friendly).
 int fill_u32(schulze_ctx *ctx, hipStream_t s, uint32_t *ptr, size_t words, uint32_t value);
 
-// Per-candidate features (as schulze_features) and the weight matrices w and
-// w^T (as schulze_weights) in one pass over d; arguments already checked.
+// Per-candidate features (as schulze_features) and the weights in one pass
+// over d; arguments already checked.  16-bit counts: w and w^T (as
+// schulze_weights) into w and wt.  int32 counts: the signed weights
+// S = w - w^T into w (wt unused): w[i][j] = max(S[i][j], 0),
+// w[j][i] = max(-S[i][j], 0).
 int weights_and_features(schulze_ctx *ctx, hipStream_t s, const void *d, int64_t ldd, int32_t m, int dtype, int mode,
                          float n_voters, float *feat, void *w, int64_t ldw, void *wt, int64_t ldwt);
+
+// schulze_verify over signed weights sw = w - w^T (int32, pitch ld);
+// arguments already checked.
+int verify_signed(schulze_ctx *ctx, hipStream_t s, const int32_t *sw, int64_t ld, int32_t m, int32_t cand,
+                  const float *score, int32_t *p_from, int32_t *p_to, int32_t *verdict, int32_t *tied);
 
 // Device address of the static scratch of schulze_verify_noalloc on `device`
 // (looked up once per device; the device must be current).

@@ -68,20 +68,23 @@ extern "C" int schulze_winners_learned(schulze_ctx *ctx, void *stream, const voi
     const size_t mat = round_up(es * (size_t)m * m, 256);
     const size_t vec_e = round_up(es * (size_t)m, 256), vec_f = round_up(4 * (size_t)m, 256);
     const size_t feat_b = round_up(4 * 16 * (size_t)m, 256);
-    int rc = ws_reserve(ctx, WS_LEARNED, 2 * mat + feat_b + vec_f + 2 * vec_e + vec_f + 256);
+    // int32 counts: one matrix of signed weights w - w^T; 16-bit counts: w and w^T
+    const bool sgn = dtype == SCHULZE_I32;
+    const size_t mats = (sgn ? 1 : 2) * mat;
+    int rc = ws_reserve(ctx, WS_LEARNED, mats + feat_b + vec_f + 2 * vec_e + vec_f + 256);
     if (rc != SCHULZE_OK) return rc;
     char *b = static_cast<char *>(ctx->ws[WS_LEARNED]);
-    void *w = b, *wt = b + mat;
-    float *feat = reinterpret_cast<float *>(b + 2 * mat);
-    float *score = reinterpret_cast<float *>(b + 2 * mat + feat_b);
-    void *p_from = b + 2 * mat + feat_b + vec_f;
-    void *p_to = b + 2 * mat + feat_b + vec_f + vec_e;
-    int32_t *tied = reinterpret_cast<int32_t *>(b + 2 * mat + feat_b + vec_f + 2 * vec_e);
-    int32_t *small = reinterpret_cast<int32_t *>(b + 2 * mat + feat_b + 2 * vec_f + 2 * vec_e);  // verdict + pick
+    void *w = b, *wt = sgn ? nullptr : b + mat;
+    float *feat = reinterpret_cast<float *>(b + mats);
+    float *score = reinterpret_cast<float *>(b + mats + feat_b);
+    void *p_from = b + mats + feat_b + vec_f;
+    void *p_to = b + mats + feat_b + vec_f + vec_e;
+    int32_t *tied = reinterpret_cast<int32_t *>(b + mats + feat_b + vec_f + 2 * vec_e);
+    int32_t *small = reinterpret_cast<int32_t *>(b + mats + feat_b + 2 * vec_f + 2 * vec_e);  // verdict + pick
 
     schulze_learned_stats st{};
     st.proposal = -1;
-    // weights, transposed weights and features in one pass over d
+    // weights (signed, or w and w^T) and features in one pass over d
     if ((rc = weights_and_features(ctx, s, d, ldd, m, dtype, mode, n_voters, feat, w, m, wt, m)) != SCHULZE_OK)
         return rc;
     // scores: the network, or one feature column (Borda: column 2, the vertex
@@ -115,7 +118,9 @@ extern "C" int schulze_winners_learned(schulze_ctx *ctx, void *stream, const voi
     // stops with SCHULZE_EDEVICE (the word stays set for
     // schulze_get_device_error) instead of deciding on stale rows.
     auto verify = [&](int32_t c, int32_t (&v)[4]) -> int {
-        int r = schulze_verify(ctx, stream, w, m, wt, m, m, dtype, c, score, p_from, p_to, small, tied);
+        int r = sgn ? verify_signed(ctx, s, static_cast<const int32_t *>(w), m, m, c, score,
+                                    static_cast<int32_t *>(p_from), static_cast<int32_t *>(p_to), small, tied)
+                    : schulze_verify(ctx, stream, w, m, wt, m, m, dtype, c, score, p_from, p_to, small, tied);
         if (r != SCHULZE_OK) return r;
         ++st.verify_calls;
         int32_t err = 0;

@@ -238,7 +238,7 @@ __global__ __launch_bounds__(256) void k_prop_sweep(SweepArgs<E> a) {
     const uint8_t *status = a.status;
     const bool ok = sweep::run<K, E, 2>(
         a.run, a.m,
-        [](K k, uint32_t wij) -> K {
+        [](int, K k, uint32_t wij) -> K {
             if (wij == 0 || k == 0) return (K)0;
             return (k & HIGH) | (K)min((uint32_t)(k & Key<E>::LOW), wij);
         },

@@ -123,9 +123,9 @@ __device__ inline int32_t *count_at(const Run<X, E, NP> &r, int q, int c) {
     return (NP > 1 && q) ? r.p[NP - 1].count + c : r.p[0].count + c;
 }
 
-// The sweeps.  comb(xi, a) combines a row value with an edge entry a
-// (returning 0 when nothing passes); accept(j) says whether column j may
-// take values.  Returns false if a barrier gave up or the sweep bound was
+// The sweeps.  comb(q, xi, a) combines a row value with an entry a of
+// problem q's matrix (returning 0 when nothing passes; q is uniform over a
+// workgroup); accept(j) says whether column j may take values.  Returns false if a barrier gave up or the sweep bound was
 // passed (the caller records the error).
 template <typename X, typename E, int NP, typename Comb, typename Accept>
 __device__ bool run(const Run<X, E, NP> &r, int32_t m, Comb comb, Accept accept) {
@@ -202,7 +202,7 @@ __device__ bool run(const Run<X, E, NP> &r, int32_t m, Comb comb, Accept accept)
                 for (int u = 0; u < U; ++u) xi[u] = idx[u] < 0 ? (X)0 : x[idx[u] < 0 ? 0 : idx[u]];
                 load_idx(q0 + U * step, idx);
                 for (int u = 0; u < U; ++u)
-                    for (int c = 0; c < CPL; ++c) best[c] = max(best[c], comb(xi[u], a[u][c]));
+                    for (int c = 0; c < CPL; ++c) best[c] = max(best[c], comb(q, xi[u], a[u][c]));
             }
             for (int c = 0; c < CPL; ++c) part[wave][lane_col<E>(lane, c)] = best[c];
         }

@@ -12,6 +12,12 @@
 // anything, so each sweep walks just that frontier.  The target direction
 // p[.][t] is the same computation on the transposed weights.
 //
+// Both weight rules give an edge at most one direction per pair (winning
+// votes: the larger count; margin: the positive difference), so the signed
+// matrix S = w - w^T holds both: w[i][j] = max(S[i][j], 0) and
+// w^T[i][j] = max(-S[i][j], 0).  With int32 counts the learned path keeps
+// only S, and its two directions read rows of the same matrix.
+//
 // One persistent cooperative launch runs all sweeps of both directions (the
 // column-block and frontier-share layout of sweep.h), with one grid barrier
 // per sweep.
@@ -125,11 +131,22 @@ __global__ __launch_bounds__(256) void k_widest_init(WidestArgs<E, NP> a) {
     for (size_t i = blockIdx.x * 256 + threadIdx.x; i < grid::BAR_WORDS; i += gridDim.x * 256) bar[i] = 0u;
 }
 
-template <typename E, int NP>
+// SIGNED: every problem's matrix holds signed weights S (int32); problem 0
+// takes edge weights max(S, 0), problem 1 max(-S, 0) (|S| < 2^31).
+template <typename E, int NP, bool SIGNED>
 __global__ __launch_bounds__(256) void k_widest(WidestArgs<E, NP> a) {
+    static_assert(!SIGNED || sizeof(E) == 4, "signed weights are int32");
     const int32_t m = a.m;
     const bool ok = sweep::run<uint32_t, E, NP>(
-        a.run, m, [](uint32_t xi, uint32_t e) { return min(xi, e); }, [](int32_t) { return true; });
+        a.run, m,
+        [](int q, uint32_t xi, uint32_t e) {
+            if constexpr (SIGNED) {
+                const int32_t v = q ? -(int32_t)e : (int32_t)e;
+                e = (uint32_t)max(v, 0);
+            }
+            return min(xi, e);
+        },
+        [](int32_t) { return true; });
     if (!ok) {
         if (threadIdx.x == 0) set_device_error(a.run.err, SCHULZE_EDEVICE);
         return;
@@ -196,8 +213,9 @@ size_t widest_scratch_bytes(int32_t m, int np) {
 // Widest paths from src over the rows of A[q] (q < NP) into out[q], with
 // the sweep state in `base` (widest_scratch_bytes(m, NP) bytes of device
 // memory, all of it set by the init launch before it is read).  `timed`
-// brackets both launches with the context's timing events.
-template <typename E, int NP>
+// brackets both launches with the context's timing events.  SIGNED: A[q]
+// hold signed weights (see k_widest).
+template <typename E, int NP, bool SIGNED = false>
 int widest_in(schulze_ctx *ctx, hipStream_t s, const E *const (&A)[NP], const int64_t (&ld)[NP], int32_t m,
               int32_t src, E *const (&out)[NP], char *base, bool timed) {
     const size_t v = round_up(sizeof(uint32_t) * (size_t)m, 256);
@@ -222,7 +240,8 @@ int widest_in(schulze_ctx *ctx, hipStream_t s, const E *const (&A)[NP], const in
     a.m = m;
     a.s = src;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_widest<E, NP>, 256, 0) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_widest<E, NP, SIGNED>, 256, 0) != hipSuccess ||
+        per_cu < 1)
         return SCHULZE_EDEVICE;
     const int64_t G = sweep::grid_size(m, NP, (int64_t)ctx->num_cus * std::min(per_cu, 2));
     int tok = -1;
@@ -231,7 +250,8 @@ int widest_in(schulze_ctx *ctx, hipStream_t s, const E *const (&A)[NP], const in
     hipError_t e = hipGetLastError();
     void *args[] = {&a};
     if (e == hipSuccess)
-        e = hipLaunchCooperativeKernel((const void *)k_widest<E, NP>, dim3((unsigned)G), dim3(256), args, 0, s);
+        e = hipLaunchCooperativeKernel((const void *)k_widest<E, NP, SIGNED>, dim3((unsigned)G), dim3(256), args, 0,
+                                       s);
     if (timed) timing_end(ctx, tok, s);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -251,8 +271,9 @@ int widest(schulze_ctx *ctx, hipStream_t s, const E *w, int64_t ldw, int32_t m, 
 }
 
 // Both widest-path directions (one launch) and the verdict, with the sweep
-// state in base (nullptr: the context's workspace).
-template <typename E>
+// state in base (nullptr: the context's workspace).  SIGNED: w = wt = the
+// signed weights.
+template <typename E, bool SIGNED = false>
 int verify_all(schulze_ctx *ctx, hipStream_t s, const E *w, int64_t ldw, const E *wt, int64_t ldwt, int32_t m,
                int32_t cand, const float *score, E *p_from, E *p_to, int32_t *verdict, int32_t *tied, char *base) {
     int rc;
@@ -260,13 +281,13 @@ int verify_all(schulze_ctx *ctx, hipStream_t s, const E *w, int64_t ldw, const E
     const int64_t ld[2] = {ldw, ldwt};
     E *const out[2] = {p_from, p_to};
     if (base) {
-        if ((rc = widest_in<E, 2>(ctx, s, A, ld, m, cand, out, base, false)) != SCHULZE_OK) return rc;
+        if ((rc = widest_in<E, 2, SIGNED>(ctx, s, A, ld, m, cand, out, base, false)) != SCHULZE_OK) return rc;
         k_verdict<E><<<dim3(1), dim3(256), 0, s>>>(p_from, p_to, m, cand, score, verdict, tied);
         return launch_status();
     }
     if ((rc = ws_reserve(ctx, WS_VERIFY, widest_scratch_bytes(m, 2))) != SCHULZE_OK) return rc;
-    if ((rc = widest_in<E, 2>(ctx, s, A, ld, m, cand, out, static_cast<char *>(ctx->ws[WS_VERIFY]), true)) !=
-        SCHULZE_OK)
+    if ((rc = widest_in<E, 2, SIGNED>(ctx, s, A, ld, m, cand, out, static_cast<char *>(ctx->ws[WS_VERIFY]),
+                                      true)) != SCHULZE_OK)
         return rc;
     SCHULZE_LAUNCH(ctx, K_VERDICT, s,
                    k_verdict<E><<<dim3(1), dim3(256), 0, s>>>(p_from, p_to, m, cand, score, verdict, tied));
@@ -356,4 +377,11 @@ extern "C" int schulze_verify_noalloc(schulze_ctx *ctx, void *stream, const void
     using E = int32_t;
     return verify_all<E>(ctx, s, static_cast<const E *>(w), ldw, static_cast<const E *>(wt), ldwt, m, cand, score,
                          static_cast<E *>(p_from), static_cast<E *>(p_to), verdict, tied, base);
+}
+
+// Internal: schulze_verify over signed weights sw = w - w^T (int32, pitch
+// ld; device pointers, m <= 65535, cand < m, checked by the caller).
+int verify_signed(schulze_ctx *ctx, hipStream_t s, const int32_t *sw, int64_t ld, int32_t m, int32_t cand,
+                  const float *score, int32_t *p_from, int32_t *p_to, int32_t *verdict, int32_t *tied) {
+    return verify_all<int32_t, true>(ctx, s, sw, ld, sw, ld, m, cand, score, p_from, p_to, verdict, tied, nullptr);
 }

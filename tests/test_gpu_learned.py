@@ -104,3 +104,31 @@ def test_learned_winners_with_plain_proposers(ctx, proposer):
         ctx.set_proposer("network")
     import paper_2505_12976_amd as sz
     assert ctx._lib.schulze_set_proposer(ctx._h, 7) == sz.EINVAL
+
+
+@pytest.mark.parametrize("mode", ["winning_votes", "margin"])
+def test_learned_winners_by_count_width_and_mode(ctx, mode):
+    """int32 counts take the signed-weight form of the exact check (one
+    matrix S = w - w^T, both directions reading its rows), 16-bit counts the
+    w and w^T form: both give the oracle's winners under either weight rule,
+    and, as the proposals and every verdict agree, the same search (same
+    proposal, climbs and number of checks)."""
+    import torch
+    from paper_2505_12976_amd.proposer import init_params
+    om = oracle.MARGIN if mode == "margin" else oracle.WINNING_VOTES
+    for which, p in (("random", init_params(7)), ("negated", -init_params(8))):
+        pt = torch.from_numpy(np.asarray(p, dtype=np.float32)).cuda()
+        for name, b, m in elections():
+            log(f"[case] learned {mode} {which} {name} m={m}")
+            want = oracle.schulze(b, m, om)["is_winner"]
+            for max_climb, max_tied in ((8, 64), (0, 64), (8, 0)):
+                stats = {}
+                for dtype in ("u16", "i32"):
+                    d = ctx.pairwise(torch.from_numpy(b).cuda(), m, dtype=dtype)
+                    w, nw, st = ctx.winners_learned(d, float(b.shape[0]), pt, mode=mode, max_climb=max_climb,
+                                                    max_tied=max_tied)
+                    got = w.cpu().numpy().astype(bool)
+                    assert np.array_equal(got, want), (mode, which, name, dtype, max_climb, max_tied, st)
+                    assert int(nw.cpu()[0]) == int(want.sum()) == st["n_winners"]
+                    stats[dtype] = st
+                assert stats["u16"] == stats["i32"], (mode, which, name, max_climb, max_tied, stats)
