@@ -196,6 +196,26 @@ int schulze_verify(schulze_ctx *ctx, void *stream, const void *w, int64_t ldw, c
                    void *p_from, void *p_to, int32_t *verdict, int32_t *tied);
 
 /*
+ * schulze_verify straight from the pairwise counts (Section 3's membership
+ * argument, as above): the same outputs and verdict, but the weights are
+ * formed from d inside the widest-path sweeps (w[i][j] from d[i][j] and
+ * d[j][i], Section 2.1), so no weight matrix is written first.  A sweep with
+ * few frontier vertices reads their rows and columns of d; one with more
+ * than about m/16 relaxes every edge in one pass over d.
+ *
+ * d, ldd     m x m pairwise counts (dtype), device memory.
+ * mode       schulze_weight_mode.
+ * p_from, p_to  m elements of dtype each; verdict, tied as for schulze_verify.
+ * Asynchronous on the stream; uses the context's workspace.  Returns
+ * SCHULZE_EINVAL for bad arguments, SCHULZE_EUNSUPPORTED for m > 65535,
+ * SCHULZE_EDEVICE if the device refuses the cooperative launch (a sweep
+ * that gives up on its bounded wait sets the device error word instead).
+ */
+int schulze_verify_counts(schulze_ctx *ctx, void *stream, const void *d, int64_t ldd, int32_t m, int dtype,
+                          int mode, int32_t cand, const float *score, void *p_from, void *p_to, int32_t *verdict,
+                          int32_t *tied);
+
+/*
  * schulze_verify for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * same arguments, outputs and errors as schulze_verify, but the sweep state
@@ -325,10 +345,13 @@ typedef struct {
  * n_voters   feature scale (number of voters).
  * is_winner  m device bytes.   n_winners: NULL or one device int32.
  * stats      NULL or host struct.
- * Workspace: int32 counts: m^2 int32 signed weights w - w^T (both weight
- * rules give a pair an edge in at most one direction, so w = max(S, 0) and
- * w^T = max(-S, 0)); 16-bit counts: 2 m^2 elements (w and w^T); plus O(m);
- * m^2 elements more if the fallback runs.
+ * The first check is schulze_verify_counts (it reads d, nothing written);
+ * later checks of the same call (climbs, tied candidates) write the weights
+ * once and sweep over their rows.
+ * Workspace: O(m); once a second check runs, int32 counts add m^2 int32
+ * signed weights S = w - w^T (both weight rules give a pair an edge in at
+ * most one direction, so w = max(S, 0) and w^T = max(-S, 0)) and 16-bit
+ * counts 2 m^2 elements (w and w^T); m^2 elements more if the fallback runs.
  */
 int schulze_winners_learned(schulze_ctx *ctx, void *stream, const void *d, int64_t ldd, int32_t m,
                             int dtype, int mode, float n_voters, const float *params,

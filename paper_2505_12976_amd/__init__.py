@@ -36,6 +36,7 @@ EXPORTS = (
     "schulze_batch_plan", "schulze_batch_destroy", "schulze_batch_run", "schulze_batch_set_closure",
     "schulze_batch_get_closure", "schulze_batch_autotune", "schulze_winners_propagate",
     "schulze_topk_propagate", "schulze_valu_probe", "schulze_closure_value_bits", "schulze_set_proposer", "schulze_verify_noalloc",
+    "schulze_verify_counts",
 )
 
 
@@ -140,6 +141,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.schulze_widest_from.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_i32, vp]
     lib.schulze_verify.argtypes = [vp, vp, vp, c_i64, vp, c_i64, c_i32, c_int, c_i32, vp, vp, vp, vp, vp]
     lib.schulze_verify_noalloc.argtypes = [vp, vp, vp, c_i64, vp, c_i64, c_i32, c_int, c_i32, vp, vp, vp, vp, vp]
+    lib.schulze_verify_counts.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_int, c_i32, vp, vp, vp, vp, vp]
     lib.schulze_features.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_int, ctypes.c_float, vp]
     lib.schulze_mlp_param_count.argtypes = []
     lib.schulze_winners_learned.argtypes = [vp, vp, vp, c_i64, c_i32, c_int, c_int, ctypes.c_float, vp, c_i32, c_i32,
@@ -364,6 +366,28 @@ class Context:
                 self._dev(p_from, "p_from"), self._dev(p_to, "p_to"),
                 self._dev(verdict, "verdict"), None if tied is None else self._dev(tied, "tied"))
         _check(rc, "schulze_verify_noalloc" if noalloc else "schulze_verify")
+        return verdict, p_from, p_to, tied
+
+    def verify_counts(self, d, cand: int, mode="winning_votes", score=None, want_tied=False):
+        """(verdict int32[4], p_from, p_to, tied or None) of cand straight
+        from the counts d; see schulze_verify_counts."""
+        import torch
+        m = d.shape[0]
+        p_from = torch.empty(m, dtype=d.dtype, device=self._torch_device)
+        p_to = torch.empty(m, dtype=d.dtype, device=self._torch_device)
+        verdict = torch.empty(4, dtype=torch.int32, device=self._torch_device)
+        tied = torch.empty(m, dtype=torch.int32, device=self._torch_device) if want_tied else None
+        sp = None
+        if score is not None:
+            if score.dtype != torch.float32 or score.shape != (m,):
+                raise ValueError("score must be a float32 tensor of shape (m,)")
+            sp = self._dev(score, "score")
+        rc = self._lib.schulze_verify_counts(self._h, self._stream(), self._dev(d, "d"), d.stride(0), m,
+                                             _dtype_code(d.dtype), _mode_code(mode), cand, sp,
+                                             self._dev(p_from, "p_from"), self._dev(p_to, "p_to"),
+                                             self._dev(verdict, "verdict"),
+                                             None if tied is None else self._dev(tied, "tied"))
+        _check(rc, "schulze_verify_counts")
         return verdict, p_from, p_to, tied
 
     def features(self, d, n_voters: float, mode="winning_votes", out=None):

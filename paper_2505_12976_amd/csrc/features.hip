@@ -23,10 +23,8 @@
 namespace {
 
 constexpr int NF = 16;
-// Lanes that share a row of a 64 x 64 tile: eight, so that each store of a
-// wavefront writes whole 128-byte lines (eight rows of eight 16-byte
-// pieces; four lanes per row wrote half lines, and the pass ran 13% slower);
-// a thread takes two rows, r and r + 32.
+// Lanes that share a row of a 64 x 64 tile: eight; a thread takes two rows,
+// r and r + 32.
 constexpr int ROW_LANES = 8;
 constexpr int ROW_HALF = tio::T / 2;
 
@@ -135,30 +133,19 @@ __device__ __forceinline__ void acc_add(Acc<E> &s, int32_t xy, int32_t yx, int32
 // One lane's share of a tile: row r of the rows starting at row0 over the
 // columns starting at col0, with A[r][c] = d[row0 + r][col0 + c] and
 // B[c][r] = d[col0 + c][row0 + r].  The lane takes columns
-// c = 8V k + V g + u (V elements per 16-byte vector), so that the eight
-// lanes of a row write a 128-byte line of w and of wt per store:
-// w[x][y] = wo and wt[x][y] = w[y][x] = wi come out of the same two LDS
-// reads as the statistics (SIGNED: w[x][y] = wo - wi, the signed weight,
-// and no wt).  Interior tiles of aligned matrices, off the diagonal.
-template <typename E, bool MARGIN, bool SIGNED>
+// c = 8V k + V g + u (V elements per 16-byte vector).  Interior tiles of
+// aligned matrices, off the diagonal.
+template <typename E, bool MARGIN>
 __device__ __forceinline__ void tile_rows(const E (*A)[tio::PITCH], const E (*B)[tio::PITCH], int r, int g,
-                                          int32_t row0, int32_t col0, Acc<E> &s, E *__restrict__ w, int64_t ldw,
-                                          E *__restrict__ wt, int64_t ldwt) {
+                                          Acc<E> &s) {
     constexpr int V = 16 / (int)sizeof(E), KV = tio::T / (ROW_LANES * V);
-    const int64_t x = row0 + r;
     for (int k = 0; k < KV; ++k) {
-        E ow[V], ot[V];
         for (int u = 0; u < V; ++u) {
             const int c = k * ROW_LANES * V + g * V + u;
             int32_t wo, wi;
             acc_add<E, MARGIN>(s, (int32_t)A[r][c], (int32_t)B[c][r], wo, wi);
-            ow[u] = (E)(SIGNED ? wo - wi : wo);
-            ot[u] = (E)wi;
         }
         s.pin();
-        const int32_t c0 = col0 + k * ROW_LANES * V + g * V;
-        if (w) *reinterpret_cast<uint4 *>(w + x * ldw + c0) = tio::pack<E>(ow);
-        if (!SIGNED && wt) *reinterpret_cast<uint4 *>(wt + x * ldwt + c0) = tio::pack<E>(ot);
     }
 }
 
@@ -166,21 +153,18 @@ __device__ __forceinline__ void tile_rows(const E (*A)[tio::PITCH], const E (*B)
 // matrices: bounds and the diagonal checked, one element at a time (a
 // plain loop: these tiles are few, and unrolling them would cost the
 // interior loop registers).
-template <typename E, bool MARGIN, bool SIGNED>
+template <typename E, bool MARGIN>
 __device__ __forceinline__ void tile_rows_edge(const E (*A)[tio::PITCH], const E (*B)[tio::PITCH], int r, int g,
-                                            int32_t row0, int32_t col0, int32_t m, Acc<E> &s, E *__restrict__ w,
-                                            int64_t ldw, E *__restrict__ wt, int64_t ldwt) {
+                                               int32_t row0, int32_t col0, int32_t m, Acc<E> &s) {
     constexpr int V = 16 / (int)sizeof(E);
     const int32_t x = row0 + r;
     if (x >= m) return;
 #pragma unroll 1
     for (int q = 0; q < tio::T / ROW_LANES; ++q) {
         const int c = (q / V) * ROW_LANES * V + g * V + q % V, y = col0 + c;
-        if (y >= m) continue;
-        int32_t wo = 0, wi = 0;
-        if (y != x) acc_add<E, MARGIN>(s, (int32_t)A[r][c], (int32_t)B[c][r], wo, wi);
-        if (w) w[(int64_t)x * ldw + y] = (E)(SIGNED ? wo - wi : wo);
-        if (!SIGNED && wt) wt[(int64_t)x * ldwt + y] = (E)wi;
+        if (y >= m || y == x) continue;
+        int32_t wo, wi;
+        acc_add<E, MARGIN>(s, (int32_t)A[r][c], (int32_t)B[c][r], wo, wi);
     }
 }
 
@@ -195,14 +179,9 @@ __device__ __forceinline__ void tile_rows_edge(const E (*A)[tio::PITCH], const E
 // columns of super-block s: rows of I over J and rows of J over I, each
 // (row, slot) written by exactly one workgroup (on the diagonal
 // super-block, row tile i adds what the tiles before it gave it as
-// mirrored rows).  With w / wt given, the same pass writes the edge weights
-// of both tiles to w and to its transpose wt (SIGNED: the signed weights
-// w - w^T to w alone).  VD: d is read in 16-byte vectors (see tio::fetch);
-// bits 1, 2 of vec: w, wt are vector-aligned (or absent).
-template <typename E, bool MARGIN, int SBV, bool VD, bool SIGNED>
-__global__ __launch_bounds__(256) void k_feature_rows(const E *__restrict__ d, int64_t ldd, int32_t m, RawStats part,
-                                                      int vec, E *__restrict__ w, int64_t ldw, E *__restrict__ wt,
-                                                      int64_t ldwt) {
+// mirrored rows).  VD: d is read in 16-byte vectors (see tio::fetch).
+template <typename E, bool MARGIN, int SBV, bool VD>
+__global__ __launch_bounds__(256) void k_feature_rows(const E *__restrict__ d, int64_t ldd, int32_t m, RawStats part) {
     __shared__ E a[tio::T][tio::PITCH];  // a[r][c] = d[X0 + r][Y0 + c]
     __shared__ E b[tio::T][tio::PITCH];  // b[r][c] = d[Y0 + r][X0 + c]
     __shared__ Acc<E> mir[SBV][tio::T];
@@ -212,7 +191,6 @@ __global__ __launch_bounds__(256) void k_feature_rows(const E *__restrict__ d, i
     const int lane = threadIdx.x & 63;
     // rows r and r + ROW_HALF, ROW_LANES lanes per row
     const int r = (threadIdx.x >> 6) * (64 / ROW_LANES) + lane / ROW_LANES, g = lane % ROW_LANES;
-    const bool vall = vec == 7;
     if (g == 0)
         for (int q = 0; q < SBV; ++q) {  // read and written by this lane only
             mir[q][r].init();
@@ -255,18 +233,18 @@ __global__ __launch_bounds__(256) void k_feature_rows(const E *__restrict__ d, i
         __syncthreads();
         if (X == Y) {
             for (int h = 0; h < 2; ++h)
-                tile_rows_edge<E, MARGIN, SIGNED>(a, a, r + h * ROW_HALF, g, X0, Y0, m, rs[h], w, ldw, wt, ldwt);
+                tile_rows_edge<E, MARGIN>(a, a, r + h * ROW_HALF, g, X0, Y0, m, rs[h]);
         } else {
             for (int h = 0; h < 2; ++h) {
                 const int rr = r + h * ROW_HALF;
                 Acc<E> ms;
                 ms.init();
-                if (vall && X0 + 64 <= m && Y0 + 64 <= m) {
-                    tile_rows<E, MARGIN, SIGNED>(a, b, rr, g, X0, Y0, rs[h], w, ldw, wt, ldwt);
-                    tile_rows<E, MARGIN, SIGNED>(b, a, rr, g, Y0, X0, ms, w, ldw, wt, ldwt);
+                if (X0 + 64 <= m && Y0 + 64 <= m) {
+                    tile_rows<E, MARGIN>(a, b, rr, g, rs[h]);
+                    tile_rows<E, MARGIN>(b, a, rr, g, ms);
                 } else {
-                    tile_rows_edge<E, MARGIN, SIGNED>(a, b, rr, g, X0, Y0, m, rs[h], w, ldw, wt, ldwt);
-                    tile_rows_edge<E, MARGIN, SIGNED>(b, a, rr, g, Y0, X0, m, ms, w, ldw, wt, ldwt);
+                    tile_rows_edge<E, MARGIN>(a, b, rr, g, X0, Y0, m, rs[h]);
+                    tile_rows_edge<E, MARGIN>(b, a, rr, g, Y0, X0, m, ms);
                 }
                 ms.row_reduce();
                 if (g == 0) mir[j][rr].merge(ms);
@@ -418,18 +396,16 @@ RawStats carve(char *p, size_t n, size_t *bytes) {
     return st;
 }
 
-template <typename E, int SBV, bool VD, bool SIGNED>
+template <typename E, int SBV, bool VD>
 int launch_rows(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32_t m, int mode, RawStats part,
-                int vec, E *w, int64_t ldw, E *wt, int64_t ldwt, int32_t S) {
+                int32_t S) {
     const dim3 grid((unsigned)S, (unsigned)S);
     if (mode == SCHULZE_MARGIN)
         SCHULZE_LAUNCH(ctx, K_FEATURE_ROWS, s,
-                       k_feature_rows<E, true, SBV, VD, SIGNED>
-                       <<<grid, dim3(256), 0, s>>>(d, ldd, m, part, vec, w, ldw, wt, ldwt));
+                       k_feature_rows<E, true, SBV, VD><<<grid, dim3(256), 0, s>>>(d, ldd, m, part));
     else
         SCHULZE_LAUNCH(ctx, K_FEATURE_ROWS, s,
-                       k_feature_rows<E, false, SBV, VD, SIGNED>
-                       <<<grid, dim3(256), 0, s>>>(d, ldd, m, part, vec, w, ldw, wt, ldwt));
+                       k_feature_rows<E, false, SBV, VD><<<grid, dim3(256), 0, s>>>(d, ldd, m, part));
     return SCHULZE_OK;
 }
 
@@ -440,11 +416,9 @@ constexpr int feature_sb() {
     return 4;
 }
 
-// SIGNED (int32 only): w receives the signed weights, wt must be null.
-template <typename E, bool SIGNED = false>
+template <typename E>
 int run_features(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32_t m, int mode, float n_voters,
-                 float *feat, E *w = nullptr, int64_t ldw = 0, E *wt = nullptr, int64_t ldwt = 0) {
-    static_assert(!SIGNED || sizeof(E) == 4, "signed weights are int32");
+                 float *feat) {
     constexpr int SBV = feature_sb<E>();
     // S super-blocks per side: a partial slot per super-block column
     const int32_t S = (int32_t)ceil_div(ceil_div(m, 64), SBV);
@@ -459,9 +433,8 @@ int run_features(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32
     uint32_t *mx = reinterpret_cast<uint32_t *>(p + fin_bytes + part_bytes);
     if ((rc = fill_u32(ctx, s, mx, 4, 0u)) != SCHULZE_OK) return rc;
     const bool vd = tio::vec_ok<E>(d, ldd) && m % (16 / (int)sizeof(E)) == 0;
-    const int vec = (vd ? 1 : 0) | (!w || tio::vec_ok<E>(w, ldw) ? 2 : 0) | (!wt || tio::vec_ok<E>(wt, ldwt) ? 4 : 0);
-    rc = vd ? launch_rows<E, SBV, true, SIGNED>(ctx, s, d, ldd, m, mode, part, vec, w, ldw, wt, ldwt, S)
-            : launch_rows<E, SBV, false, SIGNED>(ctx, s, d, ldd, m, mode, part, vec, w, ldw, wt, ldwt, S);
+    rc = vd ? launch_rows<E, SBV, true>(ctx, s, d, ldd, m, mode, part, S)
+            : launch_rows<E, SBV, false>(ctx, s, d, ldd, m, mode, part, S);
     if (rc != SCHULZE_OK) return rc;
     SCHULZE_LAUNCH(ctx, K_FEATURES, s,
                    k_feature_reduce<<<dim3((unsigned)ceil_div(m, 64)), dim3(256), 0, s>>>(m, S, part, st));
@@ -485,19 +458,4 @@ extern "C" int schulze_features(schulze_ctx *ctx, void *stream, const void *d, i
     if (dtype == SCHULZE_U16)
         return run_features(ctx, s, static_cast<const uint16_t *>(d), ldd, m, mode, n_voters, feat);
     return run_features(ctx, s, static_cast<const int32_t *>(d), ldd, m, mode, n_voters, feat);
-}
-
-// Internal: features and the weights in one pass over d (the learned path
-// needs both): w and w^T for 16-bit counts; for int32 counts the signed
-// weights w - w^T alone (one matrix instead of two: half the writes, and
-// both directions of the exact check read its rows).
-int weights_and_features(schulze_ctx *ctx, hipStream_t s, const void *d, int64_t ldd, int32_t m, int dtype, int mode,
-                         float n_voters, float *feat, void *w, int64_t ldw, void *wt, int64_t ldwt) {
-    if (dtype == SCHULZE_U16)
-        return run_features(ctx, s, static_cast<const uint16_t *>(d), ldd, m, mode, n_voters, feat,
-                            static_cast<uint16_t *>(w), ldw, static_cast<uint16_t *>(wt), ldwt);
-    (void)wt;
-    (void)ldwt;
-    return run_features<int32_t, true>(ctx, s, static_cast<const int32_t *>(d), ldd, m, mode, n_voters, feat,
-                                       static_cast<int32_t *>(w), ldw, nullptr, 0);
 }

@@ -26,7 +26,8 @@ enum WsSlot {
     WS_FEATURES,         // per-candidate raw statistics
     WS_MLP,              // BF16 copies of the network weights
     WS_MLP_PARTIAL,      // per-workgroup gradient partials
-    WS_LEARNED,          // learned path: weights, transposed weights, features, scores
+    WS_LEARNED,          // learned path: features, scores, check outputs
+    WS_LEARNED_W,        // learned path: weights of the checks after the first
     WS_LEARNED_P,        // learned path: closure for the fallback
     WS_PROPAGATE,        // label propagation: weights, keys, frontiers, statuses
     WS_RANKED,           // ranked closure: value bitmap, rank tables, uint16 matrix
@@ -139,13 +140,11 @@ int launch_status();
 // Zero `words` 32-bit words with a fill kernel (graph-capture friendly).
 int fill_u32(schulze_ctx *ctx, hipStream_t s, uint32_t *ptr, size_t words, uint32_t value);
 
-// Per-candidate features (as schulze_features) and the weights in one pass
-// over d; arguments already checked.  16-bit counts: w and w^T (as
-// schulze_weights) into w and wt.  int32 counts: the signed weights
-// S = w - w^T into w (wt unused): w[i][j] = max(S[i][j], 0),
-// w[j][i] = max(-S[i][j], 0).
-int weights_and_features(schulze_ctx *ctx, hipStream_t s, const void *d, int64_t ldd, int32_t m, int dtype, int mode,
-                         float n_voters, float *feat, void *w, int64_t ldw, void *wt, int64_t ldwt);
+// Signed weights S = w - w^T of d (int32; pitch lds): both weight rules
+// give a pair an edge in at most one direction, so w[i][j] = max(S[i][j], 0)
+// and w[j][i] = max(-S[i][j], 0).  Arguments already checked.
+int signed_weights(schulze_ctx *ctx, hipStream_t s, const int32_t *d, int64_t ldd, int32_t m, int mode, int32_t *S,
+                   int64_t lds);
 
 // schulze_verify over signed weights sw = w - w^T (int32, pitch ld);
 // arguments already checked.

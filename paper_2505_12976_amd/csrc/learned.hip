@@ -68,25 +68,20 @@ extern "C" int schulze_winners_learned(schulze_ctx *ctx, void *stream, const voi
     const size_t mat = round_up(es * (size_t)m * m, 256);
     const size_t vec_e = round_up(es * (size_t)m, 256), vec_f = round_up(4 * (size_t)m, 256);
     const size_t feat_b = round_up(4 * 16 * (size_t)m, 256);
-    // int32 counts: one matrix of signed weights w - w^T; 16-bit counts: w and w^T
-    const bool sgn = dtype == SCHULZE_I32;
-    const size_t mats = (sgn ? 1 : 2) * mat;
-    int rc = ws_reserve(ctx, WS_LEARNED, mats + feat_b + vec_f + 2 * vec_e + vec_f + 256);
+    int rc = ws_reserve(ctx, WS_LEARNED, feat_b + vec_f + 2 * vec_e + vec_f + 256);
     if (rc != SCHULZE_OK) return rc;
     char *b = static_cast<char *>(ctx->ws[WS_LEARNED]);
-    void *w = b, *wt = sgn ? nullptr : b + mat;
-    float *feat = reinterpret_cast<float *>(b + mats);
-    float *score = reinterpret_cast<float *>(b + mats + feat_b);
-    void *p_from = b + mats + feat_b + vec_f;
-    void *p_to = b + mats + feat_b + vec_f + vec_e;
-    int32_t *tied = reinterpret_cast<int32_t *>(b + mats + feat_b + vec_f + 2 * vec_e);
-    int32_t *small = reinterpret_cast<int32_t *>(b + mats + feat_b + 2 * vec_f + 2 * vec_e);  // verdict + pick
+    float *feat = reinterpret_cast<float *>(b);
+    float *score = reinterpret_cast<float *>(b + feat_b);
+    void *p_from = b + feat_b + vec_f;
+    void *p_to = b + feat_b + vec_f + vec_e;
+    int32_t *tied = reinterpret_cast<int32_t *>(b + feat_b + vec_f + 2 * vec_e);
+    int32_t *small = reinterpret_cast<int32_t *>(b + feat_b + 2 * vec_f + 2 * vec_e);  // verdict + pick
 
     schulze_learned_stats st{};
     st.proposal = -1;
-    // weights (signed, or w and w^T) and features in one pass over d
-    if ((rc = weights_and_features(ctx, s, d, ldd, m, dtype, mode, n_voters, feat, w, m, wt, m)) != SCHULZE_OK)
-        return rc;
+    // features in one pass over d (nothing else written)
+    if ((rc = schulze_features(ctx, stream, d, ldd, m, dtype, mode, n_voters, feat)) != SCHULZE_OK) return rc;
     // scores: the network, or one feature column (Borda: column 2, the vertex
     // order of Section 4; Copeland: column 0); the filter of Section 4 applies
     // to the network and to filtered Borda
@@ -112,15 +107,41 @@ extern "C" int schulze_winners_learned(schulze_ctx *ctx, void *stream, const voi
     }
     st.proposal = cand;
 
-    // One exact check.  The verdict is only used when the device error word
-    // is clear: a widest-path launch that gave up on its bounded grid
-    // barrier leaves its rows unwritten and sets the word, so the search
-    // stops with SCHULZE_EDEVICE (the word stays set for
-    // schulze_get_device_error) instead of deciding on stale rows.
+    // One exact check.  The first reads d itself (schulze_verify_counts:
+    // weights formed where they are used, nothing written first), which
+    // suits the common case of a proposal that wins outright.  A search that
+    // goes on (a climb, tied candidates) writes the weights once, then
+    // sweeps over their rows: int32 counts as the signed weights w - w^T
+    // (both directions read rows of one matrix), 16-bit counts as w and w^T.
+    // The verdict is only used when the device error word is clear: a
+    // widest-path launch that gave up on its bounded grid barrier leaves its
+    // rows unwritten and sets the word, so the search stops with
+    // SCHULZE_EDEVICE (the word stays set for schulze_get_device_error)
+    // instead of deciding on stale rows.
+    void *w = nullptr, *wt = nullptr;
+    const bool sgn = dtype == SCHULZE_I32;
     auto verify = [&](int32_t c, int32_t (&v)[4]) -> int {
-        int r = sgn ? verify_signed(ctx, s, static_cast<const int32_t *>(w), m, m, c, score,
+        int r;
+        if (st.verify_calls == 0) {
+            r = schulze_verify_counts(ctx, stream, d, ldd, m, dtype, mode, c, score, p_from, p_to, small, tied);
+        } else {
+            if (!w) {
+                if ((r = ws_reserve(ctx, WS_LEARNED_W, (sgn ? 1 : 2) * mat)) != SCHULZE_OK) return r;
+                char *wb = static_cast<char *>(ctx->ws[WS_LEARNED_W]);
+                if (sgn) {
+                    r = signed_weights(ctx, s, static_cast<const int32_t *>(d), ldd, m, mode,
+                                       reinterpret_cast<int32_t *>(wb), m);
+                } else {
+                    r = schulze_weights(ctx, stream, d, ldd, m, dtype, mode, wb, m, wb + mat, m);
+                }
+                if (r != SCHULZE_OK) return r;
+                w = wb;
+                wt = sgn ? nullptr : wb + mat;
+            }
+            r = sgn ? verify_signed(ctx, s, static_cast<const int32_t *>(w), m, m, c, score,
                                     static_cast<int32_t *>(p_from), static_cast<int32_t *>(p_to), small, tied)
                     : schulze_verify(ctx, stream, w, m, wt, m, m, dtype, c, score, p_from, p_to, small, tied);
+        }
         if (r != SCHULZE_OK) return r;
         ++st.verify_calls;
         int32_t err = 0;
