@@ -184,7 +184,9 @@ __global__ __launch_bounds__(256) void k_widest(WidestArgs<E, NP> a) {
 // width of some path).  A gathered column costs about a line per element,
 // so the dense pass is the cheaper one beyond about m / 16 frontier rows.
 constexpr int CHECK_DENSE_RATIO = 16;
-constexpr int CHECK_ROW_LANES = 8;  // lanes per tile row; a thread takes rows r and r + 32
+constexpr int CHECK_ROW_LANES = 4;  // lanes per tile row (0.88 ms at m = 32768; eight: 0.96 ms)
+constexpr int CHECK_RPT = CHECK_ROW_LANES * tio::T / 256;  // rows per thread: r + h * CHECK_ROW_STEP
+constexpr int CHECK_ROW_STEP = tio::T / CHECK_RPT;
 
 template <bool MARGIN>
 __device__ __forceinline__ uint32_t edge_weight(int32_t a, int32_t b) {  // d[i][j] = a, d[j][i] = b
@@ -241,9 +243,11 @@ __device__ __forceinline__ void check_row(const E (*A)[tio::PITCH], const E (*B)
 
 // Both directions from (to) a.s over d (both problems' A = d), to the
 // fixpoint, in one cooperative launch after k_widest_init.  VD: d is
-// vector-aligned and m a multiple of the vector length.
+// vector-aligned and m a multiple of the vector length.  Three workgroups
+// per CU (registers capped accordingly; a few spill in the gather branch):
+// 0.95 ms instead of 1.11 ms with two at m = 32768.
 template <typename E, bool MARGIN, bool VD>
-__global__ __launch_bounds__(256) void k_check(WidestArgs<E, 2> a) {
+__global__ __launch_bounds__(256, 3) void k_check(WidestArgs<E, 2> a) {
     using sweep::CB;
     using sweep::CPL;
     __shared__ E ta[tio::T][tio::PITCH];      // ta[r][c] = d[X0 + r][Y0 + c]
@@ -257,7 +261,7 @@ __global__ __launch_bounds__(256) void k_check(WidestArgs<E, 2> a) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t *const x0 = R.p[0].x, *const x1 = R.p[1].x;
     int32_t *const st0 = R.p[0].stamp, *const st1 = R.p[1].stamp;
-    // dense pass: tile pairs, rows r and r + 32, eight lanes per row
+    // dense pass: tile pairs, CHECK_RPT rows per thread
     const int32_t nb = (m + tio::T - 1) / tio::T;
     const int64_t npairs = (int64_t)nb * (nb + 1) / 2;
     const int r = wave * (64 / CHECK_ROW_LANES) + lane / CHECK_ROW_LANES, gl = lane % CHECK_ROW_LANES;
@@ -285,13 +289,24 @@ __global__ __launch_bounds__(256) void k_check(WidestArgs<E, 2> a) {
         int32_t *const fn0 = R.p[0].front[(t + 1) & 1], *const fn1 = R.p[1].front[(t + 1) & 1];
         if ((int64_t)(n0 + n1) * CHECK_DENSE_RATIO > m) {
             // ---- dense pass over the tile pairs
+            // A pair's two tiles and the 256 values of its rows and columns
+            // (one per thread: side, direction, index) are loaded into
+            // registers while the previous pair is worked on; the values may
+            // be a pair old, which only delays a raise to the next sweep.
             tio::Regs<E> ga, gb;
+            uint32_t xr = 0;
+            const int xside = (threadIdx.x >> 7) & 1, xq = (threadIdx.x >> 6) & 1;
+            auto fetch = [&](int32_t Xf, int32_t Yf) {
+                tio::fetch<E, VD>(ga, d, ld, Xf * tio::T, Yf * tio::T, m, m);
+                if (Xf != Yf) tio::fetch<E, VD>(gb, d, ld, Yf * tio::T, Xf * tio::T, m, m);
+                const int32_t v = (xside ? Yf : Xf) * tio::T + lane;
+                xr = v < m ? __hip_atomic_load((xq ? x1 : x0) + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+            };
             int64_t p = g;
             int32_t X = 0, Y = 0;
             if (p < npairs) {
                 tile_pair(p, nb, X, Y);
-                tio::fetch<E, VD>(ga, d, ld, X * tio::T, Y * tio::T, m, m);
-                if (X != Y) tio::fetch<E, VD>(gb, d, ld, Y * tio::T, X * tio::T, m, m);
+                fetch(X, Y);
             }
             while (p < npairs) {
                 const int32_t X0 = X * tio::T, Y0 = Y * tio::T;
@@ -299,18 +314,12 @@ __global__ __launch_bounds__(256) void k_check(WidestArgs<E, 2> a) {
                 __syncthreads();  // the previous pair's LDS reads are done
                 tio::put<E>(ta, ga);
                 if (!diag) tio::put<E>(tb, gb);
-                {
-                    const int side = (threadIdx.x >> 7) & 1, q = (threadIdx.x >> 6) & 1, c = lane;
-                    const int32_t v = (side ? Y0 : X0) + c;
-                    const uint32_t *xq = q ? x1 : x0;
-                    xs[side][q][c] = v < m ? __hip_atomic_load(xq + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
-                }
+                xs[xside][xq][lane] = xr;
                 const int64_t pn = p + G;
                 int32_t Xn = 0, Yn = 0;
                 if (pn < npairs) {  // in flight during the work below
                     tile_pair(pn, nb, Xn, Yn);
-                    tio::fetch<E, VD>(ga, d, ld, Xn * tio::T, Yn * tio::T, m, m);
-                    if (Xn != Yn) tio::fetch<E, VD>(gb, d, ld, Yn * tio::T, Xn * tio::T, m, m);
+                    fetch(Xn, Yn);
                 }
                 __syncthreads();
                 for (int side = 0; side < (diag ? 1 : 2); ++side) {
@@ -319,8 +328,8 @@ __global__ __launch_bounds__(256) void k_check(WidestArgs<E, 2> a) {
                     const E(*B)[tio::PITCH] = diag ? ta : (side ? ta : tb);
                     const int cs = diag ? 0 : 1 - side;
                     const int32_t row0 = side ? Y0 : X0;
-                    for (int h = 0; h < 2; ++h) {
-                        const int rr = r + h * (tio::T / 2);
+                    for (int h = 0; h < CHECK_RPT; ++h) {
+                        const int rr = r + h * CHECK_ROW_STEP;
                         uint32_t v0 = 0, v1 = 0;
                         check_row<E, MARGIN>(A, B, xs[cs], rr, gl, v0, v1);
                         for (int off = 1; off < CHECK_ROW_LANES; off <<= 1) {
@@ -347,33 +356,23 @@ __global__ __launch_bounds__(256) void k_check(WidestArgs<E, 2> a) {
             uint32_t best[CPL] = {};
             if (gactive) {
                 const bool full = VD && valid >= CB;
-                const int32_t step = 4 * shares;
-                for (int32_t qi = share * 4 + wave; qi < nf; qi += 2 * step) {
-                    // two frontier vertices per wavefront in flight
-                    int32_t v[2];
-                    uint32_t row[2][CPL], col[2][CPL], xv[2];
-                    for (int u = 0; u < 2; ++u) {
-                        const int32_t k = qi + u * step;
-                        v[u] = k < nf ? F[k] : -1;
+                for (int32_t qi = share * 4 + wave; qi < nf; qi += 4 * shares) {
+                    const int32_t v = F[qi];
+                    uint32_t row[CPL], col[CPL];
+                    if (full)
+                        sweep::load_row<E, true>(d + (int64_t)v * ld + blk0, valid, lane, row);
+                    else
+                        sweep::load_row<E, false>(d + (int64_t)v * ld + blk0, valid, lane, row);
+                    for (int c = 0; c < CPL; ++c) {
+                        const int32_t k = blk0 + sweep::lane_col<E>(lane, c);
+                        col[c] = k < m ? (uint32_t)d[(int64_t)k * ld + v] : 0u;
                     }
-                    for (int u = 0; u < 2; ++u) {
-                        const int32_t vv = v[u] < 0 ? 0 : v[u];
-                        if (full)
-                            sweep::load_row<E, true>(d + (int64_t)vv * ld + blk0, valid, lane, row[u]);
-                        else
-                            sweep::load_row<E, false>(d + (int64_t)vv * ld + blk0, valid, lane, row[u]);
-                        for (int c = 0; c < CPL; ++c) {
-                            const int32_t k = blk0 + sweep::lane_col<E>(lane, c);
-                            col[u][c] = k < m ? (uint32_t)d[(int64_t)k * ld + vv] : 0u;
-                        }
-                        xv[u] = v[u] < 0 ? 0u : xq[vv];
+                    const uint32_t xv = xq[v];
+                    for (int c = 0; c < CPL; ++c) {
+                        const uint32_t w = gq ? edge_weight<MARGIN>((int32_t)col[c], (int32_t)row[c])
+                                              : edge_weight<MARGIN>((int32_t)row[c], (int32_t)col[c]);
+                        best[c] = max(best[c], min(xv, w));
                     }
-                    for (int u = 0; u < 2; ++u)
-                        for (int c = 0; c < CPL; ++c) {
-                            const uint32_t w = gq ? edge_weight<MARGIN>((int32_t)col[u][c], (int32_t)row[u][c])
-                                                  : edge_weight<MARGIN>((int32_t)row[u][c], (int32_t)col[u][c]);
-                            best[c] = max(best[c], min(xv[u], w));
-                        }
                 }
                 for (int c = 0; c < CPL; ++c) part[wave][sweep::lane_col<E>(lane, c)] = best[c];
             }
@@ -575,7 +574,7 @@ int check_counts_as(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, in
     // column block of both gather problems (cap >= 128 >= 2 ceil(m / 1024))
     const int64_t nb = ceil_div(m, 64);
     const int64_t want = std::max<int64_t>(sweep::grid_size(m, 2, INT64_MAX), nb * (nb + 1) / 2);
-    const int64_t G = std::min<int64_t>((int64_t)ctx->num_cus * std::min(per_cu, 2), want);
+    const int64_t G = std::min<int64_t>((int64_t)ctx->num_cus * std::min(per_cu, 3), want);
     int tok = -1;
     timing_begin(ctx, K_WIDEST, s, &tok);
     k_widest_init<E, 2><<<dim3((unsigned)std::min<int64_t>(ceil_div(m, 256), 1024)), dim3(256), 0, s>>>(a);
