@@ -18,20 +18,38 @@ namespace {
 
 // argmax of score over candidates the filter keeps (feat[x][5] == 0);
 // ties -> lowest id; out[0] = candidate or -1 if every candidate is filtered.
-__global__ __launch_bounds__(256) void k_propose(const float *__restrict__ score, const float *__restrict__ feat,
-                                                 int32_t m, int use_filter, int32_t *out) {
+// One workgroup of 1024 threads, four candidates per thread in flight, a
+// wavefront maximum, then one LDS atomic per wavefront.
+constexpr int PROPOSE_THREADS = 1024;
+__global__ __launch_bounds__(PROPOSE_THREADS) void k_propose(const float *__restrict__ score,
+                                                             const float *__restrict__ feat, int32_t m,
+                                                             int use_filter, int32_t *out) {
     __shared__ unsigned long long best;
     if (threadIdx.x == 0) best = 0ull;
     __syncthreads();
     unsigned long long mine = 0ull;
-    for (int32_t x = threadIdx.x; x < m; x += 256) {
-        if (use_filter && feat[(int64_t)x * 16 + 5] != 0.0f) continue;
-        const uint32_t bits = __float_as_uint(score[x]);
-        const uint32_t key = (bits & 0x80000000u) ? ~bits : (bits | 0x80000000u);
-        const unsigned long long k = ((unsigned long long)key << 32) | (uint32_t)(0xFFFFFFFFu - (uint32_t)x);
-        mine = k > mine ? k : mine;
+    for (int32_t x0 = threadIdx.x; x0 < m; x0 += 4 * PROPOSE_THREADS) {
+        float sc[4], fl[4];
+        for (int u = 0; u < 4; ++u) {  // loads first, so that they are in flight together
+            const int32_t x = x0 + u * PROPOSE_THREADS;
+            const int32_t xc = x < m ? x : 0;
+            sc[u] = score[xc];
+            fl[u] = use_filter ? feat[(int64_t)xc * 16 + 5] : 0.0f;
+        }
+        for (int u = 0; u < 4; ++u) {
+            const int32_t x = x0 + u * PROPOSE_THREADS;
+            if (x >= m || fl[u] != 0.0f) continue;
+            const uint32_t bits = __float_as_uint(sc[u]);
+            const uint32_t key = (bits & 0x80000000u) ? ~bits : (bits | 0x80000000u);
+            const unsigned long long k = ((unsigned long long)key << 32) | (uint32_t)(0xFFFFFFFFu - (uint32_t)x);
+            mine = k > mine ? k : mine;
+        }
     }
-    atomicMax(&best, mine);
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(mine, off);
+        mine = o > mine ? o : mine;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(&best, mine);
     __syncthreads();
     if (threadIdx.x == 0) out[0] = best ? (int32_t)(0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull)) : -1;
 }
@@ -94,13 +112,13 @@ extern "C" int schulze_winners_learned(schulze_ctx *ctx, void *stream, const voi
     }
     const int use_filter = proposer == SCHULZE_PROPOSER_NETWORK || proposer == SCHULZE_PROPOSER_FILTER_BORDA;
     SCHULZE_LAUNCH(ctx, K_PROPOSE, s,
-                   k_propose<<<dim3(1), dim3(256), 0, s>>>(score, feat, m, use_filter, small + 4));
+                   k_propose<<<dim3(1), dim3(PROPOSE_THREADS), 0, s>>>(score, feat, m, use_filter, small + 4));
     int32_t cand = -1;
     if (hipMemcpyAsync(&cand, small + 4, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return SCHULZE_EDEVICE;
     if (cand < 0) {  // every candidate filtered: cannot happen for consistent data; score all
-        SCHULZE_LAUNCH(ctx, K_PROPOSE, s, k_propose<<<dim3(1), dim3(256), 0, s>>>(score, feat, m, 0, small + 4));
+        SCHULZE_LAUNCH(ctx, K_PROPOSE, s, k_propose<<<dim3(1), dim3(PROPOSE_THREADS), 0, s>>>(score, feat, m, 0, small + 4));
         if (hipMemcpyAsync(&cand, small + 4, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return SCHULZE_EDEVICE;

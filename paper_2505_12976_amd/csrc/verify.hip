@@ -404,10 +404,13 @@ __global__ __launch_bounds__(256, 3) void k_check(WidestArgs<E, 2> a) {
 // out[2] = a beater (highest score, or widest margin p(x,c) - p(c,x) when
 // no scores are given; ties -> lowest id) or -1; out[3] = number of x != c
 // tied with c (p(c,x) = p(x,c)).  tied[] (optional) lists them.
+constexpr int VERDICT_THREADS = 1024;
 template <typename E>
-__global__ __launch_bounds__(256) void k_verdict(const E *__restrict__ from, const E *__restrict__ to, int32_t m,
-                                                 int32_t c, const float *__restrict__ score, int32_t *out,
-                                                 int32_t *tied) {
+__global__ __launch_bounds__(VERDICT_THREADS) void k_verdict(const E *__restrict__ from, const E *__restrict__ to,
+                                                             int32_t m, int32_t c, const float *__restrict__ score,
+                                                             int32_t *out, int32_t *tied) {
+    // one workgroup; counts and the tied list per wavefront (ballots), the
+    // best beater as a wavefront maximum, then one LDS atomic each
     __shared__ int32_t nbeat, ntie;
     __shared__ unsigned long long best;
     if (threadIdx.x == 0) {
@@ -416,26 +419,54 @@ __global__ __launch_bounds__(256) void k_verdict(const E *__restrict__ from, con
         best = 0ull;
     }
     __syncthreads();
-    for (int32_t x = threadIdx.x; x < m; x += 256) {
-        if (x == c) continue;
-        const E f = from[x], t = to[x];
-        if (t > f) {
-            atomicAdd(&nbeat, 1);
-            // key: larger is better; ids ascending on ties
-            uint32_t hi;
-            if (score) {
-                const float sc = score[x];
-                uint32_t bits = __float_as_uint(sc);
-                hi = (bits & 0x80000000u) ? ~bits : (bits | 0x80000000u);  // order-preserving
-            } else {
-                hi = (uint32_t)(t - f);
-            }
-            const unsigned long long key = ((unsigned long long)hi << 32) | (uint32_t)(0xFFFFFFFFu - (uint32_t)x);
-            atomicMax(&best, key);
-        } else if (t == f) {
-            const int32_t k = atomicAdd(&ntie, 1);
-            if (tied) tied[k] = x;
+    const int lane = threadIdx.x & 63;
+    unsigned long long mine = 0ull;
+    int32_t beats = 0;
+    // uniform trip count (the ballots below see every lane); four
+    // candidates per thread loaded together
+    for (int32_t x0 = 0; x0 < m; x0 += 4 * VERDICT_THREADS) {
+        E fv[4], tv[4];
+        for (int u = 0; u < 4; ++u) {
+            const int32_t x = x0 + u * VERDICT_THREADS + (int32_t)threadIdx.x;
+            const int32_t xc = x < m ? x : 0;
+            fv[u] = from[xc];
+            tv[u] = to[xc];
         }
+        for (int u = 0; u < 4; ++u) {
+            const int32_t x = x0 + u * VERDICT_THREADS + (int32_t)threadIdx.x;
+            const bool in = x < m && x != c;
+            const E f = fv[u], t = tv[u];
+            const bool beat = in && t > f, tie = in && t == f;
+            if (beat) {
+                ++beats;
+                // key: larger is better; ids ascending on ties
+                uint32_t hi;
+                if (score) {
+                    const uint32_t bits = __float_as_uint(score[x]);
+                    hi = (bits & 0x80000000u) ? ~bits : (bits | 0x80000000u);  // order-preserving
+                } else {
+                    hi = (uint32_t)(t - f);
+                }
+                const unsigned long long key = ((unsigned long long)hi << 32) | (uint32_t)(0xFFFFFFFFu - (uint32_t)x);
+                mine = key > mine ? key : mine;
+            }
+            const uint64_t bal = __ballot(tie);
+            if (bal) {
+                int32_t base = 0;
+                if (lane == 0) base = atomicAdd(&ntie, (int32_t)__popcll(bal));
+                base = __shfl(base, 0);
+                if (tie && tied) tied[base + (int32_t)__popcll(bal & ((1ull << lane) - 1ull))] = x;
+            }
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(mine, off);
+        mine = o > mine ? o : mine;
+        beats += __shfl_xor(beats, off);
+    }
+    if (lane == 0) {
+        atomicMax(&best, mine);
+        atomicAdd(&nbeat, beats);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -525,7 +556,7 @@ int verify_all(schulze_ctx *ctx, hipStream_t s, const E *w, int64_t ldw, const E
     E *const out[2] = {p_from, p_to};
     if (base) {
         if ((rc = widest_in<E, 2, SIGNED>(ctx, s, A, ld, m, cand, out, base, false)) != SCHULZE_OK) return rc;
-        k_verdict<E><<<dim3(1), dim3(256), 0, s>>>(p_from, p_to, m, cand, score, verdict, tied);
+        k_verdict<E><<<dim3(1), dim3(VERDICT_THREADS), 0, s>>>(p_from, p_to, m, cand, score, verdict, tied);
         return launch_status();
     }
     if ((rc = ws_reserve(ctx, WS_VERIFY, widest_scratch_bytes(m, 2))) != SCHULZE_OK) return rc;
@@ -533,7 +564,7 @@ int verify_all(schulze_ctx *ctx, hipStream_t s, const E *w, int64_t ldw, const E
                                       true)) != SCHULZE_OK)
         return rc;
     SCHULZE_LAUNCH(ctx, K_VERDICT, s,
-                   k_verdict<E><<<dim3(1), dim3(256), 0, s>>>(p_from, p_to, m, cand, score, verdict, tied));
+                   k_verdict<E><<<dim3(1), dim3(VERDICT_THREADS), 0, s>>>(p_from, p_to, m, cand, score, verdict, tied));
     return SCHULZE_OK;
 }
 
@@ -589,7 +620,7 @@ int check_counts_as(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, in
         return SCHULZE_EDEVICE;
     }
     SCHULZE_LAUNCH(ctx, K_VERDICT, s,
-                   k_verdict<E><<<dim3(1), dim3(256), 0, s>>>(p_from, p_to, m, cand, score, verdict, tied));
+                   k_verdict<E><<<dim3(1), dim3(VERDICT_THREADS), 0, s>>>(p_from, p_to, m, cand, score, verdict, tied));
     return SCHULZE_OK;
 }
 
