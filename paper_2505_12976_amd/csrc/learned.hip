@@ -54,6 +54,24 @@ __global__ __launch_bounds__(PROPOSE_THREADS) void k_propose(const float *__rest
     if (threadIdx.x == 0) out[0] = best ? (int32_t)(0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull)) : -1;
 }
 
+// The winner set of a search that found at most MAX_LISTED winners:
+// is_winner[j] = 1 for the listed ids, 0 elsewhere; *n_winners = count.
+constexpr int MAX_LISTED = 64;
+struct WinnerList {
+    int32_t n;
+    int32_t id[MAX_LISTED];
+};
+__global__ __launch_bounds__(256) void k_set_winners(uint8_t *__restrict__ is_winner, int32_t m, WinnerList list,
+                                                     int32_t *n_winners) {
+    const int32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j < m) {
+        uint8_t v = 0;
+        for (int k = 0; k < list.n; ++k) v |= list.id[k] == j ? 1 : 0;
+        is_winner[j] = v;
+    }
+    if (j == 0 && n_winners) *n_winners = list.n;
+}
+
 // score[x] = feat[x][col]: the proposers that rank by one feature column.
 __global__ __launch_bounds__(256) void k_score_column(const float *__restrict__ feat, int32_t m, int32_t col,
                                                       float *__restrict__ score) {
@@ -200,11 +218,20 @@ extern "C" int schulze_winners_learned(schulze_ctx *ctx, void *stream, const voi
         int32_t nw = 0;
         for (uint8_t x : host_win) nw += x;
         st.n_winners = nw;
-        if (hipMemcpyAsync(is_winner, host_win.data(), (size_t)m, hipMemcpyHostToDevice, s) != hipSuccess)
-            return SCHULZE_EDEVICE;
-        if (n_winners && hipMemcpyAsync(n_winners, &st.n_winners, sizeof(int32_t), hipMemcpyHostToDevice, s) !=
-                             hipSuccess)
-            return SCHULZE_EDEVICE;
+        if (nw <= MAX_LISTED) {  // the usual case: the few ids as kernel arguments, no host-to-device copy
+            WinnerList list{};
+            for (int32_t x = 0; x < m; ++x)
+                if (host_win[x]) list.id[list.n++] = x;
+            SCHULZE_LAUNCH(ctx, K_WINNERS, s,
+                           k_set_winners<<<dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s>>>(is_winner, m, list,
+                                                                                               n_winners));
+        } else {
+            if (hipMemcpyAsync(is_winner, host_win.data(), (size_t)m, hipMemcpyHostToDevice, s) != hipSuccess)
+                return SCHULZE_EDEVICE;
+            if (n_winners && hipMemcpyAsync(n_winners, &st.n_winners, sizeof(int32_t), hipMemcpyHostToDevice, s) !=
+                                 hipSuccess)
+                return SCHULZE_EDEVICE;
+        }
         if (hipStreamSynchronize(s) != hipSuccess) return SCHULZE_EDEVICE;
     } else {
         // fallback: the full closure decides
