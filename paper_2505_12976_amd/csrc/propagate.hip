@@ -118,9 +118,11 @@ __global__ __launch_bounds__(256) void k_prop_rows(const E *__restrict__ d, int6
         if (threadIdx.x == 0) status[x] = ST_REMOVED;
         return;
     }
+    // int32: w holds the signed weights S = w - w^T and wt is unused
+    constexpr bool SGN = sizeof(E) == 4;
     uint32_t mo = 0, mi = 0;
     unsigned long long b = 0;
-    const E *wr = w + (int64_t)x * ld, *wtr = wt + (int64_t)x * ld, *dr = d + (int64_t)x * ldd;
+    const E *wr = w + (int64_t)x * ld, *wtr = SGN ? wr : wt + (int64_t)x * ld, *dr = d + (int64_t)x * ldd;
     // four columns per thread and step: 8- or 16-byte accesses where the rows allow them
     const bool wv = (vec & 1) != 0, dv = (vec & 2) != 0;
     for (int32_t y0 = threadIdx.x * 4; y0 < m; y0 += 1024) {
@@ -129,17 +131,23 @@ __global__ __launch_bounds__(256) void k_prop_rows(const E *__restrict__ d, int6
         const bool full = y0 + 4 <= m;
         if (full && wv) {
             load4<E>(wr + y0, true, 4, a);
-            load4<E>(wtr + y0, true, 4, at);
+            if (!SGN) load4<E>(wtr + y0, true, 4, at);
             const uint32_t rw = *reinterpret_cast<const uint32_t *>(rem + y0);
             for (int u = 0; u < 4; ++u) r[u] = (uint8_t)(rw >> (8 * u));
         } else {
             for (int u = 0; u < 4; ++u) {
                 const bool in = y0 + u < m;
                 a[u] = in ? (uint32_t)wr[y0 + u] : 0u;
-                at[u] = in ? (uint32_t)wtr[y0 + u] : 0u;
+                if (!SGN) at[u] = in ? (uint32_t)wtr[y0 + u] : 0u;
                 r[u] = in ? rem[y0 + u] : (uint8_t)1;
             }
         }
+        if constexpr (SGN)
+            for (int u = 0; u < 4; ++u) {
+                const int32_t v = (int32_t)a[u];
+                a[u] = (uint32_t)max(v, 0);
+                at[u] = (uint32_t)max(-v, 0);
+            }
         if (with_borda) load4<E>(dr + y0, full && dv, full ? 4 : m - y0, ad);
         for (int u = 0; u < 4; ++u) {
             if (r[u]) continue;
@@ -196,7 +204,8 @@ __global__ __launch_bounds__(256) void k_prop_order(const unsigned long long *__
 
 // ------------------------------------------------------------------ propagation sweeps
 // Both directions in one launch: problem 0 propagates forward over the
-// rows of w into kf, problem 1 backward over the rows of wt into kb.
+// rows of w into kf, problem 1 backward over the rows of wt into kb (int32:
+// both over the rows of the signed weights S, as max(S, 0) and max(-S, 0)).
 template <typename E>
 struct SweepArgs {
     sweep::Run<typename Key<E>::K, E, 2> run;
@@ -238,7 +247,11 @@ __global__ __launch_bounds__(256) void k_prop_sweep(SweepArgs<E> a) {
     const uint8_t *status = a.status;
     const bool ok = sweep::run<K, E, 2>(
         a.run, a.m,
-        [](int, K k, uint32_t wij) -> K {
+        [](int q, K k, uint32_t wij) -> K {
+            if constexpr (sizeof(E) == 4) {  // signed weights: problem 0 takes max(S, 0), problem 1 max(-S, 0)
+                const int32_t v = q ? -(int32_t)wij : (int32_t)wij;
+                wij = (uint32_t)max(v, 0);
+            }
             if (wij == 0 || k == 0) return (K)0;
             return (k & HIGH) | (K)min((uint32_t)(k & Key<E>::LOW), wij);
         },
@@ -317,7 +330,9 @@ __global__ __launch_bounds__(256) void k_prop_cross(const E *__restrict__ wt, in
                 pv[u] = v0 + u < m ? pair[v0 + u] : PAIR_OUT;
             }
         }
-        for (int u = 0; u < 4; ++u) cross |= e[u] != 0 && pv[u] != PAIR_OUT && pv[u] != pc;
+        // an edge v -> c: wt[c][v] > 0, or with signed weights (int32) S[c][v] < 0
+        for (int u = 0; u < 4; ++u)
+            cross |= (sizeof(E) == 4 ? (int32_t)e[u] < 0 : e[u] != 0) && pv[u] != PAIR_OUT && pv[u] != pc;
     }
     if (__ballot(cross) && lane == 0) {
         const uint32_t s = pc >> 16, t = pc & 0xFFFFu;
@@ -437,7 +452,11 @@ int prop_prepare(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32
     // w | wt | kf | kb | fronts x4 | stamps x2 | label | vertex | pair | borda | status | mark | dead | rem |
     // counters | barrier | tail
     const size_t barb = round_up(grid::BAR_BYTES, 256);
-    const size_t need = 2 * mat + 2 * kvec + 9 * ivec + u64vec + 4 * bvec + 512 + barb + 256;
+    // int32 counts keep one matrix of signed weights S = w - w^T (both weight
+    // rules give a pair an edge in at most one direction): w = max(S, 0),
+    // w^T = max(-S, 0); 16-bit counts keep w and w^T
+    constexpr bool SGN = sizeof(E) == 4;
+    const size_t need = (SGN ? 1 : 2) * mat + 2 * kvec + 9 * ivec + u64vec + 4 * bvec + 512 + barb + 256;
     int rc = ws_reserve(ctx, WS_PROPAGATE, need);
     if (rc != SCHULZE_OK) return rc;
     char *p = static_cast<char *>(ctx->ws[WS_PROPAGATE]);
@@ -447,7 +466,7 @@ int prop_prepare(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32
         return q;
     };
     b.w = reinterpret_cast<E *>(take(mat));
-    b.wt = reinterpret_cast<E *>(take(mat));
+    b.wt = SGN ? nullptr : reinterpret_cast<E *>(take(mat));
     b.kf = reinterpret_cast<K *>(take(kvec));
     b.kb = reinterpret_cast<K *>(take(kvec));
     for (int i = 0; i < 4; ++i) b.front[i] = reinterpret_cast<int32_t *>(take(ivec));
@@ -466,7 +485,12 @@ int prop_prepare(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, int32
     b.bvec = bvec;
 
     const int dtype = sizeof(E) == 2 ? SCHULZE_U16 : SCHULZE_I32;
-    if ((rc = schulze_weights(ctx, s, d, ldd, m, dtype, mode, b.w, m, b.wt, m)) != SCHULZE_OK) return rc;
+    if constexpr (SGN)
+        rc = signed_weights(ctx, s, reinterpret_cast<const int32_t *>(d), ldd, m, mode,
+                            reinterpret_cast<int32_t *>(b.w), m);
+    else
+        rc = schulze_weights(ctx, s, d, ldd, m, dtype, mode, b.w, m, b.wt, m);
+    if (rc != SCHULZE_OK) return rc;
     if ((rc = fill_u32(ctx, s, reinterpret_cast<uint32_t *>(b.rem), bvec / 4, 0u)) != SCHULZE_OK) return rc;
     SCHULZE_LAUNCH(ctx, K_PROP, s,
                    k_prop_rows<E><<<dim3((unsigned)m), dim3(256), 0, s>>>(d, ldd, b.w, b.wt, m, m, b.rem, 1,
@@ -497,7 +521,7 @@ int prop_decide_all(schulze_ctx *ctx, hipStream_t s, int32_t m, PropBufs<E> &b, 
             SweepArgs<E> a;
             for (int q = 0; q < 2; ++q) {
                 sweep::Problem<K, E> &P = a.run.p[q];
-                P.A = q == 0 ? b.w : b.wt;
+                P.A = (q == 0 || sizeof(E) == 4) ? b.w : b.wt;  // int32: both read the signed weights
                 P.ld = m;
                 P.vec = sweep::vec_ok<E>(P.A, m) ? 1 : 0;
                 P.x = q == 0 ? b.kf : b.kb;
@@ -543,9 +567,10 @@ int prop_decide_all(schulze_ctx *ctx, hipStream_t s, int32_t m, PropBufs<E> &b, 
         SCHULZE_LAUNCH(ctx, K_PROP, s, k_prop_post<E><<<dim3(vb), dim3(256), 0, s>>>(b.kf, b.kb, m, b.vertex, b.mark));
         SCHULZE_LAUNCH(ctx, K_PROP, s,
                        k_prop_pair<E><<<dim3(vb), dim3(256), 0, s>>>(b.kf, b.kb, m, b.status, b.pair));
-        const int cvec = (reinterpret_cast<uintptr_t>(b.wt) % (4 * sizeof(E)) == 0 && m % 4 == 0) ? 1 : 0;
+        const E *wtc = sizeof(E) == 4 ? b.w : b.wt;  // rows of w^T, or of the signed weights
+        const int cvec = (reinterpret_cast<uintptr_t>(wtc) % (4 * sizeof(E)) == 0 && m % 4 == 0) ? 1 : 0;
         SCHULZE_LAUNCH(ctx, K_PROP, s,
-                       k_prop_cross<E><<<dim3((unsigned)ceil_div(m, 4)), dim3(256), 0, s>>>(b.wt, m, b.pair, m, cvec,
+                       k_prop_cross<E><<<dim3((unsigned)ceil_div(m, 4)), dim3(256), 0, s>>>(wtc, m, b.pair, m, cvec,
                                                                                             b.mark, b.dead));
         SCHULZE_LAUNCH(ctx, K_PROP, s,
                        k_prop_apply<E><<<dim3(vb), dim3(256), 0, s>>>(b.kf, b.kb, m, b.mark, b.dead, b.status));
