@@ -330,14 +330,18 @@ typedef struct {
 /*
  * Exact Schulze winners via a learned proposal.  The network (params, see
  * schulze_mlp_param_count) scores the features of d; the best candidate the
- * initialisation filter of Section 4 keeps is checked with schulze_verify
- * (schulze_set_proposer replaces the network by a plain score).
+ * initialisation filter of Section 4 keeps is checked exactly
+ * (schulze_verify_counts, then schulze_verify over written weights, see
+ * below; schulze_set_proposer replaces the network by a plain score).
  * If it is beaten, the check moves to the highest-scored beater (at most
  * max_climb times); once a winner is found the candidates tied with it are
  * checked too (every winner is tied with every other winner).  If no winner
  * is found or more than max_tied candidates are tied, schulze_closure and
  * schulze_winners decide.  The result equals schulze_winners on the closure
- * for any network.  Synchronises the stream (the search runs on the host).
+ * for any network.  The search runs on the host and synchronises the
+ * stream after each check; the winner set itself (is_winner, n_winners) is
+ * written by work queued on the stream when the call returns (at most 64
+ * winners; a larger set is copied before the call returns).
  * Returns SCHULZE_EDEVICE, with no winner set written, when the device error
  * word is set after a check (a widest-path launch gave up on its bounded
  * wait, or an earlier call left an error unread).

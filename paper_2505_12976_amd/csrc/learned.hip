@@ -222,6 +222,7 @@ extern "C" int schulze_winners_learned(schulze_ctx *ctx, void *stream, const voi
             WinnerList list{};
             for (int32_t x = 0; x < m; ++x)
                 if (host_win[x]) list.id[list.n++] = x;
+            // (asynchronous: the ids travel as kernel arguments)
             SCHULZE_LAUNCH(ctx, K_WINNERS, s,
                            k_set_winners<<<dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s>>>(is_winner, m, list,
                                                                                                n_winners));
@@ -231,8 +232,8 @@ extern "C" int schulze_winners_learned(schulze_ctx *ctx, void *stream, const voi
             if (n_winners && hipMemcpyAsync(n_winners, &st.n_winners, sizeof(int32_t), hipMemcpyHostToDevice, s) !=
                                  hipSuccess)
                 return SCHULZE_EDEVICE;
+            if (hipStreamSynchronize(s) != hipSuccess) return SCHULZE_EDEVICE;  // host buffers end with this call
         }
-        if (hipStreamSynchronize(s) != hipSuccess) return SCHULZE_EDEVICE;
     } else {
         // fallback: the full closure decides
         st.fallback = 1;

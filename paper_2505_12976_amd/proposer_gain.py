@@ -45,6 +45,7 @@ def run_election(ctx, params, ballots, m, n, repeats=1):
             for _ in range(repeats):
                 t0 = time.perf_counter()
                 w, nw, st = ctx.winners_learned(d, float(n), params)
+                torch.cuda.synchronize()  # the winner set is written by the call's last queued launch
                 dt = time.perf_counter() - t0
                 best = dt if best is None else min(best, dt)
             win = w.cpu().numpy().astype(bool)
