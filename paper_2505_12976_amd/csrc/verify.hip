@@ -404,9 +404,9 @@ __global__ __launch_bounds__(256, 3) void k_check(WidestArgs<E, 2> a) {
 // out[2] = a beater (highest score, or widest margin p(x,c) - p(c,x) when
 // no scores are given; ties -> lowest id) or -1; out[3] = number of x != c
 // tied with c (p(c,x) = p(x,c)).  tied[] (optional) lists them.
-constexpr int VERDICT_THREADS = 1024;
+constexpr int TALLY_THREADS = 1024;
 template <typename E>
-__global__ __launch_bounds__(VERDICT_THREADS) void k_verdict(const E *__restrict__ from, const E *__restrict__ to,
+__global__ __launch_bounds__(TALLY_THREADS) void k_verdict(const E *__restrict__ from, const E *__restrict__ to,
                                                              int32_t m, int32_t c, const float *__restrict__ score,
                                                              int32_t *out, int32_t *tied) {
     // one workgroup; counts and the tied list per wavefront (ballots), the
@@ -424,16 +424,16 @@ __global__ __launch_bounds__(VERDICT_THREADS) void k_verdict(const E *__restrict
     int32_t beats = 0;
     // uniform trip count (the ballots below see every lane); four
     // candidates per thread loaded together
-    for (int32_t x0 = 0; x0 < m; x0 += 4 * VERDICT_THREADS) {
+    for (int32_t x0 = 0; x0 < m; x0 += 4 * TALLY_THREADS) {
         E fv[4], tv[4];
         for (int u = 0; u < 4; ++u) {
-            const int32_t x = x0 + u * VERDICT_THREADS + (int32_t)threadIdx.x;
+            const int32_t x = x0 + u * TALLY_THREADS + (int32_t)threadIdx.x;
             const int32_t xc = x < m ? x : 0;
             fv[u] = from[xc];
             tv[u] = to[xc];
         }
         for (int u = 0; u < 4; ++u) {
-            const int32_t x = x0 + u * VERDICT_THREADS + (int32_t)threadIdx.x;
+            const int32_t x = x0 + u * TALLY_THREADS + (int32_t)threadIdx.x;
             const bool in = x < m && x != c;
             const E f = fv[u], t = tv[u];
             const bool beat = in && t > f, tie = in && t == f;
@@ -556,7 +556,7 @@ int verify_all(schulze_ctx *ctx, hipStream_t s, const E *w, int64_t ldw, const E
     E *const out[2] = {p_from, p_to};
     if (base) {
         if ((rc = widest_in<E, 2, SIGNED>(ctx, s, A, ld, m, cand, out, base, false)) != SCHULZE_OK) return rc;
-        k_verdict<E><<<dim3(1), dim3(VERDICT_THREADS), 0, s>>>(p_from, p_to, m, cand, score, verdict, tied);
+        k_verdict<E><<<dim3(1), dim3(TALLY_THREADS), 0, s>>>(p_from, p_to, m, cand, score, verdict, tied);
         return launch_status();
     }
     if ((rc = ws_reserve(ctx, WS_VERIFY, widest_scratch_bytes(m, 2))) != SCHULZE_OK) return rc;
@@ -564,7 +564,7 @@ int verify_all(schulze_ctx *ctx, hipStream_t s, const E *w, int64_t ldw, const E
                                       true)) != SCHULZE_OK)
         return rc;
     SCHULZE_LAUNCH(ctx, K_VERDICT, s,
-                   k_verdict<E><<<dim3(1), dim3(VERDICT_THREADS), 0, s>>>(p_from, p_to, m, cand, score, verdict, tied));
+                   k_verdict<E><<<dim3(1), dim3(TALLY_THREADS), 0, s>>>(p_from, p_to, m, cand, score, verdict, tied));
     return SCHULZE_OK;
 }
 
@@ -620,7 +620,7 @@ int check_counts_as(schulze_ctx *ctx, hipStream_t s, const E *d, int64_t ldd, in
         return SCHULZE_EDEVICE;
     }
     SCHULZE_LAUNCH(ctx, K_VERDICT, s,
-                   k_verdict<E><<<dim3(1), dim3(VERDICT_THREADS), 0, s>>>(p_from, p_to, m, cand, score, verdict, tied));
+                   k_verdict<E><<<dim3(1), dim3(TALLY_THREADS), 0, s>>>(p_from, p_to, m, cand, score, verdict, tied));
     return SCHULZE_OK;
 }
 
